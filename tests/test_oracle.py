@@ -1,0 +1,323 @@
+"""Pins for the CPU oracle (no GPU).  Each test checks the oracle against
+something other than itself: the paper's own bottom-up merge procedure, closed
+forms, invariants, a hand-worked example and published generator outputs."""
+from __future__ import annotations
+
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _pts(rows):
+    a = np.zeros(len(rows), synth.POINT_DTYPE)
+    for i, r in enumerate(rows):
+        a[i] = (r[0], r[1], r[2], r[3], r[4], r[5], r[6])
+    return a
+
+
+# --------------------------------------------------------------- cube, keys
+
+def test_cube_matches_numpy_min_max():
+    p = synth.uniform_cloud(1000, 3, lo=(-5, 2, 100), hi=(7, 3, 101))
+    lo, hi, side, scale = oracle.cube(p)
+    assert np.array_equal(lo, np.array([p["x"].min(), p["y"].min(), p["z"].min()], np.float32))
+    assert np.array_equal(hi, np.array([p["x"].max(), p["y"].max(), p["z"].max()], np.float32))
+    assert side == max(float(hi[a]) - float(lo[a]) for a in range(3))
+    assert scale == 2097152.0 / side
+
+
+def test_degenerate_extent_uses_unit_side():
+    p = _pts([[3.0, 3.0, 3.0, 1, 2, 3, 4]] * 5)
+    _, _, side, scale = oracle.cube(p)
+    assert side == 1.0 and scale == 2097152.0
+    assert np.all(oracle.keys(p) == 0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_keys_match_bitwise_interleave(seed):
+    p = synth.uniform_cloud(3000, seed, lo=(-100, 0, 5), hi=(100, 50, 6))
+    k = oracle.keys(p)
+    q = brute.quantize(p)
+    assert np.array_equal(k, brute.morton(q))
+    assert np.array_equal(brute.demorton(k), q)
+
+
+def test_quantization_within_one_cell_of_exact_rational():
+    p = synth.uniform_cloud(400, 9, lo=(-1e3, 1e-3, 7), hi=(1e3, 2e-3, 8))
+    lo, hi, side, _ = oracle.cube(p)
+    q = brute.demorton(oracle.keys(p))
+    for i in range(len(p)):
+        for a, ax in enumerate("xyz"):
+            exact = (Fraction(float(p[ax][i])) - Fraction(float(lo[a]))) * (1 << 21) / Fraction(side)
+            e = min(int(exact), (1 << 21) - 1)
+            assert abs(int(q[i, a]) - e) <= 1
+
+
+def test_extreme_faces_and_monotonicity():
+    p = synth.uniform_cloud(2000, 5, lo=(0, 0, 0), hi=(10, 10, 10))
+    q = brute.demorton(oracle.keys(p))
+    for a, ax in enumerate("xyz"):
+        imin, imax = np.argmin(p[ax]), np.argmax(p[ax])
+        assert q[imin, a] == 0
+        order = np.argsort(p[ax], kind="stable")
+        assert np.all(np.diff(q[order, a].astype(np.int64)) >= 0)
+    # the longest axis' far face maps to the last cell
+    lo, hi, side, _ = oracle.cube(p)
+    a = int(np.argmax(hi.astype(np.float64) - lo.astype(np.float64)))
+    assert q[np.argmax(p["xyz"[a]]), a] == (1 << 21) - 1
+
+
+def test_nested_prefixes():
+    p = synth.uniform_cloud(500, 11)
+    k = oracle.keys(p)
+    q = brute.demorton(k)
+    for L in range(0, 22):
+        cell = q >> np.uint32(21 - L)
+        assert np.array_equal(brute.prefix(k, L), brute.morton(cell) if L else np.zeros(len(k), np.uint64))
+
+
+def test_nonfinite_rejected():
+    p = synth.uniform_cloud(10, 1)
+    p["y"][3] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build(p)
+    assert e.value.status == oracle.ERR_NONFINITE
+    p["y"][3] = np.inf
+    with pytest.raises(oracle.OracleError):
+        oracle.build(p)
+
+
+def test_invalid_params_rejected():
+    p = synth.uniform_cloud(10, 1)
+    for kw in ({"leaf_cap": 0}, {"max_level": 15}, {"sampling": 3}):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.build(p, **kw)
+        assert e.value.status == oracle.ERR_INVALID
+
+
+# --------------------------------------------------------------- hash
+
+def test_splitmix_published_vectors():
+    g = json.load(open(os.path.join(GOLDEN, "splitmix64_vectors.json")))
+    gamma = int(g["gamma"], 16)
+    outs = [int(v, 16) for v in g["outputs"]]
+    for k, out in enumerate(outs):
+        x = (k * gamma) & ((1 << 64) - 1)  # the output function adds one more gamma
+        assert brute.splitmix64(x) == out
+        seed, pid = x >> 32, x & 0xFFFFFFFF
+        assert int(oracle.point_hash([pid], seed)[0]) == out >> 32
+
+
+# --------------------------------------------------------------- tree
+
+def _tree_invariants(t, n, T, max_level):
+    nn = t["num_nodes"]
+    if n == 0:
+        assert nn == 0
+        return
+    lv, leaf, npts, key = t["level"], t["is_leaf"].astype(bool), t["npoints"].astype(np.int64), t["key"]
+    assert lv[0] == 0 and key[0] == 0 and npts[0] == n
+    order = list(zip(lv.tolist(), key.tolist()))
+    assert order == sorted(order) and len(set(order)) == nn
+    assert npts[leaf].sum() == n
+    assert np.all(npts > 0)
+    for i in range(nn):
+        if leaf[i]:
+            assert npts[i] <= T or lv[i] == max_level
+            assert t["count"][i] == npts[i]
+        else:
+            assert npts[i] > T and lv[i] < max_level
+            fc = int(t["first_child"][i])
+            ch = [c for c in range(fc, nn) if lv[c] == lv[i] + 1 and key[c] >> np.uint64(3) == key[i]]
+            assert ch == list(range(fc, fc + len(ch))) and len(ch) >= 1
+            assert npts[ch].sum() == npts[i]
+            mask = 0
+            for c in ch:
+                mask |= 1 << int(key[c] & np.uint64(7))
+            assert mask == t["child_mask"][i]
+
+
+def _membership(t, p):
+    k = oracle.keys(p)
+    seen = np.zeros(len(p), np.int64)
+    for i in np.nonzero(t["is_leaf"])[0]:
+        ids = t["point_ids"][t["offset"][i]:t["offset"][i] + t["count"][i]]
+        seen[ids] += 1
+        assert np.all(brute.prefix(k[ids], int(t["level"][i])) == t["key"][i])
+    assert np.all(seen == 1)
+
+
+CASES = [(n, T, ml, seed) for (n, T, ml) in [(50, 1, 2), (300, 3, 4), (800, 7, 12), (2000, 50, 12),
+                                             (1500, 1, 6), (2000, 100, 3)] for seed in (0, 1)]
+
+
+@pytest.mark.parametrize("n,T,ml,seed", CASES)
+def test_tree_equals_paper_merge_procedure(n, T, ml, seed):
+    p = synth.uniform_cloud(n, seed + 17 * n)
+    t = oracle.build(p, leaf_cap=T, max_level=ml)
+    _tree_invariants(t, n, T, ml)
+    _membership(t, p)
+    assert brute.tree_nodes(t) == brute.paper_merge_tree(oracle.keys(p), T, ml)
+
+
+def test_tree_on_clustered_input_matches_merge_procedure():
+    # "teapot in a stadium": a dense cluster inside a sparse cloud
+    a = synth.uniform_cloud(400, 1, lo=(0, 0, 0), hi=(100, 100, 100))
+    b = synth.uniform_cloud(1600, 2, lo=(40, 40, 40), hi=(40.01, 40.01, 40.01))
+    p = np.concatenate([a, b])
+    t = oracle.build(p, leaf_cap=20, max_level=14)
+    _tree_invariants(t, len(p), 20, 14)
+    assert t["level"].max() >= 12
+    assert brute.tree_nodes(t) == brute.paper_merge_tree(oracle.keys(p), 20, 14)
+
+
+def test_small_input_is_one_root_leaf():
+    p = synth.uniform_cloud(50, 4)
+    t = oracle.build(p, leaf_cap=50)
+    assert t["num_nodes"] == 1 and t["is_leaf"][0] == 1 and t["num_voxels"] == 0
+    assert sorted(t["point_ids"].tolist()) == list(range(50))
+
+
+def test_empty_input():
+    t = oracle.build(np.zeros(0, synth.POINT_DTYPE))
+    assert t["num_nodes"] == 0 and t["num_points"] == 0 and t["num_voxels"] == 0
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_lattice_gives_complete_octree(k):
+    s = 2 ** k
+    g = (np.arange(s, dtype=np.float32) + 0.5)
+    xs, ys, zs = np.meshgrid(g, g, g, indexing="ij")
+    p = np.zeros(s ** 3, synth.POINT_DTYPE)
+    p["x"], p["y"], p["z"] = xs.ravel(), ys.ravel(), zs.ravel()
+    p["r"] = np.arange(s ** 3) % 256
+    t = oracle.build(p, leaf_cap=1, max_level=12)
+    for L in range(k + 1):
+        assert np.sum(t["level"] == L) == 8 ** L
+    assert np.all(t["is_leaf"][t["level"] == k]) and not np.any(t["is_leaf"][t["level"] < k])
+
+
+def test_identical_points_give_chain_to_depth_limit():
+    p = _pts([[1.0, 2.0, 3.0, 9, 9, 9, 9]] * 10 + [[5.0, 2.0, 3.0, 1, 1, 1, 1]])
+    t = oracle.build(p, leaf_cap=3, max_level=9)
+    deep = t["level"] == 9
+    assert np.sum(deep & (t["is_leaf"] == 1)) == 1 and t["npoints"][deep & (t["is_leaf"] == 1)][0] == 10
+    for L in range(1, 9):
+        inner = (t["level"] == L) & (t["is_leaf"] == 0)
+        assert np.sum(inner) == 1  # one single-child inner node per level
+
+
+# --------------------------------------------------------------- voxels
+
+def test_hand_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "tiny_hand_worked.json")))
+    p = _pts(g["points"])
+    T, ml = g["params"]["leaf_cap"], g["params"]["max_level"]
+    for sampling, field in ((oracle.AVERAGE, "average_voxels"), (oracle.FIRST, "first_voxels")):
+        t = oracle.build(p, leaf_cap=T, max_level=ml, sampling=sampling)
+        got = [{"level": int(t["level"][i]), "key": int(t["key"][i]), "leaf": bool(t["is_leaf"][i]),
+                "npoints": int(t["npoints"][i]), "child_mask": int(t["child_mask"][i])} for i in range(t["num_nodes"])]
+        assert got == g["nodes"]
+        for i in range(t["num_nodes"]):
+            name = f"{t['level'][i]}:{t['key'][i]}"
+            if t["is_leaf"][i]:
+                ids = sorted(t["point_ids"][t["offset"][i]:t["offset"][i] + t["count"][i]].tolist())
+                assert ids == g["leaf_ids"][name]
+            else:
+                v = t["voxels"][t["offset"][i]:t["offset"][i] + t["count"][i]].astype(int)
+                rows = [[r[0], r[1], r[2], r[4], r[5], r[6], r[7]] for r in v]
+                if sampling == oracle.FIRST:
+                    ids = t["voxel_ids"][t["offset"][i]:t["offset"][i] + t["count"][i]].tolist()
+                    rows = [r + [d] for r, d in zip(rows, ids)]
+                assert sorted(rows) == sorted(g[field][name])
+
+
+VOX_CASES = [(600, 5, 12, 0), (1500, 40, 12, 1), (3000, 200, 6, 2), (1200, 1, 5, 3)]
+
+
+@pytest.mark.parametrize("n,T,ml,seed", VOX_CASES)
+def test_voxel_positions_are_occupied_cells(n, T, ml, seed):
+    p = synth.uniform_cloud(n, seed)
+    t = oracle.build(p, leaf_cap=T, max_level=ml)
+    k = oracle.keys(p)
+    q = brute.demorton(k)
+    for i in np.nonzero(t["is_leaf"] == 0)[0]:
+        got = set(brute.tree_voxels(t, i).keys())
+        assert got == brute.closed_form_cells(q, k, int(t["level"][i]), int(t["key"][i]))
+
+
+@pytest.mark.parametrize("n,T,ml,seed", VOX_CASES)
+def test_average_matches_recursion_and_leaf_closed_form(n, T, ml, seed):
+    p = synth.uniform_cloud(n, seed)
+    t = oracle.build(p, leaf_cap=T, max_level=ml)
+    k = oracle.keys(p)
+    q = brute.demorton(k)
+    nodes = brute.tree_nodes(t)
+    rec = brute.recursive_voxels(p, q, k, nodes, T, ml)
+    checked_closed = 0
+    for i in np.nonzero(t["is_leaf"] == 0)[0]:
+        L, key = int(t["level"][i]), int(t["key"][i])
+        got = brute.tree_voxels(t, i)
+        assert got == rec[(L, key)]
+        fc = int(t["first_child"][i])
+        kids = [c for c in range(fc, t["num_nodes"]) if t["level"][c] == L + 1 and int(t["key"][c]) >> 3 == key]
+        if all(t["is_leaf"][c] for c in kids):
+            cf = brute.closed_form_leaf_means(p, q, k, L, key)
+            assert {c: v[:3] for c, v in got.items()} == cf
+            checked_closed += 1
+    assert checked_closed > 0
+
+
+@pytest.mark.parametrize("sampling", [oracle.FIRST, oracle.RANDOM])
+@pytest.mark.parametrize("n,T,ml,seed", VOX_CASES[:3])
+def test_pick_equals_argmin_argmax_over_subtree(sampling, n, T, ml, seed):
+    p = synth.uniform_cloud(n, seed)
+    t = oracle.build(p, leaf_cap=T, max_level=ml, sampling=sampling, seed=1234 + seed)
+    k = oracle.keys(p)
+    q = brute.demorton(k)
+    for i in np.nonzero(t["is_leaf"] == 0)[0]:
+        got = brute.tree_voxels(t, i)
+        cf = brute.closed_form_pick(p, q, k, int(t["level"][i]), int(t["key"][i]), sampling, 1234 + seed)
+        assert {c: v[4] for c, v in got.items()} == cf
+        for c, v in got.items():
+            pid = v[4]
+            assert v[:4] == (int(p["r"][pid]), int(p["g"][pid]), int(p["b"][pid]), int(p["a"][pid]))
+
+
+def test_constant_colour_gives_constant_voxels():
+    p = synth.uniform_cloud(3000, 8)
+    p["r"], p["g"], p["b"] = 7, 130, 251
+    t = oracle.build(p, leaf_cap=30, max_level=12)
+    v = t["voxels"]
+    assert len(v) > 0 and np.all(v[:, 4] == 7) and np.all(v[:, 5] == 130) and np.all(v[:, 6] == 251)
+    assert np.all(v[:, 7] == 255) and np.all(v[:, 3] == 0)
+
+
+def test_voxels_in_morton_order_and_in_grid():
+    p = synth.uniform_cloud(2000, 12)
+    t = oracle.build(p, leaf_cap=25, max_level=12)
+    for i in np.nonzero(t["is_leaf"] == 0)[0]:
+        v = t["voxels"][t["offset"][i]:t["offset"][i] + t["count"][i]]
+        assert np.all(v[:, :3] < 128)
+        codes = brute.morton(v[:, :3].astype(np.uint32))
+        assert np.all(np.diff(codes.astype(np.int64)) > 0)
+
+
+def test_child_voxel_contribution_at_most_eight_per_cell():
+    # a node whose children are all inner: each cell gathers at most 8 child voxels
+    p = synth.uniform_cloud(4000, 21)
+    t = oracle.build(p, leaf_cap=8, max_level=12)
+    assert t["num_voxels"] > 0
+    root = brute.tree_voxels(t, 0)
+    # the root's voxels are at most the number of occupied level-7 cells
+    q = brute.demorton(oracle.keys(p))
+    assert len(root) == len({tuple(c) for c in (q >> np.uint32(14)).tolist()})
