@@ -1,0 +1,162 @@
+/*
+ * lod.h -- C ABI of the MI355X (gfx950) builder for the hybrid voxel-point
+ * layered-point-cloud octree of Schuetz, Kerbl, Klaus, Wimmer,
+ * "GPU-Accelerated LOD Generation for Point Clouds" (arXiv 2302.14801).
+ *
+ * The octree (Sec. 3): leaves hold at most T original points, inner nodes hold
+ * the occupied cells ("voxels") of a 128^3 grid inscribed in the node; every
+ * child replaces one 64^3 octant of its parent's grid (Fig. 1 caption).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an lod_status; nothing throws across the ABI.  On
+ *     failure the output handle is set to NULL and nothing is leaked; the text
+ *     of the last error of the calling thread is available from
+ *     lod_last_error().
+ *   - Pointers named d_* are device pointers (HIP, the current device);
+ *     pointers named h_* are host pointers.  Inputs are borrowed: the library
+ *     never frees or keeps them beyond the call (lod_submit: until lod_poll
+ *     returns something other than LOD_PENDING).
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  The build
+ *     runs on that stream; the call synchronises it a few times internally to
+ *     size its outputs, and returns once the tree is complete.
+ *   - Results never depend on tuning (block sizes, grid depths, chunking).
+ */
+#ifndef LOD_H
+#define LOD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LOD_OK = 0,
+  LOD_PENDING = 1,              /* lod_poll: request not finished yet */
+  LOD_ERR_INVALID = -1,         /* bad argument (NULL pointer, leaf_cap 0, max_level > 14, n >= 2^32, ...) */
+  LOD_ERR_NONFINITE = -2,       /* an input coordinate is NaN or infinite */
+  LOD_ERR_OOM = -3,             /* device or host allocation failed */
+  LOD_ERR_CAPACITY = -4,        /* an internal pool stayed exhausted after re-planning */
+  LOD_ERR_TOO_LARGE = -5,       /* request larger than the server's whole memory budget */
+  LOD_ERR_UNKNOWN_TICKET = -6,  /* lod_poll: no such ticket */
+  LOD_ERR_HIP = -7              /* a HIP runtime call failed */
+} lod_status;
+
+/* 16-byte point record: input records and the records stored in leaves
+ * (Sec. 7: points and voxels share one struct with float coordinates). */
+typedef struct {
+  float x, y, z;
+  uint8_t r, g, b, a;
+} lod_point;
+
+/* 8-byte voxel: cell (x, y, z) in 0..127 of the owning inner node's 128^3
+ * grid (Sec. 4.2.1: coordinates quantized to the sampling grid), pad = 0,
+ * colour r, g, b, a. */
+typedef struct {
+  uint8_t x, y, z, pad;
+  uint8_t r, g, b, a;
+} lod_voxel;
+
+/* Sampling strategies (Sec. 4.2):
+ *   LOD_AVERAGE      cell-wise average (Sec. 4.2.3): per cell floor(sum / n) of
+ *                    R, G and B over the samples that fall in it, A = 255;
+ *                    every sample (a child's point, or a child's voxel)
+ *                    counts once.
+ *   LOD_PICK_FIRST   first-come (Sec. 4.2.1) made order-independent: the
+ *                    sample with the smallest input index wins.
+ *   LOD_PICK_RANDOM  random (Sec. 4.2.2, Listing 1) made order-independent:
+ *                    the sample with the largest (h(id, seed) << 32 | id)
+ *                    wins, h = high 32 bits of the SplitMix64 output function
+ *                    of (seed << 32 | id).
+ * Pick modes copy the winner's R, G, B, A and record its input index. */
+typedef enum { LOD_AVERAGE = 0, LOD_PICK_FIRST = 1, LOD_PICK_RANDOM = 2 } lod_sampling;
+
+enum { LOD_FLAG_POINT_IDS = 1 }; /* keep each leaf point's input index (implied by pick modes) */
+
+typedef struct {
+  uint32_t leaf_cap;     /* T (Sec. 3): a node with more than T points is split; default 50000; >= 1 */
+  uint32_t max_level;    /* depth limit (Sec. 4.1.5, 8 + 4 = 12 by default); 0..14; leaves at
+                            this level may hold more than T points */
+  uint32_t sampling;     /* lod_sampling */
+  uint32_t seed;         /* LOD_PICK_RANDOM only */
+  uint32_t flags;        /* LOD_FLAG_* */
+  uint32_t tune_levels0; /* 0 = automatic; else levels sorted by the first partition pass (1..5) */
+  uint32_t tune_levels1; /* 0 = automatic; else levels sorted by the second pass (1..5) */
+  uint32_t reserved;
+} lod_params;
+
+typedef struct lod_tree lod_tree;
+typedef struct lod_server lod_server;
+
+/* Read-only view of a finished tree.  All array pointers are DEVICE pointers,
+ * valid until lod_tree_free.  Nodes are in ascending (level, key) order and
+ * the children of a node are consecutive from node_first_child.
+ *   node_key      Morton prefix of the node (3 * level bits; x is the lowest
+ *                 bit of each 3-bit group), the cell at `level` that the node
+ *                 covers within the bounding cube
+ *   node_npoints  input points below the node
+ *   node_count    points of a leaf, voxels of an inner node
+ *   node_offset   index of the first point (leaf) or voxel (inner node)
+ * Points of a leaf are its input records (any order inside the leaf); voxels
+ * of an inner node are listed in Morton order of (x, y, z). */
+typedef struct {
+  float aabb_min[3], aabb_max[3];
+  double cube_side;            /* side of the bounding cube, anchored at aabb_min */
+  uint32_t num_nodes;
+  uint32_t reserved;
+  uint64_t num_points;
+  uint64_t num_voxels;
+  const uint8_t* node_level;
+  const uint8_t* node_is_leaf;
+  const uint8_t* node_child_mask;
+  const uint64_t* node_key;
+  const uint32_t* node_npoints;
+  const uint32_t* node_count;
+  const uint32_t* node_first_child;
+  const uint64_t* node_offset;
+  const lod_point* points;
+  const uint32_t* point_ids;   /* NULL unless ids were kept */
+  const lod_voxel* voxels;
+  const uint32_t* voxel_ids;   /* pick modes only, else NULL */
+} lod_tree_view;
+
+/* Default parameters (T = 50000, max_level = 12, AVERAGE). */
+void lod_params_default(lod_params* p);
+
+/* Build the octree of n points (Sec. 4.1 split into leaves, Sec. 4.2 voxel
+ * sampling).  d_points: device array of n records, borrowed.  n == 0 gives an
+ * empty tree (0 nodes).  Errors: LOD_ERR_INVALID (NULL out/params, n >=
+ * 2^32, bad params), LOD_ERR_NONFINITE, LOD_ERR_OOM, LOD_ERR_HIP. */
+lod_status lod_build(const lod_point* d_points, uint64_t n, const lod_params* p, void* hip_stream,
+                     lod_tree** out);
+
+/* Build num_chunks independent trees, chunk i being the records
+ * [h_offsets[i], h_offsets[i+1]) of d_points, each with its own bounding box
+ * (Sec. 7: chunks of a bottom-up out-of-core pipeline).  out: array of
+ * num_chunks handles, filled on success.  Result i equals lod_build on chunk i. */
+lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets, uint32_t num_chunks,
+                           const lod_params* p, void* hip_stream, lod_tree** out);
+
+/* Copy of the tree's header and device array pointers. */
+lod_status lod_tree_view_get(const lod_tree* t, lod_tree_view* v);
+void lod_tree_free(lod_tree* t);
+
+/* Server: requests (host point arrays) are admitted while their device
+ * footprint fits in hbm_budget_bytes next to the trees still resident, and
+ * built concurrently (continuous batching).  lod_submit returns a ticket;
+ * lod_poll returns LOD_PENDING until the tree is ready, then hands over the
+ * tree (the caller frees it with lod_tree_free, which also releases its share
+ * of the budget).  A request that could never fit gives LOD_ERR_TOO_LARGE. */
+lod_status lod_server_create(uint64_t hbm_budget_bytes, uint32_t max_inflight, const lod_params* p,
+                             lod_server** out);
+lod_status lod_submit(lod_server* s, const lod_point* h_points, uint64_t n, uint64_t* ticket);
+lod_status lod_poll(lod_server* s, uint64_t ticket, lod_tree** out);
+void lod_server_destroy(lod_server* s);
+
+const char* lod_status_str(lod_status s);
+const char* lod_last_error(void); /* thread-local text of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -77,6 +77,12 @@ def _load():
         lib.lod_oracle_cube.restype = ctypes.c_int
         lib.lod_oracle_keys.argtypes = [vp, u64, vp]
         lib.lod_oracle_keys.restype = ctypes.c_int
+        f3 = ctypes.c_float * 3
+        lib.lod_oracle_build_in_cube.argtypes = [vp, u64, u32, u32, ctypes.c_int, u32, f3, ctypes.c_double,
+                                                 ctypes.POINTER(_Tree)]
+        lib.lod_oracle_build_in_cube.restype = ctypes.c_int
+        lib.lod_oracle_keys_in_cube.argtypes = [vp, u64, f3, ctypes.c_double, vp]
+        lib.lod_oracle_keys_in_cube.restype = ctypes.c_int
         lib.lod_oracle_hash.argtypes = [u32, u32]
         lib.lod_oracle_hash.restype = u32
         _lib = lib
@@ -118,19 +124,37 @@ def keys(points) -> np.ndarray:
     return out
 
 
+def keys_in_cube(points, lo, side: float) -> np.ndarray:
+    """Morton keys of the points in a given cube (minimum corner lo, edge side)."""
+    a = _as_records(points)
+    out = np.zeros(a.shape[0], np.uint64)
+    lo3 = (ctypes.c_float * 3)(*[float(v) for v in lo])
+    st = _load().lod_oracle_keys_in_cube(a.ctypes.data, a.shape[0], lo3, float(side), out.ctypes.data)
+    if st:
+        raise OracleError(st)
+    return out
+
+
 def point_hash(ids, seed: int) -> np.ndarray:
     """32-bit hash used by the RANDOM pick (SplitMix64 output, high half)."""
     lib = _load()
     return np.array([lib.lod_oracle_hash(int(i), int(seed)) for i in np.asarray(ids).ravel()], np.uint32)
 
 
-def build(points, leaf_cap: int = 50000, max_level: int = 12, sampling: int = AVERAGE, seed: int = 0) -> dict:
-    """Build the octree; returns numpy arrays (see lod_oracle.h for meaning)."""
+def build(points, leaf_cap: int = 50000, max_level: int = 12, sampling: int = AVERAGE, seed: int = 0,
+          cube_lo=None, cube_side: float | None = None) -> dict:
+    """Build the octree; returns numpy arrays (see lod_oracle.h for meaning).
+    With cube_lo/cube_side the cube is given instead of computed from the points."""
     a = _as_records(points)
     n = a.shape[0]
     t = _Tree()
-    st = _load().lod_oracle_build(a.ctypes.data if n else None, n, leaf_cap, max_level, sampling, seed,
-                                  ctypes.byref(t))
+    if cube_lo is not None:
+        lo3 = (ctypes.c_float * 3)(*[float(v) for v in cube_lo])
+        st = _load().lod_oracle_build_in_cube(a.ctypes.data if n else None, n, leaf_cap, max_level, sampling,
+                                              seed, lo3, float(cube_side), ctypes.byref(t))
+    else:
+        st = _load().lod_oracle_build(a.ctypes.data if n else None, n, leaf_cap, max_level, sampling, seed,
+                                      ctypes.byref(t))
     if st:
         _load().lod_oracle_free(ctypes.byref(t))
         raise OracleError(st)

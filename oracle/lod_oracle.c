@@ -127,6 +127,18 @@ int lod_oracle_cube(const lod_oracle_point* pts, uint64_t n, float lo[3], float 
   return LOD_ORACLE_OK;
 }
 
+int lod_oracle_keys_in_cube(const lod_oracle_point* pts, uint64_t n, const float lo[3], double side,
+                            uint64_t* keys) {
+  const double scale = 2097152.0 / side;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint32_t qx = quantize_axis(pts[i].x, lo[0], scale);
+    uint32_t qy = quantize_axis(pts[i].y, lo[1], scale);
+    uint32_t qz = quantize_axis(pts[i].z, lo[2], scale);
+    keys[i] = morton_bits(qx, qy, qz, KEY_LEVELS);
+  }
+  return LOD_ORACLE_OK;
+}
+
 int lod_oracle_keys(const lod_oracle_point* pts, uint64_t n, uint64_t* keys) {
   float lo[3], hi[3];
   double side, scale;
@@ -204,8 +216,12 @@ static int cmp_coded(const void* a, const void* b) {
 
 /* ---------------------------------------------------------------- build */
 
-int lod_oracle_build(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap, uint32_t max_level,
-                     int sampling, uint32_t seed, lod_oracle_tree* out) {
+/* The build with the cube either computed from the points (steps 2-3) or
+ * supplied by the caller (cube_lo != NULL), so that the subtree of any node of
+ * a large cloud can be rebuilt from that node's points alone: below a node,
+ * the octree and its voxels depend only on the node's own points. */
+static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap, uint32_t max_level, int sampling,
+                      uint32_t seed, const float* cube_lo, double cube_side, lod_oracle_tree* out) {
   memset(out, 0, sizeof(*out));
   if (leaf_cap == 0 || max_level > 14 || sampling < 0 || sampling > 2) return LOD_ORACLE_ERR_INVALID;
   if (n > 0xFFFFFFFFull) return LOD_ORACLE_ERR_INVALID;
@@ -214,6 +230,11 @@ int lod_oracle_build(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap,
   /* Steps 2-3 */
   int st = lod_oracle_cube(pts, n, out->aabb_min, out->aabb_max, &out->side, &out->scale);
   if (st) return st;
+  if (cube_lo) {
+    for (int a = 0; a < 3; ++a) out->aabb_min[a] = cube_lo[a];
+    out->side = cube_side;
+    out->scale = 2097152.0 / cube_side;
+  }
   if (n == 0) return LOD_ORACLE_OK; /* empty tree: no nodes */
 
   /* Steps 4-5: key per point, then sort (key, id) ascending. */
@@ -407,4 +428,14 @@ int lod_oracle_build(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap,
   free(g.best_id); free(g.occupied); free(order);
   free(q); free(kv);
   return LOD_ORACLE_OK;
+}
+
+int lod_oracle_build(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap, uint32_t max_level, int sampling,
+                     uint32_t seed, lod_oracle_tree* out) {
+  return build_impl(pts, n, leaf_cap, max_level, sampling, seed, NULL, 0.0, out);
+}
+
+int lod_oracle_build_in_cube(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap, uint32_t max_level,
+                             int sampling, uint32_t seed, const float lo[3], double side, lod_oracle_tree* out) {
+  return build_impl(pts, n, leaf_cap, max_level, sampling, seed, lo, side, out);
 }

@@ -51,10 +51,17 @@ int lod_oracle_build(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap,
                      int sampling, uint32_t seed, lod_oracle_tree* out);
 void lod_oracle_free(lod_oracle_tree* t);
 
+/* Same build with the cube supplied instead of computed: lo is the cube's
+ * minimum corner, side its edge.  Every point must lie inside the cube. */
+int lod_oracle_build_in_cube(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap, uint32_t max_level,
+                             int sampling, uint32_t seed, const float lo[3], double side, lod_oracle_tree* out);
+
 /* Individual steps, exposed so tests can pin them one at a time. */
 int lod_oracle_cube(const lod_oracle_point* pts, uint64_t n, float lo[3], float hi[3], double* side,
                     double* scale);
 int lod_oracle_keys(const lod_oracle_point* pts, uint64_t n, uint64_t* keys);
+int lod_oracle_keys_in_cube(const lod_oracle_point* pts, uint64_t n, const float lo[3], double side,
+                            uint64_t* keys);
 uint32_t lod_oracle_hash(uint32_t id, uint32_t seed);
 
 #ifdef __cplusplus

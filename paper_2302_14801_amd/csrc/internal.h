@@ -1,0 +1,117 @@
+// internal.h -- library-internal host structures shared by the C ABI files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/lod.h"
+
+struct LodError {
+  lod_status st;
+};
+
+void lod_set_error(const char* fmt, ...);
+
+// ---------------------------------------------------------- device memory
+//
+// A small caching allocator: freed blocks are kept per device and reused for
+// requests of at least half their size, so steady-state builds do not call
+// hipMalloc.  Trees hold blocks until lod_tree_free.
+
+namespace lodint {
+
+struct Block {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+class DeviceCache {
+ public:
+  void* alloc(int dev, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto& m = free_[dev];
+      auto it = m.lower_bound(bytes);
+      if (it != m.end() && it->first <= 2 * bytes + (4u << 20)) {
+        void* p = it->second;
+        size_t cap = it->first;
+        m.erase(it);
+        used_[p] = cap;
+        return p;
+      }
+    }
+    size_t cap = (bytes + (2u << 20) - 1) & ~(size_t)((2u << 20) - 1);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim(dev);
+      e = hipMalloc(&p, cap);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        lod_set_error("device allocation of %zu bytes failed: %s", cap, hipGetErrorString(e));
+        throw LodError{LOD_ERR_OOM};
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    used_[p] = cap;
+    return p;
+  }
+  void release(int dev, void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = used_.find(p);
+    if (it == used_.end()) return;
+    free_[dev].emplace(it->second, p);
+    used_.erase(it);
+  }
+  void trim(int dev) {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& kv : free_[dev]) (void)hipFree(kv.second);
+    free_[dev].clear();
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<int, std::multimap<size_t, void*>> free_;
+  std::map<void*, size_t> used_;
+};
+
+// One process-wide cache, never destroyed (frees after runtime teardown are unsafe).
+inline DeviceCache& cache() {
+  static DeviceCache* c = new DeviceCache();
+  return *c;
+}
+}  // namespace lodint
+
+// ---------------------------------------------------------------- the tree
+
+struct lod_tree {
+  int dev = 0;
+  lod_tree_view v{};
+  std::vector<void*> blocks;
+  uint64_t footprint = 0;
+  std::shared_ptr<std::atomic<uint64_t>> budget_used;  // server accounting, if any
+  ~lod_tree() {
+    for (void* p : blocks) lodint::cache().release(dev, p);
+    if (budget_used) budget_used->fetch_sub(footprint);
+  }
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = lodint::cache().alloc(dev, count * sizeof(T));
+    blocks.push_back(p);
+    footprint += count * sizeof(T);
+    return (T*)p;
+  }
+};
+
+
+// Build one tree on `stream` (blocking until complete); throws LodError.
+lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params& p, hipStream_t stream);

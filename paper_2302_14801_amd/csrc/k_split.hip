@@ -1,0 +1,533 @@
+// k_split.hip -- bounding box, cube, and the hierarchical counting sort that
+// splits the input into octree cells (Sec. 4.1: counting, creating target
+// offsets, insert; Sec. 4.1.5: repeated for cells that need more depth).
+//
+// A "partition" call takes a list of segments (contiguous point ranges, each
+// the points of one octree node) and sorts every segment by the next e levels
+// of the Morton key: one dense 8^e counting grid per segment (Sec. 4.1.1),
+// exclusive prefix sums as target offsets (Sec. 4.1.3), and an insert pass
+// that moves every point to its cell (Sec. 4.1.4).  On gfx950 the per-point
+// counting and the insert are privatised in LDS: a workgroup counts a chunk
+// of a segment in LDS and writes one histogram row, and the insert stages a
+// round of points in LDS sorted by cell so that the global stores come out as
+// contiguous runs instead of single 16-byte writes (global atomics and
+// scattered 16-byte stores both run at ~25-40 G ops/s on this part, far below
+// what the 8 TB/s memory can stream).
+#include "common.h"
+#include "launch.h"
+#include "scan.h"
+
+namespace lod {
+
+// ------------------------------------------------------------ bounding box
+
+__global__ void k_bbox_init(BBoxAcc* acc) {
+  if (threadIdx.x < 3) {
+    acc->lo[threadIdx.x] = 0xffffffffu;
+    acc->hi[threadIdx.x] = 0u;
+  }
+  if (threadIdx.x == 0) acc->nonfinite = 0u;
+}
+
+constexpr int kBBoxWG = 256;
+
+__global__ void __launch_bounds__(kBBoxWG) k_bbox(const uint4* __restrict__ pts, uint64_t n, BBoxAcc* acc) {
+  uint32_t lo0 = 0xffffffffu, lo1 = 0xffffffffu, lo2 = 0xffffffffu;
+  uint32_t hi0 = 0u, hi1 = 0u, hi2 = 0u, bad = 0u;
+  const uint64_t stride = (uint64_t)gridDim.x * kBBoxWG;
+  uint64_t i = (uint64_t)blockIdx.x * kBBoxWG + threadIdx.x;
+  auto acc1 = [&](const uint4& v) {
+    // exponent all ones = Inf or NaN
+    uint32_t nf = ((v.x & 0x7f800000u) == 0x7f800000u) | ((v.y & 0x7f800000u) == 0x7f800000u) |
+                  ((v.z & 0x7f800000u) == 0x7f800000u);
+    bad |= nf;
+    if (!nf) {
+      uint32_t a = float_order(__uint_as_float(v.x)), b = float_order(__uint_as_float(v.y)),
+               c = float_order(__uint_as_float(v.z));
+      lo0 = min(lo0, a); hi0 = max(hi0, a);
+      lo1 = min(lo1, b); hi1 = max(hi1, b);
+      lo2 = min(lo2, c); hi2 = max(hi2, c);
+    }
+  };
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    uint4 v0 = pts[i], v1 = pts[i + stride], v2 = pts[i + 2 * stride], v3 = pts[i + 3 * stride];
+    acc1(v0); acc1(v1); acc1(v2); acc1(v3);
+  }
+  for (; i < n; i += stride) acc1(pts[i]);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo0 = min(lo0, (uint32_t)__shfl_xor((int)lo0, d, 64));
+    lo1 = min(lo1, (uint32_t)__shfl_xor((int)lo1, d, 64));
+    lo2 = min(lo2, (uint32_t)__shfl_xor((int)lo2, d, 64));
+    hi0 = max(hi0, (uint32_t)__shfl_xor((int)hi0, d, 64));
+    hi1 = max(hi1, (uint32_t)__shfl_xor((int)hi1, d, 64));
+    hi2 = max(hi2, (uint32_t)__shfl_xor((int)hi2, d, 64));
+    bad |= (uint32_t)__shfl_xor((int)bad, d, 64);
+  }
+  __shared__ uint32_t sh[7][kBBoxWG / 64];
+  const int w = threadIdx.x / 64;
+  if (lane_id() == 0) {
+    sh[0][w] = lo0; sh[1][w] = lo1; sh[2][w] = lo2;
+    sh[3][w] = hi0; sh[4][w] = hi1; sh[5][w] = hi2; sh[6][w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    uint32_t r = sh[threadIdx.x][0];
+    for (int k = 1; k < kBBoxWG / 64; ++k) {
+      uint32_t t = sh[threadIdx.x][k];
+      r = threadIdx.x < 3 ? min(r, t) : (threadIdx.x < 6 ? max(r, t) : (r | t));
+    }
+    if (threadIdx.x < 3) atomicMin(&acc->lo[threadIdx.x], r);
+    else if (threadIdx.x < 6) atomicMax(&acc->hi[threadIdx.x - 3], r);
+    else if (r) atomicOr(&acc->nonfinite, 1u);
+  }
+}
+
+// The bounding cube: anchored at the minimum, side = largest extent.
+__global__ void k_cube(const BBoxAcc* acc, uint64_t n, Cube* cube) {
+  if (threadIdx.x != 0) return;
+  double side = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    float lo = n ? order_float(acc->lo[a]) : 0.f;
+    float hi = n ? order_float(acc->hi[a]) : 0.f;
+    if (acc->lo[a] == 0xffffffffu) lo = hi = 0.f;  // every point rejected
+    cube->lo[a] = lo;
+    cube->hi[a] = hi;
+    double e = __dsub_rn((double)hi, (double)lo);
+    if (e > side) side = e;
+  }
+  if (side == 0.0) side = 1.0;
+  cube->side = side;
+  cube->scale = 2097152.0 / side;
+  cube->nonfinite = acc->nonfinite;
+}
+
+// ------------------------------------------------------------ partition
+
+// Split every segment into chunks of at most `chunk` points.  One workgroup.
+constexpr int kChunkWG = 1024;
+__global__ void __launch_bounds__(kChunkWG) k_make_chunks(Segment* segs, const uint32_t* nseg_ptr, uint32_t chunk,
+                                                          Chunk* chunks, uint32_t* nchunk_ptr, uint32_t max_chunks) {
+  __shared__ uint32_t sh[kChunkWG / 64 + 1];
+  const uint32_t nseg = *nseg_ptr;
+  uint32_t base = 0;
+  for (uint32_t s0 = 0; s0 < nseg; s0 += kChunkWG) {
+    uint32_t s = s0 + threadIdx.x;
+    uint32_t cnt = 0;
+    if (s < nseg) cnt = (segs[s].count + chunk - 1) / chunk;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kChunkWG>(cnt, sh, &tot);
+    if (s < nseg) {
+      uint32_t first = base + ex;
+      segs[s].chunk_begin = first;
+      segs[s].chunk_count = cnt;
+      for (uint32_t k = 0; k < cnt; ++k) {
+        if (first + k >= max_chunks) break;
+        Chunk c;
+        c.seg = s;
+        c.start = segs[s].start + k * chunk;
+        c.count = min(chunk, segs[s].count - k * chunk);
+        c.pad = 0;
+        chunks[first + k] = c;
+      }
+    }
+    base += tot;
+  }
+  if (threadIdx.x == 0) *nchunk_ptr = min(base, max_chunks);
+}
+
+// Count one chunk into an LDS histogram of B = 8^E cells and write the row.
+constexpr int kCountWG = 512;
+template <int E>
+__global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict__ pts, const Cube* cube,
+                                                         const Segment* __restrict__ segs,
+                                                         const Chunk* __restrict__ chunks,
+                                                         const uint32_t* nchunk_ptr, uint32_t* __restrict__ hist) {
+  constexpr uint32_t B = 1u << (3 * E);
+  __shared__ uint32_t h[B];
+  const uint32_t c = blockIdx.x;
+  if (c >= *nchunk_ptr) return;
+  const Chunk ch = chunks[c];
+  const Segment sg = segs[ch.seg];
+  const CubeD cd = load_cube(cube);
+  const uint32_t shift = 3u * (kKeyLevels - (sg.level + E));
+  for (uint32_t j = threadIdx.x; j < B; j += kCountWG) h[j] = 0;
+  __syncthreads();
+  const uint4* p = pts + ch.start;
+  uint32_t i = threadIdx.x;
+  for (; i + 3 * kCountWG < ch.count; i += 4 * kCountWG) {
+    uint4 v0 = p[i], v1 = p[i + kCountWG], v2 = p[i + 2 * kCountWG], v3 = p[i + 3 * kCountWG];
+    atomicAdd(&h[(point_key(__uint_as_float(v0.x), __uint_as_float(v0.y), __uint_as_float(v0.z), cd) >> shift) & (B - 1)], 1u);
+    atomicAdd(&h[(point_key(__uint_as_float(v1.x), __uint_as_float(v1.y), __uint_as_float(v1.z), cd) >> shift) & (B - 1)], 1u);
+    atomicAdd(&h[(point_key(__uint_as_float(v2.x), __uint_as_float(v2.y), __uint_as_float(v2.z), cd) >> shift) & (B - 1)], 1u);
+    atomicAdd(&h[(point_key(__uint_as_float(v3.x), __uint_as_float(v3.y), __uint_as_float(v3.z), cd) >> shift) & (B - 1)], 1u);
+  }
+  for (; i < ch.count; i += kCountWG) {
+    uint4 v = p[i];
+    atomicAdd(&h[(point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd) >> shift) & (B - 1)], 1u);
+  }
+  __syncthreads();
+  uint32_t* row = hist + (uint64_t)c * B;
+  for (uint32_t j = threadIdx.x; j < B; j += kCountWG) row[j] = h[j];
+}
+
+// Column scan: for every (segment, cell) turn the chunk rows into exclusive
+// offsets within the segment, and store the segment's cell totals as the
+// finest level of its grid.
+__global__ void k_part_colscan(const Segment* __restrict__ segs, const uint32_t* nseg_ptr, uint32_t E,
+                               uint32_t* __restrict__ hist, const GridDesc* __restrict__ grids, uint32_t* pool) {
+  const uint32_t B = 1u << (3 * E);
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = (uint32_t)(t >> (3 * E));
+  const uint32_t b = (uint32_t)(t & (B - 1));
+  if (s >= *nseg_ptr) return;
+  const Segment sg = segs[s];
+  uint32_t run = 0;
+  for (uint32_t k = 0; k < sg.chunk_count; ++k) {
+    uint32_t* cell = hist + (uint64_t)(sg.chunk_begin + k) * B + b;
+    uint32_t v = *cell;
+    *cell = run;
+    run += v;
+  }
+  const GridDesc g = grids[sg.grid];
+  pool[g.pyr + pyr_level_offset(E) + b] = run;
+}
+
+// Finish the grids of a partition: finest-cell offsets (exclusive prefix sum
+// plus the segment start: the target offsets of counting sort, Sec. 4.1.3),
+// the count pyramid above (Sec. 4.1.2 merges 2x2x2 groups level by level),
+// and no child grids yet.
+constexpr int kGridWG = 1024;
+__global__ void __launch_bounds__(kGridWG) k_grid_finish(const Segment* __restrict__ segs, const uint32_t* nseg_ptr,
+                                                         const GridDesc* __restrict__ grids, uint32_t* pool) {
+  __shared__ uint32_t sh[kGridWG / 64 + 1];
+  const uint32_t s = blockIdx.x;
+  if (s >= *nseg_ptr) return;
+  const Segment sg = segs[s];
+  const GridDesc g = grids[sg.grid];
+  const uint32_t E = g.e;
+  const uint32_t B = 1u << (3 * E);
+  uint32_t* fin = pool + g.pyr + pyr_level_offset(E);
+  uint32_t* off = pool + g.off;
+  int32_t* child = (int32_t*)(pool + g.child);
+  // exclusive scan, each thread owning a contiguous run of B / kGridWG cells
+  const uint32_t per = (B + kGridWG - 1) / kGridWG;
+  const uint32_t b0 = threadIdx.x * per;
+  uint32_t local = 0;
+  for (uint32_t k = 0; k < per; ++k)
+    if (b0 + k < B) local += fin[b0 + k];
+  uint32_t tot;
+  uint32_t ex = block_excl_scan<kGridWG>(local, sh, &tot);
+  uint32_t run = sg.start + ex;
+  for (uint32_t k = 0; k < per; ++k)
+    if (b0 + k < B) {
+      off[b0 + k] = run;
+      run += fin[b0 + k];
+      child[b0 + k] = -1;
+    }
+  __syncthreads();
+  for (int j = (int)E - 1; j >= 0; --j) {
+    uint32_t* up = pool + g.pyr + pyr_level_offset((uint32_t)j);
+    const uint32_t* dn = pool + g.pyr + pyr_level_offset((uint32_t)j + 1);
+    const uint32_t nj = 1u << (3 * j);
+    for (uint32_t i = threadIdx.x; i < nj; i += kGridWG) {
+      uint32_t v = 0;
+      for (int o = 0; o < 8; ++o) v += dn[8 * i + o];
+      up[i] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Insert (Sec. 4.1.4): move every point of a chunk to its cell.  A round of
+// R = WG * PPT points is sorted by cell in LDS (counting sort: LDS histogram,
+// workgroup prefix sum, staging), then written out so that consecutive lanes
+// store consecutive records of the same cell.  Per-cell cursors in LDS start
+// at the chunk's target offsets and advance round by round.
+constexpr int kScatWG = 512;
+constexpr int kScatPPT = 4;
+constexpr int kScatR = kScatWG * kScatPPT;
+
+template <int E, bool IDS>
+__global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
+                                                          uint4* __restrict__ dst, uint32_t* __restrict__ dst_ids,
+                                                          const Cube* cube, const Segment* __restrict__ segs,
+                                                          const Chunk* __restrict__ chunks, const uint32_t* nchunk_ptr,
+                                                          const uint32_t* __restrict__ hist,
+                                                          const GridDesc* __restrict__ grids, const uint32_t* __restrict__ pool) {
+  constexpr uint32_t B = 1u << (3 * E);
+  constexpr uint32_t BPT = (B + kScatWG - 1) / kScatWG;  // cells per thread in the scan
+  __shared__ uint32_t cursor[B];
+  __shared__ uint32_t cnt[B];
+  __shared__ uint4 stage[kScatR];
+  __shared__ uint16_t stage_b[kScatR];
+  __shared__ uint32_t stage_id[IDS ? kScatR : 1];
+  __shared__ uint32_t sh[kScatWG / 64 + 1];
+  const uint32_t c = blockIdx.x;
+  if (c >= *nchunk_ptr) return;
+  const Chunk ch = chunks[c];
+  const Segment sg = segs[ch.seg];
+  const GridDesc g = grids[sg.grid];
+  const CubeD cd = load_cube(cube);
+  const uint32_t shift = 3u * (kKeyLevels - (sg.level + E));
+  const uint32_t* row = hist + (uint64_t)c * B;
+  const uint32_t* goff = pool + g.off;
+  for (uint32_t j = threadIdx.x; j < B; j += kScatWG) {
+    cursor[j] = goff[j] + row[j];
+    cnt[j] = 0;
+  }
+  __syncthreads();
+  for (uint32_t base = 0; base < ch.count; base += kScatR) {
+    const uint32_t nround = min((uint32_t)kScatR, ch.count - base);
+    uint4 v[kScatPPT];
+    uint32_t bk[kScatPPT], rk[kScatPPT], id[kScatPPT];
+#pragma unroll
+    for (int k = 0; k < kScatPPT; ++k) {
+      const uint32_t j = k * kScatWG + threadIdx.x;
+      if (j < nround) {
+        const uint32_t gi = ch.start + base + j;
+        v[k] = src[gi];
+        if (IDS) id[k] = src_ids ? src_ids[gi] : gi;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kScatPPT; ++k) {
+      const uint32_t j = k * kScatWG + threadIdx.x;
+      if (j < nround) {
+        uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
+        bk[k] = (uint32_t)(key >> shift) & (B - 1);
+        rk[k] = atomicAdd(&cnt[bk[k]], 1u);
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the round's cell counts (in place); keep counts in registers
+    uint32_t mine[BPT];
+    uint32_t local = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < BPT; ++k) {
+      const uint32_t b = threadIdx.x * BPT + k;
+      mine[k] = b < B ? cnt[b] : 0u;
+      local += mine[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kScatWG>(local, sh, &tot);
+#pragma unroll
+    for (uint32_t k = 0; k < BPT; ++k) {
+      const uint32_t b = threadIdx.x * BPT + k;
+      if (b < B) cnt[b] = ex;
+      ex += mine[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScatPPT; ++k) {
+      const uint32_t j = k * kScatWG + threadIdx.x;
+      if (j < nround) {
+        const uint32_t pos = cnt[bk[k]] + rk[k];
+        stage[pos] = v[k];
+        stage_b[pos] = (uint16_t)bk[k];
+        if (IDS) stage_id[pos] = id[k];
+      }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < nround; j += kScatWG) {
+      const uint32_t b = stage_b[j];
+      const uint32_t d = cursor[b] + (j - cnt[b]);
+      dst[d] = stage[j];
+      if (IDS) dst_ids[d] = stage_id[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < BPT; ++k) {
+      const uint32_t b = threadIdx.x * BPT + k;
+      if (b < B) {
+        cursor[b] += mine[k];
+        cnt[b] = 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Copy the points (and ids) of every segment from one buffer to the other.
+__global__ void k_copy_segments(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
+                                uint4* __restrict__ dst, uint32_t* __restrict__ dst_ids, const Segment* __restrict__ segs,
+                                const uint32_t* nseg_ptr) {
+  const uint32_t s = blockIdx.x;
+  if (s >= *nseg_ptr) return;
+  const Segment sg = segs[s];
+  for (uint32_t i = threadIdx.x; i < sg.count; i += blockDim.x) {
+    dst[sg.start + i] = src[sg.start + i];
+    if (dst_ids) dst_ids[sg.start + i] = src_ids[sg.start + i];
+  }
+}
+
+// One segment per non-empty finest cell of grid `g0` (the root grid), each
+// with its own grid descriptor, to be partitioned by E2 more levels.  One
+// workgroup.
+__global__ void __launch_bounds__(kChunkWG) k_segments_from_grid(GridDesc* grids, uint32_t g0, uint32_t* pool,
+                                                                 uint32_t E2, uint64_t slot_base, uint32_t first_grid,
+                                                                 Segment* segs, uint32_t* nseg_ptr) {
+  __shared__ uint32_t sh[kChunkWG / 64 + 1];
+  const GridDesc g = grids[g0];
+  const uint32_t B = 1u << (3 * g.e);
+  const uint32_t* fin = pool + g.pyr + pyr_level_offset(g.e);
+  const uint32_t* off = pool + g.off;
+  int32_t* child = (int32_t*)(pool + g.child);
+  const uint64_t words = grid_words(E2);
+  uint32_t base = 0;
+  for (uint32_t b0 = 0; b0 < B; b0 += kChunkWG) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t cnt = b < B ? fin[b] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kChunkWG>(cnt ? 1u : 0u, sh, &tot);
+    if (cnt) {
+      const uint32_t s = base + ex;
+      const uint32_t gi = first_grid + s;
+      Segment sg;
+      sg.start = off[b];
+      sg.count = cnt;
+      sg.grid = gi;
+      sg.level = g.base_level + g.e;
+      sg.chunk_begin = 0;
+      sg.chunk_count = 0;
+      sg.key = (g.base_key << (3 * g.e)) | b;
+      segs[s] = sg;
+      GridDesc d;
+      d.base_level = sg.level;
+      d.e = E2;
+      d.base_key = sg.key;
+      d.pyr = slot_base + (uint64_t)s * words;
+      d.off = d.pyr + pyr_level_offset(E2 + 1);
+      d.child = d.off + ((uint64_t)1 << (3 * E2));
+      d.seg_start = sg.start;
+      d.seg_count = cnt;
+      grids[gi] = d;
+      child[b] = (int32_t)gi;
+    }
+    base += tot;
+  }
+  if (threadIdx.x == 0) *nseg_ptr = base;
+}
+
+// The root partition: one segment holding every point, partitioned by the
+// first E0 levels into grid 0 (based at the root).
+__global__ void k_init_root(uint32_t n, uint32_t E0, Segment* segs, uint32_t* nseg_ptr, GridDesc* grids) {
+  if (threadIdx.x != 0) return;
+  Segment sg;
+  sg.start = 0;
+  sg.count = n;
+  sg.grid = 0;
+  sg.level = 0;
+  sg.chunk_begin = 0;
+  sg.chunk_count = 0;
+  sg.key = 0;
+  segs[0] = sg;
+  *nseg_ptr = 1;
+  GridDesc d;
+  d.base_level = 0;
+  d.e = E0;
+  d.base_key = 0;
+  d.pyr = 0;
+  d.off = pyr_level_offset(E0 + 1);
+  d.child = d.off + ((uint64_t)1 << (3 * E0));
+  d.seg_start = 0;
+  d.seg_count = n;
+  grids[0] = d;
+}
+
+// ------------------------------------------------------------ launchers
+
+void launch_bbox(const void* pts, uint64_t n, BBoxAcc* acc, Cube* cube, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, acc);
+  if (n) {
+    uint64_t blocks = (n + kBBoxWG * 4 - 1) / (kBBoxWG * 4);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_bbox, dim3((uint32_t)blocks), dim3(kBBoxWG), 0, st, (const uint4*)pts, n, acc);
+  }
+  hipLaunchKernelGGL(k_cube, dim3(1), dim3(64), 0, st, acc, n, cube);
+}
+
+void launch_init_root(uint32_t n, uint32_t E0, Segment* segs, uint32_t* nseg, GridDesc* grids, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, n, E0, segs, nseg, grids);
+}
+
+void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t chunk, Chunk* chunks, uint32_t* nchunk,
+                        uint32_t max_chunks, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_chunks, dim3(1), dim3(kChunkWG), 0, st, segs, nseg, chunk, chunks, nchunk, max_chunks);
+}
+
+template <int E>
+static void count_e(const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
+                    uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
+  hipLaunchKernelGGL(k_part_count<E>, dim3(max_chunks), dim3(kCountWG), 0, st, (const uint4*)pts, cube, segs, chunks,
+                     nchunk, hist);
+}
+
+void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
+                       const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
+  if (!max_chunks) return;
+  switch (E) {
+    case 1: count_e<1>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 2: count_e<2>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 3: count_e<3>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 4: count_e<4>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    default: break;
+  }
+}
+
+void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t E, uint32_t* hist,
+                         const GridDesc* grids, uint32_t* pool, hipStream_t st) {
+  if (!max_segs) return;
+  const uint64_t threads = (uint64_t)max_segs << (3 * E);
+  const uint32_t blocks = (uint32_t)((threads + 255) / 256);
+  hipLaunchKernelGGL(k_part_colscan, dim3(blocks), dim3(256), 0, st, segs, nseg, E, hist, grids, pool);
+}
+
+void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const GridDesc* grids,
+                        uint32_t* pool, hipStream_t st) {
+  if (!max_segs) return;
+  hipLaunchKernelGGL(k_grid_finish, dim3(max_segs), dim3(kGridWG), 0, st, segs, nseg, grids, pool);
+}
+
+template <int E, bool IDS>
+static void scatter_e(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Cube* cube,
+                      const Segment* segs, const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks,
+                      const uint32_t* hist, const GridDesc* grids, const uint32_t* pool, hipStream_t st) {
+  hipLaunchKernelGGL((k_part_scatter<E, IDS>), dim3(max_chunks), dim3(kScatWG), 0, st, (const uint4*)src, src_ids,
+                     (uint4*)dst, dst_ids, cube, segs, chunks, nchunk, hist, grids, pool);
+}
+
+void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
+                         const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
+                         uint32_t max_chunks, const uint32_t* hist, const GridDesc* grids, const uint32_t* pool,
+                         hipStream_t st) {
+  if (!max_chunks) return;
+#define LOD_SCAT(EE)                                                                                           \
+  case EE:                                                                                                     \
+    if (ids) scatter_e<EE, true>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); \
+    else scatter_e<EE, false>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st);    \
+    break;
+  switch (E) {
+    LOD_SCAT(1)
+    LOD_SCAT(2)
+    LOD_SCAT(3)
+    LOD_SCAT(4)
+    default: break;
+  }
+#undef LOD_SCAT
+}
+
+void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,
+                          const uint32_t* nseg, uint32_t max_segs, hipStream_t st) {
+  if (!max_segs) return;
+  hipLaunchKernelGGL(k_copy_segments, dim3(max_segs), dim3(256), 0, st, (const uint4*)src, src_ids, (uint4*)dst,
+                     dst_ids, segs, nseg);
+}
+
+void launch_segments_from_grid(GridDesc* grids, uint32_t g0, uint32_t* pool, uint32_t E2, uint64_t slot_base,
+                               uint32_t first_grid, Segment* segs, uint32_t* nseg, hipStream_t st) {
+  hipLaunchKernelGGL(k_segments_from_grid, dim3(1), dim3(kChunkWG), 0, st, grids, g0, pool, E2, slot_base, first_grid,
+                     segs, nseg);
+}
+
+}  // namespace lod

@@ -1,0 +1,215 @@
+// k_tree.hip -- octree nodes from the counting grids (Sec. 4.1.2 merging and
+// Sec. 4.1.3 creating target pointers).
+//
+// The paper merges 2x2x2 groups bottom-up while their sum stays within T and
+// no member is unmergeable.  Because a cell's count is the sum of its
+// children's, that procedure yields exactly the nodes of the top-down rule
+// used here: a node is inner iff it holds more than T points and lies above
+// the depth limit, otherwise it is a leaf.  Nodes are enumerated level by
+// level so that they come out in ascending (level, key) order with the
+// children of a node consecutive.  Counts come from the grid pyramids; a node
+// whose children lie below the deepest level of its grid is queued for
+// refinement (the "extended counting grid" of Sec. 4.1.5) and enumeration
+// resumes after it has been partitioned.
+#include "common.h"
+#include "launch.h"
+#include "scan.h"
+
+namespace lod {
+
+__global__ void k_tree_init(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
+                            Nodes nodes, TreeState* st) {
+  if (threadIdx.x != 0) return;
+  const GridDesc g = grids[0];
+  const uint32_t n = pool[g.pyr];  // level 0 of the root grid: all points
+  memset(st, 0, sizeof(TreeState));
+  nodes.level[0] = 0;
+  nodes.key[0] = 0;
+  nodes.npoints[0] = n;
+  const bool inner = n > leaf_cap && max_level > 0;
+  nodes.is_leaf[0] = inner ? 0 : 1;
+  nodes.child_mask[0] = 0;
+  nodes.first_child[0] = 0;
+  nodes.offset[0] = 0;
+  nodes.count[0] = inner ? 0 : n;
+  nodes.cover[0] = 0;
+  nodes.grid[0] = 0;
+  nodes.parent[0] = 0xffffffffu;
+  nodes.aux[0] = 0;
+  nodes.jobofs[0] = 0;
+  st->num_nodes = 1;
+  st->next_level = 0;
+  st->level_begin[0] = 0;
+  st->level_end[0] = 1;
+  st->status = 0;
+}
+
+constexpr int kTreeWG = 1024;
+
+// Enumerate levels until done or until inner nodes need refinement.
+__global__ void __launch_bounds__(kTreeWG) k_tree_build(uint32_t leaf_cap, uint32_t max_level,
+                                                        const GridDesc* __restrict__ grids,
+                                                        const uint32_t* __restrict__ pool, Nodes nodes, TreeState* st,
+                                                        uint32_t* refine, uint32_t* leaf_refine, uint32_t max_nodes) {
+  __shared__ uint32_t sh[kTreeWG / 64 + 1];
+  __shared__ uint32_t s_need, s_inner, s_nref, s_nlref;
+  uint32_t L = st->next_level;
+  uint32_t num = st->num_nodes;
+  if (threadIdx.x == 0) {
+    s_nref = st->num_refine = 0;
+    s_nlref = st->num_leaf_refine;
+  }
+  __syncthreads();
+  for (;;) {
+    if (L >= max_level) {
+      if (threadIdx.x == 0) { st->status = 1; st->next_level = L; }
+      break;
+    }
+    const uint32_t b = st->level_begin[L], e = st->level_end[L];
+    if (threadIdx.x == 0) { s_need = 0; s_inner = 0; }
+    __syncthreads();
+    const uint32_t first_new = num;
+    for (uint32_t c0 = b; c0 < e; c0 += kTreeWG / 8) {
+      const uint32_t j = c0 + threadIdx.x / 8;
+      const uint32_t o = threadIdx.x & 7u;
+      uint32_t cnt = 0, idx = 0, r = 0;
+      int32_t cov = -1;
+      uint64_t ck = 0;
+      GridDesc G;
+      if (j < e && !nodes.is_leaf[j]) {
+        cov = nodes.grid[j] >= 0 ? nodes.grid[j] : nodes.cover[j];
+        G = grids[cov];
+        ck = (nodes.key[j] << 3) | o;
+        r = L + 1 - G.base_level;
+        idx = (uint32_t)(ck - (G.base_key << (3 * r)));
+        cnt = pool[G.pyr + pyr_level_offset(r) + idx];
+      }
+      const uint32_t exists = cnt > 0 ? 1u : 0u;
+      uint32_t tot;
+      const uint32_t pos = block_excl_scan<kTreeWG>(exists, sh, &tot);
+      const uint64_t bal = __ballot(exists);
+      const uint32_t grp = (uint32_t)((bal >> (lane_id() & ~7u)) & 0xffu);
+      if (exists) {
+        const uint32_t n = num + pos;
+        if (n < max_nodes) {
+          const uint32_t lvl = L + 1;
+          const bool inner = cnt > leaf_cap && lvl < max_level;
+          const uint32_t D = G.base_level + G.e;
+          int32_t gchild = -1;
+          if (r == G.e) gchild = ((const int32_t*)(pool + G.child))[idx];
+          nodes.level[n] = (uint8_t)lvl;
+          nodes.key[n] = ck;
+          nodes.npoints[n] = cnt;
+          nodes.is_leaf[n] = inner ? 0 : 1;
+          nodes.child_mask[n] = 0;
+          nodes.first_child[n] = 0;
+          nodes.offset[n] = pool[G.off + ((uint64_t)idx << (3 * (G.e - r)))];
+          nodes.count[n] = inner ? 0 : cnt;
+          nodes.cover[n] = cov;
+          nodes.grid[n] = gchild;
+          nodes.parent[n] = j;
+          nodes.aux[n] = 0;
+          nodes.jobofs[n] = 0;
+          if (inner) {
+            atomicOr(&s_inner, 1u);
+            if (r == G.e && gchild < 0) {
+              atomicOr(&s_need, 1u);
+              refine[atomicAdd(&s_nref, 1u)] = n;
+            }
+          } else {
+            const uint32_t sd = gchild >= 0 ? grids[gchild].base_level + grids[gchild].e : D;
+            if (sd < lvl + 2) leaf_refine[atomicAdd(&s_nlref, 1u)] = n;
+          }
+        }
+        // the lowest existing octant of each parent records its children
+        if ((grp & ((1u << o) - 1u)) == 0) {
+          nodes.first_child[j] = n;
+          nodes.child_mask[j] = (uint8_t)grp;
+        }
+      }
+      num += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      st->level_begin[L + 1] = first_new;
+      st->level_end[L + 1] = num;
+      if (num > max_nodes) st->overflow = 1;
+    }
+    L += 1;
+    const bool need = s_need != 0;
+    const bool any_inner = s_inner != 0;
+    __syncthreads();
+    if (num > max_nodes) {
+      if (threadIdx.x == 0) { st->status = 1; st->next_level = L; }
+      break;
+    }
+    if (need) {
+      if (threadIdx.x == 0) { st->status = 2; st->next_level = L; }
+      break;
+    }
+    if (!any_inner) {
+      if (threadIdx.x == 0) { st->status = 1; st->next_level = L; }
+      break;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->num_nodes = min(num, max_nodes);
+    st->num_refine = s_nref;
+    st->num_leaf_refine = s_nlref;
+  }
+}
+
+// Segments (and grid descriptors) for nodes that need a deeper partition:
+// each gets an extended grid of E levels below the node (Sec. 4.1.5).
+__global__ void k_refine_segments(Nodes nodes, const uint32_t* list, const uint32_t* nlist_ptr, uint32_t E,
+                                  uint32_t first_grid, uint64_t slot_base, GridDesc* grids, Segment* segs,
+                                  uint32_t* nseg_ptr) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nl = *nlist_ptr;
+  if (r == 0) *nseg_ptr = nl;
+  if (r >= nl) return;
+  const uint32_t n = list[r];
+  const uint32_t gi = first_grid + r;
+  Segment sg;
+  sg.start = (uint32_t)nodes.offset[n];
+  sg.count = nodes.npoints[n];
+  sg.grid = gi;
+  sg.level = nodes.level[n];
+  sg.chunk_begin = 0;
+  sg.chunk_count = 0;
+  sg.key = nodes.key[n];
+  segs[r] = sg;
+  GridDesc d;
+  d.base_level = sg.level;
+  d.e = E;
+  d.base_key = sg.key;
+  d.pyr = slot_base + (uint64_t)r * grid_words(E);
+  d.off = d.pyr + pyr_level_offset(E + 1);
+  d.child = d.off + ((uint64_t)1 << (3 * E));
+  d.seg_start = sg.start;
+  d.seg_count = sg.count;
+  grids[gi] = d;
+  nodes.grid[n] = (int32_t)gi;
+}
+
+void launch_tree_init(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
+                      const Nodes& nodes, TreeState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_tree_init, dim3(1), dim3(64), 0, s, leaf_cap, max_level, grids, pool, nodes, st);
+}
+
+void launch_tree_build(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
+                       const Nodes& nodes, TreeState* st, uint32_t* refine, uint32_t* leaf_refine, uint32_t max_nodes,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_tree_build, dim3(1), dim3(kTreeWG), 0, s, leaf_cap, max_level, grids, pool, nodes, st, refine,
+                     leaf_refine, max_nodes);
+}
+
+void launch_refine_segments(const Nodes& nodes, const uint32_t* list, const uint32_t* nlist, uint32_t max_list,
+                            uint32_t E, uint32_t first_grid, uint64_t slot_base, GridDesc* grids, Segment* segs,
+                            uint32_t* nseg, hipStream_t s) {
+  const uint32_t blocks = (max_list + 255) / 256;
+  hipLaunchKernelGGL(k_refine_segments, dim3(blocks ? blocks : 1), dim3(256), 0, s, nodes, list, nlist, E, first_grid,
+                     slot_base, grids, segs, nseg);
+}
+
+}  // namespace lod

@@ -1,0 +1,65 @@
+"""The C ABI library loads and exports every entry point that include/lod.h
+declares; host-only argument checks (no GPU work) behave as documented."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lod.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lod_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2302_14801_amd import binding
+    return binding.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "lod_build" in names and "lod_build_batch" in names and "lod_submit" in names and "lod_poll" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in lod.h but not exported"
+
+
+def test_params_default_and_status_strings(lib):
+    from paper_2302_14801_amd import binding
+    p = binding.lod_params()
+    lib.lod_params_default(ctypes.byref(p))
+    assert (p.leaf_cap, p.max_level, p.sampling) == (50000, 12, 0)
+    for st in range(-7, 2):
+        assert lib.lod_status_str(st).decode().startswith("LOD_")
+
+
+def test_argument_errors_before_any_device_work(lib):
+    from paper_2302_14801_amd import binding
+    p = binding.lod_params()
+    lib.lod_params_default(ctypes.byref(p))
+    out = ctypes.c_void_p()
+    assert lib.lod_build(None, 10, ctypes.byref(p), None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    assert lib.lod_build(None, 0, ctypes.byref(p), None, None) == binding.LOD_ERR_INVALID
+    p.leaf_cap = 0
+    assert lib.lod_build(None, 0, ctypes.byref(p), None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    p.leaf_cap, p.max_level = 10, 15
+    assert lib.lod_build(None, 0, ctypes.byref(p), None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    p.max_level = 12
+    assert lib.lod_server_create(0, 1, ctypes.byref(p), ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    assert lib.lod_poll(None, 1, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    assert b"invalid" in lib.lod_last_error()
+
+
+def test_package_refuses_to_import_without_library(tmp_path, monkeypatch):
+    from paper_2302_14801_amd import binding
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(OSError):
+        binding.load_library()

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element on the same seeded inputs.  Integer work is compared
+bit-exactly; the only floating-point step (quantization) is part of it."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import canon
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2302_14801_amd as lod
+    return lod
+
+
+def to_dev(points):
+    import torch
+    raw = np.ascontiguousarray(points).view(np.uint8).reshape(-1)
+    return torch.from_numpy(raw.copy()).to("cuda:0")
+
+
+def gpu_tree(lod, points, **kw):
+    t = lod.lod_build(to_dev(points), **kw)
+    h = t.to_host()
+    t.free()
+    return h
+
+
+def check(lod, points, T=50000, ml=12, sampling=0, seed=0, keep_ids=False, **extra):
+    print(f"case n={len(points)} T={T} ml={ml} sampling={sampling}", flush=True)
+    g = gpu_tree(lod, points, leaf_cap=T, max_level=ml, sampling=sampling, seed=seed, keep_ids=keep_ids, **extra)
+    o = oracle.build(points, leaf_cap=T, max_level=ml, sampling=sampling, seed=seed)
+    canon.compare_trees(g, o, points)
+    return g, o
+
+
+RANDOM_CASES = [(50, 1, 2), (300, 3, 4), (800, 7, 12), (2000, 50, 12), (1500, 1, 6), (2000, 100, 3),
+                (20000, 200, 12), (60000, 1000, 14), (150000, 4000, 12)]
+
+
+@pytest.mark.parametrize("sampling", [0, 1, 2])
+@pytest.mark.parametrize("n,T,ml", RANDOM_CASES)
+def test_uniform_clouds(lod, n, T, ml, sampling):
+    p = synth.uniform_cloud(n, 1000 + n, lo=(-3, 10, 100), hi=(5, 12, 101))
+    check(lod, p, T, ml, sampling, seed=77)
+
+
+@pytest.mark.parametrize("sampling", [0, 1, 2])
+def test_terrain_small(lod, sampling):
+    p = synth.terrain(200_000, seed=5)
+    check(lod, p, T=5000, ml=12, sampling=sampling, seed=3)
+
+
+def test_aerial_small(lod):
+    p = synth.aerial(400_000, seed=2)
+    check(lod, p, T=10000, ml=12)
+
+
+def test_scan_small(lod):
+    p = synth.scan(300_000, seed=3)
+    check(lod, p, T=2000, ml=14)
+
+
+def test_terrain_1m_config(lod):
+    """The 1M-point terrain plain build (T = 50 000, 128^3, colour-filtered), in full."""
+    p = synth.terrain(1_000_000, seed=1)
+    g, o = check(lod, p, T=50000, ml=12)
+    assert g["num_voxels"] > 0
+
+
+def test_keep_ids_average(lod):
+    p = synth.uniform_cloud(5000, 4)
+    g, _ = check(lod, p, T=40, ml=12, keep_ids=True)
+    assert g["point_ids"] is not None
+
+
+def test_empty(lod):
+    g = gpu_tree(lod, np.zeros(0, synth.POINT_DTYPE))
+    assert g["num_nodes"] == 0 and g["num_voxels"] == 0
+
+
+def test_single_point_and_small(lod):
+    check(lod, synth.uniform_cloud(1, 3), T=1)
+    check(lod, synth.uniform_cloud(49, 3), T=50)
+
+
+def test_identical_points_chain_to_depth_limit(lod):
+    p = np.zeros(1000, synth.POINT_DTYPE)
+    p["x"], p["y"], p["z"] = 1.5, -2.0, 7.0
+    p["r"] = np.arange(1000) % 256
+    p[-1]["x"] = 9.0
+    for s in (0, 1, 2):
+        g, _ = check(lod, p, T=10, ml=9, sampling=s)
+        assert g["level"].max() == 9
+
+
+def test_huge_micro_bucket_wide_path(lod):
+    # 70 000 coincident points in one oversize leaf at the depth limit
+    p = np.zeros(70_010, synth.POINT_DTYPE)
+    p["x"], p["y"], p["z"] = 3.0, 3.0, 3.0
+    rng = np.random.default_rng(1)
+    p["r"] = rng.integers(0, 256, len(p))
+    p["g"] = rng.integers(0, 256, len(p))
+    p["b"] = rng.integers(0, 256, len(p))
+    p["x"][-10:] = rng.uniform(0, 10, 10).astype(np.float32)
+    check(lod, p, T=100, ml=5)
+
+
+def test_lattice_and_max_face(lod):
+    s = 8
+    g1 = np.arange(s, dtype=np.float32)
+    xs, ys, zs = np.meshgrid(g1, g1, g1, indexing="ij")
+    p = np.zeros(s ** 3, synth.POINT_DTYPE)
+    p["x"], p["y"], p["z"] = xs.ravel(), ys.ravel(), zs.ravel()
+    p["g"] = np.arange(s ** 3) % 251
+    for T in (1, 2, 7):
+        check(lod, p, T=T, ml=12)
+
+
+def test_teapot_in_stadium(lod):
+    a = synth.uniform_cloud(20000, 1, lo=(0, 0, 0), hi=(1000, 1000, 1000))
+    b = synth.uniform_cloud(80000, 2, lo=(400, 400, 400), hi=(400.05, 400.05, 400.05))
+    p = np.concatenate([a, b])
+    for s in (0, 2):
+        g, _ = check(lod, p, T=500, ml=14, sampling=s, seed=5)
+        assert g["level"].max() >= 12
+
+
+def test_extreme_coordinates(lod):
+    p = synth.uniform_cloud(3000, 9, lo=(-1e6, 1e-6, -3e5), hi=(1e6, 2e-6, 3e5))
+    check(lod, p, T=20, ml=14)
+
+
+def test_nonfinite_rejected(lod):
+    p = synth.uniform_cloud(1000, 1)
+    p["z"][500] = np.inf
+    with pytest.raises(lod.LodError) as e:
+        lod.lod_build(to_dev(p))
+    assert e.value.status == -2
+
+
+def test_invalid_params_rejected(lod):
+    d = to_dev(synth.uniform_cloud(100, 1))
+    for kw in ({"leaf_cap": 0}, {"max_level": 15}, {"sampling": 3}):
+        with pytest.raises(lod.LodError) as e:
+            lod.lod_build(d, **kw)
+        assert e.value.status == -1
+
+
+def test_tuning_and_repeat_do_not_change_results(lod):
+    p = synth.terrain(300_000, seed=8)
+    base = gpu_tree(lod, p, leaf_cap=3000, max_level=12)
+    again = gpu_tree(lod, p, leaf_cap=3000, max_level=12)
+    for k in ("level", "key", "npoints", "count", "voxels"):
+        assert np.array_equal(base[k], again[k])
+    for t0, t1 in ((1, 1), (2, 4), (4, 2), (3, 3), (4, 4)):
+        params = lod.make_params(leaf_cap=3000, max_level=12, tune_levels0=t0, tune_levels1=t1)
+        t = lod.lod_build(to_dev(p), params=params)
+        h = t.to_host()
+        t.free()
+        for k in ("level", "key", "npoints", "count", "first_child", "voxels"):
+            assert np.array_equal(base[k], h[k]), (t0, t1, k)
+
+
+def test_input_order_invariance(lod):
+    p = synth.aerial(200_000, seed=12)
+    perm = np.random.default_rng(0).permutation(len(p))
+    a = gpu_tree(lod, p, leaf_cap=5000)
+    b = gpu_tree(lod, p[perm], leaf_cap=5000)
+    for k in ("level", "key", "npoints", "count", "voxels"):
+        assert np.array_equal(a[k], b[k])
+    # pick results follow the ids, so compare with the oracle on the permuted input
+    check(lod, p[perm], T=5000, sampling=1)
+
+
+def test_batch_equals_single_builds(lod):
+    sizes = [3000, 50, 120000, 0, 40000, 777]
+    pts, offs = synth.batch_chunks(sizes, seed=4)
+    trees = lod.lod_build_batch(to_dev(pts), offs, leaf_cap=2000, max_level=12)
+    assert len(trees) == len(sizes)
+    for i, t in enumerate(trees):
+        chunk = pts[offs[i]:offs[i + 1]]
+        g = t.to_host()
+        t.free()
+        o = oracle.build(chunk, leaf_cap=2000, max_level=12)
+        canon.compare_trees(g, o, chunk)
+
+
+def test_server_results_equal_alone_and_in_mix(lod):
+    sizes = [200_000, 5_000, 80_000, 1, 150_000, 30_000, 90_000, 10]
+    pts, offs = synth.batch_chunks(sizes, seed=6)
+    chunks = [np.ascontiguousarray(pts[offs[i]:offs[i + 1]]) for i in range(len(sizes))]
+    srv = lod.lod_server_create(8 << 30, 3, leaf_cap=4000, max_level=12)
+    tickets = [srv.submit(c) for c in chunks]
+    import time
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for i, tk in enumerate(tickets):
+            if i not in done:
+                r = srv.poll(tk)
+                if r is not None:
+                    done[i] = r
+        assert time.time() - t0 < 120
+        time.sleep(0.001)
+    for i, c in enumerate(chunks):
+        g = done[i].to_host()
+        alone = gpu_tree(lod, c, leaf_cap=4000, max_level=12)
+        for k in ("level", "key", "npoints", "count", "first_child", "voxels"):
+            assert np.array_equal(g[k], alone[k]), (i, k)
+        canon.compare_trees(g, oracle.build(c, leaf_cap=4000, max_level=12), c)
+        done[i].free()
+    with pytest.raises(lod.LodError) as e:
+        srv.poll(987654)
+    assert e.value.status == -6
+    srv.destroy()
+
+
+def test_server_rejects_too_large(lod):
+    srv = lod.lod_server_create(1 << 20, 1, leaf_cap=1000)
+    with pytest.raises(lod.LodError) as e:
+        srv.submit(synth.uniform_cloud(100_000, 1))
+    assert e.value.status == -5
+    srv.destroy()
+
+
+if __name__ == "__main__":
+    sys.exit(pytest.main([__file__, "-x", "-v"]))
