@@ -1,0 +1,173 @@
+"""Benchmark: LOD octree build throughput on one MI355X.
+
+Default workload: the 100M-point aerial scene (1 x 1 km: 70% terrain, 20% box
+buildings, 10% Gaussian vegetation; float32 xyz + uint8 RGBA), leaf cap
+50 000, 128^3 voxel grid per inner node, colour-filtered (cell average).  One
+step = one complete lod_build of the whole cloud (bounding box, both
+partition passes, node enumeration, leaf and inner voxels, output tables)
+plus lod_tree_free, with the input already resident in HBM.
+
+Prints one JSON line with the throughput (points/s), the roofline of the
+dominant kernel (algorithmic bytes per launch over its average duration,
+measured with HIP events on the build stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "points/s LOD build (color-filtered, 100M pts), batched vs plain; p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "aerial100m": dict(n=100_000_000, gen="aerial", seed=2,
+                       desc="aerial 1x1 km: 70% terrain, 20% on 200 box buildings, 10% in 2000 Gaussian blobs"),
+    "terrain1m": dict(n=1_000_000, gen="terrain", seed=1, desc="terrain heightfield 100x100 m"),
+}
+SAMPLING = {"average": 0, "first": 1, "random": 2}
+
+
+def stage_bytes(stage: str, n: int, ids: bool) -> float:
+    """Algorithmic bytes of one launch of a stage: each 16-byte record pass
+    counted once (reads and writes), ids 4 bytes per point when carried."""
+    idb = 4 if ids else 0
+    return {
+        "bbox": 16.0 * n,
+        "count0": 16.0 * n,
+        "scatter0": (16.0 + 16.0 + idb) * n,
+        "count1": 16.0 * n,
+        "scatter1": (16.0 + idb + 16.0 + idb) * n,
+        "leaf_voxels": (16.0 + idb) * n,
+    }.get(stage, 0.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="aerial100m", choices=sorted(WORKLOADS))
+    ap.add_argument("--sampling", default="average", choices=sorted(SAMPLING))
+    ap.add_argument("--leaf-cap", type=int, default=50000)
+    ap.add_argument("--max-level", type=int, default=12)
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000,
+                    help="points of the workload the CPU oracle builds (0 = skip)")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="run one plain device copy of the input first (known bytes, for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this builder has no multi-GPU path "
+              "(chunks of a batch shard trivially across GPUs; see DESIGN.md). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2302_14801_amd as lod
+    import synth
+
+    wl = WORKLOADS[args.workload]
+    n = wl["n"]
+    sampling = SAMPLING[args.sampling]
+    ids = sampling != 0
+    print(f"[bench] generating {n} points ({args.workload})", file=sys.stderr, flush=True)
+    host = torch.empty(n * 16, dtype=torch.uint8, pin_memory=True)
+    pts = host.numpy().view(synth.POINT_DTYPE)
+    getattr(synth, wl["gen"])(n, seed=wl["seed"], out=pts)
+    dev = host.to("cuda:0", non_blocking=False)
+    stream = torch.cuda.current_stream()
+    params = lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling, timing=True)
+
+    def step():
+        t = lod.lod_build(dev, params=params, stream=stream)
+        tm = t.timings()
+        v = t.view()
+        info = (v.num_nodes, v.num_voxels)
+        t.free()
+        return tm, info
+
+    if args.profile_copy:
+        cp = torch.empty_like(dev)
+        cp.copy_(dev)
+        torch.cuda.synchronize()
+        del cp
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stages, infos = [], []
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tm, info = step()
+        stages.append(tm)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n * args.steps / elapsed
+
+    avg = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    single = ["bbox", "count0", "scatter0", "count1", "scatter1", "leaf_voxels"]
+    dom = max(single, key=lambda k: avg[k])
+    alg = stage_bytes(dom, n, ids)
+    achieved = alg / (avg[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(avg[dom], 4)}
+    whole_alg = sum(stage_bytes(k, n, ids) for k in single)
+    nodes, voxels = infos[-1]
+
+    cpu = None
+    if args.cpu_sample > 0:
+        import oracle
+        sample = min(args.cpu_sample, n)
+        print(f"[bench] CPU oracle on the first {sample} points", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        oracle.build(pts[:sample], leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling)
+        c1 = time.perf_counter()
+        cpu = {"value": round(sample / (c1 - c0), 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {sample} points of the same {args.workload} cloud (a uniform subsample: the "
+                         f"generator interleaves scene components at random); single-threaded C oracle, "
+                         f"build only, {c1 - c0:.2f} s"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"plain build, {wl['desc']}", "points": n, "leaf_cap": args.leaf_cap,
+                   "max_level": args.max_level, "grid": 128, "sampling": args.sampling,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_ms": {k: round(v, 4) for k, v in avg.items()},
+        "whole_build_alg_GBps": round(whole_alg / (ms_per_step * 1e-3) / 1e9, 1),
+        "nodes": nodes,
+        "voxels": voxels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

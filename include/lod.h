@@ -71,7 +71,10 @@ typedef struct {
  * Pick modes copy the winner's R, G, B, A and record its input index. */
 typedef enum { LOD_AVERAGE = 0, LOD_PICK_FIRST = 1, LOD_PICK_RANDOM = 2 } lod_sampling;
 
-enum { LOD_FLAG_POINT_IDS = 1 }; /* keep each leaf point's input index (implied by pick modes) */
+enum {
+  LOD_FLAG_POINT_IDS = 1, /* keep each leaf point's input index (implied by pick modes) */
+  LOD_FLAG_TIMING = 2     /* record HIP events around every stage (lod_tree_timings) */
+};
 
 typedef struct {
   uint32_t leaf_cap;     /* T (Sec. 3): a node with more than T points is split; default 50000; >= 1 */
@@ -80,8 +83,8 @@ typedef struct {
   uint32_t sampling;     /* lod_sampling */
   uint32_t seed;         /* LOD_PICK_RANDOM only */
   uint32_t flags;        /* LOD_FLAG_* */
-  uint32_t tune_levels0; /* 0 = automatic; else levels sorted by the first partition pass (1..5) */
-  uint32_t tune_levels1; /* 0 = automatic; else levels sorted by the second pass (1..5) */
+  uint32_t tune_levels0; /* 0 = automatic; else levels sorted by the first partition pass (1..4) */
+  uint32_t tune_levels1; /* 0 = automatic; else levels sorted by the second pass (1..4) */
   uint32_t reserved;
 } lod_params;
 
@@ -136,6 +139,23 @@ lod_status lod_build(const lod_point* d_points, uint64_t n, const lod_params* p,
  * num_chunks handles, filled on success.  Result i equals lod_build on chunk i. */
 lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets, uint32_t num_chunks,
                            const lod_params* p, void* hip_stream, lod_tree** out);
+
+/* Per-stage device times in milliseconds of the build that made the tree,
+ * measured with HIP events on the build stream (only with LOD_FLAG_TIMING;
+ * otherwise all zero).  Stages: bounding box; the first partition (count,
+ * offsets, insert); the second partition (count, offsets, insert); node
+ * enumeration including refinement partitions; leaf voxels; inner levels;
+ * and the whole build from the first to the last kernel. */
+typedef struct {
+  float bbox;
+  float count0, offsets0, scatter0;
+  float count1, offsets1, scatter1;
+  float tree;
+  float leaf_voxels;
+  float levels;
+  float total;
+} lod_timings;
+lod_status lod_tree_timings(const lod_tree* t, lod_timings* out);
 
 /* Copy of the tree's header and device array pointers. */
 lod_status lod_tree_view_get(const lod_tree* t, lod_tree_view* v);

@@ -19,6 +19,7 @@ LOD_ERR_INVALID, LOD_ERR_NONFINITE, LOD_ERR_OOM, LOD_ERR_CAPACITY = -1, -2, -3, 
 LOD_ERR_TOO_LARGE, LOD_ERR_UNKNOWN_TICKET, LOD_ERR_HIP = -5, -6, -7
 LOD_AVERAGE, LOD_PICK_FIRST, LOD_PICK_RANDOM = 0, 1, 2
 LOD_FLAG_POINT_IDS = 1
+LOD_FLAG_TIMING = 2
 
 
 class LodError(RuntimeError):
@@ -45,7 +46,14 @@ class lod_tree_view(ctypes.Structure):
                 ("voxels", ctypes.c_void_p), ("voxel_ids", ctypes.c_void_p)]
 
 
+class lod_timings(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_float) for name in
+                ("bbox", "count0", "offsets0", "scatter0", "count1", "offsets1", "scatter1", "tree",
+                 "leaf_voxels", "levels", "total")]
+
+
 EXPORTED = ["lod_params_default", "lod_build", "lod_build_batch", "lod_tree_view_get", "lod_tree_free",
+            "lod_tree_timings",
             "lod_server_create", "lod_submit", "lod_poll", "lod_server_destroy", "lod_status_str",
             "lod_last_error"]
 
@@ -70,6 +78,8 @@ def load_library():
     lib.lod_build_batch.restype = ctypes.c_int
     lib.lod_tree_view_get.argtypes = [vp, P(lod_tree_view)]
     lib.lod_tree_view_get.restype = ctypes.c_int
+    lib.lod_tree_timings.argtypes = [vp, P(lod_timings)]
+    lib.lod_tree_timings.restype = ctypes.c_int
     lib.lod_tree_free.argtypes = [vp]
     lib.lod_tree_free.restype = None
     lib.lod_server_create.argtypes = [u64, u32, P(lod_params), P(vp)]
@@ -102,11 +112,11 @@ def _check(status: int):
 
 
 def make_params(leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0, keep_ids=False,
-                tune_levels0=0, tune_levels1=0) -> lod_params:
+                tune_levels0=0, tune_levels1=0, timing=False) -> lod_params:
     p = lod_params()
     load_library().lod_params_default(ctypes.byref(p))
     p.leaf_cap, p.max_level, p.sampling, p.seed = leaf_cap, max_level, sampling, seed
-    p.flags = LOD_FLAG_POINT_IDS if keep_ids else 0
+    p.flags = (LOD_FLAG_POINT_IDS if keep_ids else 0) | (LOD_FLAG_TIMING if timing else 0)
     p.tune_levels0, p.tune_levels1 = tune_levels0, tune_levels1
     return p
 
@@ -136,6 +146,11 @@ class Tree:
         v = lod_tree_view()
         _check(load_library().lod_tree_view_get(self.handle, ctypes.byref(v)))
         return v
+
+    def timings(self) -> dict:
+        t = lod_timings()
+        _check(load_library().lod_tree_timings(self.handle, ctypes.byref(t)))
+        return {name: float(getattr(t, name)) for name, _ in lod_timings._fields_}
 
     def free(self):
         if self.handle:

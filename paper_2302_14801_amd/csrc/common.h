@@ -161,12 +161,22 @@ struct Segment {
   uint32_t chunk_begin;
   uint32_t chunk_count;
   uint64_t key;  // prefix at `level`
+  uint32_t group_begin;
+  uint32_t group_count;
 };
 struct Chunk {
   uint32_t seg;
   uint32_t start;
   uint32_t count;
   uint32_t pad;
+};
+// A run of at most kGroupChunks consecutive chunks of one segment (column scans).
+constexpr uint32_t kGroupChunks = 32;
+struct ChunkGroup {
+  uint32_t seg;
+  uint32_t first;  // first chunk
+  uint32_t count;  // chunks in the group
+  uint32_t index;  // group index within its segment
 };
 
 // Node table (struct of arrays), nodes in ascending (level, key) order.
@@ -184,6 +194,8 @@ struct Nodes {
   uint32_t* parent;
   uint32_t* aux;    // per-node scratch: leaf voxel count / run count
   uint32_t* jobofs; // offset of the node's contribution inside its parent's voxel list
+  uint64_t* dstbase;  // inner node: where its contribution to the parent's list starts
+  uint32_t* firstrun; // inner node: level-wide index of its first run
 };
 
 // Tree-builder state shared between launches (device memory).
@@ -198,6 +210,12 @@ struct TreeState {
   uint32_t level_end[23];
   uint64_t voxel_total;    // running total while voxel lists are assembled
   uint64_t voxel_bound;    // capacity needed for all voxel lists
+  uint64_t level_vbegin[23];  // voxels of the inner nodes of a level: [vbegin, vbegin + vcount)
+  uint64_t level_vcount[23];
+  uint32_t level_ibegin[23];  // their node ids / voxel offsets in the inner lists: [ibegin, iend)
+  uint32_t level_iend[23];
+  uint32_t inner_total;
+  uint32_t num_tiles;
 };
 
 }  // namespace lod

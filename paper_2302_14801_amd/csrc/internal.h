@@ -96,6 +96,7 @@ inline DeviceCache& cache() {
 struct lod_tree {
   int dev = 0;
   lod_tree_view v{};
+  lod_timings timings{};
   std::vector<void*> blocks;
   uint64_t footprint = 0;
   std::shared_ptr<std::atomic<uint64_t>> budget_used;  // server accounting, if any

@@ -104,36 +104,80 @@ __global__ void k_cube(const BBoxAcc* acc, uint64_t n, Cube* cube) {
 
 // ------------------------------------------------------------ partition
 
-// Split every segment into chunks of at most `chunk` points.  One workgroup.
+// Split every segment into chunks of at most `chunk` points and the chunks
+// into groups of at most kGroupChunks (one workgroup: prefix sums only).
 constexpr int kChunkWG = 1024;
-__global__ void __launch_bounds__(kChunkWG) k_make_chunks(Segment* segs, const uint32_t* nseg_ptr, uint32_t chunk,
-                                                          Chunk* chunks, uint32_t* nchunk_ptr, uint32_t max_chunks) {
+__global__ void __launch_bounds__(kChunkWG) k_chunk_scan(Segment* segs, const uint32_t* nseg_ptr, uint32_t chunk,
+                                                         uint32_t* nchunk_ptr, uint32_t max_chunks,
+                                                         uint32_t* ngroup_ptr, uint32_t max_groups) {
   __shared__ uint32_t sh[kChunkWG / 64 + 1];
   const uint32_t nseg = *nseg_ptr;
-  uint32_t base = 0;
+  uint32_t cbase = 0, gbase = 0;
   for (uint32_t s0 = 0; s0 < nseg; s0 += kChunkWG) {
-    uint32_t s = s0 + threadIdx.x;
-    uint32_t cnt = 0;
-    if (s < nseg) cnt = (segs[s].count + chunk - 1) / chunk;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<kChunkWG>(cnt, sh, &tot);
+    const uint32_t s = s0 + threadIdx.x;
+    uint32_t cnt = 0, grp = 0;
     if (s < nseg) {
-      uint32_t first = base + ex;
-      segs[s].chunk_begin = first;
-      segs[s].chunk_count = cnt;
-      for (uint32_t k = 0; k < cnt; ++k) {
-        if (first + k >= max_chunks) break;
-        Chunk c;
-        c.seg = s;
-        c.start = segs[s].start + k * chunk;
-        c.count = min(chunk, segs[s].count - k * chunk);
-        c.pad = 0;
-        chunks[first + k] = c;
-      }
+      cnt = (segs[s].count + chunk - 1) / chunk;
+      grp = (cnt + kGroupChunks - 1) / kGroupChunks;
     }
-    base += tot;
+    uint32_t ctot, gtot;
+    const uint32_t cex = block_excl_scan<kChunkWG>(cnt, sh, &ctot);
+    const uint32_t gex = block_excl_scan<kChunkWG>(grp, sh, &gtot);
+    if (s < nseg) {
+      segs[s].chunk_begin = cbase + cex;
+      segs[s].chunk_count = cnt;
+      segs[s].group_begin = gbase + gex;
+      segs[s].group_count = grp;
+    }
+    cbase += ctot;
+    gbase += gtot;
   }
-  if (threadIdx.x == 0) *nchunk_ptr = min(base, max_chunks);
+  if (threadIdx.x == 0) {
+    *nchunk_ptr = min(cbase, max_chunks);
+    *ngroup_ptr = min(gbase, max_groups);
+  }
+}
+
+// Largest segment index whose `first` field is <= x (segments are ordered).
+__device__ __forceinline__ uint32_t find_segment(const Segment* segs, uint32_t nseg, uint32_t x, bool groups) {
+  uint32_t lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    const uint32_t f = groups ? segs[mid].group_begin : segs[mid].chunk_begin;
+    if (f <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_chunk_fill(const Segment* __restrict__ segs, const uint32_t* nseg_ptr, uint32_t chunk,
+                             Chunk* chunks, const uint32_t* nchunk_ptr, ChunkGroup* groups,
+                             const uint32_t* ngroup_ptr) {
+  const uint32_t nseg = *nseg_ptr, nchunk = *nchunk_ptr, ngroup = *ngroup_ptr;
+  if (nseg == 0) return;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nchunk; c += stride) {
+    const uint32_t s = find_segment(segs, nseg, c, false);
+    const Segment sg = segs[s];
+    const uint32_t k = c - sg.chunk_begin;
+    Chunk ch;
+    ch.seg = s;
+    ch.start = sg.start + k * chunk;
+    ch.count = min(chunk, sg.count - k * chunk);
+    ch.pad = 0;
+    chunks[c] = ch;
+  }
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroup; g += stride) {
+    const uint32_t s = find_segment(segs, nseg, g, true);
+    const Segment sg = segs[s];
+    const uint32_t k = g - sg.group_begin;
+    ChunkGroup gr;
+    gr.seg = s;
+    gr.first = sg.chunk_begin + k * kGroupChunks;
+    gr.count = min(kGroupChunks, sg.chunk_count - k * kGroupChunks);
+    gr.index = k;
+    groups[g] = gr;
+  }
 }
 
 // Count one chunk into an LDS histogram of B = 8^E cells and write the row.
@@ -171,26 +215,54 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) row[j] = h[j];
 }
 
-// Column scan: for every (segment, cell) turn the chunk rows into exclusive
-// offsets within the segment, and store the segment's cell totals as the
-// finest level of its grid.
-__global__ void k_part_colscan(const Segment* __restrict__ segs, const uint32_t* nseg_ptr, uint32_t E,
-                               uint32_t* __restrict__ hist, const GridDesc* __restrict__ grids, uint32_t* pool) {
+// Column scan of the chunk rows, in three steps so that no thread walks more
+// than kGroupChunks rows: (1) per (group, cell) sums, (2) per (segment, cell)
+// exclusive scan over the segment's groups, whose total is the segment's cell
+// count (the finest level of its grid), (3) per (group, cell) rewrite of the
+// rows as exclusive offsets within the segment.
+__global__ void k_colscan_groups(const ChunkGroup* __restrict__ groups, const uint32_t* ngroup_ptr, uint32_t E,
+                                 const uint32_t* __restrict__ hist, uint32_t* __restrict__ gsum) {
   const uint32_t B = 1u << (3 * E);
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t s = (uint32_t)(t >> (3 * E));
-  const uint32_t b = (uint32_t)(t & (B - 1));
+  const uint32_t g = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
+  if (g >= *ngroup_ptr) return;
+  const ChunkGroup gr = groups[g];
+  uint32_t s = 0;
+  for (uint32_t k = 0; k < gr.count; ++k) s += hist[(uint64_t)(gr.first + k) * B + b];
+  gsum[(uint64_t)g * B + b] = s;
+}
+
+__global__ void k_colscan_segments(const Segment* __restrict__ segs, const uint32_t* nseg_ptr, uint32_t E,
+                                   uint32_t* __restrict__ gsum, const GridDesc* __restrict__ grids, uint32_t* pool) {
+  const uint32_t B = 1u << (3 * E);
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
   if (s >= *nseg_ptr) return;
   const Segment sg = segs[s];
   uint32_t run = 0;
-  for (uint32_t k = 0; k < sg.chunk_count; ++k) {
-    uint32_t* cell = hist + (uint64_t)(sg.chunk_begin + k) * B + b;
-    uint32_t v = *cell;
+  for (uint32_t k = 0; k < sg.group_count; ++k) {
+    uint32_t* cell = gsum + (uint64_t)(sg.group_begin + k) * B + b;
+    const uint32_t v = *cell;
     *cell = run;
     run += v;
   }
-  const GridDesc g = grids[sg.grid];
-  pool[g.pyr + pyr_level_offset(E) + b] = run;
+  pool[grids[sg.grid].pyr + pyr_level_offset(E) + b] = run;
+}
+
+__global__ void k_colscan_apply(const ChunkGroup* __restrict__ groups, const uint32_t* ngroup_ptr, uint32_t E,
+                                uint32_t* __restrict__ hist, const uint32_t* __restrict__ gsum) {
+  const uint32_t B = 1u << (3 * E);
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t g = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
+  if (g >= *ngroup_ptr) return;
+  const ChunkGroup gr = groups[g];
+  uint32_t run = gsum[(uint64_t)g * B + b];
+  for (uint32_t k = 0; k < gr.count; ++k) {
+    uint32_t* cell = hist + (uint64_t)(gr.first + k) * B + b;
+    const uint32_t v = *cell;
+    *cell = run;
+    run += v;
+  }
 }
 
 // Finish the grids of a partition: finest-cell offsets (exclusive prefix sum
@@ -245,6 +317,7 @@ __global__ void __launch_bounds__(kGridWG) k_grid_finish(const Segment* __restri
 // store consecutive records of the same cell.  Per-cell cursors in LDS start
 // at the chunk's target offsets and advance round by round.
 constexpr int kScatWG = 512;
+#define PAD(b) ((b) + ((b) >> 5))
 constexpr int kScatPPT = 4;
 constexpr int kScatR = kScatWG * kScatPPT;
 
@@ -257,8 +330,11 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
                                                           const GridDesc* __restrict__ grids, const uint32_t* __restrict__ pool) {
   constexpr uint32_t B = 1u << (3 * E);
   constexpr uint32_t BPT = (B + kScatWG - 1) / kScatWG;  // cells per thread in the scan
-  __shared__ uint32_t cursor[B];
-  __shared__ uint32_t cnt[B];
+  // one padding word per 32 cells: the scan's per-thread runs of BPT cells
+  // then fall on distinct LDS banks
+  constexpr uint32_t BP = B + B / 32 + 1;
+  __shared__ uint32_t cursor[BP];
+  __shared__ uint32_t cnt[BP];
   __shared__ uint4 stage[kScatR];
   __shared__ uint16_t stage_b[kScatR];
   __shared__ uint32_t stage_id[IDS ? kScatR : 1];
@@ -273,32 +349,42 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
   const uint32_t* row = hist + (uint64_t)c * B;
   const uint32_t* goff = pool + g.off;
   for (uint32_t j = threadIdx.x; j < B; j += kScatWG) {
-    cursor[j] = goff[j] + row[j];
-    cnt[j] = 0;
+    cursor[PAD(j)] = goff[j] + row[j];
+    cnt[PAD(j)] = 0;
   }
   __syncthreads();
-  for (uint32_t base = 0; base < ch.count; base += kScatR) {
-    const uint32_t nround = min((uint32_t)kScatR, ch.count - base);
-    uint4 v[kScatPPT];
-    uint32_t bk[kScatPPT], rk[kScatPPT], id[kScatPPT];
+  // software pipeline: the records of round r + 1 are loaded while round r is
+  // sorted in LDS and written out
+  uint4 v[kScatPPT];
+  uint32_t id[kScatPPT];
+  auto load_round = [&](uint32_t base, uint4* vv, uint32_t* ii) {
+    const uint32_t nround = base < ch.count ? min((uint32_t)kScatR, ch.count - base) : 0u;
 #pragma unroll
     for (int k = 0; k < kScatPPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
         const uint32_t gi = ch.start + base + j;
-        v[k] = src[gi];
-        if (IDS) id[k] = src_ids ? src_ids[gi] : gi;
+        vv[k] = src[gi];
+        if (IDS) ii[k] = src_ids ? src_ids[gi] : gi;
       }
     }
+  };
+  load_round(0, v, id);
+  for (uint32_t base = 0; base < ch.count; base += kScatR) {
+    const uint32_t nround = min((uint32_t)kScatR, ch.count - base);
+    uint32_t bk[kScatPPT], rk[kScatPPT];
 #pragma unroll
     for (int k = 0; k < kScatPPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
         uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
         bk[k] = (uint32_t)(key >> shift) & (B - 1);
-        rk[k] = atomicAdd(&cnt[bk[k]], 1u);
+        rk[k] = atomicAdd(&cnt[PAD(bk[k])], 1u);
       }
     }
+    uint4 vn[kScatPPT];
+    uint32_t idn[kScatPPT];
+    load_round(base + kScatR, vn, idn);
     __syncthreads();
     // exclusive scan of the round's cell counts (in place); keep counts in registers
     uint32_t mine[BPT];
@@ -306,7 +392,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
 #pragma unroll
     for (uint32_t k = 0; k < BPT; ++k) {
       const uint32_t b = threadIdx.x * BPT + k;
-      mine[k] = b < B ? cnt[b] : 0u;
+      mine[k] = b < B ? cnt[PAD(b)] : 0u;
       local += mine[k];
     }
     uint32_t tot;
@@ -314,7 +400,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
 #pragma unroll
     for (uint32_t k = 0; k < BPT; ++k) {
       const uint32_t b = threadIdx.x * BPT + k;
-      if (b < B) cnt[b] = ex;
+      if (b < B) cnt[PAD(b)] = ex;
       ex += mine[k];
     }
     __syncthreads();
@@ -322,7 +408,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     for (int k = 0; k < kScatPPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
-        const uint32_t pos = cnt[bk[k]] + rk[k];
+        const uint32_t pos = cnt[PAD(bk[k])] + rk[k];
         stage[pos] = v[k];
         stage_b[pos] = (uint16_t)bk[k];
         if (IDS) stage_id[pos] = id[k];
@@ -331,7 +417,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < nround; j += kScatWG) {
       const uint32_t b = stage_b[j];
-      const uint32_t d = cursor[b] + (j - cnt[b]);
+      const uint32_t d = cursor[PAD(b)] + (j - cnt[PAD(b)]);
       dst[d] = stage[j];
       if (IDS) dst_ids[d] = stage_id[j];
     }
@@ -340,11 +426,16 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     for (uint32_t k = 0; k < BPT; ++k) {
       const uint32_t b = threadIdx.x * BPT + k;
       if (b < B) {
-        cursor[b] += mine[k];
-        cnt[b] = 0;
+        cursor[PAD(b)] += mine[k];
+        cnt[PAD(b)] = 0;
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScatPPT; ++k) {
+      v[k] = vn[k];
+      if (IDS) id[k] = idn[k];
+    }
   }
 }
 
@@ -451,9 +542,15 @@ void launch_init_root(uint32_t n, uint32_t E0, Segment* segs, uint32_t* nseg, Gr
   hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, n, E0, segs, nseg, grids);
 }
 
-void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t chunk, Chunk* chunks, uint32_t* nchunk,
-                        uint32_t max_chunks, hipStream_t st) {
-  hipLaunchKernelGGL(k_make_chunks, dim3(1), dim3(kChunkWG), 0, st, segs, nseg, chunk, chunks, nchunk, max_chunks);
+void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t chunk, Chunk* chunks,
+                        uint32_t* nchunk, uint32_t max_chunks, ChunkGroup* groups, uint32_t* ngroup,
+                        uint32_t max_groups, hipStream_t st) {
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kChunkWG), 0, st, segs, nseg, chunk, nchunk, max_chunks, ngroup,
+                     max_groups);
+  uint32_t blocks = (max_chunks + max_segs + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_chunk_fill, dim3(blocks ? blocks : 1), dim3(256), 0, st, segs, nseg, chunk, chunks, nchunk,
+                     groups, ngroup);
 }
 
 template <int E>
@@ -475,12 +572,18 @@ void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segm
   }
 }
 
-void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t E, uint32_t* hist,
+void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const ChunkGroup* groups,
+                         const uint32_t* ngroup, uint32_t max_groups, uint32_t E, uint32_t* hist, uint32_t* gsum,
                          const GridDesc* grids, uint32_t* pool, hipStream_t st) {
   if (!max_segs) return;
-  const uint64_t threads = (uint64_t)max_segs << (3 * E);
-  const uint32_t blocks = (uint32_t)((threads + 255) / 256);
-  hipLaunchKernelGGL(k_part_colscan, dim3(blocks), dim3(256), 0, st, segs, nseg, E, hist, grids, pool);
+  const uint64_t tg = (uint64_t)max_groups << (3 * E);
+  const uint64_t ts = (uint64_t)max_segs << (3 * E);
+  hipLaunchKernelGGL(k_colscan_groups, dim3((uint32_t)((tg + 255) / 256)), dim3(256), 0, st, groups, ngroup, E, hist,
+                     gsum);
+  hipLaunchKernelGGL(k_colscan_segments, dim3((uint32_t)((ts + 255) / 256)), dim3(256), 0, st, segs, nseg, E, gsum,
+                     grids, pool);
+  hipLaunchKernelGGL(k_colscan_apply, dim3((uint32_t)((tg + 255) / 256)), dim3(256), 0, st, groups, ngroup, E, hist,
+                     gsum);
 }
 
 void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const GridDesc* grids,

@@ -24,15 +24,71 @@
 #include "launch.h"
 #include "scan.h"
 
+#include <algorithm>
+
 namespace lod {
 
 constexpr int kLeafWG = 256;
 constexpr uint32_t kSubCells = 4096;  // 2 levels of micro-bucket -> 4 levels of voxel cells = 12 bits
 constexpr uint32_t kPackedMax = 65535;  // largest micro-bucket the packed 24/24/16-bit sums can hold
+constexpr int kLeafPF = 4;              // points in flight per thread
+
+// Wide accumulation for one micro-bucket whose cells may hold more samples
+// than the packed 16-bit fields allow: windows of 512 cells with 64-bit sums
+// of R, G, B and the count, re-reading the micro-bucket's points per window.
+__device__ void leaf_wide_average(uint64_t* acc /* 2048 words of LDS */, uint32_t* sh, const uint4* __restrict__ pts,
+                                  uint32_t off, uint32_t cnt, uint32_t sub_shift, const CubeD& cd, uint32_t code_hi,
+                                  uint64_t* __restrict__ temp, uint64_t out, uint32_t& vbase) {
+  uint64_t* wr = acc;
+  uint64_t* wg = acc + 512;
+  uint64_t* wb = acc + 1024;
+  uint64_t* wn = acc + 1536;
+  for (uint32_t w0 = 0; w0 < kSubCells; w0 += 512) {
+    for (uint32_t i = threadIdx.x; i < 2048; i += kLeafWG) acc[i] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += kLeafWG) {
+      const uint4 v = pts[off + i];
+      const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
+      const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
+      if (sub >= w0 && sub < w0 + 512) {
+        const uint32_t q = sub - w0;
+        atomicAdd((unsigned long long*)&wr[q], (unsigned long long)(v.w & 0xff));
+        atomicAdd((unsigned long long*)&wg[q], (unsigned long long)((v.w >> 8) & 0xff));
+        atomicAdd((unsigned long long*)&wb[q], (unsigned long long)((v.w >> 16) & 0xff));
+        atomicAdd((unsigned long long*)&wn[q], 1ull);
+      }
+    }
+    __syncthreads();
+    for (uint32_t s0 = 0; s0 < 512; s0 += kLeafWG) {
+      const uint32_t q = s0 + threadIdx.x;
+      const uint64_t c = wn[q];
+      uint32_t tot;
+      const uint32_t pos = block_excl_scan<kLeafWG>(c ? 1u : 0u, sh, &tot);
+      if (c) {
+        const uint32_t rgba = (uint32_t)(wr[q] / c) | ((uint32_t)(wg[q] / c) << 8) | ((uint32_t)(wb[q] / c) << 16) |
+                              (255u << 24);
+        temp[out + vbase + pos] = make_voxel(code_hi | (w0 + q), rgba);
+      }
+      vbase += tot;
+    }
+    __syncthreads();
+  }
+}
 
 // Parent voxels from the points of every leaf (level >= 1).  One workgroup per
 // node; non-leaves exit.  Voxels go to temp[offset .. offset + k) of the leaf
 // (k <= points of the leaf), the count to nodes.aux.
+//
+// One 64-bit LDS atomic per point:
+//   average: acc[cell] += R | G << 16 | B << 32 | 1 << 48.  The 16-bit fields
+//            are exact while a cell holds at most 257 samples (255 * 257 <
+//            2^16); a micro-bucket with a fuller cell is redone by the wide
+//            path above.
+//   pick:    acc[cell] = min/max of the sample's order key; a second pass over
+//            the micro-bucket lets the winner deposit its colour and id.
+// Occupied cells are those whose accumulator left its initial value; the
+// emission walks the 4096 cells in order (16 per thread), which lists the
+// voxels in Morton order.
 template <int MODE>  // 0 average, 1 first, 2 random
 __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t num_nodes,
                                                          const GridDesc* __restrict__ grids,
@@ -40,10 +96,10 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
                                                          const uint4* __restrict__ pts, const uint32_t* __restrict__ ids,
                                                          const Cube* cube, uint64_t* __restrict__ temp,
                                                          uint32_t* __restrict__ temp_ids, uint32_t seed) {
-  __shared__ uint64_t acc[kSubCells];    // average: R | G << 24 | n << 48 ; pick: best order key
-  __shared__ uint32_t accb[kSubCells];   // average: sum of B ; pick: winner rgba
-  __shared__ uint32_t accid[MODE ? kSubCells : 1];
-  __shared__ uint64_t occ[kSubCells / 64];
+  __shared__ uint64_t acc[kSubCells];
+  __shared__ uint64_t bitmap[kSubCells / 64];
+  __shared__ uint32_t wrgba[MODE ? kSubCells : 1];
+  __shared__ uint32_t wid[MODE ? kSubCells : 1];
   __shared__ uint32_t sh[kLeafWG / 64 + 1];
   const uint32_t n = blockIdx.x;
   if (n >= num_nodes || !nodes.is_leaf[n] || nodes.level[n] == 0) return;
@@ -59,11 +115,7 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
   const uint64_t init = MODE == 1 ? ~0ull : 0ull;
   const CubeD cd = load_cube(cube);
   const uint64_t out0 = nodes.offset[n];
-  for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) {
-    acc[i] = init;
-    accb[i] = 0;
-  }
-  if (threadIdx.x < kSubCells / 64) occ[threadIdx.x] = 0;
+  for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
   __syncthreads();
   uint32_t vbase = 0;
   for (uint32_t jm = 0; jm < 64; ++jm) {
@@ -73,62 +125,39 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
     const uint32_t off = goff[idx << (3 * (G.e - rm))];
     const uint32_t code_hi = top9 | (jm << 12);
     if (MODE == 0 && cnt > kPackedMax) {
-      // Wide path for very large micro-buckets (only at the depth limit): one
-      // window of 512 cells per pass with 64-bit sums in the same LDS.
-      uint64_t* wr = acc;            // 512 x R
-      uint64_t* wg = acc + 512;      // 512 x G
-      uint64_t* wb = acc + 1024;     // 512 x B
-      uint64_t* wn = acc + 1536;     // 512 x n
-      for (uint32_t w0 = 0; w0 < kSubCells; w0 += 512) {
-        for (uint32_t i = threadIdx.x; i < 2048; i += kLeafWG) acc[i] = 0;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cnt; i += kLeafWG) {
-          const uint4 v = pts[off + i];
-          const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
-          const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
-          if (sub >= w0 && sub < w0 + 512) {
-            const uint32_t s = sub - w0;
-            atomicAdd((unsigned long long*)&wr[s], (unsigned long long)(v.w & 0xff));
-            atomicAdd((unsigned long long*)&wg[s], (unsigned long long)((v.w >> 8) & 0xff));
-            atomicAdd((unsigned long long*)&wb[s], (unsigned long long)((v.w >> 16) & 0xff));
-            atomicAdd((unsigned long long*)&wn[s], 1ull);
-          }
-        }
-        __syncthreads();
-        // emit in cell order
-        for (uint32_t s0 = 0; s0 < 512; s0 += kLeafWG) {
-          const uint32_t s = s0 + threadIdx.x;
-          const uint64_t c = wn[s];
-          uint32_t tot;
-          const uint32_t pos = block_excl_scan<kLeafWG>(c ? 1u : 0u, sh, &tot);
-          if (c) {
-            const uint32_t rgba = (uint32_t)(wr[s] / c) | ((uint32_t)(wg[s] / c) << 8) | ((uint32_t)(wb[s] / c) << 16) |
-                                  (255u << 24);
-            temp[out0 + vbase + pos] = make_voxel(code_hi | (w0 + s), rgba);
-          }
-          vbase += tot;
-        }
-        __syncthreads();
-      }
-      for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) { acc[i] = init; accb[i] = 0; }
+      leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
+      for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
       __syncthreads();
       continue;
     }
-    // accumulate
-    for (uint32_t i = threadIdx.x; i < cnt; i += kLeafWG) {
-      const uint4 v = pts[off + i];
-      const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
-      const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
-      if (MODE == 0) {
-        const uint64_t packed = (uint64_t)(v.w & 0xff) | ((uint64_t)((v.w >> 8) & 0xff) << 24) | (1ull << 48);
-        atomicAdd((unsigned long long*)&acc[sub], (unsigned long long)packed);
-        atomicAdd(&accb[sub], (v.w >> 16) & 0xffu);
-      } else {
-        const uint64_t k = pick_order(ids[off + i], seed, MODE == 2);
-        if (MODE == 1) atomicMin((unsigned long long*)&acc[sub], (unsigned long long)k);
-        else atomicMax((unsigned long long*)&acc[sub], (unsigned long long)k);
+    // accumulate: every thread first issues all loads of a batch, then hashes
+    for (uint32_t b0 = 0; b0 < cnt; b0 += kLeafWG * kLeafPF) {
+      uint4 v[kLeafPF];
+      uint32_t idv[kLeafPF];
+#pragma unroll
+      for (int k = 0; k < kLeafPF; ++k) {
+        const uint32_t i = b0 + k * kLeafWG + threadIdx.x;
+        if (i < cnt) {
+          v[k] = pts[off + i];
+          if (MODE) idv[k] = ids[off + i];
+        }
       }
-      atomicOr((unsigned long long*)&occ[sub >> 6], 1ull << (sub & 63));
+#pragma unroll
+      for (int k = 0; k < kLeafPF; ++k) {
+        const uint32_t i = b0 + k * kLeafWG + threadIdx.x;
+        if (i >= cnt) continue;
+        const uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
+        const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
+        if (MODE == 0) {
+          const uint64_t packed = (uint64_t)(v[k].w & 0xff) | ((uint64_t)((v[k].w >> 8) & 0xff) << 16) |
+                                  ((uint64_t)((v[k].w >> 16) & 0xff) << 32) | (1ull << 48);
+          atomicAdd((unsigned long long*)&acc[sub], (unsigned long long)packed);
+        } else {
+          const uint64_t ok = pick_order(idv[k], seed, MODE == 2);
+          if (MODE == 1) atomicMin((unsigned long long*)&acc[sub], (unsigned long long)ok);
+          else atomicMax((unsigned long long*)&acc[sub], (unsigned long long)ok);
+        }
+      }
     }
     __syncthreads();
     if (MODE != 0) {
@@ -139,37 +168,63 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
         const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
         const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
         if (acc[sub] == pick_order(id, seed, MODE == 2)) {
-          accb[sub] = v.w;
-          accid[sub] = id;
+          wrgba[sub] = v.w;
+          wid[sub] = id;
         }
       }
       __syncthreads();
     }
-    // emit: each thread owns 16 consecutive cells (a quarter of a bitmask word)
+    // emit.  (1) coalesced pass: lane l of wave w reads cells 256k + 64w + l,
+    // and the wave's ballot is bitmap word 4k + w (occupancy in cell order);
+    // (2) thread t takes 16 bits of the bitmap, a workgroup prefix sum gives
+    // every occupied cell its position, so voxels come out in Morton order.
+    uint32_t over = 0;
+    {
+      const uint32_t w = threadIdx.x / 64, l = lane_id();
+#pragma unroll
+      for (uint32_t k = 0; k < 16; ++k) {
+        const uint64_t a = acc[256 * k + 64 * w + l];
+        if (MODE == 0) over |= (a >> 48) > 257 ? 1u : 0u;
+        const uint64_t m = __ballot(a != init);
+        if (l == 0) bitmap[4 * k + w] = m;
+      }
+    }
+    __syncthreads();
     const uint32_t word = threadIdx.x >> 2, q = (threadIdx.x & 3u) * 16u;
-    const uint32_t bits = (uint32_t)((occ[word] >> q) & 0xffffu);
+    const uint32_t bits = (uint32_t)((bitmap[word] >> q) & 0xffffu);
     uint32_t tot;
-    uint32_t pos = block_excl_scan<kLeafWG>((uint32_t)__popc(bits), sh, &tot);
+    uint32_t pos = block_excl_scan<kLeafWG>((uint32_t)__popc(bits) | (over << 20), sh, &tot);
+    if (MODE == 0 && (tot >> 20)) {
+      // a cell overflowed the packed fields: clear and redo this micro-bucket exactly
+      for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
+      __syncthreads();
+      leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
+      for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
+      __syncthreads();
+      continue;
+    }
+    pos &= (1u << 20) - 1;
     for (uint32_t m = bits; m; m &= m - 1) {
       const uint32_t s = word * 64 + q + (uint32_t)__ffs(m) - 1;
+      const uint64_t a = acc[s];
       uint32_t rgba;
       if (MODE == 0) {
-        const uint64_t a = acc[s];
-        const uint32_t c = (uint32_t)(a >> 48);
-        rgba = (uint32_t)((a & 0xffffffu) / c) | ((uint32_t)(((a >> 24) & 0xffffffu) / c) << 8) |
-               ((accb[s] / c) << 16) | (255u << 24);
+        // floor(sum / n): sums < 2^16 and n < 2^16 are exact in float and the
+        // correctly rounded quotient (< 256) is at least 1/n away from the
+        // next integer whenever it is not one, so truncation is exact
+        const float c = (float)(uint32_t)(a >> 48);
+        rgba = (uint32_t)__fdiv_rn((float)(uint32_t)(a & 0xffffu), c) |
+               ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 16) & 0xffffu), c) << 8) |
+               ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 32) & 0xffffu), c) << 16) | (255u << 24);
       } else {
-        rgba = accb[s];
-        temp_ids[out0 + vbase + pos] = accid[s];
+        rgba = wrgba[s];
+        temp_ids[out0 + vbase + pos] = wid[s];
       }
       temp[out0 + vbase + pos] = make_voxel(code_hi | s, rgba);
       acc[s] = init;
-      accb[s] = 0;
       ++pos;
     }
-    vbase += tot;
-    __syncthreads();
-    if (threadIdx.x < kSubCells / 64) occ[threadIdx.x] = 0;
+    vbase += tot & ((1u << 20) - 1);
     __syncthreads();
   }
   if (threadIdx.x == 0) nodes.aux[n] = vbase;
@@ -208,129 +263,242 @@ __global__ void __launch_bounds__(kBoundWG) k_voxel_bound(Nodes nodes, TreeState
   if (threadIdx.x == 0) {
     st->voxel_bound = total;
     st->voxel_total = 0;
+    st->inner_total = 0;
   }
 }
 
-// Number of parent voxels an inner node contributes: runs of equal (code >> 3)
-// in its Morton-ordered list.  One workgroup per node of the level.
-constexpr int kRunWG = 256;
-__global__ void __launch_bounds__(kRunWG) k_runs(Nodes nodes, uint32_t begin, uint32_t end,
-                                                 const uint64_t* __restrict__ vox) {
-  __shared__ uint32_t sh[kRunWG / 64];
-  const uint32_t j = begin + blockIdx.x;
-  if (j >= end || nodes.is_leaf[j]) return;
-  const uint64_t o = nodes.offset[j];
-  const uint32_t cnt = nodes.count[j];
-  uint32_t runs = 0;
-  for (uint32_t i = threadIdx.x; i < cnt; i += kRunWG) {
-    const uint32_t c = voxel_code(vox[o + i]) >> 3;
-    runs += (i == 0 || (voxel_code(vox[o + i - 1]) >> 3) != c) ? 1u : 0u;
-  }
-  runs = wave_sum(runs);
-  if (lane_id() == 0) sh[threadIdx.x / 64] = runs;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int w = 0; w < kRunWG / 64; ++w) t += sh[w];
-    nodes.aux[j] = t;
+// ------------------------------------------------------------ inner levels
+//
+// The voxels of all inner nodes of one level are contiguous and each node's
+// list is in Morton order.  A parent cell collects the child voxels whose
+// codes agree above the lowest 3 bits (2x2x2 -> 1), i.e. a run of at most 8
+// consecutive entries of one node.  Whoever writes a voxel also writes its
+// owner node and a one-byte flag telling whether it starts such a run (first
+// voxel of a child's contribution, or a change of code >> 3); an exclusive
+// prefix sum over the flags of a level numbers the runs, and every run is
+// reduced by the thread at its start.
+
+constexpr uint32_t kTile = 4096;
+constexpr int kTileWG = 256;
+constexpr uint32_t kTilePT = kTile / kTileWG;  // 16 flags per thread, read as 4 words
+
+__device__ __forceinline__ uint32_t flags4(const uint8_t* __restrict__ f, uint64_t i, uint64_t V) {
+  // 4 consecutive flags starting at i, one byte each; zero past V (byte loads:
+  // a level's flags need not start on a word boundary)
+  uint32_t w = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k)
+    if (i + k < V) w |= (uint32_t)f[i + k] << (8 * k);
+  return w;
+}
+
+// (1) run starts per tile of the level's voxels
+__global__ void __launch_bounds__(kTileWG) k_run_tiles(const TreeState* st, uint32_t lvl,
+                                                       const uint8_t* __restrict__ vflag, uint32_t* __restrict__ tilesum) {
+  __shared__ uint32_t sh[kTileWG / 64];
+  const uint64_t vb = st->level_vbegin[lvl], V = st->level_vcount[lvl];
+  const uint8_t* f = vflag + vb;
+  const uint32_t ntiles = (uint32_t)((V + kTile - 1) / kTile);
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t c = 0;
+    for (uint32_t k = 0; k < kTilePT / 4; ++k) {
+      const uint64_t j = (uint64_t)t * kTile + 4ull * (k * kTileWG + threadIdx.x);
+      if (j < V) c += (uint32_t)__popc(flags4(f, j, V) & 0x01010101u);
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) sh[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t s = 0;
+      for (int w = 0; w < kTileWG / 64; ++w) s += sh[w];
+      tilesum[t] = s;
+    }
+    __syncthreads();
   }
 }
 
-// Voxel offsets of the inner nodes of one level (one workgroup): the node's
-// list is its children's contributions in octant order; nodes follow each
-// other in key order after everything already written.
+// (2) exclusive scan of the tile counts (one workgroup); tilesum[ntiles] = total
+constexpr int kScanWG = 1024;
+__global__ void __launch_bounds__(kScanWG) k_tile_scan(const TreeState* st, uint32_t lvl, uint32_t* tilesum) {
+  __shared__ uint32_t sh[kScanWG / 64 + 1];
+  const uint64_t V = st->level_vcount[lvl];
+  const uint32_t ntiles = (uint32_t)((V + kTile - 1) / kTile);
+  uint32_t base = 0;
+  for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanWG) {
+    const uint32_t t = t0 + threadIdx.x;
+    const uint32_t v = t < ntiles ? tilesum[t] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<kScanWG>(v, sh, &tot);
+    if (t < ntiles) tilesum[t] = base + ex;
+    base += tot;
+  }
+  if (threadIdx.x == 0) tilesum[ntiles] = base;
+}
+
+// (3) global run index of every voxel of the level (runidx[V] = number of runs)
+__global__ void __launch_bounds__(kTileWG) k_run_index(const TreeState* st, uint32_t lvl,
+                                                       const uint8_t* __restrict__ vflag,
+                                                       const uint32_t* __restrict__ tilesum, uint32_t* __restrict__ runidx,
+                                                       uint32_t* __restrict__ runpos) {
+  __shared__ uint32_t sh[kTileWG / 64 + 1];
+  const uint64_t vb = st->level_vbegin[lvl], V = st->level_vcount[lvl];
+  const uint8_t* f = vflag + vb;
+  const uint32_t ntiles = (uint32_t)((V + kTile - 1) / kTile);
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t j0 = (uint64_t)t * kTile + (uint64_t)threadIdx.x * kTilePT;  // contiguous per thread
+    uint32_t w[kTilePT / 4];
+    uint32_t local = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kTilePT / 4; ++k) {
+      w[k] = j0 + 4 * k < V ? flags4(f, j0 + 4 * k, V) : 0u;
+      local += (uint32_t)__popc(w[k] & 0x01010101u);
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kTileWG>(local, sh, &tot) + tilesum[t];
+#pragma unroll
+    for (uint32_t k = 0; k < kTilePT; ++k) {
+      const uint64_t j = j0 + k;
+      const uint32_t f = (w[k / 4] >> (8 * (k & 3))) & 1u;
+      if (j < V) {
+        runidx[j] = ex;
+        if (f) runpos[ex] = (uint32_t)j;
+      }
+      ex += f;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) runidx[V] = tilesum[ntiles];
+}
+
+// (4) voxel offsets of the level's inner nodes (one workgroup): a node's list
+// is its children's contributions in octant order, nodes follow in key order.
 constexpr int kOffWG = 1024;
-__global__ void __launch_bounds__(kOffWG) k_level_offsets(Nodes nodes, uint32_t begin, uint32_t end, TreeState* st) {
+__global__ void __launch_bounds__(kOffWG) k_level_offsets(Nodes nodes, uint32_t lvl, uint32_t begin, uint32_t end,
+                                                          TreeState* st, const uint32_t* __restrict__ runidx) {
   __shared__ uint64_t sh[kOffWG / 64 + 1];
-  uint64_t base = st->voxel_total;
+  const uint64_t level_base = st->voxel_total;
+  const uint64_t cvb = st->level_vbegin[lvl + 1];
+  uint64_t base = level_base;
   for (uint32_t c0 = begin; c0 < end; c0 += kOffWG) {
     const uint32_t j = c0 + threadIdx.x;
+    const bool inner = j < end && !nodes.is_leaf[j];
     uint64_t total = 0;
-    if (j < end && !nodes.is_leaf[j]) {
+    if (inner) {
       const uint32_t fc = nodes.first_child[j];
       const uint32_t nc = (uint32_t)__popc(nodes.child_mask[j]);
       for (uint32_t k = 0; k < nc; ++k) {
-        nodes.jobofs[fc + k] = (uint32_t)total;
-        total += nodes.aux[fc + k];
+        const uint32_t c = fc + k;
+        nodes.jobofs[c] = (uint32_t)total;
+        if (nodes.is_leaf[c]) {
+          total += nodes.aux[c];
+        } else {
+          const uint64_t r0 = nodes.offset[c] - cvb;
+          total += runidx[r0 + nodes.count[c]] - runidx[r0];
+        }
       }
     }
     uint64_t tot;
     const uint64_t ex = block_excl_scan<kOffWG>(total, sh, &tot);
-    if (j < end && !nodes.is_leaf[j]) {
-      nodes.offset[j] = base + ex;
+    if (inner) {
+      const uint64_t off = base + ex;
+      nodes.offset[j] = off;
       nodes.count[j] = (uint32_t)total;
-    }
-    base += tot;
-  }
-  if (threadIdx.x == 0) st->voxel_total = base;
-}
-
-// Write the voxels of the level-L parents: one workgroup per node of level
-// L + 1 (every such node is a child of an inner node).  Leaf children copy
-// their staged voxels; inner children reduce runs of their own voxels.
-constexpr int kWriteWG = 256;
-template <int MODE>
-__global__ void __launch_bounds__(kWriteWG) k_write(Nodes nodes, uint32_t begin, uint32_t end,
-                                                    const uint64_t* __restrict__ temp, const uint32_t* __restrict__ temp_ids,
-                                                    uint64_t* __restrict__ vox, uint32_t* __restrict__ vids, uint32_t seed) {
-  __shared__ uint32_t sh[kWriteWG / 64 + 1];
-  const uint32_t j = begin + blockIdx.x;
-  if (j >= end) return;
-  const uint32_t p = nodes.parent[j];
-  const uint64_t dst = nodes.offset[p] + nodes.jobofs[j];
-  if (nodes.is_leaf[j]) {
-    const uint64_t src = nodes.offset[j];
-    const uint32_t cnt = nodes.aux[j];
-    for (uint32_t i = threadIdx.x; i < cnt; i += kWriteWG) {
-      vox[dst + i] = temp[src + i];
-      if (MODE) vids[dst + i] = temp_ids[src + i];
-    }
-    return;
-  }
-  const uint64_t o = nodes.offset[j];
-  const uint32_t cnt = nodes.count[j];
-  const uint32_t oct = (uint32_t)(nodes.key[j] & 7u) << 18;
-  uint32_t base = 0;
-  for (uint32_t i0 = 0; i0 < cnt; i0 += kWriteWG) {
-    const uint32_t i = i0 + threadIdx.x;
-    uint32_t c = 0, start = 0;
-    if (i < cnt) {
-      c = voxel_code(vox[o + i]) >> 3;
-      start = (i == 0 || (voxel_code(vox[o + i - 1]) >> 3) != c) ? 1u : 0u;
-    }
-    uint32_t tot;
-    const uint32_t r = block_excl_scan<kWriteWG>(start, sh, &tot);
-    if (start) {
-      uint32_t sr = 0, sg = 0, sb = 0, nn = 0;
-      uint64_t best = MODE == 1 ? ~0ull : 0ull;
-      uint32_t brgba = 0, bid = 0;
-      for (uint32_t k = i; k < cnt && k < i + 8; ++k) {
-        const uint64_t v = vox[o + k];
-        if ((voxel_code(v) >> 3) != c) break;
-        const uint32_t rgba = (uint32_t)(v >> 32);
-        if (MODE == 0) {
-          sr += rgba & 0xffu;
-          sg += (rgba >> 8) & 0xffu;
-          sb += (rgba >> 16) & 0xffu;
-          ++nn;
-        } else {
-          const uint32_t id = vids[o + k];
-          const uint64_t key = pick_order(id, seed, MODE == 2);
-          if (MODE == 1 ? key < best : key > best) {
-            best = key;
-            brgba = rgba;
-            bid = id;
-          }
+      const uint32_t fc = nodes.first_child[j];
+      const uint32_t nc = (uint32_t)__popc(nodes.child_mask[j]);
+      for (uint32_t k = 0; k < nc; ++k) {
+        const uint32_t c = fc + k;
+        if (!nodes.is_leaf[c]) {
+          nodes.dstbase[c] = off + nodes.jobofs[c];
+          nodes.firstrun[c] = runidx[nodes.offset[c] - cvb];
         }
       }
-      uint32_t rgba;
-      if (MODE == 0) rgba = (sr / nn) | ((sg / nn) << 8) | ((sb / nn) << 16) | (255u << 24);
-      else rgba = brgba;
-      vox[dst + base + r] = make_voxel(oct | c, rgba);
-      if (MODE) vids[dst + base + r] = bid;
     }
     base += tot;
   }
+  if (threadIdx.x == 0) {
+    st->level_vbegin[lvl] = level_base;
+    st->level_vcount[lvl] = base - level_base;
+    st->voxel_total = base;
+  }
+}
+
+// (5) reduce every run of the child level into its parent's list: one
+// thread per run (the run starts were listed densely by k_run_index)
+template <int MODE>
+__global__ void __launch_bounds__(kTileWG) k_write_runs(Nodes nodes, const TreeState* st, uint32_t clvl,
+                                                        const uint32_t* __restrict__ runidx,
+                                                        const uint32_t* __restrict__ runpos, uint64_t* vox,
+                                                        uint32_t* vids, uint8_t* vflag, uint32_t* vowner,
+                                                        uint32_t seed) {
+  const uint64_t vb = st->level_vbegin[clvl], V = st->level_vcount[clvl];
+  if (V == 0) return;
+  const uint32_t R = runidx[V];
+  const uint32_t stride = gridDim.x * kTileWG;
+  for (uint32_t r = blockIdx.x * kTileWG + threadIdx.x; r < R; r += stride) {
+    const uint64_t j = runpos[r];
+    const uint64_t jend = r + 1 < R ? runpos[r + 1] : V;
+    const uint64_t i = vb + j;
+    const uint32_t c = vowner[i];
+    const uint32_t rank = r - nodes.firstrun[c];
+    const uint64_t dst = nodes.dstbase[c] + rank;
+    const uint64_t v0 = vox[i];
+    const uint32_t code = voxel_code(v0) >> 3;
+    const uint32_t oct = (uint32_t)(nodes.key[c] & 7u) << 18;
+    uint32_t sr = 0, sg = 0, sb = 0, nn = 0, brgba = 0, bid = 0;
+    uint64_t best = MODE == 1 ? ~0ull : 0ull;
+    for (uint64_t k = i; k < vb + jend; ++k) {
+      const uint64_t v = k == i ? v0 : vox[k];
+      const uint32_t rgba = (uint32_t)(v >> 32);
+      if (MODE == 0) {
+        sr += rgba & 0xffu;
+        sg += (rgba >> 8) & 0xffu;
+        sb += (rgba >> 16) & 0xffu;
+        ++nn;
+      } else {
+        const uint32_t id = vids[k];
+        const uint64_t key = pick_order(id, seed, MODE == 2);
+        if (MODE == 1 ? key < best : key > best) {
+          best = key;
+          brgba = rgba;
+          bid = id;
+        }
+      }
+    }
+    const uint32_t rgba =
+        MODE == 0 ? ((sr / nn) | ((sg / nn) << 8) | ((sb / nn) << 16) | (255u << 24)) : brgba;
+    vox[dst] = make_voxel(oct | code, rgba);
+    if (MODE) vids[dst] = bid;
+    vowner[dst] = nodes.parent[c];
+    // the new voxel starts a run of the next level up if it opens this child's
+    // contribution or if its code >> 3 differs from the previous run's
+    vflag[dst] = (rank == 0 || (code >> 3) != ((voxel_code(vox[i - 1]) >> 3) >> 3)) ? 1 : 0;
+  }
+}
+
+// (6) leaf children: copy their staged voxels into the parent's list
+template <int MODE>
+__global__ void __launch_bounds__(kTileWG) k_copy_leaf_voxels(Nodes nodes, uint32_t begin, uint32_t end,
+                                                              const uint64_t* __restrict__ temp,
+                                                              const uint32_t* __restrict__ temp_ids,
+                                                              uint64_t* __restrict__ vox, uint32_t* __restrict__ vids,
+                                                              uint8_t* __restrict__ vflag, uint32_t* __restrict__ vowner) {
+  const uint32_t c = begin + blockIdx.x;
+  if (c >= end || !nodes.is_leaf[c]) return;
+  const uint32_t p = nodes.parent[c];
+  const uint64_t dst = nodes.offset[p] + nodes.jobofs[c];
+  const uint64_t src = nodes.offset[c];
+  const uint32_t cnt = nodes.aux[c];
+  for (uint32_t i = threadIdx.x; i < cnt; i += kTileWG) {
+    const uint64_t v = temp[src + i];
+    vox[dst + i] = v;
+    if (MODE) vids[dst + i] = temp_ids[src + i];
+    vowner[dst + i] = p;
+    vflag[dst + i] = (i == 0 || (voxel_code(v) >> 3) != (voxel_code(temp[src + i - 1]) >> 3)) ? 1 : 0;
+  }
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 void launch_leaf_voxels(uint32_t mode, const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids,
@@ -352,21 +520,40 @@ void launch_voxel_bound(const Nodes& nodes, TreeState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_voxel_bound, dim3(1), dim3(kBoundWG), 0, s, nodes, st);
 }
 
-void launch_level(uint32_t mode, const Nodes& nodes, uint32_t pbegin, uint32_t pend, uint32_t cbegin, uint32_t cend,
-                  const uint64_t* temp, const uint32_t* temp_ids, uint64_t* vox, uint32_t* vids, TreeState* st,
-                  uint32_t seed, hipStream_t s) {
-  if (cend <= cbegin) return;
-  hipLaunchKernelGGL(k_runs, dim3(cend - cbegin), dim3(kRunWG), 0, s, nodes, cbegin, cend, (const uint64_t*)vox);
-  hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(kOffWG), 0, s, nodes, pbegin, pend, st);
-  if (mode == 0)
-    hipLaunchKernelGGL(k_write<0>, dim3(cend - cbegin), dim3(kWriteWG), 0, s, nodes, cbegin, cend, temp, temp_ids, vox,
-                       vids, seed);
-  else if (mode == 1)
-    hipLaunchKernelGGL(k_write<1>, dim3(cend - cbegin), dim3(kWriteWG), 0, s, nodes, cbegin, cend, temp, temp_ids, vox,
-                       vids, seed);
-  else
-    hipLaunchKernelGGL(k_write<2>, dim3(cend - cbegin), dim3(kWriteWG), 0, s, nodes, cbegin, cend, temp, temp_ids, vox,
-                       vids, seed);
+void launch_fill_zero(uint64_t* p, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_level(uint32_t mode, const Nodes& nodes, uint32_t L, uint32_t pbegin, uint32_t pend, uint32_t cbegin,
+                  uint32_t cend, uint64_t vcap, const uint64_t* temp, const uint32_t* temp_ids, uint64_t* vox,
+                  uint32_t* vids, TreeState* st, uint32_t* tilesum, uint32_t* runidx, uint32_t* runpos,
+                  uint8_t* vflag, uint32_t* vowner, uint32_t seed, hipStream_t s) {
+  const uint64_t tiles = (vcap + kTile - 1) / kTile;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 2048);
+  const uint32_t cl = L + 1;
+  hipLaunchKernelGGL(k_run_tiles, dim3(grid), dim3(kTileWG), 0, s, st, cl, vflag, tilesum);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanWG), 0, s, st, cl, tilesum);
+  hipLaunchKernelGGL(k_run_index, dim3(grid), dim3(kTileWG), 0, s, st, cl, vflag, tilesum, runidx, runpos);
+  hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(kOffWG), 0, s, nodes, L, pbegin, pend, st, runidx);
+  const uint32_t wgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((vcap / 4 + kTileWG - 1) / kTileWG, 1), 4096);
+  const uint32_t nc = cend - cbegin;
+#define LOD_LEVEL(M)                                                                                               \
+  hipLaunchKernelGGL(k_write_runs<M>, dim3(wgrid), dim3(kTileWG), 0, s, nodes, st, cl, runidx, runpos, vox, vids,  \
+                     vflag, vowner, seed);                                                                                \
+  if (nc)                                                                                                          \
+    hipLaunchKernelGGL(k_copy_leaf_voxels<M>, dim3(nc), dim3(kTileWG), 0, s, nodes, cbegin, cend, temp, temp_ids, vox, \
+                       vids, vflag, vowner);
+  if (mode == 0) {
+    LOD_LEVEL(0)
+  } else if (mode == 1) {
+    LOD_LEVEL(1)
+  } else {
+    LOD_LEVEL(2)
+  }
+#undef LOD_LEVEL
 }
 
 }  // namespace lod

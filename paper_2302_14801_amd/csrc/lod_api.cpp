@@ -91,13 +91,19 @@ struct HostStage {
 struct Workspace {
   int dev = 0;
   Scratch X, Xid, bbox, cube, segs, chunks, counters, hist, grids, pool, pool2, refine, leaf_refine;
+  Scratch groups, gsum, tilesum, runidx, inner_ids, inner_voff, starts;
   Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_aux, n_jobofs;
+  Scratch n_dstbase, n_firstrun, runpos;
   Scratch state;
   HostStage* host = nullptr;
+  hipEvent_t ev[16] = {};
+  bool ev_ready = false;
   ~Workspace() {
+    if (ev_ready)
+      for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
     Scratch* all[] = {&X, &Xid, &bbox, &cube, &segs, &chunks, &counters, &hist, &grids, &pool, &pool2, &refine,
-                      &leaf_refine, &n_level, &n_leaf, &n_mask, &n_key, &n_npts, &n_count, &n_first, &n_off,
-                      &n_cover, &n_grid, &n_parent, &n_aux, &n_jobofs, &state};
+                      &leaf_refine, &groups, &gsum, &tilesum, &runidx, &inner_ids, &inner_voff, &starts, &n_level, &n_leaf, &n_mask, &n_key, &n_npts, &n_count, &n_first, &n_off,
+                      &n_cover, &n_grid, &n_parent, &n_aux, &n_jobofs, &state, &n_dstbase, &n_firstrun, &runpos};
     for (Scratch* s : all) s->drop(dev);
     if (host) (void)hipHostFree(host);
   }
@@ -136,6 +142,37 @@ struct WsGuard {
   Workspace* w;
   explicit WsGuard(int dev) : w(acquire_ws(dev)) {}
   ~WsGuard() { release_ws(w); }
+};
+
+// Stage timer: events recorded on the build stream (no effect when disabled).
+enum { EV_START, EV_BBOX, EV_COUNT0, EV_OFF0, EV_SCAT0, EV_COUNT1, EV_OFF1, EV_SCAT1, EV_TREE, EV_LEAF, EV_LEVELS,
+       EV_NUM };
+struct StageTimer {
+  Workspace& w;
+  hipStream_t s;
+  bool on;
+  StageTimer(Workspace& ws, hipStream_t st, bool enabled) : w(ws), s(st), on(enabled) {
+    if (on && !w.ev_ready) {
+      for (int i = 0; i < EV_NUM; ++i)
+        if (hipEventCreate(&w.ev[i]) != hipSuccess) {
+          (void)hipGetLastError();
+          on = false;
+          return;
+        }
+      w.ev_ready = true;
+    }
+  }
+  void mark(int i) {
+    if (on) (void)hipEventRecord(w.ev[i], s);
+  }
+  float ms(int a, int b) {
+    float t = 0.f;
+    if (on && hipEventElapsedTime(&t, w.ev[a], w.ev[b]) != hipSuccess) {
+      (void)hipGetLastError();
+      t = 0.f;
+    }
+    return t;
+  }
 };
 
 }  // namespace
@@ -182,6 +219,8 @@ Nodes node_ptrs(Workspace& w, uint32_t cap) {
   nd.parent = w.n_parent.get<uint32_t>(w.dev, cap);
   nd.aux = w.n_aux.get<uint32_t>(w.dev, cap);
   nd.jobofs = w.n_jobofs.get<uint32_t>(w.dev, cap);
+  nd.dstbase = w.n_dstbase.get<uint64_t>(w.dev, cap);
+  nd.firstrun = w.n_firstrun.get<uint32_t>(w.dev, cap);
   return nd;
 }
 
@@ -236,17 +275,24 @@ struct GridPool {
 // max_points points) by E levels from src into dst.
 void partition(Workspace& w, GridPool& gp, uint32_t E, uint32_t chunk, uint32_t max_segs, uint64_t max_points,
                const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, bool ids, Segment* segs,
-               uint32_t* nseg, const Cube* cube, hipStream_t s) {
+               uint32_t* nseg, const Cube* cube, hipStream_t s, StageTimer* tm = nullptr, int ev0 = 0) {
   uint32_t* nchunk = nseg + 1;
+  uint32_t* ngroup = nseg + 2;
   const uint32_t max_chunks = ceil_div(max_points, chunk) + max_segs;
+  const uint32_t max_groups = ceil_div(max_chunks, kGroupChunks) + max_segs;
   Chunk* chunks = w.chunks.get<Chunk>(w.dev, max_chunks);
+  ChunkGroup* groups = w.groups.get<ChunkGroup>(w.dev, max_groups);
   uint32_t* hist = w.hist.get<uint32_t>(w.dev, (size_t)max_chunks << (3 * E));
-  launch_make_chunks(segs, nseg, chunk, chunks, nchunk, max_chunks, s);
+  uint32_t* gsum = w.gsum.get<uint32_t>(w.dev, (size_t)max_groups << (3 * E));
+  launch_make_chunks(segs, nseg, max_segs, chunk, chunks, nchunk, max_chunks, groups, ngroup, max_groups, s);
   launch_part_count(E, src, cube, segs, chunks, nchunk, max_chunks, hist, s);
-  launch_part_colscan(segs, nseg, max_segs, E, hist, gp.grids, gp.pool, s);
+  if (tm) tm->mark(ev0);
+  launch_part_colscan(segs, nseg, max_segs, groups, ngroup, max_groups, E, hist, gsum, gp.grids, gp.pool, s);
   launch_grid_finish(segs, nseg, max_segs, gp.grids, gp.pool, s);
+  if (tm) tm->mark(ev0 + 1);
   launch_part_scatter(E, ids, src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, hist, gp.grids,
                       gp.pool, s);
+  if (tm) tm->mark(ev0 + 2);
   HIPCHK(hipGetLastError());
 }
 
@@ -303,18 +349,21 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
   const uint32_t max_segs1 = (uint32_t)std::min<uint64_t>(root_cells, n);
   gp.reserve(1 + max_segs1, grid_words(pl.E0) + (uint64_t)max_segs1 * grid_words(pl.E1));
 
+  StageTimer tm(w, s, (prm.flags & LOD_FLAG_TIMING) != 0);
+  tm.mark(EV_START);
   // 1. bounding box and cube
   launch_bbox(d_points, n, bb, cube, s);
+  tm.mark(EV_BBOX);
   // 2. root partition, input -> X
   Segment* segs = w.segs.get<Segment>(dev, std::max<uint32_t>(max_segs1, 1));
   uint32_t* nseg = ctr;
   launch_init_root((uint32_t)n, pl.E0, segs, nseg, gp.grids, s);
-  partition(w, gp, pl.E0, pl.chunk0, 1, n, d_points, nullptr, X, Xid, ids, segs, nseg, cube, s);
+  partition(w, gp, pl.E0, pl.chunk0, 1, n, d_points, nullptr, X, Xid, ids, segs, nseg, cube, s, &tm, EV_COUNT0);
   gp.num_grids = 1;
   gp.used_words = grid_words(pl.E0);
   // 3. every root cell by E1 more levels, X -> Y
   launch_segments_from_grid(gp.grids, 0, gp.pool, pl.E1, gp.used_words, 1, segs, nseg, s);
-  partition(w, gp, pl.E1, pl.chunk1, max_segs1, n, X, Xid, Y, Yid, ids, segs, nseg, cube, s);
+  partition(w, gp, pl.E1, pl.chunk1, max_segs1, n, X, Xid, Y, Yid, ids, segs, nseg, cube, s, &tm, EV_COUNT1);
   gp.num_grids = 1 + max_segs1;  // descriptors past the real count are never referenced
   gp.used_words += (uint64_t)max_segs1 * grid_words(pl.E1);
 
@@ -345,10 +394,12 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
     refine_nodes(w, gp, nd, leaf_refine, hs->st.num_leaf_refine, n, Y, Yid, ids, cube, pl.chunk_ref, s);
   const uint32_t num_nodes = hs->st.num_nodes;
   TreeState levels = hs->st;
+  tm.mark(EV_TREE);
 
   // 5. voxels: leaves (all levels at once) into X, then the bound, then levels bottom-up
   uint64_t* temp = (uint64_t*)X;
   launch_leaf_voxels(pl.mode, nd, num_nodes, gp.grids, gp.pool, Y, Yid, cube, temp, Xid, prm.seed, s);
+  tm.mark(EV_LEAF);
   launch_voxel_bound(nd, st, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(&hs->st, st, sizeof(TreeState), hipMemcpyDeviceToHost, s));
@@ -359,10 +410,17 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
   int deepest_inner = -1;
   for (int L = 0; L < 22; ++L)
     if (levels.level_end[L + 1] > levels.level_begin[L + 1]) deepest_inner = L;
+  uint32_t* tilesum = w.tilesum.get<uint32_t>(dev, (vcap + 4095) / 4096 + 2);
+  uint32_t* runidx = w.runidx.get<uint32_t>(dev, vcap + 2);
+  uint8_t* vflag = w.starts.get<uint8_t>(dev, vcap + 8);
+  uint32_t* vowner = w.inner_ids.get<uint32_t>(dev, vcap + 1);
+  uint32_t* runpos = w.runpos.get<uint32_t>(dev, vcap + 1);
   for (int L = deepest_inner; L >= 0; --L)
-    launch_level(pl.mode, nd, levels.level_begin[L], levels.level_end[L], levels.level_begin[L + 1],
-                 levels.level_end[L + 1], temp, Xid, vox, vids, st, prm.seed, s);
+    launch_level(pl.mode, nd, (uint32_t)L, levels.level_begin[L], levels.level_end[L], levels.level_begin[L + 1],
+                 levels.level_end[L + 1], vcap, temp, Xid, vox, vids, st, tilesum, runidx, runpos, vflag, vowner,
+                 prm.seed, s);
   HIPCHK(hipGetLastError());
+  tm.mark(EV_LEVELS);
 
   // 6. exact-size node table for the tree
   uint8_t* o_level = t->alloc<uint8_t>(num_nodes);
@@ -384,6 +442,20 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
   HIPCHK(hipMemcpyAsync(&hs->st, st, sizeof(TreeState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
 
+  if (tm.on) {
+    lod_timings& T = t->timings;
+    T.bbox = tm.ms(EV_START, EV_BBOX);
+    T.count0 = tm.ms(EV_BBOX, EV_COUNT0);
+    T.offsets0 = tm.ms(EV_COUNT0, EV_OFF0);
+    T.scatter0 = tm.ms(EV_OFF0, EV_SCAT0);
+    T.count1 = tm.ms(EV_SCAT0, EV_COUNT1);
+    T.offsets1 = tm.ms(EV_COUNT1, EV_OFF1);
+    T.scatter1 = tm.ms(EV_OFF1, EV_SCAT1);
+    T.tree = tm.ms(EV_SCAT1, EV_TREE);
+    T.leaf_voxels = tm.ms(EV_TREE, EV_LEAF);
+    T.levels = tm.ms(EV_LEAF, EV_LEVELS);
+    T.total = tm.ms(EV_START, EV_LEVELS);
+  }
   lod_tree_view& v = t->v;
   for (int a = 0; a < 3; ++a) {
     v.aabb_min[a] = hs->cube.lo[a];
@@ -496,6 +568,15 @@ lod_status lod_tree_view_get(const lod_tree* t, lod_tree_view* v) {
 }
 
 void lod_tree_free(lod_tree* t) { delete t; }
+
+lod_status lod_tree_timings(const lod_tree* t, lod_timings* out) {
+  if (!t || !out) {
+    set_err("tree or output is NULL");
+    return LOD_ERR_INVALID;
+  }
+  *out = t->timings;
+  return LOD_OK;
+}
 
 const char* lod_status_str(lod_status s) {
   switch (s) {
