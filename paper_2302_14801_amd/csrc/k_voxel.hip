@@ -89,19 +89,26 @@ __device__ void leaf_wide_average(uint64_t* acc /* 2048 words of LDS */, uint32_
 // Occupied cells are those whose accumulator left its initial value; the
 // emission walks the 4096 cells in order (16 per thread), which lists the
 // voxels in Morton order.
+//
+// A work item is one leaf and one of its 8 child cells (8 micro-buckets), so
+// that large leaves spread over 8 workgroups.  Its voxels go to temp starting
+// at the first point of that child cell (never more voxels than points); the
+// count and start are recorded per (leaf, child cell) in gcount / gstart.
 template <int MODE>  // 0 average, 1 first, 2 random
 __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t num_nodes,
                                                          const GridDesc* __restrict__ grids,
                                                          const uint32_t* __restrict__ pool,
                                                          const uint4* __restrict__ pts, const uint32_t* __restrict__ ids,
                                                          const Cube* cube, uint64_t* __restrict__ temp,
-                                                         uint32_t* __restrict__ temp_ids, uint32_t seed) {
+                                                         uint32_t* __restrict__ temp_ids, uint32_t* __restrict__ gcount,
+                                                         uint32_t* __restrict__ gstart, uint32_t seed) {
   __shared__ uint64_t acc[kSubCells];
-  __shared__ uint64_t bitmap[kSubCells / 64];
+  __shared__ uint32_t wcount[64];
+  __shared__ uint32_t wover[4];
   __shared__ uint32_t wrgba[MODE ? kSubCells : 1];
   __shared__ uint32_t wid[MODE ? kSubCells : 1];
   __shared__ uint32_t sh[kLeafWG / 64 + 1];
-  const uint32_t n = blockIdx.x;
+  const uint32_t n = blockIdx.x >> 3, grp = blockIdx.x & 7u;
   if (n >= num_nodes || !nodes.is_leaf[n] || nodes.level[n] == 0) return;
   const uint32_t lvl = nodes.level[n];
   const int32_t gi = nodes.grid[n] >= 0 ? nodes.grid[n] : nodes.cover[n];
@@ -114,11 +121,20 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
   const uint32_t top9 = (uint32_t)(nodes.key[n] & 7u) << 18;
   const uint64_t init = MODE == 1 ? ~0ull : 0ull;
   const CubeD cd = load_cube(cube);
-  const uint64_t out0 = nodes.offset[n];
+  const uint64_t out0 = goff[((leaf_rel << 6) | (grp << 3)) << (3 * (G.e - rm))];
+  bool any = false;
+  for (uint32_t jm = grp * 8; jm < grp * 8 + 8; ++jm) any |= mcnt[(leaf_rel << 6) | jm] != 0;
+  if (!any) {
+    if (threadIdx.x == 0) {
+      gcount[blockIdx.x] = 0;
+      gstart[blockIdx.x] = (uint32_t)out0;
+    }
+    return;
+  }
   for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
   __syncthreads();
   uint32_t vbase = 0;
-  for (uint32_t jm = 0; jm < 64; ++jm) {
+  for (uint32_t jm = grp * 8; jm < grp * 8 + 8; ++jm) {
     const uint64_t idx = (leaf_rel << 6) | jm;
     const uint32_t cnt = mcnt[idx];
     if (cnt == 0) continue;
@@ -174,60 +190,88 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
       }
       __syncthreads();
     }
-    // emit.  (1) coalesced pass: lane l of wave w reads cells 256k + 64w + l,
-    // and the wave's ballot is bitmap word 4k + w (occupancy in cell order);
-    // (2) thread t takes 16 bits of the bitmap, a workgroup prefix sum gives
-    // every occupied cell its position, so voxels come out in Morton order.
-    uint32_t over = 0;
+    // emit.  Lane l of wave w owns cells 256k + 64w + l (k = 0..15); the
+    // wave's ballot over cells 256k + 64w .. +63 is occupancy word 4k + w, so
+    // word order is cell (Morton) order.  One exchange of the 64 word counts
+    // gives every word its prefix, and each lane writes its own occupied
+    // cells at prefix(word) + occupied lanes below it.
     {
       const uint32_t w = threadIdx.x / 64, l = lane_id();
+      uint64_t bal[16];
+      uint32_t over = 0;
 #pragma unroll
       for (uint32_t k = 0; k < 16; ++k) {
         const uint64_t a = acc[256 * k + 64 * w + l];
         if (MODE == 0) over |= (a >> 48) > 257 ? 1u : 0u;
-        const uint64_t m = __ballot(a != init);
-        if (l == 0) bitmap[4 * k + w] = m;
+        bal[k] = __ballot(a != init);
       }
-    }
-    __syncthreads();
-    const uint32_t word = threadIdx.x >> 2, q = (threadIdx.x & 3u) * 16u;
-    const uint32_t bits = (uint32_t)((bitmap[word] >> q) & 0xffffu);
-    uint32_t tot;
-    uint32_t pos = block_excl_scan<kLeafWG>((uint32_t)__popc(bits) | (over << 20), sh, &tot);
-    if (MODE == 0 && (tot >> 20)) {
-      // a cell overflowed the packed fields: clear and redo this micro-bucket exactly
-      for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
+      const bool any_over = MODE == 0 && __ballot(over != 0) != 0;
+      if (l == 0) {
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) wcount[4 * k + w] = (uint32_t)__popcll(bal[k]);
+        wover[w] = any_over ? 1u : 0u;
+      }
       __syncthreads();
-      leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
-      for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-      __syncthreads();
-      continue;
-    }
-    pos &= (1u << 20) - 1;
-    for (uint32_t m = bits; m; m &= m - 1) {
-      const uint32_t s = word * 64 + q + (uint32_t)__ffs(m) - 1;
-      const uint64_t a = acc[s];
-      uint32_t rgba;
-      if (MODE == 0) {
-        // floor(sum / n): sums < 2^16 and n < 2^16 are exact in float and the
-        // correctly rounded quotient (< 256) is at least 1/n away from the
-        // next integer whenever it is not one, so truncation is exact
-        const float c = (float)(uint32_t)(a >> 48);
-        rgba = (uint32_t)__fdiv_rn((float)(uint32_t)(a & 0xffffu), c) |
-               ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 16) & 0xffffu), c) << 8) |
-               ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 32) & 0xffffu), c) << 16) | (255u << 24);
+      const bool redo = MODE == 0 && (wover[0] | wover[1] | wover[2] | wover[3]);
+      const uint32_t mine = wcount[l];
+      const uint32_t incl = wave_incl_scan(mine);
+      const uint32_t total = __shfl(incl, 63, 64);
+      const uint32_t excl = incl - mine;
+      if (!redo) {
+        const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
+        // word prefixes, read with every lane active (a shuffle from a lane
+        // masked off by a branch is undefined)
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) {
+          const uint32_t pre = (uint32_t)__shfl(excl, (int)(4 * k + w), 64);
+          if ((bal[k] >> l) & 1ull) {
+            const uint32_t pos = pre + (uint32_t)__popcll(bal[k] & below);
+            const uint32_t s = 256 * k + 64 * w + l;
+            const uint64_t a = acc[s];
+            uint32_t rgba;
+            if (MODE == 0) {
+              // floor(sum / n): sums < 2^16 and n <= 257 are exact in float and
+              // the correctly rounded quotient (< 256) stays at least 1/n away
+              // from the next integer when it is not one, so truncation is exact
+              const float c = (float)(uint32_t)(a >> 48);
+              rgba = (uint32_t)__fdiv_rn((float)(uint32_t)(a & 0xffffu), c) |
+                     ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 16) & 0xffffu), c) << 8) |
+                     ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 32) & 0xffffu), c) << 16) | (255u << 24);
+            } else {
+              rgba = wrgba[s];
+              temp_ids[out0 + vbase + pos] = wid[s];
+            }
+            temp[out0 + vbase + pos] = make_voxel(code_hi | s, rgba);
+            acc[s] = init;
+          }
+        }
+        vbase += total;
+        __syncthreads();
       } else {
-        rgba = wrgba[s];
-        temp_ids[out0 + vbase + pos] = wid[s];
+        // a cell overflowed the packed fields: clear and redo this micro-bucket exactly
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
+        __syncthreads();
+        leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
+        for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
+        __syncthreads();
       }
-      temp[out0 + vbase + pos] = make_voxel(code_hi | s, rgba);
-      acc[s] = init;
-      ++pos;
     }
-    vbase += tot & ((1u << 20) - 1);
-    __syncthreads();
   }
-  if (threadIdx.x == 0) nodes.aux[n] = vbase;
+  if (threadIdx.x == 0) {
+    gcount[blockIdx.x] = vbase;
+    gstart[blockIdx.x] = (uint32_t)out0;
+  }
+}
+
+// Voxel count of every leaf: the sum over its 8 child-cell work items.
+__global__ void k_leaf_sums(Nodes nodes, uint32_t num_nodes, const uint32_t* __restrict__ gcount) {
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= num_nodes || !nodes.is_leaf[n]) return;
+  uint32_t s = 0;
+  if (nodes.level[n] != 0)
+    for (uint32_t g = 0; g < 8; ++g) s += gcount[8 * n + g];
+  nodes.aux[n] = s;
 }
 
 // Capacity for all voxel lists: per level, at most min(2^21, points) per node
@@ -474,9 +518,14 @@ __global__ void __launch_bounds__(kTileWG) k_write_runs(Nodes nodes, const TreeS
   }
 }
 
-// (6) leaf children: copy their staged voxels into the parent's list
+// (6) leaf children: copy their staged voxels (8 segments, one per child
+// cell) into the parent's list.  A segment's first voxel always starts a run
+// of the next level up: different child cells differ in the code bits above
+// the lowest 3.
 template <int MODE>
 __global__ void __launch_bounds__(kTileWG) k_copy_leaf_voxels(Nodes nodes, uint32_t begin, uint32_t end,
+                                                              const uint32_t* __restrict__ gcount,
+                                                              const uint32_t* __restrict__ gstart,
                                                               const uint64_t* __restrict__ temp,
                                                               const uint32_t* __restrict__ temp_ids,
                                                               uint64_t* __restrict__ vox, uint32_t* __restrict__ vids,
@@ -484,15 +533,18 @@ __global__ void __launch_bounds__(kTileWG) k_copy_leaf_voxels(Nodes nodes, uint3
   const uint32_t c = begin + blockIdx.x;
   if (c >= end || !nodes.is_leaf[c]) return;
   const uint32_t p = nodes.parent[c];
-  const uint64_t dst = nodes.offset[p] + nodes.jobofs[c];
-  const uint64_t src = nodes.offset[c];
-  const uint32_t cnt = nodes.aux[c];
-  for (uint32_t i = threadIdx.x; i < cnt; i += kTileWG) {
-    const uint64_t v = temp[src + i];
-    vox[dst + i] = v;
-    if (MODE) vids[dst + i] = temp_ids[src + i];
-    vowner[dst + i] = p;
-    vflag[dst + i] = (i == 0 || (voxel_code(v) >> 3) != (voxel_code(temp[src + i - 1]) >> 3)) ? 1 : 0;
+  uint64_t dst = nodes.offset[p] + nodes.jobofs[c];
+  for (uint32_t g = 0; g < 8; ++g) {
+    const uint32_t cnt = gcount[8 * c + g];
+    const uint64_t src = gstart[8 * c + g];
+    for (uint32_t i = threadIdx.x; i < cnt; i += kTileWG) {
+      const uint64_t v = temp[src + i];
+      vox[dst + i] = v;
+      if (MODE) vids[dst + i] = temp_ids[src + i];
+      vowner[dst + i] = p;
+      vflag[dst + i] = (i == 0 || (voxel_code(v) >> 3) != (voxel_code(temp[src + i - 1]) >> 3)) ? 1 : 0;
+    }
+    dst += cnt;
   }
 }
 
@@ -503,17 +555,19 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n) {
 
 void launch_leaf_voxels(uint32_t mode, const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids,
                         const uint32_t* pool, const void* pts, const uint32_t* ids, const Cube* cube, uint64_t* temp,
-                        uint32_t* temp_ids, uint32_t seed, hipStream_t s) {
+                        uint32_t* temp_ids, uint32_t* gcount, uint32_t* gstart, uint32_t seed, hipStream_t s) {
   if (!num_nodes) return;
+  const dim3 grid(num_nodes * 8);
   if (mode == 0)
-    hipLaunchKernelGGL(k_leaf_voxels<0>, dim3(num_nodes), dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool,
-                       (const uint4*)pts, ids, cube, temp, temp_ids, seed);
+    hipLaunchKernelGGL(k_leaf_voxels<0>, grid, dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool, (const uint4*)pts,
+                       ids, cube, temp, temp_ids, gcount, gstart, seed);
   else if (mode == 1)
-    hipLaunchKernelGGL(k_leaf_voxels<1>, dim3(num_nodes), dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool,
-                       (const uint4*)pts, ids, cube, temp, temp_ids, seed);
+    hipLaunchKernelGGL(k_leaf_voxels<1>, grid, dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool, (const uint4*)pts,
+                       ids, cube, temp, temp_ids, gcount, gstart, seed);
   else
-    hipLaunchKernelGGL(k_leaf_voxels<2>, dim3(num_nodes), dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool,
-                       (const uint4*)pts, ids, cube, temp, temp_ids, seed);
+    hipLaunchKernelGGL(k_leaf_voxels<2>, grid, dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool, (const uint4*)pts,
+                       ids, cube, temp, temp_ids, gcount, gstart, seed);
+  hipLaunchKernelGGL(k_leaf_sums, dim3((num_nodes + 255) / 256), dim3(256), 0, s, nodes, num_nodes, gcount);
 }
 
 void launch_voxel_bound(const Nodes& nodes, TreeState* st, hipStream_t s) {
@@ -530,7 +584,8 @@ void launch_fill_zero(uint64_t* p, uint64_t n, hipStream_t s) {
 void launch_level(uint32_t mode, const Nodes& nodes, uint32_t L, uint32_t pbegin, uint32_t pend, uint32_t cbegin,
                   uint32_t cend, uint64_t vcap, const uint64_t* temp, const uint32_t* temp_ids, uint64_t* vox,
                   uint32_t* vids, TreeState* st, uint32_t* tilesum, uint32_t* runidx, uint32_t* runpos,
-                  uint8_t* vflag, uint32_t* vowner, uint32_t seed, hipStream_t s) {
+                  uint8_t* vflag, uint32_t* vowner, const uint32_t* gcount, const uint32_t* gstart, uint32_t seed,
+                  hipStream_t s) {
   const uint64_t tiles = (vcap + kTile - 1) / kTile;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 2048);
   const uint32_t cl = L + 1;
@@ -544,8 +599,8 @@ void launch_level(uint32_t mode, const Nodes& nodes, uint32_t L, uint32_t pbegin
   hipLaunchKernelGGL(k_write_runs<M>, dim3(wgrid), dim3(kTileWG), 0, s, nodes, st, cl, runidx, runpos, vox, vids,  \
                      vflag, vowner, seed);                                                                                \
   if (nc)                                                                                                          \
-    hipLaunchKernelGGL(k_copy_leaf_voxels<M>, dim3(nc), dim3(kTileWG), 0, s, nodes, cbegin, cend, temp, temp_ids, vox, \
-                       vids, vflag, vowner);
+    hipLaunchKernelGGL(k_copy_leaf_voxels<M>, dim3(nc), dim3(kTileWG), 0, s, nodes, cbegin, cend, gcount, gstart,     \
+                       temp, temp_ids, vox, vids, vflag, vowner);
   if (mode == 0) {
     LOD_LEVEL(0)
   } else if (mode == 1) {

@@ -42,12 +42,13 @@ void launch_refine_segments(const Nodes& nodes, const uint32_t* list, const uint
 // k_voxel.hip
 void launch_leaf_voxels(uint32_t mode, const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids,
                         const uint32_t* pool, const void* pts, const uint32_t* ids, const Cube* cube, uint64_t* temp,
-                        uint32_t* temp_ids, uint32_t seed, hipStream_t s);
+                        uint32_t* temp_ids, uint32_t* gcount, uint32_t* gstart, uint32_t seed, hipStream_t s);
 void launch_voxel_bound(const Nodes& nodes, TreeState* st, hipStream_t s);
 void launch_fill_zero(uint64_t* p, uint64_t n, hipStream_t s);
 void launch_level(uint32_t mode, const Nodes& nodes, uint32_t L, uint32_t pbegin, uint32_t pend, uint32_t cbegin,
                   uint32_t cend, uint64_t vcap, const uint64_t* temp, const uint32_t* temp_ids, uint64_t* vox,
                   uint32_t* vids, TreeState* st, uint32_t* tilesum, uint32_t* runidx, uint32_t* runpos,
-                  uint8_t* vflag, uint32_t* vowner, uint32_t seed, hipStream_t s);
+                  uint8_t* vflag, uint32_t* vowner, const uint32_t* gcount, const uint32_t* gstart, uint32_t seed,
+                  hipStream_t s);
 
 }  // namespace lod

@@ -93,7 +93,7 @@ struct Workspace {
   Scratch X, Xid, bbox, cube, segs, chunks, counters, hist, grids, pool, pool2, refine, leaf_refine;
   Scratch groups, gsum, tilesum, runidx, inner_ids, inner_voff, starts;
   Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_aux, n_jobofs;
-  Scratch n_dstbase, n_firstrun, runpos;
+  Scratch n_dstbase, n_firstrun, runpos, gcount, gstart;
   Scratch state;
   HostStage* host = nullptr;
   hipEvent_t ev[16] = {};
@@ -103,7 +103,7 @@ struct Workspace {
       for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
     Scratch* all[] = {&X, &Xid, &bbox, &cube, &segs, &chunks, &counters, &hist, &grids, &pool, &pool2, &refine,
                       &leaf_refine, &groups, &gsum, &tilesum, &runidx, &inner_ids, &inner_voff, &starts, &n_level, &n_leaf, &n_mask, &n_key, &n_npts, &n_count, &n_first, &n_off,
-                      &n_cover, &n_grid, &n_parent, &n_aux, &n_jobofs, &state, &n_dstbase, &n_firstrun, &runpos};
+                      &n_cover, &n_grid, &n_parent, &n_aux, &n_jobofs, &state, &n_dstbase, &n_firstrun, &runpos, &gcount, &gstart};
     for (Scratch* s : all) s->drop(dev);
     if (host) (void)hipHostFree(host);
   }
@@ -398,7 +398,9 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
 
   // 5. voxels: leaves (all levels at once) into X, then the bound, then levels bottom-up
   uint64_t* temp = (uint64_t*)X;
-  launch_leaf_voxels(pl.mode, nd, num_nodes, gp.grids, gp.pool, Y, Yid, cube, temp, Xid, prm.seed, s);
+  uint32_t* gcount = w.gcount.get<uint32_t>(dev, 8ull * num_nodes);
+  uint32_t* gstart = w.gstart.get<uint32_t>(dev, 8ull * num_nodes);
+  launch_leaf_voxels(pl.mode, nd, num_nodes, gp.grids, gp.pool, Y, Yid, cube, temp, Xid, gcount, gstart, prm.seed, s);
   tm.mark(EV_LEAF);
   launch_voxel_bound(nd, st, s);
   HIPCHK(hipGetLastError());
@@ -418,7 +420,7 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
   for (int L = deepest_inner; L >= 0; --L)
     launch_level(pl.mode, nd, (uint32_t)L, levels.level_begin[L], levels.level_end[L], levels.level_begin[L + 1],
                  levels.level_end[L + 1], vcap, temp, Xid, vox, vids, st, tilesum, runidx, runpos, vflag, vowner,
-                 prm.seed, s);
+                 gcount, gstart, prm.seed, s);
   HIPCHK(hipGetLastError());
   tm.mark(EV_LEVELS);
 
