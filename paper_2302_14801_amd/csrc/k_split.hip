@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
   const CubeD cd = load_cube(cube);
   const uint32_t shift = 3u * (kKeyLevels - (sg.level + E));
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) h[j] = 0;
-  __syncthreads();
+  lds_barrier();
   const uint4* p = pts + ch.start;
   uint32_t i = threadIdx.x;
   for (; i + 3 * kCountWG < ch.count; i += 4 * kCountWG) {
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
     uint4 v = p[i];
     atomicAdd(&h[(point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd) >> shift) & (B - 1)], 1u);
   }
-  __syncthreads();
+  lds_barrier();
   uint32_t* row = hist + (uint64_t)c * B;
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) row[j] = h[j];
 }
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     cursor[PAD(j)] = goff[j] + row[j];
     cnt[PAD(j)] = 0;
   }
-  __syncthreads();
+  lds_barrier();
   // software pipeline: the records of round r + 1 are loaded while round r is
   // sorted in LDS and written out
   uint4 v[kScatPPT];
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     uint4 vn[kScatPPT];
     uint32_t idn[kScatPPT];
     load_round(base + kScatR, vn, idn);
-    __syncthreads();
+    lds_barrier();
     // exclusive scan of the round's cell counts (in place); keep counts in registers
     uint32_t mine[BPT];
     uint32_t local = 0;
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
       if (b < B) cnt[PAD(b)] = ex;
       ex += mine[k];
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int k = 0; k < kScatPPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
@@ -414,14 +414,14 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
         if (IDS) stage_id[pos] = id[k];
       }
     }
-    __syncthreads();
+    lds_barrier();
     for (uint32_t j = threadIdx.x; j < nround; j += kScatWG) {
       const uint32_t b = stage_b[j];
       const uint32_t d = cursor[PAD(b)] + (j - cnt[PAD(b)]);
       dst[d] = stage[j];
       if (IDS) dst_ids[d] = stage_id[j];
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (uint32_t k = 0; k < BPT; ++k) {
       const uint32_t b = threadIdx.x * BPT + k;
@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
         cnt[PAD(b)] = 0;
       }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int k = 0; k < kScatPPT; ++k) {
       v[k] = vn[k];

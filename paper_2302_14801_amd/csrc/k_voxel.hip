@@ -45,7 +45,7 @@ __device__ void leaf_wide_average(uint64_t* acc /* 2048 words of LDS */, uint32_
   uint64_t* wn = acc + 1536;
   for (uint32_t w0 = 0; w0 < kSubCells; w0 += 512) {
     for (uint32_t i = threadIdx.x; i < 2048; i += kLeafWG) acc[i] = 0;
-    __syncthreads();
+    lds_barrier();
     for (uint32_t i = threadIdx.x; i < cnt; i += kLeafWG) {
       const uint4 v = pts[off + i];
       const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
@@ -58,7 +58,7 @@ __device__ void leaf_wide_average(uint64_t* acc /* 2048 words of LDS */, uint32_
         atomicAdd((unsigned long long*)&wn[q], 1ull);
       }
     }
-    __syncthreads();
+    lds_barrier();
     for (uint32_t s0 = 0; s0 < 512; s0 += kLeafWG) {
       const uint32_t q = s0 + threadIdx.x;
       const uint64_t c = wn[q];
@@ -71,7 +71,7 @@ __device__ void leaf_wide_average(uint64_t* acc /* 2048 words of LDS */, uint32_
       }
       vbase += tot;
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
     return;
   }
   for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-  __syncthreads();
+  lds_barrier();
   uint32_t vbase = 0;
   for (uint32_t jm = grp * 8; jm < grp * 8 + 8; ++jm) {
     const uint64_t idx = (leaf_rel << 6) | jm;
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
     if (MODE == 0 && cnt > kPackedMax) {
       leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
       for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-      __syncthreads();
+      lds_barrier();
       continue;
     }
     // accumulate: every thread first issues all loads of a batch, then hashes
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (MODE != 0) {
       // the winner of every cell deposits its colour and id
       for (uint32_t i = threadIdx.x; i < cnt; i += kLeafWG) {
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
           wid[sub] = id;
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
     // emit.  Lane l of wave w owns cells 256k + 64w + l (k = 0..15); the
     // wave's ballot over cells 256k + 64w .. +63 is occupancy word 4k + w, so
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
         for (uint32_t k = 0; k < 16; ++k) wcount[4 * k + w] = (uint32_t)__popcll(bal[k]);
         wover[w] = any_over ? 1u : 0u;
       }
-      __syncthreads();
+      lds_barrier();
       const bool redo = MODE == 0 && (wover[0] | wover[1] | wover[2] | wover[3]);
       const uint32_t mine = wcount[l];
       const uint32_t incl = wave_incl_scan(mine);
@@ -246,15 +246,15 @@ __global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t n
           }
         }
         vbase += total;
-        __syncthreads();
+        lds_barrier();
       } else {
         // a cell overflowed the packed fields: clear and redo this micro-bucket exactly
-        __syncthreads();
+        lds_barrier();
         for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-        __syncthreads();
+        lds_barrier();
         leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
         for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-        __syncthreads();
+        lds_barrier();
       }
     }
   }

@@ -7,6 +7,13 @@ namespace lod {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations and meets the other waves, but, unlike
+// __syncthreads(), does not wait for outstanding global loads and stores, so
+// prefetched loads and stores stay in flight across it.  Use __syncthreads()
+// where waves exchange data through global memory.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Inclusive scan across the 64 lanes of a wavefront.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
@@ -37,7 +44,7 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
   const uint32_t w = threadIdx.x / 64;
   T inc = wave_incl_scan(v);
   if (lane == 63) sh[w] = inc;
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     T s = 0;
     for (int i = 0; i < NW; ++i) {
@@ -47,10 +54,10 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
     }
     sh[NW] = s;
   }
-  __syncthreads();
+  lds_barrier();
   T r = sh[w] + inc - v;
   *total = sh[NW];
-  __syncthreads();
+  lds_barrier();
   return r;
 }
 
