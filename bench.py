@@ -7,10 +7,22 @@ step = one complete lod_build of the whole cloud (bounding box, both
 partition passes, node enumeration, leaf and inner voxels, output tables)
 plus lod_tree_free, with the input already resident in HBM.
 
+Beside it, on the same box and in the same run:
+  batched: 512 independent chunks (lognormal sizes, median 1M, sigma 0.5,
+           clipped 10k-20M; terrain + buildings tiles) built by one
+           lod_build_batch call, against lod_build on each chunk in turn,
+           both with the input resident in HBM;
+  served:  Poisson arrivals at 200 requests/s of chunks from host memory
+           (lognormal sizes, median 2M, sigma 1.0, clipped 50k-50M; prefixes
+           of 50M-point tiles of the same generator) through lod_submit /
+           lod_poll, reporting throughput and p50/p99 latency (completion
+           minus scheduled arrival, including queueing and the host-to-device
+           copy), against the same requests built one by one.
+
 Prints one JSON line with the throughput (points/s), the roofline of the
 dominant kernel (algorithmic bytes per launch over its average duration,
-measured with HIP events on the build stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+measured with HIP events on the build stream), the CPU oracle timed on a
+bounded sample of the same workload, and the batched and served results.
 """
 from __future__ import annotations
 
@@ -81,6 +93,150 @@ def measured_traffic(kernel: str, workload: str, sampling: int):
     return round(sum(per) / len(per), 1)
 
 
+def params_plain(lod, args, sampling):
+    return lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling)
+
+
+def run_batched(lod, torch, num_chunks: int, reps: int, params):
+    """One lod_build_batch over all chunks (median of `reps`) against
+    lod_build per chunk, input resident in HBM in both cases."""
+    import synth
+    sizes = synth.chunk_sizes(num_chunks, seed=4)
+    total = int(sizes.sum())
+    print(f"[bench] batched: generating {num_chunks} chunks, {total} points", file=sys.stderr, flush=True)
+    host = torch.empty(total * 16, dtype=torch.uint8, pin_memory=True)
+    pts = host.numpy().view(synth.POINT_DTYPE)
+    _, offs = synth.batch_chunks(sizes, seed=4, out=pts)
+    dev = host.to("cuda:0")
+    del host, pts
+    stream = torch.cuda.current_stream()
+
+    def batch(p):
+        trees = lod.lod_build_batch(dev, offs, params=p, stream=stream)
+        nodes = sum(t.view().num_nodes for t in trees)
+        voxels = sum(t.view().num_voxels for t in trees)
+        for t in trees:
+            t.free()
+        return nodes, voxels
+
+    def timed(p):
+        batch(p)  # warm-up (allocations)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = batch(p)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return float(np.median(times)), res
+
+    from paper_2302_14801_amd import autotune
+    t0 = time.perf_counter()
+    tuned, tune_info = autotune.tune_batch(dev, offs, params, sample_chunks=64, reps=2, stream=stream)
+    tune_info["tuning_s"] = round(time.perf_counter() - t0, 3)
+    print(f"[bench] batched: tuned plan {tune_info['plan']}", file=sys.stderr, flush=True)
+    t_default, _ = timed(params)
+    t_batch, (nodes, voxels) = timed(tuned)
+    print(f"[bench] batched: {1e3 * t_batch:.2f} ms per batch; plain builds next", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(num_chunks):
+        t = lod.lod_build(dev[int(offs[i]) * 16:int(offs[i + 1]) * 16], params=params, stream=stream)
+        t.free()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    del dev
+    torch.cuda.empty_cache()
+    return {"workload": f"{num_chunks} chunks, lognormal sizes (median 1M, sigma 0.5, clipped 10k-20M), "
+                        "terrain+buildings tiles with their own bounding boxes; input resident in HBM",
+            "chunks": num_chunks, "points": total, "nodes": nodes, "voxels": voxels,
+            "batched_points_per_s": round(total / t_batch, 1), "batched_ms": round(1e3 * t_batch, 3),
+            "untuned_points_per_s": round(total / t_default, 1), "autotune": tune_info,
+            "plain_points_per_s": round(total / t_plain, 1), "plain_ms": round(1e3 * t_plain, 3),
+            "batched_over_plain": round(t_plain / t_batch, 3), "reps": reps}
+
+
+def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, inflight: int,
+               pool_tiles: int, keep: int):
+    """Open-loop Poisson client of the request server, then the same requests
+    built one by one (host to device copy + lod_build each)."""
+    import synth
+    rng = np.random.default_rng(5)
+    gaps = rng.exponential(1.0 / rate, num_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    sizes = synth.chunk_sizes(num_requests, seed=5, median=2e6, sigma=1.0, lo=50_000, hi=50_000_000)
+    tile_n = int(min(50_000_000, sizes.max()))
+    print(f"[bench] served: generating {pool_tiles} tiles of {tile_n} points", file=sys.stderr, flush=True)
+    tiles = []
+    for k in range(pool_tiles):
+        h = torch.empty(tile_n * 16, dtype=torch.uint8, pin_memory=True)
+        synth.serve_tile(tile_n, seed=5000 + k, out=h.numpy().view(synth.POINT_DTYPE))
+        tiles.append(h.numpy().view(synth.POINT_DTYPE))
+    reqs = [tiles[r % pool_tiles][:int(sizes[r])] for r in range(num_requests)]
+    total = int(sizes.sum())
+
+    srv = lod.Server(budget, inflight, params=params)
+    # warm-up: one request of each of a few sizes
+    for r in range(min(4, num_requests)):
+        tk = srv.submit(reqs[r])
+        while srv.poll(tk) is None:
+            time.sleep(0.0005)
+    resident, lat, build_done = [], np.zeros(num_requests), np.zeros(num_requests)
+    pending = {}
+    print(f"[bench] served: {num_requests} requests at {rate}/s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    nxt = 0
+    while nxt < num_requests or pending:
+        now = time.perf_counter() - t0
+        while nxt < num_requests and arrivals[nxt] <= now:
+            pending[srv.submit(reqs[nxt])] = nxt
+            nxt += 1
+        for tk in list(pending):
+            t = srv.poll(tk)
+            if t is not None:
+                i = pending.pop(tk)
+                done = time.perf_counter() - t0
+                lat[i] = done - arrivals[i]
+                build_done[i] = done
+                resident.append(t)
+                while len(resident) > keep:
+                    resident.pop(0).free()
+        if nxt < num_requests and not pending:
+            time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))
+        else:
+            time.sleep(0.0002)
+    t_served = build_done.max() - arrivals[0]
+    for t in resident:
+        t.free()
+    srv.destroy()
+    # the same requests one by one
+    print("[bench] served: plain sequential builds", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    dbuf = torch.empty(tile_n * 16, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for r in range(num_requests):
+        n = int(sizes[r])
+        src = torch.from_numpy(reqs[r].view(np.uint8).reshape(-1))
+        dbuf[:n * 16].copy_(src, non_blocking=True)
+        t = lod.lod_build(dbuf[:n * 16], params=params, stream=stream)
+        t.free()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - p0
+    del dbuf, tiles, reqs
+    torch.cuda.empty_cache()
+    return {"workload": f"{num_requests} requests, Poisson arrivals at {rate:g}/s, lognormal sizes (median 2M, "
+                        f"sigma 1.0, clipped 50k-50M), prefixes of {pool_tiles} pinned host tiles of {tile_n} points; "
+                        f"budget {budget >> 30} GiB, {inflight} in flight, newest {keep} trees kept",
+            "requests": num_requests, "points": total,
+            "served_points_per_s": round(total / t_served, 1),
+            "p50_latency_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "p99_latency_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+            "max_latency_ms": round(1e3 * float(lat.max()), 3),
+            "offered_points_per_s": round(total / (arrivals[-1] - arrivals[0]), 1),
+            "plain_points_per_s": round(total / t_plain, 1), "plain_s": round(t_plain, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +250,11 @@ def main():
                     help="points of the workload the CPU oracle builds (0 = skip)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one plain device copy of the input first (known bytes, for counter calibration)")
+    ap.add_argument("--batch-chunks", type=int, default=512, help="chunks of the batched run (0 = skip)")
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests of the served run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-tiles", type=int, default=4)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -181,6 +342,15 @@ def main():
                          f"generator interleaves scene components at random); single-threaded C oracle, "
                          f"build only, {c1 - c0:.2f} s"}
 
+    del dev
+    torch.cuda.empty_cache()
+    batched = served = None
+    if args.batch_chunks > 0:
+        batched = run_batched(lod, torch, args.batch_chunks, args.batch_reps, params_plain(lod, args, sampling))
+    if args.serve_requests > 0:
+        served = run_served(lod, torch, args.serve_requests, args.serve_rate, params_plain(lod, args, sampling),
+                            192 << 30, 4, args.serve_tiles, 256)
+
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -204,6 +374,8 @@ def main():
         "whole_build_alg_GBps": round(whole_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "nodes": nodes,
         "voxels": voxels,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
 

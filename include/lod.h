@@ -85,7 +85,9 @@ typedef struct {
   uint32_t flags;        /* LOD_FLAG_* */
   uint32_t tune_levels0; /* 0 = automatic; else levels sorted by the first partition pass (1..4) */
   uint32_t tune_levels1; /* 0 = automatic; else levels sorted by the second pass (1..4) */
-  uint32_t reserved;
+  uint32_t tune_chunk;   /* 0 = automatic; else points per partition work item (rounded to
+                            whole insert rounds, at least one).  The tune_* fields choose
+                            how the work is cut, never what is computed. */
 } lod_params;
 
 typedef struct lod_tree lod_tree;

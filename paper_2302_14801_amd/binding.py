@@ -31,7 +31,7 @@ class LodError(RuntimeError):
 class lod_params(ctypes.Structure):
     _fields_ = [("leaf_cap", ctypes.c_uint32), ("max_level", ctypes.c_uint32), ("sampling", ctypes.c_uint32),
                 ("seed", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("tune_levels0", ctypes.c_uint32),
-                ("tune_levels1", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("tune_levels1", ctypes.c_uint32), ("tune_chunk", ctypes.c_uint32)]
 
 
 class lod_tree_view(ctypes.Structure):
@@ -112,12 +112,12 @@ def _check(status: int):
 
 
 def make_params(leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0, keep_ids=False,
-                tune_levels0=0, tune_levels1=0, timing=False) -> lod_params:
+                tune_levels0=0, tune_levels1=0, timing=False, tune_chunk=0) -> lod_params:
     p = lod_params()
     load_library().lod_params_default(ctypes.byref(p))
     p.leaf_cap, p.max_level, p.sampling, p.seed = leaf_cap, max_level, sampling, seed
     p.flags = (LOD_FLAG_POINT_IDS if keep_ids else 0) | (LOD_FLAG_TIMING if timing else 0)
-    p.tune_levels0, p.tune_levels1 = tune_levels0, tune_levels1
+    p.tune_levels0, p.tune_levels1, p.tune_chunk = tune_levels0, tune_levels1, tune_chunk
     return p
 
 

@@ -163,6 +163,18 @@ struct Segment {
   uint64_t key;  // prefix at `level`
   uint32_t group_begin;
   uint32_t group_count;
+  uint32_t cloud;  // input cloud whose cube quantises the segment's points
+  uint32_t pad;
+};
+
+// One independent input cloud of a build (lod_build: one, lod_build_batch:
+// one per non-empty chunk).  Its points stay in [start, start + count) of
+// every point buffer of the build.
+struct CloudInfo {
+  uint32_t start;
+  uint32_t count;
+  uint32_t tile_base;  // first bounding-box tile of the cloud
+  uint32_t pad;
 };
 struct Chunk {
   uint32_t seg;
@@ -186,36 +198,59 @@ struct Nodes {
   uint8_t* child_mask;
   uint64_t* key;
   uint32_t* npoints;
-  uint32_t* count;
+  uint32_t* count;        // points (leaf) or voxels (inner)
   uint32_t* first_child;
-  uint64_t* offset;
+  uint64_t* offset;       // into the points (leaf) or the voxels (inner)
   int32_t* cover;   // grid whose range contains the node
   int32_t* grid;    // grid based at the node (-1 = none)
   uint32_t* parent;
-  uint32_t* aux;    // per-node scratch: leaf voxel count / run count
-  uint32_t* jobofs; // offset of the node's contribution inside its parent's voxel list
-  uint64_t* dstbase;  // inner node: where its contribution to the parent's list starts
-  uint32_t* firstrun; // inner node: level-wide index of its first run
+  uint32_t* tree;   // input cloud (tree) of the node
+};
+
+// Where a finished tree sits in the build's arrays (device copy per tree).
+struct TreeInfo {
+  uint32_t node_base;  // first node of the tree in the compact node table
+  uint32_t num_nodes;
+  uint32_t point_base;  // first point of the tree's cloud
+  uint32_t deepest;     // deepest level with nodes
+  uint32_t level_begin[23];  // nodes of level L: [level_begin[L], level_end[L]) (compact)
+  uint32_t level_end[23];
+  uint64_t vbase;   // first voxel of the tree in the build's voxel array
+  uint64_t vtotal;  // voxels of the tree
+};
+
+// Per-node data of the voxel stage.
+struct VoxTree {
+  uint32_t* sz;        // nodes in the subtree (the node included)
+  uint32_t* dfs;       // depth-first position
+  uint32_t* dfs_node;  // node at a depth-first position
+  uint32_t* psize;     // 8 per node: piece lengths by depth above the node (1..7)
+  uint64_t* poff;      // 8 per node: output position of each piece
+  uint32_t* selfc;     // self voxel (nodes at level >= 7): colour and id
+  uint32_t* selfid;
 };
 
 // Tree-builder state shared between launches (device memory).
+// One per tree while it is built; node indices are absolute slots of the
+// tree's region [node_begin, node_end) of the build's node table.
 struct TreeState {
-  uint32_t num_nodes;
+  uint32_t num_nodes;      // next free node slot
   uint32_t next_level;     // level whose nodes have not been enumerated yet
   uint32_t status;         // 0 running, 1 done, 2 needs refinement of inner nodes
-  uint32_t num_refine;     // inner nodes to refine before continuing
-  uint32_t num_leaf_refine;
+  uint32_t node_begin;
+  uint32_t node_end;
   uint32_t overflow;       // node capacity exceeded
   uint32_t level_begin[23];
   uint32_t level_end[23];
-  uint64_t voxel_total;    // running total while voxel lists are assembled
-  uint64_t voxel_bound;    // capacity needed for all voxel lists
-  uint64_t level_vbegin[23];  // voxels of the inner nodes of a level: [vbegin, vbegin + vcount)
-  uint64_t level_vcount[23];
-  uint32_t level_ibegin[23];  // their node ids / voxel offsets in the inner lists: [ibegin, iend)
-  uint32_t level_iend[23];
-  uint32_t inner_total;
-  uint32_t num_tiles;
+};
+
+// Build-wide state of the tree and voxel passes.
+struct BuildState {
+  uint32_t nref;         // inner nodes queued for refinement in this round
+  uint32_t nlref;        // leaves queued for refinement (all rounds)
+  uint32_t overflow;     // some tree exceeded its node capacity
+  uint32_t pad;
+  uint64_t coarse_used;  // entries of the coarse-list buffer handed out
 };
 
 }  // namespace lod

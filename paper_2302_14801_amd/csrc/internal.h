@@ -93,26 +93,40 @@ inline DeviceCache& cache() {
 
 // ---------------------------------------------------------------- the tree
 
-struct lod_tree {
+// Device memory of the trees of one build call (one tree for lod_build, the
+// chunks of lod_build_batch), released with the last of them.
+struct LodArena {
   int dev = 0;
-  lod_tree_view v{};
-  lod_timings timings{};
   std::vector<void*> blocks;
-  uint64_t footprint = 0;
-  std::shared_ptr<std::atomic<uint64_t>> budget_used;  // server accounting, if any
-  ~lod_tree() {
+  uint64_t bytes = 0;
+  ~LodArena() {
     for (void* p : blocks) lodint::cache().release(dev, p);
-    if (budget_used) budget_used->fetch_sub(footprint);
   }
   template <typename T>
   T* alloc(size_t count) {
     void* p = lodint::cache().alloc(dev, count * sizeof(T));
     blocks.push_back(p);
-    footprint += count * sizeof(T);
+    bytes += count * sizeof(T);
     return (T*)p;
   }
 };
 
+struct lod_tree {
+  int dev = 0;
+  lod_tree_view v{};
+  lod_timings timings{};
+  std::shared_ptr<LodArena> arena;
+  uint64_t footprint = 0;                              // device bytes accounted to this tree
+  std::shared_ptr<std::atomic<uint64_t>> budget_used;  // server accounting, if any
+  ~lod_tree() {
+    if (budget_used) budget_used->fetch_sub(footprint);
+  }
+};
 
-// Build one tree on `stream` (blocking until complete); throws LodError.
+// Build the trees of `nclouds` independent clouds, cloud i being points
+// [offs[i], offs[i+1]) of d_points (offs on the host), on `stream`, blocking
+// until complete; throws LodError.  One tree per cloud, in order.
+std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_t* offs, uint32_t nclouds,
+                                        const lod_params& p, hipStream_t stream);
+// One cloud.
 lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params& p, hipStream_t stream);

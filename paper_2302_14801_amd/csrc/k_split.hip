@@ -21,21 +21,43 @@ namespace lod {
 
 // ------------------------------------------------------------ bounding box
 
-__global__ void k_bbox_init(BBoxAcc* acc) {
-  if (threadIdx.x < 3) {
-    acc->lo[threadIdx.x] = 0xffffffffu;
-    acc->hi[threadIdx.x] = 0u;
+__global__ void k_bbox_init(BBoxAcc* acc, uint32_t nclouds) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nclouds) return;
+  for (int a = 0; a < 3; ++a) {
+    acc[c].lo[a] = 0xffffffffu;
+    acc[c].hi[a] = 0u;
   }
-  if (threadIdx.x == 0) acc->nonfinite = 0u;
+  acc[c].nonfinite = 0u;
 }
 
 constexpr int kBBoxWG = 256;
+constexpr uint32_t kBBoxTile = kBBoxWG * 64;  // points per workgroup
 
-__global__ void __launch_bounds__(kBBoxWG) k_bbox(const uint4* __restrict__ pts, uint64_t n, BBoxAcc* acc) {
+// Cloud of a bounding-box tile: the last cloud whose first tile is <= t.
+__device__ __forceinline__ uint32_t tile_cloud(const CloudInfo* __restrict__ clouds, uint32_t nclouds, uint32_t t) {
+  uint32_t lo = 0, hi = nclouds;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (clouds[mid].tile_base <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One tile of at most kBBoxTile points of one cloud per workgroup; per-cloud
+// minima and maxima of the order-preserving integer images of x, y, z.
+__global__ void __launch_bounds__(kBBoxWG) k_bbox(const uint4* __restrict__ pts, const CloudInfo* __restrict__ clouds,
+                                                  uint32_t nclouds, BBoxAcc* acc) {
+  const uint32_t c = tile_cloud(clouds, nclouds, blockIdx.x);
+  const CloudInfo ci = clouds[c];
+  const uint64_t t0 = (uint64_t)ci.start + (uint64_t)(blockIdx.x - ci.tile_base) * kBBoxTile;
+  const uint64_t n = min((uint64_t)ci.start + ci.count, t0 + kBBoxTile);
+  acc += c;
   uint32_t lo0 = 0xffffffffu, lo1 = 0xffffffffu, lo2 = 0xffffffffu;
   uint32_t hi0 = 0u, hi1 = 0u, hi2 = 0u, bad = 0u;
-  const uint64_t stride = (uint64_t)gridDim.x * kBBoxWG;
-  uint64_t i = (uint64_t)blockIdx.x * kBBoxWG + threadIdx.x;
+  const uint64_t stride = kBBoxWG;
+  uint64_t i = t0 + threadIdx.x;
   auto acc1 = [&](const uint4& v) {
     // exponent all ones = Inf or NaN
     uint32_t nf = ((v.x & 0x7f800000u) == 0x7f800000u) | ((v.y & 0x7f800000u) == 0x7f800000u) |
@@ -83,23 +105,26 @@ __global__ void __launch_bounds__(kBBoxWG) k_bbox(const uint4* __restrict__ pts,
   }
 }
 
-// The bounding cube: anchored at the minimum, side = largest extent.
-__global__ void k_cube(const BBoxAcc* acc, uint64_t n, Cube* cube) {
-  if (threadIdx.x != 0) return;
+// The bounding cube of every cloud: anchored at the minimum, side = largest
+// extent (1 if all points coincide).
+__global__ void k_cube(const BBoxAcc* acc, const CloudInfo* clouds, uint32_t nclouds, Cube* cube) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nclouds) return;
+  const uint32_t n = clouds[c].count;
   double side = 0.0;
   for (int a = 0; a < 3; ++a) {
-    float lo = n ? order_float(acc->lo[a]) : 0.f;
-    float hi = n ? order_float(acc->hi[a]) : 0.f;
-    if (acc->lo[a] == 0xffffffffu) lo = hi = 0.f;  // every point rejected
-    cube->lo[a] = lo;
-    cube->hi[a] = hi;
+    float lo = n ? order_float(acc[c].lo[a]) : 0.f;
+    float hi = n ? order_float(acc[c].hi[a]) : 0.f;
+    if (acc[c].lo[a] == 0xffffffffu) lo = hi = 0.f;  // every point rejected
+    cube[c].lo[a] = lo;
+    cube[c].hi[a] = hi;
     double e = __dsub_rn((double)hi, (double)lo);
     if (e > side) side = e;
   }
   if (side == 0.0) side = 1.0;
-  cube->side = side;
-  cube->scale = 2097152.0 / side;
-  cube->nonfinite = acc->nonfinite;
+  cube[c].side = side;
+  cube[c].scale = 2097152.0 / side;
+  cube[c].nonfinite = acc[c].nonfinite;
 }
 
 // ------------------------------------------------------------ partition
@@ -193,7 +218,7 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
   if (c >= *nchunk_ptr) return;
   const Chunk ch = chunks[c];
   const Segment sg = segs[ch.seg];
-  const CubeD cd = load_cube(cube);
+  const CubeD cd = load_cube(cube + sg.cloud);
   const uint32_t shift = 3u * (kKeyLevels - (sg.level + E));
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) h[j] = 0;
   lds_barrier();
@@ -314,12 +339,20 @@ __global__ void __launch_bounds__(kGridWG) k_grid_finish(const Segment* __restri
 // Insert (Sec. 4.1.4): move every point of a chunk to its cell.  A round of
 // R = WG * PPT points is sorted by cell in LDS (counting sort: LDS histogram,
 // workgroup prefix sum, staging), then written out so that consecutive lanes
-// store consecutive records of the same cell.  Per-cell cursors in LDS start
-// at the chunk's target offsets and advance round by round.
-constexpr int kScatWG = 512;
+// store consecutive records of the same cell.  The per-cell output cursors
+// start at the chunk's target offsets and advance round by round; they live
+// in registers (thread t owns cells t*BPT .. t*BPT+BPT-1), so that a single
+// LDS array of cell counts serves the histogram, the staging offsets and the
+// output deltas, and the rest of LDS holds as large a round as possible: the
+// stores of a round are runs of consecutive records per cell, and longer runs
+// write HBM more efficiently.
+constexpr int kScatWG = 1024;
 #define PAD(b) ((b) + ((b) >> 5))
-constexpr int kScatPPT = 4;
-constexpr int kScatR = kScatWG * kScatPPT;
+template <bool IDS>
+struct ScatShape {
+  static constexpr int PPT = IDS ? 6 : 7;  // LDS: R*(16 + 2 + 4*IDS) bytes of staging + 16.5 KB of counts
+  static constexpr int R = kScatWG * PPT;
+};
 
 template <int E, bool IDS>
 __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
@@ -328,53 +361,60 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
                                                           const Chunk* __restrict__ chunks, const uint32_t* nchunk_ptr,
                                                           const uint32_t* __restrict__ hist,
                                                           const GridDesc* __restrict__ grids, const uint32_t* __restrict__ pool) {
+  constexpr int PPT = ScatShape<IDS>::PPT;
+  constexpr uint32_t R = ScatShape<IDS>::R;
   constexpr uint32_t B = 1u << (3 * E);
   constexpr uint32_t BPT = (B + kScatWG - 1) / kScatWG;  // cells per thread in the scan
   // one padding word per 32 cells: the scan's per-thread runs of BPT cells
   // then fall on distinct LDS banks
   constexpr uint32_t BP = B + B / 32 + 1;
-  __shared__ uint32_t cursor[BP];
   __shared__ uint32_t cnt[BP];
-  __shared__ uint4 stage[kScatR];
-  __shared__ uint16_t stage_b[kScatR];
-  __shared__ uint32_t stage_id[IDS ? kScatR : 1];
+  __shared__ uint4 stage[R];
+  __shared__ uint16_t stage_b[R];
+  __shared__ uint32_t stage_id[IDS ? R : 1];
   __shared__ uint32_t sh[kScatWG / 64 + 1];
   const uint32_t c = blockIdx.x;
   if (c >= *nchunk_ptr) return;
   const Chunk ch = chunks[c];
   const Segment sg = segs[ch.seg];
   const GridDesc g = grids[sg.grid];
-  const CubeD cd = load_cube(cube);
+  const CubeD cd = load_cube(cube + sg.cloud);
   const uint32_t shift = 3u * (kKeyLevels - (sg.level + E));
   const uint32_t* row = hist + (uint64_t)c * B;
   const uint32_t* goff = pool + g.off;
-  for (uint32_t j = threadIdx.x; j < B; j += kScatWG) {
-    cursor[PAD(j)] = goff[j] + row[j];
-    cnt[PAD(j)] = 0;
+  // without source ids (the first pass over the input, one segment per
+  // cloud) a point's id is its index in its cloud
+  const uint32_t ch_cloud_start = sg.start;
+  uint32_t cur[BPT];
+#pragma unroll
+  for (uint32_t k = 0; k < BPT; ++k) {
+    const uint32_t b = threadIdx.x * BPT + k;
+    cur[k] = b < B ? goff[b] + row[b] : 0u;
   }
+  for (uint32_t j = threadIdx.x; j < B; j += kScatWG) cnt[PAD(j)] = 0;
   lds_barrier();
   // software pipeline: the records of round r + 1 are loaded while round r is
   // sorted in LDS and written out
-  uint4 v[kScatPPT];
-  uint32_t id[kScatPPT];
+  uint4 v[PPT];
+  uint32_t id[PPT];
   auto load_round = [&](uint32_t base, uint4* vv, uint32_t* ii) {
-    const uint32_t nround = base < ch.count ? min((uint32_t)kScatR, ch.count - base) : 0u;
+    const uint32_t nround = base < ch.count ? min(R, ch.count - base) : 0u;
 #pragma unroll
-    for (int k = 0; k < kScatPPT; ++k) {
+    for (int k = 0; k < PPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
         const uint32_t gi = ch.start + base + j;
         vv[k] = src[gi];
-        if (IDS) ii[k] = src_ids ? src_ids[gi] : gi;
+        if (IDS) ii[k] = src_ids ? src_ids[gi] : gi - ch_cloud_start;
       }
     }
   };
   load_round(0, v, id);
-  for (uint32_t base = 0; base < ch.count; base += kScatR) {
-    const uint32_t nround = min((uint32_t)kScatR, ch.count - base);
-    uint32_t bk[kScatPPT], rk[kScatPPT];
+  for (uint32_t base = 0; base < ch.count; base += R) {
+    const uint32_t nround = min(R, ch.count - base);
+    uint32_t bk[PPT], rk[PPT];
 #pragma unroll
-    for (int k = 0; k < kScatPPT; ++k) {
+    for (int k = 0; k < PPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
         uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
@@ -382,12 +422,13 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
         rk[k] = atomicAdd(&cnt[PAD(bk[k])], 1u);
       }
     }
-    uint4 vn[kScatPPT];
-    uint32_t idn[kScatPPT];
-    load_round(base + kScatR, vn, idn);
+    uint4 vn[PPT];
+    uint32_t idn[PPT];
+    load_round(base + R, vn, idn);
     lds_barrier();
-    // exclusive scan of the round's cell counts (in place); keep counts in registers
-    uint32_t mine[BPT];
+    // exclusive scan of the round's cell counts (in place); counts and
+    // prefixes stay in registers
+    uint32_t mine[BPT], exk[BPT];
     uint32_t local = 0;
 #pragma unroll
     for (uint32_t k = 0; k < BPT; ++k) {
@@ -400,12 +441,13 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
 #pragma unroll
     for (uint32_t k = 0; k < BPT; ++k) {
       const uint32_t b = threadIdx.x * BPT + k;
+      exk[k] = ex;
       if (b < B) cnt[PAD(b)] = ex;
       ex += mine[k];
     }
     lds_barrier();
 #pragma unroll
-    for (int k = 0; k < kScatPPT; ++k) {
+    for (int k = 0; k < PPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
         const uint32_t pos = cnt[PAD(bk[k])] + rk[k];
@@ -415,9 +457,16 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
       }
     }
     lds_barrier();
+    // staged position j of cell b goes to cursor(b) + (j - prefix(b))
+#pragma unroll
+    for (uint32_t k = 0; k < BPT; ++k) {
+      const uint32_t b = threadIdx.x * BPT + k;
+      if (b < B) cnt[PAD(b)] = cur[k] - exk[k];
+      cur[k] += mine[k];
+    }
+    lds_barrier();
     for (uint32_t j = threadIdx.x; j < nround; j += kScatWG) {
-      const uint32_t b = stage_b[j];
-      const uint32_t d = cursor[PAD(b)] + (j - cnt[PAD(b)]);
+      const uint32_t d = cnt[PAD(stage_b[j])] + j;
       dst[d] = stage[j];
       if (IDS) dst_ids[d] = stage_id[j];
     }
@@ -425,19 +474,18 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
 #pragma unroll
     for (uint32_t k = 0; k < BPT; ++k) {
       const uint32_t b = threadIdx.x * BPT + k;
-      if (b < B) {
-        cursor[PAD(b)] += mine[k];
-        cnt[PAD(b)] = 0;
-      }
+      if (b < B) cnt[PAD(b)] = 0;
     }
     lds_barrier();
 #pragma unroll
-    for (int k = 0; k < kScatPPT; ++k) {
+    for (int k = 0; k < PPT; ++k) {
       v[k] = vn[k];
       if (IDS) id[k] = idn[k];
     }
   }
 }
+
+uint32_t scatter_round(bool ids) { return ids ? (uint32_t)ScatShape<true>::R : (uint32_t)ScatShape<false>::R; }
 
 // Copy the points (and ids) of every segment from one buffer to the other.
 __global__ void k_copy_segments(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
@@ -452,27 +500,31 @@ __global__ void k_copy_segments(const uint4* __restrict__ src, const uint32_t* _
   }
 }
 
-// One segment per non-empty finest cell of grid `g0` (the root grid), each
-// with its own grid descriptor, to be partitioned by E2 more levels.  One
-// workgroup.
-__global__ void __launch_bounds__(kChunkWG) k_segments_from_grid(GridDesc* grids, uint32_t g0, uint32_t* pool,
-                                                                 uint32_t E2, uint64_t slot_base, uint32_t first_grid,
+// One segment per non-empty finest cell of every root grid (grids 0 ..
+// ngrids-1, one workgroup each), each with its own grid descriptor, to be
+// partitioned by E2 more levels.  Segments are appended in any order; the
+// segment counter must start at 0.
+__global__ void __launch_bounds__(kChunkWG) k_segments_from_grid(GridDesc* grids, uint32_t* pool, uint32_t E2,
+                                                                 uint64_t slot_base, uint32_t first_grid,
                                                                  Segment* segs, uint32_t* nseg_ptr) {
   __shared__ uint32_t sh[kChunkWG / 64 + 1];
+  __shared__ uint32_t s_base;
+  const uint32_t g0 = blockIdx.x;
   const GridDesc g = grids[g0];
   const uint32_t B = 1u << (3 * g.e);
   const uint32_t* fin = pool + g.pyr + pyr_level_offset(g.e);
   const uint32_t* off = pool + g.off;
   int32_t* child = (int32_t*)(pool + g.child);
   const uint64_t words = grid_words(E2);
-  uint32_t base = 0;
   for (uint32_t b0 = 0; b0 < B; b0 += kChunkWG) {
     const uint32_t b = b0 + threadIdx.x;
     const uint32_t cnt = b < B ? fin[b] : 0u;
     uint32_t tot;
-    uint32_t ex = block_excl_scan<kChunkWG>(cnt ? 1u : 0u, sh, &tot);
+    const uint32_t ex = block_excl_scan<kChunkWG>(cnt ? 1u : 0u, sh, &tot);
+    if (threadIdx.x == 0) s_base = tot ? atomicAdd(nseg_ptr, tot) : 0u;
+    __syncthreads();
     if (cnt) {
-      const uint32_t s = base + ex;
+      const uint32_t s = s_base + ex;
       const uint32_t gi = first_grid + s;
       Segment sg;
       sg.start = off[b];
@@ -482,6 +534,10 @@ __global__ void __launch_bounds__(kChunkWG) k_segments_from_grid(GridDesc* grids
       sg.chunk_begin = 0;
       sg.chunk_count = 0;
       sg.key = (g.base_key << (3 * g.e)) | b;
+      sg.group_begin = 0;
+      sg.group_count = 0;
+      sg.cloud = g0;
+      sg.pad = 0;
       segs[s] = sg;
       GridDesc d;
       d.base_level = sg.level;
@@ -495,51 +551,57 @@ __global__ void __launch_bounds__(kChunkWG) k_segments_from_grid(GridDesc* grids
       grids[gi] = d;
       child[b] = (int32_t)gi;
     }
-    base += tot;
+    __syncthreads();
   }
-  if (threadIdx.x == 0) *nseg_ptr = base;
 }
 
-// The root partition: one segment holding every point, partitioned by the
-// first E0 levels into grid 0 (based at the root).
-__global__ void k_init_root(uint32_t n, uint32_t E0, Segment* segs, uint32_t* nseg_ptr, GridDesc* grids) {
-  if (threadIdx.x != 0) return;
+// One root segment and root grid (E0 levels, pool slot c) per cloud.
+__global__ void k_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, Segment* segs, uint32_t* nseg_ptr,
+                             GridDesc* grids) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) *nseg_ptr = nclouds;
+  if (c >= nclouds) return;
   Segment sg;
-  sg.start = 0;
-  sg.count = n;
-  sg.grid = 0;
+  sg.start = clouds[c].start;
+  sg.count = clouds[c].count;
+  sg.grid = c;
   sg.level = 0;
   sg.chunk_begin = 0;
   sg.chunk_count = 0;
   sg.key = 0;
-  segs[0] = sg;
-  *nseg_ptr = 1;
+  sg.group_begin = 0;
+  sg.group_count = 0;
+  sg.cloud = c;
+  sg.pad = 0;
+  segs[c] = sg;
   GridDesc d;
   d.base_level = 0;
   d.e = E0;
   d.base_key = 0;
-  d.pyr = 0;
-  d.off = pyr_level_offset(E0 + 1);
+  d.pyr = (uint64_t)c * grid_words(E0);
+  d.off = d.pyr + pyr_level_offset(E0 + 1);
   d.child = d.off + ((uint64_t)1 << (3 * E0));
-  d.seg_start = 0;
-  d.seg_count = n;
-  grids[0] = d;
+  d.seg_start = sg.start;
+  d.seg_count = sg.count;
+  grids[c] = d;
 }
 
 // ------------------------------------------------------------ launchers
 
-void launch_bbox(const void* pts, uint64_t n, BBoxAcc* acc, Cube* cube, hipStream_t st) {
-  hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, acc);
-  if (n) {
-    uint64_t blocks = (n + kBBoxWG * 4 - 1) / (kBBoxWG * 4);
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_bbox, dim3((uint32_t)blocks), dim3(kBBoxWG), 0, st, (const uint4*)pts, n, acc);
-  }
-  hipLaunchKernelGGL(k_cube, dim3(1), dim3(64), 0, st, acc, n, cube);
+uint32_t bbox_tiles(uint32_t count) { return (count + kBBoxTile - 1) / kBBoxTile; }
+
+void launch_bbox(const void* pts, const CloudInfo* clouds, uint32_t nclouds, uint32_t ntiles, BBoxAcc* acc, Cube* cube,
+                 hipStream_t st) {
+  const uint32_t cb = (nclouds + 255) / 256;
+  hipLaunchKernelGGL(k_bbox_init, dim3(cb), dim3(256), 0, st, acc, nclouds);
+  if (ntiles) hipLaunchKernelGGL(k_bbox, dim3(ntiles), dim3(kBBoxWG), 0, st, (const uint4*)pts, clouds, nclouds, acc);
+  hipLaunchKernelGGL(k_cube, dim3(cb), dim3(256), 0, st, acc, clouds, nclouds, cube);
 }
 
-void launch_init_root(uint32_t n, uint32_t E0, Segment* segs, uint32_t* nseg, GridDesc* grids, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, n, E0, segs, nseg, grids);
+void launch_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, Segment* segs, uint32_t* nseg,
+                       GridDesc* grids, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_roots, dim3((nclouds + 255) / 256), dim3(256), 0, st, clouds, nclouds, E0, segs, nseg,
+                     grids);
 }
 
 void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t chunk, Chunk* chunks,
@@ -627,9 +689,9 @@ void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, u
                      dst_ids, segs, nseg);
 }
 
-void launch_segments_from_grid(GridDesc* grids, uint32_t g0, uint32_t* pool, uint32_t E2, uint64_t slot_base,
+void launch_segments_from_grid(GridDesc* grids, uint32_t ngrids, uint32_t* pool, uint32_t E2, uint64_t slot_base,
                                uint32_t first_grid, Segment* segs, uint32_t* nseg, hipStream_t st) {
-  hipLaunchKernelGGL(k_segments_from_grid, dim3(1), dim3(kChunkWG), 0, st, grids, g0, pool, E2, slot_base, first_grid,
+  hipLaunchKernelGGL(k_segments_from_grid, dim3(ngrids), dim3(kChunkWG), 0, st, grids, pool, E2, slot_base, first_grid,
                      segs, nseg);
 }
 

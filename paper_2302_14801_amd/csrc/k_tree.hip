@@ -17,49 +17,57 @@
 
 namespace lod {
 
+// The root of every tree (one thread per cloud): node slot node_begin of the
+// tree's region, counted by root grid c.
 __global__ void k_tree_init(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
-                            Nodes nodes, TreeState* st) {
-  if (threadIdx.x != 0) return;
-  const GridDesc g = grids[0];
-  const uint32_t n = pool[g.pyr];  // level 0 of the root grid: all points
+                            Nodes nodes, TreeState* sts, const uint32_t* node_begin, const uint32_t* node_end,
+                            uint32_t nclouds) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nclouds) return;
+  TreeState* st = sts + c;
+  const GridDesc g = grids[c];
+  const uint32_t n = pool[g.pyr];  // level 0 of the root grid: all points of the cloud
+  const uint32_t r = node_begin[c];
   memset(st, 0, sizeof(TreeState));
-  nodes.level[0] = 0;
-  nodes.key[0] = 0;
-  nodes.npoints[0] = n;
+  nodes.level[r] = 0;
+  nodes.key[r] = 0;
+  nodes.npoints[r] = n;
   const bool inner = n > leaf_cap && max_level > 0;
-  nodes.is_leaf[0] = inner ? 0 : 1;
-  nodes.child_mask[0] = 0;
-  nodes.first_child[0] = 0;
-  nodes.offset[0] = 0;
-  nodes.count[0] = inner ? 0 : n;
-  nodes.cover[0] = 0;
-  nodes.grid[0] = 0;
-  nodes.parent[0] = 0xffffffffu;
-  nodes.aux[0] = 0;
-  nodes.jobofs[0] = 0;
-  st->num_nodes = 1;
+  nodes.is_leaf[r] = inner ? 0 : 1;
+  nodes.child_mask[r] = 0;
+  nodes.first_child[r] = 0;
+  nodes.offset[r] = g.seg_start;
+  nodes.count[r] = inner ? 0 : n;
+  nodes.cover[r] = (int32_t)c;
+  nodes.grid[r] = (int32_t)c;
+  nodes.parent[r] = 0xffffffffu;
+  nodes.tree[r] = c;
+  st->num_nodes = r + 1;
+  st->node_begin = r;
+  st->node_end = node_end[c];
   st->next_level = 0;
-  st->level_begin[0] = 0;
-  st->level_end[0] = 1;
+  st->level_begin[0] = r;
+  st->level_end[0] = r + 1;
   st->status = 0;
 }
 
 constexpr int kTreeWG = 1024;
 
-// Enumerate levels until done or until inner nodes need refinement.
+// Enumerate levels until done or until inner nodes need refinement (one
+// workgroup per tree; finished trees return at once).  Nodes to refine are
+// appended to the build-wide lists.
 __global__ void __launch_bounds__(kTreeWG) k_tree_build(uint32_t leaf_cap, uint32_t max_level,
                                                         const GridDesc* __restrict__ grids,
-                                                        const uint32_t* __restrict__ pool, Nodes nodes, TreeState* st,
-                                                        uint32_t* refine, uint32_t* leaf_refine, uint32_t max_nodes) {
+                                                        const uint32_t* __restrict__ pool, Nodes nodes, TreeState* sts,
+                                                        uint32_t* refine, uint32_t* leaf_refine, BuildState* bs) {
   __shared__ uint32_t sh[kTreeWG / 64 + 1];
-  __shared__ uint32_t s_need, s_inner, s_nref, s_nlref;
+  __shared__ uint32_t s_need, s_inner;
+  const uint32_t tree = blockIdx.x;
+  TreeState* st = sts + tree;
+  if (st->status == 1) return;
   uint32_t L = st->next_level;
   uint32_t num = st->num_nodes;
-  if (threadIdx.x == 0) {
-    s_nref = st->num_refine = 0;
-    s_nlref = st->num_leaf_refine;
-  }
-  __syncthreads();
+  const uint32_t max_nodes = st->node_end;
   for (;;) {
     if (L >= max_level) {
       if (threadIdx.x == 0) { st->status = 1; st->next_level = L; }
@@ -108,17 +116,16 @@ __global__ void __launch_bounds__(kTreeWG) k_tree_build(uint32_t leaf_cap, uint3
           nodes.cover[n] = cov;
           nodes.grid[n] = gchild;
           nodes.parent[n] = j;
-          nodes.aux[n] = 0;
-          nodes.jobofs[n] = 0;
+          nodes.tree[n] = tree;
           if (inner) {
             atomicOr(&s_inner, 1u);
             if (r == G.e && gchild < 0) {
               atomicOr(&s_need, 1u);
-              refine[atomicAdd(&s_nref, 1u)] = n;
+              refine[atomicAdd(&bs->nref, 1u)] = n;
             }
           } else {
             const uint32_t sd = gchild >= 0 ? grids[gchild].base_level + grids[gchild].e : D;
-            if (sd < lvl + 2) leaf_refine[atomicAdd(&s_nlref, 1u)] = n;
+            if (sd < lvl + 2) leaf_refine[atomicAdd(&bs->nlref, 1u)] = n;
           }
         }
         // the lowest existing octant of each parent records its children
@@ -133,7 +140,10 @@ __global__ void __launch_bounds__(kTreeWG) k_tree_build(uint32_t leaf_cap, uint3
     if (threadIdx.x == 0) {
       st->level_begin[L + 1] = first_new;
       st->level_end[L + 1] = num;
-      if (num > max_nodes) st->overflow = 1;
+      if (num > max_nodes) {
+        st->overflow = 1;
+        atomicOr(&bs->overflow, 1u);
+      }
     }
     L += 1;
     const bool need = s_need != 0;
@@ -152,11 +162,7 @@ __global__ void __launch_bounds__(kTreeWG) k_tree_build(uint32_t leaf_cap, uint3
       break;
     }
   }
-  if (threadIdx.x == 0) {
-    st->num_nodes = min(num, max_nodes);
-    st->num_refine = s_nref;
-    st->num_leaf_refine = s_nlref;
-  }
+  if (threadIdx.x == 0) st->num_nodes = min(num, max_nodes);
 }
 
 // Segments (and grid descriptors) for nodes that need a deeper partition:
@@ -178,6 +184,10 @@ __global__ void k_refine_segments(Nodes nodes, const uint32_t* list, const uint3
   sg.chunk_begin = 0;
   sg.chunk_count = 0;
   sg.key = nodes.key[n];
+  sg.group_begin = 0;
+  sg.group_count = 0;
+  sg.cloud = nodes.tree[n];
+  sg.pad = 0;
   segs[r] = sg;
   GridDesc d;
   d.base_level = sg.level;
@@ -192,16 +202,88 @@ __global__ void k_refine_segments(Nodes nodes, const uint32_t* list, const uint3
   nodes.grid[n] = (int32_t)gi;
 }
 
+// Tree of compact node i: the last tree whose first node is <= i.
+__device__ __forceinline__ uint32_t node_tree(const TreeInfo* __restrict__ trees, uint32_t ntrees, uint32_t i) {
+  uint32_t lo = 0, hi = ntrees;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (trees[mid].node_base <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Move every tree's nodes from its capacity region to its compact range
+// [node_base, node_base + num_nodes), shifting node references.
+__global__ void k_compact_nodes(Nodes src, Nodes dst, const TreeInfo* __restrict__ trees,
+                                const uint32_t* __restrict__ cap_begin, uint32_t ntrees, uint32_t total) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const uint32_t c = node_tree(trees, ntrees, i);
+  const uint32_t nb = trees[c].node_base;
+  const uint32_t j = cap_begin[c] + (i - nb);
+  const uint32_t shift = nb - cap_begin[c];  // modular: references move by the same amount
+  const bool leaf = src.is_leaf[j] != 0;
+  dst.level[i] = src.level[j];
+  dst.is_leaf[i] = src.is_leaf[j];
+  dst.child_mask[i] = src.child_mask[j];
+  dst.key[i] = src.key[j];
+  dst.npoints[i] = src.npoints[j];
+  dst.count[i] = src.count[j];
+  dst.first_child[i] = leaf ? 0u : src.first_child[j] + shift;
+  dst.offset[i] = src.offset[j];
+  dst.cover[i] = src.cover[j];
+  dst.grid[i] = src.grid[j];
+  const uint32_t par = src.parent[j];
+  dst.parent[i] = par == 0xffffffffu ? par : par + shift;
+  dst.tree[i] = src.tree[j];
+}
+
+// Output node table: per-tree node indices and per-tree point / voxel offsets.
+__global__ void k_finalize_nodes(Nodes nodes, const TreeInfo* __restrict__ trees, uint32_t total, uint8_t* o_level,
+                                 uint8_t* o_leaf, uint8_t* o_mask, uint64_t* o_key, uint32_t* o_npts,
+                                 uint32_t* o_count, uint32_t* o_first, uint64_t* o_off) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const TreeInfo& ti = trees[nodes.tree[i]];
+  const bool leaf = nodes.is_leaf[i] != 0;
+  o_level[i] = nodes.level[i];
+  o_leaf[i] = nodes.is_leaf[i];
+  o_mask[i] = nodes.child_mask[i];
+  o_key[i] = nodes.key[i];
+  o_npts[i] = nodes.npoints[i];
+  o_count[i] = nodes.count[i];
+  o_first[i] = leaf ? 0u : nodes.first_child[i] - ti.node_base;
+  o_off[i] = leaf ? nodes.offset[i] - ti.point_base : nodes.offset[i];
+}
+
+void launch_compact_nodes(const Nodes& src, const Nodes& dst, const TreeInfo* trees, const uint32_t* cap_begin,
+                          uint32_t ntrees, uint32_t total, hipStream_t s) {
+  if (!total) return;
+  hipLaunchKernelGGL(k_compact_nodes, dim3((total + 255) / 256), dim3(256), 0, s, src, dst, trees, cap_begin, ntrees,
+                     total);
+}
+
+void launch_finalize_nodes(const Nodes& nodes, const TreeInfo* trees, uint32_t total, uint8_t* o_level, uint8_t* o_leaf,
+                           uint8_t* o_mask, uint64_t* o_key, uint32_t* o_npts, uint32_t* o_count, uint32_t* o_first,
+                           uint64_t* o_off, hipStream_t s) {
+  if (!total) return;
+  hipLaunchKernelGGL(k_finalize_nodes, dim3((total + 255) / 256), dim3(256), 0, s, nodes, trees, total, o_level, o_leaf,
+                     o_mask, o_key, o_npts, o_count, o_first, o_off);
+}
+
 void launch_tree_init(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
-                      const Nodes& nodes, TreeState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_tree_init, dim3(1), dim3(64), 0, s, leaf_cap, max_level, grids, pool, nodes, st);
+                      const Nodes& nodes, TreeState* sts, const uint32_t* node_begin, const uint32_t* node_end,
+                      uint32_t nclouds, hipStream_t s) {
+  hipLaunchKernelGGL(k_tree_init, dim3((nclouds + 255) / 256), dim3(256), 0, s, leaf_cap, max_level, grids, pool, nodes,
+                     sts, node_begin, node_end, nclouds);
 }
 
 void launch_tree_build(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
-                       const Nodes& nodes, TreeState* st, uint32_t* refine, uint32_t* leaf_refine, uint32_t max_nodes,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_tree_build, dim3(1), dim3(kTreeWG), 0, s, leaf_cap, max_level, grids, pool, nodes, st, refine,
-                     leaf_refine, max_nodes);
+                       const Nodes& nodes, TreeState* sts, uint32_t nclouds, uint32_t* refine, uint32_t* leaf_refine,
+                       BuildState* bs, hipStream_t s) {
+  hipLaunchKernelGGL(k_tree_build, dim3(nclouds), dim3(kTreeWG), 0, s, leaf_cap, max_level, grids, pool, nodes, sts,
+                     refine, leaf_refine, bs);
 }
 
 void launch_refine_segments(const Nodes& nodes, const uint32_t* list, const uint32_t* nlist, uint32_t max_list,

@@ -1,25 +1,36 @@
 // k_voxel.hip -- bottom-up voxel sampling of inner nodes (Sec. 4.2).
 //
-// Every inner node at level L gets the occupied cells of its 128^3 grid (cells
-// at level L + 7), and each child fills one 64^3 octant of that grid (Fig. 1
-// caption).  A child's samples are its points (leaf child) or its voxels
-// (inner child).  Sampling strategies: cell-wise average (Sec. 4.2.3) and the
-// two pick strategies (Sec. 4.2.1, 4.2.2) made independent of arrival order.
+// Every inner node A at level L gets the occupied cells of its 128^3 grid
+// (cells at level L + 7, Fig. 1).  Sampling is hierarchical: the samples of a
+// cell of A are the points of a leaf child, or the voxels of an inner child
+// (Sec. 4.2.1-4.2.3), so a cell of A holds one sample per occupied sub-cell
+// of the level below.  Two consequences shape the gfx950 design:
 //
-// The gfx950 design differs from the paper's one-workgroup-per-node loop over
-// a 128^3 grid in global memory:
-//   * leaf children: the leaf's points are sorted by the cell two levels below
-//     the leaf ("micro-bucket"), so each micro-bucket maps to at most 4096
-//     cells of the parent's grid and is accumulated in a directly indexed LDS
-//     array with 64-bit LDS atomics (packed R|G|n sums), then emitted in Morton
-//     order from an LDS occupancy bitmask.  All leaves of all levels run in
-//     one launch because they only depend on their own points.
-//   * inner children: a child's voxel list is in Morton order, so the child
-//     voxels that fold into one parent cell (2x2x2 -> 1) are consecutive; the
-//     parent voxel is a reduction over a run of at most 8 entries.  This runs
-//     level by level, deepest first.
-// Voxel lists therefore come out in Morton order of (x, y, z), and the output
-// is fully deterministic.
+//   * Inside the region of a leaf at level l, the cells of every ancestor at
+//     depth k = 1..6 above it (levels l + 7 - k, all finer than the leaf)
+//     depend on the leaf's own points only.  One kernel therefore computes,
+//     for every leaf, its contributions to all of those ancestors at once,
+//     level after level in LDS and registers, instead of one pass per level.
+//   * A node N exactly 7 levels below A is a single cell of A's grid; its
+//     "self voxel" reduces the self voxels of N's children (for a leaf, the
+//     voxels of its 8 child cells).
+// The voxel list of A is thus a sequence, in Morton order, of pieces: the
+// depth-(l - L) list of each leaf below A with l <= L + 6, and the self voxel
+// of each node at level L + 7 below A.  In a depth-first order of the tree,
+// A's pieces are the qualifying nodes of A's subtree range, already in Morton
+// order, so their offsets are block-wide prefix sums over that range.  Voxel
+// lists come out sorted by cell, and the output is fully deterministic.
+//
+// Stages (each launched once per build, whatever the depth of the tree):
+//   k_item_desc      descriptor and coarse-list space of every (leaf, child
+//                    cell) work item
+//   k_leaf_voxels    the depth 1..6 lists of every item
+//   k_piece_sizes    piece sizes of every node; self voxels of deep leaves
+//   k_vox_tree       subtree sizes, depth-first order, inner self voxels
+//   k_piece_count    voxel count of every inner node
+//   k_voxel_offsets  voxel offset of every inner node (node order)
+//   k_piece_offsets  output position of every piece; writes the self voxels
+//   k_gather         copies every item's lists to their output positions
 #include "common.h"
 #include "launch.h"
 #include "scan.h"
@@ -29,586 +40,864 @@
 namespace lod {
 
 constexpr int kLeafWG = 256;
-constexpr uint32_t kSubCells = 4096;  // 2 levels of micro-bucket -> 4 levels of voxel cells = 12 bits
-constexpr uint32_t kPackedMax = 65535;  // largest micro-bucket the packed 24/24/16-bit sums can hold
-constexpr int kLeafPF = 4;              // points in flight per thread
+constexpr uint32_t kSubCells = 4096;    // cells of a micro-bucket at depth 1 (4 levels = 12 bits)
+constexpr uint32_t kPackedMax = 65535;  // largest micro-bucket the packed 16-bit fields can hold
+constexpr uint32_t kLeafSlots = 8;      // points per thread per pass
+constexpr uint32_t kLeafPass = kLeafWG * kLeafSlots;
+constexpr uint32_t kNoCell = 0xffffffffu;
+constexpr uint32_t kCodeMask = (1u << 21) - 1;
 
-// Wide accumulation for one micro-bucket whose cells may hold more samples
-// than the packed 16-bit fields allow: windows of 512 cells with 64-bit sums
-// of R, G, B and the count, re-reading the micro-bucket's points per window.
-__device__ void leaf_wide_average(uint64_t* acc /* 2048 words of LDS */, uint32_t* sh, const uint4* __restrict__ pts,
-                                  uint32_t off, uint32_t cnt, uint32_t sub_shift, const CubeD& cd, uint32_t code_hi,
-                                  uint64_t* __restrict__ temp, uint64_t out, uint32_t& vbase) {
-  uint64_t* wr = acc;
-  uint64_t* wg = acc + 512;
-  uint64_t* wb = acc + 1024;
-  uint64_t* wn = acc + 1536;
-  for (uint32_t w0 = 0; w0 < kSubCells; w0 += 512) {
-    for (uint32_t i = threadIdx.x; i < 2048; i += kLeafWG) acc[i] = 0;
-    lds_barrier();
-    for (uint32_t i = threadIdx.x; i < cnt; i += kLeafWG) {
-      const uint4 v = pts[off + i];
-      const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
-      const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
-      if (sub >= w0 && sub < w0 + 512) {
-        const uint32_t q = sub - w0;
-        atomicAdd((unsigned long long*)&wr[q], (unsigned long long)(v.w & 0xff));
-        atomicAdd((unsigned long long*)&wg[q], (unsigned long long)((v.w >> 8) & 0xff));
-        atomicAdd((unsigned long long*)&wb[q], (unsigned long long)((v.w >> 16) & 0xff));
-        atomicAdd((unsigned long long*)&wn[q], 1ull);
-      }
-    }
-    lds_barrier();
-    for (uint32_t s0 = 0; s0 < 512; s0 += kLeafWG) {
-      const uint32_t q = s0 + threadIdx.x;
-      const uint64_t c = wn[q];
-      uint32_t tot;
-      const uint32_t pos = block_excl_scan<kLeafWG>(c ? 1u : 0u, sh, &tot);
-      if (c) {
-        const uint32_t rgba = (uint32_t)(wr[q] / c) | ((uint32_t)(wg[q] / c) << 8) | ((uint32_t)(wb[q] / c) << 16) |
-                              (255u << 24);
-        temp[out + vbase + pos] = make_voxel(code_hi | (w0 + q), rgba);
-      }
-      vbase += tot;
-    }
-    lds_barrier();
-  }
+// Cells of one work item (a leaf's child cell) in the grid of the ancestor
+// k = 1..6 levels above the leaf: 8^(6-k).
+__host__ __device__ __forceinline__ uint32_t item_cells(uint32_t k) { return 1u << (3 * (6 - k)); }
+// Start of the depth-k list (k = 2..6) in an item's block of coarse lists;
+// k = 7 gives the size of the block.  p = points of the item (no list is
+// longer than the item's points or cells).
+__host__ __device__ __forceinline__ uint32_t coarse_base(uint32_t k, uint32_t p) {
+  uint32_t b = 0;
+  for (uint32_t j = 2; j < k; ++j) b += p < item_cells(j) ? p : item_cells(j);
+  return b;
+}
+// Code of a cell in the grid of the ancestor k levels above a leaf (a cell at
+// level l + 7 - k): the leaf's key extended by 3*(7-k) bits of position inside
+// the leaf, cut to the grid's 21 bits.
+__device__ __forceinline__ uint32_t anc_code(uint64_t leaf_key, uint32_t k, uint32_t rel) {
+  return (uint32_t)(((leaf_key << (3 * (7 - k))) | rel) & kCodeMask);
 }
 
-// Parent voxels from the points of every leaf (level >= 1).  One workgroup per
-// node; non-leaves exit.  Voxels go to temp[offset .. offset + k) of the leaf
-// (k <= points of the leaf), the count to nodes.aux.
-//
-// One 64-bit LDS atomic per point:
-//   average: acc[cell] += R | G << 16 | B << 32 | 1 << 48.  The 16-bit fields
-//            are exact while a cell holds at most 257 samples (255 * 257 <
-//            2^16); a micro-bucket with a fuller cell is redone by the wide
-//            path above.
-//   pick:    acc[cell] = min/max of the sample's order key; a second pass over
-//            the micro-bucket lets the winner deposit its colour and id.
-// Occupied cells are those whose accumulator left its initial value; the
-// emission walks the 4096 cells in order (16 per thread), which lists the
-// voxels in Morton order.
-//
-// A work item is one leaf and one of its 8 child cells (8 micro-buckets), so
-// that large leaves spread over 8 workgroups.  Its voxels go to temp starting
-// at the first point of that child cell (never more voxels than points); the
-// count and start are recorded per (leaf, child cell) in gcount / gstart.
-template <int MODE>  // 0 average, 1 first, 2 random
-__global__ void __launch_bounds__(kLeafWG) k_leaf_voxels(Nodes nodes, uint32_t num_nodes,
-                                                         const GridDesc* __restrict__ grids,
-                                                         const uint32_t* __restrict__ pool,
-                                                         const uint4* __restrict__ pts, const uint32_t* __restrict__ ids,
-                                                         const Cube* cube, uint64_t* __restrict__ temp,
-                                                         uint32_t* __restrict__ temp_ids, uint32_t* __restrict__ gcount,
-                                                         uint32_t* __restrict__ gstart, uint32_t seed) {
-  __shared__ uint64_t acc[kSubCells];
-  __shared__ uint32_t wcount[64];
-  __shared__ uint32_t wover[4];
-  __shared__ uint32_t wrgba[MODE ? kSubCells : 1];
-  __shared__ uint32_t wid[MODE ? kSubCells : 1];
-  __shared__ uint32_t sh[kLeafWG / 64 + 1];
-  const uint32_t n = blockIdx.x >> 3, grp = blockIdx.x & 7u;
-  if (n >= num_nodes || !nodes.is_leaf[n] || nodes.level[n] == 0) return;
+// floor(sum / n) for 1 <= n <= 257 and sum <= 255 n (the mean of 8-bit
+// values), from r = rcp(n) (relative error at most 2^-23): the computed
+// sum * r + 2^-10 lies within 2^-14 of sum / n + 2^-10 (each rounding is below
+// 2^-17 for values under 256).  The true quotient is either an integer q,
+// which gives a value in (q, q + 2^-9), or at least 1/n >= 1/257 below the next
+// integer, which 2^-10 + 2^-14 does not reach; truncation is exact either way.
+__device__ __forceinline__ float rcp_count(uint32_t n) { return __builtin_amdgcn_rcpf((float)n); }
+__device__ __forceinline__ uint32_t floor_div(uint32_t sum, float r) {
+  return (uint32_t)__fadd_rn(__fmul_rn((float)sum, r), 0x1p-10f);
+}
+__device__ __forceinline__ uint32_t mean_rgba(uint32_t sr, uint32_t sg, uint32_t sb, uint32_t n) {
+  const float r = rcp_count(n);
+  return floor_div(sr, r) | (floor_div(sg, r) << 8) | (floor_div(sb, r) << 16) | (255u << 24);
+}
+
+// Samples of one cell: channel sums and count (average), or the pick so far
+// (pick modes; n > 0 marks it valid).
+template <int MODE>
+struct Smp {
+  uint32_t r, g, b, n;
+  uint64_t ok;  // order key of the pick; its low 32 bits are the id
+  uint32_t col;
+};
+template <int MODE>
+__device__ __forceinline__ Smp<MODE> smp_empty() {
+  Smp<MODE> s;
+  s.r = s.g = s.b = s.n = 0;
+  s.ok = 0;
+  s.col = 0;
+  return s;
+}
+template <int MODE>
+__device__ __forceinline__ bool pick_better(uint64_t a, uint64_t b) {
+  return MODE == 1 ? a < b : a > b;
+}
+// one voxel (colour, id) as a sample
+template <int MODE>
+__device__ __forceinline__ void smp_add(Smp<MODE>& s, uint32_t rgba, uint32_t id, uint32_t seed) {
+  if (MODE == 0) {
+    s.r += rgba & 0xffu;
+    s.g += (rgba >> 8) & 0xffu;
+    s.b += (rgba >> 16) & 0xffu;
+  } else {
+    const uint64_t k = pick_order(id, seed, MODE == 2);
+    if (s.n == 0 || pick_better<MODE>(k, s.ok)) {
+      s.ok = k;
+      s.col = rgba;
+    }
+  }
+  s.n += 1;
+}
+template <int MODE>
+__device__ __forceinline__ void smp_merge(Smp<MODE>& a, const Smp<MODE>& b) {
+  if (MODE == 0) {
+    a.r += b.r;
+    a.g += b.g;
+    a.b += b.b;
+  } else if (b.n && (a.n == 0 || pick_better<MODE>(b.ok, a.ok))) {
+    a.ok = b.ok;
+    a.col = b.col;
+  }
+  a.n += b.n;
+}
+// merge with the samples of lane ^ m (every lane of the wave executes this)
+// (average: sums of at most 8 voxels, so two 16-bit fields share a word)
+template <int MODE>
+__device__ __forceinline__ void smp_xor(Smp<MODE>& s, int m) {
+  if (MODE == 0) {
+    const uint32_t rg = (uint32_t)__shfl_xor((int)(s.r | (s.g << 16)), m, 64);
+    const uint32_t bn = (uint32_t)__shfl_xor((int)(s.b | (s.n << 16)), m, 64);
+    s.r += rg & 0xffffu;
+    s.g += rg >> 16;
+    s.b += bn & 0xffffu;
+    s.n += bn >> 16;
+  } else {
+    Smp<MODE> o = smp_empty<MODE>();
+    o.n = __shfl_xor(s.n, m, 64);
+    o.ok = __shfl_xor(s.ok, m, 64);
+    o.col = __shfl_xor(s.col, m, 64);
+    smp_merge<MODE>(s, o);
+  }
+}
+// the cell's voxel colour: floor of the mean per channel with A = 255
+// (sums of at most 8 voxels here), or the pick's colour
+template <int MODE>
+__device__ __forceinline__ uint32_t smp_rgba(const Smp<MODE>& s) {
+  if (MODE == 0) return mean_rgba(s.r, s.g, s.b, s.n);
+  return s.col;
+}
+
+// Exclusive prefix over the wave of counts below 2^BITS: one ballot per bit.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c) {
+  const uint64_t below = (1ull << lane_id()) - 1;
+  uint32_t r = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) r += (uint32_t)__popcll(__ballot((c >> b) & 1u) & below) << b;
+  return r;
+}
+
+// Point range of work item (leaf n, child cell grp) and what is needed to
+// find its micro-buckets (cells two levels below the leaf) in the leaf's grid.
+struct Item {
+  GridDesc G;
+  uint32_t rm;    // micro-bucket level relative to the grid
+  uint64_t mb0;   // index of the item's first micro-bucket at that level
+  uint32_t fine;  // 3 * (G.e - rm): micro-bucket index -> finest-cell index
+  uint32_t I0, I1;
+};
+__device__ __forceinline__ Item item_of(const Nodes& nodes, uint32_t n, uint32_t grp, const GridDesc* __restrict__ grids,
+                                        const uint32_t* __restrict__ pool) {
+  Item it;
   const uint32_t lvl = nodes.level[n];
   const int32_t gi = nodes.grid[n] >= 0 ? nodes.grid[n] : nodes.cover[n];
-  const GridDesc G = grids[gi];
-  const uint32_t rm = lvl + 2 - G.base_level;  // micro-bucket level relative to the grid
-  const uint64_t leaf_rel = nodes.key[n] - (G.base_key << (3 * (lvl - G.base_level)));
-  const uint32_t* mcnt = pool + G.pyr + pyr_level_offset(rm);
-  const uint32_t* goff = pool + G.off;
-  const uint32_t sub_shift = 3u * (15u - lvl);  // key >> sub_shift = voxel cell at level lvl + 6
-  const uint32_t top9 = (uint32_t)(nodes.key[n] & 7u) << 18;
-  const uint64_t init = MODE == 1 ? ~0ull : 0ull;
-  const CubeD cd = load_cube(cube);
-  const uint64_t out0 = goff[((leaf_rel << 6) | (grp << 3)) << (3 * (G.e - rm))];
-  bool any = false;
-  for (uint32_t jm = grp * 8; jm < grp * 8 + 8; ++jm) any |= mcnt[(leaf_rel << 6) | jm] != 0;
-  if (!any) {
-    if (threadIdx.x == 0) {
-      gcount[blockIdx.x] = 0;
-      gstart[blockIdx.x] = (uint32_t)out0;
+  it.G = grids[gi];
+  it.rm = lvl + 2 - it.G.base_level;
+  const uint64_t leaf_rel = nodes.key[n] - (it.G.base_key << (3 * (lvl - it.G.base_level)));
+  it.mb0 = (leaf_rel << 6) | ((uint64_t)grp << 3);
+  it.fine = 3 * (it.G.e - it.rm);
+  it.I0 = pool[it.G.off + (it.mb0 << it.fine)];
+  it.I1 = it.I0 + pool[it.G.pyr + pyr_level_offset(it.rm - 1) + (it.mb0 >> 3)];  // points of the child cell
+  return it;
+}
+
+// ------------------------------------------------------------ item descriptors
+//
+// What the leaf kernel and the gather need about a work item, gathered once
+// per item so that a leaf workgroup waits for one load before its points.
+struct ItemDesc {
+  uint32_t I0, P;  // first point and points of the item (P = 0: nothing to do)
+  uint32_t lvl, tree;
+  uint64_t lkey;   // the leaf's key
+  uint64_t t2;     // start of the item's block of coarse lists
+  uint32_t mc[8];  // points of each micro-bucket, in order
+};
+static_assert(sizeof(ItemDesc) == 64, "ItemDesc is read as four 16-byte words");
+
+// One thread per item.  Coarse-list blocks are handed out by a wave-wide
+// prefix sum and one atomic add per wave on bs->coarse_used.
+__global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nodes, const GridDesc* __restrict__ grids,
+                                                   const uint32_t* __restrict__ pool, BuildState* bs,
+                                                   ItemDesc* __restrict__ desc) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < 8 * num_nodes;
+  ItemDesc d;
+  d.I0 = d.P = d.lvl = d.tree = 0;
+  d.lkey = 0;
+  for (uint32_t j = 0; j < 8; ++j) d.mc[j] = 0;
+  if (valid) {
+    const uint32_t n = i >> 3;
+    if (nodes.is_leaf[n] && nodes.level[n] != 0) {
+      const Item it = item_of(nodes, n, i & 7u, grids, pool);
+      d.I0 = it.I0;
+      d.P = it.I1 - it.I0;
+      d.lvl = nodes.level[n];
+      d.tree = nodes.tree[n];
+      d.lkey = nodes.key[n];
+      const uint32_t* mcnt = pool + it.G.pyr + pyr_level_offset(it.rm);
+      for (uint32_t j = 0; j < 8; ++j) d.mc[j] = mcnt[it.mb0 | j];
     }
+  }
+  const uint64_t sz = coarse_base(7, d.P);
+  const uint64_t incl = wave_incl_scan(sz);
+  const uint64_t total = __shfl(incl, 63, 64);
+  uint64_t base = 0;
+  if (lane_id() == 63 && total) base = atomicAdd((unsigned long long*)&bs->coarse_used, (unsigned long long)total);
+  base = __shfl(base, 63, 64);
+  d.t2 = base + incl - sz;
+  if (valid) {
+    const uint4* src = (const uint4*)&d;
+    uint4* dst = (uint4*)(desc + i);
+    for (int k = 0; k < 4; ++k) dst[k] = src[k];
+  }
+}
+
+// First sample of a depth-1 cell: mark it and, the first time, its depth-2,
+// 3 and 4 cells in the occupancy bitmasks, counting every newly occupied cell
+// for its quarter of the micro-bucket's cells (the cells a wave emits).
+__device__ __forceinline__ void claim_cell(uint32_t* bm1, uint32_t* bm2, uint32_t* bm3, uint32_t* bm4,
+                                           uint32_t (*nocc)[8][4], uint32_t jm, uint32_t s) {
+  uint32_t bit = 1u << (s & 31);
+  if (atomicOr(&bm1[s >> 5], bit) & bit) return;
+  atomicAdd(&nocc[0][jm][s >> 10], 1u);
+  const uint32_t c2 = s >> 3;
+  bit = 1u << (c2 & 31);
+  if (atomicOr(&bm2[c2 >> 5], bit) & bit) return;
+  atomicAdd(&nocc[1][jm][c2 >> 7], 1u);
+  const uint32_t c3 = s >> 6;
+  bit = 1u << (c3 & 31);
+  if (atomicOr(&bm3[c3 >> 5], bit) & bit) return;
+  atomicAdd(&nocc[2][jm][c3 >> 4], 1u);
+  const uint32_t c4 = s >> 9;
+  bit = 1u << c4;
+  if (atomicOr(&bm4[jm], bit) & bit) return;
+  atomicAdd(&nocc[3][jm][c4 >> 1], 1u);
+}
+
+// ------------------------------------------------------------ leaf kernel
+//
+// A work item is one leaf and one of its 8 child cells (8 micro-buckets), so
+// that large leaves spread over 8 workgroups.  Its points are contiguous and
+// sorted by micro-bucket.  They are read in passes of kLeafPass points, every
+// thread issuing all of its loads of a pass at once, and each point is kept
+// in registers as (15-bit cell within the child cell, colour, id).  The
+// micro-buckets are then reduced one after the other into a directly indexed
+// LDS array of the 4096 depth-1 cells (parent's grid) of one micro-bucket,
+// with one 64-bit LDS atomic per point:
+//   average: acc[cell] += R | G << 16 | B << 32 | 1 << 48.  The 16-bit fields
+//            are exact while a cell holds at most 257 samples (255 * 257 <
+//            2^16); the add that takes a cell past 257 flags the
+//            micro-bucket, which is then redone with exact 64-bit sums.
+//   pick:    acc[cell] = min/max of the sample's order key, whose low 32 bits
+//            are the point id; the winner then replaces it by its colour and
+//            id (ids are unique, so no other point can match afterwards).
+// The first sample of a cell claims it in an occupancy bitmask per depth
+// (depth 1: 4096 cells, 2: 512, 3: 64, 4: 8 per micro-bucket) and counts it
+// for its quarter of the cells, so that every list position is a prefix over
+// counters and bits, without further passes.  The emission (thread t owns
+// depth-1 cells 16t .. 16t+15, i.e. depth-2 cells 2t and 2t+1) writes the
+// depth-1 voxels and reduces them upward through registers and wave
+// shuffles: depth 2 in the thread, depth 3 over 4 lanes, depth 4 over 32
+// lanes.  Depth 5 (the micro-bucket) and 6 (the item) are reduced at the end.
+// Depth-1 lists go to T1 at the item's first point (never more voxels than
+// points), the coarse lists to the item's block in T2.  icnt receives the 6
+// list lengths and iself the depth-6 voxel (colour, id) of every item.
+template <int MODE>  // 0 average, 1 first, 2 random
+__global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(const ItemDesc* __restrict__ desc,
+                                                                          const uint4* __restrict__ pts,
+                                                                          const uint32_t* __restrict__ ids,
+                                                                          const Cube* cube, uint64_t* __restrict__ T1,
+                                                                          uint32_t* __restrict__ T1id,
+                                                                          uint64_t* __restrict__ T2,
+                                                                          uint32_t* __restrict__ T2id,
+                                                                          uint32_t* __restrict__ icnt,
+                                                                          uint64_t* __restrict__ iself, uint32_t seed) {
+  __shared__ uint64_t acc[kSubCells];
+  __shared__ uint32_t bm1[kSubCells / 32], bm2[16], bm3[2], bm4[8];
+  __shared__ uint32_t nocc[4][8][4];  // [depth - 1][micro-bucket][quarter]: occupied cells
+  __shared__ uint32_t over[8];        // a cell of the micro-bucket passed 257 samples
+  __shared__ uint64_t k4ok[8][8];     // depth-4 voxels of each micro-bucket: pick key and colour
+  __shared__ uint32_t k4col[8][8];
+  const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+  const ItemDesc& sd = desc[blockIdx.x];  // uniform: scalar loads
+  const uint64_t init = MODE == 1 ? ~0ull : 0ull;
+  for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
+  if (t < kSubCells / 32) bm1[t] = 0;
+  if (t < 16) bm2[t] = 0;
+  if (t < 2) bm3[t] = 0;
+  if (t < 128) nocc[t >> 5][(t >> 2) & 7][t & 3] = 0;
+  if (t < 8) {
+    bm4[t] = 0;
+    over[t] = 0;
+  }
+  const uint32_t P = sd.P;
+  const CubeD cd = load_cube(cube + sd.tree);
+  __syncthreads();
+  if (P == 0) {
+    if (t < 6) icnt[6 * blockIdx.x + t] = 0;
     return;
   }
-  for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-  lds_barrier();
-  uint32_t vbase = 0;
-  for (uint32_t jm = grp * 8; jm < grp * 8 + 8; ++jm) {
-    const uint64_t idx = (leaf_rel << 6) | jm;
-    const uint32_t cnt = mcnt[idx];
-    if (cnt == 0) continue;
-    const uint32_t off = goff[idx << (3 * (G.e - rm))];
-    const uint32_t code_hi = top9 | (jm << 12);
-    if (MODE == 0 && cnt > kPackedMax) {
-      leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
-      for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-      lds_barrier();
-      continue;
-    }
-    // accumulate: every thread first issues all loads of a batch, then hashes
-    for (uint32_t b0 = 0; b0 < cnt; b0 += kLeafWG * kLeafPF) {
-      uint4 v[kLeafPF];
-      uint32_t idv[kLeafPF];
-#pragma unroll
-      for (int k = 0; k < kLeafPF; ++k) {
-        const uint32_t i = b0 + k * kLeafWG + threadIdx.x;
-        if (i < cnt) {
-          v[k] = pts[off + i];
-          if (MODE) idv[k] = ids[off + i];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kLeafPF; ++k) {
-        const uint32_t i = b0 + k * kLeafWG + threadIdx.x;
-        if (i >= cnt) continue;
-        const uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
-        const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
-        if (MODE == 0) {
-          const uint64_t packed = (uint64_t)(v[k].w & 0xff) | ((uint64_t)((v[k].w >> 8) & 0xff) << 16) |
-                                  ((uint64_t)((v[k].w >> 16) & 0xff) << 32) | (1ull << 48);
-          atomicAdd((unsigned long long*)&acc[sub], (unsigned long long)packed);
-        } else {
-          const uint64_t ok = pick_order(idv[k], seed, MODE == 2);
-          if (MODE == 1) atomicMin((unsigned long long*)&acc[sub], (unsigned long long)ok);
-          else atomicMax((unsigned long long*)&acc[sub], (unsigned long long)ok);
-        }
-      }
-    }
-    lds_barrier();
-    if (MODE != 0) {
-      // the winner of every cell deposits its colour and id
-      for (uint32_t i = threadIdx.x; i < cnt; i += kLeafWG) {
-        const uint32_t id = ids[off + i];
-        const uint4 v = pts[off + i];
-        const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
-        const uint32_t sub = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
-        if (acc[sub] == pick_order(id, seed, MODE == 2)) {
-          wrgba[sub] = v.w;
-          wid[sub] = id;
-        }
-      }
-      lds_barrier();
-    }
-    // emit.  Lane l of wave w owns cells 256k + 64w + l (k = 0..15); the
-    // wave's ballot over cells 256k + 64w .. +63 is occupancy word 4k + w, so
-    // word order is cell (Morton) order.  One exchange of the 64 word counts
-    // gives every word its prefix, and each lane writes its own occupied
-    // cells at prefix(word) + occupied lanes below it.
+  const uint32_t I0 = sd.I0, I1 = I0 + P, lvl = sd.lvl, grp = blockIdx.x & 7u;
+  const uint64_t lkey = sd.lkey, t2b = sd.t2;
+  const uint32_t sub_shift = 3u * (15u - lvl);  // key >> sub_shift = depth-1 cell (level lvl + 6)
+  const uint32_t cb3 = coarse_base(3, P), cb4 = coarse_base(4, P), cb5 = coarse_base(5, P), cb6 = coarse_base(6, P);
+  uint32_t base1 = 0, base2 = 0, base3 = 0, base4 = 0;  // list lengths so far
+  for (uint32_t P0 = I0; P0 < I1; P0 += kLeafPass) {
+    const uint32_t P1 = min(P0 + kLeafPass, I1);
+    uint32_t cell[kLeafSlots], col[kLeafSlots], pid[kLeafSlots];
     {
-      const uint32_t w = threadIdx.x / 64, l = lane_id();
-      uint64_t bal[16];
-      uint32_t over = 0;
+      uint4 v[kLeafSlots];
 #pragma unroll
-      for (uint32_t k = 0; k < 16; ++k) {
-        const uint64_t a = acc[256 * k + 64 * w + l];
-        if (MODE == 0) over |= (a >> 48) > 257 ? 1u : 0u;
-        bal[k] = __ballot(a != init);
+      for (uint32_t k = 0; k < kLeafSlots; ++k) {
+        const uint32_t i = P0 + k * kLeafWG + t;
+        if (i < P1) {
+          v[k] = pts[i];
+          if (MODE) pid[k] = ids[i];
+        }
       }
-      const bool any_over = MODE == 0 && __ballot(over != 0) != 0;
-      if (l == 0) {
 #pragma unroll
-        for (uint32_t k = 0; k < 16; ++k) wcount[4 * k + w] = (uint32_t)__popcll(bal[k]);
-        wover[w] = any_over ? 1u : 0u;
+      for (uint32_t k = 0; k < kLeafSlots; ++k) {
+        const uint32_t i = P0 + k * kLeafWG + t;
+        cell[k] = kNoCell;
+        if (i < P1) {
+          const uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
+          cell[k] = (uint32_t)(key >> sub_shift) & 0x7fffu;
+          col[k] = v[k].w;
+        }
       }
+    }
+    uint32_t next = I0;  // first point of the next micro-bucket
+    for (uint32_t jm = 0; jm < 8; ++jm) {
+      const uint32_t cnt = sd.mc[jm];
+      const uint32_t off = next;
+      next += cnt;
+      if (cnt == 0) continue;
+      if (off >= P1 || off + cnt <= P0) continue;  // no points in this pass
+      const bool wide = MODE == 0 && cnt > kPackedMax;
+      if (!wide) {
+#pragma unroll
+        for (uint32_t k = 0; k < kLeafSlots; ++k) {
+          // keep the per-slot work inside the loop over micro-buckets (hoisted
+          // out of it, it would hold several registers per slot)
+          asm volatile("" : "+v"(cell[k]), "+v"(col[k]));
+          if ((cell[k] >> 12) != jm) continue;
+          const uint32_t sc = cell[k] & (kSubCells - 1);
+          if (MODE == 0) {
+            const uint64_t packed = (uint64_t)(col[k] & 0xff) | ((uint64_t)((col[k] >> 8) & 0xff) << 16) |
+                                    ((uint64_t)((col[k] >> 16) & 0xff) << 32) | (1ull << 48);
+            const uint64_t old = atomicAdd((unsigned long long*)&acc[sc], (unsigned long long)packed);
+            if ((old >> 48) == 257) over[jm] = 1;
+          } else {
+            const uint64_t ok = pick_order(pid[k], seed, MODE == 2);
+            if (MODE == 1) atomicMin((unsigned long long*)&acc[sc], (unsigned long long)ok);
+            else atomicMax((unsigned long long*)&acc[sc], (unsigned long long)ok);
+          }
+          claim_cell(bm1, bm2, bm3, bm4, nocc, jm, sc);
+        }
+      }
+      if (off + cnt > P1) break;  // continues in the next pass
       lds_barrier();
-      const bool redo = MODE == 0 && (wover[0] | wover[1] | wover[2] | wover[3]);
-      const uint32_t mine = wcount[l];
-      const uint32_t incl = wave_incl_scan(mine);
-      const uint32_t total = __shfl(incl, 63, 64);
-      const uint32_t excl = incl - mine;
-      if (!redo) {
-        const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
-        // word prefixes, read with every lane active (a shuffle from a lane
-        // masked off by a branch is undefined)
-#pragma unroll
-        for (uint32_t k = 0; k < 16; ++k) {
-          const uint32_t pre = (uint32_t)__shfl(excl, (int)(4 * k + w), 64);
-          if ((bal[k] >> l) & 1ull) {
-            const uint32_t pos = pre + (uint32_t)__popcll(bal[k] & below);
-            const uint32_t s = 256 * k + 64 * w + l;
-            const uint64_t a = acc[s];
-            uint32_t rgba;
-            if (MODE == 0) {
-              // floor(sum / n): sums < 2^16 and n <= 257 are exact in float and
-              // the correctly rounded quotient (< 256) stays at least 1/n away
-              // from the next integer when it is not one, so truncation is exact
-              const float c = (float)(uint32_t)(a >> 48);
-              rgba = (uint32_t)__fdiv_rn((float)(uint32_t)(a & 0xffffu), c) |
-                     ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 16) & 0xffffu), c) << 8) |
-                     ((uint32_t)__fdiv_rn((float)(uint32_t)((a >> 32) & 0xffffu), c) << 16) | (255u << 24);
-            } else {
-              rgba = wrgba[s];
-              temp_ids[out0 + vbase + pos] = wid[s];
+      const bool redo = wide || (MODE == 0 && over[jm]);
+      if (redo) {
+        // exact 64-bit sums over windows of 512 cells, re-reading the points;
+        // occupancy is rebuilt in the first window, and the floored colours
+        // are kept in the upper half of acc
+        if (t < kSubCells / 32) bm1[t] = 0;
+        if (t < 16) {
+          bm2[t] = 0;
+          nocc[t >> 2][jm][t & 3] = 0;
+        }
+        if (t < 2) bm3[t] = 0;
+        if (t == 0) bm4[jm] = 0;
+        uint64_t* wr = acc;
+        uint64_t* wg = acc + 512;
+        uint64_t* wb = acc + 1024;
+        uint64_t* wn = acc + 1536;
+        uint32_t* colw = (uint32_t*)(acc + 2048);
+        for (uint32_t w0 = 0; w0 < kSubCells; w0 += 512) {
+          for (uint32_t i = t; i < 2048; i += kLeafWG) acc[i] = 0;
+          lds_barrier();
+          for (uint32_t i = t; i < cnt; i += kLeafWG) {
+            const uint4 v = pts[off + i];
+            const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
+            const uint32_t sc = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
+            if (w0 == 0) claim_cell(bm1, bm2, bm3, bm4, nocc, jm, sc);
+            if (sc >= w0 && sc < w0 + 512) {
+              const uint32_t q = sc - w0;
+              atomicAdd((unsigned long long*)&wr[q], (unsigned long long)(v.w & 0xff));
+              atomicAdd((unsigned long long*)&wg[q], (unsigned long long)((v.w >> 8) & 0xff));
+              atomicAdd((unsigned long long*)&wb[q], (unsigned long long)((v.w >> 16) & 0xff));
+              atomicAdd((unsigned long long*)&wn[q], 1ull);
             }
-            temp[out0 + vbase + pos] = make_voxel(code_hi | s, rgba);
-            acc[s] = init;
+          }
+          lds_barrier();
+          for (uint32_t q = t; q < 512; q += kLeafWG) {
+            const uint64_t c = wn[q];
+            if (c) {
+              // sums below 2^40 and counts below 2^32 are exact in double; the
+              // quotient (<= 255) is at least 2^-32 from the next integer when
+              // it is not one, far above the rounding error: floor is exact
+              const double dc = (double)c;
+              colw[w0 + q] = (uint32_t)((double)wr[q] / dc) | ((uint32_t)((double)wg[q] / dc) << 8) |
+                             ((uint32_t)((double)wb[q] / dc) << 16) | (255u << 24);
+            }
+          }
+          lds_barrier();
+        }
+      }
+      if (MODE != 0) {
+        // the winner of every cell deposits its colour beside its id
+        if (off >= P0) {
+#pragma unroll
+          for (uint32_t k = 0; k < kLeafSlots; ++k) {
+            if ((cell[k] >> 12) != jm) continue;
+            const uint32_t sc = cell[k] & (kSubCells - 1);
+            if (acc[sc] == pick_order(pid[k], seed, MODE == 2)) acc[sc] = ((uint64_t)col[k] << 32) | pid[k];
+          }
+        } else {
+          // the micro-bucket began in an earlier pass: read its points again
+          for (uint32_t i = off + t; i < off + cnt; i += kLeafWG) {
+            const uint32_t id = ids[i];
+            const uint4 v = pts[i];
+            const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
+            const uint32_t sc = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
+            if (acc[sc] == pick_order(id, seed, MODE == 2)) acc[sc] = ((uint64_t)v.w << 32) | id;
           }
         }
-        vbase += total;
-        lds_barrier();
-      } else {
-        // a cell overflowed the packed fields: clear and redo this micro-bucket exactly
-        lds_barrier();
-        for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
-        lds_barrier();
-        leaf_wide_average(acc, sh, pts, off, cnt, sub_shift, cd, code_hi, temp, out0, vbase);
-        for (uint32_t i = threadIdx.x; i < kSubCells; i += kLeafWG) acc[i] = init;
         lds_barrier();
       }
-    }
-  }
-  if (threadIdx.x == 0) {
-    gcount[blockIdx.x] = vbase;
-    gstart[blockIdx.x] = (uint32_t)out0;
-  }
-}
-
-// Voxel count of every leaf: the sum over its 8 child-cell work items.
-__global__ void k_leaf_sums(Nodes nodes, uint32_t num_nodes, const uint32_t* __restrict__ gcount) {
-  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= num_nodes || !nodes.is_leaf[n]) return;
-  uint32_t s = 0;
-  if (nodes.level[n] != 0)
-    for (uint32_t g = 0; g < 8; ++g) s += gcount[8 * n + g];
-  nodes.aux[n] = s;
-}
-
-// Capacity for all voxel lists: per level, at most min(2^21, points) per node
-// and at most (voxels from leaf children) + (bound of the level below).  One
-// workgroup.
-constexpr int kBoundWG = 1024;
-__global__ void __launch_bounds__(kBoundWG) k_voxel_bound(Nodes nodes, TreeState* st) {
-  __shared__ uint64_t sh[2][kBoundWG / 64];
-  uint32_t deepest = 0;
-  for (uint32_t L = 0; L < 22; ++L)
-    if (st->level_end[L] > st->level_begin[L]) deepest = L;
-  uint64_t below = 0, total = 0;
-  for (int L = (int)deepest; L >= 0; --L) {
-    uint64_t by_points = 0, from_leaves = 0;
-    for (uint32_t j = st->level_begin[L] + threadIdx.x; j < st->level_end[L]; j += kBoundWG)
-      if (!nodes.is_leaf[j]) by_points += min((uint64_t)nodes.npoints[j], (uint64_t)1 << 21);
-    for (uint32_t j = st->level_begin[L + 1] + threadIdx.x; j < st->level_end[L + 1]; j += kBoundWG)
-      if (nodes.is_leaf[j]) from_leaves += nodes.aux[j];
-    by_points = wave_sum(by_points);
-    from_leaves = wave_sum(from_leaves);
-    if (lane_id() == 0) {
-      sh[0][threadIdx.x / 64] = by_points;
-      sh[1][threadIdx.x / 64] = from_leaves;
-    }
-    __syncthreads();
-    uint64_t a = 0, b = 0;
-    for (int w = 0; w < kBoundWG / 64; ++w) { a += sh[0][w]; b += sh[1][w]; }
-    __syncthreads();
-    const uint64_t bl = min(a, b + below);
-    total += bl;
-    below = bl;
-  }
-  if (threadIdx.x == 0) {
-    st->voxel_bound = total;
-    st->voxel_total = 0;
-    st->inner_total = 0;
-  }
-}
-
-// ------------------------------------------------------------ inner levels
-//
-// The voxels of all inner nodes of one level are contiguous and each node's
-// list is in Morton order.  A parent cell collects the child voxels whose
-// codes agree above the lowest 3 bits (2x2x2 -> 1), i.e. a run of at most 8
-// consecutive entries of one node.  Whoever writes a voxel also writes its
-// owner node and a one-byte flag telling whether it starts such a run (first
-// voxel of a child's contribution, or a change of code >> 3); an exclusive
-// prefix sum over the flags of a level numbers the runs, and every run is
-// reduced by the thread at its start.
-
-constexpr uint32_t kTile = 4096;
-constexpr int kTileWG = 256;
-constexpr uint32_t kTilePT = kTile / kTileWG;  // 16 flags per thread, read as 4 words
-
-__device__ __forceinline__ uint32_t flags4(const uint8_t* __restrict__ f, uint64_t i, uint64_t V) {
-  // 4 consecutive flags starting at i, one byte each; zero past V (byte loads:
-  // a level's flags need not start on a word boundary)
-  uint32_t w = 0;
+      // ---- emission of this micro-bucket at depths 1..4
+      uint32_t qb[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};
 #pragma unroll
-  for (uint32_t k = 0; k < 4; ++k)
-    if (i + k < V) w |= (uint32_t)f[i + k] << (8 * k);
-  return w;
-}
-
-// (1) run starts per tile of the level's voxels
-__global__ void __launch_bounds__(kTileWG) k_run_tiles(const TreeState* st, uint32_t lvl,
-                                                       const uint8_t* __restrict__ vflag, uint32_t* __restrict__ tilesum) {
-  __shared__ uint32_t sh[kTileWG / 64];
-  const uint64_t vb = st->level_vbegin[lvl], V = st->level_vcount[lvl];
-  const uint8_t* f = vflag + vb;
-  const uint32_t ntiles = (uint32_t)((V + kTile - 1) / kTile);
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    uint32_t c = 0;
-    for (uint32_t k = 0; k < kTilePT / 4; ++k) {
-      const uint64_t j = (uint64_t)t * kTile + 4ull * (k * kTileWG + threadIdx.x);
-      if (j < V) c += (uint32_t)__popc(flags4(f, j, V) & 0x01010101u);
-    }
-    c = wave_sum(c);
-    if (lane_id() == 0) sh[threadIdx.x / 64] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t s = 0;
-      for (int w = 0; w < kTileWG / 64; ++w) s += sh[w];
-      tilesum[t] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// (2) exclusive scan of the tile counts (one workgroup); tilesum[ntiles] = total
-constexpr int kScanWG = 1024;
-__global__ void __launch_bounds__(kScanWG) k_tile_scan(const TreeState* st, uint32_t lvl, uint32_t* tilesum) {
-  __shared__ uint32_t sh[kScanWG / 64 + 1];
-  const uint64_t V = st->level_vcount[lvl];
-  const uint32_t ntiles = (uint32_t)((V + kTile - 1) / kTile);
-  uint32_t base = 0;
-  for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanWG) {
-    const uint32_t t = t0 + threadIdx.x;
-    const uint32_t v = t < ntiles ? tilesum[t] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<kScanWG>(v, sh, &tot);
-    if (t < ntiles) tilesum[t] = base + ex;
-    base += tot;
-  }
-  if (threadIdx.x == 0) tilesum[ntiles] = base;
-}
-
-// (3) global run index of every voxel of the level (runidx[V] = number of runs)
-__global__ void __launch_bounds__(kTileWG) k_run_index(const TreeState* st, uint32_t lvl,
-                                                       const uint8_t* __restrict__ vflag,
-                                                       const uint32_t* __restrict__ tilesum, uint32_t* __restrict__ runidx,
-                                                       uint32_t* __restrict__ runpos) {
-  __shared__ uint32_t sh[kTileWG / 64 + 1];
-  const uint64_t vb = st->level_vbegin[lvl], V = st->level_vcount[lvl];
-  const uint8_t* f = vflag + vb;
-  const uint32_t ntiles = (uint32_t)((V + kTile - 1) / kTile);
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t j0 = (uint64_t)t * kTile + (uint64_t)threadIdx.x * kTilePT;  // contiguous per thread
-    uint32_t w[kTilePT / 4];
-    uint32_t local = 0;
+      for (uint32_t d = 0; d < 4; ++d)
 #pragma unroll
-    for (uint32_t k = 0; k < kTilePT / 4; ++k) {
-      w[k] = j0 + 4 * k < V ? flags4(f, j0 + 4 * k, V) : 0u;
-      local += (uint32_t)__popc(w[k] & 0x01010101u);
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<kTileWG>(local, sh, &tot) + tilesum[t];
-#pragma unroll
-    for (uint32_t k = 0; k < kTilePT; ++k) {
-      const uint64_t j = j0 + k;
-      const uint32_t f = (w[k / 4] >> (8 * (k & 3))) & 1u;
-      if (j < V) {
-        runidx[j] = ex;
-        if (f) runpos[ex] = (uint32_t)j;
-      }
-      ex += f;
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) runidx[V] = tilesum[ntiles];
-}
-
-// (4) voxel offsets of the level's inner nodes (one workgroup): a node's list
-// is its children's contributions in octant order, nodes follow in key order.
-constexpr int kOffWG = 1024;
-__global__ void __launch_bounds__(kOffWG) k_level_offsets(Nodes nodes, uint32_t lvl, uint32_t begin, uint32_t end,
-                                                          TreeState* st, const uint32_t* __restrict__ runidx) {
-  __shared__ uint64_t sh[kOffWG / 64 + 1];
-  const uint64_t level_base = st->voxel_total;
-  const uint64_t cvb = st->level_vbegin[lvl + 1];
-  uint64_t base = level_base;
-  for (uint32_t c0 = begin; c0 < end; c0 += kOffWG) {
-    const uint32_t j = c0 + threadIdx.x;
-    const bool inner = j < end && !nodes.is_leaf[j];
-    uint64_t total = 0;
-    if (inner) {
-      const uint32_t fc = nodes.first_child[j];
-      const uint32_t nc = (uint32_t)__popc(nodes.child_mask[j]);
-      for (uint32_t k = 0; k < nc; ++k) {
-        const uint32_t c = fc + k;
-        nodes.jobofs[c] = (uint32_t)total;
-        if (nodes.is_leaf[c]) {
-          total += nodes.aux[c];
+        for (uint32_t qq = 0; qq < 4; ++qq) {
+          const uint32_t a = nocc[d][jm][qq];
+          if (qq < w) qb[d] += a;
+          tot[d] += a;
+        }
+      const uint32_t rel5 = (grp << 3) | jm;  // micro-bucket within the leaf (6 bits)
+      // depth 1: cells 16t .. 16t + 15
+      const uint32_t word = bm1[t >> 1];
+      uint32_t m = (t & 1) ? (word >> 16) : (word & 0xffffu);
+      if ((t & 1) == 0) bm1[t >> 1] = 0;
+      if (t < 16) bm2[t] = 0;
+      if (t < 2) bm3[t] = 0;
+      uint32_t pos = base1 + qb[0] + wave_prefix_small<5>((uint32_t)__popc(m));
+      Smp<MODE> h0 = smp_empty<MODE>(), h1 = smp_empty<MODE>();
+      const uint32_t* colw = (const uint32_t*)(acc + 2048);
+      while (m) {
+        const uint32_t b = (uint32_t)(__ffs(m) - 1);
+        m &= m - 1;
+        const uint32_t s = 16 * t + b;
+        uint32_t rgba, id = 0;
+        if (MODE == 0) {
+          if (redo) {
+            rgba = colw[s];
+          } else {
+            const uint64_t a = acc[s];
+            acc[s] = init;
+            rgba = mean_rgba((uint32_t)(a & 0xffffu), (uint32_t)((a >> 16) & 0xffffu), (uint32_t)((a >> 32) & 0xffffu),
+                             (uint32_t)(a >> 48));
+          }
         } else {
-          const uint64_t r0 = nodes.offset[c] - cvb;
-          total += runidx[r0 + nodes.count[c]] - runidx[r0];
+          const uint64_t a = acc[s];
+          acc[s] = init;
+          rgba = (uint32_t)(a >> 32);
+          id = (uint32_t)a;
+          T1id[I0 + pos] = id;
+        }
+        T1[I0 + pos] = make_voxel(anc_code(lkey, 1, (rel5 << 12) | s), rgba);
+        ++pos;
+        if (b < 8) smp_add<MODE>(h0, rgba, id, seed);
+        else smp_add<MODE>(h1, rgba, id, seed);
+      }
+      // depth 2: cells 2t, 2t + 1
+      pos = base2 + qb[1] + wave_prefix_small<2>((h0.n ? 1u : 0u) + (h1.n ? 1u : 0u));
+      Smp<MODE> g3 = smp_empty<MODE>();
+#pragma unroll
+      for (uint32_t e = 0; e < 2; ++e) {
+        const Smp<MODE>& h = e ? h1 : h0;
+        if (h.n) {
+          const uint32_t rgba = smp_rgba<MODE>(h), id = (uint32_t)h.ok;
+          T2[t2b + pos] = make_voxel(anc_code(lkey, 2, (rel5 << 9) | (2 * t + e)), rgba);
+          if (MODE) T2id[t2b + pos] = id;
+          ++pos;
+          smp_add<MODE>(g3, rgba, id, seed);
         }
       }
-    }
-    uint64_t tot;
-    const uint64_t ex = block_excl_scan<kOffWG>(total, sh, &tot);
-    if (inner) {
-      const uint64_t off = base + ex;
-      nodes.offset[j] = off;
-      nodes.count[j] = (uint32_t)total;
-      const uint32_t fc = nodes.first_child[j];
-      const uint32_t nc = (uint32_t)__popc(nodes.child_mask[j]);
-      for (uint32_t k = 0; k < nc; ++k) {
-        const uint32_t c = fc + k;
-        if (!nodes.is_leaf[c]) {
-          nodes.dstbase[c] = off + nodes.jobofs[c];
-          nodes.firstrun[c] = runidx[nodes.offset[c] - cvb];
+      // depth 3: cell t / 4, over lanes 4q .. 4q + 3
+      smp_xor<MODE>(g3, 1);
+      smp_xor<MODE>(g3, 2);
+      const bool lead3 = (l & 3) == 0;
+      pos = base3 + qb[2] + wave_prefix_small<1>((lead3 && g3.n) ? 1u : 0u);
+      Smp<MODE> g4 = smp_empty<MODE>();
+      if (g3.n) {
+        const uint32_t rgba = smp_rgba<MODE>(g3), id = (uint32_t)g3.ok;
+        if (lead3) {
+          T2[t2b + cb3 + pos] = make_voxel(anc_code(lkey, 3, (rel5 << 6) | (t >> 2)), rgba);
+          if (MODE) T2id[t2b + cb3 + pos] = id;
         }
+        smp_add<MODE>(g4, rgba, id, seed);
+      }
+      // depth 4: cell t / 32, over the 8 groups of 4 lanes of a half-wave (the
+      // 4 lanes of a group hold the same depth-3 voxel: one lane per group
+      // takes part in each exchange)
+      smp_xor<MODE>(g4, 4);
+      smp_xor<MODE>(g4, 8);
+      smp_xor<MODE>(g4, 16);
+      const bool lead4 = (l & 31) == 0;
+      pos = base4 + qb[3] + wave_prefix_small<1>((lead4 && g4.n) ? 1u : 0u);
+      if (lead4 && g4.n) {
+        const uint32_t rgba = smp_rgba<MODE>(g4), id = (uint32_t)g4.ok;
+        T2[t2b + cb4 + pos] = make_voxel(anc_code(lkey, 4, (rel5 << 3) | (t >> 5)), rgba);
+        if (MODE) T2id[t2b + cb4 + pos] = id;
+        k4col[jm][t >> 5] = rgba;
+        k4ok[jm][t >> 5] = g4.ok;
+      }
+      base1 += tot[0];
+      base2 += tot[1];
+      base3 += tot[2];
+      base4 += tot[3];
+      lds_barrier();
+      if (redo) {
+        for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
+        lds_barrier();
       }
     }
-    base += tot;
+  }
+  // ---- depth 5 (the micro-buckets) and 6 (the item), from the depth-4
+  // voxels; lanes 0..7 of wave 0 take the 8 micro-buckets
+  if (w == 0) {
+    Smp<MODE> s5 = smp_empty<MODE>();
+    if (t < 8) {
+      const uint32_t m4 = bm4[t];
+      for (uint32_t c = 0; c < 8; ++c)
+        if ((m4 >> c) & 1u) smp_add<MODE>(s5, k4col[t][c], (uint32_t)k4ok[t][c], seed);
+    }
+    const uint32_t has = (t < 8 && s5.n) ? 1u : 0u;
+    const uint32_t p5 = wave_prefix_small<1>(has);
+    const uint32_t c5 = (uint32_t)__shfl(p5 + has, 7, 64);
+    uint32_t rgba = 0, id = 0;
+    if (has) {
+      rgba = smp_rgba<MODE>(s5);
+      id = (uint32_t)s5.ok;
+      T2[t2b + cb5 + p5] = make_voxel(anc_code(lkey, 5, (grp << 3) | t), rgba);
+      if (MODE) T2id[t2b + cb5 + p5] = id;
+    }
+    Smp<MODE> s6 = smp_empty<MODE>();
+    if (has) smp_add<MODE>(s6, rgba, id, seed);
+    smp_xor<MODE>(s6, 1);
+    smp_xor<MODE>(s6, 2);
+    smp_xor<MODE>(s6, 4);
+    if (t == 0) {
+      uint32_t c6 = 0;
+      if (s6.n) {
+        const uint32_t rgba = smp_rgba<MODE>(s6);
+        T2[t2b + cb6] = make_voxel(anc_code(lkey, 6, grp), rgba);
+        if (MODE) T2id[t2b + cb6] = (uint32_t)s6.ok;
+        iself[blockIdx.x] = ((uint64_t)rgba << 32) | (uint32_t)s6.ok;
+        c6 = 1;
+      }
+      uint32_t* ic = icnt + 6 * blockIdx.x;
+      ic[0] = base1;
+      ic[1] = base2;
+      ic[2] = base3;
+      ic[3] = base4;
+      ic[4] = c5;
+      ic[5] = c6;
+    }
+  }
+}
+
+// ------------------------------------------------------------ tree pass
+//
+// Piece sizes of every node (one thread per node):
+//   psize[8N + d], d = 1..6: length of leaf N's depth-d list (0 if N is inner
+//   or has no ancestor d levels up); psize[8N + 7] = 1 for every node at level
+//   >= 7 (its self voxel in the ancestor 7 levels up).
+// Leaves at level >= 7 also get their self voxel from their items' voxels.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_piece_sizes(Nodes nodes, VoxTree vt, uint32_t num_nodes,
+                                                     const uint32_t* __restrict__ icnt,
+                                                     const uint64_t* __restrict__ iself, uint32_t seed) {
+  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= num_nodes) return;
+  const uint32_t L = nodes.level[j];
+  const bool leaf = nodes.is_leaf[j] != 0;
+  uint32_t ps[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t c6[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (leaf && L >= 1) {
+    const uint4* q = (const uint4*)(icnt + 48ull * j);  // 8 items x 6 lengths
+#pragma unroll
+    for (uint32_t k = 0; k < 12; ++k) {
+      const uint4 u = q[k];
+      const uint32_t e[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (uint32_t h = 0; h < 4; ++h) {
+        const uint32_t f = 4 * k + h, d = f % 6 + 1;
+        ps[d] += e[h];
+        if (d == 6) c6[f / 6] = e[h];
+      }
+    }
+    for (uint32_t d = 1; d <= 6; ++d)
+      if (d > L) ps[d] = 0;
+  }
+  ps[7] = L >= 7 ? 1u : 0u;
+  uint4* o = (uint4*)(vt.psize + 8ull * j);
+  o[0] = make_uint4(ps[0], ps[1], ps[2], ps[3]);
+  o[1] = make_uint4(ps[4], ps[5], ps[6], ps[7]);
+  if (leaf && L >= 7) {
+    Smp<MODE> sm = smp_empty<MODE>();
+#pragma unroll
+    for (uint32_t g = 0; g < 8; ++g)
+      if (c6[g]) {
+        const uint64_t v = iself[8ull * j + g];
+        smp_add<MODE>(sm, (uint32_t)(v >> 32), (uint32_t)v, seed);
+      }
+    vt.selfc[j] = smp_rgba<MODE>(sm);
+    vt.selfid[j] = (uint32_t)sm.ok;
+  }
+}
+
+// One workgroup per tree: subtree sizes (bottom-up), depth-first positions
+// (top-down: a node, then its children's subtrees in octant order; a tree's
+// positions are its own node range), and the self voxels of the inner nodes
+// at level >= 7 (bottom-up).
+constexpr int kVTWG = 1024;
+template <int MODE>
+__global__ void __launch_bounds__(kVTWG) k_vox_tree(Nodes nodes, VoxTree vt, const TreeInfo* __restrict__ trees,
+                                                    uint32_t seed) {
+  const TreeInfo& ti = trees[blockIdx.x];
+  const int deepest = (int)ti.deepest;
+  for (int L = deepest; L >= 0; --L) {
+    for (uint32_t j = ti.level_begin[L] + threadIdx.x; j < ti.level_end[L]; j += kVTWG) {
+      uint32_t s = 1;
+      if (!nodes.is_leaf[j]) {
+        const uint32_t fc = nodes.first_child[j], nc = (uint32_t)__popc(nodes.child_mask[j]);
+        for (uint32_t k = 0; k < nc; ++k) s += vt.sz[fc + k];
+      }
+      vt.sz[j] = s;
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
-    st->level_vbegin[lvl] = level_base;
-    st->level_vcount[lvl] = base - level_base;
-    st->voxel_total = base;
+    vt.dfs[ti.node_base] = ti.node_base;
+    vt.dfs_node[ti.node_base] = ti.node_base;
   }
-}
-
-// (5) reduce every run of the child level into its parent's list: one
-// thread per run (the run starts were listed densely by k_run_index)
-template <int MODE>
-__global__ void __launch_bounds__(kTileWG) k_write_runs(Nodes nodes, const TreeState* st, uint32_t clvl,
-                                                        const uint32_t* __restrict__ runidx,
-                                                        const uint32_t* __restrict__ runpos, uint64_t* vox,
-                                                        uint32_t* vids, uint8_t* vflag, uint32_t* vowner,
-                                                        uint32_t seed) {
-  const uint64_t vb = st->level_vbegin[clvl], V = st->level_vcount[clvl];
-  if (V == 0) return;
-  const uint32_t R = runidx[V];
-  const uint32_t stride = gridDim.x * kTileWG;
-  for (uint32_t r = blockIdx.x * kTileWG + threadIdx.x; r < R; r += stride) {
-    const uint64_t j = runpos[r];
-    const uint64_t jend = r + 1 < R ? runpos[r + 1] : V;
-    const uint64_t i = vb + j;
-    const uint32_t c = vowner[i];
-    const uint32_t rank = r - nodes.firstrun[c];
-    const uint64_t dst = nodes.dstbase[c] + rank;
-    const uint64_t v0 = vox[i];
-    const uint32_t code = voxel_code(v0) >> 3;
-    const uint32_t oct = (uint32_t)(nodes.key[c] & 7u) << 18;
-    uint32_t sr = 0, sg = 0, sb = 0, nn = 0, brgba = 0, bid = 0;
-    uint64_t best = MODE == 1 ? ~0ull : 0ull;
-    for (uint64_t k = i; k < vb + jend; ++k) {
-      const uint64_t v = k == i ? v0 : vox[k];
-      const uint32_t rgba = (uint32_t)(v >> 32);
-      if (MODE == 0) {
-        sr += rgba & 0xffu;
-        sg += (rgba >> 8) & 0xffu;
-        sb += (rgba >> 16) & 0xffu;
-        ++nn;
-      } else {
-        const uint32_t id = vids[k];
-        const uint64_t key = pick_order(id, seed, MODE == 2);
-        if (MODE == 1 ? key < best : key > best) {
-          best = key;
-          brgba = rgba;
-          bid = id;
-        }
+  __syncthreads();
+  for (int L = 0; L <= deepest; ++L) {
+    for (uint32_t j = ti.level_begin[L] + threadIdx.x; j < ti.level_end[L]; j += kVTWG) {
+      if (nodes.is_leaf[j]) continue;
+      uint32_t r = vt.dfs[j] + 1;
+      const uint32_t fc = nodes.first_child[j], nc = (uint32_t)__popc(nodes.child_mask[j]);
+      for (uint32_t k = 0; k < nc; ++k) {
+        vt.dfs[fc + k] = r;
+        vt.dfs_node[r] = fc + k;
+        r += vt.sz[fc + k];
       }
     }
-    const uint32_t rgba =
-        MODE == 0 ? ((sr / nn) | ((sg / nn) << 8) | ((sb / nn) << 16) | (255u << 24)) : brgba;
-    vox[dst] = make_voxel(oct | code, rgba);
-    if (MODE) vids[dst] = bid;
-    vowner[dst] = nodes.parent[c];
-    // the new voxel starts a run of the next level up if it opens this child's
-    // contribution or if its code >> 3 differs from the previous run's
-    vflag[dst] = (rank == 0 || (code >> 3) != ((voxel_code(vox[i - 1]) >> 3) >> 3)) ? 1 : 0;
+    __syncthreads();
   }
-}
-
-// (6) leaf children: copy their staged voxels (8 segments, one per child
-// cell) into the parent's list.  A segment's first voxel always starts a run
-// of the next level up: different child cells differ in the code bits above
-// the lowest 3.
-template <int MODE>
-__global__ void __launch_bounds__(kTileWG) k_copy_leaf_voxels(Nodes nodes, uint32_t begin, uint32_t end,
-                                                              const uint32_t* __restrict__ gcount,
-                                                              const uint32_t* __restrict__ gstart,
-                                                              const uint64_t* __restrict__ temp,
-                                                              const uint32_t* __restrict__ temp_ids,
-                                                              uint64_t* __restrict__ vox, uint32_t* __restrict__ vids,
-                                                              uint8_t* __restrict__ vflag, uint32_t* __restrict__ vowner) {
-  const uint32_t c = begin + blockIdx.x;
-  if (c >= end || !nodes.is_leaf[c]) return;
-  const uint32_t p = nodes.parent[c];
-  uint64_t dst = nodes.offset[p] + nodes.jobofs[c];
-  for (uint32_t g = 0; g < 8; ++g) {
-    const uint32_t cnt = gcount[8 * c + g];
-    const uint64_t src = gstart[8 * c + g];
-    for (uint32_t i = threadIdx.x; i < cnt; i += kTileWG) {
-      const uint64_t v = temp[src + i];
-      vox[dst + i] = v;
-      if (MODE) vids[dst + i] = temp_ids[src + i];
-      vowner[dst + i] = p;
-      vflag[dst + i] = (i == 0 || (voxel_code(v) >> 3) != (voxel_code(temp[src + i - 1]) >> 3)) ? 1 : 0;
+  for (int L = deepest; L >= 7; --L) {
+    for (uint32_t j = ti.level_begin[L] + threadIdx.x; j < ti.level_end[L]; j += kVTWG) {
+      if (nodes.is_leaf[j]) continue;
+      Smp<MODE> s = smp_empty<MODE>();
+      const uint32_t fc = nodes.first_child[j], nc = (uint32_t)__popc(nodes.child_mask[j]);
+      for (uint32_t k = 0; k < nc; ++k) smp_add<MODE>(s, vt.selfc[fc + k], vt.selfid[fc + k], seed);
+      vt.selfc[j] = smp_rgba<MODE>(s);
+      vt.selfid[j] = (uint32_t)s.ok;
     }
-    dst += cnt;
+    __syncthreads();
   }
 }
 
-__global__ void k_fill_u64(uint64_t* p, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0;
+constexpr int kPrefWG = 1024;
+
+// ------------------------------------------------------------ offsets
+//
+// The pieces of inner node A are the nodes N of A's depth-first range with
+// d = level(N) - level(A) <= 7 and psize[8N + d] > 0, in that order.
+constexpr int kPieceWG = 256;
+__device__ __forceinline__ uint32_t piece_size(const Nodes& nodes, const VoxTree& vt, uint32_t i, uint32_t e,
+                                               uint32_t L, uint32_t& N, uint32_t& d) {
+  if (i >= e) return 0;
+  N = vt.dfs_node[i];
+  d = nodes.level[N] - L;
+  return d <= 7 ? vt.psize[8ull * N + d] : 0u;
 }
 
-void launch_leaf_voxels(uint32_t mode, const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids,
-                        const uint32_t* pool, const void* pts, const uint32_t* ids, const Cube* cube, uint64_t* temp,
-                        uint32_t* temp_ids, uint32_t* gcount, uint32_t* gstart, uint32_t seed, hipStream_t s) {
+__global__ void __launch_bounds__(kPieceWG) k_piece_count(Nodes nodes, VoxTree vt, uint32_t num_nodes) {
+  __shared__ uint32_t sh[kPieceWG / 64];
+  const uint32_t a = blockIdx.x;
+  if (a >= num_nodes || nodes.is_leaf[a]) return;
+  const uint32_t L = nodes.level[a], b = vt.dfs[a] + 1, e = vt.dfs[a] + vt.sz[a];
+  uint32_t s = 0;
+  for (uint32_t i = b + threadIdx.x; i < e; i += kPieceWG) {
+    uint32_t N, d;
+    s += piece_size(nodes, vt, i, e, L, N, d);
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0) sh[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int q = 0; q < kPieceWG / 64; ++q) tot += sh[q];
+    nodes.count[a] = tot;
+  }
+}
+
+// Voxel offsets of the inner nodes of a tree in node order, counted from the
+// tree's first voxel (one workgroup per tree); the total goes to vtotal.
+__global__ void __launch_bounds__(kPrefWG) k_voxel_offsets(Nodes nodes, TreeInfo* trees) {
+  __shared__ uint64_t sh[kPrefWG / 64 + 1];
+  TreeInfo& ti = trees[blockIdx.x];
+  const uint32_t b = ti.node_base, e = ti.node_base + ti.num_nodes;
+  uint64_t base = 0;
+  for (uint32_t j0 = b; j0 < e; j0 += kPrefWG) {
+    const uint32_t j = j0 + threadIdx.x;
+    const bool inner = j < e && !nodes.is_leaf[j];
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan<kPrefWG>(inner ? (uint64_t)nodes.count[j] : (uint64_t)0, sh, &tot);
+    if (inner) nodes.offset[j] = base + ex;
+    base += tot;
+  }
+  if (threadIdx.x == 0) ti.vtotal = base;
+}
+
+// Output position of every piece of inner node A; self voxels are written
+// here directly.
+template <int MODE>
+__global__ void __launch_bounds__(kPieceWG) k_piece_offsets(Nodes nodes, VoxTree vt, uint32_t num_nodes,
+                                                            const TreeInfo* __restrict__ trees,
+                                                            uint64_t* __restrict__ vox, uint32_t* __restrict__ vids) {
+  __shared__ uint32_t sh[kPieceWG / 64 + 1];
+  const uint32_t a = blockIdx.x;
+  if (a >= num_nodes || nodes.is_leaf[a]) return;
+  const uint32_t L = nodes.level[a], b = vt.dfs[a] + 1, e = vt.dfs[a] + vt.sz[a];
+  uint64_t run = trees[nodes.tree[a]].vbase + nodes.offset[a];
+  for (uint32_t i0 = b; i0 < e; i0 += kPieceWG) {
+    uint32_t N = 0, d = 0;
+    const uint32_t s = piece_size(nodes, vt, i0 + threadIdx.x, e, L, N, d);
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<kPieceWG>(s, sh, &tot);
+    if (s) {
+      const uint64_t o = run + ex;
+      vt.poff[8ull * N + d] = o;
+      if (d == 7) {
+        vox[o] = make_voxel((uint32_t)nodes.key[N] & kCodeMask, vt.selfc[N]);
+        if (MODE) vids[o] = vt.selfid[N];
+      }
+    }
+    run += tot;
+  }
+}
+
+// Copy every item's depth-1..6 lists to their output positions: the leaf's
+// piece for that depth plus the lengths of the leaf's earlier items.
+constexpr int kGatherWG = 256;
+template <int MODE>
+__global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, uint32_t num_nodes,
+                                                      const uint32_t* __restrict__ icnt,
+                                                      const ItemDesc* __restrict__ desc,
+                                                      const uint64_t* __restrict__ T1, const uint32_t* __restrict__ T1id,
+                                                      const uint64_t* __restrict__ T2, const uint32_t* __restrict__ T2id,
+                                                      uint64_t* __restrict__ vox, uint32_t* __restrict__ vids) {
+  __shared__ uint64_t sdst[6], ssrc[6];
+  __shared__ uint32_t scnt[6];
+  const uint32_t item = blockIdx.x, n = item >> 3, g = item & 7u;
+  if (n >= num_nodes || !nodes.is_leaf[n] || nodes.level[n] == 0) return;
+  const uint32_t L = nodes.level[n];
+  if (threadIdx.x < 6) {
+    const uint32_t k = threadIdx.x + 1;
+    const uint32_t c = k <= L ? icnt[6ull * item + k - 1] : 0u;
+    uint64_t dst = 0, src = 0;
+    if (c) {
+      dst = vt.poff[8ull * n + k];
+      for (uint32_t q = 0; q < g; ++q) dst += icnt[6ull * (8 * n + q) + k - 1];
+      src = k == 1 ? (uint64_t)desc[item].I0 : desc[item].t2 + coarse_base(k, desc[item].P);
+    }
+    sdst[threadIdx.x] = dst;
+    ssrc[threadIdx.x] = src;
+    scnt[threadIdx.x] = c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < 6; ++k) {
+    const uint32_t c = scnt[k];
+    const uint64_t dst = sdst[k], src = ssrc[k];
+    const uint64_t* sv = k == 0 ? T1 : T2;
+    const uint32_t* si = k == 0 ? T1id : T2id;
+    uint32_t i = threadIdx.x;
+    for (; i + 3 * kGatherWG < c; i += 4 * kGatherWG) {
+      const uint64_t a0 = sv[src + i], a1 = sv[src + i + kGatherWG], a2 = sv[src + i + 2 * kGatherWG],
+                     a3 = sv[src + i + 3 * kGatherWG];
+      vox[dst + i] = a0;
+      vox[dst + i + kGatherWG] = a1;
+      vox[dst + i + 2 * kGatherWG] = a2;
+      vox[dst + i + 3 * kGatherWG] = a3;
+      if (MODE)
+        for (uint32_t q = 0; q < 4; ++q) vids[dst + i + q * kGatherWG] = si[src + i + q * kGatherWG];
+    }
+    for (; i < c; i += kGatherWG) {
+      vox[dst + i] = sv[src + i];
+      if (MODE) vids[dst + i] = si[src + i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes) {
+  // a block holds at most min(5p, 4681) entries for an item of p points
+  return std::min<uint64_t>(5 * n, (uint64_t)coarse_base(7, 0xffffffffu) * 8ull * num_nodes) + 1;
+}
+
+void launch_item_desc(const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids, const uint32_t* pool,
+                      BuildState* bs, void* desc, hipStream_t s) {
   if (!num_nodes) return;
-  const dim3 grid(num_nodes * 8);
-  if (mode == 0)
-    hipLaunchKernelGGL(k_leaf_voxels<0>, grid, dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool, (const uint4*)pts,
-                       ids, cube, temp, temp_ids, gcount, gstart, seed);
-  else if (mode == 1)
-    hipLaunchKernelGGL(k_leaf_voxels<1>, grid, dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool, (const uint4*)pts,
-                       ids, cube, temp, temp_ids, gcount, gstart, seed);
-  else
-    hipLaunchKernelGGL(k_leaf_voxels<2>, grid, dim3(kLeafWG), 0, s, nodes, num_nodes, grids, pool, (const uint4*)pts,
-                       ids, cube, temp, temp_ids, gcount, gstart, seed);
-  hipLaunchKernelGGL(k_leaf_sums, dim3((num_nodes + 255) / 256), dim3(256), 0, s, nodes, num_nodes, gcount);
+  hipLaunchKernelGGL(k_item_desc, dim3((8 * num_nodes + 255) / 256), dim3(256), 0, s, nodes, num_nodes, grids, pool, bs,
+                     (ItemDesc*)desc);
 }
 
-void launch_voxel_bound(const Nodes& nodes, TreeState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_voxel_bound, dim3(1), dim3(kBoundWG), 0, s, nodes, st);
-}
-
-void launch_fill_zero(uint64_t* p, uint64_t n, hipStream_t s) {
-  if (!n) return;
-  uint64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, s, p, n);
-}
-
-void launch_level(uint32_t mode, const Nodes& nodes, uint32_t L, uint32_t pbegin, uint32_t pend, uint32_t cbegin,
-                  uint32_t cend, uint64_t vcap, const uint64_t* temp, const uint32_t* temp_ids, uint64_t* vox,
-                  uint32_t* vids, TreeState* st, uint32_t* tilesum, uint32_t* runidx, uint32_t* runpos,
-                  uint8_t* vflag, uint32_t* vowner, const uint32_t* gcount, const uint32_t* gstart, uint32_t seed,
-                  hipStream_t s) {
-  const uint64_t tiles = (vcap + kTile - 1) / kTile;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 2048);
-  const uint32_t cl = L + 1;
-  hipLaunchKernelGGL(k_run_tiles, dim3(grid), dim3(kTileWG), 0, s, st, cl, vflag, tilesum);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanWG), 0, s, st, cl, tilesum);
-  hipLaunchKernelGGL(k_run_index, dim3(grid), dim3(kTileWG), 0, s, st, cl, vflag, tilesum, runidx, runpos);
-  hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(kOffWG), 0, s, nodes, L, pbegin, pend, st, runidx);
-  const uint32_t wgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((vcap / 4 + kTileWG - 1) / kTileWG, 1), 4096);
-  const uint32_t nc = cend - cbegin;
-#define LOD_LEVEL(M)                                                                                               \
-  hipLaunchKernelGGL(k_write_runs<M>, dim3(wgrid), dim3(kTileWG), 0, s, nodes, st, cl, runidx, runpos, vox, vids,  \
-                     vflag, vowner, seed);                                                                                \
-  if (nc)                                                                                                          \
-    hipLaunchKernelGGL(k_copy_leaf_voxels<M>, dim3(nc), dim3(kTileWG), 0, s, nodes, cbegin, cend, gcount, gstart,     \
-                       temp, temp_ids, vox, vids, vflag, vowner);
-  if (mode == 0) {
-    LOD_LEVEL(0)
-  } else if (mode == 1) {
-    LOD_LEVEL(1)
-  } else {
-    LOD_LEVEL(2)
+#define LOD_MODE_SWITCH(mode, M, BODY) \
+  switch (mode) {                      \
+    case 0: {                          \
+      constexpr int M = 0;             \
+      BODY;                            \
+    } break;                           \
+    case 1: {                          \
+      constexpr int M = 1;             \
+      BODY;                            \
+    } break;                           \
+    default: {                         \
+      constexpr int M = 2;             \
+      BODY;                            \
+    } break;                           \
   }
-#undef LOD_LEVEL
+
+void launch_leaf_voxels(uint32_t mode, uint32_t num_nodes, const void* desc, const void* pts, const uint32_t* ids,
+                        const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2, uint32_t* T2id, uint32_t* icnt,
+                        uint64_t* iself, uint32_t seed, hipStream_t s) {
+  if (!num_nodes) return;
+  LOD_MODE_SWITCH(mode, M,
+                  hipLaunchKernelGGL(k_leaf_voxels<M>, dim3(num_nodes * 8), dim3(kLeafWG), 0, s,
+                                     (const ItemDesc*)desc, (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt,
+                                     iself, seed))
 }
+
+void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes, TreeInfo* trees,
+                       uint32_t ntrees, const uint32_t* icnt, const uint64_t* iself, uint32_t seed, hipStream_t s) {
+  if (!num_nodes) return;
+  LOD_MODE_SWITCH(mode, M, {
+    hipLaunchKernelGGL(k_piece_sizes<M>, dim3((num_nodes + 255) / 256), dim3(256), 0, s, nodes, vt, num_nodes, icnt,
+                       iself, seed);
+    hipLaunchKernelGGL(k_vox_tree<M>, dim3(ntrees), dim3(kVTWG), 0, s, nodes, vt, (const TreeInfo*)trees, seed);
+  })
+  hipLaunchKernelGGL(k_piece_count, dim3(num_nodes), dim3(kPieceWG), 0, s, nodes, vt, num_nodes);
+  hipLaunchKernelGGL(k_voxel_offsets, dim3(ntrees), dim3(kPrefWG), 0, s, nodes, trees);
+}
+
+void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes,
+                         const TreeInfo* trees, const uint32_t* icnt, const void* desc, const uint64_t* T1,
+                         const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
+                         hipStream_t s) {
+  if (!num_nodes) return;
+  LOD_MODE_SWITCH(mode, M, {
+    hipLaunchKernelGGL(k_piece_offsets<M>, dim3(num_nodes), dim3(kPieceWG), 0, s, nodes, vt, num_nodes, trees, vox,
+                       vids);
+    hipLaunchKernelGGL(k_gather<M>, dim3(num_nodes * 8), dim3(kGatherWG), 0, s, nodes, vt, num_nodes, icnt,
+                       (const ItemDesc*)desc, T1, T1id, T2, T2id, vox, vids);
+  })
+}
+#undef LOD_MODE_SWITCH
 
 }  // namespace lod

@@ -8,8 +8,12 @@
 namespace lod {
 
 // k_split.hip
-void launch_bbox(const void* pts, uint64_t n, BBoxAcc* acc, Cube* cube, hipStream_t st);
-void launch_init_root(uint32_t n, uint32_t E0, Segment* segs, uint32_t* nseg, GridDesc* grids, hipStream_t st);
+// Bounding-box tiles of a cloud of `count` points.
+uint32_t bbox_tiles(uint32_t count);
+void launch_bbox(const void* pts, const CloudInfo* clouds, uint32_t nclouds, uint32_t ntiles, BBoxAcc* acc, Cube* cube,
+                 hipStream_t st);
+void launch_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, Segment* segs, uint32_t* nseg,
+                       GridDesc* grids, hipStream_t st);
 void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t chunk, Chunk* chunks,
                         uint32_t* nchunk, uint32_t max_chunks, ChunkGroup* groups, uint32_t* ngroup,
                         uint32_t max_groups, hipStream_t st);
@@ -20,35 +24,48 @@ void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max
                          const GridDesc* grids, uint32_t* pool, hipStream_t st);
 void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const GridDesc* grids,
                         uint32_t* pool, hipStream_t st);
+// Points per insert round of the partition scatter (with or without ids).
+uint32_t scatter_round(bool ids);
 void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
                          const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
                          uint32_t max_chunks, const uint32_t* hist, const GridDesc* grids, const uint32_t* pool,
                          hipStream_t st);
 void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,
                           const uint32_t* nseg, uint32_t max_segs, hipStream_t st);
-void launch_segments_from_grid(GridDesc* grids, uint32_t g0, uint32_t* pool, uint32_t E2, uint64_t slot_base,
+void launch_segments_from_grid(GridDesc* grids, uint32_t ngrids, uint32_t* pool, uint32_t E2, uint64_t slot_base,
                                uint32_t first_grid, Segment* segs, uint32_t* nseg, hipStream_t st);
 
 // k_tree.hip
 void launch_tree_init(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
-                      const Nodes& nodes, TreeState* st, hipStream_t s);
+                      const Nodes& nodes, TreeState* sts, const uint32_t* node_begin, const uint32_t* node_end,
+                      uint32_t nclouds, hipStream_t s);
 void launch_tree_build(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
-                       const Nodes& nodes, TreeState* st, uint32_t* refine, uint32_t* leaf_refine, uint32_t max_nodes,
-                       hipStream_t s);
+                       const Nodes& nodes, TreeState* sts, uint32_t nclouds, uint32_t* refine, uint32_t* leaf_refine,
+                       BuildState* bs, hipStream_t s);
+void launch_compact_nodes(const Nodes& src, const Nodes& dst, const TreeInfo* trees, const uint32_t* cap_begin,
+                          uint32_t ntrees, uint32_t total, hipStream_t s);
+void launch_finalize_nodes(const Nodes& nodes, const TreeInfo* trees, uint32_t total, uint8_t* o_level, uint8_t* o_leaf,
+                           uint8_t* o_mask, uint64_t* o_key, uint32_t* o_npts, uint32_t* o_count, uint32_t* o_first,
+                           uint64_t* o_off, hipStream_t s);
 void launch_refine_segments(const Nodes& nodes, const uint32_t* list, const uint32_t* nlist, uint32_t max_list,
                             uint32_t E, uint32_t first_grid, uint64_t slot_base, GridDesc* grids, Segment* segs,
                             uint32_t* nseg, hipStream_t s);
 
 // k_voxel.hip
-void launch_leaf_voxels(uint32_t mode, const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids,
-                        const uint32_t* pool, const void* pts, const uint32_t* ids, const Cube* cube, uint64_t* temp,
-                        uint32_t* temp_ids, uint32_t* gcount, uint32_t* gstart, uint32_t seed, hipStream_t s);
-void launch_voxel_bound(const Nodes& nodes, TreeState* st, hipStream_t s);
-void launch_fill_zero(uint64_t* p, uint64_t n, hipStream_t s);
-void launch_level(uint32_t mode, const Nodes& nodes, uint32_t L, uint32_t pbegin, uint32_t pend, uint32_t cbegin,
-                  uint32_t cend, uint64_t vcap, const uint64_t* temp, const uint32_t* temp_ids, uint64_t* vox,
-                  uint32_t* vids, TreeState* st, uint32_t* tilesum, uint32_t* runidx, uint32_t* runpos,
-                  uint8_t* vflag, uint32_t* vowner, const uint32_t* gcount, const uint32_t* gstart, uint32_t seed,
-                  hipStream_t s);
+// Work-item descriptors: 64 bytes per item, 8 items per node.
+void launch_item_desc(const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids, const uint32_t* pool,
+                      BuildState* bs, void* desc, hipStream_t s);
+void launch_leaf_voxels(uint32_t mode, uint32_t num_nodes, const void* desc, const void* pts, const uint32_t* ids,
+                        const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2, uint32_t* T2id, uint32_t* icnt,
+                        uint64_t* iself, uint32_t seed, hipStream_t s);
+void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes, TreeInfo* trees,
+                       uint32_t ntrees, const uint32_t* icnt, const uint64_t* iself, uint32_t seed, hipStream_t s);
+void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes,
+                         const TreeInfo* trees, const uint32_t* icnt, const void* desc, const uint64_t* T1,
+                         const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
+                         hipStream_t s);
+// Size of the coarse-list blocks of all work items, bounded from the node
+// count alone (for allocation before the item prefix is known).
+uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes);
 
 }  // namespace lod

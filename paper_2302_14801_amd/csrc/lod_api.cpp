@@ -1,16 +1,23 @@
 // lod_api.cpp -- host orchestration and C ABI of the gfx950 octree builder.
 //
-// Pipeline of one build (all kernels on the caller's stream):
-//   1. bounding box and cube                       (k_split.hip)
-//   2. partition by the first E0 levels            (root counting grid, Sec. 4.1.1-4.1.4)
-//   3. partition every root cell by E1 more levels (extended counting grids, Sec. 4.1.5)
-//   4. node enumeration; nodes whose region is not sorted deep enough are
-//      partitioned again (4 more levels) and enumeration resumes
-//   5. leaf voxels for all leaves at once, then the inner levels bottom-up
-//      (Sec. 4.2)
-// The host synchronises the stream a few times: after node enumeration (to
-// size the node table and handle refinements), after the leaf voxels (to size
-// the voxel buffer) and at the end.
+// One build call handles any number of independent clouds (lod_build: one,
+// lod_build_batch: one per chunk) with the same launches: every kernel works
+// on lists of segments, trees or work items that may belong to any cloud.
+// Pipeline (all kernels on the caller's stream):
+//   1. bounding box and cube of every cloud        (k_split.hip)
+//   2. partition by the first E0 levels            (a root counting grid per
+//                                                   cloud, Sec. 4.1.1-4.1.4)
+//   3. partition every root cell by E1 more levels (extended counting grids,
+//                                                   Sec. 4.1.5)
+//   4. node enumeration, one workgroup per tree; nodes whose region is not
+//      sorted deep enough are partitioned again (4 more levels) and
+//      enumeration resumes                          (k_tree.hip)
+//   5. voxels of every leaf for all its ancestors up to 6 levels above it,
+//      then offsets and the gather into each tree's voxel list (Sec. 4.2,
+//      k_voxel.hip)
+// The host synchronises the stream once per enumeration round (to size and
+// launch refinements), once to size the voxel output, and at the end: a
+// constant number of times per call, however many clouds it builds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -83,29 +90,55 @@ struct Scratch {
   }
 };
 
-struct HostStage {
-  TreeState st;
-  Cube cube;
+// Growable pinned host buffer for small tables exchanged with the device.
+struct Pinned {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <typename T>
+  T* get(size_t count) {
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 64);
+    if (bytes > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      const size_t c = std::max<size_t>(bytes, 4096);
+      if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        set_err("pinned host allocation failed");
+        throw LodError{LOD_ERR_OOM};
+      }
+      cap = c;
+    }
+    return (T*)p;
+  }
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
 };
 
 struct Workspace {
   int dev = 0;
   Scratch X, Xid, bbox, cube, segs, chunks, counters, hist, grids, pool, pool2, refine, leaf_refine;
-  Scratch groups, gsum, tilesum, runidx, inner_ids, inner_voff, starts;
-  Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_aux, n_jobofs;
-  Scratch n_dstbase, n_firstrun, runpos, gcount, gstart;
-  Scratch state;
-  HostStage* host = nullptr;
+  Scratch groups, gsum;
+  Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_tree;
+  Scratch c_level, c_leaf, c_mask, c_key, c_npts, c_count, c_first, c_off, c_cover, c_grid, c_parent, c_tree;
+  Scratch t2, t2id, icnt, idesc, iself, v_sz, v_dfs, v_dfsn, v_psize, v_poff, v_selfc, v_selfid;
+  Scratch state, bstate, clouds, trees, nbeg;
+  Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs;
   hipEvent_t ev[16] = {};
   bool ev_ready = false;
   ~Workspace() {
     if (ev_ready)
       for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
-    Scratch* all[] = {&X, &Xid, &bbox, &cube, &segs, &chunks, &counters, &hist, &grids, &pool, &pool2, &refine,
-                      &leaf_refine, &groups, &gsum, &tilesum, &runidx, &inner_ids, &inner_voff, &starts, &n_level, &n_leaf, &n_mask, &n_key, &n_npts, &n_count, &n_first, &n_off,
-                      &n_cover, &n_grid, &n_parent, &n_aux, &n_jobofs, &state, &n_dstbase, &n_firstrun, &runpos, &gcount, &gstart};
+    Scratch* all[] = {&X,       &Xid,     &bbox,    &cube,    &segs,     &chunks,  &counters, &hist,    &grids,
+                      &pool,    &pool2,   &refine,  &leaf_refine, &groups, &gsum,     &n_level, &n_leaf,  &n_mask,
+                      &n_key,   &n_npts,  &n_count, &n_first, &n_off,    &n_cover, &n_grid,   &n_parent, &n_tree,
+                      &c_level, &c_leaf,  &c_mask,  &c_key,   &c_npts,   &c_count, &c_first,  &c_off,   &c_cover,
+                      &c_grid,  &c_parent, &c_tree, &t2,      &t2id,     &icnt,    &idesc,    &iself,   &v_sz,
+                      &v_dfs,   &v_dfsn,  &v_psize, &v_poff,  &v_selfc,  &v_selfid, &state,   &bstate,  &clouds,
+                      &trees,   &nbeg};
     for (Scratch* s : all) s->drop(dev);
-    if (host) (void)hipHostFree(host);
   }
 };
 
@@ -124,12 +157,6 @@ Workspace* acquire_ws(int dev) {
   }
   Workspace* w = new Workspace();
   w->dev = dev;
-  if (hipHostMalloc((void**)&w->host, sizeof(HostStage), hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    delete w;
-    set_err("pinned host allocation failed");
-    throw LodError{LOD_ERR_OOM};
-  }
   return w;
 }
 
@@ -190,17 +217,25 @@ struct Plan {
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
-Plan make_plan(uint64_t n, const lod_params& p) {
+// E0/E1 follow the typical (median) cloud, chunk sizes the total: chunks set
+// the parallelism of a pass over all clouds.
+Plan make_plan(uint64_t n_typical, uint64_t n_total, const lod_params& p) {
   Plan pl;
+  const uint64_t n = n_typical;
   pl.E0 = n >= (4u << 20) ? 4 : (n >= (256u << 10) ? 3 : 2);
   pl.E1 = n >= (4u << 20) ? 4 : (n >= (64u << 10) ? 3 : 2);
   if (p.tune_levels0) pl.E0 = std::min<uint32_t>(4, p.tune_levels0);
   if (p.tune_levels1) pl.E1 = std::min<uint32_t>(4, p.tune_levels1);
-  pl.chunk0 = n >= (64u << 20) ? 65536 : (n >= (4u << 20) ? 16384 : 4096);
-  pl.chunk1 = pl.chunk0;
-  pl.chunk_ref = 16384;
   pl.mode = p.sampling;
   pl.ids = p.sampling != LOD_AVERAGE || (p.flags & LOD_FLAG_POINT_IDS);
+  // chunks are whole numbers of insert rounds (about 64k points for large
+  // inputs, two rounds in the middle range and for refinements)
+  const uint32_t R = scatter_round(pl.ids);
+  const uint64_t N = n_total;
+  pl.chunk0 = N >= (64u << 20) ? R * ((65536 + R / 2) / R) : (N >= (4u << 20) ? 2 * R : 4096);
+  if (p.tune_chunk) pl.chunk0 = std::max<uint32_t>(1, (p.tune_chunk + R / 2) / R) * R;
+  pl.chunk1 = pl.chunk0;
+  pl.chunk_ref = 2 * R;
   return pl;
 }
 
@@ -217,11 +252,38 @@ Nodes node_ptrs(Workspace& w, uint32_t cap) {
   nd.cover = w.n_cover.get<int32_t>(w.dev, cap);
   nd.grid = w.n_grid.get<int32_t>(w.dev, cap);
   nd.parent = w.n_parent.get<uint32_t>(w.dev, cap);
-  nd.aux = w.n_aux.get<uint32_t>(w.dev, cap);
-  nd.jobofs = w.n_jobofs.get<uint32_t>(w.dev, cap);
-  nd.dstbase = w.n_dstbase.get<uint64_t>(w.dev, cap);
-  nd.firstrun = w.n_firstrun.get<uint32_t>(w.dev, cap);
+  nd.tree = w.n_tree.get<uint32_t>(w.dev, cap);
   return nd;
+}
+
+Nodes compact_ptrs(Workspace& w, uint32_t cap) {
+  Nodes nd;
+  nd.level = w.c_level.get<uint8_t>(w.dev, cap);
+  nd.is_leaf = w.c_leaf.get<uint8_t>(w.dev, cap);
+  nd.child_mask = w.c_mask.get<uint8_t>(w.dev, cap);
+  nd.key = w.c_key.get<uint64_t>(w.dev, cap);
+  nd.npoints = w.c_npts.get<uint32_t>(w.dev, cap);
+  nd.count = w.c_count.get<uint32_t>(w.dev, cap);
+  nd.first_child = w.c_first.get<uint32_t>(w.dev, cap);
+  nd.offset = w.c_off.get<uint64_t>(w.dev, cap);
+  nd.cover = w.c_cover.get<int32_t>(w.dev, cap);
+  nd.grid = w.c_grid.get<int32_t>(w.dev, cap);
+  nd.parent = w.c_parent.get<uint32_t>(w.dev, cap);
+  nd.tree = w.c_tree.get<uint32_t>(w.dev, cap);
+  return nd;
+}
+
+VoxTree vox_ptrs(Workspace& w, uint32_t num_nodes) {
+  VoxTree vt;
+  const size_t c = std::max<uint32_t>(num_nodes, 1);
+  vt.sz = w.v_sz.get<uint32_t>(w.dev, c);
+  vt.dfs = w.v_dfs.get<uint32_t>(w.dev, c);
+  vt.dfs_node = w.v_dfsn.get<uint32_t>(w.dev, c);
+  vt.psize = w.v_psize.get<uint32_t>(w.dev, 8 * c);
+  vt.poff = w.v_poff.get<uint64_t>(w.dev, 8 * c);
+  vt.selfc = w.v_selfc.get<uint32_t>(w.dev, c);
+  vt.selfid = w.v_selfid.get<uint32_t>(w.dev, c);
+  return vt;
 }
 
 // Grid storage grows on demand; descriptors hold offsets, so relocation is a copy.
@@ -318,134 +380,210 @@ void refine_nodes(Workspace& w, GridPool& gp, const Nodes& nd, uint32_t* list, u
 
 }  // namespace
 
-lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params& prm, hipStream_t s) {
+std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_t* offs, uint32_t nchunks,
+                                        const lod_params& prm, hipStream_t s) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  std::unique_ptr<lod_tree> t(new lod_tree());
-  t->dev = dev;
-  t->v.num_points = n;
-  if (n == 0) {
-    t->v.cube_side = 1.0;
-    return t.release();
+  const uint64_t N = offs[nchunks] - offs[0];
+  const lod_point* in = d_points + offs[0];
+  // empty chunks get empty trees and take no part in the build
+  std::vector<uint32_t> active;
+  for (uint32_t i = 0; i < nchunks; ++i)
+    if (offs[i + 1] > offs[i]) active.push_back(i);
+  const uint32_t nc = (uint32_t)active.size();
+  std::vector<std::unique_ptr<lod_tree>> trees(nchunks);
+  for (uint32_t i = 0; i < nchunks; ++i) {
+    trees[i].reset(new lod_tree());
+    trees[i]->dev = dev;
+    trees[i]->v.cube_side = 1.0;
   }
+  auto release_all = [&]() {
+    std::vector<lod_tree*> out(nchunks);
+    for (uint32_t i = 0; i < nchunks; ++i) out[i] = trees[i].release();
+    return out;
+  };
+  if (nc == 0) return release_all();
+
   WsGuard guard(dev);
   Workspace& w = *guard.w;
-  const Plan pl = make_plan(n, prm);
+  std::vector<uint64_t> sizes(nc);
+  for (uint32_t c = 0; c < nc; ++c) sizes[c] = offs[active[c] + 1] - offs[active[c]];
+  std::vector<uint64_t> sorted = sizes;
+  std::nth_element(sorted.begin(), sorted.begin() + nc / 2, sorted.end());
+  const Plan pl = make_plan(sorted[nc / 2], N, prm);
   const bool ids = pl.ids;
 
-  // outputs that do not depend on the tree shape
-  lod_point* Y = t->alloc<lod_point>(n);
-  uint32_t* Yid = ids ? t->alloc<uint32_t>(n) : nullptr;
+  // cloud table
+  CloudInfo* hci = w.h_clouds.get<CloudInfo>(nc);
+  uint32_t ntiles = 0;
+  uint64_t passb_bound = 0;
+  const uint64_t root_cells = 1ull << (3 * pl.E0);
+  for (uint32_t c = 0; c < nc; ++c) {
+    hci[c].start = (uint32_t)(offs[active[c]] - offs[0]);
+    hci[c].count = (uint32_t)sizes[c];
+    hci[c].tile_base = ntiles;
+    hci[c].pad = 0;
+    ntiles += bbox_tiles(hci[c].count);
+    passb_bound += std::min<uint64_t>(root_cells, sizes[c]);
+  }
+  CloudInfo* clouds = w.clouds.get<CloudInfo>(dev, nc);
+  HIPCHK(hipMemcpyAsync(clouds, hci, sizeof(CloudInfo) * nc, hipMemcpyHostToDevice, s));
+
+  // outputs that do not depend on the tree shapes
+  std::shared_ptr<LodArena> arena = std::make_shared<LodArena>();
+  arena->dev = dev;
+  lod_point* Y = arena->alloc<lod_point>(N);
+  uint32_t* Yid = ids ? arena->alloc<uint32_t>(N) : nullptr;
   // scratch
-  void* X = w.X.get<uint4>(dev, n);
-  uint32_t* Xid = w.Xid.get<uint32_t>(dev, ids ? n : 1);
-  BBoxAcc* bb = w.bbox.get<BBoxAcc>(dev, 1);
-  Cube* cube = w.cube.get<Cube>(dev, 1);
+  void* X = w.X.get<uint4>(dev, N);
+  uint32_t* Xid = w.Xid.get<uint32_t>(dev, ids ? N : 1);
+  BBoxAcc* bb = w.bbox.get<BBoxAcc>(dev, nc);
+  Cube* cube = w.cube.get<Cube>(dev, nc);
   uint32_t* ctr = w.counters.get<uint32_t>(dev, 16);
-  TreeState* st = w.state.get<TreeState>(dev, 1);
+  BuildState* bs = w.bstate.get<BuildState>(dev, 1);
+  HIPCHK(hipMemsetAsync(bs, 0, sizeof(BuildState), s));
 
   GridPool gp(w, s);
-  const uint32_t root_cells = 1u << (3 * pl.E0);
-  const uint32_t max_segs1 = (uint32_t)std::min<uint64_t>(root_cells, n);
-  gp.reserve(1 + max_segs1, grid_words(pl.E0) + (uint64_t)max_segs1 * grid_words(pl.E1));
+  gp.reserve((uint32_t)(nc + passb_bound), (uint64_t)nc * grid_words(pl.E0) + passb_bound * grid_words(pl.E1));
 
   StageTimer tm(w, s, (prm.flags & LOD_FLAG_TIMING) != 0);
   tm.mark(EV_START);
-  // 1. bounding box and cube
-  launch_bbox(d_points, n, bb, cube, s);
+  // 1. bounding boxes and cubes
+  launch_bbox(in, clouds, nc, ntiles, bb, cube, s);
   tm.mark(EV_BBOX);
   // 2. root partition, input -> X
-  Segment* segs = w.segs.get<Segment>(dev, std::max<uint32_t>(max_segs1, 1));
+  Segment* segs = w.segs.get<Segment>(dev, std::max<uint64_t>(std::max<uint64_t>(passb_bound, nc), 1));
   uint32_t* nseg = ctr;
-  launch_init_root((uint32_t)n, pl.E0, segs, nseg, gp.grids, s);
-  partition(w, gp, pl.E0, pl.chunk0, 1, n, d_points, nullptr, X, Xid, ids, segs, nseg, cube, s, &tm, EV_COUNT0);
-  gp.num_grids = 1;
-  gp.used_words = grid_words(pl.E0);
+  launch_init_roots(clouds, nc, pl.E0, segs, nseg, gp.grids, s);
+  partition(w, gp, pl.E0, pl.chunk0, nc, N, in, nullptr, X, Xid, ids, segs, nseg, cube, s, &tm, EV_COUNT0);
+  gp.num_grids = nc;
+  gp.used_words = (uint64_t)nc * grid_words(pl.E0);
   // 3. every root cell by E1 more levels, X -> Y
-  launch_segments_from_grid(gp.grids, 0, gp.pool, pl.E1, gp.used_words, 1, segs, nseg, s);
-  partition(w, gp, pl.E1, pl.chunk1, max_segs1, n, X, Xid, Y, Yid, ids, segs, nseg, cube, s, &tm, EV_COUNT1);
-  gp.num_grids = 1 + max_segs1;  // descriptors past the real count are never referenced
-  gp.used_words += (uint64_t)max_segs1 * grid_words(pl.E1);
+  HIPCHK(hipMemsetAsync(nseg, 0, sizeof(uint32_t), s));
+  launch_segments_from_grid(gp.grids, nc, gp.pool, pl.E1, gp.used_words, nc, segs, nseg, s);
+  partition(w, gp, pl.E1, pl.chunk1, (uint32_t)passb_bound, N, X, Xid, Y, Yid, ids, segs, nseg, cube, s, &tm,
+            EV_COUNT1);
+  gp.num_grids = (uint32_t)(nc + passb_bound);  // descriptors past the real count are never referenced
+  gp.used_words += passb_bound * grid_words(pl.E1);
 
-  // 4. nodes
-  const uint64_t inner_max = n / ((uint64_t)prm.leaf_cap + 1);
-  const uint64_t cap64 = 1 + 8ull * inner_max * std::max<uint32_t>(prm.max_level, 1) + 8;
-  const uint32_t max_nodes = (uint32_t)std::min<uint64_t>(cap64, 0x7fffffffu);
+  // 4. nodes: one region of slots per tree
+  uint32_t* hnb = w.h_nbeg.get<uint32_t>(2 * (size_t)nc);
+  uint64_t cap_total = 0;
+  for (uint32_t c = 0; c < nc; ++c) {
+    const uint64_t inner_max = sizes[c] / ((uint64_t)prm.leaf_cap + 1);
+    const uint64_t cap = 1 + 8ull * inner_max * std::max<uint32_t>(prm.max_level, 1) + 8;
+    hnb[c] = (uint32_t)cap_total;
+    cap_total += cap;
+    if (cap_total >= 0x7fffffffull) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
+    hnb[nc + c] = (uint32_t)cap_total;
+  }
+  uint32_t* nbeg = w.nbeg.get<uint32_t>(dev, 2 * (size_t)nc);
+  HIPCHK(hipMemcpyAsync(nbeg, hnb, 8ull * nc, hipMemcpyHostToDevice, s));
+  const uint32_t max_nodes = (uint32_t)cap_total;
   Nodes nd = node_ptrs(w, max_nodes);
+  TreeState* st = w.state.get<TreeState>(dev, nc);
   uint32_t* refine = w.refine.get<uint32_t>(dev, max_nodes);
   uint32_t* leaf_refine = w.leaf_refine.get<uint32_t>(dev, max_nodes);
-  launch_tree_init(prm.leaf_cap, prm.max_level, gp.grids, gp.pool, nd, st, s);
-  HostStage* hs = w.host;
+  launch_tree_init(prm.leaf_cap, prm.max_level, gp.grids, gp.pool, nd, st, nbeg, nbeg + nc, nc, s);
+  BuildState* hbs = w.h_bs.get<BuildState>(1);
+  TreeState* hst = w.h_states.get<TreeState>(nc);
+  Cube* hcube = w.h_cubes.get<Cube>(nc);
+  HIPCHK(hipMemcpyAsync(hcube, cube, sizeof(Cube) * nc, hipMemcpyDeviceToHost, s));
   for (;;) {
-    launch_tree_build(prm.leaf_cap, prm.max_level, gp.grids, gp.pool, nd, st, refine, leaf_refine, max_nodes, s);
+    HIPCHK(hipMemsetAsync(&bs->nref, 0, sizeof(uint32_t), s));
+    launch_tree_build(prm.leaf_cap, prm.max_level, gp.grids, gp.pool, nd, st, nc, refine, leaf_refine, bs, s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&hs->st, st, sizeof(TreeState), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&hs->cube, cube, sizeof(Cube), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hbs, bs, sizeof(BuildState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hst, st, sizeof(TreeState) * nc, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hs->cube.nonfinite) fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
-    if (hs->st.overflow) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
-    if (hs->st.status == 2) {
-      refine_nodes(w, gp, nd, refine, hs->st.num_refine, n, Y, Yid, ids, cube, pl.chunk_ref, s);
+    for (uint32_t c = 0; c < nc; ++c)
+      if (hcube[c].nonfinite) fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
+    if (hbs->overflow) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
+    if (hbs->nref) {
+      refine_nodes(w, gp, nd, refine, hbs->nref, N, Y, Yid, ids, cube, pl.chunk_ref, s);
       continue;
     }
     break;
   }
-  if (hs->st.num_leaf_refine)
-    refine_nodes(w, gp, nd, leaf_refine, hs->st.num_leaf_refine, n, Y, Yid, ids, cube, pl.chunk_ref, s);
-  const uint32_t num_nodes = hs->st.num_nodes;
-  TreeState levels = hs->st;
+  if (hbs->nlref) refine_nodes(w, gp, nd, leaf_refine, hbs->nlref, N, Y, Yid, ids, cube, pl.chunk_ref, s);
+
+  // per-tree placement in the compact node table
+  TreeInfo* hti = w.h_trees.get<TreeInfo>(nc);
+  uint32_t num_nodes = 0;
+  for (uint32_t c = 0; c < nc; ++c) {
+    TreeInfo& ti = hti[c];
+    memset(&ti, 0, sizeof(ti));
+    const TreeState& ts = hst[c];
+    ti.node_base = num_nodes;
+    ti.num_nodes = ts.num_nodes - ts.node_begin;
+    ti.point_base = hci[c].start;
+    const uint32_t shift = ti.node_base - ts.node_begin;
+    for (int L = 0; L < 23; ++L) {
+      if (ts.level_end[L] > ts.level_begin[L]) {
+        ti.level_begin[L] = ts.level_begin[L] + shift;
+        ti.level_end[L] = ts.level_end[L] + shift;
+        ti.deepest = (uint32_t)L;
+      } else {
+        ti.level_begin[L] = ti.level_end[L] = 0;
+      }
+    }
+    num_nodes += ti.num_nodes;
+  }
+  TreeInfo* tinfo = w.trees.get<TreeInfo>(dev, nc);
+  HIPCHK(hipMemcpyAsync(tinfo, hti, sizeof(TreeInfo) * nc, hipMemcpyHostToDevice, s));
+  if (nc > 1) {
+    const Nodes cn = compact_ptrs(w, num_nodes);
+    launch_compact_nodes(nd, cn, tinfo, nbeg, nc, num_nodes, s);
+    nd = cn;
+  }
   tm.mark(EV_TREE);
 
-  // 5. voxels: leaves (all levels at once) into X, then the bound, then levels bottom-up
-  uint64_t* temp = (uint64_t*)X;
-  uint32_t* gcount = w.gcount.get<uint32_t>(dev, 8ull * num_nodes);
-  uint32_t* gstart = w.gstart.get<uint32_t>(dev, 8ull * num_nodes);
-  launch_leaf_voxels(pl.mode, nd, num_nodes, gp.grids, gp.pool, Y, Yid, cube, temp, Xid, gcount, gstart, prm.seed, s);
+  // 5. voxels: every leaf's lists for its ancestors up to 6 levels above it
+  // (depth 1 into X, coarser ones into t2), then the tree pass and the node
+  // offsets, one sync to size the output, then piece offsets and the gather
+  const uint32_t items = 8 * num_nodes;
+  uint64_t* T1 = (uint64_t*)X;
+  uint32_t* icnt = w.icnt.get<uint32_t>(dev, 6ull * items);
+  void* desc = w.idesc.get<uint4>(dev, 4ull * items);
+  uint64_t* iself = w.iself.get<uint64_t>(dev, items);
+  const uint64_t t2cap = coarse_space_bound(N, num_nodes);
+  uint64_t* T2 = w.t2.get<uint64_t>(dev, t2cap);
+  uint32_t* T2id = pl.mode ? w.t2id.get<uint32_t>(dev, t2cap) : nullptr;
+  const VoxTree vt = vox_ptrs(w, num_nodes);
+  launch_item_desc(nd, num_nodes, gp.grids, gp.pool, bs, desc, s);
+  launch_leaf_voxels(pl.mode, num_nodes, desc, Y, Yid, cube, T1, Xid, T2, T2id, icnt, iself, prm.seed, s);
   tm.mark(EV_LEAF);
-  launch_voxel_bound(nd, st, s);
+  launch_voxel_tree(pl.mode, nd, vt, num_nodes, tinfo, nc, icnt, iself, prm.seed, s);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(&hs->st, st, sizeof(TreeState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hti, tinfo, sizeof(TreeInfo) * nc, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const uint64_t vcap = hs->st.voxel_bound;
-  uint64_t* vox = t->alloc<uint64_t>(std::max<uint64_t>(vcap, 1));
-  uint32_t* vids = pl.mode ? t->alloc<uint32_t>(std::max<uint64_t>(vcap, 1)) : nullptr;
-  int deepest_inner = -1;
-  for (int L = 0; L < 22; ++L)
-    if (levels.level_end[L + 1] > levels.level_begin[L + 1]) deepest_inner = L;
-  uint32_t* tilesum = w.tilesum.get<uint32_t>(dev, (vcap + 4095) / 4096 + 2);
-  uint32_t* runidx = w.runidx.get<uint32_t>(dev, vcap + 2);
-  uint8_t* vflag = w.starts.get<uint8_t>(dev, vcap + 8);
-  uint32_t* vowner = w.inner_ids.get<uint32_t>(dev, vcap + 1);
-  uint32_t* runpos = w.runpos.get<uint32_t>(dev, vcap + 1);
-  for (int L = deepest_inner; L >= 0; --L)
-    launch_level(pl.mode, nd, (uint32_t)L, levels.level_begin[L], levels.level_end[L], levels.level_begin[L + 1],
-                 levels.level_end[L + 1], vcap, temp, Xid, vox, vids, st, tilesum, runidx, runpos, vflag, vowner,
-                 gcount, gstart, prm.seed, s);
+  uint64_t vtotal = 0;
+  for (uint32_t c = 0; c < nc; ++c) {
+    hti[c].vbase = vtotal;
+    vtotal += hti[c].vtotal;
+  }
+  HIPCHK(hipMemcpyAsync(tinfo, hti, sizeof(TreeInfo) * nc, hipMemcpyHostToDevice, s));
+  uint64_t* vox = arena->alloc<uint64_t>(std::max<uint64_t>(vtotal, 1));
+  uint32_t* vids = pl.mode ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
+  launch_voxel_gather(pl.mode, nd, vt, num_nodes, tinfo, icnt, desc, T1, Xid, T2, T2id, vox, vids, s);
   HIPCHK(hipGetLastError());
   tm.mark(EV_LEVELS);
 
-  // 6. exact-size node table for the tree
-  uint8_t* o_level = t->alloc<uint8_t>(num_nodes);
-  uint8_t* o_leaf = t->alloc<uint8_t>(num_nodes);
-  uint8_t* o_mask = t->alloc<uint8_t>(num_nodes);
-  uint64_t* o_key = t->alloc<uint64_t>(num_nodes);
-  uint32_t* o_npts = t->alloc<uint32_t>(num_nodes);
-  uint32_t* o_count = t->alloc<uint32_t>(num_nodes);
-  uint32_t* o_first = t->alloc<uint32_t>(num_nodes);
-  uint64_t* o_off = t->alloc<uint64_t>(num_nodes);
-  HIPCHK(hipMemcpyAsync(o_level, nd.level, num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(o_leaf, nd.is_leaf, num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(o_mask, nd.child_mask, num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(o_key, nd.key, 8ull * num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(o_npts, nd.npoints, 4ull * num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(o_count, nd.count, 4ull * num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(o_first, nd.first_child, 4ull * num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(o_off, nd.offset, 8ull * num_nodes, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(&hs->st, st, sizeof(TreeState), hipMemcpyDeviceToHost, s));
+  // 6. output node tables (per-tree indices and offsets)
+  uint8_t* o_level = arena->alloc<uint8_t>(num_nodes);
+  uint8_t* o_leaf = arena->alloc<uint8_t>(num_nodes);
+  uint8_t* o_mask = arena->alloc<uint8_t>(num_nodes);
+  uint64_t* o_key = arena->alloc<uint64_t>(num_nodes);
+  uint32_t* o_npts = arena->alloc<uint32_t>(num_nodes);
+  uint32_t* o_count = arena->alloc<uint32_t>(num_nodes);
+  uint32_t* o_first = arena->alloc<uint32_t>(num_nodes);
+  uint64_t* o_off = arena->alloc<uint64_t>(num_nodes);
+  launch_finalize_nodes(nd, tinfo, num_nodes, o_level, o_leaf, o_mask, o_key, o_npts, o_count, o_first, o_off, s);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
 
+  lod_timings T{};
   if (tm.on) {
-    lod_timings& T = t->timings;
     T.bbox = tm.ms(EV_START, EV_BBOX);
     T.count0 = tm.ms(EV_BBOX, EV_COUNT0);
     T.offsets0 = tm.ms(EV_COUNT0, EV_OFF0);
@@ -458,28 +596,41 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
     T.levels = tm.ms(EV_LEAF, EV_LEVELS);
     T.total = tm.ms(EV_START, EV_LEVELS);
   }
-  lod_tree_view& v = t->v;
-  for (int a = 0; a < 3; ++a) {
-    v.aabb_min[a] = hs->cube.lo[a];
-    v.aabb_max[a] = hs->cube.hi[a];
+  for (uint32_t c = 0; c < nc; ++c) {
+    lod_tree& t = *trees[active[c]];
+    const TreeInfo& ti = hti[c];
+    t.arena = arena;
+    t.timings = T;
+    t.footprint = (uint64_t)((double)arena->bytes * (double)hci[c].count / (double)N);
+    lod_tree_view& v = t.v;
+    for (int a = 0; a < 3; ++a) {
+      v.aabb_min[a] = hcube[c].lo[a];
+      v.aabb_max[a] = hcube[c].hi[a];
+    }
+    v.cube_side = hcube[c].side;
+    v.num_nodes = ti.num_nodes;
+    v.num_points = hci[c].count;
+    v.num_voxels = ti.vtotal;
+    v.node_level = o_level + ti.node_base;
+    v.node_is_leaf = o_leaf + ti.node_base;
+    v.node_child_mask = o_mask + ti.node_base;
+    v.node_key = o_key + ti.node_base;
+    v.node_npoints = o_npts + ti.node_base;
+    v.node_count = o_count + ti.node_base;
+    v.node_first_child = o_first + ti.node_base;
+    v.node_offset = o_off + ti.node_base;
+    v.points = Y + ti.point_base;
+    v.point_ids = Yid ? Yid + ti.point_base : nullptr;
+    v.voxels = (const lod_voxel*)(vox + ti.vbase);
+    v.voxel_ids = vids ? vids + ti.vbase : nullptr;
   }
-  v.cube_side = hs->cube.side;
-  v.num_nodes = num_nodes;
-  v.num_points = n;
-  v.num_voxels = hs->st.voxel_total;
-  v.node_level = o_level;
-  v.node_is_leaf = o_leaf;
-  v.node_child_mask = o_mask;
-  v.node_key = o_key;
-  v.node_npoints = o_npts;
-  v.node_count = o_count;
-  v.node_first_child = o_first;
-  v.node_offset = o_off;
-  v.points = Y;
-  v.point_ids = Yid;
-  v.voxels = (const lod_voxel*)vox;
-  v.voxel_ids = vids;
-  return t.release();
+  return release_all();
+}
+
+lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params& prm, hipStream_t s) {
+  const uint64_t offs[2] = {0, n};
+  std::vector<lod_tree*> t = lod_build_clouds(d_points, offs, 1, prm, s);
+  return t[0];
 }
 
 namespace {
@@ -547,17 +698,26 @@ lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets,
       set_err("offsets must be non-decreasing and chunks below 2^32 points");
       return LOD_ERR_INVALID;
     }
-  for (uint32_t i = 0; i < num_chunks; ++i) {
-    lod_status stt = lod_build(d_points + h_offsets[i], h_offsets[i + 1] - h_offsets[i], p, hip_stream, &out[i]);
-    if (stt != LOD_OK) {
-      for (uint32_t k = 0; k < i; ++k) {
-        lod_tree_free(out[k]);
-        out[k] = nullptr;
-      }
-      return stt;
-    }
+  if (num_chunks && h_offsets[num_chunks] - h_offsets[0] >= 0xffffffffull) {
+    set_err("a batch holds fewer than 2^32 points");
+    return LOD_ERR_INVALID;
   }
-  return LOD_OK;
+  if (num_chunks && h_offsets[num_chunks] > h_offsets[0] && !d_points) {
+    set_err("d_points is NULL");
+    return LOD_ERR_INVALID;
+  }
+  if (num_chunks == 0) return LOD_OK;
+  try {
+    std::vector<lod_tree*> t = lod_build_clouds(d_points, h_offsets, num_chunks, *p, (hipStream_t)hip_stream);
+    for (uint32_t i = 0; i < num_chunks; ++i) out[i] = t[i];
+    return LOD_OK;
+  } catch (const LodError& e) {
+    (void)hipGetLastError();
+    return e.st;
+  } catch (...) {
+    set_err("unexpected host exception");
+    return LOD_ERR_OOM;
+  }
 }
 
 lod_status lod_tree_view_get(const lod_tree* t, lod_tree_view* v) {

@@ -137,6 +137,16 @@ def batch_chunks(sizes, seed: int = 4, out=None):
     return a[:offs[-1]], offs
 
 
+def serve_tile(n: int, seed: int, out=None) -> np.ndarray:
+    """First n points of a 50M-point tile of the batch generator (terrain 7/9
+    + buildings 2/9, 100 points per square metre, 707 m side).  Components
+    interleave at random, so any prefix is a uniform subsample of the tile."""
+    full = 50_000_000
+    side = 100.0 * math.sqrt(full / 1e6)
+    return tile(n, seed, side=side, amp=10.0, wavelength=100.0, f_building=2.0 / 9.0,
+                n_buildings=int(round(20 * full / 1e6)), out=out)
+
+
 def uniform_cloud(n: int, seed: int, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), colors: bool = True) -> np.ndarray:
     """Small uniform random cloud for tests (numpy only)."""
     rng = np.random.default_rng(seed)

@@ -163,13 +163,13 @@ def test_tuning_and_repeat_do_not_change_results(lod):
     again = gpu_tree(lod, p, leaf_cap=3000, max_level=12)
     for k in ("level", "key", "npoints", "count", "voxels"):
         assert np.array_equal(base[k], again[k])
-    for t0, t1 in ((1, 1), (2, 4), (4, 2), (3, 3), (4, 4)):
-        params = lod.make_params(leaf_cap=3000, max_level=12, tune_levels0=t0, tune_levels1=t1)
+    for t0, t1, ch in ((1, 1, 0), (2, 4, 1), (4, 2, 50_000), (3, 3, 7000), (4, 4, 0)):
+        params = lod.make_params(leaf_cap=3000, max_level=12, tune_levels0=t0, tune_levels1=t1, tune_chunk=ch)
         t = lod.lod_build(to_dev(p), params=params)
         h = t.to_host()
         t.free()
         for k in ("level", "key", "npoints", "count", "first_child", "voxels"):
-            assert np.array_equal(base[k], h[k]), (t0, t1, k)
+            assert np.array_equal(base[k], h[k]), (t0, t1, ch, k)
 
 
 def test_input_order_invariance(lod):
@@ -183,17 +183,49 @@ def test_input_order_invariance(lod):
     check(lod, p[perm], T=5000, sampling=1)
 
 
-def test_batch_equals_single_builds(lod):
+@pytest.mark.parametrize("sampling", [0, 2])
+def test_batch_equals_single_builds(lod, sampling):
     sizes = [3000, 50, 120000, 0, 40000, 777]
     pts, offs = synth.batch_chunks(sizes, seed=4)
-    trees = lod.lod_build_batch(to_dev(pts), offs, leaf_cap=2000, max_level=12)
+    trees = lod.lod_build_batch(to_dev(pts), offs, leaf_cap=2000, max_level=12, sampling=sampling, seed=11)
     assert len(trees) == len(sizes)
     for i, t in enumerate(trees):
         chunk = pts[offs[i]:offs[i + 1]]
         g = t.to_host()
         t.free()
-        o = oracle.build(chunk, leaf_cap=2000, max_level=12)
+        o = oracle.build(chunk, leaf_cap=2000, max_level=12, sampling=sampling, seed=11)
         canon.compare_trees(g, o, chunk)
+
+
+def test_autotuned_batch_plan_gives_same_trees(lod):
+    from paper_2302_14801_amd import autotune
+    sizes = [30_000, 200_000, 5_000, 90_000, 60_000, 1]
+    pts, offs = synth.batch_chunks(sizes, seed=21)
+    dev = to_dev(pts)
+    base = lod.make_params(leaf_cap=4000, max_level=12)
+    tuned, info = autotune.tune_batch(dev, offs, base, sample_chunks=4, reps=1)
+    assert len(info["plan"]) == 3
+    a = lod.lod_build_batch(dev, offs, params=base)
+    b = lod.lod_build_batch(dev, offs, params=tuned)
+    for ta, tb in zip(a, b):
+        ga, gb = ta.to_host(), tb.to_host()
+        ta.free()
+        tb.free()
+        for k in ("level", "key", "npoints", "count", "first_child", "voxels"):
+            assert np.array_equal(ga[k], gb[k]), k
+
+
+def test_batch_many_uneven_chunks(lod):
+    # 48 chunks of lognormal sizes (one launch sequence for all), every tree
+    # checked against the oracle on its own chunk
+    sizes = synth.chunk_sizes(48, seed=9, median=20_000, sigma=1.0, lo=1, hi=400_000)
+    pts, offs = synth.batch_chunks(sizes, seed=9)
+    trees = lod.lod_build_batch(to_dev(pts), offs, leaf_cap=3000, max_level=12)
+    for i, t in enumerate(trees):
+        chunk = pts[offs[i]:offs[i + 1]]
+        g = t.to_host()
+        t.free()
+        canon.compare_trees(g, oracle.build(chunk, leaf_cap=3000, max_level=12), chunk)
 
 
 def test_server_results_equal_alone_and_in_mix(lod):

@@ -1,0 +1,45 @@
+"""GPU parity at the 2B-point configuration: a dense terrestrial-scan-like
+scene (64 spheres and planes, 1 mm noise, 50 m box; 32 GB of input) built on
+one GPU with T = 50 000, 128^3, colour-filtered, checked by the properties
+and sampled oracle subtrees of fullsize.py (membership on a sample of
+leaves).  It needs about 70 GB of host memory, 130 GB of device memory and a
+few minutes, so it runs only when LOD_TEST_2B=1."""
+from __future__ import annotations
+
+import os
+
+import pytest
+
+import fullsize
+import synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("LOD_TEST_2B") != "1", reason="2B-point run: set LOD_TEST_2B=1")]
+
+N = 2_000_000_000
+T = 50_000
+ML = 12
+
+
+def test_scan_2b_configuration():
+    import torch
+
+    import paper_2302_14801_amd as lod
+
+    fullsize.log("generating 2B points")
+    host = torch.empty(N * 16, dtype=torch.uint8, pin_memory=True)
+    pts = host.numpy().view(synth.POINT_DTYPE)
+    for i in range(0, N, 250_000_000):
+        n = min(250_000_000, N - i)
+        synth.scan(n, seed=3, first=i, out=pts[i:i + n])
+    dev = host.to("cuda:0")
+    fullsize.log("building on the GPU")
+    params = lod.make_params(leaf_cap=T, max_level=ML, timing=True)
+    t = lod.lod_build(dev, params=params)
+    tm = t.timings()
+    g = t.to_host()
+    t.free()
+    del dev
+    torch.cuda.empty_cache()
+    fullsize.log(f"{g['num_nodes']} nodes, {g['num_voxels']} voxels, build {tm['total']:.2f} ms (stage sum)")
+    fullsize.check_build(g, pts, T, ML, subtree_picks=3, leaf_sample=64)
