@@ -208,6 +208,23 @@ def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, 
     t_served = build_done.max() - arrivals[0]
     for t in resident:
         t.free()
+    resident.clear()
+    # the same requests all at once (closed loop): the server's throughput
+    print("[bench] served: saturated", file=sys.stderr, flush=True)
+    s0 = time.perf_counter()
+    pending = {srv.submit(reqs[r]): r for r in range(num_requests)}
+    while pending:
+        for tk in list(pending):
+            t = srv.poll(tk)
+            if t is not None:
+                pending.pop(tk)
+                resident.append(t)
+                while len(resident) > keep:
+                    resident.pop(0).free()
+        time.sleep(0.0002)
+    t_sat = time.perf_counter() - s0
+    for t in resident:
+        t.free()
     srv.destroy()
     # the same requests one by one
     print("[bench] served: plain sequential builds", file=sys.stderr, flush=True)
@@ -234,6 +251,7 @@ def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, 
             "p99_latency_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
             "max_latency_ms": round(1e3 * float(lat.max()), 3),
             "offered_points_per_s": round(total / (arrivals[-1] - arrivals[0]), 1),
+            "saturated_points_per_s": round(total / t_sat, 1), "saturated_s": round(t_sat, 3),
             "plain_points_per_s": round(total / t_plain, 1), "plain_s": round(t_plain, 3)}
 
 
