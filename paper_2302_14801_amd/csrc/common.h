@@ -96,6 +96,26 @@ __device__ __forceinline__ uint64_t point_key(float x, float y, float z, const C
   return spread21(qx) | (spread21(qy) << 1) | (spread21(qz) << 2);
 }
 
+// Spread the low 10 bits of v so that bit i lands at bit 3i (32-bit).
+__host__ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
+  uint32_t x = v & 0x3ffu;
+  x = (x | x << 16) & 0x030000ffu;
+  x = (x | x << 8) & 0x0300f00fu;
+  x = (x | x << 4) & 0x030c30c3u;
+  x = (x | x << 2) & 0x09249249u;
+  return x;
+}
+
+// The E <= 10 key levels below bit level p of the Morton key, i.e.
+// (point_key >> 3p) & (8^E - 1), from the E bits of each axis at and above p.
+__device__ __forceinline__ uint32_t point_cell(float x, float y, float z, const CubeD& c, uint32_t p, uint32_t E) {
+  const uint32_t m = (1u << E) - 1u;
+  const uint32_t qx = (quantize(x, c.lo[0], c.scale) >> p) & m;
+  const uint32_t qy = (quantize(y, c.lo[1], c.scale) >> p) & m;
+  const uint32_t qz = (quantize(z, c.lo[2], c.scale) >> p) & m;
+  return spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+}
+
 // 7-bit-per-axis Morton code of a voxel cell and its inverse.
 __host__ __device__ __forceinline__ uint32_t morton7(uint32_t x, uint32_t y, uint32_t z) {
   return (uint32_t)(spread21(x) | (spread21(y) << 1) | (spread21(z) << 2));

@@ -219,21 +219,21 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
   const Chunk ch = chunks[c];
   const Segment sg = segs[ch.seg];
   const CubeD cd = load_cube(cube + sg.cloud);
-  const uint32_t shift = 3u * (kKeyLevels - (sg.level + E));
+  const uint32_t lvl_bit = kKeyLevels - (sg.level + E);  // the E levels below the segment's level
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) h[j] = 0;
   lds_barrier();
   const uint4* p = pts + ch.start;
   uint32_t i = threadIdx.x;
   for (; i + 3 * kCountWG < ch.count; i += 4 * kCountWG) {
     uint4 v0 = p[i], v1 = p[i + kCountWG], v2 = p[i + 2 * kCountWG], v3 = p[i + 3 * kCountWG];
-    atomicAdd(&h[(point_key(__uint_as_float(v0.x), __uint_as_float(v0.y), __uint_as_float(v0.z), cd) >> shift) & (B - 1)], 1u);
-    atomicAdd(&h[(point_key(__uint_as_float(v1.x), __uint_as_float(v1.y), __uint_as_float(v1.z), cd) >> shift) & (B - 1)], 1u);
-    atomicAdd(&h[(point_key(__uint_as_float(v2.x), __uint_as_float(v2.y), __uint_as_float(v2.z), cd) >> shift) & (B - 1)], 1u);
-    atomicAdd(&h[(point_key(__uint_as_float(v3.x), __uint_as_float(v3.y), __uint_as_float(v3.z), cd) >> shift) & (B - 1)], 1u);
+    atomicAdd(&h[point_cell(__uint_as_float(v0.x), __uint_as_float(v0.y), __uint_as_float(v0.z), cd, lvl_bit, E)], 1u);
+    atomicAdd(&h[point_cell(__uint_as_float(v1.x), __uint_as_float(v1.y), __uint_as_float(v1.z), cd, lvl_bit, E)], 1u);
+    atomicAdd(&h[point_cell(__uint_as_float(v2.x), __uint_as_float(v2.y), __uint_as_float(v2.z), cd, lvl_bit, E)], 1u);
+    atomicAdd(&h[point_cell(__uint_as_float(v3.x), __uint_as_float(v3.y), __uint_as_float(v3.z), cd, lvl_bit, E)], 1u);
   }
   for (; i < ch.count; i += kCountWG) {
     uint4 v = p[i];
-    atomicAdd(&h[(point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd) >> shift) & (B - 1)], 1u);
+    atomicAdd(&h[point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, lvl_bit, E)], 1u);
   }
   lds_barrier();
   uint32_t* row = hist + (uint64_t)c * B;
@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
   const Segment sg = segs[ch.seg];
   const GridDesc g = grids[sg.grid];
   const CubeD cd = load_cube(cube + sg.cloud);
-  const uint32_t shift = 3u * (kKeyLevels - (sg.level + E));
+  const uint32_t lvl_bit = kKeyLevels - (sg.level + E);  // the E levels below the segment's level
   const uint32_t* row = hist + (uint64_t)c * B;
   const uint32_t* goff = pool + g.off;
   // without source ids (the first pass over the input, one segment per
@@ -417,8 +417,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     for (int k = 0; k < PPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
-        uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
-        bk[k] = (uint32_t)(key >> shift) & (B - 1);
+        bk[k] = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E);
         rk[k] = atomicAdd(&cnt[PAD(bk[k])], 1u);
       }
     }

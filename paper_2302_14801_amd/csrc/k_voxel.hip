@@ -240,16 +240,14 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nod
   }
 }
 
-// First sample of a depth-1 cell: mark it and, the first time, its depth-2,
-// 3 and 4 cells in the occupancy bitmasks, counting every newly occupied cell
-// for its quarter of the micro-bucket's cells (the cells a wave emits).
-__device__ __forceinline__ void claim_cell(uint32_t* bm1, uint32_t* bm2, uint32_t* bm3, uint32_t* bm4,
-                                           uint32_t (*nocc)[8][4], uint32_t jm, uint32_t s) {
-  uint32_t bit = 1u << (s & 31);
-  if (atomicOr(&bm1[s >> 5], bit) & bit) return;
+// First sample of a depth-1 cell s (its bit in bm1 already set): count it
+// for its quarter of the micro-bucket's cells (the cells a wave emits) and,
+// the first time, mark and count its depth-2, 3 and 4 cells likewise.
+__device__ __forceinline__ void claim_counts(uint32_t* bm2, uint32_t* bm3, uint32_t* bm4, uint32_t (*nocc)[8][4],
+                                             uint32_t jm, uint32_t s) {
   atomicAdd(&nocc[0][jm][s >> 10], 1u);
   const uint32_t c2 = s >> 3;
-  bit = 1u << (c2 & 31);
+  uint32_t bit = 1u << (c2 & 31);
   if (atomicOr(&bm2[c2 >> 5], bit) & bit) return;
   atomicAdd(&nocc[1][jm][c2 >> 7], 1u);
   const uint32_t c3 = s >> 6;
@@ -260,6 +258,19 @@ __device__ __forceinline__ void claim_cell(uint32_t* bm1, uint32_t* bm2, uint32_
   bit = 1u << c4;
   if (atomicOr(&bm4[jm], bit) & bit) return;
   atomicAdd(&nocc[3][jm][c4 >> 1], 1u);
+}
+// A sample of cell s: the one that sets its occupancy bit claims it.
+__device__ __forceinline__ void claim_cell(uint32_t* bm1, uint32_t* bm2, uint32_t* bm3, uint32_t* bm4,
+                                           uint32_t (*nocc)[8][4], uint32_t jm, uint32_t s) {
+  const uint32_t bit = 1u << (s & 31);
+  if (atomicOr(&bm1[s >> 5], bit) & bit) return;
+  claim_counts(bm2, bm3, bm4, nocc, jm, s);
+}
+// The caller knows that it brings the first sample of s.
+__device__ __forceinline__ void claim_new(uint32_t* bm1, uint32_t* bm2, uint32_t* bm3, uint32_t* bm4,
+                                          uint32_t (*nocc)[8][4], uint32_t jm, uint32_t s) {
+  atomicOr(&bm1[s >> 5], 1u << (s & 31));
+  claim_counts(bm2, bm3, bm4, nocc, jm, s);
 }
 
 // ------------------------------------------------------------ leaf kernel
@@ -327,7 +338,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   }
   const uint32_t I0 = sd.I0, I1 = I0 + P, lvl = sd.lvl, grp = blockIdx.x & 7u;
   const uint64_t lkey = sd.lkey, t2b = sd.t2;
-  const uint32_t sub_shift = 3u * (15u - lvl);  // key >> sub_shift = depth-1 cell (level lvl + 6)
+  const uint32_t sub_bit = 15u - lvl;  // bit level of the depth-1 cells (level lvl + 6)
   const uint32_t cb3 = coarse_base(3, P), cb4 = coarse_base(4, P), cb5 = coarse_base(5, P), cb6 = coarse_base(6, P);
   uint32_t base1 = 0, base2 = 0, base3 = 0, base4 = 0;  // list lengths so far
   for (uint32_t P0 = I0; P0 < I1; P0 += kLeafPass) {
@@ -348,8 +359,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         const uint32_t i = P0 + k * kLeafWG + t;
         cell[k] = kNoCell;
         if (i < P1) {
-          const uint64_t key = point_key(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd);
-          cell[k] = (uint32_t)(key >> sub_shift) & 0x7fffu;
+          cell[k] = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, sub_bit, 5);
           col[k] = v[k].w;
         }
       }
@@ -375,12 +385,15 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
                                     ((uint64_t)((col[k] >> 16) & 0xff) << 32) | (1ull << 48);
             const uint64_t old = atomicAdd((unsigned long long*)&acc[sc], (unsigned long long)packed);
             if ((old >> 48) == 257) over[jm] = 1;
+            // the count field is nonzero after any add (and cannot wrap below
+            // 2^16 samples): a zero old value marks the cell's first sample
+            if (old == 0) claim_new(bm1, bm2, bm3, bm4, nocc, jm, sc);
           } else {
             const uint64_t ok = pick_order(pid[k], seed, MODE == 2);
             if (MODE == 1) atomicMin((unsigned long long*)&acc[sc], (unsigned long long)ok);
             else atomicMax((unsigned long long*)&acc[sc], (unsigned long long)ok);
+            claim_cell(bm1, bm2, bm3, bm4, nocc, jm, sc);
           }
-          claim_cell(bm1, bm2, bm3, bm4, nocc, jm, sc);
         }
       }
       if (off + cnt > P1) break;  // continues in the next pass
@@ -407,8 +420,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
           lds_barrier();
           for (uint32_t i = t; i < cnt; i += kLeafWG) {
             const uint4 v = pts[off + i];
-            const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
-            const uint32_t sc = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
+            const uint32_t sc = point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, sub_bit, 4);
             if (w0 == 0) claim_cell(bm1, bm2, bm3, bm4, nocc, jm, sc);
             if (sc >= w0 && sc < w0 + 512) {
               const uint32_t q = sc - w0;
@@ -447,8 +459,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
           for (uint32_t i = off + t; i < off + cnt; i += kLeafWG) {
             const uint32_t id = ids[i];
             const uint4 v = pts[i];
-            const uint64_t key = point_key(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd);
-            const uint32_t sc = (uint32_t)(key >> sub_shift) & (kSubCells - 1);
+            const uint32_t sc = point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, sub_bit, 4);
             if (acc[sc] == pick_order(id, seed, MODE == 2)) acc[sc] = ((uint64_t)v.w << 32) | id;
           }
         }
