@@ -29,6 +29,8 @@ def multiset_hash(rows: np.ndarray) -> tuple:
     64-bit value per record (two independent aggregations), in chunks."""
     s, x = np.uint64(0), np.uint64(0)
     for i in range(0, len(rows), CHUNK):
+        if i and i % (10 * CHUNK) == 0:
+            log(f"  hashed {i} records")
         w = np.ascontiguousarray(rows[i:i + CHUNK]).view(np.uint64).reshape(-1, 2)
         with np.errstate(over="ignore"):
             h = (w[:, 0] * np.uint64(0x9E3779B97F4A7C15)) ^ (w[:, 1] + np.uint64(0xD1B54A32D192ED03))
@@ -91,6 +93,8 @@ def check_build(g: dict, pts: np.ndarray, T: int, ML: int, subtree_picks: int = 
     want = {x: (int(lv[x]), np.uint64(int(key[x]))) for x in picks}
     sel = {x: [] for x in picks}
     for i in range(0, N, CHUNK):
+        if i and i % (10 * CHUNK) == 0:
+            log(f"  keyed {i} input points")
         ik = oracle.keys_in_cube(pts[i:i + CHUNK], lo, side)
         for x, (L, kx) in want.items():
             sel[x].append(np.nonzero((ik >> np.uint64(3 * (21 - L))) == kx)[0] + i)

@@ -32,6 +32,7 @@ def test_scan_2b_configuration():
     for i in range(0, N, 250_000_000):
         n = min(250_000_000, N - i)
         synth.scan(n, seed=3, first=i, out=pts[i:i + n])
+        fullsize.log(f"  generated {i + n}")
     dev = host.to("cuda:0")
     fullsize.log("building on the GPU")
     params = lod.make_params(leaf_cap=T, max_level=ML, timing=True)
