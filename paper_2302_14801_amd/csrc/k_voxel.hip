@@ -240,39 +240,6 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nod
   }
 }
 
-// First sample of a depth-1 cell s (its bit in bm1 already set): count it
-// for its quarter of the micro-bucket's cells (the cells a wave emits) and,
-// the first time, mark and count its depth-2, 3 and 4 cells likewise.
-__device__ __forceinline__ void claim_counts(uint32_t* bm2, uint32_t* bm3, uint32_t* bm4, uint32_t (*nocc)[8][4],
-                                             uint32_t jm, uint32_t s) {
-  atomicAdd(&nocc[0][jm][s >> 10], 1u);
-  const uint32_t c2 = s >> 3;
-  uint32_t bit = 1u << (c2 & 31);
-  if (atomicOr(&bm2[c2 >> 5], bit) & bit) return;
-  atomicAdd(&nocc[1][jm][c2 >> 7], 1u);
-  const uint32_t c3 = s >> 6;
-  bit = 1u << (c3 & 31);
-  if (atomicOr(&bm3[c3 >> 5], bit) & bit) return;
-  atomicAdd(&nocc[2][jm][c3 >> 4], 1u);
-  const uint32_t c4 = s >> 9;
-  bit = 1u << c4;
-  if (atomicOr(&bm4[jm], bit) & bit) return;
-  atomicAdd(&nocc[3][jm][c4 >> 1], 1u);
-}
-// A sample of cell s: the one that sets its occupancy bit claims it.
-__device__ __forceinline__ void claim_cell(uint32_t* bm1, uint32_t* bm2, uint32_t* bm3, uint32_t* bm4,
-                                           uint32_t (*nocc)[8][4], uint32_t jm, uint32_t s) {
-  const uint32_t bit = 1u << (s & 31);
-  if (atomicOr(&bm1[s >> 5], bit) & bit) return;
-  claim_counts(bm2, bm3, bm4, nocc, jm, s);
-}
-// The caller knows that it brings the first sample of s.
-__device__ __forceinline__ void claim_new(uint32_t* bm1, uint32_t* bm2, uint32_t* bm3, uint32_t* bm4,
-                                          uint32_t (*nocc)[8][4], uint32_t jm, uint32_t s) {
-  atomicOr(&bm1[s >> 5], 1u << (s & 31));
-  claim_counts(bm2, bm3, bm4, nocc, jm, s);
-}
-
 // ------------------------------------------------------------ leaf kernel
 //
 // A work item is one leaf and one of its 8 child cells (8 micro-buckets), so
@@ -285,19 +252,24 @@ __device__ __forceinline__ void claim_new(uint32_t* bm1, uint32_t* bm2, uint32_t
 // with one 64-bit LDS atomic per point:
 //   average: acc[cell] += R | G << 16 | B << 32 | 1 << 48.  The 16-bit fields
 //            are exact while a cell holds at most 257 samples (255 * 257 <
-//            2^16); the add that takes a cell past 257 flags the
-//            micro-bucket, which is then redone with exact 64-bit sums.
+//            2^16); overflowing fields only carry upward, so a cell with
+//            more samples shows a count above 257 (see below).
 //   pick:    acc[cell] = min/max of the sample's order key, whose low 32 bits
 //            are the point id; the winner then replaces it by its colour and
 //            id (ids are unique, so no other point can match afterwards).
-// The first sample of a cell claims it in an occupancy bitmask per depth
-// (depth 1: 4096 cells, 2: 512, 3: 64, 4: 8 per micro-bucket) and counts it
-// for its quarter of the cells, so that every list position is a prefix over
-// counters and bits, without further passes.  The emission (thread t owns
-// depth-1 cells 16t .. 16t+15, i.e. depth-2 cells 2t and 2t+1) writes the
-// depth-1 voxels and reduces them upward through registers and wave
-// shuffles: depth 2 in the thread, depth 3 over 4 lanes, depth 4 over 32
-// lanes.  Depth 5 (the micro-bucket) and 6 (the item) are reduced at the end.
+// Every sample also sets its cell's bit in an occupancy bitmask of the 4096
+// depth-1 cells (two masks alternate between micro-buckets, so one is
+// cleared while the other fills).  After the barrier every wave reads the
+// whole mask and derives by ballots the occupied cells of each depth (a
+// depth-2 cell is a nonzero byte, a depth-3 cell a nonzero pair of words, a
+// depth-4 cell eight of those) in the earlier waves' quarters and in total,
+// so that all list positions follow without any counting during the
+// accumulation.  The emission (thread t owns depth-1 cells 16t .. 16t+15,
+// i.e. depth-2 cells 2t and 2t+1) writes the depth-1 voxels and reduces them
+// upward through registers and wave shuffles: depth 2 in the thread, depth 3
+// over 4 lanes, depth 4 over 32 lanes.  Depth 5 (the micro-bucket) and 6 (the
+// item) are reduced at the end.  An average cell seen with more than 257
+// samples sends its micro-bucket to a second, exact round.
 // Depth-1 lists go to T1 at the item's first point (never more voxels than
 // points), the coarse lists to the item's block in T2.  icnt receives the 6
 // list lengths and iself the depth-6 voxel (colour, id) of every item.
@@ -312,21 +284,21 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
                                                                           uint32_t* __restrict__ icnt,
                                                                           uint64_t* __restrict__ iself, uint32_t seed) {
   __shared__ uint64_t acc[kSubCells];
-  __shared__ uint32_t bm1[kSubCells / 32], bm2[16], bm3[2], bm4[8];
-  __shared__ uint32_t nocc[4][8][4];  // [depth - 1][micro-bucket][quarter]: occupied cells
-  __shared__ uint32_t over[8];        // a cell of the micro-bucket passed 257 samples
-  __shared__ uint64_t k4ok[8][8];     // depth-4 voxels of each micro-bucket: pick key and colour
+  __shared__ uint32_t bm1[2][kSubCells / 32];  // depth-1 occupancy, alternating between micro-buckets
+  __shared__ uint32_t over[8];                 // a cell of the micro-bucket passed 257 samples
+  __shared__ uint32_t k4m[8];                  // occupied depth-4 cells of each micro-bucket
+  __shared__ uint64_t k4ok[8][8];              // depth-4 voxels of each micro-bucket: pick key and colour
   __shared__ uint32_t k4col[8][8];
   const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
   const ItemDesc& sd = desc[blockIdx.x];  // uniform: scalar loads
   const uint64_t init = MODE == 1 ? ~0ull : 0ull;
   for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
-  if (t < kSubCells / 32) bm1[t] = 0;
-  if (t < 16) bm2[t] = 0;
-  if (t < 2) bm3[t] = 0;
-  if (t < 128) nocc[t >> 5][(t >> 2) & 7][t & 3] = 0;
+  if (t < kSubCells / 32) {
+    bm1[0][t] = 0;
+    bm1[1][t] = 0;
+  }
   if (t < 8) {
-    bm4[t] = 0;
+    k4m[t] = 0;
     over[t] = 0;
   }
   const uint32_t P = sd.P;
@@ -340,7 +312,10 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   const uint64_t lkey = sd.lkey, t2b = sd.t2;
   const uint32_t sub_bit = 15u - lvl;  // bit level of the depth-1 cells (level lvl + 6)
   const uint32_t cb3 = coarse_base(3, P), cb4 = coarse_base(4, P), cb5 = coarse_base(5, P), cb6 = coarse_base(6, P);
+  const uint64_t below = (1ull << l) - 1;               // lanes under this one
+  const uint64_t earlier = (1ull << (16 * w)) - 1;      // lanes 0 .. 16w-1: the words of earlier waves
   uint32_t base1 = 0, base2 = 0, base3 = 0, base4 = 0;  // list lengths so far
+  uint32_t nproc = 0;                                   // micro-buckets emitted so far (bitmask alternation)
   for (uint32_t P0 = I0; P0 < I1; P0 += kLeafPass) {
     const uint32_t P1 = min(P0 + kLeafPass, I1);
     uint32_t cell[kLeafSlots], col[kLeafSlots], pid[kLeafSlots];
@@ -372,7 +347,10 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
       if (cnt == 0) continue;
       if (off >= P1 || off + cnt <= P0) continue;  // no points in this pass
       const bool wide = MODE == 0 && cnt > kPackedMax;
+      uint32_t* occ = bm1[nproc & 1];
       if (!wide) {
+        // every sample: one LDS reduction on its cell and one occupancy bit
+        // (no returned values, so nothing waits)
 #pragma unroll
         for (uint32_t k = 0; k < kLeafSlots; ++k) {
           // keep the per-slot work inside the loop over micro-buckets (hoisted
@@ -383,68 +361,17 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
           if (MODE == 0) {
             const uint64_t packed = (uint64_t)(col[k] & 0xff) | ((uint64_t)((col[k] >> 8) & 0xff) << 16) |
                                     ((uint64_t)((col[k] >> 16) & 0xff) << 32) | (1ull << 48);
-            const uint64_t old = atomicAdd((unsigned long long*)&acc[sc], (unsigned long long)packed);
-            if ((old >> 48) == 257) over[jm] = 1;
-            // the count field is nonzero after any add (and cannot wrap below
-            // 2^16 samples): a zero old value marks the cell's first sample
-            if (old == 0) claim_new(bm1, bm2, bm3, bm4, nocc, jm, sc);
+            atomicAdd((unsigned long long*)&acc[sc], (unsigned long long)packed);
           } else {
             const uint64_t ok = pick_order(pid[k], seed, MODE == 2);
             if (MODE == 1) atomicMin((unsigned long long*)&acc[sc], (unsigned long long)ok);
             else atomicMax((unsigned long long*)&acc[sc], (unsigned long long)ok);
-            claim_cell(bm1, bm2, bm3, bm4, nocc, jm, sc);
           }
+          atomicOr(&occ[sc >> 5], 1u << (sc & 31));
         }
       }
       if (off + cnt > P1) break;  // continues in the next pass
       lds_barrier();
-      const bool redo = wide || (MODE == 0 && over[jm]);
-      if (redo) {
-        // exact 64-bit sums over windows of 512 cells, re-reading the points;
-        // occupancy is rebuilt in the first window, and the floored colours
-        // are kept in the upper half of acc
-        if (t < kSubCells / 32) bm1[t] = 0;
-        if (t < 16) {
-          bm2[t] = 0;
-          nocc[t >> 2][jm][t & 3] = 0;
-        }
-        if (t < 2) bm3[t] = 0;
-        if (t == 0) bm4[jm] = 0;
-        uint64_t* wr = acc;
-        uint64_t* wg = acc + 512;
-        uint64_t* wb = acc + 1024;
-        uint64_t* wn = acc + 1536;
-        uint32_t* colw = (uint32_t*)(acc + 2048);
-        for (uint32_t w0 = 0; w0 < kSubCells; w0 += 512) {
-          for (uint32_t i = t; i < 2048; i += kLeafWG) acc[i] = 0;
-          lds_barrier();
-          for (uint32_t i = t; i < cnt; i += kLeafWG) {
-            const uint4 v = pts[off + i];
-            const uint32_t sc = point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, sub_bit, 4);
-            if (w0 == 0) claim_cell(bm1, bm2, bm3, bm4, nocc, jm, sc);
-            if (sc >= w0 && sc < w0 + 512) {
-              const uint32_t q = sc - w0;
-              atomicAdd((unsigned long long*)&wr[q], (unsigned long long)(v.w & 0xff));
-              atomicAdd((unsigned long long*)&wg[q], (unsigned long long)((v.w >> 8) & 0xff));
-              atomicAdd((unsigned long long*)&wb[q], (unsigned long long)((v.w >> 16) & 0xff));
-              atomicAdd((unsigned long long*)&wn[q], 1ull);
-            }
-          }
-          lds_barrier();
-          for (uint32_t q = t; q < 512; q += kLeafWG) {
-            const uint64_t c = wn[q];
-            if (c) {
-              // sums below 2^40 and counts below 2^32 are exact in double; the
-              // quotient (<= 255) is at least 2^-32 from the next integer when
-              // it is not one, far above the rounding error: floor is exact
-              const double dc = (double)c;
-              colw[w0 + q] = (uint32_t)((double)wr[q] / dc) | ((uint32_t)((double)wg[q] / dc) << 8) |
-                             ((uint32_t)((double)wb[q] / dc) << 16) | (255u << 24);
-            }
-          }
-          lds_barrier();
-        }
-      }
       if (MODE != 0) {
         // the winner of every cell deposits its colour beside its id
         if (off >= P0) {
@@ -465,104 +392,185 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         }
         lds_barrier();
       }
-      // ---- emission of this micro-bucket at depths 1..4
-      uint32_t qb[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};
-#pragma unroll
-      for (uint32_t d = 0; d < 4; ++d)
-#pragma unroll
-        for (uint32_t qq = 0; qq < 4; ++qq) {
-          const uint32_t a = nocc[d][jm][qq];
-          if (qq < w) qb[d] += a;
-          tot[d] += a;
-        }
       const uint32_t rel5 = (grp << 3) | jm;  // micro-bucket within the leaf (6 bits)
-      // depth 1: cells 16t .. 16t + 15
-      const uint32_t word = bm1[t >> 1];
-      uint32_t m = (t & 1) ? (word >> 16) : (word & 0xffffu);
-      if ((t & 1) == 0) bm1[t >> 1] = 0;
-      if (t < 16) bm2[t] = 0;
-      if (t < 2) bm3[t] = 0;
-      uint32_t pos = base1 + qb[0] + wave_prefix_small<5>((uint32_t)__popc(m));
-      Smp<MODE> h0 = smp_empty<MODE>(), h1 = smp_empty<MODE>();
-      const uint32_t* colw = (const uint32_t*)(acc + 2048);
-      while (m) {
-        const uint32_t b = (uint32_t)(__ffs(m) - 1);
-        m &= m - 1;
-        const uint32_t s = 16 * t + b;
-        uint32_t rgba, id = 0;
-        if (MODE == 0) {
-          if (redo) {
-            rgba = colw[s];
-          } else {
-            const uint64_t a = acc[s];
-            acc[s] = init;
-            rgba = mean_rgba((uint32_t)(a & 0xffffu), (uint32_t)((a >> 16) & 0xffffu), (uint32_t)((a >> 32) & 0xffffu),
-                             (uint32_t)(a >> 48));
+      // Emission at depths 1..4, run once, or twice when an average cell
+      // overflowed the packed sums (second round: exact colours of the wide
+      // accumulation).  The occupancy bits are exact in both rounds, so the
+      // second round rewrites the same positions.
+      bool redo = wide;
+      uint32_t tot1 = 0, tot2 = 0, tot3 = 0, tot4 = 0;
+      for (int round = wide ? 1 : 0; round < 2; ++round) {
+        if (round == 1) {
+          if (!redo) break;
+          // exact 64-bit sums over windows of 512 cells, re-reading the points;
+          // the floored colours are kept in the upper half of acc
+          uint64_t* wr = acc;
+          uint64_t* wg = acc + 512;
+          uint64_t* wb = acc + 1024;
+          uint64_t* wn = acc + 1536;
+          uint32_t* colw = (uint32_t*)(acc + 2048);
+          for (uint32_t w0 = 0; w0 < kSubCells; w0 += 512) {
+            for (uint32_t i = t; i < 2048; i += kLeafWG) acc[i] = 0;
+            lds_barrier();
+            for (uint32_t i = t; i < cnt; i += kLeafWG) {
+              const uint4 v = pts[off + i];
+              const uint32_t sc = point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, sub_bit, 4);
+              if (w0 == 0) atomicOr(&occ[sc >> 5], 1u << (sc & 31));
+              if (sc >= w0 && sc < w0 + 512) {
+                const uint32_t q = sc - w0;
+                atomicAdd((unsigned long long*)&wr[q], (unsigned long long)(v.w & 0xff));
+                atomicAdd((unsigned long long*)&wg[q], (unsigned long long)((v.w >> 8) & 0xff));
+                atomicAdd((unsigned long long*)&wb[q], (unsigned long long)((v.w >> 16) & 0xff));
+                atomicAdd((unsigned long long*)&wn[q], 1ull);
+              }
+            }
+            lds_barrier();
+            for (uint32_t q = t; q < 512; q += kLeafWG) {
+              const uint64_t c = wn[q];
+              if (c) {
+                // sums below 2^40 and counts below 2^32 are exact in double; the
+                // quotient (<= 255) is at least 2^-32 from the next integer when
+                // it is not one, far above the rounding error: floor is exact
+                const double dc = (double)c;
+                colw[w0 + q] = (uint32_t)((double)wr[q] / dc) | ((uint32_t)((double)wg[q] / dc) << 8) |
+                               ((uint32_t)((double)wb[q] / dc) << 16) | (255u << 24);
+              }
+            }
+            lds_barrier();
           }
-        } else {
-          const uint64_t a = acc[s];
-          acc[s] = init;
-          rgba = (uint32_t)(a >> 32);
-          id = (uint32_t)a;
-          T1id[I0 + pos] = id;
         }
-        T1[I0 + pos] = make_voxel(anc_code(lkey, 1, (rel5 << 12) | s), rgba);
-        ++pos;
-        if (b < 8) smp_add<MODE>(h0, rgba, id, seed);
-        else smp_add<MODE>(h1, rgba, id, seed);
-      }
-      // depth 2: cells 2t, 2t + 1
-      pos = base2 + qb[1] + wave_prefix_small<2>((h0.n ? 1u : 0u) + (h1.n ? 1u : 0u));
-      Smp<MODE> g3 = smp_empty<MODE>();
+        // positions: every wave reads the whole depth-1 bitmask (lane l: words
+        // 2l, 2l+1) and derives, by ballots, the occupied cells of each depth
+        // in the earlier waves' quarters and in total
+        const uint32_t wa = occ[2 * l], wb2 = occ[2 * l + 1];
+        const uint32_t c1l = (uint32_t)__popc(wa) + (uint32_t)__popc(wb2);  // depth-1 cells, 0..64
+        auto nzb = [](uint32_t x) {  // nonzero bytes: occupied depth-2 cells of a word
+          uint32_t y = x | (x >> 4);
+          y |= y >> 2;
+          y |= y >> 1;
+          return (uint32_t)__popc(y & 0x01010101u);
+        };
+        const uint32_t c2l = nzb(wa) + nzb(wb2);  // 0..8
+        const uint64_t b3 = __ballot((wa | wb2) != 0u);  // bit l: depth-3 cell l occupied
+        uint32_t cross1 = 0, cross2 = 0;
+        tot1 = tot2 = 0;
 #pragma unroll
-      for (uint32_t e = 0; e < 2; ++e) {
-        const Smp<MODE>& h = e ? h1 : h0;
-        if (h.n) {
-          const uint32_t rgba = smp_rgba<MODE>(h), id = (uint32_t)h.ok;
-          T2[t2b + pos] = make_voxel(anc_code(lkey, 2, (rel5 << 9) | (2 * t + e)), rgba);
-          if (MODE) T2id[t2b + pos] = id;
+        for (int b = 0; b < 7; ++b) {
+          const uint64_t bal = __ballot((c1l >> b) & 1u);
+          cross1 += (uint32_t)__popcll(bal & earlier) << b;
+          tot1 += (uint32_t)__popcll(bal) << b;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const uint64_t bal = __ballot((c2l >> b) & 1u);
+          cross2 += (uint32_t)__popcll(bal & earlier) << b;
+          tot2 += (uint32_t)__popcll(bal) << b;
+        }
+        uint32_t m4 = 0;  // occupied depth-4 cells (a depth-4 cell is 8 depth-3 cells)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m4 |= ((b3 >> (8 * q)) & 0xffu) ? (1u << q) : 0u;
+        const uint32_t cross3 = (uint32_t)__popcll(b3 & earlier);
+        tot3 = (uint32_t)__popcll(b3);
+        const uint32_t cross4 = (uint32_t)__popc(m4 & ((1u << (2 * w)) - 1u));
+        tot4 = (uint32_t)__popc(m4);
+        // depth 1: cells 16t .. 16t + 15 (the half word t & 1 of word t >> 1)
+        const uint32_t word = occ[t >> 1];
+        uint32_t m = (t & 1) ? (word >> 16) : (word & 0xffffu);
+        uint32_t pos = base1 + cross1 + wave_prefix_small<5>((uint32_t)__popc(m));
+        Smp<MODE> h0 = smp_empty<MODE>(), h1 = smp_empty<MODE>();
+        const uint32_t* colw = (const uint32_t*)(acc + 2048);
+        bool ovf = false;
+        while (m) {
+          const uint32_t b = (uint32_t)(__ffs(m) - 1);
+          m &= m - 1;
+          const uint32_t sc = 16 * t + b;
+          uint32_t rgba, id = 0;
+          if (MODE == 0) {
+            if (round == 1) {
+              rgba = colw[sc];
+            } else {
+              const uint64_t a = acc[sc];
+              acc[sc] = init;
+              const uint32_t c = (uint32_t)(a >> 48);
+              // the 16-bit fields are exact up to 257 samples; a larger
+              // observed count (carries only add to it) sends the
+              // micro-bucket to the exact round
+              ovf |= c > 257;
+              rgba = mean_rgba((uint32_t)(a & 0xffffu), (uint32_t)((a >> 16) & 0xffffu),
+                               (uint32_t)((a >> 32) & 0xffffu), c);
+            }
+          } else {
+            const uint64_t a = acc[sc];
+            acc[sc] = init;
+            rgba = (uint32_t)(a >> 32);
+            id = (uint32_t)a;
+            T1id[I0 + pos] = id;
+          }
+          T1[I0 + pos] = make_voxel(anc_code(lkey, 1, (rel5 << 12) | sc), rgba);
           ++pos;
-          smp_add<MODE>(g3, rgba, id, seed);
+          if (b < 8) smp_add<MODE>(h0, rgba, id, seed);
+          else smp_add<MODE>(h1, rgba, id, seed);
         }
-      }
-      // depth 3: cell t / 4, over lanes 4q .. 4q + 3
-      smp_xor<MODE>(g3, 1);
-      smp_xor<MODE>(g3, 2);
-      const bool lead3 = (l & 3) == 0;
-      pos = base3 + qb[2] + wave_prefix_small<1>((lead3 && g3.n) ? 1u : 0u);
-      Smp<MODE> g4 = smp_empty<MODE>();
-      if (g3.n) {
-        const uint32_t rgba = smp_rgba<MODE>(g3), id = (uint32_t)g3.ok;
-        if (lead3) {
-          T2[t2b + cb3 + pos] = make_voxel(anc_code(lkey, 3, (rel5 << 6) | (t >> 2)), rgba);
-          if (MODE) T2id[t2b + cb3 + pos] = id;
+        if (MODE == 0 && ovf) over[jm] = 1;
+        // depth 2: cells 2t, 2t + 1
+        pos = base2 + cross2 + wave_prefix_small<2>((h0.n ? 1u : 0u) + (h1.n ? 1u : 0u));
+        Smp<MODE> g3 = smp_empty<MODE>();
+#pragma unroll
+        for (uint32_t e = 0; e < 2; ++e) {
+          const Smp<MODE>& h = e ? h1 : h0;
+          if (h.n) {
+            const uint32_t rgba = smp_rgba<MODE>(h), id = (uint32_t)h.ok;
+            T2[t2b + pos] = make_voxel(anc_code(lkey, 2, (rel5 << 9) | (2 * t + e)), rgba);
+            if (MODE) T2id[t2b + pos] = id;
+            ++pos;
+            smp_add<MODE>(g3, rgba, id, seed);
+          }
         }
-        smp_add<MODE>(g4, rgba, id, seed);
+        // depth 3: cell t / 4, over lanes 4q .. 4q + 3
+        smp_xor<MODE>(g3, 1);
+        smp_xor<MODE>(g3, 2);
+        const bool lead3 = (l & 3) == 0;
+        pos = base3 + cross3 + (uint32_t)__popcll(__ballot(lead3 && g3.n) & below);
+        Smp<MODE> g4 = smp_empty<MODE>();
+        if (g3.n) {
+          const uint32_t rgba = smp_rgba<MODE>(g3), id = (uint32_t)g3.ok;
+          if (lead3) {
+            T2[t2b + cb3 + pos] = make_voxel(anc_code(lkey, 3, (rel5 << 6) | (t >> 2)), rgba);
+            if (MODE) T2id[t2b + cb3 + pos] = id;
+          }
+          smp_add<MODE>(g4, rgba, id, seed);
+        }
+        // depth 4: cell t / 32, over the 8 groups of 4 lanes of a half-wave (the
+        // 4 lanes of a group hold the same depth-3 voxel: one lane per group
+        // takes part in each exchange)
+        smp_xor<MODE>(g4, 4);
+        smp_xor<MODE>(g4, 8);
+        smp_xor<MODE>(g4, 16);
+        const bool lead4 = (l & 31) == 0;
+        pos = base4 + cross4 + (uint32_t)__popcll(__ballot(lead4 && g4.n) & below);
+        if (lead4 && g4.n) {
+          const uint32_t rgba = smp_rgba<MODE>(g4), id = (uint32_t)g4.ok;
+          T2[t2b + cb4 + pos] = make_voxel(anc_code(lkey, 4, (rel5 << 3) | (t >> 5)), rgba);
+          if (MODE) T2id[t2b + cb4 + pos] = id;
+          k4col[jm][t >> 5] = rgba;
+          k4ok[jm][t >> 5] = g4.ok;
+        }
+        if (t == 0) k4m[jm] = m4;
+        // the other bitmask (the previous micro-bucket's, read by every wave
+        // before the last barrier) is cleared for the next one
+        if (t < kSubCells / 32) bm1[(nproc + 1) & 1][t] = 0;
+        lds_barrier();
+        if (MODE == 0 && round == 0) redo = over[jm] != 0;
       }
-      // depth 4: cell t / 32, over the 8 groups of 4 lanes of a half-wave (the
-      // 4 lanes of a group hold the same depth-3 voxel: one lane per group
-      // takes part in each exchange)
-      smp_xor<MODE>(g4, 4);
-      smp_xor<MODE>(g4, 8);
-      smp_xor<MODE>(g4, 16);
-      const bool lead4 = (l & 31) == 0;
-      pos = base4 + qb[3] + wave_prefix_small<1>((lead4 && g4.n) ? 1u : 0u);
-      if (lead4 && g4.n) {
-        const uint32_t rgba = smp_rgba<MODE>(g4), id = (uint32_t)g4.ok;
-        T2[t2b + cb4 + pos] = make_voxel(anc_code(lkey, 4, (rel5 << 3) | (t >> 5)), rgba);
-        if (MODE) T2id[t2b + cb4 + pos] = id;
-        k4col[jm][t >> 5] = rgba;
-        k4ok[jm][t >> 5] = g4.ok;
-      }
-      base1 += tot[0];
-      base2 += tot[1];
-      base3 += tot[2];
-      base4 += tot[3];
-      lds_barrier();
       if (redo) {
         for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
         lds_barrier();
       }
+      base1 += tot1;
+      base2 += tot2;
+      base3 += tot3;
+      base4 += tot4;
+      ++nproc;
     }
   }
   // ---- depth 5 (the micro-buckets) and 6 (the item), from the depth-4
@@ -570,7 +578,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   if (w == 0) {
     Smp<MODE> s5 = smp_empty<MODE>();
     if (t < 8) {
-      const uint32_t m4 = bm4[t];
+      const uint32_t m4 = k4m[t];
       for (uint32_t c = 0; c < 8; ++c)
         if ((m4 >> c) & 1u) smp_add<MODE>(s5, k4col[t][c], (uint32_t)k4ok[t][c], seed);
     }

@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -70,14 +71,23 @@ static void fail(lod_status st, const char* msg) {
 namespace {
 
 // Grow-only scratch buffer owned by a workspace.
+// Grow-only scratch buffer owned by a workspace.  A block outgrown during a
+// build may still be read by kernels queued on the build's stream, and the
+// device cache is shared by every thread (the server builds on several
+// streams at once), so outgrown blocks are retired to the workspace and only
+// returned to the cache once the build's stream has drained.
 struct Scratch {
   void* p = nullptr;
   size_t cap = 0;
+  std::vector<void*>* retired = nullptr;
   template <typename T>
   T* get(int dev, size_t count) {
     size_t bytes = count * sizeof(T);
     if (bytes > cap) {
-      cache().release(dev, p);
+      if (p) {
+        if (retired) retired->push_back(p);
+        else cache().release(dev, p);
+      }
       p = cache().alloc(dev, bytes);
       cap = bytes;
     }
@@ -126,19 +136,31 @@ struct Workspace {
   Scratch t2, t2id, icnt, idesc, iself, v_sz, v_dfs, v_dfsn, v_psize, v_poff, v_selfc, v_selfid;
   Scratch state, bstate, clouds, trees, nbeg;
   Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs;
+  std::vector<void*> retired;  // outgrown blocks, released when the build's stream has drained
   hipEvent_t ev[16] = {};
   bool ev_ready = false;
+  std::vector<Scratch*> scratches() {
+    return {&X,       &Xid,     &bbox,    &cube,    &segs,     &chunks,  &counters, &hist,    &grids,
+            &pool,    &pool2,   &refine,  &leaf_refine, &groups, &gsum,     &n_level, &n_leaf,  &n_mask,
+            &n_key,   &n_npts,  &n_count, &n_first, &n_off,    &n_cover, &n_grid,   &n_parent, &n_tree,
+            &c_level, &c_leaf,  &c_mask,  &c_key,   &c_npts,   &c_count, &c_first,  &c_off,   &c_cover,
+            &c_grid,  &c_parent, &c_tree, &t2,      &t2id,     &icnt,    &idesc,    &iself,   &v_sz,
+            &v_dfs,   &v_dfsn,  &v_psize, &v_poff,  &v_selfc,  &v_selfid, &state,   &bstate,  &clouds,
+            &trees,   &nbeg};
+  }
+  Workspace() {
+    for (Scratch* sc : scratches()) sc->retired = &retired;
+  }
+  // only once nothing queued by the last build can still touch them
+  void flush_retired() {
+    for (void* q : retired) cache().release(dev, q);
+    retired.clear();
+  }
   ~Workspace() {
     if (ev_ready)
       for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
-    Scratch* all[] = {&X,       &Xid,     &bbox,    &cube,    &segs,     &chunks,  &counters, &hist,    &grids,
-                      &pool,    &pool2,   &refine,  &leaf_refine, &groups, &gsum,     &n_level, &n_leaf,  &n_mask,
-                      &n_key,   &n_npts,  &n_count, &n_first, &n_off,    &n_cover, &n_grid,   &n_parent, &n_tree,
-                      &c_level, &c_leaf,  &c_mask,  &c_key,   &c_npts,   &c_count, &c_first,  &c_off,   &c_cover,
-                      &c_grid,  &c_parent, &c_tree, &t2,      &t2id,     &icnt,    &idesc,    &iself,   &v_sz,
-                      &v_dfs,   &v_dfsn,  &v_psize, &v_poff,  &v_selfc,  &v_selfid, &state,   &bstate,  &clouds,
-                      &trees,   &nbeg};
-    for (Scratch* s : all) s->drop(dev);
+    flush_retired();
+    for (Scratch* sc : scratches()) sc->drop(dev);
   }
 };
 
@@ -161,6 +183,7 @@ Workspace* acquire_ws(int dev) {
 }
 
 void release_ws(Workspace* w) {
+  w->flush_retired();
   std::lock_guard<std::mutex> g(g_ws_mu);
   g_ws_free.push_back(w);
 }
@@ -169,6 +192,21 @@ struct WsGuard {
   Workspace* w;
   explicit WsGuard(int dev) : w(acquire_ws(dev)) {}
   ~WsGuard() { release_ws(w); }
+};
+
+// When a build ends by an exception, kernels may still be queued on its
+// stream: drain it before device memory goes back to the shared cache
+// (declared after the owners of that memory, so it runs first).
+struct DrainOnUnwind {
+  hipStream_t s;
+  int pending;
+  explicit DrainOnUnwind(hipStream_t st) : s(st), pending(std::uncaught_exceptions()) {}
+  ~DrainOnUnwind() {
+    if (std::uncaught_exceptions() > pending) {
+      (void)hipStreamSynchronize(s);
+      (void)hipGetLastError();
+    }
+  }
 };
 
 // Stage timer: events recorded on the build stream (no effect when disabled).
@@ -309,6 +347,7 @@ struct GridPool {
         HIPCHK(hipMemcpyAsync(nw, old, sizeof(GridDesc) * num_grids, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
         w.grids.drop(w.dev);
+        tmp.retired = w.grids.retired;
         w.grids = tmp;
         grids = nw;
       }
@@ -325,6 +364,7 @@ struct GridPool {
         HIPCHK(hipMemcpyAsync(nw, old, 4ull * used_words, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
         w.pool.drop(w.dev);
+        tmp.retired = w.pool.retired;
         w.pool = tmp;
         pool = nw;
       }
@@ -432,6 +472,7 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   // outputs that do not depend on the tree shapes
   std::shared_ptr<LodArena> arena = std::make_shared<LodArena>();
   arena->dev = dev;
+  DrainOnUnwind drain(s);
   lod_point* Y = arena->alloc<lod_point>(N);
   uint32_t* Yid = ids ? arena->alloc<uint32_t>(N) : nullptr;
   // scratch
