@@ -17,7 +17,10 @@ Beside it, on the same box and in the same run:
            of 50M-point tiles of the same generator) through lod_submit /
            lod_poll, reporting throughput and p50/p99 latency (completion
            minus scheduled arrival, including queueing and the host-to-device
-           copy), against the same requests built one by one.
+           copy), against the same requests built one by one;
+  full precision: the plain build again with a full-precision record (input
+           coordinates of the cell's accepted sample, voxel colour) for every
+           voxel of the lower levels.
 
 Prints one JSON line with the throughput (points/s), the roofline of the
 dominant kernel (algorithmic bytes per launch over its average duration,
@@ -273,6 +276,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400, help="requests of the served run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-tiles", type=int, default=4)
+    ap.add_argument("--full-precision-steps", type=int, default=5,
+                    help="builds of the same cloud with full-precision lower levels (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -347,6 +352,30 @@ def main():
     whole_alg = sum(stage_bytes(k, n, ids) for k in single)
     nodes, voxels = infos[-1]
 
+    full = None
+    if args.full_precision_steps > 0:
+        # same cloud and parameters, plus a full-precision record (accepted
+        # sample's coordinates, voxel colour) for every voxel
+        pf = lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling, timing=True,
+                             full_precision=True)
+
+        def fstep():
+            t = lod.lod_build(dev, params=pf, stream=stream)
+            tm = t.timings()
+            t.free()
+            return tm
+
+        fstep()
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        ftm = [fstep() for _ in range(args.full_precision_steps)]
+        torch.cuda.synchronize()
+        fms = 1e3 * (time.perf_counter() - f0) / args.full_precision_steps
+        full = {"ms_per_build": round(fms, 4), "points_per_s": round(n / (fms * 1e-3), 1),
+                "vs_plain": round(fms / ms_per_step, 3), "steps": args.full_precision_steps,
+                "leaf_voxels_ms": round(float(np.mean([t["leaf_voxels"] for t in ftm])), 4),
+                "levels_ms": round(float(np.mean([t["levels"] for t in ftm])), 4)}
+
     cpu = None
     if args.cpu_sample > 0:
         import oracle
@@ -392,6 +421,7 @@ def main():
         "whole_build_alg_GBps": round(whole_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "nodes": nodes,
         "voxels": voxels,
+        "full_precision": full,
         "batched": batched,
         "served": served,
     }

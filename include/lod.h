@@ -73,7 +73,16 @@ typedef enum { LOD_AVERAGE = 0, LOD_PICK_FIRST = 1, LOD_PICK_RANDOM = 2 } lod_sa
 
 enum {
   LOD_FLAG_POINT_IDS = 1, /* keep each leaf point's input index (implied by pick modes) */
-  LOD_FLAG_TIMING = 2     /* record HIP events around every stage (lod_tree_timings) */
+  LOD_FLAG_TIMING = 2,    /* record HIP events around every stage (lod_tree_timings) */
+  /* Full-precision samples in the lower levels of detail (Sec. 7): besides the
+   * quantised voxel cells, every inner-node sample is also given as a 16-byte
+   * record with the input coordinates of an accepted sample of its cell and
+   * the voxel's colour (voxel_points).  Pick modes accept the picked sample;
+   * LOD_AVERAGE accepts the sample with the smallest input index in the cell
+   * (the arg-min over all points of the subtree that fall in the cell) and
+   * keeps the averaged colour.  voxel_ids then holds the accepted sample's
+   * index in every mode. */
+  LOD_FLAG_FULL_PRECISION = 4
 };
 
 typedef struct {
@@ -122,7 +131,8 @@ typedef struct {
   const lod_point* points;
   const uint32_t* point_ids;   /* NULL unless ids were kept */
   const lod_voxel* voxels;
-  const uint32_t* voxel_ids;   /* pick modes only, else NULL */
+  const uint32_t* voxel_ids;      /* pick modes, or with LOD_FLAG_FULL_PRECISION; else NULL */
+  const lod_point* voxel_points;  /* with LOD_FLAG_FULL_PRECISION, else NULL */
 } lod_tree_view;
 
 /* Default parameters (T = 50000, max_level = 12, AVERAGE). */

@@ -142,9 +142,46 @@ def point_hash(ids, seed: int) -> np.ndarray:
 
 
 def build(points, leaf_cap: int = 50000, max_level: int = 12, sampling: int = AVERAGE, seed: int = 0,
-          cube_lo=None, cube_side: float | None = None) -> dict:
+          cube_lo=None, cube_side: float | None = None, full_precision: bool = False) -> dict:
     """Build the octree; returns numpy arrays (see lod_oracle.h for meaning).
-    With cube_lo/cube_side the cube is given instead of computed from the points."""
+    With cube_lo/cube_side the cube is given instead of computed from the points.
+    full_precision adds "voxel_ids" and "voxel_points" (see full_precision_points)."""
+    t = _build(points, leaf_cap, max_level, sampling, seed, cube_lo, cube_side)
+    if full_precision:
+        t = full_precision_points(points, t, leaf_cap, max_level, sampling, seed, cube_lo, cube_side)
+    return t
+
+
+def full_precision_points(points, tree: dict, leaf_cap: int, max_level: int, sampling: int, seed: int,
+                          cube_lo=None, cube_side: float | None = None) -> dict:
+    """Full-precision samples of the lower levels (Sec. 7, Discussion).
+
+    The pick modes keep the picked point itself: its input coordinates, with
+    quantization switched off.  For the average, the cell's accepted sample
+    is the one a first-come pass accepts (Sec. 4.2.1, made order-independent
+    as the smallest input index), and the record takes its coordinates with
+    the averaged colour.  The first-come voxel ids are those of the same tree
+    built with FIRST sampling (same nodes, same occupied cells).  Returns the
+    tree with "voxel_ids" and "voxel_points" ((num_voxels, 16) uint8 records
+    x, y, z float32 and r, g, b, a of the voxel)."""
+    raw = _as_records(points).view(np.uint8).reshape(-1, 16)
+    out = dict(tree)
+    if sampling == AVERAGE:
+        first = _build(points, leaf_cap, max_level, FIRST, seed, cube_lo, cube_side)
+        assert first["num_voxels"] == tree["num_voxels"]
+        ids = first["voxel_ids"]
+    else:
+        ids = tree["voxel_ids"]
+    if ids is None:
+        ids = np.zeros(0, np.uint32)
+    rec = raw[ids.astype(np.int64)].copy() if len(ids) else np.zeros((0, 16), np.uint8)
+    rec[:, 12:16] = tree["voxels"][:, 4:8]
+    out["voxel_ids"] = ids
+    out["voxel_points"] = rec
+    return out
+
+
+def _build(points, leaf_cap, max_level, sampling, seed, cube_lo, cube_side) -> dict:
     a = _as_records(points)
     n = a.shape[0]
     t = _Tree()

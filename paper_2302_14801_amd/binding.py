@@ -20,6 +20,7 @@ LOD_ERR_TOO_LARGE, LOD_ERR_UNKNOWN_TICKET, LOD_ERR_HIP = -5, -6, -7
 LOD_AVERAGE, LOD_PICK_FIRST, LOD_PICK_RANDOM = 0, 1, 2
 LOD_FLAG_POINT_IDS = 1
 LOD_FLAG_TIMING = 2
+LOD_FLAG_FULL_PRECISION = 4
 
 
 class LodError(RuntimeError):
@@ -43,7 +44,7 @@ class lod_tree_view(ctypes.Structure):
                 ("node_npoints", ctypes.c_void_p), ("node_count", ctypes.c_void_p),
                 ("node_first_child", ctypes.c_void_p), ("node_offset", ctypes.c_void_p),
                 ("points", ctypes.c_void_p), ("point_ids", ctypes.c_void_p),
-                ("voxels", ctypes.c_void_p), ("voxel_ids", ctypes.c_void_p)]
+                ("voxels", ctypes.c_void_p), ("voxel_ids", ctypes.c_void_p), ("voxel_points", ctypes.c_void_p)]
 
 
 class lod_timings(ctypes.Structure):
@@ -112,11 +113,12 @@ def _check(status: int):
 
 
 def make_params(leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0, keep_ids=False,
-                tune_levels0=0, tune_levels1=0, timing=False, tune_chunk=0) -> lod_params:
+                tune_levels0=0, tune_levels1=0, timing=False, tune_chunk=0, full_precision=False) -> lod_params:
     p = lod_params()
     load_library().lod_params_default(ctypes.byref(p))
     p.leaf_cap, p.max_level, p.sampling, p.seed = leaf_cap, max_level, sampling, seed
-    p.flags = (LOD_FLAG_POINT_IDS if keep_ids else 0) | (LOD_FLAG_TIMING if timing else 0)
+    p.flags = ((LOD_FLAG_POINT_IDS if keep_ids else 0) | (LOD_FLAG_TIMING if timing else 0)
+               | (LOD_FLAG_FULL_PRECISION if full_precision else 0))
     p.tune_levels0, p.tune_levels1, p.tune_chunk = tune_levels0, tune_levels1, tune_chunk
     return p
 
@@ -178,6 +180,7 @@ class Tree:
             "point_ids": _d2h(v.point_ids, np_, np.uint32) if v.point_ids else None,
             "voxels": _d2h(v.voxels, nv * 8, np.uint8).reshape(-1, 8),
             "voxel_ids": _d2h(v.voxel_ids, nv, np.uint32) if v.voxel_ids else None,
+            "voxel_points": _d2h(v.voxel_points, nv * 16, np.uint8).reshape(-1, 16) if v.voxel_points else None,
         }
         return out
 
@@ -210,9 +213,10 @@ def _d2h(ptr, count, dtype):
 # ---------------------------------------------------------------- C names
 
 def lod_build(points, leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0, keep_ids=False,
-              stream=None, params: lod_params | None = None) -> Tree:
+              stream=None, params: lod_params | None = None, full_precision=False) -> Tree:
     n = _check_points(points)
-    p = params if params is not None else make_params(leaf_cap, max_level, sampling, seed, keep_ids)
+    p = params if params is not None else make_params(leaf_cap, max_level, sampling, seed, keep_ids,
+                                                      full_precision=full_precision)
     out = ctypes.c_void_p()
     _check(load_library().lod_build(ctypes.c_void_p(points.data_ptr()), n, ctypes.byref(p),
                                     _stream_handle(stream), ctypes.byref(out)))
@@ -220,11 +224,12 @@ def lod_build(points, leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0
 
 
 def lod_build_batch(points, offsets, leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0,
-                    keep_ids=False, stream=None, params: lod_params | None = None) -> list:
+                    keep_ids=False, stream=None, params: lod_params | None = None, full_precision=False) -> list:
     _check_points(points)
     offs = np.ascontiguousarray(np.asarray(offsets, np.uint64))
     k = len(offs) - 1
-    p = params if params is not None else make_params(leaf_cap, max_level, sampling, seed, keep_ids)
+    p = params if params is not None else make_params(leaf_cap, max_level, sampling, seed, keep_ids,
+                                                      full_precision=full_precision)
     outs = (ctypes.c_void_p * max(k, 1))()
     _check(load_library().lod_build_batch(ctypes.c_void_p(points.data_ptr()),
                                           offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), k,

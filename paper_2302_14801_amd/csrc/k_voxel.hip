@@ -80,8 +80,14 @@ __device__ __forceinline__ uint32_t mean_rgba(uint32_t sr, uint32_t sg, uint32_t
   return floor_div(sr, r) | (floor_div(sg, r) << 8) | (floor_div(sb, r) << 16) | (255u << 24);
 }
 
-// Samples of one cell: channel sums and count (average), or the pick so far
-// (pick modes; n > 0 marks it valid).
+// Modes of the voxel stage: 0 average, 1 first, 2 random (the sampling
+// strategies), 3 average that also keeps the smallest sample id of every cell
+// (the accepted sample of a full-precision lower level).
+__host__ __device__ constexpr bool avg_mode(int m) { return m == 0 || m == 3; }
+
+// Samples of one cell: channel sums and count (average modes; mode 3 also the
+// smallest id, 2^32 - 1 while empty), or the pick so far (pick modes; n > 0
+// marks it valid).
 template <int MODE>
 struct Smp {
   uint32_t r, g, b, n;
@@ -92,7 +98,7 @@ template <int MODE>
 __device__ __forceinline__ Smp<MODE> smp_empty() {
   Smp<MODE> s;
   s.r = s.g = s.b = s.n = 0;
-  s.ok = 0;
+  s.ok = MODE == 3 ? 0xffffffffull : 0ull;
   s.col = 0;
   return s;
 }
@@ -103,10 +109,11 @@ __device__ __forceinline__ bool pick_better(uint64_t a, uint64_t b) {
 // one voxel (colour, id) as a sample
 template <int MODE>
 __device__ __forceinline__ void smp_add(Smp<MODE>& s, uint32_t rgba, uint32_t id, uint32_t seed) {
-  if (MODE == 0) {
+  if (avg_mode(MODE)) {
     s.r += rgba & 0xffu;
     s.g += (rgba >> 8) & 0xffu;
     s.b += (rgba >> 16) & 0xffu;
+    if (MODE == 3) s.ok = min(s.ok, (uint64_t)id);
   } else {
     const uint64_t k = pick_order(id, seed, MODE == 2);
     if (s.n == 0 || pick_better<MODE>(k, s.ok)) {
@@ -118,10 +125,11 @@ __device__ __forceinline__ void smp_add(Smp<MODE>& s, uint32_t rgba, uint32_t id
 }
 template <int MODE>
 __device__ __forceinline__ void smp_merge(Smp<MODE>& a, const Smp<MODE>& b) {
-  if (MODE == 0) {
+  if (avg_mode(MODE)) {
     a.r += b.r;
     a.g += b.g;
     a.b += b.b;
+    if (MODE == 3) a.ok = min(a.ok, b.ok);
   } else if (b.n && (a.n == 0 || pick_better<MODE>(b.ok, a.ok))) {
     a.ok = b.ok;
     a.col = b.col;
@@ -132,13 +140,14 @@ __device__ __forceinline__ void smp_merge(Smp<MODE>& a, const Smp<MODE>& b) {
 // (average: sums of at most 8 voxels, so two 16-bit fields share a word)
 template <int MODE>
 __device__ __forceinline__ void smp_xor(Smp<MODE>& s, int m) {
-  if (MODE == 0) {
+  if (avg_mode(MODE)) {
     const uint32_t rg = (uint32_t)__shfl_xor((int)(s.r | (s.g << 16)), m, 64);
     const uint32_t bn = (uint32_t)__shfl_xor((int)(s.b | (s.n << 16)), m, 64);
     s.r += rg & 0xffffu;
     s.g += rg >> 16;
     s.b += bn & 0xffffu;
     s.n += bn >> 16;
+    if (MODE == 3) s.ok = min(s.ok, (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)s.ok, m, 64));
   } else {
     Smp<MODE> o = smp_empty<MODE>();
     o.n = __shfl_xor(s.n, m, 64);
@@ -151,7 +160,7 @@ __device__ __forceinline__ void smp_xor(Smp<MODE>& s, int m) {
 // (sums of at most 8 voxels here), or the pick's colour
 template <int MODE>
 __device__ __forceinline__ uint32_t smp_rgba(const Smp<MODE>& s) {
-  if (MODE == 0) return mean_rgba(s.r, s.g, s.b, s.n);
+  if (avg_mode(MODE)) return mean_rgba(s.r, s.g, s.b, s.n);
   return s.col;
 }
 
@@ -257,6 +266,7 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nod
 //   pick:    acc[cell] = min/max of the sample's order key, whose low 32 bits
 //            are the point id; the winner then replaces it by its colour and
 //            id (ids are unique, so no other point can match afterwards).
+//   mode 3:  as average, plus a 32-bit LDS atomic min of the id per cell.
 // Every sample also sets its cell's bit in an occupancy bitmask of the 4096
 // depth-1 cells (two masks alternate between micro-buckets, so one is
 // cleared while the other fills).  After the barrier every wave reads the
@@ -273,7 +283,7 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nod
 // Depth-1 lists go to T1 at the item's first point (never more voxels than
 // points), the coarse lists to the item's block in T2.  icnt receives the 6
 // list lengths and iself the depth-6 voxel (colour, id) of every item.
-template <int MODE>  // 0 average, 1 first, 2 random
+template <int MODE>  // 0 average, 1 first, 2 random, 3 average with smallest ids
 __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(const ItemDesc* __restrict__ desc,
                                                                           const uint4* __restrict__ pts,
                                                                           const uint32_t* __restrict__ ids,
@@ -289,10 +299,13 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   __shared__ uint32_t k4m[8];                  // occupied depth-4 cells of each micro-bucket
   __shared__ uint64_t k4ok[8][8];              // depth-4 voxels of each micro-bucket: pick key and colour
   __shared__ uint32_t k4col[8][8];
+  __shared__ uint32_t minid[MODE == 3 ? kSubCells : 1];  // mode 3: smallest id of every depth-1 cell
   const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
   const ItemDesc& sd = desc[blockIdx.x];  // uniform: scalar loads
   const uint64_t init = MODE == 1 ? ~0ull : 0ull;
   for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
+  if (MODE == 3)
+    for (uint32_t i = t; i < kSubCells; i += kLeafWG) minid[i] = ~0u;
   if (t < kSubCells / 32) {
     bm1[0][t] = 0;
     bm1[1][t] = 0;
@@ -346,7 +359,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
       next += cnt;
       if (cnt == 0) continue;
       if (off >= P1 || off + cnt <= P0) continue;  // no points in this pass
-      const bool wide = MODE == 0 && cnt > kPackedMax;
+      const bool wide = avg_mode(MODE) && cnt > kPackedMax;
       uint32_t* occ = bm1[nproc & 1];
       if (!wide) {
         // every sample: one LDS reduction on its cell and one occupancy bit
@@ -358,10 +371,11 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
           asm volatile("" : "+v"(cell[k]), "+v"(col[k]));
           if ((cell[k] >> 12) != jm) continue;
           const uint32_t sc = cell[k] & (kSubCells - 1);
-          if (MODE == 0) {
+          if (avg_mode(MODE)) {
             const uint64_t packed = (uint64_t)(col[k] & 0xff) | ((uint64_t)((col[k] >> 8) & 0xff) << 16) |
                                     ((uint64_t)((col[k] >> 16) & 0xff) << 32) | (1ull << 48);
             atomicAdd((unsigned long long*)&acc[sc], (unsigned long long)packed);
+            if (MODE == 3) atomicMin(&minid[sc], pid[k]);
           } else {
             const uint64_t ok = pick_order(pid[k], seed, MODE == 2);
             if (MODE == 1) atomicMin((unsigned long long*)&acc[sc], (unsigned long long)ok);
@@ -372,7 +386,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
       }
       if (off + cnt > P1) break;  // continues in the next pass
       lds_barrier();
-      if (MODE != 0) {
+      if (!avg_mode(MODE)) {
         // the winner of every cell deposits its colour beside its id
         if (off >= P0) {
 #pragma unroll
@@ -415,7 +429,10 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
             for (uint32_t i = t; i < cnt; i += kLeafWG) {
               const uint4 v = pts[off + i];
               const uint32_t sc = point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, sub_bit, 4);
-              if (w0 == 0) atomicOr(&occ[sc >> 5], 1u << (sc & 31));
+              if (w0 == 0) {
+                atomicOr(&occ[sc >> 5], 1u << (sc & 31));
+                if (MODE == 3) atomicMin(&minid[sc], ids[off + i]);
+              }
               if (sc >= w0 && sc < w0 + 512) {
                 const uint32_t q = sc - w0;
                 atomicAdd((unsigned long long*)&wr[q], (unsigned long long)(v.w & 0xff));
@@ -485,7 +502,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
           m &= m - 1;
           const uint32_t sc = 16 * t + b;
           uint32_t rgba, id = 0;
-          if (MODE == 0) {
+          if (avg_mode(MODE)) {
             if (round == 1) {
               rgba = colw[sc];
             } else {
@@ -499,6 +516,11 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
               rgba = mean_rgba((uint32_t)(a & 0xffffu), (uint32_t)((a >> 16) & 0xffffu),
                                (uint32_t)((a >> 32) & 0xffffu), c);
             }
+            if (MODE == 3) {
+              id = minid[sc];
+              minid[sc] = ~0u;
+              T1id[I0 + pos] = id;
+            }
           } else {
             const uint64_t a = acc[sc];
             acc[sc] = init;
@@ -511,7 +533,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
           if (b < 8) smp_add<MODE>(h0, rgba, id, seed);
           else smp_add<MODE>(h1, rgba, id, seed);
         }
-        if (MODE == 0 && ovf) over[jm] = 1;
+        if (avg_mode(MODE) && ovf) over[jm] = 1;
         // depth 2: cells 2t, 2t + 1
         pos = base2 + cross2 + wave_prefix_small<2>((h0.n ? 1u : 0u) + (h1.n ? 1u : 0u));
         Smp<MODE> g3 = smp_empty<MODE>();
@@ -560,7 +582,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         // before the last barrier) is cleared for the next one
         if (t < kSubCells / 32) bm1[(nproc + 1) & 1][t] = 0;
         lds_barrier();
-        if (MODE == 0 && round == 0) redo = over[jm] != 0;
+        if (avg_mode(MODE) && round == 0) redo = over[jm] != 0;
       }
       if (redo) {
         for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
@@ -853,6 +875,28 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, u
   }
 }
 
+// ------------------------------------------------------------ full precision
+//
+// Full-precision samples of the lower levels (Sec. 7): the input coordinates
+// of every voxel's accepted sample with the voxel's colour, one thread per
+// voxel of the call.  The voxel's tree is the last one whose first voxel is
+// not after it (trees without voxels share their first voxel with the next).
+__global__ void __launch_bounds__(256) k_voxel_points(const uint64_t* __restrict__ vox, const uint32_t* __restrict__ vids,
+                                                      uint64_t vtotal, const TreeInfo* __restrict__ trees,
+                                                      const CloudInfo* __restrict__ clouds, uint32_t ntrees,
+                                                      const uint4* __restrict__ pts, uint4* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= vtotal) return;
+  uint32_t lo = 0, hi = ntrees - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (trees[mid].vbase <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint4 p = pts[(uint64_t)clouds[lo].start + vids[i]];
+  out[i] = make_uint4(p.x, p.y, p.z, (uint32_t)(vox[i] >> 32));
+}
+
 // ------------------------------------------------------------ launchers
 
 uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes) {
@@ -877,8 +921,12 @@ void launch_item_desc(const Nodes& nodes, uint32_t num_nodes, const GridDesc* gr
       constexpr int M = 1;             \
       BODY;                            \
     } break;                           \
-    default: {                         \
+    case 2: {                          \
       constexpr int M = 2;             \
+      BODY;                            \
+    } break;                           \
+    default: {                         \
+      constexpr int M = 3;             \
       BODY;                            \
     } break;                           \
   }
@@ -918,5 +966,12 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
   })
 }
 #undef LOD_MODE_SWITCH
+
+void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,
+                         const CloudInfo* clouds, uint32_t ntrees, const void* pts, void* out, hipStream_t s) {
+  if (!vtotal || !ntrees) return;
+  hipLaunchKernelGGL(k_voxel_points, dim3((uint32_t)((vtotal + 255) / 256)), dim3(256), 0, s, vox, vids, vtotal, trees,
+                     clouds, ntrees, (const uint4*)pts, (uint4*)out);
+}
 
 }  // namespace lod

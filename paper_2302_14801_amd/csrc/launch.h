@@ -64,6 +64,10 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
                          const TreeInfo* trees, const uint32_t* icnt, const void* desc, const uint64_t* T1,
                          const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
                          hipStream_t s);
+// Full-precision records (input coordinates of the accepted sample, voxel
+// colour) of the vtotal voxels of a call.
+void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,
+                         const CloudInfo* clouds, uint32_t ntrees, const void* pts, void* out, hipStream_t s);
 // Size of the coarse-list blocks of all work items, bounded from the node
 // count alone (for allocation before the item prefix is known).
 uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes);

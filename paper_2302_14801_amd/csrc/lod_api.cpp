@@ -249,8 +249,9 @@ namespace {
 struct Plan {
   uint32_t E0, E1;
   uint32_t chunk0, chunk1, chunk_ref;
-  uint32_t mode;
+  uint32_t mode;  // voxel-stage mode: the sampling strategy, or 3 (average with accepted ids)
   bool ids;
+  bool full;      // full-precision records of the voxels
 };
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -264,8 +265,9 @@ Plan make_plan(uint64_t n_typical, uint64_t n_total, const lod_params& p) {
   pl.E1 = n >= (4u << 20) ? 4 : (n >= (64u << 10) ? 3 : 2);
   if (p.tune_levels0) pl.E0 = std::min<uint32_t>(4, p.tune_levels0);
   if (p.tune_levels1) pl.E1 = std::min<uint32_t>(4, p.tune_levels1);
-  pl.mode = p.sampling;
-  pl.ids = p.sampling != LOD_AVERAGE || (p.flags & LOD_FLAG_POINT_IDS);
+  pl.full = (p.flags & LOD_FLAG_FULL_PRECISION) != 0;
+  pl.mode = p.sampling == LOD_AVERAGE && pl.full ? 3u : p.sampling;
+  pl.ids = p.sampling != LOD_AVERAGE || (p.flags & LOD_FLAG_POINT_IDS) || pl.full;
   // chunks are whole numbers of insert rounds (about 64k points for large
   // inputs, two rounds in the middle range and for refinements)
   const uint32_t R = scatter_round(pl.ids);
@@ -607,6 +609,11 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   uint64_t* vox = arena->alloc<uint64_t>(std::max<uint64_t>(vtotal, 1));
   uint32_t* vids = pl.mode ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
   launch_voxel_gather(pl.mode, nd, vt, num_nodes, tinfo, icnt, desc, T1, Xid, T2, T2id, vox, vids, s);
+  lod_point* vpts = nullptr;
+  if (pl.full) {
+    vpts = arena->alloc<lod_point>(std::max<uint64_t>(vtotal, 1));
+    launch_voxel_points(vox, vids, vtotal, tinfo, clouds, nc, in, vpts, s);
+  }
   HIPCHK(hipGetLastError());
   tm.mark(EV_LEVELS);
 
@@ -664,6 +671,7 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     v.point_ids = Yid ? Yid + ti.point_base : nullptr;
     v.voxels = (const lod_voxel*)(vox + ti.vbase);
     v.voxel_ids = vids ? vids + ti.vbase : nullptr;
+    v.voxel_points = vpts ? vpts + ti.vbase : nullptr;
   }
   return release_all();
 }

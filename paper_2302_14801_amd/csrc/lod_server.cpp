@@ -40,7 +40,12 @@ struct Request {
 // (16 B/pt), the partition scratch and staged voxels (20 B/pt), the tree's
 // points and ids (20 B/pt), voxel lists (at most ~8 B per point per inner
 // level, 24 B/pt is a safe typical bound) plus fixed-size grids and tables.
-uint64_t footprint_estimate(uint64_t n) { return 80ull * n + (96ull << 20); }
+// Full-precision records add 20 B per voxel (record and id), bounded the same
+// way by 24 B/pt.
+uint64_t footprint_estimate(uint64_t n, const lod_params& p) {
+  const uint64_t full = (p.flags & LOD_FLAG_FULL_PRECISION) ? 24ull * n : 0ull;
+  return 80ull * n + full + (96ull << 20);
+}
 
 }  // namespace
 
@@ -142,7 +147,7 @@ lod_status lod_submit(lod_server* s, const lod_point* h_points, uint64_t n, uint
     lod_set_error("invalid submit arguments");
     return LOD_ERR_INVALID;
   }
-  const uint64_t est = footprint_estimate(n);
+  const uint64_t est = footprint_estimate(n, s->params);
   if (est > s->budget) {
     lod_set_error("request of %llu points needs about %llu bytes, more than the whole budget",
                   (unsigned long long)n, (unsigned long long)est);

@@ -63,3 +63,27 @@ def test_package_refuses_to_import_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(OSError):
         binding.load_library()
+
+
+@pytest.mark.parametrize("name", ["lod_params", "lod_tree_view", "lod_timings"])
+def test_struct_layouts_match_header(name, tmp_path):
+    """The binding's ctypes mirrors have the C compiler's sizes and offsets."""
+    import shutil
+    import subprocess
+    from paper_2302_14801_amd import binding
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    cls = getattr(binding, name)
+    fields = [f for f, _ in cls._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lod.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({name}));']
+    lines += [f'  printf("%zu\\n", offsetof({name}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(cls)
+    for f, off in zip(fields, got[1:]):
+        assert getattr(cls, f).offset == off, f

@@ -228,6 +228,56 @@ def test_batch_many_uneven_chunks(lod):
         canon.compare_trees(g, oracle.build(chunk, leaf_cap=3000, max_level=12), chunk)
 
 
+def check_full(g, o, points):
+    """Tree, accepted ids and full-precision records, node by node."""
+    canon.compare_trees(g, o, points)
+    assert g["voxel_points"] is not None and g["voxel_ids"] is not None
+    for i in np.nonzero(g["is_leaf"] == 0)[0]:
+        go, oo, c = int(g["offset"][i]), int(o["offset"][i]), int(g["count"][i])
+        assert np.array_equal(g["voxel_points"][go:go + c], o["voxel_points"][oo:oo + c]), f"records of node {i}"
+
+
+@pytest.mark.parametrize("sampling", [0, 1, 2])
+def test_full_precision_lower_levels(lod, sampling):
+    p = synth.terrain(200_000, seed=5)
+    print(f"full precision n={len(p)} sampling={sampling}", flush=True)
+    g = gpu_tree(lod, p, leaf_cap=5000, max_level=12, sampling=sampling, seed=3, full_precision=True)
+    o = oracle.build(p, leaf_cap=5000, max_level=12, sampling=sampling, seed=3, full_precision=True)
+    check_full(g, o, p)
+
+
+def test_full_precision_exact_rounds(lod):
+    # a depth-limited cell of 999 samples (packed sums overflow: exact second
+    # round) and a micro-bucket of 70 000 points (wide path)
+    p = np.zeros(1000, synth.POINT_DTYPE)
+    p["x"], p["y"], p["z"] = 1.5, -2.0, 7.0
+    p["r"] = np.arange(1000) % 256
+    p[-1]["x"] = 9.0
+    q = np.zeros(70_010, synth.POINT_DTYPE)
+    q["x"], q["y"], q["z"] = 3.0, 3.0, 3.0
+    rng = np.random.default_rng(1)
+    q["g"] = rng.integers(0, 256, len(q))
+    q["x"][-10:] = rng.uniform(0, 10, 10).astype(np.float32)
+    for pts, T, ml in ((p, 10, 9), (q[rng.permutation(len(q))], 100, 5)):
+        print(f"full precision exact n={len(pts)}", flush=True)
+        g = gpu_tree(lod, pts, leaf_cap=T, max_level=ml, full_precision=True)
+        check_full(g, oracle.build(pts, leaf_cap=T, max_level=ml, full_precision=True), pts)
+
+
+def test_full_precision_batch(lod):
+    sizes = [3000, 50, 120000, 0, 40000, 777]
+    pts, offs = synth.batch_chunks(sizes, seed=4)
+    trees = lod.lod_build_batch(to_dev(pts), offs, leaf_cap=2000, max_level=12, full_precision=True)
+    for i, t in enumerate(trees):
+        chunk = pts[offs[i]:offs[i + 1]]
+        g = t.to_host()
+        t.free()
+        if len(chunk) == 0:
+            assert g["num_voxels"] == 0
+            continue
+        check_full(g, oracle.build(chunk, leaf_cap=2000, max_level=12, full_precision=True), chunk)
+
+
 def test_server_results_equal_alone_and_in_mix(lod):
     sizes = [200_000, 5_000, 80_000, 1, 150_000, 30_000, 90_000, 10]
     pts, offs = synth.batch_chunks(sizes, seed=6)

@@ -293,6 +293,44 @@ def test_pick_equals_argmin_argmax_over_subtree(sampling, n, T, ml, seed):
             assert v[:4] == (int(p["r"][pid]), int(p["g"][pid]), int(p["b"][pid]), int(p["a"][pid]))
 
 
+@pytest.mark.parametrize("sampling", [oracle.AVERAGE, oracle.FIRST, oracle.RANDOM])
+@pytest.mark.parametrize("n,T,ml,seed", VOX_CASES[:3])
+def test_full_precision_records_hold_the_accepted_sample(sampling, n, T, ml, seed):
+    """Sec. 7: a full-precision record is an input point of the voxel's cell --
+    the pick of the pick modes, the smallest-index point under the node in
+    the cell for the average -- with the voxel's colour."""
+    p = synth.uniform_cloud(n, seed)
+    raw = p.view(np.uint8).reshape(-1, 16)
+    t = oracle.build(p, leaf_cap=T, max_level=ml, sampling=sampling, seed=99, full_precision=True)
+    k = oracle.keys(p)
+    q = brute.demorton(k)
+    rec = t["voxel_points"]
+    assert rec.shape == (t["num_voxels"], 16) and len(t["voxel_ids"]) == t["num_voxels"]
+    for i in np.nonzero(t["is_leaf"] == 0)[0]:
+        L, key = int(t["level"][i]), int(t["key"][i])
+        off, cnt = int(t["offset"][i]), int(t["count"][i])
+        want = brute.closed_form_pick(p, q, k, L, key, oracle.FIRST if sampling == oracle.AVERAGE else sampling, 99)
+        for j in range(off, off + cnt):
+            v = t["voxels"][j]
+            pid = int(t["voxel_ids"][j])
+            assert want[(int(v[0]), int(v[1]), int(v[2]))] == pid
+            # the accepted point lies in the voxel's cell and keeps its coordinates
+            assert tuple(brute._point_cell(q[pid:pid + 1], L)[0].tolist()) == (int(v[0]), int(v[1]), int(v[2]))
+            assert np.array_equal(rec[j, :12], raw[pid, :12])
+            assert np.array_equal(rec[j, 12:], v[4:8])
+            if sampling != oracle.AVERAGE:
+                assert np.array_equal(rec[j], raw[pid])
+
+
+def test_full_precision_leaves_the_voxels_alone():
+    p = synth.uniform_cloud(2000, 6)
+    a = oracle.build(p, leaf_cap=20, max_level=12)
+    b = oracle.build(p, leaf_cap=20, max_level=12, full_precision=True)
+    for f in ("level", "key", "count", "offset", "voxels"):
+        assert np.array_equal(a[f], b[f])
+    assert a["voxel_ids"] is None and b["voxel_ids"] is not None
+
+
 def test_constant_colour_gives_constant_voxels():
     p = synth.uniform_cloud(3000, 8)
     p["r"], p["g"], p["b"] = 7, 130, 251
