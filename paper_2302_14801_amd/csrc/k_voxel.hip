@@ -71,7 +71,11 @@ __device__ __forceinline__ uint32_t anc_code(uint64_t leaf_key, uint32_t k, uint
 // 2^-17 for values under 256).  The true quotient is either an integer q,
 // which gives a value in (q, q + 2^-9), or at least 1/n >= 1/257 below the next
 // integer, which 2^-10 + 2^-14 does not reach; truncation is exact either way.
-__device__ __forceinline__ float rcp_count(uint32_t n) { return __builtin_amdgcn_rcpf((float)n); }
+// (n < 2^23 is converted through the mantissa: the compiler otherwise widens
+// a count taken from the top bits of a 64-bit word into a 64-bit conversion)
+__device__ __forceinline__ float rcp_count(uint32_t n) {
+  return __builtin_amdgcn_rcpf(__uint_as_float(0x4b000000u | n) - 8388608.0f);
+}
 __device__ __forceinline__ uint32_t floor_div(uint32_t sum, float r) {
   return (uint32_t)__fadd_rn(__fmul_rn((float)sum, r), 0x1p-10f);
 }
@@ -156,6 +160,69 @@ __device__ __forceinline__ void smp_xor(Smp<MODE>& s, int m) {
     smp_merge<MODE>(s, o);
   }
 }
+// Lane exchanges without the LDS crossbar: DPP (quad permutations, rotations
+// within a row of 16 lanes) and, across the two rows of a half-wave, a
+// swizzle.  Used for all-lane reductions, where the order of the merges does
+// not matter (sums are exact, picks are min/max).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_get(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
+}
+constexpr int kQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kRowRor1 = 0x121;   // row_ror:n = 0x120 + n
+constexpr int kRowRor2 = 0x122;
+constexpr int kRowRor4 = 0x124;
+constexpr int kRowRor8 = 0x128;
+constexpr int kRowShr1 = 0x111;   // row_shr:n = 0x110 + n
+constexpr int kRowShr2 = 0x112;
+constexpr int kRowShr4 = 0x114;
+constexpr int kRowShr8 = 0x118;
+constexpr int kSwap16 = 0x10000 | 0x401F;  // ds_swizzle: lane ^ 16 within 32 lanes
+template <int CTRL>
+__device__ __forceinline__ uint32_t lane_get(uint32_t x) {
+  if constexpr (CTRL >= 0x10000) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, CTRL & 0xffff);
+  else return dpp_get<CTRL>(x);
+}
+// merge with the samples of the lane selected by CTRL (every lane executes this)
+template <int MODE, int CTRL>
+__device__ __forceinline__ void smp_lane(Smp<MODE>& s) {
+  if (avg_mode(MODE)) {
+    const uint32_t rg = lane_get<CTRL>(s.r | (s.g << 16));
+    const uint32_t bn = lane_get<CTRL>(s.b | (s.n << 16));
+    s.r += rg & 0xffffu;
+    s.g += rg >> 16;
+    s.b += bn & 0xffffu;
+    s.n += bn >> 16;
+    if (MODE == 3) s.ok = min(s.ok, (uint64_t)lane_get<CTRL>((uint32_t)s.ok));
+  } else {
+    Smp<MODE> o = smp_empty<MODE>();
+    o.n = lane_get<CTRL>(s.n);
+    o.ok = (uint64_t)lane_get<CTRL>((uint32_t)s.ok) | ((uint64_t)lane_get<CTRL>((uint32_t)(s.ok >> 32)) << 32);
+    o.col = lane_get<CTRL>(s.col);
+    smp_merge<MODE>(s, o);
+  }
+}
+// Inclusive prefix sum over the wave (row scans by shifts, then the row
+// totals carried by broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x) {
+  x += dpp_get<kRowShr1>(x);
+  x += dpp_get<kRowShr2>(x);
+  x += dpp_get<kRowShr4>(x);
+  x += dpp_get<kRowShr8>(x);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+  return x;
+}
+// Sum over each row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ uint32_t row_sum_dpp(uint32_t x) {
+  x += dpp_get<kRowRor8>(x);
+  x += dpp_get<kRowRor4>(x);
+  x += dpp_get<kRowRor2>(x);
+  x += dpp_get<kRowRor1>(x);
+  return x;
+}
+
 // the cell's voxel colour: floor of the mean per channel with A = 255
 // (sums of at most 8 voxels here), or the pick's colour
 template <int MODE>
@@ -270,15 +337,16 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nod
 // Every sample also sets its cell's bit in an occupancy bitmask of the 4096
 // depth-1 cells (two masks alternate between micro-buckets, so one is
 // cleared while the other fills).  After the barrier every wave reads the
-// whole mask and derives by ballots the occupied cells of each depth (a
-// depth-2 cell is a nonzero byte, a depth-3 cell a nonzero pair of words, a
-// depth-4 cell eight of those) in the earlier waves' quarters and in total,
-// so that all list positions follow without any counting during the
-// accumulation.  The emission (thread t owns depth-1 cells 16t .. 16t+15,
-// i.e. depth-2 cells 2t and 2t+1) writes the depth-1 voxels and reduces them
-// upward through registers and wave shuffles: depth 2 in the thread, depth 3
-// over 4 lanes, depth 4 over 32 lanes.  Depth 5 (the micro-bucket) and 6 (the
-// item) are reduced at the end.  An average cell seen with more than 257
+// whole mask and counts the occupied cells of each depth (a depth-2 cell is
+// a nonzero byte, a depth-3 cell a nonzero pair of words, a depth-4 cell
+// eight of those) in the earlier waves' quarters and in total (DPP row sums),
+// and its own lanes' counts before them (a DPP wave scan), so that all list
+// positions follow without any counting during the accumulation.  The
+// emission (thread t owns depth-1 cells 16t .. 16t+15, i.e. depth-2 cells 2t
+// and 2t+1) writes the depth-1 voxels and reduces them upward through
+// registers and DPP lane exchanges: depth 2 in the thread, depth 3 over 4
+// lanes, depth 4 over 32 lanes.  Depth 5 (the micro-bucket) and 6 (the item)
+// are reduced at the end.  An average cell seen with more than 257
 // samples sends its micro-bucket to a second, exact round.
 // Depth-1 lists go to T1 at the item's first point (never more voxels than
 // points), the coarse lists to the item's block in T2.  icnt receives the 6
@@ -302,6 +370,11 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   __shared__ uint32_t minid[MODE == 3 ? kSubCells : 1];  // mode 3: smallest id of every depth-1 cell
   const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
   const ItemDesc& sd = desc[blockIdx.x];  // uniform: scalar loads
+  const uint32_t P = sd.P;
+  if (P == 0) {  // an empty child cell, or not a leaf item (uniform)
+    if (t < 6) icnt[6 * blockIdx.x + t] = 0;
+    return;
+  }
   const uint64_t init = MODE == 1 ? ~0ull : 0ull;
   for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
   if (MODE == 3)
@@ -314,19 +387,27 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
     k4m[t] = 0;
     over[t] = 0;
   }
-  const uint32_t P = sd.P;
   const CubeD cd = load_cube(cube + sd.tree);
   __syncthreads();
-  if (P == 0) {
-    if (t < 6) icnt[6 * blockIdx.x + t] = 0;
-    return;
-  }
   const uint32_t I0 = sd.I0, I1 = I0 + P, lvl = sd.lvl, grp = blockIdx.x & 7u;
   const uint64_t lkey = sd.lkey, t2b = sd.t2;
   const uint32_t sub_bit = 15u - lvl;  // bit level of the depth-1 cells (level lvl + 6)
   const uint32_t cb3 = coarse_base(3, P), cb4 = coarse_base(4, P), cb5 = coarse_base(5, P), cb6 = coarse_base(6, P);
-  const uint64_t below = (1ull << l) - 1;               // lanes under this one
-  const uint64_t earlier = (1ull << (16 * w)) - 1;      // lanes 0 .. 16w-1: the words of earlier waves
+  const uint64_t below = (1ull << l) - 1;  // lanes under this one
+  // Voxel coordinates.  A depth-1 cell has global coordinates (X, Y, Z) at
+  // level lvl + 6; the ancestor k levels up holds it in its cell with
+  // coordinates (X, Y, Z) >> (k - 1), taken mod 128.  X = the leaf's
+  // coordinates << 6 | micro-bucket << 4 | the thread's part | the cell's
+  // part (thread t owns cells 16t .. 16t+15: Morton bits 4..11 of the cell
+  // index are t, bits 0..3 the cell within the thread).
+  const uint32_t X0 = compact21(lkey), Y0 = compact21(lkey >> 1), Z0 = compact21(lkey >> 2);
+  const uint32_t xt = (((t >> 2) & 1u) << 2) | (((t >> 5) & 1u) << 3);
+  const uint32_t yt = ((t & 1u) << 1) | (((t >> 3) & 1u) << 2) | (((t >> 6) & 1u) << 3);
+  const uint32_t zt = (((t >> 1) & 1u) << 1) | (((t >> 4) & 1u) << 2) | (((t >> 7) & 1u) << 3);
+  auto vox_at = [](uint32_t sh, uint32_t X, uint32_t Y, uint32_t Z, uint32_t rgba) -> uint64_t {
+    return (uint64_t)(((X >> sh) & 127u) | (((Y >> sh) & 127u) << 8) | (((Z >> sh) & 127u) << 16)) |
+           ((uint64_t)rgba << 32);
+  };
   uint32_t base1 = 0, base2 = 0, base3 = 0, base4 = 0;  // list lengths so far
   uint32_t nproc = 0;                                   // micro-buckets emitted so far (bitmask alternation)
   for (uint32_t P0 = I0; P0 < I1; P0 += kLeafPass) {
@@ -406,7 +487,10 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         }
         lds_barrier();
       }
-      const uint32_t rel5 = (grp << 3) | jm;  // micro-bucket within the leaf (6 bits)
+      // coordinates of the thread's first depth-1 cell at level lvl + 6
+      const uint32_t Xb = (X0 << 6) | (((jm & 1u) | ((grp & 1u) << 1)) << 4) | xt;
+      const uint32_t Yb = (Y0 << 6) | ((((jm >> 1) & 1u) | (((grp >> 1) & 1u) << 1)) << 4) | yt;
+      const uint32_t Zb = (Z0 << 6) | ((((jm >> 2) & 1u) | (((grp >> 2) & 1u) << 1)) << 4) | zt;
       // Emission at depths 1..4, run once, or twice when an average cell
       // overflowed the packed sums (second round: exact colours of the wide
       // accumulation).  The occupancy bits are exact in both rounds, so the
@@ -457,43 +541,43 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
           }
         }
         // positions: every wave reads the whole depth-1 bitmask (lane l: words
-        // 2l, 2l+1) and derives, by ballots, the occupied cells of each depth
-        // in the earlier waves' quarters and in total
+        // 2l, 2l+1; row r of the wave reads quarter r, the cells of wave r)
+        // and sums its occupied cells of depths 1..3 per row (packed 13, 10
+        // and 7-bit fields: at most 4096, 512 and 64 cells), which gives the
+        // list lengths of the earlier waves' quarters and of the micro-bucket
         const uint32_t wa = occ[2 * l], wb2 = occ[2 * l + 1];
-        const uint32_t c1l = (uint32_t)__popc(wa) + (uint32_t)__popc(wb2);  // depth-1 cells, 0..64
         auto nzb = [](uint32_t x) {  // nonzero bytes: occupied depth-2 cells of a word
           uint32_t y = x | (x >> 4);
           y |= y >> 2;
           y |= y >> 1;
           return (uint32_t)__popc(y & 0x01010101u);
         };
-        const uint32_t c2l = nzb(wa) + nzb(wb2);  // 0..8
+        const uint32_t rs = row_sum_dpp(((uint32_t)__popc(wa) + (uint32_t)__popc(wb2)) | ((nzb(wa) + nzb(wb2)) << 13) |
+                                        (((wa | wb2) != 0u ? 1u : 0u) << 23));
+        const uint32_t q0 = (uint32_t)__builtin_amdgcn_readlane((int)rs, 0);
+        const uint32_t q1 = (uint32_t)__builtin_amdgcn_readlane((int)rs, 16);
+        const uint32_t q2 = (uint32_t)__builtin_amdgcn_readlane((int)rs, 32);
+        const uint32_t q3 = (uint32_t)__builtin_amdgcn_readlane((int)rs, 48);
+        const uint32_t qa = q0 + q1 + q2 + q3;
+        const uint32_t qc = (w > 0 ? q0 : 0u) + (w > 1 ? q1 : 0u) + (w > 2 ? q2 : 0u);
+        tot1 = qa & 0x1fffu;
+        tot2 = (qa >> 13) & 0x3ffu;
+        tot3 = qa >> 23;
+        const uint32_t cross1 = qc & 0x1fffu, cross2 = (qc >> 13) & 0x3ffu, cross3 = qc >> 23;
         const uint64_t b3 = __ballot((wa | wb2) != 0u);  // bit l: depth-3 cell l occupied
-        uint32_t cross1 = 0, cross2 = 0;
-        tot1 = tot2 = 0;
-#pragma unroll
-        for (int b = 0; b < 7; ++b) {
-          const uint64_t bal = __ballot((c1l >> b) & 1u);
-          cross1 += (uint32_t)__popcll(bal & earlier) << b;
-          tot1 += (uint32_t)__popcll(bal) << b;
-        }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const uint64_t bal = __ballot((c2l >> b) & 1u);
-          cross2 += (uint32_t)__popcll(bal & earlier) << b;
-          tot2 += (uint32_t)__popcll(bal) << b;
-        }
         uint32_t m4 = 0;  // occupied depth-4 cells (a depth-4 cell is 8 depth-3 cells)
 #pragma unroll
         for (int q = 0; q < 8; ++q) m4 |= ((b3 >> (8 * q)) & 0xffu) ? (1u << q) : 0u;
-        const uint32_t cross3 = (uint32_t)__popcll(b3 & earlier);
-        tot3 = (uint32_t)__popcll(b3);
         const uint32_t cross4 = (uint32_t)__popc(m4 & ((1u << (2 * w)) - 1u));
         tot4 = (uint32_t)__popc(m4);
-        // depth 1: cells 16t .. 16t + 15 (the half word t & 1 of word t >> 1)
+        // depth 1: cells 16t .. 16t + 15 (the half word t & 1 of word t >> 1);
+        // in-wave positions of the depth-1 and depth-2 voxels by one scan of
+        // (depth-1 cells | depth-2 cells << 11)
         const uint32_t word = occ[t >> 1];
         uint32_t m = (t & 1) ? (word >> 16) : (word & 0xffffu);
-        uint32_t pos = base1 + cross1 + wave_prefix_small<5>((uint32_t)__popc(m));
+        const uint32_t own = (uint32_t)__popc(m) | ((((m & 0xffu) != 0u ? 1u : 0u) + ((m >> 8) != 0u ? 1u : 0u)) << 11);
+        const uint32_t exs = wave_incl_scan_dpp(own) - own;
+        uint32_t pos = base1 + cross1 + (exs & 0x7ffu);
         Smp<MODE> h0 = smp_empty<MODE>(), h1 = smp_empty<MODE>();
         const uint32_t* colw = (const uint32_t*)(acc + 2048);
         bool ovf = false;
@@ -528,51 +612,52 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
             id = (uint32_t)a;
             T1id[I0 + pos] = id;
           }
-          T1[I0 + pos] = make_voxel(anc_code(lkey, 1, (rel5 << 12) | sc), rgba);
+          T1[I0 + pos] = vox_at(0, Xb | (b & 1u) | ((b >> 2) & 2u), Yb | ((b >> 1) & 1u), Zb | ((b >> 2) & 1u), rgba);
           ++pos;
           if (b < 8) smp_add<MODE>(h0, rgba, id, seed);
           else smp_add<MODE>(h1, rgba, id, seed);
         }
         if (avg_mode(MODE) && ovf) over[jm] = 1;
         // depth 2: cells 2t, 2t + 1
-        pos = base2 + cross2 + wave_prefix_small<2>((h0.n ? 1u : 0u) + (h1.n ? 1u : 0u));
+        pos = base2 + cross2 + (exs >> 11);
         Smp<MODE> g3 = smp_empty<MODE>();
 #pragma unroll
         for (uint32_t e = 0; e < 2; ++e) {
           const Smp<MODE>& h = e ? h1 : h0;
           if (h.n) {
             const uint32_t rgba = smp_rgba<MODE>(h), id = (uint32_t)h.ok;
-            T2[t2b + pos] = make_voxel(anc_code(lkey, 2, (rel5 << 9) | (2 * t + e)), rgba);
+            T2[t2b + pos] = vox_at(1, Xb | (e << 1), Yb, Zb, rgba);
             if (MODE) T2id[t2b + pos] = id;
             ++pos;
             smp_add<MODE>(g3, rgba, id, seed);
           }
         }
         // depth 3: cell t / 4, over lanes 4q .. 4q + 3
-        smp_xor<MODE>(g3, 1);
-        smp_xor<MODE>(g3, 2);
+        smp_lane<MODE, kQuadXor1>(g3);
+        smp_lane<MODE, kQuadXor2>(g3);
         const bool lead3 = (l & 3) == 0;
         pos = base3 + cross3 + (uint32_t)__popcll(__ballot(lead3 && g3.n) & below);
         Smp<MODE> g4 = smp_empty<MODE>();
         if (g3.n) {
           const uint32_t rgba = smp_rgba<MODE>(g3), id = (uint32_t)g3.ok;
           if (lead3) {
-            T2[t2b + cb3 + pos] = make_voxel(anc_code(lkey, 3, (rel5 << 6) | (t >> 2)), rgba);
+            T2[t2b + cb3 + pos] = vox_at(2, Xb, Yb, Zb, rgba);
             if (MODE) T2id[t2b + cb3 + pos] = id;
           }
           smp_add<MODE>(g4, rgba, id, seed);
         }
         // depth 4: cell t / 32, over the 8 groups of 4 lanes of a half-wave (the
-        // 4 lanes of a group hold the same depth-3 voxel: one lane per group
-        // takes part in each exchange)
-        smp_xor<MODE>(g4, 4);
-        smp_xor<MODE>(g4, 8);
-        smp_xor<MODE>(g4, 16);
+        // 4 lanes of a group hold the same depth-3 voxel; exchanges that keep
+        // a lane's place in its group take each group once): the 4 groups of
+        // a row by rotations by 4 and 8 lanes, then the two rows
+        smp_lane<MODE, kRowRor4>(g4);
+        smp_lane<MODE, kRowRor8>(g4);
+        smp_lane<MODE, kSwap16>(g4);
         const bool lead4 = (l & 31) == 0;
         pos = base4 + cross4 + (uint32_t)__popcll(__ballot(lead4 && g4.n) & below);
         if (lead4 && g4.n) {
           const uint32_t rgba = smp_rgba<MODE>(g4), id = (uint32_t)g4.ok;
-          T2[t2b + cb4 + pos] = make_voxel(anc_code(lkey, 4, (rel5 << 3) | (t >> 5)), rgba);
+          T2[t2b + cb4 + pos] = vox_at(3, Xb, Yb, Zb, rgba);
           if (MODE) T2id[t2b + cb4 + pos] = id;
           k4col[jm][t >> 5] = rgba;
           k4ok[jm][t >> 5] = g4.ok;
