@@ -486,14 +486,17 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
 
 uint32_t scatter_round(bool ids) { return ids ? (uint32_t)ScatShape<true>::R : (uint32_t)ScatShape<false>::R; }
 
-// Copy the points (and ids) of every segment from one buffer to the other.
-__global__ void k_copy_segments(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
-                                uint4* __restrict__ dst, uint32_t* __restrict__ dst_ids, const Segment* __restrict__ segs,
-                                const uint32_t* nseg_ptr) {
+// Copy the points (and ids) of every segment from one buffer to the other;
+// kCopySplit workgroups share a segment (refinement lists are short and
+// their segments large).
+constexpr uint32_t kCopySplit = 64;
+__global__ void __launch_bounds__(256) k_copy_segments(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
+                                                       uint4* __restrict__ dst, uint32_t* __restrict__ dst_ids,
+                                                       const Segment* __restrict__ segs, const uint32_t* nseg_ptr) {
   const uint32_t s = blockIdx.x;
   if (s >= *nseg_ptr) return;
   const Segment sg = segs[s];
-  for (uint32_t i = threadIdx.x; i < sg.count; i += blockDim.x) {
+  for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < sg.count; i += kCopySplit * 256) {
     dst[sg.start + i] = src[sg.start + i];
     if (dst_ids) dst_ids[sg.start + i] = src_ids[sg.start + i];
   }
@@ -684,8 +687,8 @@ void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* 
 void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,
                           const uint32_t* nseg, uint32_t max_segs, hipStream_t st) {
   if (!max_segs) return;
-  hipLaunchKernelGGL(k_copy_segments, dim3(max_segs), dim3(256), 0, st, (const uint4*)src, src_ids, (uint4*)dst,
-                     dst_ids, segs, nseg);
+  hipLaunchKernelGGL(k_copy_segments, dim3(max_segs, kCopySplit), dim3(256), 0, st, (const uint4*)src, src_ids,
+                     (uint4*)dst, dst_ids, segs, nseg);
 }
 
 void launch_segments_from_grid(GridDesc* grids, uint32_t ngrids, uint32_t* pool, uint32_t E2, uint64_t slot_base,

@@ -908,7 +908,9 @@ __global__ void __launch_bounds__(kPieceWG) k_piece_offsets(Nodes nodes, VoxTree
 }
 
 // Copy every item's depth-1..6 lists to their output positions: the leaf's
-// piece for that depth plus the lengths of the leaf's earlier items.
+// piece for that depth plus the lengths of the leaf's earlier items.  One
+// workgroup per leaf: its 48 lists (6 depths x 8 items) are described once,
+// then each wave copies every fourth list.
 constexpr int kGatherWG = 256;
 template <int MODE>
 __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, uint32_t num_nodes,
@@ -917,43 +919,46 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, u
                                                       const uint64_t* __restrict__ T1, const uint32_t* __restrict__ T1id,
                                                       const uint64_t* __restrict__ T2, const uint32_t* __restrict__ T2id,
                                                       uint64_t* __restrict__ vox, uint32_t* __restrict__ vids) {
-  __shared__ uint64_t sdst[6], ssrc[6];
-  __shared__ uint32_t scnt[6];
-  const uint32_t item = blockIdx.x, n = item >> 3, g = item & 7u;
+  __shared__ uint64_t sdst[48], ssrc[48];
+  __shared__ uint32_t scnt[48];
+  const uint32_t n = blockIdx.x, t = threadIdx.x;
   if (n >= num_nodes || !nodes.is_leaf[n] || nodes.level[n] == 0) return;
   const uint32_t L = nodes.level[n];
-  if (threadIdx.x < 6) {
-    const uint32_t k = threadIdx.x + 1;
-    const uint32_t c = k <= L ? icnt[6ull * item + k - 1] : 0u;
+  // list j: depth k = j / 8 + 1 of item g = j % 8
+  const uint32_t k = t / 8 + 1, g = t % 8;
+  if (t < 48) scnt[t] = k <= L ? icnt[6ull * (8 * n + g) + k - 1] : 0u;
+  __syncthreads();
+  if (t < 48) {
+    const uint32_t c = scnt[t];
     uint64_t dst = 0, src = 0;
     if (c) {
       dst = vt.poff[8ull * n + k];
-      for (uint32_t q = 0; q < g; ++q) dst += icnt[6ull * (8 * n + q) + k - 1];
-      src = k == 1 ? (uint64_t)desc[item].I0 : desc[item].t2 + coarse_base(k, desc[item].P);
+      for (uint32_t q = 0; q < g; ++q) dst += scnt[t - g + q];
+      const ItemDesc& d = desc[8 * n + g];
+      src = k == 1 ? (uint64_t)d.I0 : d.t2 + coarse_base(k, d.P);
     }
-    sdst[threadIdx.x] = dst;
-    ssrc[threadIdx.x] = src;
-    scnt[threadIdx.x] = c;
+    sdst[t] = dst;
+    ssrc[t] = src;
   }
   __syncthreads();
-#pragma unroll
-  for (uint32_t k = 0; k < 6; ++k) {
-    const uint32_t c = scnt[k];
-    const uint64_t dst = sdst[k], src = ssrc[k];
-    const uint64_t* sv = k == 0 ? T1 : T2;
-    const uint32_t* si = k == 0 ? T1id : T2id;
-    uint32_t i = threadIdx.x;
-    for (; i + 3 * kGatherWG < c; i += 4 * kGatherWG) {
-      const uint64_t a0 = sv[src + i], a1 = sv[src + i + kGatherWG], a2 = sv[src + i + 2 * kGatherWG],
-                     a3 = sv[src + i + 3 * kGatherWG];
+  const uint32_t w = t / 64, l = lane_id();
+  for (uint32_t j = w; j < 48; j += kGatherWG / 64) {
+    const uint32_t c = scnt[j];
+    if (c == 0) continue;
+    const uint64_t dst = sdst[j], src = ssrc[j];
+    const uint64_t* sv = j < 8 ? T1 : T2;
+    const uint32_t* si = j < 8 ? T1id : T2id;
+    uint32_t i = l;
+    for (; i + 192 < c; i += 256) {
+      const uint64_t a0 = sv[src + i], a1 = sv[src + i + 64], a2 = sv[src + i + 128], a3 = sv[src + i + 192];
       vox[dst + i] = a0;
-      vox[dst + i + kGatherWG] = a1;
-      vox[dst + i + 2 * kGatherWG] = a2;
-      vox[dst + i + 3 * kGatherWG] = a3;
+      vox[dst + i + 64] = a1;
+      vox[dst + i + 128] = a2;
+      vox[dst + i + 192] = a3;
       if (MODE)
-        for (uint32_t q = 0; q < 4; ++q) vids[dst + i + q * kGatherWG] = si[src + i + q * kGatherWG];
+        for (uint32_t q = 0; q < 4; ++q) vids[dst + i + 64 * q] = si[src + i + 64 * q];
     }
-    for (; i < c; i += kGatherWG) {
+    for (; i < c; i += 64) {
       vox[dst + i] = sv[src + i];
       if (MODE) vids[dst + i] = si[src + i];
     }
@@ -1046,7 +1051,7 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
   LOD_MODE_SWITCH(mode, M, {
     hipLaunchKernelGGL(k_piece_offsets<M>, dim3(num_nodes), dim3(kPieceWG), 0, s, nodes, vt, num_nodes, trees, vox,
                        vids);
-    hipLaunchKernelGGL(k_gather<M>, dim3(num_nodes * 8), dim3(kGatherWG), 0, s, nodes, vt, num_nodes, icnt,
+    hipLaunchKernelGGL(k_gather<M>, dim3(num_nodes), dim3(kGatherWG), 0, s, nodes, vt, num_nodes, icnt,
                        (const ItemDesc*)desc, T1, T1id, T2, T2id, vox, vids);
   })
 }
