@@ -71,9 +71,12 @@ __global__ void __launch_bounds__(kBBoxWG) k_bbox(const uint4* __restrict__ pts,
       lo2 = min(lo2, c); hi2 = max(hi2, c);
     }
   };
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    uint4 v0 = pts[i], v1 = pts[i + stride], v2 = pts[i + 2 * stride], v3 = pts[i + 3 * stride];
-    acc1(v0); acc1(v1); acc1(v2); acc1(v3);
+  for (; i + 7 * stride < n; i += 8 * stride) {
+    uint4 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = pts[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc1(v[k]);
   }
   for (; i < n; i += stride) acc1(pts[i]);
 #pragma unroll
@@ -224,12 +227,14 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
   lds_barrier();
   const uint4* p = pts + ch.start;
   uint32_t i = threadIdx.x;
-  for (; i + 3 * kCountWG < ch.count; i += 4 * kCountWG) {
-    uint4 v0 = p[i], v1 = p[i + kCountWG], v2 = p[i + 2 * kCountWG], v3 = p[i + 3 * kCountWG];
-    atomicAdd(&h[point_cell(__uint_as_float(v0.x), __uint_as_float(v0.y), __uint_as_float(v0.z), cd, lvl_bit, E)], 1u);
-    atomicAdd(&h[point_cell(__uint_as_float(v1.x), __uint_as_float(v1.y), __uint_as_float(v1.z), cd, lvl_bit, E)], 1u);
-    atomicAdd(&h[point_cell(__uint_as_float(v2.x), __uint_as_float(v2.y), __uint_as_float(v2.z), cd, lvl_bit, E)], 1u);
-    atomicAdd(&h[point_cell(__uint_as_float(v3.x), __uint_as_float(v3.y), __uint_as_float(v3.z), cd, lvl_bit, E)], 1u);
+  for (; i + 7 * kCountWG < ch.count; i += 8 * kCountWG) {
+    uint4 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = p[i + k * kCountWG];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      atomicAdd(&h[point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E)],
+                1u);
   }
   for (; i < ch.count; i += kCountWG) {
     uint4 v = p[i];
