@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liblod_oracle.so")
 _SRC = os.path.join(_HERE, "lod_oracle.c")
 
-AVERAGE, FIRST, RANDOM = 0, 1, 2
+AVERAGE, FIRST, RANDOM, WEIGHTED = 0, 1, 2, 3
 OK, ERR_INVALID, ERR_NONFINITE, ERR_OOM = 0, -1, -2, -3
 
 
@@ -157,7 +157,7 @@ def full_precision_points(points, tree: dict, leaf_cap: int, max_level: int, sam
     """Full-precision samples of the lower levels (Sec. 7, Discussion).
 
     The pick modes keep the picked point itself: its input coordinates, with
-    quantization switched off.  For the average, the cell's accepted sample
+    quantization switched off.  For the (weighted) average, the cell's accepted sample
     is the one a first-come pass accepts (Sec. 4.2.1, made order-independent
     as the smallest input index), and the record takes its coordinates with
     the averaged colour.  The first-come voxel ids are those of the same tree
@@ -166,7 +166,7 @@ def full_precision_points(points, tree: dict, leaf_cap: int, max_level: int, sam
     x, y, z float32 and r, g, b, a of the voxel)."""
     raw = _as_records(points).view(np.uint8).reshape(-1, 16)
     out = dict(tree)
-    if sampling == AVERAGE:
+    if sampling in (AVERAGE, WEIGHTED):
         first = _build(points, leaf_cap, max_level, FIRST, seed, cube_lo, cube_side)
         assert first["num_voxels"] == tree["num_voxels"]
         ids = first["voxel_ids"]

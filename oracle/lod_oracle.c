@@ -25,6 +25,15 @@
  *        RANDOM:  sample with the largest (h(id,seed) << 32 | id), h from the
  *                 SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014)
  *                                           (Sec. 4.2.2, Listing 1, made order-free)
+ *        WEIGHTED: every sample adds w * RGB and w to the 2x2x2 cells around it,
+ *                 w = 1 - (distance to the cell centre in cells), clamped at 0;
+ *                 only the cell containing a sample is occupied; colour =
+ *                 floor(sum(w * c) / sum(w)), A = 255   (Sec. 4.2.4)
+ *                 Reading, to make it exact: positions on the half-cell lattice
+ *                 of the 2^21 quantization grid (a point at its quantization
+ *                 cell's centre, a child voxel at its cell's centre), weights in
+ *                 16-bit fixed point, w = 65536 - floor(65536 * distance), from
+ *                 an exact integer square root.
  *
  * Arithmetic: IEEE double for the one float->int projection, compiled with
  * -ffp-contract=off; everything after quantization is integer.
@@ -203,6 +212,74 @@ static void grid_add(grid128* g, int sampling, uint32_t seed, uint32_t x, uint32
   if (fresh) g->occupied[g->num_occupied++] = c;
 }
 
+/* Exact floor(sqrt(x)) for x < 2^52: a double estimate, then integer
+ * corrections (the estimate is within one of the answer). */
+static uint64_t isqrt_u64(uint64_t x) {
+  uint64_t r = (uint64_t)sqrt((double)x);
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
+/* Coordinate along one axis (0 = x) of the cell a Morton key names. */
+static uint32_t key_axis(uint64_t key, int axis) {
+  uint32_t c = 0;
+  for (int i = 0; i < KEY_LEVELS; ++i) c |= (uint32_t)((key >> (3 * i + axis)) & 1u) << i;
+  return c;
+}
+
+/* WEIGHTED (Sec. 4.2.4): per-cell weighted sums over the whole 128^3 grid of
+ * the node being sampled, and the list of cells touched (for clearing). */
+typedef struct {
+  uint64_t* wr; uint64_t* wg; uint64_t* wb; uint64_t* w;
+  uint8_t* touched; uint32_t* touched_list; uint32_t num_touched;
+} wgrid128;
+
+/* A sample of node (L, key) at position pos2 (per axis, in units of half a
+ * cell of the 2^21 grid) splats onto the 2x2x2 cells of the node's grid whose
+ * centres surround it.  A cell at distance d (in cells of the node's grid,
+ * 2^(15-L) units) gets weight max(0, 65536 - floor(65536 d)). */
+static void wgrid_splat(wgrid128* g, int L, const uint32_t node_xyz[3], const uint64_t pos2[3], const uint8_t rgba[4]) {
+  const int cs = 15 - L; /* log2 of the node's cell size in pos2 units */
+  int64_t cand[3][2];
+  for (int a = 0; a < 3; ++a) {
+    int64_t k = (int64_t)(pos2[a] >> cs);                    /* containing cell, global index */
+    int64_t f = (int64_t)pos2[a] - (k << cs);                /* offset inside it */
+    cand[a][0] = k;
+    cand[a][1] = f < ((int64_t)1 << (cs - 1)) ? k - 1 : k + 1; /* the other neighbour on this axis */
+  }
+  for (int m = 0; m < 8; ++m) {
+    int64_t c[3];
+    int inside = 1;
+    for (int a = 0; a < 3; ++a) {
+      c[a] = cand[a][(m >> a) & 1];
+      int64_t local = c[a] - ((int64_t)node_xyz[a] << 7);
+      if (local < 0 || local > 127) inside = 0;
+    }
+    if (!inside) continue;
+    uint64_t d2 = 0;
+    for (int a = 0; a < 3; ++a) {
+      int64_t d = (int64_t)pos2[a] - ((2 * c[a] + 1) << (cs - 1));
+      d2 += (uint64_t)(d * d);
+    }
+    uint64_t r = isqrt_u64(d2 << (2 * L + 2)); /* floor(65536 * distance) */
+    if (r >= 65536) continue;
+    uint64_t w = 65536 - r;
+    uint32_t x = (uint32_t)(c[0] - ((int64_t)node_xyz[0] << 7));
+    uint32_t y = (uint32_t)(c[1] - ((int64_t)node_xyz[1] << 7));
+    uint32_t z = (uint32_t)(c[2] - ((int64_t)node_xyz[2] << 7));
+    uint32_t cell = (z * 128u + y) * 128u + x;
+    if (!g->touched[cell]) {
+      g->touched[cell] = 1;
+      g->touched_list[g->num_touched++] = cell;
+    }
+    g->wr[cell] += w * rgba[0];
+    g->wg[cell] += w * rgba[1];
+    g->wb[cell] += w * rgba[2];
+    g->w[cell] += w;
+  }
+}
+
 typedef struct {
   uint64_t code;
   uint32_t cell;
@@ -223,7 +300,10 @@ static int cmp_coded(const void* a, const void* b) {
 static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap, uint32_t max_level, int sampling,
                       uint32_t seed, const float* cube_lo, double cube_side, lod_oracle_tree* out) {
   memset(out, 0, sizeof(*out));
-  if (leaf_cap == 0 || max_level > 14 || sampling < 0 || sampling > 2) return LOD_ORACLE_ERR_INVALID;
+  if (leaf_cap == 0 || max_level > 14 || sampling < 0 || sampling > 3) return LOD_ORACLE_ERR_INVALID;
+  /* WEIGHTED marks occupancy like AVERAGE and keeps its own weighted sums */
+  const int weighted = sampling == LOD_ORACLE_WEIGHTED;
+  if (weighted) sampling = LOD_ORACLE_AVERAGE;
   if (n > 0xFFFFFFFFull) return LOD_ORACLE_ERR_INVALID;
   if (n > 0 && !pts) return LOD_ORACLE_ERR_INVALID;
 
@@ -331,6 +411,16 @@ static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap
     g.best_id = (uint32_t*)calloc(GRID_CELLS, 4);
   }
   coded_cell* order = (coded_cell*)malloc(sizeof(coded_cell) * GRID_CELLS);
+  wgrid128 wg;
+  memset(&wg, 0, sizeof(wg));
+  if (weighted) {
+    wg.wr = (uint64_t*)calloc(GRID_CELLS, 8);
+    wg.wg = (uint64_t*)calloc(GRID_CELLS, 8);
+    wg.wb = (uint64_t*)calloc(GRID_CELLS, 8);
+    wg.w = (uint64_t*)calloc(GRID_CELLS, 8);
+    wg.touched = (uint8_t*)calloc(GRID_CELLS, 1);
+    wg.touched_list = (uint32_t*)malloc(4ull * GRID_CELLS);
+  }
 
   int deepest = 0;
   for (uint32_t h = 0; h < nn; ++h) if (out->level[h] > deepest) deepest = out->level[h];
@@ -339,6 +429,8 @@ static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap
     for (uint32_t h = 0; h < nn; ++h) {
       if (out->level[h] != (uint8_t)L || out->is_leaf[h]) continue;
       g.num_occupied = 0;
+      wg.num_touched = 0;
+      const uint32_t node_xyz[3] = {key_axis(out->key[h], 0), key_axis(out->key[h], 1), key_axis(out->key[h], 2)};
       /* The 8 children, in octant order; child octant o covers cells
        * [64*ox, 64*ox+64) x [64*oy, ..) x [64*oz, ..) of this node's grid. */
       for (uint32_t c = out->first_child[h]; c < nn && out->level[c] == (uint8_t)(L + 1) &&
@@ -358,6 +450,11 @@ static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap
             uint8_t rgba[4] = {p->r, p->g, p->b, p->a};
             grid_add(&g, sampling, seed, (qx >> sh) & 127u, (qy >> sh) & 127u, (qz >> sh) & 127u, rgba,
                      kv[i].id);
+            if (weighted) {
+              /* a point sits at the centre of its 2^21-grid cell */
+              const uint64_t pos2[3] = {2ull * qx + 1, 2ull * qy + 1, 2ull * qz + 1};
+              wgrid_splat(&wg, L, node_xyz, pos2, rgba);
+            }
           }
         } else {
           /* samples are the child's voxels; the child's 128^3 grid folds
@@ -368,6 +465,16 @@ static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap
             uint32_t id = node_vid[c] ? node_vid[c][v] : 0u;
             grid_add(&g, sampling, seed, ox * 64u + (vx[0] >> 1), oy * 64u + (vx[1] >> 1),
                      oz * 64u + (vx[2] >> 1), rgba, id);
+            if (weighted) {
+              /* a child voxel sits at the centre of its cell (level L + 8):
+               * global index j = child coordinate * 128 + voxel coordinate */
+              uint64_t pos2[3];
+              for (int a = 0; a < 3; ++a) {
+                const uint64_t j = ((uint64_t)key_axis(out->key[c], a) << 7) + vx[a];
+                pos2[a] = (2 * j + 1) << (13 - L);
+              }
+              wgrid_splat(&wg, L, node_xyz, pos2, rgba);
+            }
           }
         }
       }
@@ -389,7 +496,15 @@ static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap
         v[1] = (uint8_t)((cell >> 7) & 127u);
         v[2] = (uint8_t)(cell >> 14);
         v[3] = 0;
-        if (sampling == LOD_ORACLE_AVERAGE) {
+        if (weighted) {
+          /* the containing sample has weight > 0.13, so the sum is positive */
+          uint64_t ws = wg.w[cell];
+          v[4] = (uint8_t)(wg.wr[cell] / ws); /* weighted mean, truncated */
+          v[5] = (uint8_t)(wg.wg[cell] / ws);
+          v[6] = (uint8_t)(wg.wb[cell] / ws);
+          v[7] = 255;
+          g.sum_r[cell] = g.sum_g[cell] = g.sum_b[cell] = 0;
+        } else if (sampling == LOD_ORACLE_AVERAGE) {
           uint64_t cnt = g.n[cell];
           v[4] = (uint8_t)(g.sum_r[cell] / cnt); /* arithmetic mean, truncated */
           v[5] = (uint8_t)(g.sum_g[cell] / cnt);
@@ -403,6 +518,11 @@ static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap
           g.best[cell] = 0;
         }
         g.n[cell] = 0; /* only occupied cells are cleared for reuse */
+      }
+      for (uint32_t k = 0; k < wg.num_touched; ++k) {
+        uint32_t cell = wg.touched_list[k];
+        wg.wr[cell] = wg.wg[cell] = wg.wb[cell] = wg.w[cell] = 0;
+        wg.touched[cell] = 0;
       }
       node_vox[h] = vox;
       node_vid[h] = vid;
@@ -426,6 +546,7 @@ static int build_impl(const lod_oracle_point* pts, uint64_t n, uint32_t leaf_cap
   free(node_vox); free(node_vid);
   free(g.sum_r); free(g.sum_g); free(g.sum_b); free(g.n); free(g.best); free(g.best_rgba);
   free(g.best_id); free(g.occupied); free(order);
+  free(wg.wr); free(wg.wg); free(wg.wb); free(wg.w); free(wg.touched); free(wg.touched_list);
   free(q); free(kv);
   return LOD_ORACLE_OK;
 }

@@ -13,7 +13,7 @@ extern "C" {
 #endif
 
 enum { LOD_ORACLE_OK = 0, LOD_ORACLE_ERR_INVALID = -1, LOD_ORACLE_ERR_NONFINITE = -2, LOD_ORACLE_ERR_OOM = -3 };
-enum { LOD_ORACLE_AVERAGE = 0, LOD_ORACLE_FIRST = 1, LOD_ORACLE_RANDOM = 2 };
+enum { LOD_ORACLE_AVERAGE = 0, LOD_ORACLE_FIRST = 1, LOD_ORACLE_RANDOM = 2, LOD_ORACLE_WEIGHTED = 3 };
 
 /* 16-byte input record: position and colour (Sec. 7: points and voxels share
  * one struct with float coordinates). */

@@ -11,11 +11,17 @@ formulations, so that a mistake in the oracle shows up as a disagreement:
 * ``recursive_voxels``       -- a dict-based recursion over the tree
   (Sec. 4.2.3), while the oracle uses dense 128^3 grids level by level;
 * ``closed_form_*``          -- results that do not need the recursion at all
-  (occupied cells, means of points, arg-min/arg-max picks).
+  (occupied cells, means of points, arg-min/arg-max picks);
+* ``recursive_weighted``     -- the neighbourhood-weighted average (Sec. 4.2.4)
+  gathered per occupied cell from every sample of the node (the oracle
+  scatters every sample onto its 2x2x2 cells), plus a real-arithmetic
+  variant with float64 weights.
 """
 from __future__ import annotations
 
 from collections import Counter, defaultdict
+
+import math
 
 import numpy as np
 
@@ -217,3 +223,70 @@ def tree_voxels(tree, node):
     ids = tree["voxel_ids"][off:off + cnt] if tree.get("voxel_ids") is not None else np.zeros(cnt, np.uint32)
     return {(int(a[0]), int(a[1]), int(a[2])): (int(a[4]), int(a[5]), int(a[6]), int(a[7]), int(i))
             for a, i in zip(v, ids)}
+
+
+def _node_xyz(level, key):
+    return tuple(int(v) for v in demorton(np.array([key], np.uint64) << np.uint64(3 * (KEY_LEVELS - level)))[0] >>
+                 np.uint32(KEY_LEVELS - level))
+
+
+def recursive_weighted(pts, q, keys, nodes, real=False, child_voxels=None):
+    """Weighted-average voxels {(x, y, z): (r, g, b, 255)} per inner node.
+
+    Sample positions are in units of half a cell of the 2^21 grid: a point at
+    2q + 1, a child voxel at the centre of its cell.  For every occupied cell
+    (one that contains a sample) the colour gathers w * colour over ALL samples
+    of the node, w = 1 - distance (cells of the node's grid), clamped at 0;
+    fixed point w = 65536 - floor(65536 d) via math.isqrt, or plain float64
+    (real=True).  child_voxels, if given, maps (level, key) to the voxel dict
+    used as the samples of an inner child (instead of the recursion)."""
+    by = {(l, k): leaf for (l, k, leaf, n) in nodes}
+    memo = {}
+
+    def samples_of(l, k):
+        out = []
+        for o in range(8):
+            ck = (k << 3) | o
+            if (l + 1, ck) not in by:
+                continue
+            if by[(l + 1, ck)]:
+                for i in subtree_members(keys, l + 1, ck).tolist():
+                    pos = tuple(2 * int(q[i][a]) + 1 for a in range(3))
+                    out.append((pos, (int(pts["r"][i]), int(pts["g"][i]), int(pts["b"][i]))))
+            else:
+                cxyz = _node_xyz(l + 1, ck)
+                src = child_voxels[(l + 1, ck)] if child_voxels is not None else vox(l + 1, ck)
+                for (x, y, z), col in src.items():
+                    pos = tuple((2 * ((cxyz[a] << 7) + (x, y, z)[a]) + 1) << (13 - l) for a in range(3))
+                    out.append((pos, col[:3]))
+        return out
+
+    def vox(l, k):
+        if (l, k) in memo:
+            return memo[(l, k)]
+        cs = 15 - l
+        nxyz = _node_xyz(l, k)
+        ss = samples_of(l, k)
+        occupied = {tuple((s[0][a] >> cs) - (nxyz[a] << 7) for a in range(3)) for s in ss}
+        out = {}
+        for c in occupied:
+            centre = [(2 * ((nxyz[a] << 7) + c[a]) + 1) << (cs - 1) for a in range(3)]
+            acc = [0, 0, 0, 0] if not real else [0.0, 0.0, 0.0, 0.0]
+            for pos, col in ss:
+                d2 = sum((pos[a] - centre[a]) ** 2 for a in range(3))
+                if real:
+                    w = max(0.0, 1.0 - math.sqrt(d2) / (1 << cs))
+                else:
+                    r = math.isqrt(d2 << (2 * l + 2))
+                    w = 65536 - r if r < 65536 else 0
+                for a in range(3):
+                    acc[a] += w * col[a]
+                acc[3] += w
+            if real:
+                out[c] = tuple(int(math.floor(acc[a] / acc[3])) for a in range(3)) + (255,)
+            else:
+                out[c] = tuple(acc[a] // acc[3] for a in range(3)) + (255,)
+        memo[(l, k)] = out
+        return out
+
+    return {(l, k): vox(l, k) for (l, k, leaf, n) in nodes if not leaf}

@@ -98,7 +98,7 @@ def test_nonfinite_rejected():
 
 def test_invalid_params_rejected():
     p = synth.uniform_cloud(10, 1)
-    for kw in ({"leaf_cap": 0}, {"max_level": 15}, {"sampling": 3}):
+    for kw in ({"leaf_cap": 0}, {"max_level": 15}, {"sampling": 4}):
         with pytest.raises(oracle.OracleError) as e:
             oracle.build(p, **kw)
         assert e.value.status == oracle.ERR_INVALID
@@ -329,6 +329,73 @@ def test_full_precision_leaves_the_voxels_alone():
     for f in ("level", "key", "count", "offset", "voxels"):
         assert np.array_equal(a[f], b[f])
     assert a["voxel_ids"] is None and b["voxel_ids"] is not None
+
+
+WEIGHTED_CASES = [(150, 3, 12, 0), (250, 10, 12, 1), (200, 1, 5, 2), (120, 7, 14, 3)]
+
+
+@pytest.mark.parametrize("n,T,ml,seed", WEIGHTED_CASES)
+def test_weighted_equals_gather_form(n, T, ml, seed):
+    """Sec. 4.2.4: the oracle scatters every sample onto its 2x2x2 cells; the
+    brute-force form gathers, for every occupied cell, all samples of the node."""
+    p = synth.uniform_cloud(n, seed)
+    t = oracle.build(p, leaf_cap=T, max_level=ml, sampling=oracle.WEIGHTED)
+    k = oracle.keys(p)
+    q = brute.demorton(k)
+    want = brute.recursive_weighted(p, q, k, brute.tree_nodes(t))
+    for i in np.nonzero(t["is_leaf"] == 0)[0]:
+        got = {c: v[:4] for c, v in brute.tree_voxels(t, i).items()}
+        assert got == want[(int(t["level"][i]), int(t["key"][i]))]
+
+
+@pytest.mark.parametrize("n,T,ml,seed", WEIGHTED_CASES[:3])
+def test_weighted_within_bound_of_real_weights(n, T, ml, seed):
+    """Fixed-point weights against float64 weights on the same samples (the
+    oracle's child voxels): each fixed weight exceeds the real one by less than
+    one unit of 2^-16 and the sum of weights is at least that of the
+    containing sample (> 0.13), so a colour moves by less than
+    1 + 255 * samples / (0.13 * 65536) steps."""
+    p = synth.uniform_cloud(n, seed)
+    t = oracle.build(p, leaf_cap=T, max_level=ml, sampling=oracle.WEIGHTED)
+    k = oracle.keys(p)
+    q = brute.demorton(k)
+    nodes = brute.tree_nodes(t)
+    mine = {(int(t["level"][i]), int(t["key"][i])): {c: v[:4] for c, v in brute.tree_voxels(t, i).items()}
+            for i in np.nonzero(t["is_leaf"] == 0)[0]}
+    real = brute.recursive_weighted(p, q, k, nodes, real=True, child_voxels=mine)
+    bound = int(np.ceil(1 + 255 * n / (0.13 * 65536)))
+    worst = 0
+    for node, vox in mine.items():
+        for c, v in vox.items():
+            worst = max(worst, max(abs(v[a] - real[node][c][a]) for a in range(3)))
+    assert worst <= bound
+
+
+def test_weighted_keeps_cells_and_constant_colour():
+    p = synth.uniform_cloud(3000, 8)
+    a = oracle.build(p, leaf_cap=30, max_level=12)
+    p2 = p.copy()
+    p2["r"], p2["g"], p2["b"] = 7, 130, 251
+    w = oracle.build(p2, leaf_cap=30, max_level=12, sampling=oracle.WEIGHTED)
+    for f in ("level", "key", "count", "offset"):
+        assert np.array_equal(a[f], w[f])
+    assert np.array_equal(a["voxels"][:, :4], w["voxels"][:, :4])
+    assert np.all(w["voxels"][:, 4:] == np.array([7, 130, 251, 255], np.uint8))
+
+
+def test_weighted_differs_from_average_where_neighbours_overlap():
+    # a surface with several samples per cell and two halves of different
+    # colour: cells along the seam mix both sides, cells far from it do not
+    p = synth.terrain(60_000, seed=4)
+    p["r"] = np.where(p["x"] < np.median(p["x"]), 0, 240)
+    p["g"] = 100
+    a = oracle.build(p, leaf_cap=2000, max_level=12)
+    w = oracle.build(p, leaf_cap=2000, max_level=12, sampling=oracle.WEIGHTED)
+    assert np.array_equal(a["voxels"][:, :4], w["voxels"][:, :4])
+    assert np.all(w["voxels"][:, 5] == 100)
+    mixed = (w["voxels"][:, 4] != 0) & (w["voxels"][:, 4] != 240)
+    mixed_avg = (a["voxels"][:, 4] != 0) & (a["voxels"][:, 4] != 240)
+    assert mixed_avg.sum() < mixed.sum() < len(w["voxels"]) // 2
 
 
 def test_constant_colour_gives_constant_voxels():
