@@ -20,7 +20,8 @@ Beside it, on the same box and in the same run:
            copy), against the same requests built one by one;
   full precision: the plain build again with a full-precision record (input
            coordinates of the cell's accepted sample, voxel colour) for every
-           voxel of the lower levels.
+           voxel of the lower levels;
+  weighted: the same cloud with the neighbourhood-weighted average.
 
 Prints one JSON line with the throughput (points/s), the roofline of the
 dominant kernel (algorithmic bytes per launch over its average duration,
@@ -278,6 +279,8 @@ def main():
     ap.add_argument("--serve-tiles", type=int, default=4)
     ap.add_argument("--full-precision-steps", type=int, default=5,
                     help="builds of the same cloud with full-precision lower levels (0 = skip)")
+    ap.add_argument("--weighted-steps", type=int, default=3,
+                    help="builds of the same cloud with the neighbourhood-weighted average (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -352,29 +355,33 @@ def main():
     whole_alg = sum(stage_bytes(k, n, ids) for k in single)
     nodes, voxels = infos[-1]
 
-    full = None
-    if args.full_precision_steps > 0:
-        # same cloud and parameters, plus a full-precision record (accepted
-        # sample's coordinates, voxel colour) for every voxel
-        pf = lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling, timing=True,
-                             full_precision=True)
+    def variant(steps, **kw):
+        """The same cloud built `steps` times with other parameters (one warm-up)."""
+        pv = lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, timing=True, **kw)
 
-        def fstep():
-            t = lod.lod_build(dev, params=pf, stream=stream)
+        def vstep():
+            t = lod.lod_build(dev, params=pv, stream=stream)
             tm = t.timings()
             t.free()
             return tm
 
-        fstep()
+        vstep()
         torch.cuda.synchronize()
-        f0 = time.perf_counter()
-        ftm = [fstep() for _ in range(args.full_precision_steps)]
+        v0 = time.perf_counter()
+        vtm = [vstep() for _ in range(steps)]
         torch.cuda.synchronize()
-        fms = 1e3 * (time.perf_counter() - f0) / args.full_precision_steps
-        full = {"ms_per_build": round(fms, 4), "points_per_s": round(n / (fms * 1e-3), 1),
-                "vs_plain": round(fms / ms_per_step, 3), "steps": args.full_precision_steps,
-                "leaf_voxels_ms": round(float(np.mean([t["leaf_voxels"] for t in ftm])), 4),
-                "levels_ms": round(float(np.mean([t["levels"] for t in ftm])), 4)}
+        vms = 1e3 * (time.perf_counter() - v0) / steps
+        return {"ms_per_build": round(vms, 4), "points_per_s": round(n / (vms * 1e-3), 1),
+                "vs_plain": round(vms / ms_per_step, 3), "steps": steps,
+                "leaf_voxels_ms": round(float(np.mean([t["leaf_voxels"] for t in vtm])), 4),
+                "levels_ms": round(float(np.mean([t["levels"] for t in vtm])), 4)}
+
+    # same cloud and parameters, plus a full-precision record (accepted
+    # sample's coordinates, voxel colour) for every voxel
+    full = variant(args.full_precision_steps, sampling=sampling, full_precision=True) \
+        if args.full_precision_steps > 0 else None
+    # the neighbourhood-weighted average on the same cloud
+    weighted = variant(args.weighted_steps, sampling=3) if args.weighted_steps > 0 else None
 
     cpu = None
     if args.cpu_sample > 0:
@@ -422,6 +429,7 @@ def main():
         "nodes": nodes,
         "voxels": voxels,
         "full_precision": full,
+        "weighted": weighted,
         "batched": batched,
         "served": served,
     }

@@ -68,8 +68,18 @@ typedef struct {
  *                    the sample with the largest (h(id, seed) << 32 | id)
  *                    wins, h = high 32 bits of the SplitMix64 output function
  *                    of (seed << 32 | id).
+ *   LOD_WEIGHTED     neighbourhood-weighted average (Sec. 4.2.4): every
+ *                    sample adds w * (R, G, B) and w to the 2x2x2 cells of
+ *                    the node's grid around it, w = 1 - distance to the cell
+ *                    centre in cells, clamped at 0; only a sample's own cell
+ *                    is occupied (the same cells as LOD_AVERAGE); colour =
+ *                    floor(sum(w * c) / sum(w)), A = 255.  Exact reading: a
+ *                    point sits at the centre of its 2^21-grid cell, a child
+ *                    voxel at the centre of its cell; w is 65536 -
+ *                    floor(65536 * distance) from an exact integer square
+ *                    root.  Slower than the other modes (global atomics).
  * Pick modes copy the winner's R, G, B, A and record its input index. */
-typedef enum { LOD_AVERAGE = 0, LOD_PICK_FIRST = 1, LOD_PICK_RANDOM = 2 } lod_sampling;
+typedef enum { LOD_AVERAGE = 0, LOD_PICK_FIRST = 1, LOD_PICK_RANDOM = 2, LOD_WEIGHTED = 3 } lod_sampling;
 
 enum {
   LOD_FLAG_POINT_IDS = 1, /* keep each leaf point's input index (implied by pick modes) */
@@ -78,9 +88,9 @@ enum {
    * quantised voxel cells, every inner-node sample is also given as a 16-byte
    * record with the input coordinates of an accepted sample of its cell and
    * the voxel's colour (voxel_points).  Pick modes accept the picked sample;
-   * LOD_AVERAGE accepts the sample with the smallest input index in the cell
+   * the average modes accept the sample with the smallest input index in the cell
    * (the arg-min over all points of the subtree that fall in the cell) and
-   * keeps the averaged colour.  voxel_ids then holds the accepted sample's
+   * keep their (weighted) average colour.  voxel_ids then holds the accepted sample's
    * index in every mode. */
   LOD_FLAG_FULL_PRECISION = 4
 };

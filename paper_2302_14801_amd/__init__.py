@@ -6,7 +6,8 @@ The work runs in ``liblod.so`` (hand-written HIP kernels behind the C ABI in
 ``include/lod.h``); this package is a thin ctypes binding with the same names.
 Importing it loads the library and raises if it has not been built.
 """
-from .binding import (LOD_AVERAGE, LOD_FLAG_FULL_PRECISION, LOD_PICK_FIRST, LOD_PICK_RANDOM, LodError, Server, Tree,  # noqa: F401
+from .binding import (LOD_AVERAGE, LOD_FLAG_FULL_PRECISION, LOD_PICK_FIRST, LOD_PICK_RANDOM, LOD_WEIGHTED,  # noqa: F401
+                      LodError, Server, Tree,
                       load_library, lod_build, lod_build_batch, lod_poll, lod_server_create,
                       lod_server_destroy, lod_submit, lod_tree_free, lod_tree_view_get, make_params)
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblod.so")
 LOD_OK, LOD_PENDING = 0, 1
 LOD_ERR_INVALID, LOD_ERR_NONFINITE, LOD_ERR_OOM, LOD_ERR_CAPACITY = -1, -2, -3, -4
 LOD_ERR_TOO_LARGE, LOD_ERR_UNKNOWN_TICKET, LOD_ERR_HIP = -5, -6, -7
-LOD_AVERAGE, LOD_PICK_FIRST, LOD_PICK_RANDOM = 0, 1, 2
+LOD_AVERAGE, LOD_PICK_FIRST, LOD_PICK_RANDOM, LOD_WEIGHTED = 0, 1, 2, 3
 LOD_FLAG_POINT_IDS = 1
 LOD_FLAG_TIMING = 2
 LOD_FLAG_FULL_PRECISION = 4

@@ -64,6 +64,11 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
                          const TreeInfo* trees, const uint32_t* icnt, const void* desc, const uint64_t* T1,
                          const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
                          hipStream_t s);
+// Neighbourhood-weighted colours of all inner voxels (after the average
+// build): hash of (node, cell) -> voxel, then per level splat and finalize.
+void launch_weighted(const Nodes& nodes, uint32_t num_nodes, uint32_t deepest, const TreeInfo* trees, const Cube* cube,
+                     const void* Y, uint64_t* vox, unsigned long long* hkeys, uint32_t* hvals, uint64_t hmask,
+                     unsigned long long* acc, hipStream_t s);
 // Full-precision records (input coordinates of the accepted sample, voxel
 // colour) of the vtotal voxels of a call.
 void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,

@@ -134,7 +134,7 @@ struct Workspace {
   Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_tree;
   Scratch c_level, c_leaf, c_mask, c_key, c_npts, c_count, c_first, c_off, c_cover, c_grid, c_parent, c_tree;
   Scratch t2, t2id, icnt, idesc, iself, v_sz, v_dfs, v_dfsn, v_psize, v_poff, v_selfc, v_selfid;
-  Scratch state, bstate, clouds, trees, nbeg;
+  Scratch state, bstate, clouds, trees, nbeg, whkeys, whvals, wacc;
   Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs;
   std::vector<void*> retired;  // outgrown blocks, released when the build's stream has drained
   hipEvent_t ev[16] = {};
@@ -146,7 +146,7 @@ struct Workspace {
             &c_level, &c_leaf,  &c_mask,  &c_key,   &c_npts,   &c_count, &c_first,  &c_off,   &c_cover,
             &c_grid,  &c_parent, &c_tree, &t2,      &t2id,     &icnt,    &idesc,    &iself,   &v_sz,
             &v_dfs,   &v_dfsn,  &v_psize, &v_poff,  &v_selfc,  &v_selfid, &state,   &bstate,  &clouds,
-            &trees,   &nbeg};
+            &trees,   &nbeg,    &whkeys,  &whvals,  &wacc};
   }
   Workspace() {
     for (Scratch* sc : scratches()) sc->retired = &retired;
@@ -252,6 +252,7 @@ struct Plan {
   uint32_t mode;  // voxel-stage mode: the sampling strategy, or 3 (average with accepted ids)
   bool ids;
   bool full;      // full-precision records of the voxels
+  bool weighted;  // neighbourhood-weighted colours, rewritten after the average build
 };
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -266,8 +267,10 @@ Plan make_plan(uint64_t n_typical, uint64_t n_total, const lod_params& p) {
   if (p.tune_levels0) pl.E0 = std::min<uint32_t>(4, p.tune_levels0);
   if (p.tune_levels1) pl.E1 = std::min<uint32_t>(4, p.tune_levels1);
   pl.full = (p.flags & LOD_FLAG_FULL_PRECISION) != 0;
-  pl.mode = p.sampling == LOD_AVERAGE && pl.full ? 3u : p.sampling;
-  pl.ids = p.sampling != LOD_AVERAGE || (p.flags & LOD_FLAG_POINT_IDS) || pl.full;
+  pl.weighted = p.sampling == LOD_WEIGHTED;
+  const bool averaging = p.sampling == LOD_AVERAGE || pl.weighted;
+  pl.mode = averaging ? (pl.full ? 3u : 0u) : p.sampling;
+  pl.ids = !averaging || (p.flags & LOD_FLAG_POINT_IDS) || pl.full;
   // chunks are whole numbers of insert rounds (about 64k points for large
   // inputs, two rounds in the middle range and for refinements)
   const uint32_t R = scatter_round(pl.ids);
@@ -609,6 +612,20 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   uint64_t* vox = arena->alloc<uint64_t>(std::max<uint64_t>(vtotal, 1));
   uint32_t* vids = pl.mode ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
   launch_voxel_gather(pl.mode, nd, vt, num_nodes, tinfo, icnt, desc, T1, Xid, T2, T2id, vox, vids, s);
+  if (pl.weighted && vtotal) {
+    if (vtotal > 0xffffffffull) fail(LOD_ERR_INVALID, "weighted sampling handles at most 2^32 - 1 voxels per call");
+    // (node, cell) -> voxel table at most half full, per-voxel weighted sums
+    uint64_t hsize = 1024;
+    while (hsize < 2 * vtotal) hsize *= 2;
+    unsigned long long* hkeys = w.whkeys.get<unsigned long long>(dev, hsize);
+    uint32_t* hvals = w.whvals.get<uint32_t>(dev, hsize);
+    unsigned long long* wacc = w.wacc.get<unsigned long long>(dev, 4 * vtotal);
+    HIPCHK(hipMemsetAsync(hkeys, 0, 8 * hsize, s));
+    HIPCHK(hipMemsetAsync(wacc, 0, 32 * vtotal, s));
+    uint32_t deepest = 0;
+    for (uint32_t c = 0; c < nc; ++c) deepest = std::max(deepest, hti[c].deepest);
+    launch_weighted(nd, num_nodes, deepest, tinfo, cube, Y, vox, hkeys, hvals, hsize - 1, wacc, s);
+  }
   lod_point* vpts = nullptr;
   if (pl.full) {
     vpts = arena->alloc<lod_point>(std::max<uint64_t>(vtotal, 1));
@@ -686,7 +703,7 @@ namespace {
 
 lod_status check_params(const lod_params* p) {
   if (!p) return LOD_ERR_INVALID;
-  if (p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 2) return LOD_ERR_INVALID;
+  if (p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 3) return LOD_ERR_INVALID;
   if (p->tune_levels0 > 4 || p->tune_levels1 > 4) return LOD_ERR_INVALID;
   return LOD_OK;
 }

@@ -48,22 +48,23 @@ RANDOM_CASES = [(50, 1, 2), (300, 3, 4), (800, 7, 12), (2000, 50, 12), (1500, 1,
                 (20000, 200, 12), (60000, 1000, 14), (150000, 4000, 12)]
 
 
-@pytest.mark.parametrize("sampling", [0, 1, 2])
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
 @pytest.mark.parametrize("n,T,ml", RANDOM_CASES)
 def test_uniform_clouds(lod, n, T, ml, sampling):
     p = synth.uniform_cloud(n, 1000 + n, lo=(-3, 10, 100), hi=(5, 12, 101))
     check(lod, p, T, ml, sampling, seed=77)
 
 
-@pytest.mark.parametrize("sampling", [0, 1, 2])
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
 def test_terrain_small(lod, sampling):
     p = synth.terrain(200_000, seed=5)
     check(lod, p, T=5000, ml=12, sampling=sampling, seed=3)
 
 
-def test_aerial_small(lod):
+@pytest.mark.parametrize("sampling", [0, 3])
+def test_aerial_small(lod, sampling):
     p = synth.aerial(400_000, seed=2)
-    check(lod, p, T=10000, ml=12)
+    check(lod, p, T=10000, ml=12, sampling=sampling)
 
 
 def test_scan_small(lod):
@@ -99,7 +100,7 @@ def test_identical_points_chain_to_depth_limit(lod):
     p["x"], p["y"], p["z"] = 1.5, -2.0, 7.0
     p["r"] = np.arange(1000) % 256
     p[-1]["x"] = 9.0
-    for s in (0, 1, 2):
+    for s in (0, 1, 2, 3):
         g, _ = check(lod, p, T=10, ml=9, sampling=s)
         assert g["level"].max() == 9
 
@@ -114,6 +115,7 @@ def test_huge_micro_bucket_wide_path(lod):
     p["b"] = rng.integers(0, 256, len(p))
     p["x"][-10:] = rng.uniform(0, 10, 10).astype(np.float32)
     check(lod, p, T=100, ml=5)
+    check(lod, p, T=100, ml=5, sampling=3)
 
 
 def test_lattice_and_max_face(lod):
@@ -151,7 +153,7 @@ def test_nonfinite_rejected(lod):
 
 def test_invalid_params_rejected(lod):
     d = to_dev(synth.uniform_cloud(100, 1))
-    for kw in ({"leaf_cap": 0}, {"max_level": 15}, {"sampling": 3}):
+    for kw in ({"leaf_cap": 0}, {"max_level": 15}, {"sampling": 4}):
         with pytest.raises(lod.LodError) as e:
             lod.lod_build(d, **kw)
         assert e.value.status == -1
@@ -183,7 +185,7 @@ def test_input_order_invariance(lod):
     check(lod, p[perm], T=5000, sampling=1)
 
 
-@pytest.mark.parametrize("sampling", [0, 2])
+@pytest.mark.parametrize("sampling", [0, 2, 3])
 def test_batch_equals_single_builds(lod, sampling):
     sizes = [3000, 50, 120000, 0, 40000, 777]
     pts, offs = synth.batch_chunks(sizes, seed=4)
@@ -237,7 +239,7 @@ def check_full(g, o, points):
         assert np.array_equal(g["voxel_points"][go:go + c], o["voxel_points"][oo:oo + c]), f"records of node {i}"
 
 
-@pytest.mark.parametrize("sampling", [0, 1, 2])
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
 def test_full_precision_lower_levels(lod, sampling):
     p = synth.terrain(200_000, seed=5)
     print(f"full precision n={len(p)} sampling={sampling}", flush=True)
