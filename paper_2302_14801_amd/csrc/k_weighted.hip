@@ -21,8 +21,10 @@
 // those of the cell average (the same occupancy rule), so this pass runs after
 // the average build and rewrites the colours, level by level from the deepest
 // inner level up: a node's samples include its inner children's weighted
-// voxels.  A hash table over all inner voxels, keyed by (node, cell), finds
-// the position of a target cell.
+// voxels.  Before a level is sampled, each of its inner nodes gets an
+// occupancy bitmap of its 2^21 cells in Morton order plus, per 64-bit word,
+// the list index of the word's first voxel: the position of an occupied cell
+// is that index plus the set bits below it (the lists are sorted by cell).
 //
 // A child's samples (its points in leaf order, or its voxels in Morton order)
 // are taken in chunks of consecutive samples, which cover a compact region of
@@ -40,67 +42,78 @@ namespace lod {
 constexpr int kWSplit = 16;  // workgroups per child node in the splat
 constexpr uint32_t kWeightOne = 65536;
 
-__device__ __forceinline__ uint64_t whash_slot(uint64_t key, uint64_t mask) {
-  return ((key * 0x9E3779B97F4A7C15ull) >> 24) & mask;
-}
-__device__ __forceinline__ uint64_t whash_key(uint32_t node, uint32_t code) {
-  return (((uint64_t)node << 21) | code) + 1;  // 0 marks an empty slot
-}
-
-// floor(sqrt(x)) for x < 2^52: a correctly rounded double square root is
-// within one of it; the integer checks settle the last step.
+// floor(sqrt(x)) for x < 2^40: the single-precision square root of x
+// (rounded to 24 bits) is within 2^-4 of sqrt(x) there, so its truncation is
+// within one of the answer; the integer checks settle the last step.
 __device__ __forceinline__ uint64_t isqrt_u64(uint64_t x) {
-  uint64_t r = (uint64_t)__dsqrt_rn((double)x);
+  uint64_t r = (uint64_t)__fsqrt_rn((float)x);
   for (int i = 0; i < 2 && r * r > x; ++i) --r;
   for (int i = 0; i < 2 && (r + 1) * (r + 1) <= x; ++i) ++r;
   return r;
 }
 
-// kWSplit workgroups per inner node: insert (node, cell) -> voxel index for
-// each of its voxels (linear probing; the table holds at least twice the
-// voxels).
-__global__ void __launch_bounds__(256) k_whash_insert(Nodes nodes, uint32_t num_nodes, const TreeInfo* __restrict__ trees,
-                                                      const uint64_t* __restrict__ vox, unsigned long long* hkeys,
-                                                      uint32_t* hvals, uint64_t mask) {
+constexpr uint32_t kWWords = 1u << 15;  // 64-bit words of a node's 2^21-cell bitmap
+
+// A slot (bitmap) for every inner node at level L.
+__global__ void __launch_bounds__(256) k_wslots(Nodes nodes, uint32_t num_nodes, uint32_t L, uint32_t* wslot,
+                                                uint32_t* slot_ctr) {
+  const uint32_t n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= num_nodes || nodes.is_leaf[n] || nodes.level[n] != L) return;
+  wslot[n] = atomicAdd(slot_ctr + L, 1u);
+}
+
+// The bitmap words of the inner nodes at level L (set = true) or their reset
+// (set = false): the first voxel of every 64-cell word writes the whole word
+// (the word's voxels follow it in the list) and, when setting, its own index.
+__global__ void __launch_bounds__(256) k_wbits(Nodes nodes, uint32_t num_nodes, uint32_t L,
+                                               const TreeInfo* __restrict__ trees, const uint64_t* __restrict__ vox,
+                                               const uint32_t* __restrict__ wslot, unsigned long long* bits,
+                                               uint32_t* wpre, bool set) {
   const uint32_t n = blockIdx.x;
-  if (n >= num_nodes || nodes.is_leaf[n]) return;
+  if (n >= num_nodes || nodes.is_leaf[n] || nodes.level[n] != L) return;
   const uint64_t base = trees[nodes.tree[n]].vbase + nodes.offset[n];
   const uint32_t cnt = nodes.count[n];
+  const uint64_t sb = (uint64_t)wslot[n] * kWWords;
   for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < cnt; i += kWSplit * 256) {
-    const uint64_t v = vox[base + i];
-    const uint64_t key = whash_key(n, morton7((uint32_t)v & 0xffu, (uint32_t)(v >> 8) & 0xffu, (uint32_t)(v >> 16) & 0xffu));
-    uint64_t s = whash_slot(key, mask);
-    for (uint64_t probe = 0; probe <= mask; ++probe) {
-      const unsigned long long prev = atomicCAS(&hkeys[s], 0ull, (unsigned long long)key);
-      if (prev == 0ull || prev == key) {
-        hvals[s] = (uint32_t)(base + i);
-        break;
-      }
-      s = (s + 1) & mask;
+    const uint32_t word = voxel_code(vox[base + i]) >> 6;
+    if (i > 0 && (voxel_code(vox[base + i - 1]) >> 6) == word) continue;
+    if (!set) {
+      bits[sb + word] = 0ull;
+      continue;
     }
+    unsigned long long b = 0;
+    for (uint32_t j = i; j < cnt && j < i + 64; ++j) {
+      const uint32_t c = voxel_code(vox[base + j]);
+      if ((c >> 6) != word) break;
+      b |= 1ull << (c & 63u);
+    }
+    bits[sb + word] = b;
+    wpre[sb + word] = i;
   }
 }
 
-__device__ __forceinline__ uint32_t whash_find(const unsigned long long* __restrict__ hkeys,
-                                               const uint32_t* __restrict__ hvals, uint64_t mask, uint64_t key) {
-  uint64_t s = whash_slot(key, mask);
-  for (uint64_t probe = 0; probe <= mask; ++probe) {
-    const uint64_t k = hkeys[s];
-    if (k == key) return hvals[s];
-    if (k == 0) break;
-    s = (s + 1) & mask;
-  }
-  return 0xffffffffu;
+// Voxel index of cell `code` of the node whose bitmap starts at sb and whose
+// list starts at vbase, or ~0 when the cell is not occupied.
+__device__ __forceinline__ uint32_t wfind(const unsigned long long* __restrict__ bits, const uint32_t* __restrict__ wpre,
+                                          uint64_t sb, uint64_t vbase, uint32_t code) {
+  const unsigned long long word = bits[sb + (code >> 6)];
+  const uint32_t b = code & 63u;
+  if (!((word >> b) & 1ull)) return 0xffffffffu;
+  return (uint32_t)(vbase + wpre[sb + (code >> 6)] + (uint32_t)__popcll(word & ((1ull << b) - 1ull)));
 }
 
 constexpr int kWChunk = 256;       // samples per chunk (one per thread)
 constexpr uint32_t kWSlots = 1024;  // LDS hash slots per workgroup
 constexpr int kWProbe = 32;         // LDS probes before a splat goes global
 
+// A chunk puts at most one splat of each sample on a cell, so a cell's chunk
+// sums stay below 256 * 65536 * 255 < 2^32 (colour) and 2^24 (weight): two
+// 32-bit sums share each 64-bit LDS word.
 struct WLocal {
   uint32_t key[kWSlots];  // cell code + 1 (0 = empty)
-  unsigned long long sum[kWSlots][4];
+  unsigned long long rg[kWSlots], bw[kWSlots];  // R | G << 32, B | w << 32
 };
+static_assert(kWChunk <= 256, "packed chunk sums need at most 256 samples per chunk");
 
 __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi, uint64_t w, uint64_t R, uint64_t Gc,
                                             uint64_t B) {
@@ -113,9 +126,9 @@ __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi
 
 // Splat one sample of node A (level L, grid origin G = A's coordinates * 128,
 // per axis) at pos2 with colour rgba into the workgroup's LDS table.
-__device__ __forceinline__ void wsplat(uint32_t A, uint32_t L, const uint32_t G[3], const uint64_t pos2[3], uint32_t rgba,
-                                       WLocal& lt, const unsigned long long* __restrict__ hkeys,
-                                       const uint32_t* __restrict__ hvals, uint64_t mask, unsigned long long* acc) {
+__device__ __forceinline__ void wsplat(uint32_t L, const uint32_t G[3], const uint64_t pos2[3], uint32_t rgba, WLocal& lt,
+                                       const unsigned long long* __restrict__ bits, const uint32_t* __restrict__ wpre,
+                                       uint64_t sb, uint64_t vbase, unsigned long long* acc) {
   const uint32_t cs = 15 - L;  // log2 of A's cell size in pos2 units
   int64_t cand[3][2];
 #pragma unroll
@@ -154,17 +167,15 @@ __device__ __forceinline__ void wsplat(uint32_t A, uint32_t L, const uint32_t G[
     for (int probe = 0; probe < kWProbe; ++probe) {
       const uint32_t prev = atomicCAS(&lt.key[slot], 0u, code + 1);
       if (prev == 0u || prev == code + 1) {
-        atomicAdd(&lt.sum[slot][0], (unsigned long long)(w * R));
-        atomicAdd(&lt.sum[slot][1], (unsigned long long)(w * Gc));
-        atomicAdd(&lt.sum[slot][2], (unsigned long long)(w * B));
-        atomicAdd(&lt.sum[slot][3], (unsigned long long)w);
+        atomicAdd(&lt.rg[slot], (unsigned long long)((w * R) | ((w * Gc) << 32)));
+        atomicAdd(&lt.bw[slot], (unsigned long long)((w * B) | (w << 32)));
         done = true;
         break;
       }
       slot = (slot + 1) & (kWSlots - 1);
     }
     if (!done) {  // the LDS table is full around this code: straight to the global sums
-      const uint32_t vi = whash_find(hkeys, hvals, mask, whash_key(A, code));
+      const uint32_t vi = wfind(bits, wpre, sb, vbase, code);
       if (vi != 0xffffffffu) wadd_global(acc, vi, w, R, Gc, B);
     }
   }
@@ -175,9 +186,9 @@ __device__ __forceinline__ void wsplat(uint32_t A, uint32_t L, const uint32_t G[
 __global__ void __launch_bounds__(256) k_wsplat(Nodes nodes, uint32_t num_nodes, uint32_t L,
                                                 const TreeInfo* __restrict__ trees, const Cube* cube,
                                                 const uint4* __restrict__ Y, const uint64_t* __restrict__ vox,
-                                                const unsigned long long* __restrict__ hkeys,
-                                                const uint32_t* __restrict__ hvals, uint64_t mask,
-                                                unsigned long long* acc) {
+                                                const uint32_t* __restrict__ wslot,
+                                                const unsigned long long* __restrict__ bits,
+                                                const uint32_t* __restrict__ wpre, unsigned long long* acc) {
   __shared__ WLocal lt;
   const uint32_t n = blockIdx.x, t = threadIdx.x;
   if (n >= num_nodes || nodes.level[n] != L + 1) return;
@@ -186,6 +197,7 @@ __global__ void __launch_bounds__(256) k_wsplat(Nodes nodes, uint32_t num_nodes,
   const uint32_t A = nodes.parent[n];
   const uint64_t ka = nodes.key[A];
   const uint32_t G[3] = {compact21(ka), compact21(ka >> 1), compact21(ka >> 2)};
+  const uint64_t sb = (uint64_t)wslot[A] * kWWords, vbase = trees[nodes.tree[A]].vbase + nodes.offset[A];
   const bool leaf = nodes.is_leaf[n] != 0;
   const CubeD cd = load_cube(cube + nodes.tree[n]);
   const uint64_t kn = nodes.key[n];
@@ -193,7 +205,7 @@ __global__ void __launch_bounds__(256) k_wsplat(Nodes nodes, uint32_t num_nodes,
   const uint64_t first = leaf ? nodes.offset[n] : trees[nodes.tree[n]].vbase + nodes.offset[n];
   for (uint32_t i = t; i < kWSlots; i += 256) {
     lt.key[i] = 0;
-    lt.sum[i][0] = lt.sum[i][1] = lt.sum[i][2] = lt.sum[i][3] = 0;
+    lt.rg[i] = lt.bw[i] = 0;
   }
   __syncthreads();
   for (uint32_t c0 = blockIdx.y * kWChunk; c0 < cnt; c0 += kWSplit * kWChunk) {
@@ -218,7 +230,7 @@ __global__ void __launch_bounds__(256) k_wsplat(Nodes nodes, uint32_t num_nodes,
         }
         rgba = (uint32_t)(v >> 32);
       }
-      wsplat(A, L, G, pos2, rgba, lt, hkeys, hvals, mask, acc);
+      wsplat(L, G, pos2, rgba, lt, bits, wpre, sb, vbase, acc);
     }
     __syncthreads();
     // each touched cell once to the global sums (if it is occupied), then
@@ -226,16 +238,17 @@ __global__ void __launch_bounds__(256) k_wsplat(Nodes nodes, uint32_t num_nodes,
     for (uint32_t k = t; k < kWSlots; k += 256) {
       const uint32_t key = lt.key[k];
       if (key == 0u) continue;
-      const uint32_t vi = whash_find(hkeys, hvals, mask, whash_key(A, key - 1));
+      const uint32_t vi = wfind(bits, wpre, sb, vbase, key - 1);
       if (vi != 0xffffffffu) {
         unsigned long long* a4 = acc + 4ull * vi;
-        atomicAdd(a4 + 0, lt.sum[k][0]);
-        atomicAdd(a4 + 1, lt.sum[k][1]);
-        atomicAdd(a4 + 2, lt.sum[k][2]);
-        atomicAdd(a4 + 3, lt.sum[k][3]);
+        const unsigned long long rg = lt.rg[k], bw = lt.bw[k];
+        atomicAdd(a4 + 0, rg & 0xffffffffull);
+        atomicAdd(a4 + 1, rg >> 32);
+        atomicAdd(a4 + 2, bw & 0xffffffffull);
+        atomicAdd(a4 + 3, bw >> 32);
       }
       lt.key[k] = 0;
-      lt.sum[k][0] = lt.sum[k][1] = lt.sum[k][2] = lt.sum[k][3] = 0;
+      lt.rg[k] = lt.bw[k] = 0;
     }
     __syncthreads();
   }
@@ -261,18 +274,26 @@ __global__ void __launch_bounds__(256) k_wfinal(Nodes nodes, uint32_t num_nodes,
 }
 
 void launch_weighted(const Nodes& nodes, uint32_t num_nodes, uint32_t deepest, const TreeInfo* trees, const Cube* cube,
-                     const void* Y, uint64_t* vox, unsigned long long* hkeys, uint32_t* hvals, uint64_t hmask,
-                     unsigned long long* acc, hipStream_t s) {
+                     const void* Y, uint64_t* vox, uint32_t* wslot, uint32_t* slot_ctr, unsigned long long* bits,
+                     uint32_t* wpre, unsigned long long* acc, hipStream_t s) {
   if (!num_nodes || deepest == 0) return;
-  hipLaunchKernelGGL(k_whash_insert, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, trees, (const uint64_t*)vox,
-                     hkeys, hvals, hmask);
   for (int L = (int)deepest - 1; L >= 0; --L) {
-    hipLaunchKernelGGL(k_wsplat, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, (uint32_t)L, trees, cube,
-                       (const uint4*)Y, (const uint64_t*)vox, (const unsigned long long*)hkeys, (const uint32_t*)hvals,
-                       hmask, acc);
-    hipLaunchKernelGGL(k_wfinal, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, (uint32_t)L, trees, vox,
+    const uint32_t l = (uint32_t)L;
+    hipLaunchKernelGGL(k_wslots, dim3((num_nodes + 255) / 256), dim3(256), 0, s, nodes, num_nodes, l, wslot, slot_ctr);
+    hipLaunchKernelGGL(k_wbits, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees,
+                       (const uint64_t*)vox, (const uint32_t*)wslot, bits, wpre, true);
+    hipLaunchKernelGGL(k_wsplat, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees, cube,
+                       (const uint4*)Y, (const uint64_t*)vox, (const uint32_t*)wslot, (const unsigned long long*)bits,
+                       (const uint32_t*)wpre, acc);
+    hipLaunchKernelGGL(k_wfinal, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees, vox,
                        (const unsigned long long*)acc);
+    // the bitmaps are cleared word by word (from the unchanged cell lists) for
+    // the next level's nodes
+    hipLaunchKernelGGL(k_wbits, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees,
+                       (const uint64_t*)vox, (const uint32_t*)wslot, bits, wpre, false);
   }
 }
+
+uint64_t weighted_bitmap_words() { return kWWords; }
 
 }  // namespace lod

@@ -65,10 +65,14 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
                          const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
                          hipStream_t s);
 // Neighbourhood-weighted colours of all inner voxels (after the average
-// build): hash of (node, cell) -> voxel, then per level splat and finalize.
+// build), level by level: occupancy bitmaps of the level's nodes (one slot of
+// weighted_bitmap_words() 64-bit words and as many u32 word prefixes each,
+// bitmaps zero on entry and on return), splat, colours.  slot_ctr: 16 zeroed
+// counters; acc: 4 zeroed u64 per voxel.
 void launch_weighted(const Nodes& nodes, uint32_t num_nodes, uint32_t deepest, const TreeInfo* trees, const Cube* cube,
-                     const void* Y, uint64_t* vox, unsigned long long* hkeys, uint32_t* hvals, uint64_t hmask,
-                     unsigned long long* acc, hipStream_t s);
+                     const void* Y, uint64_t* vox, uint32_t* wslot, uint32_t* slot_ctr, unsigned long long* bits,
+                     uint32_t* wpre, unsigned long long* acc, hipStream_t s);
+uint64_t weighted_bitmap_words();
 // Full-precision records (input coordinates of the accepted sample, voxel
 // colour) of the vtotal voxels of a call.
 void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,
