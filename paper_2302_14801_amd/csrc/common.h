@@ -227,6 +227,18 @@ struct Nodes {
   uint32_t* tree;   // input cloud (tree) of the node
 };
 
+// A voxel-stage work item (one leaf and one of its 8 child cells): what the
+// leaf kernel, the gather and the weighted pass need about it, gathered once
+// per item so that a leaf workgroup waits for one load before its points.
+struct ItemDesc {
+  uint32_t I0, P;  // first point and points of the item (P = 0: nothing to do)
+  uint32_t lvl, tree;
+  uint64_t lkey;   // the leaf's key
+  uint64_t t2;     // start of the item's block of coarse lists
+  uint32_t mc[8];  // points of each micro-bucket (cells two levels below the leaf), in order
+};
+static_assert(sizeof(ItemDesc) == 64, "ItemDesc is read as four 16-byte words");
+
 // Where a finished tree sits in the build's arrays (device copy per tree).
 struct TreeInfo {
   uint32_t node_base;  // first node of the tree in the compact node table

@@ -267,17 +267,6 @@ __device__ __forceinline__ Item item_of(const Nodes& nodes, uint32_t n, uint32_t
 
 // ------------------------------------------------------------ item descriptors
 //
-// What the leaf kernel and the gather need about a work item, gathered once
-// per item so that a leaf workgroup waits for one load before its points.
-struct ItemDesc {
-  uint32_t I0, P;  // first point and points of the item (P = 0: nothing to do)
-  uint32_t lvl, tree;
-  uint64_t lkey;   // the leaf's key
-  uint64_t t2;     // start of the item's block of coarse lists
-  uint32_t mc[8];  // points of each micro-bucket, in order
-};
-static_assert(sizeof(ItemDesc) == 64, "ItemDesc is read as four 16-byte words");
-
 // One thread per item.  Coarse-list blocks are handed out by a wave-wide
 // prefix sum and one atomic add per wave on bs->coarse_used.
 __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nodes, const GridDesc* __restrict__ grids,

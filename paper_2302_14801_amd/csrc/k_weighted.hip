@@ -254,6 +254,70 @@ __global__ void __launch_bounds__(256) k_wsplat(Nodes nodes, uint32_t num_nodes,
   }
 }
 
+// Leaf points sorted by their depth-1 cell (the parent's grid) inside each
+// micro-bucket, so that a chunk of consecutive points covers few cells.  The
+// order of points inside a leaf is free; the voxel lists are already built.
+// One workgroup per work item; micro-buckets of more than kWSortMax points
+// keep their order (the sums do not depend on it).
+constexpr uint32_t kWSortMax = 2048;
+__global__ void __launch_bounds__(256) k_wsort(const ItemDesc* __restrict__ desc, const Cube* cube, uint4* Y,
+                                               uint32_t* Yid) {
+  __shared__ uint4 sp[kWSortMax];
+  __shared__ uint32_t sid[kWSortMax];
+  __shared__ uint16_t scell[kWSortMax];
+  __shared__ uint32_t hist[4096];
+  __shared__ uint32_t sh[256 / 64 + 1];
+  const ItemDesc& d = desc[blockIdx.x];
+  const uint32_t P = d.P, t = threadIdx.x;
+  if (P == 0) return;
+  const CubeD cd = load_cube(cube + d.tree);
+  const uint32_t sub_bit = 15u - d.lvl;  // bit level of the depth-1 cells (level lvl + 6)
+  uint32_t off = d.I0;
+  for (uint32_t jm = 0; jm < 8; ++jm) {
+    const uint32_t cnt = d.mc[jm];
+    const uint32_t o = off;
+    off += cnt;
+    if (cnt < 2 || cnt > kWSortMax) continue;  // uniform
+    for (uint32_t i = t; i < 4096; i += 256) hist[i] = 0;
+    __syncthreads();
+    for (uint32_t i = t; i < cnt; i += 256) {
+      const uint4 v = Y[o + i];
+      sp[i] = v;
+      if (Yid) sid[i] = Yid[o + i];
+      const uint32_t c = point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, sub_bit, 4);
+      scell[i] = (uint16_t)c;
+      atomicAdd(&hist[c], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the 4096 counts (16 per thread)
+    uint32_t loc[16], run = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      loc[k] = hist[16 * t + k];
+      run += loc[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<256>(run, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      hist[16 * t + k] = ex;
+      ex += loc[k];
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < cnt; i += 256) {
+      const uint32_t pos = atomicAdd(&hist[scell[i]], 1u);
+      Y[o + pos] = sp[i];
+      if (Yid) Yid[o + pos] = sid[i];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_weighted_sort(uint32_t num_nodes, const void* desc, const Cube* cube, void* Y, uint32_t* Yid, hipStream_t s) {
+  if (!num_nodes) return;
+  hipLaunchKernelGGL(k_wsort, dim3(8 * num_nodes), dim3(256), 0, s, (const ItemDesc*)desc, cube, (uint4*)Y, Yid);
+}
+
 // Colours of the voxels of the inner nodes at level L from their sums
 // (kWSplit workgroups per node).
 __global__ void __launch_bounds__(256) k_wfinal(Nodes nodes, uint32_t num_nodes, uint32_t L,

@@ -73,6 +73,9 @@ void launch_weighted(const Nodes& nodes, uint32_t num_nodes, uint32_t deepest, c
                      const void* Y, uint64_t* vox, uint32_t* wslot, uint32_t* slot_ctr, unsigned long long* bits,
                      uint32_t* wpre, unsigned long long* acc, hipStream_t s);
 uint64_t weighted_bitmap_words();
+// Sort the points of every micro-bucket of every work item by depth-1 cell
+// (in place; ids follow when Yid is not NULL).
+void launch_weighted_sort(uint32_t num_nodes, const void* desc, const Cube* cube, void* Y, uint32_t* Yid, hipStream_t s);
 // Full-precision records (input coordinates of the accepted sample, voxel
 // colour) of the vtotal voxels of a call.
 void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,

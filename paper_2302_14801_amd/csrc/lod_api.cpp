@@ -633,6 +633,7 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     HIPCHK(hipMemsetAsync(wctr, 0, 64, s));
     HIPCHK(hipMemsetAsync(wbits, 0, 8 * words, s));
     HIPCHK(hipMemsetAsync(wacc, 0, 32 * vtotal, s));
+    launch_weighted_sort(num_nodes, desc, cube, Y, Yid, s);
     launch_weighted(nd, num_nodes, deepest, tinfo, cube, Y, vox, wslot, wctr, wbits, wpre, wacc, s);
   }
   lod_point* vpts = nullptr;
