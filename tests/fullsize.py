@@ -43,8 +43,9 @@ def multiset_hash(rows: np.ndarray) -> tuple:
 
 
 def check_build(g: dict, pts: np.ndarray, T: int, ML: int, subtree_picks: int = 4, seed: int = 7,
-                leaf_sample: int | None = None):
-    """g: the GPU tree copied to the host; pts: the input records."""
+                leaf_sample: int | None = None, sampling: int = 0):
+    """g: the GPU tree copied to the host; pts: the input records; sampling:
+    the mode of the build (the subtrees are rebuilt with it)."""
     N = len(pts)
     lo = np.array([pts["x"].min(), pts["y"].min(), pts["z"].min()], np.float32)
     hi = np.array([pts["x"].max(), pts["y"].max(), pts["z"].max()], np.float32)
@@ -103,7 +104,7 @@ def check_build(g: dict, pts: np.ndarray, T: int, ML: int, subtree_picks: int = 
         s = np.concatenate(sel[x])
         assert len(s) == npt[x]
         sub = np.ascontiguousarray(pts[s])
-        o = oracle.build(sub, leaf_cap=T, max_level=ML, cube_lo=lo, cube_side=side)
+        o = oracle.build(sub, leaf_cap=T, max_level=ML, sampling=sampling, cube_lo=lo, cube_side=side)
         ox = int(np.nonzero((o["level"] == L) & (o["key"] == kx))[0][0])
         gi, oi = canon.subtree_indices(g, x), canon.subtree_indices(o, ox)
         assert len(gi) == len(oi)

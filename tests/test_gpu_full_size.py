@@ -33,3 +33,40 @@ def test_aerial_100m_bench_configuration():
     del dev
     fullsize.log(f"{g['num_nodes']} nodes, {g['num_voxels']} voxels")
     fullsize.check_build(g, pts, T, ML)
+
+
+def test_aerial_20m_weighted_and_full_precision():
+    """The neighbourhood-weighted average on a 20M-point aerial cloud (T =
+    50 000): same cells as the average build, colours checked on sampled
+    subtrees rebuilt by the oracle; full-precision records of a pick build
+    are input records of their voxels' cells."""
+    import numpy as np
+    import torch
+
+    import paper_2302_14801_amd as lod
+
+    n = 20_000_000
+    fullsize.log("generating 20M")
+    host = torch.empty(n * 16, dtype=torch.uint8, pin_memory=True)
+    pts = host.numpy().view(synth.POINT_DTYPE)
+    synth.aerial(n, seed=5, out=pts)
+    dev = host.to("cuda:0")
+    fullsize.log("building (weighted, average, first with full precision)")
+    t = lod.lod_build(dev, leaf_cap=T, max_level=ML, sampling=3)
+    g = t.to_host()
+    t.free()
+    t = lod.lod_build(dev, leaf_cap=T, max_level=ML)
+    a = t.to_host()
+    t.free()
+    t = lod.lod_build(dev, leaf_cap=T, max_level=ML, sampling=1, full_precision=True)
+    f = t.to_host()
+    t.free()
+    del dev
+    for k in ("level", "key", "count", "offset"):
+        assert np.array_equal(g[k], a[k]), k
+    assert np.array_equal(g["voxels"][:, :4], a["voxels"][:, :4])
+    assert not np.array_equal(g["voxels"][:, 4:], a["voxels"][:, 4:])
+    raw = pts.view(np.uint8).reshape(-1, 16)
+    assert np.array_equal(f["voxel_points"], raw[f["voxel_ids"].astype(np.int64)])
+    fullsize.log("weighted cells equal the average's; full-precision records are input records")
+    fullsize.check_build(g, pts, T, ML, subtree_picks=2, leaf_sample=2000, sampling=3)
