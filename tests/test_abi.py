@@ -87,3 +87,13 @@ def test_struct_layouts_match_header(name, tmp_path):
     assert got[0] == ctypes.sizeof(cls)
     for f, off in zip(fields, got[1:]):
         assert getattr(cls, f).offset == off, f
+
+
+def test_binding_constants_match_header():
+    """Sampling modes, flags and status codes of the binding are the header's."""
+    from paper_2302_14801_amd import binding
+    text = open(HEADER).read()
+    want = {name: int(val) for name, val in re.findall(r"\b(LOD_[A-Z_]+)\s*=\s*(-?\d+)", text)}
+    for name in ("LOD_AVERAGE", "LOD_PICK_FIRST", "LOD_PICK_RANDOM", "LOD_WEIGHTED", "LOD_FLAG_POINT_IDS",
+                 "LOD_FLAG_TIMING", "LOD_FLAG_FULL_PRECISION", "LOD_ERR_INVALID"):
+        assert getattr(binding, name) == want[name], name
