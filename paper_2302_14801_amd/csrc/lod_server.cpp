@@ -127,7 +127,7 @@ extern "C" {
 
 lod_status lod_server_create(uint64_t hbm_budget_bytes, uint32_t max_inflight, const lod_params* p,
                              lod_server** out) {
-  if (!out || !p || p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 2 || max_inflight == 0 ||
+  if (!out || !p || p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 3 || max_inflight == 0 ||
       max_inflight > 64 || hbm_budget_bytes == 0) {
     lod_set_error("invalid server arguments");
     if (out) *out = nullptr;

@@ -85,9 +85,19 @@ def test_keep_ids_average(lod):
     assert g["point_ids"] is not None
 
 
-def test_empty(lod):
-    g = gpu_tree(lod, np.zeros(0, synth.POINT_DTYPE))
-    assert g["num_nodes"] == 0 and g["num_voxels"] == 0
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
+def test_empty(lod, sampling):
+    for fp in (False, True):
+        g = gpu_tree(lod, np.zeros(0, synth.POINT_DTYPE), sampling=sampling, full_precision=fp)
+        assert g["num_nodes"] == 0 and g["num_voxels"] == 0
+
+
+@pytest.mark.parametrize("sampling", [0, 3])
+def test_shallow_depth_limits(lod, sampling):
+    # depth limits 1 and 2: every inner node is a root or its child
+    p = synth.terrain(30_000, seed=14)
+    for ml in (1, 2):
+        check(lod, p, T=100, ml=ml, sampling=sampling)
 
 
 def test_single_point_and_small(lod):
@@ -307,6 +317,35 @@ def test_server_results_equal_alone_and_in_mix(lod):
     with pytest.raises(lod.LodError) as e:
         srv.poll(987654)
     assert e.value.status == -6
+    srv.destroy()
+
+
+def test_server_weighted_full_precision(lod):
+    # requests with the weighted mode and full-precision records through the
+    # server equal lod_build on the same points
+    sizes = [60_000, 1_000, 120_000, 0]
+    pts, offs = synth.batch_chunks(sizes, seed=17)
+    chunks = [np.ascontiguousarray(pts[offs[i]:offs[i + 1]]) for i in range(len(sizes))]
+    srv = lod.lod_server_create(8 << 30, 2, leaf_cap=3000, max_level=12, sampling=3, full_precision=True)
+    tickets = [srv.submit(c) for c in chunks]
+    import time
+    t0 = time.time()
+    for i, (tk, c) in enumerate(zip(tickets, chunks)):
+        r = srv.poll(tk)
+        while r is None:
+            assert time.time() - t0 < 120
+            time.sleep(0.001)
+            r = srv.poll(tk)
+        g = r.to_host()
+        r.free()
+        alone = gpu_tree(lod, c, leaf_cap=3000, max_level=12, sampling=3, full_precision=True)
+        for k in ("level", "key", "count", "voxels", "voxel_ids", "voxel_points"):
+            if alone[k] is None:
+                assert g[k] is None or len(g[k]) == 0
+            else:
+                assert np.array_equal(g[k], alone[k]), (i, k)
+        if len(c):
+            check_full(g, oracle.build(c, leaf_cap=3000, max_level=12, sampling=3, full_precision=True), c)
     srv.destroy()
 
 
