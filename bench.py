@@ -50,7 +50,7 @@ WORKLOADS = {
                        desc="aerial 1x1 km: 70% terrain, 20% on 200 box buildings, 10% in 2000 Gaussian blobs"),
     "terrain1m": dict(n=1_000_000, gen="terrain", seed=1, desc="terrain heightfield 100x100 m"),
 }
-SAMPLING = {"average": 0, "first": 1, "random": 2}
+SAMPLING = {"average": 0, "first": 1, "random": 2, "weighted": 3}
 
 
 def stage_bytes(stage: str, n: int, ids: bool) -> float:
@@ -297,7 +297,7 @@ def main():
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     sampling = SAMPLING[args.sampling]
-    ids = sampling != 0
+    ids = sampling in (1, 2)  # pick modes carry point ids through the partition
     print(f"[bench] generating {n} points ({args.workload})", file=sys.stderr, flush=True)
     host = torch.empty(n * 16, dtype=torch.uint8, pin_memory=True)
     pts = host.numpy().view(synth.POINT_DTYPE)
