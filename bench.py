@@ -285,7 +285,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this builder has no multi-GPU path "
-              "(chunks of a batch shard trivially across GPUs; see DESIGN.md). Run with --gpus 1.",
+              "(the chunks of a batch are independent and would be assigned to GPUs by size). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
