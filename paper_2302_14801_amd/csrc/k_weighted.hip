@@ -54,29 +54,38 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t x) {
 
 constexpr uint32_t kWWords = 1u << 15;  // 64-bit words of a node's 2^21-cell bitmap
 
-// A slot (bitmap) for every inner node at level L.
-__global__ void __launch_bounds__(256) k_wslots(Nodes nodes, uint32_t num_nodes, uint32_t L, uint32_t* wslot,
-                                                uint32_t* slot_ctr) {
-  const uint32_t n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= num_nodes || nodes.is_leaf[n] || nodes.level[n] != L) return;
-  wslot[n] = atomicAdd(slot_ctr + L, 1u);
+// The kernels of one level run over that level's nodes only: `ln` lists the
+// nodes of the level (of all trees of the call), and a node's bitmap slot is
+// its position in the list.
+__global__ void __launch_bounds__(256) k_wslots(const uint32_t* __restrict__ ln, uint32_t cnt, uint32_t* wslot) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i < cnt) wslot[ln[i]] = i;
 }
 
-// The bitmap words of the inner nodes at level L (set = true) or their reset
+// The bitmap words of the inner nodes in ln (set = true) or their reset
 // (set = false): the first voxel of every 64-cell word writes the whole word
 // (the word's voxels follow it in the list) and, when setting, its own index.
-__global__ void __launch_bounds__(256) k_wbits(Nodes nodes, uint32_t num_nodes, uint32_t L,
+// When setting, the node's list is also cut at its 64 aligned 32^3 blocks of
+// cells (contiguous code ranges): bseg[64 n + b] = [first, end) of block b,
+// relative to the node's first voxel (zero for empty blocks).
+__global__ void __launch_bounds__(256) k_wbits(Nodes nodes, const uint32_t* __restrict__ ln,
                                                const TreeInfo* __restrict__ trees, const uint64_t* __restrict__ vox,
                                                const uint32_t* __restrict__ wslot, unsigned long long* bits,
-                                               uint32_t* wpre, bool set) {
-  const uint32_t n = blockIdx.x;
-  if (n >= num_nodes || nodes.is_leaf[n] || nodes.level[n] != L) return;
+                                               uint32_t* wpre, uint2* bseg, bool set) {
+  const uint32_t n = ln[blockIdx.x];
+  if (nodes.is_leaf[n]) return;
   const uint64_t base = trees[nodes.tree[n]].vbase + nodes.offset[n];
   const uint32_t cnt = nodes.count[n];
   const uint64_t sb = (uint64_t)wslot[n] * kWWords;
   for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < cnt; i += kWSplit * 256) {
-    const uint32_t word = voxel_code(vox[base + i]) >> 6;
-    if (i > 0 && (voxel_code(vox[base + i - 1]) >> 6) == word) continue;
+    const uint32_t code = voxel_code(vox[base + i]), word = code >> 6;
+    const uint32_t prev = i > 0 ? voxel_code(vox[base + i - 1]) : 0xffffffffu;
+    if (set) {
+      const uint32_t b = code >> 15;
+      if (i == 0 || (prev >> 15) != b) bseg[64ull * n + b].x = i;
+      if (i + 1 == cnt || (voxel_code(vox[base + i + 1]) >> 15) != b) bseg[64ull * n + b].y = i + 1;
+    }
+    if (i > 0 && (prev >> 6) == word) continue;
     if (!set) {
       bits[sb + word] = 0ull;
       continue;
@@ -102,18 +111,7 @@ __device__ __forceinline__ uint32_t wfind(const unsigned long long* __restrict__
   return (uint32_t)(vbase + wpre[sb + (code >> 6)] + (uint32_t)__popcll(word & ((1ull << b) - 1ull)));
 }
 
-constexpr int kWChunk = 256;       // samples per chunk (one per thread)
-constexpr uint32_t kWSlots = 1024;  // LDS hash slots per workgroup
-constexpr int kWProbe = 32;         // LDS probes before a splat goes global
-
-// A chunk puts at most one splat of each sample on a cell, so a cell's chunk
-// sums stay below 256 * 65536 * 255 < 2^32 (colour) and 2^24 (weight): two
-// 32-bit sums share each 64-bit LDS word.
-struct WLocal {
-  uint32_t key[kWSlots];  // cell code + 1 (0 = empty)
-  unsigned long long rg[kWSlots], bw[kWSlots];  // R | G << 32, B | w << 32
-};
-static_assert(kWChunk <= 256, "packed chunk sums need at most 256 samples per chunk");
+constexpr int kWProbe = 32;  // LDS probes before a splat goes global
 
 __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi, uint64_t w, uint64_t R, uint64_t Gc,
                                             uint64_t B) {
@@ -124,21 +122,21 @@ __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi
   atomicAdd(a4 + 3, (unsigned long long)w);
 }
 
-// Splat one sample of node A (level L, grid origin G = A's coordinates * 128,
-// per axis) at pos2 with colour rgba into the workgroup's LDS table.
-__device__ __forceinline__ void wsplat(uint32_t L, const uint32_t G[3], const uint64_t pos2[3], uint32_t rgba, WLocal& lt,
-                                       const unsigned long long* __restrict__ bits, const uint32_t* __restrict__ wpre,
-                                       uint64_t sb, uint64_t vbase, unsigned long long* acc) {
+// Calls f(code, w) for every cell of node A's grid (level L, origin G = A's
+// coordinates * 128 per axis) that a sample at pos2 reaches with weight w > 0:
+// the cell containing it and, per axis, the neighbour on the side of its
+// offset (the 2x2x2 cells whose centres surround it), inside A only.
+template <class F>
+__device__ __forceinline__ void wtargets(uint32_t L, const uint32_t G[3], const uint64_t pos2[3], F&& f) {
   const uint32_t cs = 15 - L;  // log2 of A's cell size in pos2 units
   int64_t cand[3][2];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int64_t k = (int64_t)(pos2[a] >> cs);
-    const int64_t f = (int64_t)pos2[a] - (k << cs);
+    const int64_t fo = (int64_t)pos2[a] - (k << cs);
     cand[a][0] = k;
-    cand[a][1] = f < ((int64_t)1 << (cs - 1)) ? k - 1 : k + 1;
+    cand[a][1] = fo < ((int64_t)1 << (cs - 1)) ? k - 1 : k + 1;
   }
-  const uint64_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     int64_t c[3];
@@ -160,201 +158,227 @@ __device__ __forceinline__ void wsplat(uint32_t L, const uint32_t G[3], const ui
     }
     const uint64_t r = isqrt_u64(d2 << (2 * L + 2));  // floor(65536 * distance)
     if (r >= kWeightOne) continue;
-    const uint64_t w = kWeightOne - r;
-    const uint32_t code = morton7(loc[0], loc[1], loc[2]);
-    uint32_t slot = (code * 0x9E3779B1u) >> 22;  // 10 bits
-    bool done = false;
-    for (int probe = 0; probe < kWProbe; ++probe) {
-      const uint32_t prev = atomicCAS(&lt.key[slot], 0u, code + 1);
-      if (prev == 0u || prev == code + 1) {
-        atomicAdd(&lt.rg[slot], (unsigned long long)((w * R) | ((w * Gc) << 32)));
-        atomicAdd(&lt.bw[slot], (unsigned long long)((w * B) | (w << 32)));
-        done = true;
-        break;
-      }
-      slot = (slot + 1) & (kWSlots - 1);
-    }
-    if (!done) {  // the LDS table is full around this code: straight to the global sums
-      const uint32_t vi = wfind(bits, wpre, sb, vbase, code);
-      if (vi != 0xffffffffu) wadd_global(acc, vi, w, R, Gc, B);
-    }
+    f(morton7(loc[0], loc[1], loc[2]), kWeightOne - r);
   }
 }
 
-// Samples of the nodes at level L + 1 into their parents (level L): the
-// workgroups (n, y) of node n take its chunks y, y + kWSplit, ...
-__global__ void __launch_bounds__(256) k_wsplat(Nodes nodes, uint32_t num_nodes, uint32_t L,
-                                                const TreeInfo* __restrict__ trees, const Cube* cube,
-                                                const uint4* __restrict__ Y, const uint64_t* __restrict__ vox,
-                                                const uint32_t* __restrict__ wslot,
-                                                const unsigned long long* __restrict__ bits,
-                                                const uint32_t* __restrict__ wpre, unsigned long long* acc) {
-  __shared__ WLocal lt;
-  const uint32_t n = blockIdx.x, t = threadIdx.x;
-  if (n >= num_nodes || nodes.level[n] != L + 1) return;
-  const uint32_t cnt = nodes.count[n];
-  if (blockIdx.y * kWChunk >= cnt) return;
-  const uint32_t A = nodes.parent[n];
-  const uint64_t ka = nodes.key[A];
-  const uint32_t G[3] = {compact21(ka), compact21(ka >> 1), compact21(ka >> 2)};
-  const uint64_t sb = (uint64_t)wslot[A] * kWWords, vbase = trees[nodes.tree[A]].vbase + nodes.offset[A];
+// The samples of the children at level L + 1 (points of leaves, voxels of
+// inner nodes) into their parents (level L), one workgroup per child and
+// aligned 16^3 block of the parent's cells inside the child's octant (64 per
+// child): a leaf's micro-bucket (its points two levels down), or an inner
+// child's 32^3 block of its own cells (a contiguous range of its voxel list).
+// A block's cells are a contiguous range of 4096 cell codes.  All of a
+// block's splats are summed in an LDS hash first.  A cell at least one cell
+// inside the block gets samples from this block only (weights vanish beyond
+// one cell, and the block lies inside one child's octant), so its colour is
+// final here and is written directly; cells on the block's border and the
+// cells around it take the sums through global atomics and get their colour
+// in k_wfinal.  If the table overflows, every cell goes through the atomics.
+// The block's 64 bitmap words are read once, so cells inside it find their
+// voxel index in LDS.
+constexpr uint32_t kWLSlots = 2048;
+constexpr uint32_t kWLThreads = 512;
+struct WBlockLocal {
+  uint32_t key[kWLSlots];                 // cell code + 1 (0 = empty)
+  unsigned long long sum[4][kWLSlots];    // w * R, w * G, w * B, w (one array each: no bank conflicts)
+  unsigned long long bbits[64];           // the block's occupancy words
+  uint32_t bpre[64];                      // list index (from the node's first voxel) of each word's first cell
+  uint32_t overflow;
+};
+__global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const uint32_t* __restrict__ ln, uint32_t L,
+                                                             const ItemDesc* __restrict__ desc,
+                                                             const uint2* __restrict__ bseg,
+                                                             const TreeInfo* __restrict__ trees, const Cube* cube,
+                                                             const uint4* __restrict__ Y, uint64_t* vox,
+                                                             const uint32_t* __restrict__ wslot,
+                                                             const unsigned long long* __restrict__ bits,
+                                                             const uint32_t* __restrict__ wpre,
+                                                             unsigned long long* acc) {
+  __shared__ WBlockLocal lt;
+  const uint32_t n = ln[blockIdx.x >> 6], sub = blockIdx.x & 63u, t = threadIdx.x;
   const bool leaf = nodes.is_leaf[n] != 0;
-  const CubeD cd = load_cube(cube + nodes.tree[n]);
-  const uint64_t kn = nodes.key[n];
+  uint64_t first;
+  uint32_t cnt;
+  if (leaf) {
+    // work item sub / 8 of the leaf (a child cell), micro-bucket sub % 8
+    const ItemDesc& d = desc[8 * n + (sub >> 3)];
+    cnt = d.P ? d.mc[sub & 7u] : 0u;
+    uint32_t o = d.I0;
+    for (uint32_t k = 0; k < (sub & 7u); ++k) o += d.mc[k];
+    first = o;
+  } else {
+    const uint2 sg = bseg[64ull * n + sub];
+    cnt = sg.y - sg.x;
+    first = trees[nodes.tree[n]].vbase + nodes.offset[n] + sg.x;
+  }
+  if (cnt == 0) return;
+  const uint32_t A = nodes.parent[n];
+  const uint64_t ka = nodes.key[A], kn = nodes.key[n];
+  const uint32_t G[3] = {compact21(ka), compact21(ka >> 1), compact21(ka >> 2)};
   const uint32_t C[3] = {compact21(kn), compact21(kn >> 1), compact21(kn >> 2)};
-  const uint64_t first = leaf ? nodes.offset[n] : trees[nodes.tree[n]].vbase + nodes.offset[n];
-  for (uint32_t i = t; i < kWSlots; i += 256) {
+  const uint64_t sb = (uint64_t)wslot[A] * kWWords, vbase = trees[nodes.tree[A]].vbase + nodes.offset[A];
+  const CubeD cd = load_cube(cube + nodes.tree[n]);
+  // the block's cells in A's grid: codes blk * 4096 + [0, 4096), blk = the
+  // child's octant, then the octants of the two levels below it (for a leaf,
+  // the work item's and the micro-bucket's)
+  const uint32_t blk = ((uint32_t)(kn & 7u) << 6) | sub;
+  // a sample: a point record, or a voxel word in .x / .y
+  auto load = [&](uint32_t i) -> uint4 {
+    if (leaf) return Y[first + i];
+    const uint64_t v = vox[first + i];
+    return make_uint4((uint32_t)v, (uint32_t)(v >> 32), 0u, 0u);
+  };
+  uint4 nxt = make_uint4(0, 0, 0, 0);
+  if (t < cnt) nxt = load(t);
+  for (uint32_t i = t; i < kWLSlots; i += kWLThreads) {
     lt.key[i] = 0;
-    lt.rg[i] = lt.bw[i] = 0;
+    lt.sum[0][i] = lt.sum[1][i] = lt.sum[2][i] = lt.sum[3][i] = 0;
+  }
+  if (t < 64) {
+    // the block's bitmap words and the list index of each word's first cell
+    const uint64_t w0 = sb + ((uint64_t)blk << 6);
+    const unsigned long long wd = bits[w0 + t];
+    const uint32_t pc = (uint32_t)__popcll(wd);
+    const uint32_t inc = wave_incl_scan(pc);
+    const unsigned long long nz = __ballot(wd != 0ull);
+    const uint32_t start = nz ? wpre[w0 + (uint32_t)(__ffsll((unsigned long long)nz) - 1)] : 0u;
+    lt.bbits[t] = wd;
+    lt.bpre[t] = start + inc - pc;
+    if (t == 0) lt.overflow = 0;
   }
   __syncthreads();
-  for (uint32_t c0 = blockIdx.y * kWChunk; c0 < cnt; c0 += kWSplit * kWChunk) {
-    const uint32_t i = c0 + t;
-    if (i < cnt) {
-      uint64_t pos2[3];
-      uint32_t rgba;
-      if (leaf) {
-        // a point at the centre of its 2^21-grid cell
-        const uint4 v = Y[first + i];
-        pos2[0] = 2ull * quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) + 1;
-        pos2[1] = 2ull * quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) + 1;
-        pos2[2] = 2ull * quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) + 1;
-        rgba = v.w;
-      } else {
-        // a child voxel at the centre of its cell (level L + 8)
-        const uint64_t v = vox[first + i];
+  for (uint32_t i = t; i < cnt; i += kWLThreads) {
+    // the next sample is loaded while this one is splat
+    const uint4 v = nxt;
+    if (i + kWLThreads < cnt) nxt = load(i + kWLThreads);
+    uint64_t pos2[3];
+    uint32_t rgba;
+    if (leaf) {
+      // a point at the centre of its 2^21-grid cell
+      pos2[0] = 2ull * quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) + 1;
+      pos2[1] = 2ull * quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) + 1;
+      pos2[2] = 2ull * quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) + 1;
+      rgba = v.w;
+    } else {
+      // a child voxel at the centre of its cell (level L + 8)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const uint64_t j = ((uint64_t)C[a] << 7) + ((v >> (8 * a)) & 0xffu);
-          pos2[a] = (2 * j + 1) << (13 - L);
+      for (int a = 0; a < 3; ++a) {
+        const uint64_t j = ((uint64_t)C[a] << 7) + ((v.x >> (8 * a)) & 0xffu);
+        pos2[a] = (2 * j + 1) << (13 - L);
+      }
+      rgba = v.y;
+    }
+    const uint64_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
+    wtargets(L, G, pos2, [&](uint32_t code, uint64_t w) {
+      uint32_t slot = (code * 0x9E3779B1u) >> 21;  // 11 bits
+      bool done = false;
+      for (int probe = 0; probe < kWProbe; ++probe) {
+        const uint32_t prev = atomicCAS(&lt.key[slot], 0u, code + 1);
+        if (prev == 0u || prev == code + 1) {
+          atomicAdd(&lt.sum[0][slot], (unsigned long long)(w * R));
+          atomicAdd(&lt.sum[1][slot], (unsigned long long)(w * Gc));
+          atomicAdd(&lt.sum[2][slot], (unsigned long long)(w * B));
+          atomicAdd(&lt.sum[3][slot], (unsigned long long)w);
+          done = true;
+          break;
         }
-        rgba = (uint32_t)(v >> 32);
+        slot = (slot + 1) & (kWLSlots - 1);
       }
-      wsplat(L, G, pos2, rgba, lt, bits, wpre, sb, vbase, acc);
-    }
-    __syncthreads();
-    // each touched cell once to the global sums (if it is occupied), then
-    // the slot is cleared for the next chunk
-    for (uint32_t k = t; k < kWSlots; k += 256) {
-      const uint32_t key = lt.key[k];
-      if (key == 0u) continue;
-      const uint32_t vi = wfind(bits, wpre, sb, vbase, key - 1);
-      if (vi != 0xffffffffu) {
-        unsigned long long* a4 = acc + 4ull * vi;
-        const unsigned long long rg = lt.rg[k], bw = lt.bw[k];
-        atomicAdd(a4 + 0, rg & 0xffffffffull);
-        atomicAdd(a4 + 1, rg >> 32);
-        atomicAdd(a4 + 2, bw & 0xffffffffull);
-        atomicAdd(a4 + 3, bw >> 32);
+      if (!done) {  // table full around this code: straight to the global sums
+        lt.overflow = 1;
+        const uint32_t vi = wfind(bits, wpre, sb, vbase, code);
+        if (vi != 0xffffffffu) wadd_global(acc, vi, w, R, Gc, B);
       }
-      lt.key[k] = 0;
-      lt.rg[k] = lt.bw[k] = 0;
+    });
+  }
+  __syncthreads();
+  const bool direct_ok = lt.overflow == 0;
+  // each thread's kWLSlots / kWLThreads slots at once: the bitmap words of cells
+  // outside the block are loaded together, then their prefixes, so a flush
+  // waits for two global round trips
+  constexpr int kPer = kWLSlots / kWLThreads;
+  uint32_t code[kPer], vi[kPer];
+  unsigned long long wd[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t key = lt.key[t + kWLThreads * j];
+    code[j] = key - 1u;
+    wd[j] = 0ull;
+    if (key != 0u) {
+      if ((code[j] >> 12) == blk) wd[j] = lt.bbits[(code[j] >> 6) & 63u];
+      else wd[j] = bits[sb + (code[j] >> 6)];
     }
-    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t b = code[j] & 63u;
+    vi[j] = 0xffffffffu;
+    if ((wd[j] >> b) & 1ull) {
+      const uint32_t pre = (code[j] >> 12) == blk ? lt.bpre[(code[j] >> 6) & 63u] : wpre[sb + (code[j] >> 6)];
+      vi[j] = (uint32_t)(vbase + pre + (uint32_t)__popcll(wd[j] & ((1ull << b) - 1ull)));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (vi[j] == 0xffffffffu) continue;  // untouched slot, or not an occupied cell
+    const uint32_t k = t + kWLThreads * j, c = code[j];
+    const uint32_t x = compact21(c) & 15u, y = compact21(c >> 1) & 15u, z = compact21(c >> 2) & 15u;
+    const bool interior = direct_ok && (c >> 12) == blk && x - 1u < 14u && y - 1u < 14u && z - 1u < 14u;
+    const unsigned long long s0 = lt.sum[0][k], s1 = lt.sum[1][k], s2 = lt.sum[2][k], ws = lt.sum[3][k];
+    if (interior && ws != 0ull) {
+      const uint32_t rgba = (uint32_t)(s0 / ws) | ((uint32_t)(s1 / ws) << 8) | ((uint32_t)(s2 / ws) << 16) | (255u << 24);
+      vox[vi[j]] = make_voxel(c, rgba);
+    } else {
+      unsigned long long* a4 = acc + 4ull * vi[j];
+      atomicAdd(a4 + 0, s0);
+      atomicAdd(a4 + 1, s1);
+      atomicAdd(a4 + 2, s2);
+      atomicAdd(a4 + 3, ws);
+    }
   }
 }
 
-// Leaf points sorted by their depth-1 cell (the parent's grid) inside each
-// micro-bucket, so that a chunk of consecutive points covers few cells.  The
-// order of points inside a leaf is free; the voxel lists are already built.
-// One workgroup per work item; micro-buckets of more than kWSortMax points
-// keep their order (the sums do not depend on it).
-constexpr uint32_t kWSortMax = 2048;
-__global__ void __launch_bounds__(256) k_wsort(const ItemDesc* __restrict__ desc, const Cube* cube, uint4* Y,
-                                               uint32_t* Yid) {
-  __shared__ uint4 sp[kWSortMax];
-  __shared__ uint32_t sid[kWSortMax];
-  __shared__ uint16_t scell[kWSortMax];
-  __shared__ uint32_t hist[4096];
-  __shared__ uint32_t sh[256 / 64 + 1];
-  const ItemDesc& d = desc[blockIdx.x];
-  const uint32_t P = d.P, t = threadIdx.x;
-  if (P == 0) return;
-  const CubeD cd = load_cube(cube + d.tree);
-  const uint32_t sub_bit = 15u - d.lvl;  // bit level of the depth-1 cells (level lvl + 6)
-  uint32_t off = d.I0;
-  for (uint32_t jm = 0; jm < 8; ++jm) {
-    const uint32_t cnt = d.mc[jm];
-    const uint32_t o = off;
-    off += cnt;
-    if (cnt < 2 || cnt > kWSortMax) continue;  // uniform
-    for (uint32_t i = t; i < 4096; i += 256) hist[i] = 0;
-    __syncthreads();
-    for (uint32_t i = t; i < cnt; i += 256) {
-      const uint4 v = Y[o + i];
-      sp[i] = v;
-      if (Yid) sid[i] = Yid[o + i];
-      const uint32_t c = point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, sub_bit, 4);
-      scell[i] = (uint16_t)c;
-      atomicAdd(&hist[c], 1u);
-    }
-    __syncthreads();
-    // exclusive scan of the 4096 counts (16 per thread)
-    uint32_t loc[16], run = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      loc[k] = hist[16 * t + k];
-      run += loc[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<256>(run, sh, &tot);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      hist[16 * t + k] = ex;
-      ex += loc[k];
-    }
-    __syncthreads();
-    for (uint32_t i = t; i < cnt; i += 256) {
-      const uint32_t pos = atomicAdd(&hist[scell[i]], 1u);
-      Y[o + pos] = sp[i];
-      if (Yid) Yid[o + pos] = sid[i];
-    }
-    __syncthreads();
-  }
-}
-
-void launch_weighted_sort(uint32_t num_nodes, const void* desc, const Cube* cube, void* Y, uint32_t* Yid, hipStream_t s) {
-  if (!num_nodes) return;
-  hipLaunchKernelGGL(k_wsort, dim3(8 * num_nodes), dim3(256), 0, s, (const ItemDesc*)desc, cube, (uint4*)Y, Yid);
-}
-
-// Colours of the voxels of the inner nodes at level L from their sums
-// (kWSplit workgroups per node).
-__global__ void __launch_bounds__(256) k_wfinal(Nodes nodes, uint32_t num_nodes, uint32_t L,
+// Colours of the voxels of the inner nodes in ln from their sums (kWSplit
+// workgroups per node); cells without sums were written by k_wsplat_leaf.
+__global__ void __launch_bounds__(256) k_wfinal(Nodes nodes, const uint32_t* __restrict__ ln,
                                                 const TreeInfo* __restrict__ trees, uint64_t* vox,
                                                 const unsigned long long* __restrict__ acc) {
-  const uint32_t n = blockIdx.x;
-  if (n >= num_nodes || nodes.is_leaf[n] || nodes.level[n] != L) return;
+  const uint32_t n = ln[blockIdx.x];
+  if (nodes.is_leaf[n]) return;
   const uint64_t base = trees[nodes.tree[n]].vbase + nodes.offset[n];
   const uint32_t cnt = nodes.count[n];
   for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < cnt; i += kWSplit * 256) {
     const unsigned long long* a4 = acc + 4ull * (base + i);
     const uint64_t ws = a4[3];
-    if (ws == 0) continue;  // unreachable: a cell's own sample weighs more than 0.13
+    if (ws == 0) continue;  // colour already final
     const uint32_t rgba = (uint32_t)(a4[0] / ws) | ((uint32_t)(a4[1] / ws) << 8) | ((uint32_t)(a4[2] / ws) << 16) |
                           (255u << 24);
     vox[base + i] = (vox[base + i] & 0xffffffffull) | ((uint64_t)rgba << 32);
   }
 }
 
-void launch_weighted(const Nodes& nodes, uint32_t num_nodes, uint32_t deepest, const TreeInfo* trees, const Cube* cube,
-                     const void* Y, uint64_t* vox, uint32_t* wslot, uint32_t* slot_ctr, unsigned long long* bits,
-                     uint32_t* wpre, unsigned long long* acc, hipStream_t s) {
-  if (!num_nodes || deepest == 0) return;
+void launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t* loff, uint32_t deepest,
+                     const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
+                     uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg, unsigned long long* acc,
+                     hipStream_t s) {
   for (int L = (int)deepest - 1; L >= 0; --L) {
     const uint32_t l = (uint32_t)L;
-    hipLaunchKernelGGL(k_wslots, dim3((num_nodes + 255) / 256), dim3(256), 0, s, nodes, num_nodes, l, wslot, slot_ctr);
-    hipLaunchKernelGGL(k_wbits, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees,
-                       (const uint64_t*)vox, (const uint32_t*)wslot, bits, wpre, true);
-    hipLaunchKernelGGL(k_wsplat, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees, cube,
-                       (const uint4*)Y, (const uint64_t*)vox, (const uint32_t*)wslot, (const unsigned long long*)bits,
-                       (const uint32_t*)wpre, acc);
-    hipLaunchKernelGGL(k_wfinal, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees, vox,
+    const uint32_t* pa = lnodes + loff[l];       // the parents' level
+    const uint32_t* ch = lnodes + loff[l + 1];   // the children's level
+    const uint32_t na = (uint32_t)(loff[l + 1] - loff[l]), nch = (uint32_t)(loff[l + 2] - loff[l + 1]);
+    if (!na || !nch) continue;
+    hipLaunchKernelGGL(k_wslots, dim3((na + 255) / 256), dim3(256), 0, s, pa, na, wslot);
+    hipLaunchKernelGGL(k_wbits, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, (const uint64_t*)vox,
+                       (const uint32_t*)wslot, bits, wpre, bseg, true);
+    hipLaunchKernelGGL(k_wsplat_block, dim3(64 * nch), dim3(kWLThreads), 0, s, nodes, ch, l, (const ItemDesc*)desc,
+                       (const uint2*)bseg, trees, cube, (const uint4*)Y, vox, (const uint32_t*)wslot,
+                       (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
+    hipLaunchKernelGGL(k_wfinal, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, vox,
                        (const unsigned long long*)acc);
     // the bitmaps are cleared word by word (from the unchanged cell lists) for
     // the next level's nodes
-    hipLaunchKernelGGL(k_wbits, dim3(num_nodes, kWSplit), dim3(256), 0, s, nodes, num_nodes, l, trees,
-                       (const uint64_t*)vox, (const uint32_t*)wslot, bits, wpre, false);
+    hipLaunchKernelGGL(k_wbits, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, (const uint64_t*)vox,
+                       (const uint32_t*)wslot, bits, wpre, bseg, false);
   }
 }
 

@@ -65,17 +65,18 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
                          const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
                          hipStream_t s);
 // Neighbourhood-weighted colours of all inner voxels (after the average
-// build), level by level: occupancy bitmaps of the level's nodes (one slot of
-// weighted_bitmap_words() 64-bit words and as many u32 word prefixes each,
-// bitmaps zero on entry and on return), splat, colours.  slot_ctr: 16 zeroed
-// counters; acc: 4 zeroed u64 per voxel.
-void launch_weighted(const Nodes& nodes, uint32_t num_nodes, uint32_t deepest, const TreeInfo* trees, const Cube* cube,
-                     const void* Y, uint64_t* vox, uint32_t* wslot, uint32_t* slot_ctr, unsigned long long* bits,
-                     uint32_t* wpre, unsigned long long* acc, hipStream_t s);
+// build), level by level.  lnodes: the node indices of the call grouped by
+// level, level L at [loff[L], loff[L + 1]) (loff: host array of deepest + 2
+// entries).  Occupancy bitmaps of a level's nodes: one slot of
+// weighted_bitmap_words() 64-bit words and as many u32 word prefixes per node
+// of the level, zero on entry and on return; wslot: one u32 per node; acc: 4
+// zeroed u64 per voxel; bseg: 64 zeroed uint2 per node.  desc and Y: the
+// leaf items and leaf-ordered points.
+void launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t* loff, uint32_t deepest,
+                     const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
+                     uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg, unsigned long long* acc,
+                     hipStream_t s);
 uint64_t weighted_bitmap_words();
-// Sort the points of every micro-bucket of every work item by depth-1 cell
-// (in place; ids follow when Yid is not NULL).
-void launch_weighted_sort(uint32_t num_nodes, const void* desc, const Cube* cube, void* Y, uint32_t* Yid, hipStream_t s);
 // Full-precision records (input coordinates of the accepted sample, voxel
 // colour) of the vtotal voxels of a call.
 void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,

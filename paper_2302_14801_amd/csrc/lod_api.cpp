@@ -134,8 +134,8 @@ struct Workspace {
   Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_tree;
   Scratch c_level, c_leaf, c_mask, c_key, c_npts, c_count, c_first, c_off, c_cover, c_grid, c_parent, c_tree;
   Scratch t2, t2id, icnt, idesc, iself, v_sz, v_dfs, v_dfsn, v_psize, v_poff, v_selfc, v_selfid;
-  Scratch state, bstate, clouds, trees, nbeg, wslot, wctr, wbits, wpre, wacc;
-  Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs;
+  Scratch state, bstate, clouds, trees, nbeg, wslot, wlist, wbits, wpre, wacc, wseg;
+  Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs, h_wlist;
   std::vector<void*> retired;  // outgrown blocks, released when the build's stream has drained
   hipEvent_t ev[16] = {};
   bool ev_ready = false;
@@ -146,7 +146,7 @@ struct Workspace {
             &c_level, &c_leaf,  &c_mask,  &c_key,   &c_npts,   &c_count, &c_first,  &c_off,   &c_cover,
             &c_grid,  &c_parent, &c_tree, &t2,      &t2id,     &icnt,    &idesc,    &iself,   &v_sz,
             &v_dfs,   &v_dfsn,  &v_psize, &v_poff,  &v_selfc,  &v_selfid, &state,   &bstate,  &clouds,
-            &trees,   &nbeg,    &wslot,   &wctr,    &wbits,   &wpre,    &wacc};
+            &trees,   &nbeg,    &wslot,   &wlist,   &wbits,   &wpre,    &wacc,    &wseg};
   }
   Workspace() {
     for (Scratch* sc : scratches()) sc->retired = &retired;
@@ -614,27 +614,36 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   launch_voxel_gather(pl.mode, nd, vt, num_nodes, tinfo, icnt, desc, T1, Xid, T2, T2id, vox, vids, s);
   if (pl.weighted && vtotal) {
     if (vtotal > 0xffffffffull) fail(LOD_ERR_INVALID, "weighted sampling handles at most 2^32 - 1 voxels per call");
-    // one occupancy bitmap per inner node of a level: at most the level's
-    // node count over all trees
+    // the nodes of the call grouped by level (each tree's levels are
+    // contiguous in the node table); one occupancy bitmap slot per node of
+    // the widest level
     uint32_t deepest = 0;
-    uint64_t slots = 1;
     for (uint32_t c = 0; c < nc; ++c) deepest = std::max(deepest, hti[c].deepest);
-    for (uint32_t L = 0; L + 1 <= deepest && L < 23; ++L) {
-      uint64_t k = 0;
-      for (uint32_t c = 0; c < nc; ++c) k += hti[c].level_end[L] - hti[c].level_begin[L];
-      slots = std::max(slots, k);
+    uint32_t* hl = w.h_wlist.get<uint32_t>(num_nodes);
+    uint64_t loff[25] = {};
+    uint64_t slots = 1, k = 0;
+    for (uint32_t L = 0; L <= deepest; ++L) {
+      loff[L] = k;
+      for (uint32_t c = 0; c < nc; ++c) {
+        if (k + (hti[c].level_end[L] - hti[c].level_begin[L]) > num_nodes)
+          fail(LOD_ERR_CAPACITY, "level ranges exceed the node table");
+        for (uint32_t i = hti[c].level_begin[L]; i < hti[c].level_end[L]; ++i) hl[k++] = i;
+      }
+      slots = std::max<uint64_t>(slots, k - loff[L]);
     }
+    loff[deepest + 1] = k;
     const uint64_t words = slots * weighted_bitmap_words();
+    uint32_t* wlist = w.wlist.get<uint32_t>(dev, num_nodes);
     uint32_t* wslot = w.wslot.get<uint32_t>(dev, num_nodes);
-    uint32_t* wctr = w.wctr.get<uint32_t>(dev, 16);
     unsigned long long* wbits = w.wbits.get<unsigned long long>(dev, words);
     uint32_t* wpre = w.wpre.get<uint32_t>(dev, words);
     unsigned long long* wacc = w.wacc.get<unsigned long long>(dev, 4 * vtotal);
-    HIPCHK(hipMemsetAsync(wctr, 0, 64, s));
+    uint2* wseg = w.wseg.get<uint2>(dev, 64ull * num_nodes);
+    HIPCHK(hipMemcpyAsync(wlist, hl, sizeof(uint32_t) * k, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(wbits, 0, 8 * words, s));
     HIPCHK(hipMemsetAsync(wacc, 0, 32 * vtotal, s));
-    launch_weighted_sort(num_nodes, desc, cube, Y, Yid, s);
-    launch_weighted(nd, num_nodes, deepest, tinfo, cube, Y, vox, wslot, wctr, wbits, wpre, wacc, s);
+    HIPCHK(hipMemsetAsync(wseg, 0, 64ull * sizeof(uint2) * num_nodes, s));
+    launch_weighted(nd, wlist, loff, deepest, tinfo, cube, desc, Y, vox, wslot, wbits, wpre, wseg, wacc, s);
   }
   lod_point* vpts = nullptr;
   if (pl.full) {
