@@ -77,9 +77,9 @@ typedef struct {
  *                    point sits at the centre of its 2^21-grid cell, a child
  *                    voxel at the centre of its cell; w is 65536 -
  *                    floor(65536 * distance) from an exact integer square
- *                    root.  Slower than the other modes (global atomics);
- *                    scratch of about 32 B per voxel plus 384 KB per node of
- *                    the widest inner level.
+ *                    root.  Slower than the other modes (a pass per level
+ *                    after the average build); scratch of about 32 B per
+ *                    voxel plus 384 KB per node of the widest level.
  * Pick modes copy the winner's R, G, B, A and record its input index. */
 typedef enum { LOD_AVERAGE = 0, LOD_PICK_FIRST = 1, LOD_PICK_RANDOM = 2, LOD_WEIGHTED = 3 } lod_sampling;
 

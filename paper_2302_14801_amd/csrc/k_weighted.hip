@@ -26,20 +26,20 @@
 // the list index of the word's first voxel: the position of an occupied cell
 // is that index plus the set bits below it (the lists are sorted by cell).
 //
-// A child's samples (its points in leaf order, or its voxels in Morton order)
-// are taken in chunks of consecutive samples, which cover a compact region of
-// the parent's grid: a workgroup first sums a chunk's splats per target cell
-// in an LDS hash table, then adds each cell's sums to the global ones, so the
-// global table and the global atomics see one update per (chunk, cell) instead
-// of one per (sample, cell).  A splat that finds the LDS table full goes to the
-// global sums directly (the sums are the same either way).
+// A child's samples are taken per aligned 16^3 block of the parent's grid
+// (a leaf's micro-bucket of points, or a 32^3 block of an inner child's own
+// cells, which is a contiguous range of its sorted voxel list): a workgroup
+// sums the block's splats per target cell in an LDS hash.  Cells one cell or
+// more inside the block get all their samples from it and take their colour
+// there; the other cells add their sums to global 64-bit sums, and a last
+// pass gives them their colour.
 #include "common.h"
 #include "launch.h"
 #include "scan.h"
 
 namespace lod {
 
-constexpr int kWSplit = 16;  // workgroups per child node in the splat
+constexpr int kWSplit = 16;  // workgroups per node in the bitmap and colour passes
 constexpr uint32_t kWeightOne = 65536;
 
 // floor(sqrt(x)) for x < 2^40: the single-precision square root of x

@@ -11,6 +11,7 @@
 // (and count against the budget) until the client frees them.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -44,7 +45,11 @@ struct Request {
 // way by 24 B/pt.
 uint64_t footprint_estimate(uint64_t n, const lod_params& p) {
   const uint64_t full = (p.flags & LOD_FLAG_FULL_PRECISION) ? 24ull * n : 0ull;
-  return 80ull * n + full + (96ull << 20);
+  // weighted: 32 B of sums per voxel (at most about half a voxel per point)
+  // and a 384 KB bitmap per node of the widest level (at most about 2 n / T)
+  const uint64_t weighted =
+      p.sampling == LOD_WEIGHTED ? 16ull * n + (385ull << 10) * (2ull * n / std::max(p.leaf_cap, 1u) + 8ull) : 0ull;
+  return 80ull * n + full + weighted + (96ull << 20);
 }
 
 }  // namespace
