@@ -8,7 +8,7 @@ Importing it loads the library and raises if it has not been built.
 """
 from .binding import (LOD_AVERAGE, LOD_FLAG_FULL_PRECISION, LOD_PICK_FIRST, LOD_PICK_RANDOM, LOD_WEIGHTED,  # noqa: F401
                       LodError, Server, Tree,
-                      load_library, lod_build, lod_build_batch, lod_poll, lod_server_create,
+                      load_library, lod_build, lod_build_batch, lod_build_chunked, lod_poll, lod_server_create,
                       lod_server_destroy, lod_submit, lod_tree_free, lod_tree_view_get, make_params)
 
 load_library()

@@ -77,6 +77,8 @@ def load_library():
     lib.lod_build.restype = ctypes.c_int
     lib.lod_build_batch.argtypes = [vp, P(u64), u32, P(lod_params), vp, P(vp)]
     lib.lod_build_batch.restype = ctypes.c_int
+    lib.lod_build_chunked.argtypes = [vp, u64, P(lod_params), u64, vp, P(vp)]
+    lib.lod_build_chunked.restype = ctypes.c_int
     lib.lod_tree_view_get.argtypes = [vp, P(lod_tree_view)]
     lib.lod_tree_view_get.restype = ctypes.c_int
     lib.lod_tree_timings.argtypes = [vp, P(lod_timings)]
@@ -235,6 +237,21 @@ def lod_build_batch(points, offsets, leaf_cap=50000, max_level=12, sampling=LOD_
                                           offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), k,
                                           ctypes.byref(p), _stream_handle(stream), outs))
     return [Tree(outs[i]) for i in range(k)]
+
+
+def lod_build_chunked(host_points: np.ndarray, chunk_points: int, leaf_cap=50000, max_level=12,
+                      sampling=LOD_AVERAGE, seed=0, keep_ids=False, stream=None,
+                      params: lod_params | None = None) -> Tree:
+    """The tree of a HOST array of 16-byte records, built chunk by chunk."""
+    a = host_points
+    if not a.flags.c_contiguous or a.nbytes % 16:
+        raise ValueError("host_points must be a contiguous array of 16-byte records")
+    n = a.nbytes // 16
+    p = params if params is not None else make_params(leaf_cap, max_level, sampling, seed, keep_ids)
+    out = ctypes.c_void_p()
+    _check(load_library().lod_build_chunked(ctypes.c_void_p(a.ctypes.data if n else 0), n, ctypes.byref(p),
+                                            int(chunk_points), _stream_handle(stream), ctypes.byref(out)))
+    return Tree(out.value)
 
 
 def lod_tree_view_get(tree: Tree) -> lod_tree_view:

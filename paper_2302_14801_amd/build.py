@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblod.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["k_split.hip", "k_tree.hip", "k_voxel.hip", "k_weighted.hip", "lod_api.cpp", "lod_server.cpp"]
+SOURCES = ["k_split.hip", "k_tree.hip", "k_voxel.hip", "k_weighted.hip", "k_merge.hip", "lod_api.cpp", "lod_server.cpp",
+           "lod_chunked.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

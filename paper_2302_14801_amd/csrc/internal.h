@@ -18,6 +18,22 @@ struct LodError {
 
 void lod_set_error(const char* fmt, ...);
 
+// Throw LodError (HIP failure, or an out-of-memory status) after recording the
+// failing call.
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) {                                                                \
+      lod_set_error("%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+      throw LodError{e_ == hipErrorOutOfMemory ? LOD_ERR_OOM : LOD_ERR_HIP};                \
+    }                                                                                      \
+  } while (0)
+
+[[noreturn]] inline void lod_fail(lod_status st, const char* msg) {
+  lod_set_error("%s", msg);
+  throw LodError{st};
+}
+
 // ---------------------------------------------------------- device memory
 //
 // A small caching allocator: freed blocks are kept per device and reused for
@@ -126,7 +142,18 @@ struct lod_tree {
 // Build the trees of `nclouds` independent clouds, cloud i being points
 // [offs[i], offs[i+1]) of d_points (offs on the host), on `stream`, blocking
 // until complete; throws LodError.  One tree per cloud, in order.
+// Options of the chunked build: one bounding cube for every cloud (a host
+// pointer to a lod::Cube, instead of each cloud's own cube; every point must
+// lie in it), and the input index of every point (a device array parallel to
+// d_points, instead of the index within its cloud).
+struct BuildExtras {
+  const void* cube = nullptr;
+  const uint32_t* d_ids = nullptr;
+};
 std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_t* offs, uint32_t nclouds,
-                                        const lod_params& p, hipStream_t stream);
+                                        const lod_params& p, hipStream_t stream, const BuildExtras* x = nullptr);
+// The chunked build of n host points (lod_build_chunked); throws LodError.
+lod_tree* lod_build_chunked_tree(const lod_point* h_points, uint64_t n, const lod_params& p, uint64_t chunk_points,
+                                 hipStream_t stream);
 // One cloud.
 lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params& p, hipStream_t stream);

@@ -1,0 +1,216 @@
+// k_merge.hip -- kernels of the chunked build (Sec. 7: chunks of a bottom-up
+// out-of-core pipeline, merged into one octree).
+//
+// The input is cut along the cells of one level b of the common bounding
+// cube.  A cell with more than T points is an inner node of the whole tree at
+// level b, and its subtree depends on its own points only, so it is built as
+// a chunk.  The levels above b are then sampled here from the chunk roots'
+// voxels and the points of the small leaves above them, with the cell
+// average and pick rules of Sec. 4.2:
+//   * every (parent, child octant) pair is a job with a dense grid of the
+//     64^3 parent cells that the octant covers;
+//   * each sample (a child voxel: 2x2x2 child cells per parent cell; or a
+//     point) adds to its cell: R, G, B sums and a count, or the best pick
+//     order; a second pass lets the winning sample write its colour and id;
+//   * each grid's occupied cells are emitted in Morton order, so a parent's
+//     voxel list is its jobs' outputs in octant order.
+#include "common.h"
+#include "launch.h"
+#include "scan.h"
+
+namespace lod {
+
+// The level-h cell (h <= 7) of each of n points, and a histogram of them.
+__global__ void __launch_bounds__(256) k_cells(const uint4* __restrict__ pts, uint32_t n, const Cube* cube, uint32_t h,
+                                               uint32_t* __restrict__ cell, uint32_t* hist) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const CubeD cd = load_cube(cube);
+  const uint4 v = pts[i];
+  const uint32_t s = kKeyLevels - h;
+  const uint32_t c = morton7(quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) >> s,
+                             quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) >> s,
+                             quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) >> s);
+  cell[i] = c;
+  atomicAdd(hist + c, 1u);
+}
+
+void launch_cells(const void* pts, uint32_t n, const Cube* cube, uint32_t h, uint32_t* cell, uint32_t* hist,
+                  hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_cells, dim3((n + 255) / 256), dim3(256), 0, s, (const uint4*)pts, n, cube, h, cell, hist);
+}
+
+// ------------------------------------------------------------ top levels
+
+// FIRST keeps the minimum pick order (a starts at ~0); the average's sums and
+// RANDOM's maximum start at 0.
+__global__ void __launch_bounds__(256) k_top_clear(TopCell* g, uint64_t ncells, unsigned long long a0) {
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < ncells; i += (uint64_t)gridDim.x * 256) {
+    TopCell c;
+    c.a = a0;
+    c.b = c.c = 0;
+    c.n = c.pad = 0;
+    g[i] = c;
+  }
+}
+
+// Cell (18-bit Morton code inside the job's octant) and colour of sample i.
+__device__ __forceinline__ void top_sample(const TopJob& j, uint32_t i, const CubeD& cd, uint32_t& m, uint32_t& rgba) {
+  if (j.kind == 0) {
+    // a voxel of the child's 128^3 grid: two child cells per parent cell
+    const uint64_t v = ((const uint64_t*)j.src)[i];
+    m = morton7(((uint32_t)v & 0xffu) >> 1, ((uint32_t)(v >> 8) & 0xffu) >> 1, ((uint32_t)(v >> 16) & 0xffu) >> 1);
+    rgba = (uint32_t)(v >> 32);
+  } else {
+    // a point: its cell at level L + 7, inside the child's octant
+    const uint4 v = ((const uint4*)j.src)[i];
+    const uint32_t s = kKeyLevels - (j.level + 7);
+    m = morton7((quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) >> s) & 63u,
+                (quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) >> s) & 63u,
+                (quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) >> s) & 63u);
+    rgba = v.w;
+  }
+}
+
+// MODE: 0 average, 1 first, 2 random.  Grid (x: slices of the samples, y: job).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_top_splat(const TopJob* __restrict__ jobs, const Cube* cube, uint32_t seed,
+                                                   TopCell* grids) {
+  const TopJob j = jobs[blockIdx.y];
+  TopCell* g = grids + (uint64_t)blockIdx.y * kTopCells;
+  const CubeD cd = load_cube(cube);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < j.count; i += gridDim.x * 256) {
+    uint32_t m, rgba;
+    top_sample(j, i, cd, m, rgba);
+    TopCell* c = g + m;
+    atomicAdd(&c->n, 1u);
+    if (MODE == 0) {
+      atomicAdd(&c->a, (unsigned long long)(rgba & 0xffu));
+      atomicAdd(&c->b, (unsigned long long)((rgba >> 8) & 0xffu));
+      atomicAdd(&c->c, (unsigned long long)((rgba >> 16) & 0xffu));
+    } else {
+      const unsigned long long k = pick_order(j.ids[i], seed, MODE == 2);
+      if (MODE == 1) atomicMin(&c->a, k);
+      else atomicMax(&c->a, k);
+    }
+  }
+}
+
+// Pick modes: the one sample whose order won its cell (ids are distinct)
+// writes its colour and id.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_top_pick(const TopJob* __restrict__ jobs, const Cube* cube, uint32_t seed,
+                                                  TopCell* grids) {
+  const TopJob j = jobs[blockIdx.y];
+  TopCell* g = grids + (uint64_t)blockIdx.y * kTopCells;
+  const CubeD cd = load_cube(cube);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < j.count; i += gridDim.x * 256) {
+    uint32_t m, rgba;
+    top_sample(j, i, cd, m, rgba);
+    const uint32_t id = j.ids[i];
+    if (pick_order(id, seed, MODE == 2) == g[m].a) g[m].b = (unsigned long long)rgba | ((unsigned long long)id << 32);
+  }
+}
+
+// Occupied cells of each 4096-cell slice of every job's grid.
+__global__ void __launch_bounds__(256) k_top_count(const TopCell* __restrict__ grids, uint32_t* slice_cnt) {
+  __shared__ uint32_t sh[256 / 64 + 1];
+  const TopCell* g = grids + (uint64_t)blockIdx.y * kTopCells + (uint64_t)blockIdx.x * kTopSlice;
+  uint32_t c = 0;
+  for (uint32_t k = threadIdx.x; k < kTopSlice; k += 256) c += g[k].n != 0u;
+  uint32_t tot;
+  (void)block_excl_scan<256>(c, sh, &tot);
+  if (threadIdx.x == 0) slice_cnt[blockIdx.y * kTopSlices + blockIdx.x] = tot;
+}
+
+// Voxels (and ids) of every job's occupied cells in Morton order, slice s of
+// job j starting at slice_off[j * kTopSlices + s].
+template <int MODE>
+__global__ void __launch_bounds__(256) k_top_emit(const TopJob* __restrict__ jobs, const TopCell* __restrict__ grids,
+                                                  const uint64_t* __restrict__ slice_off, uint64_t* vox,
+                                                  uint32_t* vid) {
+  __shared__ uint32_t sh[256 / 64 + 1];
+  const uint32_t oct = jobs[blockIdx.y].oct;
+  const uint32_t m0 = blockIdx.x * kTopSlice;
+  const TopCell* g = grids + (uint64_t)blockIdx.y * kTopCells + m0;
+  uint64_t pos = slice_off[blockIdx.y * kTopSlices + blockIdx.x];
+  for (uint32_t r = 0; r < kTopSlice; r += 256) {
+    const TopCell c = g[r + threadIdx.x];
+    const bool occ = c.n != 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<256>((uint32_t)occ, sh, &tot);
+    if (occ) {
+      uint32_t rgba, id = 0;
+      if (MODE == 0) {
+        rgba = (uint32_t)(c.a / c.n) | ((uint32_t)(c.b / c.n) << 8) | ((uint32_t)(c.c / c.n) << 16) | (255u << 24);
+      } else {
+        rgba = (uint32_t)c.b;
+        id = (uint32_t)(c.b >> 32);
+      }
+      vox[pos + ex] = make_voxel((oct << 18) | (m0 + r + threadIdx.x), rgba);
+      if (vid) vid[pos + ex] = id;
+    }
+    pos += tot;
+  }
+}
+
+void launch_top_clear(TopCell* grids, uint32_t njobs, uint32_t mode, hipStream_t s) {
+  const uint64_t cells = (uint64_t)njobs * kTopCells;
+  hipLaunchKernelGGL(k_top_clear, dim3(2048), dim3(256), 0, s, grids, cells, mode == 1 ? ~0ull : 0ull);
+}
+
+void launch_top_splat(const TopJob* jobs, uint32_t njobs, uint32_t max_count, const Cube* cube, uint32_t mode,
+                      uint32_t seed, TopCell* grids, hipStream_t s) {
+  if (!njobs || !max_count) return;
+  const dim3 grid(std::min<uint32_t>((max_count + 255) / 256, 512), njobs);
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL(k_top_splat<0>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_top_splat<1>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      hipLaunchKernelGGL(k_top_pick<1>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      break;
+    default:
+      hipLaunchKernelGGL(k_top_splat<2>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      hipLaunchKernelGGL(k_top_pick<2>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      break;
+  }
+}
+
+void launch_top_count(const TopCell* grids, uint32_t njobs, uint32_t* slice_cnt, hipStream_t s) {
+  if (!njobs) return;
+  hipLaunchKernelGGL(k_top_count, dim3(kTopSlices, njobs), dim3(256), 0, s, grids, slice_cnt);
+}
+
+void launch_top_emit(const TopJob* jobs, uint32_t njobs, const TopCell* grids, const uint64_t* slice_off,
+                     uint32_t mode, uint64_t* vox, uint32_t* vid, hipStream_t s) {
+  if (!njobs) return;
+  if (mode == 0)
+    hipLaunchKernelGGL(k_top_emit<0>, dim3(kTopSlices, njobs), dim3(256), 0, s, jobs, grids, slice_off, vox, vid);
+  else
+    hipLaunchKernelGGL(k_top_emit<1>, dim3(kTopSlices, njobs), dim3(256), 0, s, jobs, grids, slice_off, vox, vid);
+}
+
+// ------------------------------------------------------------ copies
+
+// Run r copies runs[r].len elements from the device address runs[r].src to
+// dst + runs[r].dst.
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_runs(const CopyRun* __restrict__ runs, T* dst) {
+  const CopyRun r = runs[blockIdx.x];
+  const T* src = (const T*)r.src;
+  for (uint64_t i = (uint64_t)blockIdx.y * 256 + threadIdx.x; i < r.len; i += (uint64_t)gridDim.y * 256)
+    dst[r.dst + i] = src[i];
+}
+
+void launch_copy_runs(const CopyRun* runs, uint32_t nruns, uint32_t elem_bytes, void* dst, hipStream_t s) {
+  if (!nruns) return;
+  const dim3 grid(nruns, 16);
+  if (elem_bytes == 16) hipLaunchKernelGGL(k_copy_runs<uint4>, grid, dim3(256), 0, s, runs, (uint4*)dst);
+  else if (elem_bytes == 8) hipLaunchKernelGGL(k_copy_runs<uint64_t>, grid, dim3(256), 0, s, runs, (uint64_t*)dst);
+  else hipLaunchKernelGGL(k_copy_runs<uint32_t>, grid, dim3(256), 0, s, runs, (uint32_t*)dst);
+}
+
+}  // namespace lod

@@ -605,6 +605,18 @@ void launch_bbox(const void* pts, const CloudInfo* clouds, uint32_t nclouds, uin
   hipLaunchKernelGGL(k_cube, dim3(cb), dim3(256), 0, st, acc, clouds, nclouds, cube);
 }
 
+void launch_bbox_reset(BBoxAcc* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(256), 0, st, acc, 1u);
+}
+
+void launch_bbox_add(const void* pts, const CloudInfo* piece, uint32_t ntiles, BBoxAcc* acc, hipStream_t st) {
+  if (ntiles) hipLaunchKernelGGL(k_bbox, dim3(ntiles), dim3(kBBoxWG), 0, st, (const uint4*)pts, piece, 1u, acc);
+}
+
+void launch_bbox_cube(const BBoxAcc* acc, const CloudInfo* whole, Cube* cube, hipStream_t st) {
+  hipLaunchKernelGGL(k_cube, dim3(1), dim3(256), 0, st, acc, whole, 1u, cube);
+}
+
 void launch_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, Segment* segs, uint32_t* nseg,
                        GridDesc* grids, hipStream_t st) {
   hipLaunchKernelGGL(k_init_roots, dim3((nclouds + 255) / 256), dim3(256), 0, st, clouds, nclouds, E0, segs, nseg,

@@ -12,6 +12,12 @@ namespace lod {
 uint32_t bbox_tiles(uint32_t count);
 void launch_bbox(const void* pts, const CloudInfo* clouds, uint32_t nclouds, uint32_t ntiles, BBoxAcc* acc, Cube* cube,
                  hipStream_t st);
+// The same in steps, for one cloud streamed in pieces: reset the accumulator,
+// add a piece (clouds: one entry describing the piece), make the cube
+// (clouds: one entry with the whole count).
+void launch_bbox_reset(BBoxAcc* acc, hipStream_t st);
+void launch_bbox_add(const void* pts, const CloudInfo* piece, uint32_t ntiles, BBoxAcc* acc, hipStream_t st);
+void launch_bbox_cube(const BBoxAcc* acc, const CloudInfo* whole, Cube* cube, hipStream_t st);
 void launch_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, Segment* segs, uint32_t* nseg,
                        GridDesc* grids, hipStream_t st);
 void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t chunk, Chunk* chunks,
@@ -84,5 +90,48 @@ void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vto
 // Size of the coarse-list blocks of all work items, bounded from the node
 // count alone (for allocation before the item prefix is known).
 uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes);
+
+// k_merge.hip: the chunked build.
+// Level-h cell (Morton code, h <= 7) of each of n points in the cube, and
+// their histogram (8^h counters, added to).
+void launch_cells(const void* pts, uint32_t n, const Cube* cube, uint32_t h, uint32_t* cell, uint32_t* hist,
+                  hipStream_t s);
+// A job of the levels above the chunk roots: one child (octant `oct`) of a
+// node at `level`, whose samples are `count` voxels (kind 0, 8-byte words of
+// the child's grid) or points (kind 1, 16-byte records) at `src`, with ids
+// (pick modes) at `ids`.
+struct TopJob {
+  const void* src;
+  const uint32_t* ids;
+  uint32_t count;
+  uint32_t kind;
+  uint32_t oct;
+  uint32_t level;
+};
+// A cell of a job's dense grid: R, G, B sums and a sample count (average),
+// or the best pick order (a) and the winner's colour | id << 32 (b).
+struct TopCell {
+  unsigned long long a, b, c;
+  uint32_t n, pad;
+};
+constexpr uint32_t kTopCells = 1u << 18;  // 64^3 parent cells under one child octant
+constexpr uint32_t kTopSlice = 4096;      // cells per workgroup of the count and emit passes
+constexpr uint32_t kTopSlices = kTopCells / kTopSlice;
+// mode: 0 average, 1 first, 2 random.
+void launch_top_clear(TopCell* grids, uint32_t njobs, uint32_t mode, hipStream_t s);
+void launch_top_splat(const TopJob* jobs, uint32_t njobs, uint32_t max_count, const Cube* cube, uint32_t mode,
+                      uint32_t seed, TopCell* grids, hipStream_t s);
+// Occupied cells per slice: njobs * kTopSlices counters.
+void launch_top_count(const TopCell* grids, uint32_t njobs, uint32_t* slice_cnt, hipStream_t s);
+// Voxels of the occupied cells in Morton order from slice_off (one u64 per slice).
+void launch_top_emit(const TopJob* jobs, uint32_t njobs, const TopCell* grids, const uint64_t* slice_off,
+                     uint32_t mode, uint64_t* vox, uint32_t* vid, hipStream_t s);
+// Copies of runs of 16-, 8- or 4-byte elements into one array.
+struct CopyRun {
+  const void* src;
+  uint64_t dst;  // element index in the destination
+  uint64_t len;  // elements
+};
+void launch_copy_runs(const CopyRun* runs, uint32_t nruns, uint32_t elem_bytes, void* dst, hipStream_t s);
 
 }  // namespace lod

@@ -54,19 +54,7 @@ void lod_set_error(const char* fmt, ...) {
 #define set_err lod_set_error
 using lodint::cache;
 
-#define HIPCHK(x)                                                                    \
-  do {                                                                               \
-    hipError_t e_ = (x);                                                             \
-    if (e_ != hipSuccess) {                                                          \
-      set_err("%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
-      throw LodError{e_ == hipErrorOutOfMemory ? LOD_ERR_OOM : LOD_ERR_HIP};          \
-    }                                                                                \
-  } while (0)
-
-static void fail(lod_status st, const char* msg) {
-  set_err("%s", msg);
-  throw LodError{st};
-}
+static void fail(lod_status st, const char* msg) { lod_fail(st, msg); }
 
 namespace {
 
@@ -426,7 +414,7 @@ void refine_nodes(Workspace& w, GridPool& gp, const Nodes& nd, uint32_t* list, u
 }  // namespace
 
 std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_t* offs, uint32_t nchunks,
-                                        const lod_params& prm, hipStream_t s) {
+                                        const lod_params& prm, hipStream_t s, const BuildExtras* x) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   const uint64_t N = offs[nchunks] - offs[0];
@@ -494,14 +482,22 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
 
   StageTimer tm(w, s, (prm.flags & LOD_FLAG_TIMING) != 0);
   tm.mark(EV_START);
-  // 1. bounding boxes and cubes
-  launch_bbox(in, clouds, nc, ntiles, bb, cube, s);
+  // 1. bounding boxes and cubes (or the one cube given for all clouds)
+  if (x && x->cube) {
+    Cube* hgc = w.h_cubes.get<Cube>(nc);
+    for (uint32_t c = 0; c < nc; ++c) hgc[c] = *(const Cube*)x->cube;
+    HIPCHK(hipMemcpyAsync(cube, hgc, sizeof(Cube) * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // the pinned table is refilled below
+  } else {
+    launch_bbox(in, clouds, nc, ntiles, bb, cube, s);
+  }
   tm.mark(EV_BBOX);
   // 2. root partition, input -> X
   Segment* segs = w.segs.get<Segment>(dev, std::max<uint64_t>(std::max<uint64_t>(passb_bound, nc), 1));
   uint32_t* nseg = ctr;
   launch_init_roots(clouds, nc, pl.E0, segs, nseg, gp.grids, s);
-  partition(w, gp, pl.E0, pl.chunk0, nc, N, in, nullptr, X, Xid, ids, segs, nseg, cube, s, &tm, EV_COUNT0);
+  const uint32_t* in_ids = x && x->d_ids ? x->d_ids + offs[0] : nullptr;
+  partition(w, gp, pl.E0, pl.chunk0, nc, N, in, in_ids, X, Xid, ids, segs, nseg, cube, s, &tm, EV_COUNT0);
   gp.num_grids = nc;
   gp.used_words = (uint64_t)nc * grid_words(pl.E0);
   // 3. every root cell by E1 more levels, X -> Y

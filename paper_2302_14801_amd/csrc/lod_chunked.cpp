@@ -1,0 +1,614 @@
+// lod_chunked.cpp -- the chunked (out-of-core) build: the tree of a host
+// point cloud, equal to the in-core build, made from chunks of a bounded size
+// (Sec. 7: a bottom-up out-of-core pipeline cuts the input into chunks of
+// about 10M points, builds each on the GPU and combines them).
+//
+//   1. the bounding cube of the whole cloud, streaming it through the GPU;
+//   2. the level-h cell of every point and the cell counts (h <= 7), on the
+//      GPU; the host picks the split level b, the shallowest level whose
+//      cells hold at most chunk_points points;
+//   3. the points sorted by level-b cell on the host (stable, threaded);
+//   4. the nodes of levels 0..b from the counts alone: a node at level L is
+//      inner iff it holds more than T points and L < max_level, exactly the
+//      in-core rule;
+//   5. every level-b cell that is an inner node is a chunk root: its subtree
+//      depends on its own points only, so the cells are built in batches of
+//      about chunk_points points with the common cube (lod_build_clouds),
+//      and their nodes at levels >= b are the whole tree's;
+//   6. leaves at levels <= b (at most T points each) are copied from the
+//      sorted host points;
+//   7. the voxels of the inner nodes above b, level by level from b - 1 up,
+//      from their children's samples (k_merge.hip);
+//   8. one tree: nodes in (level, key) order, leaf points in Morton order of
+//      the leaves, voxels in node order, as the in-core build lays them out.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+#include "launch.h"
+
+using namespace lod;
+
+namespace {
+
+// Device memory from the cache for the duration of the build.
+struct DevBuf {
+  int dev = 0;
+  void* p = nullptr;
+  size_t cap = 0;
+  explicit DevBuf(int d) : dev(d) {}
+  DevBuf(const DevBuf&) = delete;
+  template <typename T>
+  T* get(size_t count) {
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (bytes > cap) {
+      release();
+      p = lodint::cache().alloc(dev, bytes);
+      cap = bytes;
+    }
+    return (T*)p;
+  }
+  void release() {
+    if (p) lodint::cache().release(dev, p);
+    p = nullptr;
+    cap = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+// Pinned host memory for the duration of the build.
+struct HostBuf {
+  void* p = nullptr;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  template <typename T>
+  T* get(size_t count) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    if (hipHostMalloc(&p, std::max<size_t>(count * sizeof(T), 64), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      lod_fail(LOD_ERR_OOM, "pinned host allocation failed");
+    }
+    return (T*)p;
+  }
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// Waits for the stream before the buffers above it are released (also when
+// the build unwinds).
+struct Drain {
+  hipStream_t s;
+  ~Drain() { (void)hipStreamSynchronize(s); }
+};
+
+struct TreeDel {
+  void operator()(lod_tree* t) const { lod_tree_free(t); }
+};
+using TreePtr = std::unique_ptr<lod_tree, TreeDel>;
+
+// A node of the merged tree and where its payload comes from.
+struct MNode {
+  uint32_t level;
+  uint64_t key;
+  bool leaf;
+  uint64_t npoints;
+  uint32_t count = 0;    // points (leaf) or voxels (inner)
+  // top leaf: host range of sorted points; top inner: level buffer range;
+  // chunk node: tree and its node index
+  int src = 0;           // 0 top leaf, 1 top inner, 2 chunk node
+  uint64_t hbeg = 0;     // top leaf: first sorted point
+  uint32_t tree = 0;     // chunk node: root index
+  uint64_t soff = 0;     // chunk node: offset in its tree; top inner: offset in its level buffer
+  uint64_t off = 0;      // output offset
+  uint8_t mask = 0;
+  uint32_t first = 0;
+};
+
+// Stable counting sort of n points by cell (nb cells) into out/out_ids, with
+// cell starts in start[nb + 1]; threaded over the input.
+void sort_by_cell(const lod_point* in, const uint32_t* cell, uint32_t shift, uint64_t n, uint32_t nb,
+                  lod_point* out, uint32_t* out_ids, std::vector<uint64_t>& start) {
+  const uint32_t T = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::vector<uint64_t>> cnt(T, std::vector<uint64_t>(nb, 0));
+  auto range = [&](uint32_t t) { return std::make_pair(n * t / T, n * (t + 1) / T); };
+  {
+    std::vector<std::thread> th;
+    for (uint32_t t = 0; t < T; ++t)
+      th.emplace_back([&, t] {
+        auto r = range(t);
+        for (uint64_t i = r.first; i < r.second; ++i) ++cnt[t][cell[i] >> shift];
+      });
+    for (auto& x : th) x.join();
+  }
+  start.assign((size_t)nb + 1, 0);
+  uint64_t run = 0;
+  for (uint32_t c = 0; c < nb; ++c) {
+    start[c] = run;
+    for (uint32_t t = 0; t < T; ++t) {
+      const uint64_t k = cnt[t][c];
+      cnt[t][c] = run;
+      run += k;
+    }
+  }
+  start[nb] = run;
+  std::vector<std::thread> th;
+  for (uint32_t t = 0; t < T; ++t)
+    th.emplace_back([&, t] {
+      auto r = range(t);
+      std::vector<uint64_t>& cur = cnt[t];
+      for (uint64_t i = r.first; i < r.second; ++i) {
+        const uint64_t d = cur[cell[i] >> shift]++;
+        out[d] = in[i];
+        out_ids[d] = (uint32_t)i;
+      }
+    });
+  for (auto& x : th) x.join();
+}
+
+uint64_t morton_order(uint32_t level, uint64_t key) { return key << (3 * (kKeyLevels - level)); }
+
+}  // namespace
+
+lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_params& prm, uint64_t chunk,
+                                 hipStream_t s) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const uint32_t T = prm.leaf_cap;
+  const uint32_t mode = prm.sampling;  // 0 average, 1 first, 2 random
+  const bool ids = mode != LOD_AVERAGE || (prm.flags & LOD_FLAG_POINT_IDS);
+
+  DevBuf d_stage(dev), d_ids(dev), d_cell(dev), d_hist(dev), d_small(dev), d_grids(dev), d_jobs(dev), d_cnt(dev),
+      d_soff(dev), d_runs(dev);
+  HostBuf h_ci, h_cube, h_sorted, h_sids;
+  std::vector<std::unique_ptr<DevBuf>> lvox, lvid;  // voxels of the levels above b
+  Drain drain{s};  // declared last: the stream drains before any buffer above is released
+
+  // everything in one chunk, or no level to split at: the in-core build
+  if (n <= chunk || prm.max_level < 2) {
+    lod_point* dp = d_stage.get<lod_point>(n);
+    if (n) HIPCHK(hipMemcpyAsync(dp, hin, 16ull * n, hipMemcpyHostToDevice, s));
+    return lod_build_tree(dp, n, prm, s);
+  }
+
+  // 1. the bounding cube, piece by piece
+  const uint64_t P = std::min<uint64_t>(n, chunk);
+  const uint64_t npieces = (n + P - 1) / P;
+  lod_point* stage = d_stage.get<lod_point>(P);
+  CloudInfo* hci = h_ci.get<CloudInfo>(npieces + 1);
+  for (uint64_t k = 0; k < npieces; ++k) {
+    const uint64_t m = std::min<uint64_t>(P, n - k * P);
+    hci[k] = CloudInfo{0u, (uint32_t)m, 0u, 0u};
+  }
+  hci[npieces] = CloudInfo{0u, (uint32_t)n, 0u, 0u};
+  char* small = d_small.get<char>(4096 + sizeof(CloudInfo) * (npieces + 1));
+  BBoxAcc* acc = (BBoxAcc*)small;
+  Cube* dcube = (Cube*)(small + 256);
+  CloudInfo* dci = (CloudInfo*)(small + 4096);
+  HIPCHK(hipMemcpyAsync(dci, hci, sizeof(CloudInfo) * (npieces + 1), hipMemcpyHostToDevice, s));
+  launch_bbox_reset(acc, s);
+  for (uint64_t k = 0; k < npieces; ++k) {
+    const uint64_t m = hci[k].count;
+    HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
+    launch_bbox_add(stage, dci + k, bbox_tiles((uint32_t)m), acc, s);
+  }
+  launch_bbox_cube(acc, dci + npieces, dcube, s);
+  Cube* hc = h_cube.get<Cube>(1);
+  HIPCHK(hipMemcpyAsync(hc, dcube, sizeof(Cube), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hc->nonfinite) lod_fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
+
+  // 2. level-h cells and their counts
+  const uint32_t h = std::min<uint32_t>(7, prm.max_level - 1);
+  const uint32_t nh = 1u << (3 * h);
+  uint32_t* hist = d_hist.get<uint32_t>(nh);
+  uint32_t* dcell = d_cell.get<uint32_t>(P);
+  HIPCHK(hipMemsetAsync(hist, 0, 4ull * nh, s));
+  std::vector<uint32_t> cell(n);
+  for (uint64_t k = 0; k < npieces; ++k) {
+    const uint64_t m = hci[k].count;
+    HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
+    launch_cells(stage, (uint32_t)m, dcube, h, dcell, hist, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(cell.data() + k * P, dcell, 4ull * m, hipMemcpyDeviceToHost, s));
+  }
+  // counts of every level 0..h (Morton-contiguous sums)
+  std::vector<std::vector<uint64_t>> cnt(h + 1);
+  {
+    std::vector<uint32_t> hh(nh);
+    HIPCHK(hipMemcpyAsync(hh.data(), hist, 4ull * nh, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    cnt[h].assign(hh.begin(), hh.end());
+    for (int L = (int)h - 1; L >= 0; --L) {
+      cnt[L].assign(1ull << (3 * L), 0);
+      for (uint64_t c = 0; c < cnt[L + 1].size(); ++c) cnt[L][c >> 3] += cnt[L + 1][c];
+    }
+  }
+  uint32_t b = h;
+  for (uint32_t L = 1; L <= h; ++L)
+    if (*std::max_element(cnt[L].begin(), cnt[L].end()) <= chunk) {
+      b = L;
+      break;
+    }
+  const uint32_t nb = 1u << (3 * b);
+
+  // 3. points sorted by level-b cell
+  lod_point* sp = h_sorted.get<lod_point>(n);
+  uint32_t* sid = h_sids.get<uint32_t>(n);
+  std::vector<uint64_t> cstart;
+  sort_by_cell(hin, cell.data(), 3 * (h - b), n, nb, sp, sid, cstart);
+  std::vector<uint32_t>().swap(cell);
+
+  // 4. nodes of levels 0..b
+  std::vector<MNode> nodes;
+  std::vector<uint64_t> roots;  // level-b cells that are inner nodes
+  {
+    std::vector<uint64_t> cur{0};
+    for (uint32_t L = 0; L <= b && !cur.empty(); ++L) {
+      std::vector<uint64_t> next;
+      for (uint64_t key : cur) {
+        MNode m;
+        m.level = L;
+        m.key = key;
+        m.npoints = cnt[L][key];
+        m.leaf = !(m.npoints > T && L < prm.max_level);
+        if (m.leaf) {
+          // a top leaf: its level-b cells are contiguous in the sorted points
+          m.src = 0;
+          m.hbeg = cstart[key << (3 * (b - L))];
+          m.count = (uint32_t)m.npoints;
+          nodes.push_back(m);
+        } else if (L == b) {
+          roots.push_back(key);  // its node comes from the chunk tree
+        } else {
+          m.src = 1;
+          nodes.push_back(m);
+          for (uint32_t o = 0; o < 8; ++o)
+            if (cnt[L + 1][(key << 3) | o]) next.push_back((key << 3) | o);
+        }
+      }
+      cur.swap(next);
+    }
+  }
+
+  // 5. chunk builds: the root cells in batches of about chunk points
+  lod_params cp = prm;
+  if (ids) cp.flags |= LOD_FLAG_POINT_IDS;
+  std::vector<TreePtr> rtrees(roots.size());
+  std::vector<uint32_t> rnode(roots.size());  // index of the level-b node in its tree
+  struct HTree {
+    std::vector<uint8_t> level, leaf;
+    std::vector<uint64_t> key, off;
+    std::vector<uint32_t> npts, count;
+  };
+  std::vector<HTree> ht(roots.size());
+  for (size_t r0 = 0; r0 < roots.size();) {
+    size_t r1 = r0;
+    uint64_t pts = 0;
+    while (r1 < roots.size() && (r1 == r0 || pts + cnt[b][roots[r1]] <= chunk)) pts += cnt[b][roots[r1++]];
+    lod_point* bp = d_stage.get<lod_point>(pts);
+    uint32_t* bid = d_ids.get<uint32_t>(pts);
+    std::vector<uint64_t> offs(r1 - r0 + 1, 0);
+    for (size_t r = r0; r < r1; ++r) {
+      const uint64_t c = roots[r], beg = cstart[c], m = cstart[c + 1] - beg, o = offs[r - r0];
+      HIPCHK(hipMemcpyAsync(bp + o, sp + beg, 16ull * m, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(bid + o, sid + beg, 4ull * m, hipMemcpyHostToDevice, s));
+      offs[r - r0 + 1] = o + m;
+    }
+    BuildExtras x;
+    x.cube = hc;
+    x.d_ids = bid;
+    std::vector<lod_tree*> t = lod_build_clouds(bp, offs.data(), (uint32_t)(r1 - r0), cp, s, &x);
+    for (size_t r = r0; r < r1; ++r) rtrees[r].reset(t[r - r0]);
+    // node tables of the new trees
+    for (size_t r = r0; r < r1; ++r) {
+      const lod_tree_view& v = rtrees[r]->v;
+      HTree& q = ht[r];
+      const uint32_t nn = v.num_nodes;
+      q.level.resize(nn); q.leaf.resize(nn); q.key.resize(nn); q.off.resize(nn); q.npts.resize(nn); q.count.resize(nn);
+      HIPCHK(hipMemcpyAsync(q.level.data(), v.node_level, nn, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(q.leaf.data(), v.node_is_leaf, nn, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(q.key.data(), v.node_key, 8ull * nn, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(q.off.data(), v.node_offset, 8ull * nn, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(q.npts.data(), v.node_npoints, 4ull * nn, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(q.count.data(), v.node_count, 4ull * nn, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t r = r0; r < r1; ++r) {
+      const HTree& q = ht[r];
+      bool found = false;
+      for (uint32_t i = 0; i < q.level.size(); ++i) {
+        if (q.level[i] < b) continue;
+        if (q.level[i] == b) {
+          if (q.key[i] != roots[r] || q.leaf[i]) lod_fail(LOD_ERR_CAPACITY, "chunk root differs from the cell counts");
+          rnode[r] = i;
+          found = true;
+        }
+        MNode m;
+        m.level = q.level[i];
+        m.key = q.key[i];
+        m.leaf = q.leaf[i] != 0;
+        m.npoints = q.npts[i];
+        m.count = q.count[i];
+        m.src = 2;
+        m.tree = (uint32_t)r;
+        m.soff = q.off[i];
+        nodes.push_back(m);
+      }
+      if (!found) lod_fail(LOD_ERR_CAPACITY, "chunk tree without its root cell");
+    }
+    r0 = r1;
+  }
+  d_ids.release();
+
+  // 8a. node order, children, leaf point offsets
+  std::sort(nodes.begin(), nodes.end(), [](const MNode& a, const MNode& c) {
+    return a.level != c.level ? a.level < c.level : a.key < c.key;
+  });
+  const uint32_t num_nodes = (uint32_t)nodes.size();
+  {
+    // children of node i: the next level's nodes whose key >> 3 is its key,
+    // consecutive in (level, key) order
+    size_t j = 0;
+    for (uint32_t i = 0; i < num_nodes; ++i) {
+      MNode& m = nodes[i];
+      if (m.leaf) continue;
+      while (j < num_nodes && (nodes[j].level < m.level + 1 ||
+                               (nodes[j].level == m.level + 1 && (nodes[j].key >> 3) < m.key)))
+        ++j;
+      m.first = (uint32_t)j;
+      for (size_t k = j; k < num_nodes && nodes[k].level == m.level + 1 && (nodes[k].key >> 3) == m.key; ++k)
+        m.mask |= (uint8_t)(1u << (nodes[k].key & 7u));
+    }
+    std::vector<uint32_t> leaves;
+    for (uint32_t i = 0; i < num_nodes; ++i)
+      if (nodes[i].leaf) leaves.push_back(i);
+    std::sort(leaves.begin(), leaves.end(), [&](uint32_t a, uint32_t c) {
+      return morton_order(nodes[a].level, nodes[a].key) < morton_order(nodes[c].level, nodes[c].key);
+    });
+    uint64_t run = 0;
+    for (uint32_t i : leaves) {
+      nodes[i].off = run;
+      run += nodes[i].count;
+    }
+    if (run != n) lod_fail(LOD_ERR_CAPACITY, "leaf points do not add up to the input");
+  }
+
+  // 6. output points: top leaves from the sorted host points, chunk leaves
+  // from their trees
+  std::shared_ptr<LodArena> arena = std::make_shared<LodArena>();
+  arena->dev = dev;
+  lod_point* Y = arena->alloc<lod_point>(n);
+  uint32_t* Yid = ids ? arena->alloc<uint32_t>(n) : nullptr;
+  std::vector<CopyRun> prun, irun;
+  for (const MNode& m : nodes) {
+    if (!m.leaf || !m.count) continue;
+    if (m.src == 0) {
+      HIPCHK(hipMemcpyAsync(Y + m.off, sp + m.hbeg, 16ull * m.count, hipMemcpyHostToDevice, s));
+      if (Yid) HIPCHK(hipMemcpyAsync(Yid + m.off, sid + m.hbeg, 4ull * m.count, hipMemcpyHostToDevice, s));
+    } else {
+      const lod_tree_view& v = rtrees[m.tree]->v;
+      prun.push_back(CopyRun{v.points + m.soff, m.off, m.count});
+      if (Yid) irun.push_back(CopyRun{v.point_ids + m.soff, m.off, m.count});
+    }
+  }
+  auto run_copies = [&](const std::vector<CopyRun>& runs, uint32_t bytes, void* dst) {
+    if (runs.empty()) return;
+    CopyRun* dr = d_runs.get<CopyRun>(runs.size());
+    HIPCHK(hipMemcpyAsync(dr, runs.data(), sizeof(CopyRun) * runs.size(), hipMemcpyHostToDevice, s));
+    launch_copy_runs(dr, (uint32_t)runs.size(), bytes, dst, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));  // the run table is reused
+  };
+  run_copies(prun, 16, Y);
+  if (Yid) run_copies(irun, 4, Yid);
+
+  // 7. voxels of the inner nodes above b, level by level
+  std::vector<uint32_t> node_at;  // (level, key) -> node index for the levels <= b
+  lvox.resize(b);
+  lvid.resize(b);
+  auto find = [&](uint32_t level, uint64_t key) -> const MNode& {
+    auto it = std::lower_bound(nodes.begin(), nodes.end(), std::make_pair(level, key),
+                               [](const MNode& a, const std::pair<uint32_t, uint64_t>& k) {
+                                 return a.level != k.first ? a.level < k.first : a.key < k.second;
+                               });
+    return *it;
+  };
+  const uint32_t kMaxJobs = 64;  // 64 dense grids of 8 MB
+  TopCell* grids = d_grids.get<TopCell>((size_t)kMaxJobs * kTopCells);
+  for (int L = (int)b - 1; L >= 0; --L) {
+    std::vector<TopJob> jobs;
+    std::vector<uint32_t> owner;  // node index of each job's parent
+    uint64_t bound = 0;
+    for (uint32_t i = 0; i < num_nodes; ++i) {
+      const MNode& a = nodes[i];
+      if (a.level != (uint32_t)L || a.leaf) continue;
+      for (uint32_t o = 0; o < 8; ++o) {
+        if (!(a.mask >> o & 1u)) continue;
+        const MNode& c = find(L + 1, (a.key << 3) | o);
+        TopJob j{};
+        j.oct = o;
+        j.level = (uint32_t)L;
+        if (c.leaf) {
+          j.kind = 1;
+          j.src = Y + c.off;
+          j.ids = Yid ? Yid + c.off : nullptr;
+          j.count = c.count;
+        } else if (c.src == 2) {
+          const lod_tree_view& v = rtrees[c.tree]->v;
+          j.kind = 0;
+          j.src = (const uint64_t*)v.voxels + c.soff;
+          j.ids = v.voxel_ids ? v.voxel_ids + c.soff : nullptr;
+          j.count = c.count;
+        } else {
+          j.kind = 0;
+          j.src = (const uint64_t*)lvox[L + 1]->p + c.soff;
+          j.ids = mode ? (const uint32_t*)lvid[L + 1]->p + c.soff : nullptr;
+          j.count = c.count;
+        }
+        bound += std::min<uint64_t>(kTopCells, j.count);
+        jobs.push_back(j);
+        owner.push_back(i);
+      }
+    }
+    lvox[L].reset(new DevBuf(dev));
+    lvid[L].reset(new DevBuf(dev));
+    uint64_t* vox = lvox[L]->get<uint64_t>(bound);
+    uint32_t* vid = mode ? lvid[L]->get<uint32_t>(bound) : nullptr;
+    uint64_t pos = 0;
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
+      const uint32_t nj = (uint32_t)std::min<size_t>(kMaxJobs, jobs.size() - j0);
+      uint32_t maxc = 0;
+      for (uint32_t k = 0; k < nj; ++k) maxc = std::max(maxc, jobs[j0 + k].count);
+      TopJob* dj = d_jobs.get<TopJob>(nj);
+      uint32_t* dcnt = d_cnt.get<uint32_t>((size_t)nj * kTopSlices);
+      uint64_t* dsoff = d_soff.get<uint64_t>((size_t)nj * kTopSlices);
+      HIPCHK(hipMemcpyAsync(dj, jobs.data() + j0, sizeof(TopJob) * nj, hipMemcpyHostToDevice, s));
+      launch_top_clear(grids, nj, mode, s);
+      launch_top_splat(dj, nj, maxc, dcube, mode, prm.seed, grids, s);
+      launch_top_count(grids, nj, dcnt, s);
+      HIPCHK(hipGetLastError());
+      std::vector<uint32_t> hcnt((size_t)nj * kTopSlices);
+      std::vector<uint64_t> hsoff((size_t)nj * kTopSlices);
+      HIPCHK(hipMemcpyAsync(hcnt.data(), dcnt, 4ull * hcnt.size(), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (uint32_t k = 0; k < nj; ++k) {
+        uint32_t jc = 0;
+        for (uint32_t q = 0; q < kTopSlices; ++q) {
+          hsoff[(size_t)k * kTopSlices + q] = pos;
+          pos += hcnt[(size_t)k * kTopSlices + q];
+          jc += hcnt[(size_t)k * kTopSlices + q];
+        }
+        MNode& a = nodes[owner[j0 + k]];
+        if (a.count == 0) a.soff = pos - jc;  // the parent's first job
+        a.count += jc;
+      }
+      HIPCHK(hipMemcpyAsync(dsoff, hsoff.data(), 8ull * hsoff.size(), hipMemcpyHostToDevice, s));
+      launch_top_emit(dj, nj, grids, dsoff, mode, vox, vid, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));  // the host tables are refilled
+    }
+  }
+  d_grids.release();
+
+  // 8b. voxels in node order
+  uint64_t vtotal = 0;
+  for (MNode& m : nodes)
+    if (!m.leaf) {
+      m.off = vtotal;
+      vtotal += m.count;
+    }
+  uint64_t* vox = arena->alloc<uint64_t>(std::max<uint64_t>(vtotal, 1));
+  uint32_t* vids = mode ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
+  std::vector<CopyRun> vrun, vidrun;
+  for (const MNode& m : nodes) {
+    if (m.leaf || !m.count) continue;
+    if (m.src == 2) {
+      const lod_tree_view& v = rtrees[m.tree]->v;
+      vrun.push_back(CopyRun{(const uint64_t*)v.voxels + m.soff, m.off, m.count});
+      if (vids) vidrun.push_back(CopyRun{v.voxel_ids + m.soff, m.off, m.count});
+    } else {
+      vrun.push_back(CopyRun{(const uint64_t*)lvox[m.level]->p + m.soff, m.off, m.count});
+      if (vids) vidrun.push_back(CopyRun{(const uint32_t*)lvid[m.level]->p + m.soff, m.off, m.count});
+    }
+  }
+  run_copies(vrun, 8, vox);
+  if (vids) run_copies(vidrun, 4, vids);
+
+  // 8c. node table
+  uint8_t* o_level = arena->alloc<uint8_t>(num_nodes);
+  uint8_t* o_leaf = arena->alloc<uint8_t>(num_nodes);
+  uint8_t* o_mask = arena->alloc<uint8_t>(num_nodes);
+  uint64_t* o_key = arena->alloc<uint64_t>(num_nodes);
+  uint32_t* o_npts = arena->alloc<uint32_t>(num_nodes);
+  uint32_t* o_count = arena->alloc<uint32_t>(num_nodes);
+  uint32_t* o_first = arena->alloc<uint32_t>(num_nodes);
+  uint64_t* o_off = arena->alloc<uint64_t>(num_nodes);
+  {
+    std::vector<uint8_t> lv(num_nodes), lf(num_nodes), mk(num_nodes);
+    std::vector<uint64_t> ky(num_nodes), of(num_nodes);
+    std::vector<uint32_t> np(num_nodes), ct(num_nodes), fc(num_nodes);
+    for (uint32_t i = 0; i < num_nodes; ++i) {
+      const MNode& m = nodes[i];
+      lv[i] = (uint8_t)m.level;
+      lf[i] = m.leaf ? 1 : 0;
+      mk[i] = m.mask;
+      ky[i] = m.key;
+      of[i] = m.off;
+      np[i] = (uint32_t)m.npoints;
+      ct[i] = m.count;
+      fc[i] = m.leaf ? 0u : m.first;
+    }
+    HIPCHK(hipMemcpyAsync(o_level, lv.data(), num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(o_leaf, lf.data(), num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(o_mask, mk.data(), num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(o_key, ky.data(), 8ull * num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(o_npts, np.data(), 4ull * num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(o_count, ct.data(), 4ull * num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(o_first, fc.data(), 4ull * num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(o_off, of.data(), 8ull * num_nodes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  std::unique_ptr<lod_tree> t(new lod_tree());
+  t->dev = dev;
+  t->arena = arena;
+  t->footprint = arena->bytes;
+  lod_tree_view& v = t->v;
+  for (int a = 0; a < 3; ++a) {
+    v.aabb_min[a] = hc->lo[a];
+    v.aabb_max[a] = hc->hi[a];
+  }
+  v.cube_side = hc->side;
+  v.num_nodes = num_nodes;
+  v.num_points = n;
+  v.num_voxels = vtotal;
+  v.node_level = o_level;
+  v.node_is_leaf = o_leaf;
+  v.node_child_mask = o_mask;
+  v.node_key = o_key;
+  v.node_npoints = o_npts;
+  v.node_count = o_count;
+  v.node_first_child = o_first;
+  v.node_offset = o_off;
+  v.points = Y;
+  v.point_ids = Yid;
+  v.voxels = (const lod_voxel*)vox;
+  v.voxel_ids = vids;
+  v.voxel_points = nullptr;
+  return t.release();
+}
+
+extern "C" lod_status lod_build_chunked(const lod_point* h_points, uint64_t n, const lod_params* p,
+                                        uint64_t chunk_points, void* hip_stream, lod_tree** out) {
+  if (!out) {
+    lod_set_error("out is NULL");
+    return LOD_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (!p || p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 2 || p->tune_levels0 > 4 ||
+      p->tune_levels1 > 4 || (p->flags & LOD_FLAG_FULL_PRECISION)) {
+    lod_set_error("invalid parameters (the chunked build takes the average and pick modes, without full precision)");
+    return LOD_ERR_INVALID;
+  }
+  if (n >= 0xffffffffull || (n && !h_points) || chunk_points == 0) {
+    lod_set_error("n must be below 2^32, h_points non-NULL and chunk_points positive");
+    return LOD_ERR_INVALID;
+  }
+  try {
+    *out = lod_build_chunked_tree(h_points, n, *p, chunk_points, (hipStream_t)hip_stream);
+    return LOD_OK;
+  } catch (const LodError& e) {
+    (void)hipGetLastError();
+    return e.st;
+  } catch (...) {
+    lod_set_error("unexpected host exception");
+    return LOD_ERR_OOM;
+  }
+}

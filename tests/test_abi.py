@@ -57,6 +57,21 @@ def test_argument_errors_before_any_device_work(lib):
     assert b"invalid" in lib.lod_last_error()
 
 
+def test_chunked_argument_errors_before_any_device_work(lib):
+    from paper_2302_14801_amd import binding
+    p = binding.lod_params()
+    lib.lod_params_default(ctypes.byref(p))
+    out = ctypes.c_void_p()
+    assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, None) == binding.LOD_ERR_INVALID
+    assert lib.lod_build_chunked(None, 10, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 0, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    p.sampling = binding.LOD_WEIGHTED
+    assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    p.sampling, p.flags = binding.LOD_AVERAGE, binding.LOD_FLAG_FULL_PRECISION
+    assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
+    assert out.value is None
+
+
 def test_package_refuses_to_import_without_library(tmp_path, monkeypatch):
     from paper_2302_14801_amd import binding
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))

@@ -1,0 +1,133 @@
+"""GPU parity of the chunked (out-of-core) build: the tree of a host cloud,
+built through cells of one level of the common cube and merged above them,
+equals the oracle's in-core tree of the whole cloud, and has the layout of
+the in-core GPU build (same node table, same voxel array, same leaf ranges)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import canon
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2302_14801_amd as lod
+    return lod
+
+
+def host_tree(t):
+    h = t.to_host()
+    t.free()
+    return h
+
+
+def in_core(lod, points, **kw):
+    import torch
+    raw = np.ascontiguousarray(points).view(np.uint8).reshape(-1)
+    return host_tree(lod.lod_build(torch.from_numpy(raw.copy()).to("cuda:0"), **kw))
+
+
+def check_chunked(lod, points, chunk, T, ml=12, sampling=0, seed=0, keep_ids=False):
+    print(f"case n={len(points)} chunk={chunk} T={T} ml={ml} sampling={sampling}", flush=True)
+    kw = dict(leaf_cap=T, max_level=ml, sampling=sampling, seed=seed, keep_ids=keep_ids)
+    g = host_tree(lod.lod_build_chunked(np.ascontiguousarray(points), chunk, **kw))
+    o = oracle.build(points, leaf_cap=T, max_level=ml, sampling=sampling, seed=seed)
+    canon.compare_trees(g, o, points)
+    d = in_core(lod, points, **kw)
+    for f in canon.NODE_FIELDS + ("offset",):
+        assert np.array_equal(g[f], d[f]), f"node field {f} differs from the in-core build"
+    assert np.array_equal(g["voxels"], d["voxels"])
+    if d["voxel_ids"] is not None:
+        assert np.array_equal(g["voxel_ids"], d["voxel_ids"])
+    for i in np.nonzero(g["is_leaf"])[0]:
+        a, c = int(g["offset"][i]), int(g["count"][i])
+        assert np.array_equal(canon.rows_sorted(g["points"][a:a + c]), canon.rows_sorted(d["points"][a:a + c]))
+        if d["point_ids"] is not None:
+            assert np.array_equal(np.sort(g["point_ids"][a:a + c]), np.sort(d["point_ids"][a:a + c]))
+    return g
+
+
+@pytest.mark.parametrize("sampling", [0, 1, 2])
+def test_uniform(lod, sampling):
+    p = synth.uniform_cloud(200_000, 31, lo=(-3, 10, 100), hi=(5, 12, 101))
+    check_chunked(lod, p, 20_000, T=500, sampling=sampling, seed=5)
+
+
+@pytest.mark.parametrize("sampling", [0, 1, 2])
+def test_terrain(lod, sampling):
+    p = synth.terrain(300_000, seed=6)
+    check_chunked(lod, p, 50_000, T=2000, sampling=sampling, seed=9)
+
+
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_aerial(lod, sampling):
+    p = synth.aerial(400_000, seed=2)
+    check_chunked(lod, p, 60_000, T=5000, sampling=sampling)
+
+
+def test_scan_with_ids(lod):
+    p = synth.scan(300_000, seed=3)
+    check_chunked(lod, p, 40_000, T=2000, ml=14, keep_ids=True)
+
+
+@pytest.mark.parametrize("sampling", [0, 2])
+def test_dense_blob_and_sparse_leaves(lod, sampling):
+    """Small leaves above the split level next to chunk roots: a dense blob and
+    a few hundred points spread over the cube."""
+    blob = synth.uniform_cloud(100_000, 41, lo=(0.40, 0.40, 0.40), hi=(0.45, 0.43, 0.41))
+    sparse = synth.uniform_cloud(300, 42)
+    p = np.concatenate([sparse[:150], blob, sparse[150:]])
+    check_chunked(lod, p, 5_000, T=1000, sampling=sampling, seed=3)
+
+
+def test_chunk_of_one_point(lod):
+    """No level has cells of at most one point: the split is at level 7, and
+    every chunk root is a batch of its own."""
+    blob = synth.uniform_cloud(30_000, 43, lo=(0.0, 0.0, 0.0), hi=(0.01, 0.01, 0.01))
+    p = np.concatenate([blob, synth.uniform_cloud(2_000, 44)])
+    check_chunked(lod, p, 1, T=300, sampling=1)
+
+
+def test_everything_above_the_split(lod):
+    p = synth.uniform_cloud(20_000, 45)
+    check_chunked(lod, p, 1, T=300)
+
+
+def test_identical_points_to_the_depth_limit(lod):
+    p = synth.uniform_cloud(5_000, 46)
+    p[:] = p[0]
+    check_chunked(lod, p, 1_000, T=100, ml=6)
+
+
+@pytest.mark.parametrize("ml", [1, 2, 3])
+def test_shallow_depth_limits(lod, ml):
+    p = synth.terrain(50_000, seed=7)
+    check_chunked(lod, p, 4_000, T=500, ml=ml, sampling=1)
+
+
+def test_one_chunk_is_the_in_core_build(lod):
+    p = synth.terrain(30_000, seed=8)
+    check_chunked(lod, p, 30_000, T=1000, sampling=2, seed=1)
+
+
+def test_empty(lod):
+    g = host_tree(lod.lod_build_chunked(synth.uniform_cloud(0, 1), 10))
+    assert g["num_nodes"] == 0 and g["num_points"] == 0
+
+
+def test_errors(lod):
+    p = synth.uniform_cloud(1_000, 47)
+    p["y"][500] = np.nan
+    with pytest.raises(lod.LodError) as e:
+        lod.lod_build_chunked(p, 100)
+    assert e.value.status == -2
+    with pytest.raises(lod.LodError) as e:
+        lod.lod_build_chunked(synth.uniform_cloud(1_000, 48), 100, sampling=3)
+    assert e.value.status == -1
