@@ -281,6 +281,9 @@ def main():
                     help="builds of the same cloud with full-precision lower levels (0 = skip)")
     ap.add_argument("--weighted-steps", type=int, default=3,
                     help="builds of the same cloud with the neighbourhood-weighted average (0 = skip)")
+    ap.add_argument("--chunked-steps", type=int, default=2,
+                    help="chunked builds of the same cloud from host memory (0 = skip)")
+    ap.add_argument("--chunk-points", type=int, default=10_000_000, help="chunk size of the chunked build")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -383,6 +386,38 @@ def main():
     # the neighbourhood-weighted average on the same cloud
     weighted = variant(args.weighted_steps, sampling=3) if args.weighted_steps > 0 else None
 
+    # the same cloud from pinned host memory, built in chunks and merged
+    # (the out-of-core scheme), beside a host -> device copy plus the in-core build
+    chunked = None
+    if args.chunked_steps > 0:
+        print(f"[bench] chunked build, {args.chunk_points} points per chunk", file=sys.stderr, flush=True)
+        pc = lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling)
+
+        def cstep():
+            t = lod.lod_build_chunked(pts, args.chunk_points, params=pc, stream=stream)
+            v = t.view()
+            info = (v.num_nodes, v.num_voxels)
+            t.free()
+            return info
+
+        cstep()
+        c0 = time.perf_counter()
+        cinfo = [cstep() for _ in range(args.chunked_steps)]
+        cms = 1e3 * (time.perf_counter() - c0) / args.chunked_steps
+        h0 = time.perf_counter()
+        for _ in range(args.chunked_steps):
+            d2 = host.to("cuda:0", non_blocking=False)
+            t = lod.lod_build(d2, params=params, stream=stream)
+            t.free()
+            del d2
+        torch.cuda.synchronize()
+        hms = 1e3 * (time.perf_counter() - h0) / args.chunked_steps
+        chunked = {"chunk_points": args.chunk_points, "ms_per_build": round(cms, 2),
+                   "points_per_s": round(n / (cms * 1e-3), 1), "steps": args.chunked_steps,
+                   "in_core_from_host_ms": round(hms, 2), "same_nodes_and_voxels": cinfo[-1] == infos[-1],
+                   "note": "host input: streaming passes for the cube and the cell counts, each piece sorted by cell on the GPU, "
+                           "chunk uploads and builds, the merge above the chunk roots"}
+
     cpu = None
     if args.cpu_sample > 0:
         import oracle
@@ -430,6 +465,7 @@ def main():
         "voxels": voxels,
         "full_precision": full,
         "weighted": weighted,
+        "chunked": chunked,
         "batched": batched,
         "served": served,
     }

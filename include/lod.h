@@ -169,16 +169,17 @@ lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets,
  * combines them).  h_points: HOST array of n records (pageable or pinned),
  * borrowed; the result equals lod_build on the whole cloud (same nodes, node
  * order, leaf point sets, voxels and ids; ids are indices into h_points).
- * The cloud streams through the GPU in pieces of chunk_points records for its
- * bounding cube and cell counts; it is cut at the shallowest level b (at most
+ * The cloud streams through the GPU in pieces of max(chunk_points, 2^20)
+ * records for its bounding cube and cell counts, and once more to be sorted
+ * by cell piece by piece; it is cut at the shallowest level b (at most
  * min(7, max_level - 1)) whose cells hold at most chunk_points points, and
  * every cell of level b with more than T points is built as a chunk (chunks
  * are batched up to chunk_points points) with the common cube; the levels
  * above b are then voxelized from the chunk roots' voxels and the points of
  * the leaves above them.  Device memory: the build workspace of one batch,
  * plus the chunk results and the output tree (about twice the output).  Host
- * memory: 20 B per point (pinned) for the points sorted by cell, and 4 B per
- * point for the cells.  With n <= chunk_points, or max_level < 2, this is
+ * memory: 20 B per point (pinned) for the pieces sorted by cell on the GPU.
+ * With n <= chunk_points, or max_level < 2, this is
  * the in-core build of a device copy.  Sampling: AVERAGE, PICK_FIRST and
  * PICK_RANDOM (LOD_WEIGHTED and LOD_FLAG_FULL_PRECISION give
  * LOD_ERR_INVALID).  Errors: LOD_ERR_INVALID (NULL out/params, n >= 2^32,

@@ -35,10 +35,157 @@ __global__ void __launch_bounds__(256) k_cells(const uint4* __restrict__ pts, ui
   atomicAdd(hist + c, 1u);
 }
 
+// The same for levels of at most 4096 cells (h <= 4): a workgroup counts a
+// tile of 4096 points in LDS and adds each cell once, so few cells do not
+// serialize millions of global atomics.
+constexpr uint32_t kCellTile = 4096;  // 16 points per thread
+constexpr uint32_t kLdsCells = 4096;
+
+__global__ void __launch_bounds__(256) k_cells_lds(const uint4* __restrict__ pts, uint32_t n, const Cube* cube,
+                                                   uint32_t h, uint32_t* __restrict__ cell, uint32_t* hist) {
+  __shared__ uint32_t lh[kLdsCells];
+  const uint32_t nb = 1u << (3 * h), t = threadIdx.x;
+  for (uint32_t c = t; c < nb; c += 256) lh[c] = 0;
+  __syncthreads();
+  const CubeD cd = load_cube(cube);
+  const uint32_t s = kKeyLevels - h;
+  for (uint32_t k = 0; k < kCellTile / 256; ++k) {
+    const uint32_t i = blockIdx.x * kCellTile + k * 256 + t;
+    if (i >= n) break;
+    const uint4 v = pts[i];
+    const uint32_t c = morton7(quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) >> s,
+                               quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) >> s,
+                               quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) >> s);
+    cell[i] = c;
+    atomicAdd(&lh[c], 1u);
+  }
+  __syncthreads();
+  for (uint32_t c = t; c < nb; c += 256)
+    if (lh[c]) atomicAdd(hist + c, lh[c]);
+}
+
 void launch_cells(const void* pts, uint32_t n, const Cube* cube, uint32_t h, uint32_t* cell, uint32_t* hist,
                   hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_cells, dim3((n + 255) / 256), dim3(256), 0, s, (const uint4*)pts, n, cube, h, cell, hist);
+  if ((1u << (3 * h)) <= kLdsCells)
+    hipLaunchKernelGGL(k_cells_lds, dim3((n + kCellTile - 1) / kCellTile), dim3(256), 0, s, (const uint4*)pts, n,
+                       cube, h, cell, hist);
+  else
+    hipLaunchKernelGGL(k_cells, dim3((n + 255) / 256), dim3(256), 0, s, (const uint4*)pts, n, cube, h, cell, hist);
+}
+
+// Counting sort of a piece by cell: exclusive prefix of the histogram (a
+// workgroup per tile of 4096 bins, a one-workgroup pass over the tile sums,
+// then the bins), then every point to its cell's next slot.  The order inside
+// a cell is free (the build does not depend on it; ids travel along).
+constexpr uint32_t kBinTile = 4096;  // 16 bins per thread
+
+__global__ void __launch_bounds__(256) k_bin_tiles(const uint32_t* __restrict__ hist, uint32_t nbins,
+                                                   uint32_t* __restrict__ tile_sum) {
+  __shared__ uint32_t sh[256 / 64 + 1];
+  const uint32_t b0 = blockIdx.x * kBinTile + threadIdx.x * 16;
+  uint32_t sum = 0;
+  for (uint32_t k = 0; k < 16; ++k)
+    if (b0 + k < nbins) sum += hist[b0 + k];
+  uint32_t tot;
+  (void)block_excl_scan<256>(sum, sh, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// In place: tile sums -> exclusive tile offsets (ntiles <= 256 * 4).
+__global__ void __launch_bounds__(256) k_tile_offsets(uint32_t* tile_sum, uint32_t ntiles) {
+  __shared__ uint32_t sh[256 / 64 + 1];
+  const uint32_t t0 = threadIdx.x * 4;
+  uint32_t v[4], sum = 0;
+  for (uint32_t k = 0; k < 4; ++k) {
+    v[k] = t0 + k < ntiles ? tile_sum[t0 + k] : 0u;
+    sum += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan<256>(sum, sh, &tot);
+  for (uint32_t k = 0; k < 4; ++k) {
+    if (t0 + k < ntiles) tile_sum[t0 + k] = run;
+    run += v[k];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bin_cursors(const uint32_t* __restrict__ hist, uint32_t nbins,
+                                                     const uint32_t* __restrict__ tile_off, uint32_t* __restrict__ cursor) {
+  __shared__ uint32_t sh[256 / 64 + 1];
+  const uint32_t b0 = blockIdx.x * kBinTile + threadIdx.x * 16;
+  uint32_t v[16], sum = 0;
+  for (uint32_t k = 0; k < 16; ++k) {
+    v[k] = b0 + k < nbins ? hist[b0 + k] : 0u;
+    sum += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = tile_off[blockIdx.x] + block_excl_scan<256>(sum, sh, &tot);
+  for (uint32_t k = 0; k < 16; ++k) {
+    if (b0 + k < nbins) cursor[b0 + k] = run;
+    run += v[k];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scatter_cells(const uint4* __restrict__ pts, const uint32_t* __restrict__ cell,
+                                                       uint32_t n, uint32_t id0, uint32_t* cursor,
+                                                       uint4* __restrict__ out, uint32_t* __restrict__ out_ids) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t pos = atomicAdd(cursor + cell[i], 1u);
+  out[pos] = pts[i];
+  out_ids[pos] = id0 + i;
+}
+
+// Few cells: a workgroup ranks a tile of 4096 points per cell in LDS, then
+// reserves each cell's slots with one global atomic.
+__global__ void __launch_bounds__(256) k_scatter_cells_lds(const uint4* __restrict__ pts,
+                                                           const uint32_t* __restrict__ cell, uint32_t n,
+                                                           uint32_t nbins, uint32_t id0, uint32_t* cursor,
+                                                           uint4* __restrict__ out, uint32_t* __restrict__ out_ids) {
+  __shared__ uint32_t lc[kLdsCells], lb[kLdsCells];
+  const uint32_t t = threadIdx.x;
+  for (uint32_t c = t; c < nbins; c += 256) lc[c] = 0;
+  __syncthreads();
+  constexpr uint32_t K = kCellTile / 256;
+  uint32_t cc[K], rk[K];
+#pragma unroll
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint32_t i = blockIdx.x * kCellTile + k * 256 + t;
+    cc[k] = 0;
+    rk[k] = 0;
+    if (i < n) {
+      cc[k] = cell[i];
+      rk[k] = atomicAdd(&lc[cc[k]], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t c = t; c < nbins; c += 256) lb[c] = lc[c] ? atomicAdd(cursor + c, lc[c]) : 0u;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint32_t i = blockIdx.x * kCellTile + k * 256 + t;
+    if (i < n) {
+      const uint32_t pos = lb[cc[k]] + rk[k];
+      out[pos] = pts[i];
+      out_ids[pos] = id0 + i;
+    }
+  }
+}
+
+void launch_sort_by_cell(const void* pts, const uint32_t* cell, uint32_t n, uint32_t id0, const uint32_t* hist,
+                         uint32_t nbins, uint32_t* tiles, uint32_t* cursor, void* out, uint32_t* out_ids,
+                         hipStream_t s) {
+  if (!n) return;
+  const uint32_t ntiles = (nbins + kBinTile - 1) / kBinTile;
+  hipLaunchKernelGGL(k_bin_tiles, dim3(ntiles), dim3(256), 0, s, hist, nbins, tiles);
+  hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(256), 0, s, tiles, ntiles);
+  hipLaunchKernelGGL(k_bin_cursors, dim3(ntiles), dim3(256), 0, s, hist, nbins, (const uint32_t*)tiles, cursor);
+  if (nbins <= kLdsCells)
+    hipLaunchKernelGGL(k_scatter_cells_lds, dim3((n + kCellTile - 1) / kCellTile), dim3(256), 0, s,
+                       (const uint4*)pts, cell, n, nbins, id0, cursor, (uint4*)out, out_ids);
+  else
+    hipLaunchKernelGGL(k_scatter_cells, dim3((n + 255) / 256), dim3(256), 0, s, (const uint4*)pts, cell, n, id0,
+                       cursor, (uint4*)out, out_ids);
 }
 
 // ------------------------------------------------------------ top levels

@@ -96,6 +96,12 @@ uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes);
 // their histogram (8^h counters, added to).
 void launch_cells(const void* pts, uint32_t n, const Cube* cube, uint32_t h, uint32_t* cell, uint32_t* hist,
                   hipStream_t s);
+// A piece sorted by cell (nbins <= 2^21 cells, hist: its histogram): tiles
+// (nbins / 4096 rounded up, at most 1024) and cursor (nbins) are scratch;
+// out / out_ids receive the points and their ids id0 + index.
+void launch_sort_by_cell(const void* pts, const uint32_t* cell, uint32_t n, uint32_t id0, const uint32_t* hist,
+                         uint32_t nbins, uint32_t* tiles, uint32_t* cursor, void* out, uint32_t* out_ids,
+                         hipStream_t s);
 // A job of the levels above the chunk roots: one child (octant `oct`) of a
 // node at `level`, whose samples are `count` voxels (kind 0, 8-byte words of
 // the child's grid) or points (kind 1, 16-byte records) at `src`, with ids

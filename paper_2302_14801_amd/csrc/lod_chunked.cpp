@@ -4,10 +4,11 @@
 // about 10M points, builds each on the GPU and combines them).
 //
 //   1. the bounding cube of the whole cloud, streaming it through the GPU;
-//   2. the level-h cell of every point and the cell counts (h <= 7), on the
-//      GPU; the host picks the split level b, the shallowest level whose
-//      cells hold at most chunk_points points;
-//   3. the points sorted by level-b cell on the host (stable, threaded);
+//   2. the level-h cell counts (h <= 7), on the GPU; the host picks the
+//      split level b, the shallowest level whose cells hold at most
+//      chunk_points points;
+//   3. each piece sorted by level-b cell on the GPU and sent back, so that a
+//      cell's points are one run per piece;
 //   4. the nodes of levels 0..b from the counts alone: a node at level L is
 //      inner iff it holds more than T points and L < max_level, exactly the
 //      in-core rule;
@@ -16,7 +17,7 @@
 //      about chunk_points points with the common cube (lod_build_clouds),
 //      and their nodes at levels >= b are the whole tree's;
 //   6. leaves at levels <= b (at most T points each) are copied from the
-//      sorted host points;
+//      sorted pieces;
 //   7. the voxels of the inner nodes above b, level by level from b - 1 up,
 //      from their children's samples (k_merge.hip);
 //   8. one tree: nodes in (level, key) order, leaf points in Morton order of
@@ -24,7 +25,6 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
-#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -103,54 +103,13 @@ struct MNode {
   // top leaf: host range of sorted points; top inner: level buffer range;
   // chunk node: tree and its node index
   int src = 0;           // 0 top leaf, 1 top inner, 2 chunk node
-  uint64_t hbeg = 0;     // top leaf: first sorted point
+  uint64_t c0 = 0, c1 = 0;  // top leaf: its level-b cells
   uint32_t tree = 0;     // chunk node: root index
   uint64_t soff = 0;     // chunk node: offset in its tree; top inner: offset in its level buffer
   uint64_t off = 0;      // output offset
   uint8_t mask = 0;
   uint32_t first = 0;
 };
-
-// Stable counting sort of n points by cell (nb cells) into out/out_ids, with
-// cell starts in start[nb + 1]; threaded over the input.
-void sort_by_cell(const lod_point* in, const uint32_t* cell, uint32_t shift, uint64_t n, uint32_t nb,
-                  lod_point* out, uint32_t* out_ids, std::vector<uint64_t>& start) {
-  const uint32_t T = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<std::vector<uint64_t>> cnt(T, std::vector<uint64_t>(nb, 0));
-  auto range = [&](uint32_t t) { return std::make_pair(n * t / T, n * (t + 1) / T); };
-  {
-    std::vector<std::thread> th;
-    for (uint32_t t = 0; t < T; ++t)
-      th.emplace_back([&, t] {
-        auto r = range(t);
-        for (uint64_t i = r.first; i < r.second; ++i) ++cnt[t][cell[i] >> shift];
-      });
-    for (auto& x : th) x.join();
-  }
-  start.assign((size_t)nb + 1, 0);
-  uint64_t run = 0;
-  for (uint32_t c = 0; c < nb; ++c) {
-    start[c] = run;
-    for (uint32_t t = 0; t < T; ++t) {
-      const uint64_t k = cnt[t][c];
-      cnt[t][c] = run;
-      run += k;
-    }
-  }
-  start[nb] = run;
-  std::vector<std::thread> th;
-  for (uint32_t t = 0; t < T; ++t)
-    th.emplace_back([&, t] {
-      auto r = range(t);
-      std::vector<uint64_t>& cur = cnt[t];
-      for (uint64_t i = r.first; i < r.second; ++i) {
-        const uint64_t d = cur[cell[i] >> shift]++;
-        out[d] = in[i];
-        out_ids[d] = (uint32_t)i;
-      }
-    });
-  for (auto& x : th) x.join();
-}
 
 uint64_t morton_order(uint32_t level, uint64_t key) { return key << (3 * (kKeyLevels - level)); }
 
@@ -165,7 +124,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   const bool ids = mode != LOD_AVERAGE || (prm.flags & LOD_FLAG_POINT_IDS);
 
   DevBuf d_stage(dev), d_ids(dev), d_cell(dev), d_hist(dev), d_small(dev), d_grids(dev), d_jobs(dev), d_cnt(dev),
-      d_soff(dev), d_runs(dev);
+      d_soff(dev), d_runs(dev), d_sorted(dev), d_sids(dev), d_cursor(dev), d_tiles(dev);
   HostBuf h_ci, h_cube, h_sorted, h_sids;
   std::vector<std::unique_ptr<DevBuf>> lvox, lvid;  // voxels of the levels above b
   Drain drain{s};  // declared last: the stream drains before any buffer above is released
@@ -177,8 +136,8 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     return lod_build_tree(dp, n, prm, s);
   }
 
-  // 1. the bounding cube, piece by piece
-  const uint64_t P = std::min<uint64_t>(n, chunk);
+  // 1. the bounding cube, piece by piece (pieces of at least 2^20 points)
+  const uint64_t P = std::min<uint64_t>(n, std::max<uint64_t>(chunk, 1u << 20));
   const uint64_t npieces = (n + P - 1) / P;
   lod_point* stage = d_stage.get<lod_point>(P);
   CloudInfo* hci = h_ci.get<CloudInfo>(npieces + 1);
@@ -210,13 +169,11 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   uint32_t* hist = d_hist.get<uint32_t>(nh);
   uint32_t* dcell = d_cell.get<uint32_t>(P);
   HIPCHK(hipMemsetAsync(hist, 0, 4ull * nh, s));
-  std::vector<uint32_t> cell(n);
   for (uint64_t k = 0; k < npieces; ++k) {
     const uint64_t m = hci[k].count;
     HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
     launch_cells(stage, (uint32_t)m, dcube, h, dcell, hist, s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(cell.data() + k * P, dcell, 4ull * m, hipMemcpyDeviceToHost, s));
   }
   // counts of every level 0..h (Morton-contiguous sums)
   std::vector<std::vector<uint64_t>> cnt(h + 1);
@@ -238,12 +195,53 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     }
   const uint32_t nb = 1u << (3 * b);
 
-  // 3. points sorted by level-b cell
+  // 3. every piece sorted by level-b cell on the GPU; pst[k][c]: first point
+  // of cell c in piece k (piece k starts at k * P3 of the sorted arrays).
+  // Pieces of at least 16 points per cell keep these tables at n / 4 bytes.
+  const uint64_t P3 = std::min<uint64_t>(n, std::max<uint64_t>(P, 16ull * nb));
+  const uint64_t npieces3 = (n + P3 - 1) / P3;
   lod_point* sp = h_sorted.get<lod_point>(n);
   uint32_t* sid = h_sids.get<uint32_t>(n);
-  std::vector<uint64_t> cstart;
-  sort_by_cell(hin, cell.data(), 3 * (h - b), n, nb, sp, sid, cstart);
-  std::vector<uint32_t>().swap(cell);
+  std::vector<std::vector<uint32_t>> pst(npieces3, std::vector<uint32_t>((size_t)nb + 1));
+  {
+    stage = d_stage.get<lod_point>(P3);
+    dcell = d_cell.get<uint32_t>(P3);
+    lod_point* dsorted = d_sorted.get<lod_point>(P3);
+    uint32_t* dsids = d_sids.get<uint32_t>(P3);
+    uint32_t* cursor = d_cursor.get<uint32_t>(nb);
+    uint32_t* tiles = d_tiles.get<uint32_t>(1024);
+    for (uint64_t k = 0; k < npieces3; ++k) {
+      const uint64_t m = std::min<uint64_t>(P3, n - k * P3);
+      HIPCHK(hipMemcpyAsync(stage, hin + k * P3, 16ull * m, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemsetAsync(hist, 0, 4ull * nb, s));
+      launch_cells(stage, (uint32_t)m, dcube, b, dcell, hist, s);
+      HIPCHK(hipMemcpyAsync(pst[k].data(), hist, 4ull * nb, hipMemcpyDeviceToHost, s));
+      launch_sort_by_cell(stage, dcell, (uint32_t)m, (uint32_t)(k * P3), hist, nb, tiles, cursor, dsorted, dsids, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(sp + k * P3, dsorted, 16ull * m, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(sid + k * P3, dsids, 4ull * m, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (uint64_t k = 0; k < npieces3; ++k) {
+      uint32_t run = 0;
+      for (uint32_t c = 0; c <= nb; ++c) {
+        const uint32_t v = c < nb ? pst[k][c] : 0u;
+        pst[k][c] = run;
+        run += v;
+      }
+    }
+  }
+  d_sorted.release();
+  d_sids.release();
+  // the points of level-b cells [c0, c1): one run per piece
+  auto for_runs = [&](uint64_t c0, uint64_t c1, auto&& f) {
+    uint64_t o = 0;
+    for (uint64_t k = 0; k < npieces3; ++k) {
+      const uint64_t beg = k * P3 + pst[k][c0], len = pst[k][c1] - pst[k][c0];
+      if (len) f(beg, len, o);
+      o += len;
+    }
+  };
 
   // 4. nodes of levels 0..b
   std::vector<MNode> nodes;
@@ -261,7 +259,8 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
         if (m.leaf) {
           // a top leaf: its level-b cells are contiguous in the sorted points
           m.src = 0;
-          m.hbeg = cstart[key << (3 * (b - L))];
+          m.c0 = key << (3 * (b - L));
+          m.c1 = (key + 1) << (3 * (b - L));
           m.count = (uint32_t)m.npoints;
           nodes.push_back(m);
         } else if (L == b) {
@@ -296,10 +295,12 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     uint32_t* bid = d_ids.get<uint32_t>(pts);
     std::vector<uint64_t> offs(r1 - r0 + 1, 0);
     for (size_t r = r0; r < r1; ++r) {
-      const uint64_t c = roots[r], beg = cstart[c], m = cstart[c + 1] - beg, o = offs[r - r0];
-      HIPCHK(hipMemcpyAsync(bp + o, sp + beg, 16ull * m, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(bid + o, sid + beg, 4ull * m, hipMemcpyHostToDevice, s));
-      offs[r - r0 + 1] = o + m;
+      const uint64_t c = roots[r], o = offs[r - r0];
+      for_runs(c, c + 1, [&](uint64_t beg, uint64_t len, uint64_t at) {
+        HIPCHK(hipMemcpyAsync(bp + o + at, sp + beg, 16ull * len, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(bid + o + at, sid + beg, 4ull * len, hipMemcpyHostToDevice, s));
+      });
+      offs[r - r0 + 1] = o + cnt[b][c];
     }
     BuildExtras x;
     x.cube = hc;
@@ -390,8 +391,10 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   for (const MNode& m : nodes) {
     if (!m.leaf || !m.count) continue;
     if (m.src == 0) {
-      HIPCHK(hipMemcpyAsync(Y + m.off, sp + m.hbeg, 16ull * m.count, hipMemcpyHostToDevice, s));
-      if (Yid) HIPCHK(hipMemcpyAsync(Yid + m.off, sid + m.hbeg, 4ull * m.count, hipMemcpyHostToDevice, s));
+      for_runs(m.c0, m.c1, [&](uint64_t beg, uint64_t len, uint64_t at) {
+        HIPCHK(hipMemcpyAsync(Y + m.off + at, sp + beg, 16ull * len, hipMemcpyHostToDevice, s));
+        if (Yid) HIPCHK(hipMemcpyAsync(Yid + m.off + at, sid + beg, 4ull * len, hipMemcpyHostToDevice, s));
+      });
     } else {
       const lod_tree_view& v = rtrees[m.tree]->v;
       prun.push_back(CopyRun{v.points + m.soff, m.off, m.count});

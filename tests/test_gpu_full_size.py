@@ -70,3 +70,44 @@ def test_aerial_20m_weighted_and_full_precision():
     assert np.array_equal(f["voxel_points"], raw[f["voxel_ids"].astype(np.int64)])
     fullsize.log("weighted cells equal the average's; full-precision records are input records")
     fullsize.check_build(g, pts, T, ML, subtree_picks=2, leaf_sample=2000, sampling=3)
+
+
+def test_aerial_100m_chunked_equals_in_core():
+    """The 100M-point aerial cloud built from host memory in chunks of 10M
+    points (bench.py's chunked run) equals the in-core build: the same node
+    table, voxel array and leaf point sets; and passes the same checks."""
+    import numpy as np
+    import torch
+
+    import paper_2302_14801_amd as lod
+
+    fullsize.log("generating")
+    host = torch.empty(N * 16, dtype=torch.uint8, pin_memory=True)
+    pts = host.numpy().view(synth.POINT_DTYPE)
+    synth.aerial(N, seed=2, out=pts)
+    params = lod.make_params(leaf_cap=T, max_level=ML, keep_ids=True)
+    fullsize.log("chunked build")
+    t = lod.lod_build_chunked(pts, 10_000_000, params=params)
+    g = t.to_host()
+    t.free()
+    fullsize.log("in-core build")
+    dev = host.to("cuda:0")
+    t = lod.lod_build(dev, params=params)
+    d = t.to_host()
+    t.free()
+    del dev
+    fullsize.log(f"{g['num_nodes']} nodes, {g['num_voxels']} voxels; comparing")
+    for f in ("level", "key", "is_leaf", "npoints", "child_mask", "first_child", "count", "offset"):
+        assert np.array_equal(g[f], d[f]), f
+    assert np.array_equal(g["voxels"], d["voxels"])
+    # leaf point sets: ids sorted inside the (identical) leaf ranges
+    leaf = np.nonzero(g["is_leaf"])[0]
+    order = np.argsort(g["offset"][leaf], kind="stable")
+    owner = np.repeat(np.arange(len(leaf), dtype=np.uint64)[order], g["count"][leaf][order].astype(np.int64))
+    for name in ("point_ids",):
+        ka = np.sort((owner << np.uint64(32)) | g[name].astype(np.uint64))
+        kb = np.sort((owner << np.uint64(32)) | d[name].astype(np.uint64))
+        assert np.array_equal(ka, kb)
+    raw = np.ascontiguousarray(pts).view(np.uint8).reshape(-1, 16)
+    assert np.array_equal(g["points"], raw[g["point_ids"]])
+    fullsize.check_build(g, pts, T, ML)
