@@ -13,10 +13,16 @@
 //     point) adds to its cell: R, G, B sums and a count, or the best pick
 //     order; a second pass lets the winning sample write its colour and id;
 //   * each grid's occupied cells are emitted in Morton order, so a parent's
-//     voxel list is its jobs' outputs in octant order.
+//     voxel list is its jobs' outputs in octant order;
+//   * the weighted average (Sec. 4.2.4) counts samples per cell the same way
+//     (its occupied cells are the average's), then every sample splats onto
+//     the up to 2x2x2 cells around it in its parent's grid -- also across
+//     octants, so a parent's eight jobs share a launch -- with the exact
+//     integer weights of the in-core weighted pass.
 #include "common.h"
 #include "launch.h"
 #include "scan.h"
+#include "weighted.h"
 
 namespace lod {
 
@@ -196,7 +202,7 @@ __global__ void __launch_bounds__(256) k_top_clear(TopCell* g, uint64_t ncells, 
   for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < ncells; i += (uint64_t)gridDim.x * 256) {
     TopCell c;
     c.a = a0;
-    c.b = c.c = 0;
+    c.b = c.c = c.w = 0;
     c.n = c.pad = 0;
     g[i] = c;
   }
@@ -220,7 +226,8 @@ __device__ __forceinline__ void top_sample(const TopJob& j, uint32_t i, const Cu
   }
 }
 
-// MODE: 0 average, 1 first, 2 random.  Grid (x: slices of the samples, y: job).
+// MODE: 0 average, 1 first, 2 random, 3 count only (the weighted mode's
+// occupancy).  Grid (x: slices of the samples, y: job).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_top_splat(const TopJob* __restrict__ jobs, const Cube* cube, uint32_t seed,
                                                    TopCell* grids) {
@@ -232,6 +239,7 @@ __global__ void __launch_bounds__(256) k_top_splat(const TopJob* __restrict__ jo
     top_sample(j, i, cd, m, rgba);
     TopCell* c = g + m;
     atomicAdd(&c->n, 1u);
+    if (MODE == 3) continue;
     if (MODE == 0) {
       atomicAdd(&c->a, (unsigned long long)(rgba & 0xffu));
       atomicAdd(&c->b, (unsigned long long)((rgba >> 8) & 0xffu));
@@ -257,6 +265,47 @@ __global__ void __launch_bounds__(256) k_top_pick(const TopJob* __restrict__ job
     top_sample(j, i, cd, m, rgba);
     const uint32_t id = j.ids[i];
     if (pick_order(id, seed, MODE == 2) == g[m].a) g[m].b = (unsigned long long)rgba | ((unsigned long long)id << 32);
+  }
+}
+
+// Weighted mode: every sample's splats onto the occupied cells of its parent's
+// grid, in whichever octant's job they fall.
+__global__ void __launch_bounds__(256) k_top_wsplat(const TopJob* __restrict__ jobs, const Cube* cube,
+                                                    TopCell* grids) {
+  const TopJob j = jobs[blockIdx.y];
+  const CubeD cd = load_cube(cube);
+  const uint32_t L = j.level;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < j.count; i += gridDim.x * 256) {
+    uint64_t pos2[3];
+    uint32_t rgba;
+    if (j.kind == 0) {
+      // a child voxel at the centre of its cell (level L + 8)
+      const uint64_t v = ((const uint64_t*)j.src)[i];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const uint64_t jj = ((uint64_t)j.C[a] << 7) + ((v >> (8 * a)) & 0xffu);
+        pos2[a] = (2 * jj + 1) << (13 - L);
+      }
+      rgba = (uint32_t)(v >> 32);
+    } else {
+      // a point at the centre of its 2^21-grid cell
+      const uint4 v = ((const uint4*)j.src)[i];
+      pos2[0] = 2ull * quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) + 1;
+      pos2[1] = 2ull * quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) + 1;
+      pos2[2] = 2ull * quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) + 1;
+      rgba = v.w;
+    }
+    const uint64_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
+    wtargets(L, j.G, pos2, [&](uint32_t code, uint64_t w) {
+      const int32_t jb = j.sib[code >> 18];
+      if (jb < 0) return;  // no child there: no occupied cell
+      TopCell* c = grids + (uint64_t)jb * kTopCells + (code & (kTopCells - 1));
+      if (c->n == 0u) return;  // not an occupied cell
+      atomicAdd(&c->a, (unsigned long long)(w * R));
+      atomicAdd(&c->b, (unsigned long long)(w * Gc));
+      atomicAdd(&c->c, (unsigned long long)(w * B));
+      atomicAdd(&c->w, (unsigned long long)w);
+    });
   }
 }
 
@@ -291,6 +340,10 @@ __global__ void __launch_bounds__(256) k_top_emit(const TopJob* __restrict__ job
       uint32_t rgba, id = 0;
       if (MODE == 0) {
         rgba = (uint32_t)(c.a / c.n) | ((uint32_t)(c.b / c.n) << 8) | ((uint32_t)(c.c / c.n) << 16) | (255u << 24);
+      } else if (MODE == 3) {
+        // a cell's own sample weighs more than 0.13, so c.w > 0
+        const unsigned long long w = c.w ? c.w : 1ull;
+        rgba = (uint32_t)(c.a / w) | ((uint32_t)(c.b / w) << 8) | ((uint32_t)(c.c / w) << 16) | (255u << 24);
       } else {
         rgba = (uint32_t)c.b;
         id = (uint32_t)(c.b >> 32);
@@ -319,9 +372,13 @@ void launch_top_splat(const TopJob* jobs, uint32_t njobs, uint32_t max_count, co
       hipLaunchKernelGGL(k_top_splat<1>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
       hipLaunchKernelGGL(k_top_pick<1>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
       break;
-    default:
+    case 2:
       hipLaunchKernelGGL(k_top_splat<2>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
       hipLaunchKernelGGL(k_top_pick<2>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      break;
+    default:
+      hipLaunchKernelGGL(k_top_splat<3>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      hipLaunchKernelGGL(k_top_wsplat, grid, dim3(256), 0, s, jobs, cube, grids);
       break;
   }
 }
@@ -336,6 +393,8 @@ void launch_top_emit(const TopJob* jobs, uint32_t njobs, const TopCell* grids, c
   if (!njobs) return;
   if (mode == 0)
     hipLaunchKernelGGL(k_top_emit<0>, dim3(kTopSlices, njobs), dim3(256), 0, s, jobs, grids, slice_off, vox, vid);
+  else if (mode == 3)
+    hipLaunchKernelGGL(k_top_emit<3>, dim3(kTopSlices, njobs), dim3(256), 0, s, jobs, grids, slice_off, vox, vid);
   else
     hipLaunchKernelGGL(k_top_emit<1>, dim3(kTopSlices, njobs), dim3(256), 0, s, jobs, grids, slice_off, vox, vid);
 }

@@ -36,22 +36,11 @@
 #include "common.h"
 #include "launch.h"
 #include "scan.h"
+#include "weighted.h"
 
 namespace lod {
 
 constexpr int kWSplit = 16;  // workgroups per node in the bitmap and colour passes
-constexpr uint32_t kWeightOne = 65536;
-
-// floor(sqrt(x)) for x < 2^40: the single-precision square root of x
-// (rounded to 24 bits) is within 2^-4 of sqrt(x) there, so its truncation is
-// within one of the answer; the integer checks settle the last step.
-__device__ __forceinline__ uint64_t isqrt_u64(uint64_t x) {
-  uint64_t r = (uint64_t)__fsqrt_rn((float)x);
-  for (int i = 0; i < 2 && r * r > x; ++i) --r;
-  for (int i = 0; i < 2 && (r + 1) * (r + 1) <= x; ++i) ++r;
-  return r;
-}
-
 constexpr uint32_t kWWords = 1u << 15;  // 64-bit words of a node's 2^21-cell bitmap
 
 // The kernels of one level run over that level's nodes only: `ln` lists the
@@ -120,46 +109,6 @@ __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi
   atomicAdd(a4 + 1, (unsigned long long)(w * Gc));
   atomicAdd(a4 + 2, (unsigned long long)(w * B));
   atomicAdd(a4 + 3, (unsigned long long)w);
-}
-
-// Calls f(code, w) for every cell of node A's grid (level L, origin G = A's
-// coordinates * 128 per axis) that a sample at pos2 reaches with weight w > 0:
-// the cell containing it and, per axis, the neighbour on the side of its
-// offset (the 2x2x2 cells whose centres surround it), inside A only.
-template <class F>
-__device__ __forceinline__ void wtargets(uint32_t L, const uint32_t G[3], const uint64_t pos2[3], F&& f) {
-  const uint32_t cs = 15 - L;  // log2 of A's cell size in pos2 units
-  int64_t cand[3][2];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int64_t k = (int64_t)(pos2[a] >> cs);
-    const int64_t fo = (int64_t)pos2[a] - (k << cs);
-    cand[a][0] = k;
-    cand[a][1] = fo < ((int64_t)1 << (cs - 1)) ? k - 1 : k + 1;
-  }
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    int64_t c[3];
-    uint32_t loc[3];
-    bool inside = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      c[a] = cand[a][(m >> a) & 1];
-      const int64_t l = c[a] - ((int64_t)G[a] << 7);
-      inside &= l >= 0 && l <= 127;
-      loc[a] = (uint32_t)l;
-    }
-    if (!inside) continue;
-    uint64_t d2 = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int64_t d = (int64_t)pos2[a] - ((2 * c[a] + 1) << (cs - 1));
-      d2 += (uint64_t)(d * d);
-    }
-    const uint64_t r = isqrt_u64(d2 << (2 * L + 2));  // floor(65536 * distance)
-    if (r >= kWeightOne) continue;
-    f(morton7(loc[0], loc[1], loc[2]), kWeightOne - r);
-  }
 }
 
 // The samples of the children at level L + 1 (points of leaves, voxels of

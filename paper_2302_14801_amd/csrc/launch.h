@@ -105,7 +105,9 @@ void launch_sort_by_cell(const void* pts, const uint32_t* cell, uint32_t n, uint
 // A job of the levels above the chunk roots: one child (octant `oct`) of a
 // node at `level`, whose samples are `count` voxels (kind 0, 8-byte words of
 // the child's grid) or points (kind 1, 16-byte records) at `src`, with ids
-// (pick modes) at `ids`.
+// (pick modes) at `ids`.  Weighted mode: the parent's and the child's cell
+// coordinates (G, C: key bits per axis) and the jobs of the parent's eight
+// octants in the same launch (sib, -1 where the octant has no child).
 struct TopJob {
   const void* src;
   const uint32_t* ids;
@@ -113,17 +115,20 @@ struct TopJob {
   uint32_t kind;
   uint32_t oct;
   uint32_t level;
+  uint32_t G[3], C[3];
+  int32_t sib[8];
 };
-// A cell of a job's dense grid: R, G, B sums and a sample count (average),
-// or the best pick order (a) and the winner's colour | id << 32 (b).
+// A cell of a job's dense grid: the sample count n; R, G, B sums (average),
+// or the best pick order (a) and the winner's colour | id << 32 (b), or the
+// weighted sums of w * R, w * G, w * B and w (a, b, c, w).
 struct TopCell {
-  unsigned long long a, b, c;
+  unsigned long long a, b, c, w;
   uint32_t n, pad;
 };
 constexpr uint32_t kTopCells = 1u << 18;  // 64^3 parent cells under one child octant
 constexpr uint32_t kTopSlice = 4096;      // cells per workgroup of the count and emit passes
 constexpr uint32_t kTopSlices = kTopCells / kTopSlice;
-// mode: 0 average, 1 first, 2 random.
+// mode: 0 average, 1 first, 2 random, 3 weighted.
 void launch_top_clear(TopCell* grids, uint32_t njobs, uint32_t mode, hipStream_t s);
 void launch_top_splat(const TopJob* jobs, uint32_t njobs, uint32_t max_count, const Cube* cube, uint32_t mode,
                       uint32_t seed, TopCell* grids, hipStream_t s);

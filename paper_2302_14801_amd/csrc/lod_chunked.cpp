@@ -120,8 +120,9 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   const uint32_t T = prm.leaf_cap;
-  const uint32_t mode = prm.sampling;  // 0 average, 1 first, 2 random
-  const bool ids = mode != LOD_AVERAGE || (prm.flags & LOD_FLAG_POINT_IDS);
+  const uint32_t mode = prm.sampling;  // 0 average, 1 first, 2 random, 3 weighted
+  const bool pick = mode == LOD_PICK_FIRST || mode == LOD_PICK_RANDOM;
+  const bool ids = pick || (prm.flags & LOD_FLAG_POINT_IDS);
 
   DevBuf d_stage(dev), d_ids(dev), d_cell(dev), d_hist(dev), d_small(dev), d_grids(dev), d_jobs(dev), d_cnt(dev),
       d_soff(dev), d_runs(dev), d_sorted(dev), d_sids(dev), d_cursor(dev), d_tiles(dev);
@@ -423,21 +424,27 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
                                });
     return *it;
   };
-  const uint32_t kMaxJobs = 64;  // 64 dense grids of 8 MB
+  const uint32_t kMaxJobs = 64;  // 64 dense grids of 10 MB
   TopCell* grids = d_grids.get<TopCell>((size_t)kMaxJobs * kTopCells);
   for (int L = (int)b - 1; L >= 0; --L) {
     std::vector<TopJob> jobs;
     std::vector<uint32_t> owner;  // node index of each job's parent
+    std::vector<size_t> first;    // a parent's first job (launches never split a parent)
     uint64_t bound = 0;
     for (uint32_t i = 0; i < num_nodes; ++i) {
       const MNode& a = nodes[i];
       if (a.level != (uint32_t)L || a.leaf) continue;
+      first.push_back(jobs.size());
       for (uint32_t o = 0; o < 8; ++o) {
         if (!(a.mask >> o & 1u)) continue;
         const MNode& c = find(L + 1, (a.key << 3) | o);
         TopJob j{};
         j.oct = o;
         j.level = (uint32_t)L;
+        for (int x = 0; x < 3; ++x) {
+          j.G[x] = compact21(a.key >> x);
+          j.C[x] = compact21(c.key >> x);
+        }
         if (c.leaf) {
           j.kind = 1;
           j.src = Y + c.off;
@@ -452,7 +459,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
         } else {
           j.kind = 0;
           j.src = (const uint64_t*)lvox[L + 1]->p + c.soff;
-          j.ids = mode ? (const uint32_t*)lvid[L + 1]->p + c.soff : nullptr;
+          j.ids = pick ? (const uint32_t*)lvid[L + 1]->p + c.soff : nullptr;
           j.count = c.count;
         }
         bound += std::min<uint64_t>(kTopCells, j.count);
@@ -463,10 +470,19 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     lvox[L].reset(new DevBuf(dev));
     lvid[L].reset(new DevBuf(dev));
     uint64_t* vox = lvox[L]->get<uint64_t>(bound);
-    uint32_t* vid = mode ? lvid[L]->get<uint32_t>(bound) : nullptr;
+    uint32_t* vid = pick ? lvid[L]->get<uint32_t>(bound) : nullptr;
+    first.push_back(jobs.size());
     uint64_t pos = 0;
-    for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
-      const uint32_t nj = (uint32_t)std::min<size_t>(kMaxJobs, jobs.size() - j0);
+    for (size_t f = 0, j0 = 0; j0 < jobs.size(); j0 = first[f]) {
+      // whole parents, at most kMaxJobs jobs (a parent has at most 8)
+      while (f + 1 < first.size() && first[f + 1] - j0 <= kMaxJobs) ++f;
+      const uint32_t nj = (uint32_t)(first[f] - j0);
+      // the jobs of each parent's octants in this launch
+      for (size_t q = j0; q < j0 + nj; ++q) {
+        for (int o = 0; o < 8; ++o) jobs[q].sib[o] = -1;
+        for (size_t r = j0; r < j0 + nj; ++r)
+          if (owner[r] == owner[q]) jobs[q].sib[jobs[r].oct] = (int32_t)(r - j0);
+      }
       uint32_t maxc = 0;
       for (uint32_t k = 0; k < nj; ++k) maxc = std::max(maxc, jobs[j0 + k].count);
       TopJob* dj = d_jobs.get<TopJob>(nj);
@@ -508,7 +524,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       vtotal += m.count;
     }
   uint64_t* vox = arena->alloc<uint64_t>(std::max<uint64_t>(vtotal, 1));
-  uint32_t* vids = mode ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
+  uint32_t* vids = pick ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
   std::vector<CopyRun> vrun, vidrun;
   for (const MNode& m : nodes) {
     if (m.leaf || !m.count) continue;
@@ -595,9 +611,9 @@ extern "C" lod_status lod_build_chunked(const lod_point* h_points, uint64_t n, c
     return LOD_ERR_INVALID;
   }
   *out = nullptr;
-  if (!p || p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 2 || p->tune_levels0 > 4 ||
+  if (!p || p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 3 || p->tune_levels0 > 4 ||
       p->tune_levels1 > 4 || (p->flags & LOD_FLAG_FULL_PRECISION)) {
-    lod_set_error("invalid parameters (the chunked build takes the average and pick modes, without full precision)");
+    lod_set_error("invalid parameters (the chunked build takes no full-precision records)");
     return LOD_ERR_INVALID;
   }
   if (n >= 0xffffffffull || (n && !h_points) || chunk_points == 0) {

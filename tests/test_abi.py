@@ -65,7 +65,7 @@ def test_chunked_argument_errors_before_any_device_work(lib):
     assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, None) == binding.LOD_ERR_INVALID
     assert lib.lod_build_chunked(None, 10, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
     assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 0, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
-    p.sampling = binding.LOD_WEIGHTED
+    p.sampling = 4
     assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
     p.sampling, p.flags = binding.LOD_AVERAGE, binding.LOD_FLAG_FULL_PRECISION
     assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID

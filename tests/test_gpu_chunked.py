@@ -1,7 +1,8 @@
 """GPU parity of the chunked (out-of-core) build: the tree of a host cloud,
 built through cells of one level of the common cube and merged above them,
 equals the oracle's in-core tree of the whole cloud, and has the layout of
-the in-core GPU build (same node table, same voxel array, same leaf ranges)."""
+the in-core GPU build (same node table, same voxel array, same leaf ranges),
+in all four sampling modes."""
 from __future__ import annotations
 
 import numpy as np
@@ -54,19 +55,19 @@ def check_chunked(lod, points, chunk, T, ml=12, sampling=0, seed=0, keep_ids=Fal
     return g
 
 
-@pytest.mark.parametrize("sampling", [0, 1, 2])
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
 def test_uniform(lod, sampling):
     p = synth.uniform_cloud(200_000, 31, lo=(-3, 10, 100), hi=(5, 12, 101))
     check_chunked(lod, p, 20_000, T=500, sampling=sampling, seed=5)
 
 
-@pytest.mark.parametrize("sampling", [0, 1, 2])
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
 def test_terrain(lod, sampling):
     p = synth.terrain(300_000, seed=6)
     check_chunked(lod, p, 50_000, T=2000, sampling=sampling, seed=9)
 
 
-@pytest.mark.parametrize("sampling", [0, 1])
+@pytest.mark.parametrize("sampling", [0, 1, 3])
 def test_aerial(lod, sampling):
     p = synth.aerial(400_000, seed=2)
     check_chunked(lod, p, 60_000, T=5000, sampling=sampling)
@@ -77,7 +78,7 @@ def test_scan_with_ids(lod):
     check_chunked(lod, p, 40_000, T=2000, ml=14, keep_ids=True)
 
 
-@pytest.mark.parametrize("sampling", [0, 2])
+@pytest.mark.parametrize("sampling", [0, 2, 3])
 def test_dense_blob_and_sparse_leaves(lod, sampling):
     """Small leaves above the split level next to chunk roots: a dense blob and
     a few hundred points spread over the cube."""
@@ -95,9 +96,10 @@ def test_chunk_of_one_point(lod):
     check_chunked(lod, p, 1, T=300, sampling=1)
 
 
-def test_everything_above_the_split(lod):
+@pytest.mark.parametrize("sampling", [0, 3])
+def test_everything_above_the_split(lod, sampling):
     p = synth.uniform_cloud(20_000, 45)
-    check_chunked(lod, p, 1, T=300)
+    check_chunked(lod, p, 1, T=300, sampling=sampling)
 
 
 def test_identical_points_to_the_depth_limit(lod):
@@ -107,9 +109,10 @@ def test_identical_points_to_the_depth_limit(lod):
 
 
 @pytest.mark.parametrize("ml", [1, 2, 3])
-def test_shallow_depth_limits(lod, ml):
+@pytest.mark.parametrize("sampling", [1, 3])
+def test_shallow_depth_limits(lod, ml, sampling):
     p = synth.terrain(50_000, seed=7)
-    check_chunked(lod, p, 4_000, T=500, ml=ml, sampling=1)
+    check_chunked(lod, p, 4_000, T=500, ml=ml, sampling=sampling)
 
 
 def test_one_chunk_is_the_in_core_build(lod):
@@ -128,6 +131,7 @@ def test_errors(lod):
     with pytest.raises(lod.LodError) as e:
         lod.lod_build_chunked(p, 100)
     assert e.value.status == -2
+    p = lod.make_params(full_precision=True)
     with pytest.raises(lod.LodError) as e:
-        lod.lod_build_chunked(synth.uniform_cloud(1_000, 48), 100, sampling=3)
+        lod.lod_build_chunked(synth.uniform_cloud(1_000, 48), 100, params=p)
     assert e.value.status == -1
