@@ -180,8 +180,9 @@ lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets,
  * plus the chunk results and the output tree (about twice the output).  Host
  * memory: 20 B per point (pinned) for the pieces sorted by cell on the GPU.
  * With n <= chunk_points, or max_level < 2, this is
- * the in-core build of a device copy.  Every sampling mode;
- * LOD_FLAG_FULL_PRECISION gives LOD_ERR_INVALID.  Errors: LOD_ERR_INVALID
+ * the in-core build of a device copy.  Every sampling mode and flag; with
+ * LOD_FLAG_FULL_PRECISION the accepted samples' records are gathered from
+ * h_points by index at the end.  Errors: LOD_ERR_INVALID
  * (NULL out/params, n >= 2^32,
  * chunk_points 0, bad params), LOD_ERR_NONFINITE, LOD_ERR_OOM, LOD_ERR_HIP. */
 lod_status lod_build_chunked(const lod_point* h_points, uint64_t n, const lod_params* p, uint64_t chunk_points,

@@ -144,11 +144,13 @@ struct lod_tree {
 // until complete; throws LodError.  One tree per cloud, in order.
 // Options of the chunked build: one bounding cube for every cloud (a host
 // pointer to a lod::Cube, instead of each cloud's own cube; every point must
-// lie in it), and the input index of every point (a device array parallel to
-// d_points, instead of the index within its cloud).
+// lie in it), the input index of every point (a device array parallel to
+// d_points, instead of the index within its cloud), and, with full precision,
+// the accepted samples' ids without their records (the caller gathers them).
 struct BuildExtras {
   const void* cube = nullptr;
   const uint32_t* d_ids = nullptr;
+  bool ids_only = false;
 };
 std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_t* offs, uint32_t nclouds,
                                         const lod_params& p, hipStream_t stream, const BuildExtras* x = nullptr);

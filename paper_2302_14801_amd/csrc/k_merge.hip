@@ -203,7 +203,8 @@ __global__ void __launch_bounds__(256) k_top_clear(TopCell* g, uint64_t ncells, 
     TopCell c;
     c.a = a0;
     c.b = c.c = c.w = 0;
-    c.n = c.pad = 0;
+    c.n = 0;
+    c.mid = 0xffffffffu;
     g[i] = c;
   }
 }
@@ -230,7 +231,7 @@ __device__ __forceinline__ void top_sample(const TopJob& j, uint32_t i, const Cu
 // occupancy).  Grid (x: slices of the samples, y: job).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_top_splat(const TopJob* __restrict__ jobs, const Cube* cube, uint32_t seed,
-                                                   TopCell* grids) {
+                                                   bool full, TopCell* grids) {
   const TopJob j = jobs[blockIdx.y];
   TopCell* g = grids + (uint64_t)blockIdx.y * kTopCells;
   const CubeD cd = load_cube(cube);
@@ -239,6 +240,8 @@ __global__ void __launch_bounds__(256) k_top_splat(const TopJob* __restrict__ jo
     top_sample(j, i, cd, m, rgba);
     TopCell* c = g + m;
     atomicAdd(&c->n, 1u);
+    // full precision in the average modes: the cell's smallest input index
+    if ((MODE == 0 || MODE == 3) && full) atomicMin(&c->mid, j.ids[i]);
     if (MODE == 3) continue;
     if (MODE == 0) {
       atomicAdd(&c->a, (unsigned long long)(rgba & 0xffu));
@@ -340,10 +343,12 @@ __global__ void __launch_bounds__(256) k_top_emit(const TopJob* __restrict__ job
       uint32_t rgba, id = 0;
       if (MODE == 0) {
         rgba = (uint32_t)(c.a / c.n) | ((uint32_t)(c.b / c.n) << 8) | ((uint32_t)(c.c / c.n) << 16) | (255u << 24);
+        id = c.mid;
       } else if (MODE == 3) {
         // a cell's own sample weighs more than 0.13, so c.w > 0
         const unsigned long long w = c.w ? c.w : 1ull;
         rgba = (uint32_t)(c.a / w) | ((uint32_t)(c.b / w) << 8) | ((uint32_t)(c.c / w) << 16) | (255u << 24);
+        id = c.mid;
       } else {
         rgba = (uint32_t)c.b;
         id = (uint32_t)(c.b >> 32);
@@ -361,23 +366,23 @@ void launch_top_clear(TopCell* grids, uint32_t njobs, uint32_t mode, hipStream_t
 }
 
 void launch_top_splat(const TopJob* jobs, uint32_t njobs, uint32_t max_count, const Cube* cube, uint32_t mode,
-                      uint32_t seed, TopCell* grids, hipStream_t s) {
+                      uint32_t seed, bool full, TopCell* grids, hipStream_t s) {
   if (!njobs || !max_count) return;
   const dim3 grid(std::min<uint32_t>((max_count + 255) / 256, 512), njobs);
   switch (mode) {
     case 0:
-      hipLaunchKernelGGL(k_top_splat<0>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      hipLaunchKernelGGL(k_top_splat<0>, grid, dim3(256), 0, s, jobs, cube, seed, full, grids);
       break;
     case 1:
-      hipLaunchKernelGGL(k_top_splat<1>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      hipLaunchKernelGGL(k_top_splat<1>, grid, dim3(256), 0, s, jobs, cube, seed, full, grids);
       hipLaunchKernelGGL(k_top_pick<1>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
       break;
     case 2:
-      hipLaunchKernelGGL(k_top_splat<2>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      hipLaunchKernelGGL(k_top_splat<2>, grid, dim3(256), 0, s, jobs, cube, seed, full, grids);
       hipLaunchKernelGGL(k_top_pick<2>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
       break;
     default:
-      hipLaunchKernelGGL(k_top_splat<3>, grid, dim3(256), 0, s, jobs, cube, seed, grids);
+      hipLaunchKernelGGL(k_top_splat<3>, grid, dim3(256), 0, s, jobs, cube, seed, full, grids);
       hipLaunchKernelGGL(k_top_wsplat, grid, dim3(256), 0, s, jobs, cube, grids);
       break;
   }
@@ -400,6 +405,22 @@ void launch_top_emit(const TopJob* jobs, uint32_t njobs, const TopCell* grids, c
 }
 
 // ------------------------------------------------------------ copies
+
+// Full-precision records: the accepted samples' input records (gathered by
+// id) with the voxels' colours.
+__global__ void __launch_bounds__(256) k_voxel_records(const uint4* __restrict__ rec, const uint64_t* __restrict__ vox,
+                                                       uint64_t n, uint4* __restrict__ out) {
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint4 r = rec[i];
+    out[i] = make_uint4(r.x, r.y, r.z, (uint32_t)(vox[i] >> 32));
+  }
+}
+
+void launch_voxel_records(const void* rec, const uint64_t* vox, uint64_t n, void* out, hipStream_t s) {
+  if (!n) return;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_voxel_records, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint4*)rec, vox, n, (uint4*)out);
+}
 
 // Run r copies runs[r].len elements from the device address runs[r].src to
 // dst + runs[r].dst.

@@ -120,21 +120,24 @@ struct TopJob {
 };
 // A cell of a job's dense grid: the sample count n; R, G, B sums (average),
 // or the best pick order (a) and the winner's colour | id << 32 (b), or the
-// weighted sums of w * R, w * G, w * B and w (a, b, c, w).
+// weighted sums of w * R, w * G, w * B and w (a, b, c, w); the smallest
+// sample id (full precision in the average modes).
 struct TopCell {
   unsigned long long a, b, c, w;
-  uint32_t n, pad;
+  uint32_t n, mid;
 };
 constexpr uint32_t kTopCells = 1u << 18;  // 64^3 parent cells under one child octant
 constexpr uint32_t kTopSlice = 4096;      // cells per workgroup of the count and emit passes
 constexpr uint32_t kTopSlices = kTopCells / kTopSlice;
 // mode: 0 average, 1 first, 2 random, 3 weighted.
 void launch_top_clear(TopCell* grids, uint32_t njobs, uint32_t mode, hipStream_t s);
+// full: keep the smallest sample id per cell (average modes; ids required).
 void launch_top_splat(const TopJob* jobs, uint32_t njobs, uint32_t max_count, const Cube* cube, uint32_t mode,
-                      uint32_t seed, TopCell* grids, hipStream_t s);
+                      uint32_t seed, bool full, TopCell* grids, hipStream_t s);
 // Occupied cells per slice: njobs * kTopSlices counters.
 void launch_top_count(const TopCell* grids, uint32_t njobs, uint32_t* slice_cnt, hipStream_t s);
-// Voxels of the occupied cells in Morton order from slice_off (one u64 per slice).
+// Voxels of the occupied cells in Morton order from slice_off (one u64 per
+// slice), and their ids (the pick winner's, or the smallest) if vid is set.
 void launch_top_emit(const TopJob* jobs, uint32_t njobs, const TopCell* grids, const uint64_t* slice_off,
                      uint32_t mode, uint64_t* vox, uint32_t* vid, hipStream_t s);
 // Copies of runs of 16-, 8- or 4-byte elements into one array.
@@ -144,5 +147,7 @@ struct CopyRun {
   uint64_t len;  // elements
 };
 void launch_copy_runs(const CopyRun* runs, uint32_t nruns, uint32_t elem_bytes, void* dst, hipStream_t s);
+// out[i] = {rec[i].x, .y, .z, colour of vox[i]} (16-byte records).
+void launch_voxel_records(const void* rec, const uint64_t* vox, uint64_t n, void* out, hipStream_t s);
 
 }  // namespace lod

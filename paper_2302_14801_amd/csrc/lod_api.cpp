@@ -642,7 +642,7 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     launch_weighted(nd, wlist, loff, deepest, tinfo, cube, desc, Y, vox, wslot, wbits, wpre, wseg, wacc, s);
   }
   lod_point* vpts = nullptr;
-  if (pl.full) {
+  if (pl.full && !(x && x->ids_only)) {
     vpts = arena->alloc<lod_point>(std::max<uint64_t>(vtotal, 1));
     launch_voxel_points(vox, vids, vtotal, tinfo, clouds, nc, in, vpts, s);
   }

@@ -23,8 +23,10 @@
 //   8. one tree: nodes in (level, key) order, leaf points in Morton order of
 //      the leaves, voxels in node order, as the in-core build lays them out.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <memory>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -122,11 +124,14 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   const uint32_t T = prm.leaf_cap;
   const uint32_t mode = prm.sampling;  // 0 average, 1 first, 2 random, 3 weighted
   const bool pick = mode == LOD_PICK_FIRST || mode == LOD_PICK_RANDOM;
-  const bool ids = pick || (prm.flags & LOD_FLAG_POINT_IDS);
+  const bool full = (prm.flags & LOD_FLAG_FULL_PRECISION) != 0;
+  const bool ids = pick || full || (prm.flags & LOD_FLAG_POINT_IDS);
+  const bool vids_out = pick || full;  // voxel ids: pick winners, or accepted samples
 
   DevBuf d_stage(dev), d_ids(dev), d_cell(dev), d_hist(dev), d_small(dev), d_grids(dev), d_jobs(dev), d_cnt(dev),
       d_soff(dev), d_runs(dev), d_sorted(dev), d_sids(dev), d_cursor(dev), d_tiles(dev);
-  HostBuf h_ci, h_cube, h_sorted, h_sids;
+  HostBuf h_ci, h_cube, h_sorted, h_sids, h_vid, h_rec;
+  DevBuf d_rec(dev);
   std::vector<std::unique_ptr<DevBuf>> lvox, lvid;  // voxels of the levels above b
   Drain drain{s};  // declared last: the stream drains before any buffer above is released
 
@@ -306,6 +311,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     BuildExtras x;
     x.cube = hc;
     x.d_ids = bid;
+    x.ids_only = true;  // full-precision records are gathered once for the whole tree
     std::vector<lod_tree*> t = lod_build_clouds(bp, offs.data(), (uint32_t)(r1 - r0), cp, s, &x);
     for (size_t r = r0; r < r1; ++r) rtrees[r].reset(t[r - r0]);
     // node tables of the new trees
@@ -459,7 +465,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
         } else {
           j.kind = 0;
           j.src = (const uint64_t*)lvox[L + 1]->p + c.soff;
-          j.ids = pick ? (const uint32_t*)lvid[L + 1]->p + c.soff : nullptr;
+          j.ids = vids_out ? (const uint32_t*)lvid[L + 1]->p + c.soff : nullptr;
           j.count = c.count;
         }
         bound += std::min<uint64_t>(kTopCells, j.count);
@@ -470,7 +476,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     lvox[L].reset(new DevBuf(dev));
     lvid[L].reset(new DevBuf(dev));
     uint64_t* vox = lvox[L]->get<uint64_t>(bound);
-    uint32_t* vid = pick ? lvid[L]->get<uint32_t>(bound) : nullptr;
+    uint32_t* vid = vids_out ? lvid[L]->get<uint32_t>(bound) : nullptr;
     first.push_back(jobs.size());
     uint64_t pos = 0;
     for (size_t f = 0, j0 = 0; j0 < jobs.size(); j0 = first[f]) {
@@ -490,7 +496,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       uint64_t* dsoff = d_soff.get<uint64_t>((size_t)nj * kTopSlices);
       HIPCHK(hipMemcpyAsync(dj, jobs.data() + j0, sizeof(TopJob) * nj, hipMemcpyHostToDevice, s));
       launch_top_clear(grids, nj, mode, s);
-      launch_top_splat(dj, nj, maxc, dcube, mode, prm.seed, grids, s);
+      launch_top_splat(dj, nj, maxc, dcube, mode, prm.seed, full, grids, s);
       launch_top_count(grids, nj, dcnt, s);
       HIPCHK(hipGetLastError());
       std::vector<uint32_t> hcnt((size_t)nj * kTopSlices);
@@ -524,7 +530,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       vtotal += m.count;
     }
   uint64_t* vox = arena->alloc<uint64_t>(std::max<uint64_t>(vtotal, 1));
-  uint32_t* vids = pick ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
+  uint32_t* vids = vids_out ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
   std::vector<CopyRun> vrun, vidrun;
   for (const MNode& m : nodes) {
     if (m.leaf || !m.count) continue;
@@ -539,6 +545,36 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   }
   run_copies(vrun, 8, vox);
   if (vids) run_copies(vidrun, 4, vids);
+
+  // full precision: the accepted samples' input records, gathered from the
+  // host cloud by id, with the voxels' colours
+  lod_point* vpts = nullptr;
+  if (full && vtotal) {
+    uint32_t* hv = h_vid.get<uint32_t>(vtotal);
+    lod_point* hr = h_rec.get<lod_point>(vtotal);
+    HIPCHK(hipMemcpyAsync(hv, vids, 4ull * vtotal, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const uint32_t nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    std::atomic<bool> bad{false};
+    for (uint32_t t = 0; t < nt; ++t)
+      th.emplace_back([&, t] {
+        for (uint64_t i = vtotal * t / nt; i < vtotal * (t + 1) / nt; ++i) {
+          if (hv[i] >= n) {
+            bad = true;
+            return;
+          }
+          hr[i] = hin[hv[i]];
+        }
+      });
+    for (auto& x : th) x.join();
+    if (bad) lod_fail(LOD_ERR_CAPACITY, "an accepted sample id lies outside the input");
+    lod_point* drec = d_rec.get<lod_point>(vtotal);
+    vpts = arena->alloc<lod_point>(vtotal);
+    HIPCHK(hipMemcpyAsync(drec, hr, 16ull * vtotal, hipMemcpyHostToDevice, s));
+    launch_voxel_records(drec, vox, vtotal, vpts, s);
+    HIPCHK(hipGetLastError());
+  }
 
   // 8c. node table
   uint8_t* o_level = arena->alloc<uint8_t>(num_nodes);
@@ -600,7 +636,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   v.point_ids = Yid;
   v.voxels = (const lod_voxel*)vox;
   v.voxel_ids = vids;
-  v.voxel_points = nullptr;
+  v.voxel_points = vpts;
   return t.release();
 }
 
@@ -612,8 +648,8 @@ extern "C" lod_status lod_build_chunked(const lod_point* h_points, uint64_t n, c
   }
   *out = nullptr;
   if (!p || p->leaf_cap == 0 || p->max_level > 14 || p->sampling > 3 || p->tune_levels0 > 4 ||
-      p->tune_levels1 > 4 || (p->flags & LOD_FLAG_FULL_PRECISION)) {
-    lod_set_error("invalid parameters (the chunked build takes no full-precision records)");
+      p->tune_levels1 > 4) {
+    lod_set_error("invalid parameters");
     return LOD_ERR_INVALID;
   }
   if (n >= 0xffffffffull || (n && !h_points) || chunk_points == 0) {

@@ -67,7 +67,7 @@ def test_chunked_argument_errors_before_any_device_work(lib):
     assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 0, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
     p.sampling = 4
     assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
-    p.sampling, p.flags = binding.LOD_AVERAGE, binding.LOD_FLAG_FULL_PRECISION
+    p.sampling, p.max_level = binding.LOD_AVERAGE, 15
     assert lib.lod_build_chunked(None, 0, ctypes.byref(p), 10, None, ctypes.byref(out)) == binding.LOD_ERR_INVALID
     assert out.value is None
 

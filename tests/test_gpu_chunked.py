@@ -29,24 +29,32 @@ def host_tree(t):
     return h
 
 
-def in_core(lod, points, **kw):
+def to_dev(points):
     import torch
     raw = np.ascontiguousarray(points).view(np.uint8).reshape(-1)
-    return host_tree(lod.lod_build(torch.from_numpy(raw.copy()).to("cuda:0"), **kw))
+    return torch.from_numpy(raw.copy()).to("cuda:0")
 
 
-def check_chunked(lod, points, chunk, T, ml=12, sampling=0, seed=0, keep_ids=False):
-    print(f"case n={len(points)} chunk={chunk} T={T} ml={ml} sampling={sampling}", flush=True)
+def check_chunked(lod, points, chunk, T, ml=12, sampling=0, seed=0, keep_ids=False, full=False):
+    print(f"case n={len(points)} chunk={chunk} T={T} ml={ml} sampling={sampling} full={full}", flush=True)
     kw = dict(leaf_cap=T, max_level=ml, sampling=sampling, seed=seed, keep_ids=keep_ids)
-    g = host_tree(lod.lod_build_chunked(np.ascontiguousarray(points), chunk, **kw))
-    o = oracle.build(points, leaf_cap=T, max_level=ml, sampling=sampling, seed=seed)
+    params = lod.make_params(full_precision=full, **kw)
+    g = host_tree(lod.lod_build_chunked(np.ascontiguousarray(points), chunk, params=params))
+    o = oracle.build(points, leaf_cap=T, max_level=ml, sampling=sampling, seed=seed, full_precision=full)
     canon.compare_trees(g, o, points)
-    d = in_core(lod, points, **kw)
+    if full:
+        assert g["voxel_points"] is not None and g["voxel_ids"] is not None
+        for i in np.nonzero(g["is_leaf"] == 0)[0]:
+            go, oo, c = int(g["offset"][i]), int(o["offset"][i]), int(g["count"][i])
+            assert np.array_equal(g["voxel_points"][go:go + c], o["voxel_points"][oo:oo + c]), f"records of node {i}"
+    d = host_tree(lod.lod_build(to_dev(points), params=params))
     for f in canon.NODE_FIELDS + ("offset",):
         assert np.array_equal(g[f], d[f]), f"node field {f} differs from the in-core build"
     assert np.array_equal(g["voxels"], d["voxels"])
     if d["voxel_ids"] is not None:
         assert np.array_equal(g["voxel_ids"], d["voxel_ids"])
+    if d["voxel_points"] is not None:
+        assert np.array_equal(g["voxel_points"], d["voxel_points"])
     for i in np.nonzero(g["is_leaf"])[0]:
         a, c = int(g["offset"][i]), int(g["count"][i])
         assert np.array_equal(canon.rows_sorted(g["points"][a:a + c]), canon.rows_sorted(d["points"][a:a + c]))
@@ -71,6 +79,18 @@ def test_terrain(lod, sampling):
 def test_aerial(lod, sampling):
     p = synth.aerial(400_000, seed=2)
     check_chunked(lod, p, 60_000, T=5000, sampling=sampling)
+
+
+@pytest.mark.parametrize("sampling", [0, 1, 2, 3])
+def test_full_precision(lod, sampling):
+    p = synth.terrain(300_000, seed=12)
+    check_chunked(lod, p, 40_000, T=2000, sampling=sampling, seed=4, full=True)
+
+
+def test_full_precision_sparse_leaves(lod):
+    blob = synth.uniform_cloud(60_000, 49, lo=(0.40, 0.40, 0.40), hi=(0.45, 0.43, 0.41))
+    p = np.concatenate([synth.uniform_cloud(200, 50), blob])
+    check_chunked(lod, p, 5_000, T=1000, sampling=3, full=True)
 
 
 def test_scan_with_ids(lod):
@@ -131,7 +151,6 @@ def test_errors(lod):
     with pytest.raises(lod.LodError) as e:
         lod.lod_build_chunked(p, 100)
     assert e.value.status == -2
-    p = lod.make_params(full_precision=True)
     with pytest.raises(lod.LodError) as e:
-        lod.lod_build_chunked(synth.uniform_cloud(1_000, 48), 100, params=p)
+        lod.lod_build_chunked(synth.uniform_cloud(1_000, 48), 100, max_level=15)
     assert e.value.status == -1
