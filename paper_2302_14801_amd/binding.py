@@ -69,6 +69,11 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise OSError(f"{LIB_PATH} is missing: build it with paper_2302_14801_amd.build.build()")
+    # PyTorch supplies the device memory and streams, so the library has to
+    # run on the HIP runtime PyTorch loads: importing torch first makes the
+    # library bind to that runtime instead of loading a second one, which
+    # would not see the device once PyTorch's runtime holds it.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, vp, u32, u64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
     lib.lod_params_default.argtypes = [P(lod_params)]

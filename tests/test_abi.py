@@ -112,3 +112,19 @@ def test_binding_constants_match_header():
     for name in ("LOD_AVERAGE", "LOD_PICK_FIRST", "LOD_PICK_RANDOM", "LOD_WEIGHTED", "LOD_FLAG_POINT_IDS",
                  "LOD_FLAG_TIMING", "LOD_FLAG_FULL_PRECISION", "LOD_ERR_INVALID"):
         assert getattr(binding, name) == want[name], name
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """The library must run on the HIP runtime that PyTorch loads (PyTorch
+    supplies its device memory and streams): importing the package before
+    torch must not bring in a second runtime, which would find no device."""
+    import subprocess
+    import sys
+    code = ("import paper_2302_14801_amd, torch\n"
+            "from paper_2302_14801_amd import binding\n"
+            "binding._hip_lib()\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
