@@ -286,7 +286,6 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   lod_params cp = prm;
   if (ids) cp.flags |= LOD_FLAG_POINT_IDS;
   std::vector<TreePtr> rtrees(roots.size());
-  std::vector<uint32_t> rnode(roots.size());  // index of the level-b node in its tree
   struct HTree {
     std::vector<uint8_t> level, leaf;
     std::vector<uint64_t> key, off;
@@ -335,7 +334,6 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
         if (q.level[i] < b) continue;
         if (q.level[i] == b) {
           if (q.key[i] != roots[r] || q.leaf[i]) lod_fail(LOD_ERR_CAPACITY, "chunk root differs from the cell counts");
-          rnode[r] = i;
           found = true;
         }
         MNode m;
