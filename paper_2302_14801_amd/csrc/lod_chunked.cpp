@@ -4,11 +4,10 @@
 // about 10M points, builds each on the GPU and combines them).
 //
 //   1. the bounding cube of the whole cloud, streaming it through the GPU;
-//   2. the level-h cell counts (h <= 7), on the GPU; the host picks the
-//      split level b, the shallowest level whose cells hold at most
-//      chunk_points points;
-//   3. each piece sorted by level-b cell on the GPU and sent back, so that a
-//      cell's points are one run per piece;
+//   2. each piece sorted by cell on the GPU and sent back, so that a cell's
+//      points are one run per piece; the same pass counts the level-h cells
+//      (h <= 7), which give the split level b, the shallowest level whose
+//      cells hold at most chunk_points points;
 //   4. the nodes of levels 0..b from the counts alone: a node at level L is
 //      inner iff it holds more than T points and L < max_level, exactly the
 //      in-core rule;
@@ -83,6 +82,29 @@ struct HostBuf {
   }
 };
 
+// A second stream (default priority) for the sorted pieces' way back, with
+// an event per buffer pair: sorted (ready to copy), done (copied back).
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t sorted[2] = {}, done[2] = {};
+  SideStream() {
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(hipEventCreateWithFlags(&sorted[i], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&done[i], hipEventDisableTiming));
+    }
+  }
+  SideStream(const SideStream&) = delete;
+  ~SideStream() {
+    if (s) (void)hipStreamSynchronize(s);
+    for (int i = 0; i < 2; ++i) {
+      if (sorted[i]) (void)hipEventDestroy(sorted[i]);
+      if (done[i]) (void)hipEventDestroy(done[i]);
+    }
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
 // Waits for the stream before the buffers above it are released (also when
 // the build unwinds).
 struct Drain {
@@ -129,7 +151,8 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   const bool vids_out = pick || full;  // voxel ids: pick winners, or accepted samples
 
   DevBuf d_stage(dev), d_ids(dev), d_cell(dev), d_hist(dev), d_small(dev), d_grids(dev), d_jobs(dev), d_cnt(dev),
-      d_soff(dev), d_runs(dev), d_sorted(dev), d_sids(dev), d_cursor(dev), d_tiles(dev);
+      d_soff(dev), d_runs(dev), d_sorted(dev), d_sorted2(dev), d_sids(dev), d_sids2(dev), d_cursor(dev),
+      d_tiles(dev), d_hist2(dev);
   HostBuf h_ci, h_cube, h_sorted, h_sids, h_vid, h_rec;
   DevBuf d_rec(dev);
   std::vector<std::unique_ptr<DevBuf>> lvox, lvid;  // voxels of the levels above b
@@ -169,29 +192,81 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   HIPCHK(hipStreamSynchronize(s));
   if (hc->nonfinite) lod_fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
 
-  // 2. level-h cells and their counts
+  // 2. every piece sorted by cell on the GPU and sent back, so that a cell's
+  // points are one run per piece; the same pass counts the points of every
+  // level-h cell (h <= 7), which gives the split level b, the shallowest
+  // level whose cells hold at most chunk_points points.  Pieces are sorted by
+  // level min(h, 4) cells (at most 4096: counts and ranks in LDS), and again
+  // by level-b cells in the rare case that b is deeper.  pst[k][c]: first
+  // point of cell c in piece k (piece k starts at k * PS of the sorted
+  // arrays).  The sorted pieces return on a second stream while the next
+  // piece is uploaded and sorted.
   const uint32_t h = std::min<uint32_t>(7, prm.max_level - 1);
   const uint32_t nh = 1u << (3 * h);
-  uint32_t* hist = d_hist.get<uint32_t>(nh);
-  uint32_t* dcell = d_cell.get<uint32_t>(P);
-  HIPCHK(hipMemsetAsync(hist, 0, 4ull * nh, s));
-  for (uint64_t k = 0; k < npieces; ++k) {
-    const uint64_t m = hci[k].count;
-    HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
-    launch_cells(stage, (uint32_t)m, dcube, h, dcell, hist, s);
-    HIPCHK(hipGetLastError());
-  }
-  // counts of every level 0..h (Morton-contiguous sums)
+  lod_point* sp = h_sorted.get<lod_point>(n);
+  uint32_t* sid = h_sids.get<uint32_t>(n);
+  std::vector<std::vector<uint32_t>> pst;
+  uint32_t* hist_h = d_hist.get<uint32_t>(nh);
+  uint64_t PS = 0, npieces_s = 0;
+  uint32_t sorted_level = 0;
+  auto sort_pass = [&](uint32_t level, bool count_h) {
+    const uint32_t ns = 1u << (3 * level);
+    // at least 16 points per cell: the per-piece tables stay at n / 4 bytes
+    PS = std::min<uint64_t>(n, std::max<uint64_t>(P, 16ull * ns));
+    npieces_s = (n + PS - 1) / PS;
+    sorted_level = level;
+    pst.assign(npieces_s, std::vector<uint32_t>((size_t)ns + 1));
+    stage = d_stage.get<lod_point>(PS);
+    uint32_t* hist_s = d_hist2.get<uint32_t>(ns);
+    uint32_t* dcell = d_cell.get<uint32_t>(PS);
+    uint32_t* cursor = d_cursor.get<uint32_t>(ns);
+    uint32_t* tiles = d_tiles.get<uint32_t>(1024);
+    lod_point* dsorted[2] = {d_sorted.get<lod_point>(PS), d_sorted2.get<lod_point>(PS)};
+    uint32_t* dsids[2] = {d_sids.get<uint32_t>(PS), d_sids2.get<uint32_t>(PS)};
+    if (count_h) HIPCHK(hipMemsetAsync(hist_h, 0, 4ull * nh, s));
+    SideStream s2;
+    for (uint64_t k = 0; k < npieces_s; ++k) {
+      const uint64_t m = std::min<uint64_t>(PS, n - k * PS);
+      const int q = (int)(k & 1);
+      HIPCHK(hipMemcpyAsync(stage, hin + k * PS, 16ull * m, hipMemcpyHostToDevice, s));
+      if (count_h) launch_cells(stage, (uint32_t)m, dcube, h, dcell, hist_h, s);
+      HIPCHK(hipMemsetAsync(hist_s, 0, 4ull * ns, s));
+      launch_cells(stage, (uint32_t)m, dcube, level, dcell, hist_s, s);
+      HIPCHK(hipMemcpyAsync(pst[k].data(), hist_s, 4ull * ns, hipMemcpyDeviceToHost, s));
+      // the buffers of piece k - 2 are free once their copy back has ended
+      if (k >= 2) HIPCHK(hipStreamWaitEvent(s, s2.done[q], 0));
+      launch_sort_by_cell(stage, dcell, (uint32_t)m, (uint32_t)(k * PS), hist_s, ns, tiles, cursor, dsorted[q],
+                          dsids[q], s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(s2.sorted[q], s));
+      HIPCHK(hipStreamWaitEvent(s2.s, s2.sorted[q], 0));
+      HIPCHK(hipMemcpyAsync(sp + k * PS, dsorted[q], 16ull * m, hipMemcpyDeviceToHost, s2.s));
+      HIPCHK(hipMemcpyAsync(sid + k * PS, dsids[q], 4ull * m, hipMemcpyDeviceToHost, s2.s));
+      HIPCHK(hipEventRecord(s2.done[q], s2.s));
+    }
+    HIPCHK(hipStreamSynchronize(s2.s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (uint64_t k = 0; k < npieces_s; ++k) {
+      uint32_t run = 0;
+      for (uint32_t c = 0; c <= ns; ++c) {
+        const uint32_t v = c < ns ? pst[k][c] : 0u;
+        pst[k][c] = run;
+        run += v;
+      }
+    }
+  };
+  sort_pass(std::min<uint32_t>(h, 4), true);
+  // counts of every level 0..h (Morton-contiguous sums) and the split level
   std::vector<std::vector<uint64_t>> cnt(h + 1);
   {
     std::vector<uint32_t> hh(nh);
-    HIPCHK(hipMemcpyAsync(hh.data(), hist, 4ull * nh, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hh.data(), hist_h, 4ull * nh, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     cnt[h].assign(hh.begin(), hh.end());
-    for (int L = (int)h - 1; L >= 0; --L) {
-      cnt[L].assign(1ull << (3 * L), 0);
-      for (uint64_t c = 0; c < cnt[L + 1].size(); ++c) cnt[L][c >> 3] += cnt[L + 1][c];
-    }
+  }
+  for (int L = (int)h - 1; L >= 0; --L) {
+    cnt[L].assign(1ull << (3 * L), 0);
+    for (uint64_t c = 0; c < cnt[L + 1].size(); ++c) cnt[L][c >> 3] += cnt[L + 1][c];
   }
   uint32_t b = h;
   for (uint32_t L = 1; L <= h; ++L)
@@ -199,51 +274,18 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       b = L;
       break;
     }
-  const uint32_t nb = 1u << (3 * b);
-
-  // 3. every piece sorted by level-b cell on the GPU; pst[k][c]: first point
-  // of cell c in piece k (piece k starts at k * P3 of the sorted arrays).
-  // Pieces of at least 16 points per cell keep these tables at n / 4 bytes.
-  const uint64_t P3 = std::min<uint64_t>(n, std::max<uint64_t>(P, 16ull * nb));
-  const uint64_t npieces3 = (n + P3 - 1) / P3;
-  lod_point* sp = h_sorted.get<lod_point>(n);
-  uint32_t* sid = h_sids.get<uint32_t>(n);
-  std::vector<std::vector<uint32_t>> pst(npieces3, std::vector<uint32_t>((size_t)nb + 1));
-  {
-    stage = d_stage.get<lod_point>(P3);
-    dcell = d_cell.get<uint32_t>(P3);
-    lod_point* dsorted = d_sorted.get<lod_point>(P3);
-    uint32_t* dsids = d_sids.get<uint32_t>(P3);
-    uint32_t* cursor = d_cursor.get<uint32_t>(nb);
-    uint32_t* tiles = d_tiles.get<uint32_t>(1024);
-    for (uint64_t k = 0; k < npieces3; ++k) {
-      const uint64_t m = std::min<uint64_t>(P3, n - k * P3);
-      HIPCHK(hipMemcpyAsync(stage, hin + k * P3, 16ull * m, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemsetAsync(hist, 0, 4ull * nb, s));
-      launch_cells(stage, (uint32_t)m, dcube, b, dcell, hist, s);
-      HIPCHK(hipMemcpyAsync(pst[k].data(), hist, 4ull * nb, hipMemcpyDeviceToHost, s));
-      launch_sort_by_cell(stage, dcell, (uint32_t)m, (uint32_t)(k * P3), hist, nb, tiles, cursor, dsorted, dsids, s);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(sp + k * P3, dsorted, 16ull * m, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(sid + k * P3, dsids, 4ull * m, hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    for (uint64_t k = 0; k < npieces3; ++k) {
-      uint32_t run = 0;
-      for (uint32_t c = 0; c <= nb; ++c) {
-        const uint32_t v = c < nb ? pst[k][c] : 0u;
-        pst[k][c] = run;
-        run += v;
-      }
-    }
-  }
+  if (b > sorted_level) sort_pass(b, false);
   d_sorted.release();
+  d_sorted2.release();
   d_sids.release();
+  d_sids2.release();
+  d_cell.release();
   // the points of level-b cells [c0, c1): one run per piece
+  const uint32_t sh = 3 * (sorted_level - b);
   auto for_runs = [&](uint64_t c0, uint64_t c1, auto&& f) {
     uint64_t o = 0;
-    for (uint64_t k = 0; k < npieces3; ++k) {
-      const uint64_t beg = k * P3 + pst[k][c0], len = pst[k][c1] - pst[k][c0];
+    for (uint64_t k = 0; k < npieces_s; ++k) {
+      const uint64_t beg = k * PS + pst[k][c0 << sh], len = pst[k][c1 << sh] - pst[k][c0 << sh];
       if (len) f(beg, len, o);
       o += len;
     }
