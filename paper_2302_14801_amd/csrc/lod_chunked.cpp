@@ -204,7 +204,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   const uint32_t h = std::min<uint32_t>(7, prm.max_level - 1);
   const uint32_t nh = 1u << (3 * h);
   lod_point* sp = h_sorted.get<lod_point>(n);
-  uint32_t* sid = h_sids.get<uint32_t>(n);
+  uint32_t* sid = ids ? h_sids.get<uint32_t>(n) : nullptr;  // input indices travel only when used
   std::vector<std::vector<uint32_t>> pst;
   uint32_t* hist_h = d_hist.get<uint32_t>(nh);
   uint64_t PS = 0, npieces_s = 0;
@@ -241,7 +241,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       HIPCHK(hipEventRecord(s2.sorted[q], s));
       HIPCHK(hipStreamWaitEvent(s2.s, s2.sorted[q], 0));
       HIPCHK(hipMemcpyAsync(sp + k * PS, dsorted[q], 16ull * m, hipMemcpyDeviceToHost, s2.s));
-      HIPCHK(hipMemcpyAsync(sid + k * PS, dsids[q], 4ull * m, hipMemcpyDeviceToHost, s2.s));
+      if (sid) HIPCHK(hipMemcpyAsync(sid + k * PS, dsids[q], 4ull * m, hipMemcpyDeviceToHost, s2.s));
       HIPCHK(hipEventRecord(s2.done[q], s2.s));
     }
     HIPCHK(hipStreamSynchronize(s2.s));
@@ -339,13 +339,13 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     uint64_t pts = 0;
     while (r1 < roots.size() && (r1 == r0 || pts + cnt[b][roots[r1]] <= chunk)) pts += cnt[b][roots[r1++]];
     lod_point* bp = d_stage.get<lod_point>(pts);
-    uint32_t* bid = d_ids.get<uint32_t>(pts);
+    uint32_t* bid = sid ? d_ids.get<uint32_t>(pts) : nullptr;
     std::vector<uint64_t> offs(r1 - r0 + 1, 0);
     for (size_t r = r0; r < r1; ++r) {
       const uint64_t c = roots[r], o = offs[r - r0];
       for_runs(c, c + 1, [&](uint64_t beg, uint64_t len, uint64_t at) {
         HIPCHK(hipMemcpyAsync(bp + o + at, sp + beg, 16ull * len, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(bid + o + at, sid + beg, 4ull * len, hipMemcpyHostToDevice, s));
+        if (bid) HIPCHK(hipMemcpyAsync(bid + o + at, sid + beg, 4ull * len, hipMemcpyHostToDevice, s));
       });
       offs[r - r0 + 1] = o + cnt[b][c];
     }
