@@ -193,7 +193,8 @@ lod_status lod_build_chunked(const lod_point* h_points, uint64_t n, const lod_pa
  * otherwise all zero).  Stages: bounding box; the first partition (count,
  * offsets, insert); the second partition (count, offsets, insert); node
  * enumeration including refinement partitions; leaf voxels; inner levels;
- * and the whole build from the first to the last kernel. */
+ * and the whole build from the first to the last kernel.  All zero for a tree
+ * that lod_build_chunked made from several chunks. */
 typedef struct {
   float bbox;
   float count0, offsets0, scatter0;
