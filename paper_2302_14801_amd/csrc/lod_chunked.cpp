@@ -334,21 +334,46 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     std::vector<uint32_t> npts, count;
   };
   std::vector<HTree> ht(roots.size());
+  // batches [bstart[i], bstart[i + 1]) of roots; batch i + 1 is uploaded on
+  // the side stream (into the other buffer pair) while batch i is built
+  std::vector<size_t> bstart{0};
+  uint64_t max_pts = 0;
   for (size_t r0 = 0; r0 < roots.size();) {
     size_t r1 = r0;
     uint64_t pts = 0;
     while (r1 < roots.size() && (r1 == r0 || pts + cnt[b][roots[r1]] <= chunk)) pts += cnt[b][roots[r1++]];
-    lod_point* bp = d_stage.get<lod_point>(pts);
-    uint32_t* bid = sid ? d_ids.get<uint32_t>(pts) : nullptr;
-    std::vector<uint64_t> offs(r1 - r0 + 1, 0);
-    for (size_t r = r0; r < r1; ++r) {
-      const uint64_t c = roots[r], o = offs[r - r0];
+    bstart.push_back(r1);
+    max_pts = std::max(max_pts, pts);
+    r0 = r1;
+  }
+  lod_point* bpts[2] = {d_stage.get<lod_point>(max_pts), d_sorted.get<lod_point>(max_pts)};
+  uint32_t* bids[2] = {sid ? d_ids.get<uint32_t>(max_pts) : nullptr, sid ? d_sids.get<uint32_t>(max_pts) : nullptr};
+  SideStream up;
+  auto upload = [&](size_t i) {
+    const int q = (int)(i & 1);
+    uint64_t o = 0;
+    for (size_t r = bstart[i]; r < bstart[i + 1]; ++r) {
+      const uint64_t c = roots[r];
       for_runs(c, c + 1, [&](uint64_t beg, uint64_t len, uint64_t at) {
-        HIPCHK(hipMemcpyAsync(bp + o + at, sp + beg, 16ull * len, hipMemcpyHostToDevice, s));
-        if (bid) HIPCHK(hipMemcpyAsync(bid + o + at, sid + beg, 4ull * len, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(bpts[q] + o + at, sp + beg, 16ull * len, hipMemcpyHostToDevice, up.s));
+        if (sid) HIPCHK(hipMemcpyAsync(bids[q] + o + at, sid + beg, 4ull * len, hipMemcpyHostToDevice, up.s));
       });
-      offs[r - r0 + 1] = o + cnt[b][c];
+      o += cnt[b][c];
     }
+    HIPCHK(hipEventRecord(up.done[q], up.s));
+  };
+  const size_t nbatches = bstart.size() - 1;
+  if (nbatches) upload(0);
+  for (size_t i = 0; i < nbatches; ++i) {
+    const size_t r0 = bstart[i], r1 = bstart[i + 1];
+    const int q = (int)(i & 1);
+    // the other buffer pair was last read by batch i - 1, whose build has ended
+    if (i + 1 < nbatches) upload(i + 1);
+    HIPCHK(hipStreamWaitEvent(s, up.done[q], 0));
+    lod_point* bp = bpts[q];
+    uint32_t* bid = bids[q];
+    std::vector<uint64_t> offs(r1 - r0 + 1, 0);
+    for (size_t r = r0; r < r1; ++r) offs[r - r0 + 1] = offs[r - r0] + cnt[b][roots[r]];
     BuildExtras x;
     x.cube = hc;
     x.d_ids = bid;
@@ -391,9 +416,11 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       }
       if (!found) lod_fail(LOD_ERR_CAPACITY, "chunk tree without its root cell");
     }
-    r0 = r1;
   }
+  HIPCHK(hipStreamSynchronize(up.s));
   d_ids.release();
+  d_sids.release();
+  d_sorted.release();
 
   // 8a. node order, children, leaf point offsets
   std::sort(nodes.begin(), nodes.end(), [](const MNode& a, const MNode& c) {
