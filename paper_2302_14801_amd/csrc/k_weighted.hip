@@ -52,10 +52,13 @@ __global__ void __launch_bounds__(256) k_wslots(const uint32_t* __restrict__ ln,
 }
 
 // The bitmap words of the inner nodes in ln (set = true) or their reset
-// (set = false): the first voxel of every 64-cell word writes the whole word
-// (the word's voxels follow it in the list) and, when setting, its own index.
-// When setting, the node's list is also cut at its 64 aligned 32^3 blocks of
-// cells (contiguous code ranges): bseg[64 n + b] = [first, end) of block b,
+// (set = false).  A wave takes 64 consecutive voxels of a node's list (sorted
+// by cell, so a word's voxels are consecutive): a segmented OR over the lanes
+// of each word gives its bits, added with one atomic OR per (wave, word); the
+// first voxel of every word writes the word's list index, or, when
+// resetting, zeroes the word.  The bitmaps are zero before setting.  When
+// setting, the node's list is also cut at its 64 aligned 32^3 blocks of cells
+// (contiguous code ranges): bseg[64 n + b] = [first, end) of block b,
 // relative to the node's first voxel (zero for empty blocks).
 __global__ void __launch_bounds__(256) k_wbits(Nodes nodes, const uint32_t* __restrict__ ln,
                                                const TreeInfo* __restrict__ trees, const uint64_t* __restrict__ vox,
@@ -66,27 +69,41 @@ __global__ void __launch_bounds__(256) k_wbits(Nodes nodes, const uint32_t* __re
   const uint64_t base = trees[nodes.tree[n]].vbase + nodes.offset[n];
   const uint32_t cnt = nodes.count[n];
   const uint64_t sb = (uint64_t)wslot[n] * kWWords;
-  for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < cnt; i += kWSplit * 256) {
-    const uint32_t code = voxel_code(vox[base + i]), word = code >> 6;
-    const uint32_t prev = i > 0 ? voxel_code(vox[base + i - 1]) : 0xffffffffu;
-    if (set) {
-      const uint32_t b = code >> 15;
-      if (i == 0 || (prev >> 15) != b) bseg[64ull * n + b].x = i;
-      if (i + 1 == cnt || (voxel_code(vox[base + i + 1]) >> 15) != b) bseg[64ull * n + b].y = i + 1;
-    }
-    if (i > 0 && (prev >> 6) == word) continue;
+  const uint32_t lane = threadIdx.x & 63u;
+  constexpr uint32_t kNone = 0xffffffffu;  // no voxel (its word and block match no real one)
+  // wave-uniform loop: every lane takes part in the shuffles
+  for (uint32_t w0 = blockIdx.y * 256 + (threadIdx.x & ~63u); w0 < cnt; w0 += kWSplit * 256) {
+    const uint32_t i = w0 + lane;
+    const bool valid = i < cnt;
+    const uint32_t code = valid ? voxel_code(vox[base + i]) : kNone, word = code >> 6;
+    uint32_t prev = __shfl_up(code, 1, 64);
+    if (lane == 0) prev = i > 0 ? voxel_code(vox[base + i - 1]) : kNone;
+    uint32_t next = __shfl_down(code, 1, 64);
+    if (lane == 63) next = i + 1 < cnt ? voxel_code(vox[base + i + 1]) : kNone;
+    const bool first = valid && (prev >> 6) != word;
     if (!set) {
-      bits[sb + word] = 0ull;
+      if (first) bits[sb + word] = 0ull;
       continue;
     }
-    unsigned long long b = 0;
-    for (uint32_t j = i; j < cnt && j < i + 64; ++j) {
-      const uint32_t c = voxel_code(vox[base + j]);
-      if ((c >> 6) != word) break;
-      b |= 1ull << (c & 63u);
+    if (valid) {
+      const uint32_t b = code >> 15;
+      if ((prev >> 15) != b) bseg[64ull * n + b].x = i;
+      if ((next >> 15) != b) bseg[64ull * n + b].y = i + 1;
     }
-    bits[sb + word] = b;
-    wpre[sb + word] = i;
+    if (first) wpre[sb + word] = i;
+    // segmented inclusive OR over the lanes of each word
+    uint32_t lo = valid && (code & 63u) < 32u ? 1u << (code & 31u) : 0u;
+    uint32_t hi = valid && (code & 63u) >= 32u ? 1u << (code & 31u) : 0u;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint32_t l2 = __shfl_up(lo, d, 64), h2 = __shfl_up(hi, d, 64), w2 = __shfl_up(word, d, 64);
+      if (lane >= d && w2 == word) {
+        lo |= l2;
+        hi |= h2;
+      }
+    }
+    if (valid && ((next >> 6) != word || lane == 63))
+      atomicOr(bits + sb + word, ((unsigned long long)hi << 32) | lo);
   }
 }
 
