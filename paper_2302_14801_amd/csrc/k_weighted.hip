@@ -236,6 +236,9 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
     }
     const uint64_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
     wtargets(L, G, pos2, [&](uint32_t code, uint64_t w) {
+      // a cell of the block without samples of its own is not a voxel: its
+      // sums would be dropped, so they are not made
+      if ((code >> 12) == blk && !((lt.bbits[(code >> 6) & 63u] >> (code & 63u)) & 1ull)) return;
       uint32_t slot = (code * 0x9E3779B1u) >> 21;  // 11 bits
       bool done = false;
       for (int probe = 0; probe < kWProbe; ++probe) {
