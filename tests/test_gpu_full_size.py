@@ -111,3 +111,41 @@ def test_aerial_100m_chunked_equals_in_core():
     raw = np.ascontiguousarray(pts).view(np.uint8).reshape(-1, 16)
     assert np.array_equal(g["points"], raw[g["point_ids"]])
     fullsize.check_build(g, pts, T, ML)
+
+
+def test_aerial_20m_chunked_weighted_full_precision():
+    """The weighted average with full-precision records on a 20M-point aerial
+    cloud, built from host memory in 2M-point chunks, equals the in-core
+    build: node table, voxels, accepted ids and records, leaf point sets."""
+    import numpy as np
+    import torch
+
+    import paper_2302_14801_amd as lod
+
+    n = 20_000_000
+    fullsize.log("generating 20M")
+    host = torch.empty(n * 16, dtype=torch.uint8, pin_memory=True)
+    pts = host.numpy().view(synth.POINT_DTYPE)
+    synth.aerial(n, seed=6, out=pts)
+    params = lod.make_params(leaf_cap=T, max_level=ML, sampling=3, full_precision=True)
+    fullsize.log("chunked build")
+    t = lod.lod_build_chunked(pts, 2_000_000, params=params)
+    g = t.to_host()
+    t.free()
+    fullsize.log("in-core build")
+    dev = host.to("cuda:0")
+    t = lod.lod_build(dev, params=params)
+    d = t.to_host()
+    t.free()
+    del dev
+    fullsize.log(f"{g['num_nodes']} nodes, {g['num_voxels']} voxels; comparing")
+    for f in ("level", "key", "is_leaf", "npoints", "child_mask", "first_child", "count", "offset"):
+        assert np.array_equal(g[f], d[f]), f
+    for f in ("voxels", "voxel_ids", "voxel_points"):
+        assert np.array_equal(g[f], d[f]), f
+    leaf = np.nonzero(g["is_leaf"])[0]
+    order = np.argsort(g["offset"][leaf], kind="stable")
+    owner = np.repeat(np.arange(len(leaf), dtype=np.uint64)[order], g["count"][leaf][order].astype(np.int64))
+    ka = np.sort((owner << np.uint64(32)) | g["point_ids"].astype(np.uint64))
+    kb = np.sort((owner << np.uint64(32)) | d["point_ids"].astype(np.uint64))
+    assert np.array_equal(ka, kb)
