@@ -151,20 +151,11 @@ struct WBlockLocal {
   uint32_t bpre[64];                      // list index (from the node's first voxel) of each word's first cell
   uint32_t overflow;
 };
-__global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const uint32_t* __restrict__ ln, uint32_t L,
-                                                             const ItemDesc* __restrict__ desc,
-                                                             const uint2* __restrict__ bseg,
-                                                             const TreeInfo* __restrict__ trees, const Cube* cube,
-                                                             const uint4* __restrict__ Y, uint64_t* vox,
-                                                             const uint32_t* __restrict__ wslot,
-                                                             const unsigned long long* __restrict__ bits,
-                                                             const uint32_t* __restrict__ wpre,
-                                                             unsigned long long* acc) {
-  __shared__ WBlockLocal lt;
-  const uint32_t n = ln[blockIdx.x >> 6], sub = blockIdx.x & 63u, t = threadIdx.x;
-  const bool leaf = nodes.is_leaf[n] != 0;
-  uint64_t first;
-  uint32_t cnt;
+// Samples of a (child, block) pair: the leaf micro-bucket's point range or
+// the inner child's voxel range; cnt = 0 for an empty block.
+__device__ __forceinline__ void wblock_range(const Nodes& nodes, const ItemDesc* __restrict__ desc,
+                                             const uint2* __restrict__ bseg, const TreeInfo* __restrict__ trees,
+                                             uint32_t n, uint32_t sub, bool leaf, uint64_t& first, uint32_t& cnt) {
   if (leaf) {
     // work item sub / 8 of the leaf (a child cell), micro-bucket sub % 8
     const ItemDesc& d = desc[8 * n + (sub >> 3)];
@@ -177,6 +168,39 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
     cnt = sg.y - sg.x;
     first = trees[nodes.tree[n]].vbase + nodes.offset[n] + sg.x;
   }
+}
+
+// The non-empty (child, block) pairs of a level: list[0 .. *count) holds
+// 64 * (position in ln) + block, in any order.
+__global__ void __launch_bounds__(256) k_wblocks(Nodes nodes, const uint32_t* __restrict__ ln, uint32_t nch,
+                                                 const ItemDesc* __restrict__ desc, const uint2* __restrict__ bseg,
+                                                 const TreeInfo* __restrict__ trees, uint32_t* list, uint32_t* count) {
+  const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= 64 * nch) return;
+  const uint32_t n = ln[idx >> 6];
+  uint64_t first;
+  uint32_t cnt;
+  wblock_range(nodes, desc, bseg, trees, n, idx & 63u, nodes.is_leaf[n] != 0, first, cnt);
+  if (cnt) list[atomicAdd(count, 1u)] = idx;
+}
+
+__global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const uint32_t* __restrict__ ln,
+                                                             const uint32_t* __restrict__ blocks, uint32_t L,
+                                                             const ItemDesc* __restrict__ desc,
+                                                             const uint2* __restrict__ bseg,
+                                                             const TreeInfo* __restrict__ trees, const Cube* cube,
+                                                             const uint4* __restrict__ Y, uint64_t* vox,
+                                                             const uint32_t* __restrict__ wslot,
+                                                             const unsigned long long* __restrict__ bits,
+                                                             const uint32_t* __restrict__ wpre,
+                                                             unsigned long long* acc) {
+  __shared__ WBlockLocal lt;
+  const uint32_t idx = blocks[blockIdx.x];
+  const uint32_t n = ln[idx >> 6], sub = idx & 63u, t = threadIdx.x;
+  const bool leaf = nodes.is_leaf[n] != 0;
+  uint64_t first;
+  uint32_t cnt;
+  wblock_range(nodes, desc, bseg, trees, n, sub, leaf, first, cnt);
   if (cnt == 0) return;
   const uint32_t A = nodes.parent[n];
   const uint64_t ka = nodes.key[A], kn = nodes.key[n];
@@ -326,10 +350,11 @@ __global__ void __launch_bounds__(256) k_wfinal(Nodes nodes, const uint32_t* __r
   }
 }
 
-void launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t* loff, uint32_t deepest,
-                     const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
-                     uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg, unsigned long long* acc,
-                     hipStream_t s) {
+hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t* loff, uint32_t deepest,
+                           const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
+                           uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg,
+                           unsigned long long* acc, uint32_t* blocks, uint32_t* nblocks, uint32_t* h_nblocks,
+                           hipStream_t s) {
   for (int L = (int)deepest - 1; L >= 0; --L) {
     const uint32_t l = (uint32_t)L;
     const uint32_t* pa = lnodes + loff[l];       // the parents' level
@@ -339,9 +364,18 @@ void launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t*
     hipLaunchKernelGGL(k_wslots, dim3((na + 255) / 256), dim3(256), 0, s, pa, na, wslot);
     hipLaunchKernelGGL(k_wbits, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, (const uint64_t*)vox,
                        (const uint32_t*)wslot, bits, wpre, bseg, true);
-    hipLaunchKernelGGL(k_wsplat_block, dim3(64 * nch), dim3(kWLThreads), 0, s, nodes, ch, l, (const ItemDesc*)desc,
-                       (const uint2*)bseg, trees, cube, (const uint4*)Y, vox, (const uint32_t*)wslot,
-                       (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
+    // the non-empty blocks only (most micro-buckets of a surface are empty)
+    hipError_t e = hipMemsetAsync(nblocks, 0, sizeof(uint32_t), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wblocks, dim3((64 * nch + 255) / 256), dim3(256), 0, s, nodes, ch, nch, (const ItemDesc*)desc,
+                       (const uint2*)bseg, trees, blocks, nblocks);
+    if ((e = hipMemcpyAsync(h_nblocks, nblocks, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const uint32_t nblk = std::min<uint32_t>(*h_nblocks, 64 * nch);
+    if (nblk)
+      hipLaunchKernelGGL(k_wsplat_block, dim3(nblk), dim3(kWLThreads), 0, s, nodes, ch, (const uint32_t*)blocks,
+                         l, (const ItemDesc*)desc, (const uint2*)bseg, trees, cube, (const uint4*)Y, vox,
+                         (const uint32_t*)wslot, (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
     hipLaunchKernelGGL(k_wfinal, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, vox,
                        (const unsigned long long*)acc);
     // the bitmaps are cleared word by word (from the unchanged cell lists) for
@@ -349,6 +383,7 @@ void launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t*
     hipLaunchKernelGGL(k_wbits, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, (const uint64_t*)vox,
                        (const uint32_t*)wslot, bits, wpre, bseg, false);
   }
+  return hipGetLastError();
 }
 
 uint64_t weighted_bitmap_words() { return kWWords; }

@@ -122,8 +122,8 @@ struct Workspace {
   Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_tree;
   Scratch c_level, c_leaf, c_mask, c_key, c_npts, c_count, c_first, c_off, c_cover, c_grid, c_parent, c_tree;
   Scratch t2, t2id, icnt, idesc, iself, v_sz, v_dfs, v_dfsn, v_psize, v_poff, v_selfc, v_selfid;
-  Scratch state, bstate, clouds, trees, nbeg, wslot, wlist, wbits, wpre, wacc, wseg;
-  Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs, h_wlist;
+  Scratch state, bstate, clouds, trees, nbeg, wslot, wlist, wbits, wpre, wacc, wseg, wblk;
+  Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs, h_wlist, h_wblk;
   std::vector<void*> retired;  // outgrown blocks, released when the build's stream has drained
   hipEvent_t ev[16] = {};
   bool ev_ready = false;
@@ -134,7 +134,7 @@ struct Workspace {
             &c_level, &c_leaf,  &c_mask,  &c_key,   &c_npts,   &c_count, &c_first,  &c_off,   &c_cover,
             &c_grid,  &c_parent, &c_tree, &t2,      &t2id,     &icnt,    &idesc,    &iself,   &v_sz,
             &v_dfs,   &v_dfsn,  &v_psize, &v_poff,  &v_selfc,  &v_selfid, &state,   &bstate,  &clouds,
-            &trees,   &nbeg,    &wslot,   &wlist,   &wbits,   &wpre,    &wacc,    &wseg};
+            &trees,   &nbeg,    &wslot,   &wlist,   &wbits,   &wpre,    &wacc,    &wseg,    &wblk};
   }
   Workspace() {
     for (Scratch* sc : scratches()) sc->retired = &retired;
@@ -635,11 +635,13 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     uint32_t* wpre = w.wpre.get<uint32_t>(dev, words);
     unsigned long long* wacc = w.wacc.get<unsigned long long>(dev, 4 * vtotal);
     uint2* wseg = w.wseg.get<uint2>(dev, 64ull * num_nodes);
+    uint32_t* wblk = w.wblk.get<uint32_t>(dev, 64ull * num_nodes + 1);
     HIPCHK(hipMemcpyAsync(wlist, hl, sizeof(uint32_t) * k, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(wbits, 0, 8 * words, s));
     HIPCHK(hipMemsetAsync(wacc, 0, 32 * vtotal, s));
     HIPCHK(hipMemsetAsync(wseg, 0, 64ull * sizeof(uint2) * num_nodes, s));
-    launch_weighted(nd, wlist, loff, deepest, tinfo, cube, desc, Y, vox, wslot, wbits, wpre, wseg, wacc, s);
+    HIPCHK(launch_weighted(nd, wlist, loff, deepest, tinfo, cube, desc, Y, vox, wslot, wbits, wpre, wseg, wacc,
+                           wblk + 1, wblk, w.h_wblk.get<uint32_t>(1), s));
   }
   lod_point* vpts = nullptr;
   if (pl.full && !(x && x->ids_only)) {
