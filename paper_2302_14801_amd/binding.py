@@ -68,7 +68,8 @@ def load_library():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise OSError(f"{LIB_PATH} is missing: build it with paper_2302_14801_amd.build.build()")
+        raise OSError(f"{LIB_PATH} is missing: build it with `python paper_2302_14801_amd/build.py` "
+                      "(or __graft_entry__.build())")
     # PyTorch supplies the device memory and streams, so the library has to
     # run on the HIP runtime PyTorch loads: importing torch first makes the
     # library bind to that runtime instead of loading a second one, which
