@@ -128,3 +128,18 @@ def test_one_hip_runtime_whatever_the_import_order():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_build_entry_does_not_need_a_built_library():
+    """build() reaches the build script without importing the package (which
+    refuses to import before liblod.so exists), so a clean tree builds."""
+    import subprocess
+    import sys
+    code = ("import sys, __graft_entry__ as g\n"
+            "m = g._builder()\n"
+            "assert callable(m.build) and m.LIB.endswith('liblod.so')\n"
+            "assert 'paper_2302_14801_amd' not in sys.modules\n"
+            "print('ok')\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().endswith("ok")
