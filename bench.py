@@ -415,7 +415,7 @@ def main():
         chunked = {"chunk_points": args.chunk_points, "ms_per_build": round(cms, 2),
                    "points_per_s": round(n / (cms * 1e-3), 1), "steps": args.chunked_steps,
                    "in_core_from_host_ms": round(hms, 2), "same_nodes_and_voxels": cinfo[-1] == infos[-1],
-                   "note": "host input: a streaming pass for the cube, one that counts and sorts each piece by cell on the GPU, "
+                   "note": "host input: a streaming pass for the cube, one that sorts each piece by cell on the GPU (its counts give the split level), "
                            "chunk uploads and builds, the merge above the chunk roots"}
 
     cpu = None

@@ -170,8 +170,8 @@ lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets,
  * borrowed; the result equals lod_build on the whole cloud (same nodes, node
  * order, leaf point sets, voxels and ids; ids are indices into h_points).
  * The cloud streams through the GPU in pieces of max(chunk_points, 2^20)
- * records for its bounding cube, and once more to be counted and sorted by
- * cell piece by piece; it is cut at the shallowest level b (at most
+ * records for its bounding cube, and once more to be sorted by cell piece by
+ * piece; it is cut at the shallowest level b (at most
  * min(7, max_level - 1)) whose cells hold at most chunk_points points, and
  * every cell of level b with more than T points is built as a chunk (chunks
  * are batched up to chunk_points points) with the common cube; the levels

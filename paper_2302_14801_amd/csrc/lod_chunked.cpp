@@ -193,11 +193,12 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   if (hc->nonfinite) lod_fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
 
   // 2. every piece sorted by cell on the GPU and sent back, so that a cell's
-  // points are one run per piece; the same pass counts the points of every
-  // level-h cell (h <= 7), which gives the split level b, the shallowest
-  // level whose cells hold at most chunk_points points.  Pieces are sorted by
-  // level min(h, 4) cells (at most 4096: counts and ranks in LDS), and again
-  // by level-b cells in the rare case that b is deeper.  pst[k][c]: first
+  // points are one run per piece.  Pieces are sorted by level s = min(h, 4)
+  // cells (at most 4096: counts and ranks in LDS), h = min(7, max_level - 1).
+  // The sort's counts give the split level b, the shallowest level whose
+  // cells hold at most chunk_points points, when that is level s or above;
+  // otherwise a pass counts the level-h cells and the pieces are sorted
+  // again by level-b cells.  pst[k][c]: first
   // point of cell c in piece k (piece k starts at k * PS of the sorted
   // arrays).  The sorted pieces return on a second stream while the next
   // piece is uploaded and sorted.
@@ -209,7 +210,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   uint32_t* hist_h = d_hist.get<uint32_t>(nh);
   uint64_t PS = 0, npieces_s = 0;
   uint32_t sorted_level = 0;
-  auto sort_pass = [&](uint32_t level, bool count_h) {
+  auto sort_pass = [&](uint32_t level) {
     const uint32_t ns = 1u << (3 * level);
     // at least 16 points per cell: the per-piece tables stay at n / 4 bytes
     PS = std::min<uint64_t>(n, std::max<uint64_t>(P, 16ull * ns));
@@ -223,13 +224,11 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     uint32_t* tiles = d_tiles.get<uint32_t>(1024);
     lod_point* dsorted[2] = {d_sorted.get<lod_point>(PS), d_sorted2.get<lod_point>(PS)};
     uint32_t* dsids[2] = {d_sids.get<uint32_t>(PS), d_sids2.get<uint32_t>(PS)};
-    if (count_h) HIPCHK(hipMemsetAsync(hist_h, 0, 4ull * nh, s));
     SideStream s2;
     for (uint64_t k = 0; k < npieces_s; ++k) {
       const uint64_t m = std::min<uint64_t>(PS, n - k * PS);
       const int q = (int)(k & 1);
       HIPCHK(hipMemcpyAsync(stage, hin + k * PS, 16ull * m, hipMemcpyHostToDevice, s));
-      if (count_h) launch_cells(stage, (uint32_t)m, dcube, h, dcell, hist_h, s);
       HIPCHK(hipMemsetAsync(hist_s, 0, 4ull * ns, s));
       launch_cells(stage, (uint32_t)m, dcube, level, dcell, hist_s, s);
       HIPCHK(hipMemcpyAsync(pst[k].data(), hist_s, 4ull * ns, hipMemcpyDeviceToHost, s));
@@ -255,26 +254,50 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       }
     }
   };
-  sort_pass(std::min<uint32_t>(h, 4), true);
-  // counts of every level 0..h (Morton-contiguous sums) and the split level
-  std::vector<std::vector<uint64_t>> cnt(h + 1);
-  {
+  const uint32_t s_level = std::min<uint32_t>(h, 4);
+  sort_pass(s_level);
+  // counts of the levels 0..top (Morton-contiguous sums), top = s_level from
+  // the sort's per-piece counts, or h from a counting pass
+  std::vector<std::vector<uint64_t>> cnt;
+  auto levels_from = [&](uint32_t top) {
+    cnt.resize(top + 1);
+    for (int L = (int)top - 1; L >= 0; --L) {
+      cnt[L].assign(1ull << (3 * L), 0);
+      for (uint64_t c = 0; c < cnt[L + 1].size(); ++c) cnt[L][c >> 3] += cnt[L + 1][c];
+    }
+  };
+  auto split_level = [&](uint32_t top) -> uint32_t {
+    for (uint32_t L = 1; L <= top; ++L)
+      if (*std::max_element(cnt[L].begin(), cnt[L].end()) <= chunk) return L;
+    return top;
+  };
+  cnt.assign(s_level + 1, {});
+  cnt[s_level].assign(1ull << (3 * s_level), 0);
+  for (uint64_t k = 0; k < npieces_s; ++k)
+    for (uint32_t c = 0; c < (1u << (3 * s_level)); ++c) cnt[s_level][c] += pst[k][c + 1] - pst[k][c];
+  levels_from(s_level);
+  uint32_t b = split_level(s_level);
+  if (b == s_level && s_level < h &&
+      *std::max_element(cnt[s_level].begin(), cnt[s_level].end()) > chunk) {
+    // level s is not fine enough: count the level-h cells, then sort again
+    HIPCHK(hipMemsetAsync(hist_h, 0, 4ull * nh, s));
+    uint32_t* dcell = d_cell.get<uint32_t>(P);
+    stage = d_stage.get<lod_point>(P);
+    for (uint64_t k = 0; k < npieces; ++k) {
+      const uint64_t m = hci[k].count;
+      HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
+      launch_cells(stage, (uint32_t)m, dcube, h, dcell, hist_h, s);
+      HIPCHK(hipGetLastError());
+    }
     std::vector<uint32_t> hh(nh);
     HIPCHK(hipMemcpyAsync(hh.data(), hist_h, 4ull * nh, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    cnt.assign(h + 1, {});
     cnt[h].assign(hh.begin(), hh.end());
+    levels_from(h);
+    b = split_level(h);
+    sort_pass(b);
   }
-  for (int L = (int)h - 1; L >= 0; --L) {
-    cnt[L].assign(1ull << (3 * L), 0);
-    for (uint64_t c = 0; c < cnt[L + 1].size(); ++c) cnt[L][c >> 3] += cnt[L + 1][c];
-  }
-  uint32_t b = h;
-  for (uint32_t L = 1; L <= h; ++L)
-    if (*std::max_element(cnt[L].begin(), cnt[L].end()) <= chunk) {
-      b = L;
-      break;
-    }
-  if (b > sorted_level) sort_pass(b, false);
   d_sorted.release();
   d_sorted2.release();
   d_sids.release();
