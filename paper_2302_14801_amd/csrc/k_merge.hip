@@ -2,9 +2,12 @@
 // out-of-core pipeline, merged into one octree).
 //
 // The input is cut along the cells of one level b of the common bounding
-// cube.  A cell with more than T points is an inner node of the whole tree at
-// level b, and its subtree depends on its own points only, so it is built as
-// a chunk.  The levels above b are then sampled here from the chunk roots'
+// cube: each piece of the input that passes through the GPU is counted and
+// sorted by cell here (a counting sort; with few cells, counts and ranks in
+// LDS), so that a cell's points are one run per piece.  A cell with more
+// than T points is an inner node of the whole tree at level b, and its
+// subtree depends on its own points only, so it is built as a chunk.  The
+// levels above b are then sampled here from the chunk roots'
 // voxels and the points of the small leaves above them, with the cell
 // average and pick rules of Sec. 4.2:
 //   * every (parent, child octant) pair is a job with a dense grid of the
