@@ -79,7 +79,8 @@ typedef struct {
  *                    floor(65536 * distance) from an exact integer square
  *                    root.  Slower than the other modes (a pass per level
  *                    after the average build); scratch of about 32 B per
- *                    voxel plus 384 KB per node of the widest level.
+ *                    voxel plus 384 KB per inner node of the widest
+ *                    level (at most n / (T + 1)).
  * Pick modes copy the winner's R, G, B, A and record its input index. */
 typedef enum { LOD_AVERAGE = 0, LOD_PICK_FIRST = 1, LOD_PICK_RANDOM = 2, LOD_WEIGHTED = 3 } lod_sampling;
 

@@ -44,11 +44,15 @@ constexpr int kWSplit = 16;  // workgroups per node in the bitmap and colour pas
 constexpr uint32_t kWWords = 1u << 15;  // 64-bit words of a node's 2^21-cell bitmap
 
 // The kernels of one level run over that level's nodes only: `ln` lists the
-// nodes of the level (of all trees of the call), and a node's bitmap slot is
-// its position in the list.
-__global__ void __launch_bounds__(256) k_wslots(const uint32_t* __restrict__ ln, uint32_t cnt, uint32_t* wslot) {
+// nodes of the level (of all trees of the call).  Its inner nodes get the
+// bitmap slots 0, 1, ... (in any order): a tree has at most n / (T + 1)
+// inner nodes on one level, each holding more than T points.
+__global__ void __launch_bounds__(256) k_wslots(Nodes nodes, const uint32_t* __restrict__ ln, uint32_t cnt,
+                                                uint32_t* wslot, uint32_t* slot_ctr) {
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i < cnt) wslot[ln[i]] = i;
+  if (i >= cnt) return;
+  const uint32_t n = ln[i];
+  if (!nodes.is_leaf[n]) wslot[n] = atomicAdd(slot_ctr, 1u);
 }
 
 // The bitmap words of the inner nodes in ln (set = true) or their reset
@@ -354,19 +358,20 @@ hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uin
                            const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
                            uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg,
                            unsigned long long* acc, uint32_t* blocks, uint32_t* nblocks, uint32_t* h_nblocks,
-                           hipStream_t s) {
+                           uint32_t* slot_ctr, hipStream_t s) {
   for (int L = (int)deepest - 1; L >= 0; --L) {
     const uint32_t l = (uint32_t)L;
     const uint32_t* pa = lnodes + loff[l];       // the parents' level
     const uint32_t* ch = lnodes + loff[l + 1];   // the children's level
     const uint32_t na = (uint32_t)(loff[l + 1] - loff[l]), nch = (uint32_t)(loff[l + 2] - loff[l + 1]);
     if (!na || !nch) continue;
-    hipLaunchKernelGGL(k_wslots, dim3((na + 255) / 256), dim3(256), 0, s, pa, na, wslot);
+    hipError_t e = hipMemsetAsync(slot_ctr, 0, sizeof(uint32_t), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wslots, dim3((na + 255) / 256), dim3(256), 0, s, nodes, pa, na, wslot, slot_ctr);
     hipLaunchKernelGGL(k_wbits, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, (const uint64_t*)vox,
                        (const uint32_t*)wslot, bits, wpre, bseg, true);
     // the non-empty blocks only (most micro-buckets of a surface are empty)
-    hipError_t e = hipMemsetAsync(nblocks, 0, sizeof(uint32_t), s);
-    if (e != hipSuccess) return e;
+    if ((e = hipMemsetAsync(nblocks, 0, sizeof(uint32_t), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_wblocks, dim3((64 * nch + 255) / 256), dim3(256), 0, s, nodes, ch, nch, (const ItemDesc*)desc,
                        (const uint2*)bseg, trees, blocks, nblocks);
     if ((e = hipMemcpyAsync(h_nblocks, nblocks, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;

@@ -73,9 +73,10 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
 // Neighbourhood-weighted colours of all inner voxels (after the average
 // build), level by level.  lnodes: the node indices of the call grouped by
 // level, level L at [loff[L], loff[L + 1]) (loff: host array of deepest + 2
-// entries).  Occupancy bitmaps of a level's nodes: one slot of
-// weighted_bitmap_words() 64-bit words and as many u32 word prefixes per node
-// of the level, zero on entry and on return; wslot: one u32 per node; acc: 4
+// entries).  Occupancy bitmaps of a level's inner nodes: one slot of
+// weighted_bitmap_words() 64-bit words and as many u32 word prefixes per
+// inner node of the level (at most the sum over trees of n / (T + 1)), zero
+// on entry and on return; wslot: one u32 per node; slot_ctr: one u32; acc: 4
 // zeroed u64 per voxel; bseg: 64 zeroed uint2 per node; blocks: 64 u32 per
 // node, nblocks one u32 (device) and h_nblocks one u32 (pinned host), the
 // list of a level's non-empty blocks and its length (the host reads it
@@ -84,7 +85,7 @@ hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uin
                            const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
                            uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg,
                            unsigned long long* acc, uint32_t* blocks, uint32_t* nblocks, uint32_t* h_nblocks,
-                           hipStream_t s);
+                           uint32_t* slot_ctr, hipStream_t s);
 uint64_t weighted_bitmap_words();
 // Full-precision records (input coordinates of the accepted sample, voxel
 // colour) of the vtotal voxels of a call.

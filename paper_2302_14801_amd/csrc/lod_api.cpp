@@ -611,8 +611,10 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   if (pl.weighted && vtotal) {
     if (vtotal > 0xffffffffull) fail(LOD_ERR_INVALID, "weighted sampling handles at most 2^32 - 1 voxels per call");
     // the nodes of the call grouped by level (each tree's levels are
-    // contiguous in the node table); one occupancy bitmap slot per node of
-    // the widest level
+    // contiguous in the node table); one occupancy bitmap slot per inner node
+    // of a level: at most the widest level's node count, and at most
+    // n / (T + 1) per tree (inner nodes of one level are disjoint and hold
+    // more than T points each)
     uint32_t deepest = 0;
     for (uint32_t c = 0; c < nc; ++c) deepest = std::max(deepest, hti[c].deepest);
     uint32_t* hl = w.h_wlist.get<uint32_t>(num_nodes);
@@ -628,6 +630,9 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
       slots = std::max<uint64_t>(slots, k - loff[L]);
     }
     loff[deepest + 1] = k;
+    uint64_t inner_bound = 0;
+    for (uint32_t c = 0; c < nc; ++c) inner_bound += hci[c].count / ((uint64_t)prm.leaf_cap + 1);
+    slots = std::max<uint64_t>(1, std::min(slots, inner_bound));
     const uint64_t words = slots * weighted_bitmap_words();
     uint32_t* wlist = w.wlist.get<uint32_t>(dev, num_nodes);
     uint32_t* wslot = w.wslot.get<uint32_t>(dev, num_nodes);
@@ -635,13 +640,13 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     uint32_t* wpre = w.wpre.get<uint32_t>(dev, words);
     unsigned long long* wacc = w.wacc.get<unsigned long long>(dev, 4 * vtotal);
     uint2* wseg = w.wseg.get<uint2>(dev, 64ull * num_nodes);
-    uint32_t* wblk = w.wblk.get<uint32_t>(dev, 64ull * num_nodes + 1);
+    uint32_t* wblk = w.wblk.get<uint32_t>(dev, 64ull * num_nodes + 2);
     HIPCHK(hipMemcpyAsync(wlist, hl, sizeof(uint32_t) * k, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(wbits, 0, 8 * words, s));
     HIPCHK(hipMemsetAsync(wacc, 0, 32 * vtotal, s));
     HIPCHK(hipMemsetAsync(wseg, 0, 64ull * sizeof(uint2) * num_nodes, s));
     HIPCHK(launch_weighted(nd, wlist, loff, deepest, tinfo, cube, desc, Y, vox, wslot, wbits, wpre, wseg, wacc,
-                           wblk + 1, wblk, w.h_wblk.get<uint32_t>(1), s));
+                           wblk + 2, wblk, w.h_wblk.get<uint32_t>(1), wblk + 1, s));
   }
   lod_point* vpts = nullptr;
   if (pl.full && !(x && x->ids_only)) {
