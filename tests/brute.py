@@ -59,6 +59,14 @@ def quantize(pts):
     return np.minimum(np.floor(v), 2097151.0).astype(np.uint32)
 
 
+def quantize_in_cube(pts, lo, side):
+    """(n, 3) uint32 grid coordinates in a given cube (minimum corner lo, edge
+    side): the same IEEE double definition evaluated by numpy, vectorised."""
+    xyz = np.stack([pts["x"], pts["y"], pts["z"]], axis=1).astype(np.float64)
+    v = (xyz - np.asarray(lo, np.float32).astype(np.float64)) * (2097152.0 / float(side))
+    return np.clip(np.floor(v), 0.0, 2097151.0).astype(np.uint32)
+
+
 def morton(q):
     """Interleave (n, 3) coordinates of 21 bits: bit i of x/y/z -> bit 3i/3i+1/3i+2."""
     q = q.astype(np.uint64)

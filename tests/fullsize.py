@@ -10,6 +10,7 @@ Two parts:
     cube) and the subtrees are compared bit for bit."""
 from __future__ import annotations
 
+import os
 import time
 
 import numpy as np
@@ -21,7 +22,14 @@ CHUNK = 50_000_000  # rows per step of the whole-cloud passes (bounded host memo
 
 
 def log(msg):
-    print(f"[full-size] {time.strftime('%H:%M:%S')} {msg}", flush=True)
+    """Progress line on stdout and, if LOD_PROGRESS_FILE names a file, appended
+    there too (pytest holds a test's stdout until the test ends)."""
+    line = f"[full-size] {time.strftime('%H:%M:%S')} {msg}"
+    print(line, flush=True)
+    path = os.environ.get("LOD_PROGRESS_FILE")
+    if path:
+        with open(path, "a") as f:
+            f.write(line + "\n")
 
 
 def multiset_hash(rows: np.ndarray) -> tuple:

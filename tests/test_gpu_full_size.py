@@ -1,11 +1,16 @@
 """GPU parity at the benchmark's full size: the 100M-point aerial plain build
-(T = 50 000, 128^3, colour-filtered), built exactly as bench.py builds it, and
-checked by the properties and sampled oracle subtrees of fullsize.py."""
+(T = 50 000, 128^3, colour-filtered), built exactly as bench.py builds it and
+compared whole with the oracle's tree (node table, every leaf's point
+multiset, every voxel), plus the properties and sampled oracle subtrees of
+fullsize.py; and whole-tree parity at 5M points, where the build uses the
+plan of large inputs (4 + 4 levels in the two partition passes)."""
 from __future__ import annotations
 
 import pytest
 
+import canon
 import fullsize
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -15,6 +20,7 @@ T = 50_000
 ML = 12
 
 
+@pytest.mark.timeout(900)
 def test_aerial_100m_bench_configuration():
     import torch
 
@@ -33,8 +39,35 @@ def test_aerial_100m_bench_configuration():
     del dev
     fullsize.log(f"{g['num_nodes']} nodes, {g['num_voxels']} voxels")
     fullsize.check_build(g, pts, T, ML)
+    fullsize.log("oracle build of the whole cloud (one core)")
+    o = oracle.build(pts, leaf_cap=T, max_level=ML)
+    fullsize.log("comparing the whole tree")
+    canon.compare_trees(g, o, pts)
+    fullsize.log("the whole 100M tree equals the oracle's")
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("sampling,T", [(0, 50_000), (1, 50_000), (2, 50_000), (3, 50_000), (0, 2_000)])
+def test_aerial_5m_whole_tree(sampling, T):
+    """5M points take the large-input plan (4 + 4 levels, several chunks per
+    root cell); T = 2 000 adds refinement partitions below level 8."""
+    import numpy as np
+    import torch
+
+    import paper_2302_14801_amd as lod
+
+    n = 5_000_000
+    print(f"case aerial n={n} T={T} sampling={sampling}", flush=True)
+    pts = synth.aerial(n, seed=17)
+    dev = torch.from_numpy(pts.view(np.uint8).reshape(-1).copy()).to("cuda:0")
+    t = lod.lod_build(dev, leaf_cap=T, max_level=ML, sampling=sampling, seed=31)
+    g = t.to_host()
+    t.free()
+    o = oracle.build(pts, leaf_cap=T, max_level=ML, sampling=sampling, seed=31)
+    canon.compare_trees(g, o, pts)
+
+
+@pytest.mark.timeout(600)
 def test_aerial_20m_weighted_and_full_precision():
     """The neighbourhood-weighted average on a 20M-point aerial cloud (T =
     50 000): same cells as the average build, colours checked on sampled
@@ -72,6 +105,7 @@ def test_aerial_20m_weighted_and_full_precision():
     fullsize.check_build(g, pts, T, ML, subtree_picks=2, leaf_sample=2000, sampling=3)
 
 
+@pytest.mark.timeout(900)
 def test_aerial_100m_chunked_equals_in_core():
     """The 100M-point aerial cloud built from host memory in chunks of 10M
     points (bench.py's chunked run) equals the in-core build: the same node
@@ -113,6 +147,7 @@ def test_aerial_100m_chunked_equals_in_core():
     fullsize.check_build(g, pts, T, ML)
 
 
+@pytest.mark.timeout(600)
 def test_aerial_20m_chunked_weighted_full_precision():
     """The weighted average with full-precision records on a 20M-point aerial
     cloud, built from host memory in 2M-point chunks, equals the in-core

@@ -170,18 +170,22 @@ def test_invalid_params_rejected(lod):
 
 
 def test_tuning_and_repeat_do_not_change_results(lod):
+    """Every plan (levels of the two partition passes, points per partition
+    work item) gives the oracle's tree, and a repeated build the same one."""
     p = synth.terrain(300_000, seed=8)
+    o = oracle.build(p, leaf_cap=3000, max_level=12)
     base = gpu_tree(lod, p, leaf_cap=3000, max_level=12)
+    canon.compare_trees(base, o, p)
     again = gpu_tree(lod, p, leaf_cap=3000, max_level=12)
     for k in ("level", "key", "npoints", "count", "voxels"):
         assert np.array_equal(base[k], again[k])
-    for t0, t1, ch in ((1, 1, 0), (2, 4, 1), (4, 2, 50_000), (3, 3, 7000), (4, 4, 0)):
+    for t0, t1, ch in ((1, 1, 0), (2, 4, 1), (4, 2, 50_000), (3, 3, 7000), (4, 4, 0), (4, 4, 65_000)):
+        print(f"plan {t0} {t1} {ch}", flush=True)
         params = lod.make_params(leaf_cap=3000, max_level=12, tune_levels0=t0, tune_levels1=t1, tune_chunk=ch)
         t = lod.lod_build(to_dev(p), params=params)
         h = t.to_host()
         t.free()
-        for k in ("level", "key", "npoints", "count", "first_child", "voxels"):
-            assert np.array_equal(base[k], h[k]), (t0, t1, ch, k)
+        canon.compare_trees(h, o, p)
 
 
 def test_input_order_invariance(lod):

@@ -426,3 +426,146 @@ def test_child_voxel_contribution_at_most_eight_per_cell():
     # the root's voxels are at most the number of occupied level-7 cells
     q = brute.demorton(oracle.keys(p))
     assert len(root) == len({tuple(c) for c in (q >> np.uint32(14)).tolist()})
+
+
+# --------------------------------------------------------------- builds in a given cube
+#
+# lod_oracle_build_in_cube / lod_oracle_keys_in_cube check every GPU build too
+# large for the oracle to rebuild whole: the subtree of a node is rebuilt from
+# the node's own points in the whole cloud's cube.  Below a node, everything
+# depends on that node's points alone (Sec. 4.1: a node's split depends on its
+# own count; Sec. 4.2: its voxels on its children's samples).
+
+def _shifted_cube(p, grow: float, shift):
+    """A cube that contains every point but is not the cloud's own: edge
+    `grow` times the cloud's side, minimum corner moved down by `shift`
+    (fractions of the side) -- a float32 corner, as the API takes it."""
+    lo, _, side, _ = oracle.cube(p)
+    lo2 = (lo.astype(np.float64) - np.asarray(shift) * side).astype(np.float32)
+    side2 = side * grow + float(np.max(lo.astype(np.float64) - lo2.astype(np.float64)))
+    return lo2, side2
+
+
+def _teapot_in_stadium():
+    a = synth.uniform_cloud(400, 1, lo=(0, 0, 0), hi=(100, 100, 100))
+    b = synth.uniform_cloud(1600, 2, lo=(40, 40, 40), hi=(40.01, 40.01, 40.01))
+    return np.concatenate([a, b])
+
+
+IN_CUBE_CLOUDS = {
+    "uniform": (lambda: synth.uniform_cloud(3000, 31, lo=(-3, 7, 1), hi=(5, 9, 2)), 25, 12),
+    "teapot_in_stadium": (_teapot_in_stadium, 20, 14),
+    "terrain": (lambda: synth.terrain(6000, seed=13), 60, 12),
+    "aerial": (lambda: synth.aerial(6000, seed=14), 40, 12),
+}
+
+
+def test_keys_in_cube_with_the_cloud_cube_equal_keys():
+    for make, _, _ in IN_CUBE_CLOUDS.values():
+        p = make()
+        lo, _, side, _ = oracle.cube(p)
+        assert np.array_equal(oracle.keys_in_cube(p, lo, side), oracle.keys(p))
+
+
+@pytest.mark.parametrize("grow,shift", [(1.0, (0.0, 0.0, 0.0)), (1.7, (0.1, 0.25, 0.0)), (3.0, (0.5, 0.5, 0.5))])
+def test_keys_in_cube_match_vectorised_and_exact_quantization(grow, shift):
+    p = synth.uniform_cloud(2000, 41, lo=(-50, 3, 1e3), hi=(80, 40, 1.02e3))
+    lo, side = _shifted_cube(p, grow, shift)
+    k = oracle.keys_in_cube(p, lo, side)
+    q = brute.quantize_in_cube(p, lo, side)
+    assert np.array_equal(k, brute.morton(q))
+    # and within one cell of the exact rational value (rounding of the two
+    # double operations), for a sample of the points
+    for i in range(0, len(p), 37):
+        for a, ax in enumerate("xyz"):
+            exact = (Fraction(float(p[ax][i])) - Fraction(float(lo[a]))) * (1 << 21) / Fraction(side)
+            assert abs(int(q[i, a]) - min(int(exact), (1 << 21) - 1)) <= 1
+
+
+@pytest.mark.parametrize("sampling", [oracle.AVERAGE, oracle.FIRST, oracle.RANDOM, oracle.WEIGHTED])
+def test_build_in_the_cloud_cube_equals_build(sampling):
+    for make, T, ml in IN_CUBE_CLOUDS.values():
+        p = make()
+        lo, _, side, _ = oracle.cube(p)
+        a = oracle.build(p, leaf_cap=T, max_level=ml, sampling=sampling, seed=5)
+        b = oracle.build(p, leaf_cap=T, max_level=ml, sampling=sampling, seed=5, cube_lo=lo, cube_side=side)
+        for f in ("level", "key", "is_leaf", "npoints", "child_mask", "first_child", "count", "offset",
+                  "point_ids", "voxels", "aabb_min", "aabb_max"):
+            assert np.array_equal(a[f], b[f]), f
+        assert a["side"] == b["side"] and a["num_voxels"] == b["num_voxels"]
+
+
+@pytest.mark.parametrize("grow,shift", [(1.5, (0.2, 0.0, 0.3)), (2.0, (0.0, 0.4, 0.1))])
+def test_build_in_a_larger_cube_matches_merge_procedure_and_recursion(grow, shift):
+    """In a cube that is not the cloud's own, the tree is the paper's merge
+    procedure on the keys quantized in that cube, the voxels are the
+    dict recursion and the closed forms on the same keys."""
+    p = synth.uniform_cloud(1500, 43)
+    lo, side = _shifted_cube(p, grow, shift)
+    T, ml = 12, 12
+    t = oracle.build(p, leaf_cap=T, max_level=ml, cube_lo=lo, cube_side=side)
+    q = brute.quantize_in_cube(p, lo, side)
+    k = brute.morton(q)
+    assert t["side"] == side and np.array_equal(t["aabb_min"], lo)
+    assert brute.tree_nodes(t) == brute.paper_merge_tree(k, T, ml)
+    # membership by the in-cube keys
+    seen = np.zeros(len(p), np.int64)
+    for i in np.nonzero(t["is_leaf"])[0]:
+        ids = t["point_ids"][t["offset"][i]:t["offset"][i] + t["count"][i]]
+        seen[ids] += 1
+        assert np.all(brute.prefix(k[ids], int(t["level"][i])) == t["key"][i])
+    assert np.all(seen == 1)
+    rec = brute.recursive_voxels(p, q, k, brute.tree_nodes(t), T, ml)
+    for i in np.nonzero(t["is_leaf"] == 0)[0]:
+        L, key = int(t["level"][i]), int(t["key"][i])
+        got = brute.tree_voxels(t, i)
+        assert got == rec[(L, key)]
+        assert set(got) == brute.closed_form_cells(q, k, L, key)
+    f = oracle.build(p, leaf_cap=T, max_level=ml, sampling=oracle.FIRST, cube_lo=lo, cube_side=side)
+    for i in np.nonzero(f["is_leaf"] == 0)[0]:
+        L, key = int(f["level"][i]), int(f["key"][i])
+        got = {c: v[4] for c, v in brute.tree_voxels(f, i).items()}
+        assert got == brute.closed_form_pick(p, q, k, L, key, oracle.FIRST, 0)
+
+
+@pytest.mark.parametrize("sampling", [oracle.AVERAGE, oracle.FIRST, oracle.WEIGHTED])
+@pytest.mark.parametrize("cloud", sorted(IN_CUBE_CLOUDS))
+def test_subtree_rebuilt_from_its_points_equals_the_whole_build(cloud, sampling):
+    """For every inner node X of the whole-cloud build, the build of X's points
+    alone in the whole cloud's cube holds X (at the same level and key) with
+    the same subtree: node fields, leaf members (mapped back to the cloud's
+    indices), voxels, and the first-come picks (mapped back; the smallest
+    local index is the smallest cloud index since the selection keeps input
+    order).  RANDOM picks hash the point index, which a sub-build renumbers,
+    so they are not compared here."""
+    import canon
+
+    make, T, ml = IN_CUBE_CLOUDS[cloud]
+    p = make()
+    lo, _, side, _ = oracle.cube(p)
+    whole = oracle.build(p, leaf_cap=T, max_level=ml, sampling=sampling)
+    keys = brute.morton(brute.quantize_in_cube(p, lo, side))
+    inner = np.nonzero(whole["is_leaf"] == 0)[0]
+    assert len(inner) >= 5
+    for x in inner[1:]:
+        L, kx = int(whole["level"][x]), np.uint64(int(whole["key"][x]))
+        s = np.nonzero(brute.prefix(keys, L) == kx)[0]
+        assert len(s) == whole["npoints"][x]
+        o = oracle.build(np.ascontiguousarray(p[s]), leaf_cap=T, max_level=ml, sampling=sampling,
+                         cube_lo=lo, cube_side=side)
+        ox = np.nonzero((o["level"] == L) & (o["key"] == kx))[0]
+        assert len(ox) == 1
+        gi, oi = canon.subtree_indices(whole, int(x)), canon.subtree_indices(o, int(ox[0]))
+        assert len(gi) == len(oi)
+        for f in ("level", "key", "is_leaf", "npoints", "child_mask", "count"):
+            assert np.array_equal(whole[f][gi], o[f][oi]), (cloud, int(x), f)
+        for a, b in zip(gi, oi):
+            ga, gc = int(whole["offset"][a]), int(whole["count"][a])
+            ob, oc = int(o["offset"][b]), int(o["count"][b])
+            if whole["is_leaf"][a]:
+                assert np.array_equal(np.sort(whole["point_ids"][ga:ga + gc]),
+                                      np.sort(s[o["point_ids"][ob:ob + oc]]))
+            else:
+                assert np.array_equal(whole["voxels"][ga:ga + gc], o["voxels"][ob:ob + oc]), (cloud, int(x), a)
+                if sampling == oracle.FIRST:
+                    assert np.array_equal(whole["voxel_ids"][ga:ga + gc], s[o["voxel_ids"][ob:ob + oc]])
