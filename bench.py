@@ -136,7 +136,7 @@ def run_batched(lod, torch, num_chunks: int, reps: int, params):
 
     from paper_2302_14801_amd import autotune
     t0 = time.perf_counter()
-    tuned, tune_info = autotune.tune_batch(dev, offs, params, sample_chunks=64, reps=2, stream=stream)
+    tuned, tune_info = autotune.tune_batch(dev, offs, params, stream=stream)
     tune_info["tuning_s"] = round(time.perf_counter() - t0, 3)
     print(f"[bench] batched: tuned plan {tune_info['plan']}", file=sys.stderr, flush=True)
     t_default, _ = timed(params)

@@ -17,8 +17,12 @@
  *     never frees or keeps them beyond the call (lod_submit: until lod_poll
  *     returns something other than LOD_PENDING).
  *   - `hip_stream` is a hipStream_t (NULL = the default stream).  The build
- *     runs on that stream; the call synchronises it a few times internally to
- *     size its outputs, and returns once the tree is complete.
+ *     runs on that stream: the whole build is enqueued with capacities fixed
+ *     beforehand, the stream is synchronised once at the end, and the call
+ *     returns once the tree is complete.  If a capacity estimated from the
+ *     input sizes (refinement grids, coarse voxel lists, voxel output) turns
+ *     out too small, the device flags it and the build is repeated with the
+ *     capacities it reported (the result never depends on it).
  *   - Results never depend on tuning (block sizes, grid depths, chunking).
  */
 #ifndef LOD_H
@@ -95,7 +99,16 @@ enum {
    * (the arg-min over all points of the subtree that fall in the cell) and
    * keep their (weighted) average colour.  voxel_ids then holds the accepted sample's
    * index in every mode. */
-  LOD_FLAG_FULL_PRECISION = 4
+  LOD_FLAG_FULL_PRECISION = 4,
+  /* lod_build_batch records the launches of a batch of several clouds into a
+   * HIP graph and runs it as one graph launch (weighted sampling, and builds
+   * with LOD_FLAG_TIMING, enqueue their launches one by one).  With this flag
+   * the launches are enqueued one by one instead; the result is the same. */
+  LOD_FLAG_NO_GRAPH = 8,
+  /* lod_build_batch / lod_build with the tune_* fields 0: use the plan that
+   * lod_tune_batch chooses for a workload of this class (tuning it on this
+   * call's input the first time the class is seen in the process). */
+  LOD_FLAG_AUTOTUNE = 16
 };
 
 typedef struct {
@@ -164,6 +177,29 @@ lod_status lod_build(const lod_point* d_points, uint64_t n, const lod_params* p,
  * num_chunks handles, filled on success.  Result i equals lod_build on chunk i. */
 lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets, uint32_t num_chunks,
                            const lod_params* p, void* hip_stream, lod_tree** out);
+
+/* Plan autotuner.  A build's plan -- the tune_* fields: levels sorted by the
+ * first and second partition pass (the resolution of the root and the
+ * extended counting grids, Sec. 4.1.1 and 4.1.5) and points per partition
+ * work item -- changes only how the work is cut, never the result.
+ * lod_tune_batch times lod_build_batch on the first min(64, num_chunks)
+ * chunks of d_points (device, borrowed; offsets as for lod_build_batch) with
+ * 17 candidate plans, one warm-up and the median of two runs each, and
+ * writes p with the fastest plan to *tuned.  The choice is cached for the
+ * process per workload class (chunk count, median and total chunk size as
+ * powers of two, sampling, ids and full-precision flags, T, max_level); a
+ * cached class returns at once.  If p already sets a tune_* field, *tuned =
+ * p.  info (may be NULL) receives whether the plan came from the cache, the
+ * sample, the plan and the sample's times with it and with the automatic
+ * plan.  Errors: those of lod_build_batch. */
+typedef struct {
+  uint32_t cached;
+  uint32_t sample_chunks;
+  uint32_t levels0, levels1, chunk; /* the chosen plan (0 = automatic) */
+  float best_ms, default_ms;        /* sample build times: chosen plan, automatic plan */
+} lod_tune_info;
+lod_status lod_tune_batch(const lod_point* d_points, const uint64_t* h_offsets, uint32_t num_chunks,
+                          const lod_params* p, void* hip_stream, lod_params* tuned, lod_tune_info* info);
 
 /* Chunked (out-of-core) build (Sec. 7: a bottom-up out-of-core pipeline cuts
  * the input into chunks of about 10M points, builds each on the GPU and

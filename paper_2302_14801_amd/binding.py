@@ -21,6 +21,8 @@ LOD_AVERAGE, LOD_PICK_FIRST, LOD_PICK_RANDOM, LOD_WEIGHTED = 0, 1, 2, 3
 LOD_FLAG_POINT_IDS = 1
 LOD_FLAG_TIMING = 2
 LOD_FLAG_FULL_PRECISION = 4
+LOD_FLAG_NO_GRAPH = 8
+LOD_FLAG_AUTOTUNE = 16
 
 
 class LodError(RuntimeError):
@@ -47,13 +49,20 @@ class lod_tree_view(ctypes.Structure):
                 ("voxels", ctypes.c_void_p), ("voxel_ids", ctypes.c_void_p), ("voxel_points", ctypes.c_void_p)]
 
 
+class lod_tune_info(ctypes.Structure):
+    _fields_ = [("cached", ctypes.c_uint32), ("sample_chunks", ctypes.c_uint32), ("levels0", ctypes.c_uint32),
+                ("levels1", ctypes.c_uint32), ("chunk", ctypes.c_uint32), ("best_ms", ctypes.c_float),
+                ("default_ms", ctypes.c_float)]
+
+
 class lod_timings(ctypes.Structure):
     _fields_ = [(name, ctypes.c_float) for name in
                 ("bbox", "count0", "offsets0", "scatter0", "count1", "offsets1", "scatter1", "tree",
                  "leaf_voxels", "levels", "total")]
 
 
-EXPORTED = ["lod_params_default", "lod_build", "lod_build_batch", "lod_tree_view_get", "lod_tree_free",
+EXPORTED = ["lod_params_default", "lod_build", "lod_build_batch", "lod_tune_batch",
+            "lod_tree_view_get", "lod_tree_free",
             "lod_tree_timings",
             "lod_server_create", "lod_submit", "lod_poll", "lod_server_destroy", "lod_status_str",
             "lod_last_error"]
@@ -83,6 +92,8 @@ def load_library():
     lib.lod_build.restype = ctypes.c_int
     lib.lod_build_batch.argtypes = [vp, P(u64), u32, P(lod_params), vp, P(vp)]
     lib.lod_build_batch.restype = ctypes.c_int
+    lib.lod_tune_batch.argtypes = [vp, P(u64), u32, P(lod_params), vp, P(lod_params), P(lod_tune_info)]
+    lib.lod_tune_batch.restype = ctypes.c_int
     lib.lod_build_chunked.argtypes = [vp, u64, P(lod_params), u64, vp, P(vp)]
     lib.lod_build_chunked.restype = ctypes.c_int
     lib.lod_tree_view_get.argtypes = [vp, P(lod_tree_view)]
@@ -175,22 +186,26 @@ class Tree:
 
     def to_host(self) -> dict:
         """Copy the tree to host numpy arrays (same keys as the oracle's result)."""
-        v = self.view()
-        nn, nv, np_ = v.num_nodes, v.num_voxels, v.num_points
-        out = {
-            "aabb_min": np.array(v.aabb_min[:], np.float32), "aabb_max": np.array(v.aabb_max[:], np.float32),
-            "side": v.cube_side, "num_nodes": nn, "num_points": np_, "num_voxels": nv,
-            "level": _d2h(v.node_level, nn, np.uint8), "is_leaf": _d2h(v.node_is_leaf, nn, np.uint8),
-            "child_mask": _d2h(v.node_child_mask, nn, np.uint8), "key": _d2h(v.node_key, nn, np.uint64),
-            "npoints": _d2h(v.node_npoints, nn, np.uint32), "count": _d2h(v.node_count, nn, np.uint32),
-            "first_child": _d2h(v.node_first_child, nn, np.uint32), "offset": _d2h(v.node_offset, nn, np.uint64),
-            "points": _d2h(v.points, np_ * 16, np.uint8).reshape(-1, 16),
-            "point_ids": _d2h(v.point_ids, np_, np.uint32) if v.point_ids else None,
-            "voxels": _d2h(v.voxels, nv * 8, np.uint8).reshape(-1, 8),
-            "voxel_ids": _d2h(v.voxel_ids, nv, np.uint32) if v.voxel_ids else None,
-            "voxel_points": _d2h(v.voxel_points, nv * 16, np.uint8).reshape(-1, 16) if v.voxel_points else None,
-        }
-        return out
+        return view_to_host(self.view())
+
+
+def view_to_host(v: lod_tree_view) -> dict:
+    """Copy the tree a view describes to host numpy arrays."""
+    nn, nv, np_ = v.num_nodes, v.num_voxels, v.num_points
+    out = {
+        "aabb_min": np.array(v.aabb_min[:], np.float32), "aabb_max": np.array(v.aabb_max[:], np.float32),
+        "side": v.cube_side, "num_nodes": nn, "num_points": np_, "num_voxels": nv,
+        "level": _d2h(v.node_level, nn, np.uint8), "is_leaf": _d2h(v.node_is_leaf, nn, np.uint8),
+        "child_mask": _d2h(v.node_child_mask, nn, np.uint8), "key": _d2h(v.node_key, nn, np.uint64),
+        "npoints": _d2h(v.node_npoints, nn, np.uint32), "count": _d2h(v.node_count, nn, np.uint32),
+        "first_child": _d2h(v.node_first_child, nn, np.uint32), "offset": _d2h(v.node_offset, nn, np.uint64),
+        "points": _d2h(v.points, np_ * 16, np.uint8).reshape(-1, 16),
+        "point_ids": _d2h(v.point_ids, np_, np.uint32) if v.point_ids else None,
+        "voxels": _d2h(v.voxels, nv * 8, np.uint8).reshape(-1, 8),
+        "voxel_ids": _d2h(v.voxel_ids, nv, np.uint32) if v.voxel_ids else None,
+        "voxel_points": _d2h(v.voxel_points, nv * 16, np.uint8).reshape(-1, 16) if v.voxel_points else None,
+    }
+    return out
 
 
 def _hip_lib():
@@ -229,6 +244,18 @@ def lod_build(points, leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0
     _check(load_library().lod_build(ctypes.c_void_p(points.data_ptr()), n, ctypes.byref(p),
                                     _stream_handle(stream), ctypes.byref(out)))
     return Tree(out.value)
+
+
+def lod_tune_batch(points, offsets, params: lod_params, stream=None):
+    """(tuned lod_params, info dict) for batches like (points, offsets)."""
+    _check_points(points)
+    offs = np.ascontiguousarray(np.asarray(offsets, np.uint64))
+    tuned, info = lod_params(), lod_tune_info()
+    _check(load_library().lod_tune_batch(ctypes.c_void_p(points.data_ptr()),
+                                         offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(offs) - 1,
+                                         ctypes.byref(params), _stream_handle(stream), ctypes.byref(tuned),
+                                         ctypes.byref(info)))
+    return tuned, {name: getattr(info, name) for name, _ in lod_tune_info._fields_}
 
 
 def lod_build_batch(points, offsets, leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0,

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "liblod.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["k_split.hip", "k_tree.hip", "k_voxel.hip", "k_weighted.hip", "k_merge.hip", "lod_api.cpp", "lod_server.cpp",
-           "lod_chunked.cpp"]
+           "lod_chunked.cpp", "lod_tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -276,13 +276,36 @@ struct TreeState {
   uint32_t level_end[23];
 };
 
-// Build-wide state of the tree and voxel passes.
+// Build-wide state of a build (device memory), zeroed by a kernel at the
+// start.  The whole build is enqueued without reading anything back: counts
+// that size later work live here, launches are sized by capacities fixed
+// beforehand, and a capacity that turns out too small sets a flag that makes
+// every later kernel of the build return at once; the host reads this state
+// once, after the last kernel, and builds again with the needed capacities.
+enum : uint32_t {
+  kOverNodes = 1,   // a tree exceeded its node region
+  kOverGrids = 2,   // the refinement grids exceeded their pool
+  kOverVoxels = 4,  // the voxels exceeded the output's capacity
+  kOverCoarse = 8,  // the coarse voxel lists of the leaf items exceeded their pool
+  kOverStop = kOverNodes | kOverGrids | kOverCoarse  // flags after which the tree is unusable
+};
 struct BuildState {
   uint32_t nref;         // inner nodes queued for refinement in this round
   uint32_t nlref;        // leaves queued for refinement (all rounds)
-  uint32_t overflow;     // some tree exceeded its node capacity
-  uint32_t pad;
+  uint32_t overflow;     // kOver* flags
+  uint32_t total_nodes;  // nodes of all trees (compact numbering)
   uint64_t coarse_used;  // entries of the coarse-list buffer handed out
+  uint32_t num_grids;    // grid descriptors in use
+  uint32_t need_grids;   // grid descriptors the refinements asked for (in use + refused)
+  uint64_t used_words;   // pool words in use
+  uint64_t need_words;   // pool words the refinements asked for
+  uint64_t vtotal;       // voxels of all trees
+  uint32_t item_next;    // next work item of the leaf kernel's queue
+  uint32_t pad;
 };
+
+__device__ __forceinline__ bool build_stopped(const BuildState* bs) {
+  return (*(volatile const uint32_t*)&bs->overflow & kOverStop) != 0;
+}
 
 }  // namespace lod

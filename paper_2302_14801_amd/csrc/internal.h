@@ -159,3 +159,11 @@ lod_tree* lod_build_chunked_tree(const lod_point* h_points, uint64_t n, const lo
                                  hipStream_t stream);
 // One cloud.
 lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params& p, hipStream_t stream);
+// The plan tuner (lod_tune.cpp): p with its tune_* fields chosen for batches
+// like (offs, n) (kept if p sets any of them); throws LodError.
+lod_params tune_batch(const lod_point* d_points, const uint64_t* offs, uint32_t n, const lod_params& p,
+                      hipStream_t s, lod_tune_info* info);
+// Device bytes a build of clouds of these sizes lays out (scratch and output,
+// with the default estimates; the weighted pass's scratch included): the
+// server admits requests by it.  Throws LodError.
+uint64_t lod_plan_bytes(const uint64_t* sizes, uint32_t n, const lod_params& p);

@@ -13,6 +13,8 @@
 // contiguous runs instead of single 16-byte writes (global atomics and
 // scattered 16-byte stores both run at ~25-40 G ops/s on this part, far below
 // what the 8 TB/s memory can stream).
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 #include "scan.h"
@@ -208,41 +210,60 @@ __global__ void k_chunk_fill(const Segment* __restrict__ segs, const uint32_t* n
   }
 }
 
-// Count one chunk into an LDS histogram of B = 8^E cells and write the row.
+// Count one chunk into an LDS histogram of B = 8^E cells and write the row
+// (each workgroup takes chunks blockIdx.x, blockIdx.x + gridDim.x, ... of the
+// device-side chunk count).  The cell of a point is either computed from its
+// record, or (DIG) read as the 2-byte digit the previous pass's insert wrote
+// beside it.
 constexpr int kCountWG = 512;
-template <int E>
-__global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict__ pts, const Cube* cube,
+template <int E, bool DIG>
+__global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict__ pts,
+                                                         const uint16_t* __restrict__ dig, const Cube* cube,
                                                          const Segment* __restrict__ segs,
                                                          const Chunk* __restrict__ chunks,
                                                          const uint32_t* nchunk_ptr, uint32_t* __restrict__ hist) {
   constexpr uint32_t B = 1u << (3 * E);
   __shared__ uint32_t h[B];
-  const uint32_t c = blockIdx.x;
-  if (c >= *nchunk_ptr) return;
+  const uint32_t nchunk = *nchunk_ptr;
+  for (uint32_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
   const Chunk ch = chunks[c];
   const Segment sg = segs[ch.seg];
-  const CubeD cd = load_cube(cube + sg.cloud);
-  const uint32_t lvl_bit = kKeyLevels - (sg.level + E);  // the E levels below the segment's level
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) h[j] = 0;
   lds_barrier();
-  const uint4* p = pts + ch.start;
   uint32_t i = threadIdx.x;
-  for (; i + 7 * kCountWG < ch.count; i += 8 * kCountWG) {
-    uint4 v[8];
+  if (DIG) {
+    const uint16_t* d = dig + ch.start;
+    for (; i + 15 * kCountWG < ch.count; i += 16 * kCountWG) {
+      uint32_t v[16];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = p[i + k * kCountWG];
+      for (int k = 0; k < 16; ++k) v[k] = d[i + k * kCountWG];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      atomicAdd(&h[point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E)],
-                1u);
-  }
-  for (; i < ch.count; i += kCountWG) {
-    uint4 v = p[i];
-    atomicAdd(&h[point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, lvl_bit, E)], 1u);
+      for (int k = 0; k < 16; ++k) atomicAdd(&h[v[k]], 1u);
+    }
+    for (; i < ch.count; i += kCountWG) atomicAdd(&h[d[i]], 1u);
+  } else {
+    const CubeD cd = load_cube(cube + sg.cloud);
+    const uint32_t lvl_bit = kKeyLevels - (sg.level + E);  // the E levels below the segment's level
+    const uint4* p = pts + ch.start;
+    for (; i + 7 * kCountWG < ch.count; i += 8 * kCountWG) {
+      uint4 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = p[i + k * kCountWG];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        atomicAdd(&h[point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E)],
+                  1u);
+    }
+    for (; i < ch.count; i += kCountWG) {
+      uint4 v = p[i];
+      atomicAdd(&h[point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, lvl_bit, E)], 1u);
+    }
   }
   lds_barrier();
   uint32_t* row = hist + (uint64_t)c * B;
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) row[j] = h[j];
+  lds_barrier();
+  }
 }
 
 // Column scan of the chunk rows, in three steps so that no thread walks more
@@ -253,45 +274,48 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
 __global__ void k_colscan_groups(const ChunkGroup* __restrict__ groups, const uint32_t* ngroup_ptr, uint32_t E,
                                  const uint32_t* __restrict__ hist, uint32_t* __restrict__ gsum) {
   const uint32_t B = 1u << (3 * E);
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t g = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
-  if (g >= *ngroup_ptr) return;
-  const ChunkGroup gr = groups[g];
-  uint32_t s = 0;
-  for (uint32_t k = 0; k < gr.count; ++k) s += hist[(uint64_t)(gr.first + k) * B + b];
-  gsum[(uint64_t)g * B + b] = s;
+  const uint64_t total = (uint64_t)*ngroup_ptr << (3 * E);
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t g = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
+    const ChunkGroup gr = groups[g];
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < gr.count; ++k) s += hist[(uint64_t)(gr.first + k) * B + b];
+    gsum[(uint64_t)g * B + b] = s;
+  }
 }
 
 __global__ void k_colscan_segments(const Segment* __restrict__ segs, const uint32_t* nseg_ptr, uint32_t E,
                                    uint32_t* __restrict__ gsum, const GridDesc* __restrict__ grids, uint32_t* pool) {
   const uint32_t B = 1u << (3 * E);
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t s = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
-  if (s >= *nseg_ptr) return;
-  const Segment sg = segs[s];
-  uint32_t run = 0;
-  for (uint32_t k = 0; k < sg.group_count; ++k) {
-    uint32_t* cell = gsum + (uint64_t)(sg.group_begin + k) * B + b;
-    const uint32_t v = *cell;
-    *cell = run;
-    run += v;
+  const uint64_t total = (uint64_t)*nseg_ptr << (3 * E);
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t s = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
+    const Segment sg = segs[s];
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < sg.group_count; ++k) {
+      uint32_t* cell = gsum + (uint64_t)(sg.group_begin + k) * B + b;
+      const uint32_t v = *cell;
+      *cell = run;
+      run += v;
+    }
+    pool[grids[sg.grid].pyr + pyr_level_offset(E) + b] = run;
   }
-  pool[grids[sg.grid].pyr + pyr_level_offset(E) + b] = run;
 }
 
 __global__ void k_colscan_apply(const ChunkGroup* __restrict__ groups, const uint32_t* ngroup_ptr, uint32_t E,
                                 uint32_t* __restrict__ hist, const uint32_t* __restrict__ gsum) {
   const uint32_t B = 1u << (3 * E);
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t g = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
-  if (g >= *ngroup_ptr) return;
-  const ChunkGroup gr = groups[g];
-  uint32_t run = gsum[(uint64_t)g * B + b];
-  for (uint32_t k = 0; k < gr.count; ++k) {
-    uint32_t* cell = hist + (uint64_t)(gr.first + k) * B + b;
-    const uint32_t v = *cell;
-    *cell = run;
-    run += v;
+  const uint64_t total = (uint64_t)*ngroup_ptr << (3 * E);
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t g = (uint32_t)(t >> (3 * E)), b = (uint32_t)(t & (B - 1));
+    const ChunkGroup gr = groups[g];
+    uint32_t run = gsum[(uint64_t)g * B + b];
+    for (uint32_t k = 0; k < gr.count; ++k) {
+      uint32_t* cell = hist + (uint64_t)(gr.first + k) * B + b;
+      const uint32_t v = *cell;
+      *cell = run;
+      run += v;
+    }
   }
 }
 
@@ -303,8 +327,8 @@ constexpr int kGridWG = 1024;
 __global__ void __launch_bounds__(kGridWG) k_grid_finish(const Segment* __restrict__ segs, const uint32_t* nseg_ptr,
                                                          const GridDesc* __restrict__ grids, uint32_t* pool) {
   __shared__ uint32_t sh[kGridWG / 64 + 1];
-  const uint32_t s = blockIdx.x;
-  if (s >= *nseg_ptr) return;
+  const uint32_t nseg = *nseg_ptr;
+  for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
   const Segment sg = segs[s];
   const GridDesc g = grids[sg.grid];
   const uint32_t E = g.e;
@@ -339,6 +363,7 @@ __global__ void __launch_bounds__(kGridWG) k_grid_finish(const Segment* __restri
     }
     __syncthreads();
   }
+  }
 }
 
 // Insert (Sec. 4.1.4): move every point of a chunk to its cell.  A round of
@@ -351,7 +376,14 @@ __global__ void __launch_bounds__(kGridWG) k_grid_finish(const Segment* __restri
 // output deltas, and the rest of LDS holds as large a round as possible: the
 // stores of a round are runs of consecutive records per cell, and longer runs
 // write HBM more efficiently.
+// Digits (DM): with DM = 1 the insert also writes, beside every record, the
+// 2-byte cell of the E2 key levels below the ones it sorts by (the next
+// pass's digit, taken from the same quantization); with DM = 2 the cell is
+// read from such a digit array instead of being computed from the record.
 constexpr int kScatWG = 1024;
+// Workgroups of a count or insert launch at most; each takes every
+// gridDim.x-th chunk of the device-side chunk list.
+constexpr uint32_t kMaxPartBlocks = 4096;
 #define PAD(b) ((b) + ((b) >> 5))
 template <bool IDS>
 struct ScatShape {
@@ -359,9 +391,11 @@ struct ScatShape {
   static constexpr int R = kScatWG * PPT;
 };
 
-template <int E, bool IDS>
+template <int E, bool IDS, int DM>
 __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
                                                           uint4* __restrict__ dst, uint32_t* __restrict__ dst_ids,
+                                                          const uint16_t* __restrict__ dig_in,
+                                                          uint16_t* __restrict__ dig_out, uint32_t E2,
                                                           const Cube* cube, const Segment* __restrict__ segs,
                                                           const Chunk* __restrict__ chunks, const uint32_t* nchunk_ptr,
                                                           const uint32_t* __restrict__ hist,
@@ -377,9 +411,11 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
   __shared__ uint4 stage[R];
   __shared__ uint16_t stage_b[R];
   __shared__ uint32_t stage_id[IDS ? R : 1];
+  constexpr bool kStageDig = DM == 1 && !IDS;  // with ids the digit is recomputed at the store
+  __shared__ uint16_t stage_d[kStageDig ? R : 1];
   __shared__ uint32_t sh[kScatWG / 64 + 1];
-  const uint32_t c = blockIdx.x;
-  if (c >= *nchunk_ptr) return;
+  const uint32_t nchunk = *nchunk_ptr;
+  for (uint32_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
   const Chunk ch = chunks[c];
   const Segment sg = segs[ch.seg];
   const GridDesc g = grids[sg.grid];
@@ -401,8 +437,8 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
   // software pipeline: the records of round r + 1 are loaded while round r is
   // sorted in LDS and written out
   uint4 v[PPT];
-  uint32_t id[PPT];
-  auto load_round = [&](uint32_t base, uint4* vv, uint32_t* ii) {
+  uint32_t id[PPT], dd[PPT];
+  auto load_round = [&](uint32_t base, uint4* vv, uint32_t* ii, uint32_t* di) {
     const uint32_t nround = base < ch.count ? min(R, ch.count - base) : 0u;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -411,24 +447,35 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
         const uint32_t gi = ch.start + base + j;
         vv[k] = src[gi];
         if (IDS) ii[k] = src_ids ? src_ids[gi] : gi - ch_cloud_start;
+        if (DM == 2) di[k] = dig_in[gi];
       }
     }
   };
-  load_round(0, v, id);
+  load_round(0, v, id, dd);
+  const uint32_t dmask = (1u << (3 * E2)) - 1u;
   for (uint32_t base = 0; base < ch.count; base += R) {
     const uint32_t nround = min(R, ch.count - base);
-    uint32_t bk[PPT], rk[PPT];
+    uint32_t bk[PPT], rk[PPT], dg[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
-        bk[k] = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E);
+        if (DM == 2) {
+          bk[k] = dd[k];
+        } else if (DM == 1) {
+          const uint32_t full = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z),
+                                           cd, lvl_bit - E2, E + E2);
+          bk[k] = full >> (3 * E2);
+          dg[k] = full & dmask;
+        } else {
+          bk[k] = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E);
+        }
         rk[k] = atomicAdd(&cnt[PAD(bk[k])], 1u);
       }
     }
     uint4 vn[PPT];
-    uint32_t idn[PPT];
-    load_round(base + R, vn, idn);
+    uint32_t idn[PPT], ddn[PPT];
+    load_round(base + R, vn, idn, ddn);
     lds_barrier();
     // exclusive scan of the round's cell counts (in place); counts and
     // prefixes stay in registers
@@ -458,6 +505,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
         stage[pos] = v[k];
         stage_b[pos] = (uint16_t)bk[k];
         if (IDS) stage_id[pos] = id[k];
+        if (kStageDig) stage_d[pos] = (uint16_t)dg[k];
       }
     }
     lds_barrier();
@@ -471,8 +519,13 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     lds_barrier();
     for (uint32_t j = threadIdx.x; j < nround; j += kScatWG) {
       const uint32_t d = cnt[PAD(stage_b[j])] + j;
-      dst[d] = stage[j];
+      const uint4 r = stage[j];
+      dst[d] = r;
       if (IDS) dst_ids[d] = stage_id[j];
+      if (kStageDig) dig_out[d] = stage_d[j];
+      if (DM == 1 && IDS)
+        dig_out[d] = (uint16_t)point_cell(__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), cd,
+                                          lvl_bit - E2, E2);
     }
     lds_barrier();
 #pragma unroll
@@ -485,7 +538,9 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     for (int k = 0; k < PPT; ++k) {
       v[k] = vn[k];
       if (IDS) id[k] = idn[k];
+      if (DM == 2) dd[k] = ddn[k];
     }
+  }
   }
 }
 
@@ -498,12 +553,13 @@ constexpr uint32_t kCopySplit = 64;
 __global__ void __launch_bounds__(256) k_copy_segments(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
                                                        uint4* __restrict__ dst, uint32_t* __restrict__ dst_ids,
                                                        const Segment* __restrict__ segs, const uint32_t* nseg_ptr) {
-  const uint32_t s = blockIdx.x;
-  if (s >= *nseg_ptr) return;
-  const Segment sg = segs[s];
-  for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < sg.count; i += kCopySplit * 256) {
-    dst[sg.start + i] = src[sg.start + i];
-    if (dst_ids) dst_ids[sg.start + i] = src_ids[sg.start + i];
+  const uint32_t nseg = *nseg_ptr;
+  for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+    const Segment sg = segs[s];
+    for (uint32_t i = blockIdx.y * 256 + threadIdx.x; i < sg.count; i += kCopySplit * 256) {
+      dst[sg.start + i] = src[sg.start + i];
+      if (dst_ids) dst_ids[sg.start + i] = src_ids[sg.start + i];
+    }
   }
 }
 
@@ -593,7 +649,31 @@ __global__ void k_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t
   grids[c] = d;
 }
 
+// ------------------------------------------------------------ fills
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_build_init(BuildState* bs, uint32_t num_grids, uint64_t used_words) {
+  BuildState z;
+  memset(&z, 0, sizeof(z));
+  z.num_grids = z.need_grids = num_grids;
+  z.used_words = z.need_words = used_words;
+  *bs = z;
+}
+
 // ------------------------------------------------------------ launchers
+
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)std::min<uint64_t>((n + 255) / 256, 4096)), dim3(256), 0, st, p, v, n);
+}
+
+void launch_build_init(BuildState* bs, uint32_t num_grids, uint64_t used_words, hipStream_t st) {
+  hipLaunchKernelGGL(k_build_init, dim3(1), dim3(1), 0, st, bs, num_grids, used_words);
+}
 
 uint32_t bbox_tiles(uint32_t count) { return (count + kBBoxTile - 1) / kBBoxTile; }
 
@@ -635,22 +715,32 @@ void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, 
 }
 
 template <int E>
-static void count_e(const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
-                    uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
-  hipLaunchKernelGGL(k_part_count<E>, dim3(max_chunks), dim3(kCountWG), 0, st, (const uint4*)pts, cube, segs, chunks,
-                     nchunk, hist);
+static void count_e(const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs, const Chunk* chunks,
+                    const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
+  const uint32_t blocks = std::min<uint32_t>(max_chunks, kMaxPartBlocks);
+  if (dig)
+    hipLaunchKernelGGL((k_part_count<E, true>), dim3(blocks), dim3(kCountWG), 0, st, (const uint4*)pts, dig, cube,
+                       segs, chunks, nchunk, hist);
+  else
+    hipLaunchKernelGGL((k_part_count<E, false>), dim3(blocks), dim3(kCountWG), 0, st, (const uint4*)pts, dig, cube,
+                       segs, chunks, nchunk, hist);
 }
 
-void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
-                       const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
+void launch_part_count(uint32_t E, const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs,
+                       const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist,
+                       hipStream_t st) {
   if (!max_chunks) return;
   switch (E) {
-    case 1: count_e<1>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 2: count_e<2>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 3: count_e<3>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 4: count_e<4>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 1: count_e<1>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 2: count_e<2>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 3: count_e<3>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 4: count_e<4>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
     default: break;
   }
+}
+
+static uint32_t stride_blocks(uint64_t threads) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((threads + 255) / 256, 8192));
 }
 
 void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const ChunkGroup* groups,
@@ -659,52 +749,68 @@ void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max
   if (!max_segs) return;
   const uint64_t tg = (uint64_t)max_groups << (3 * E);
   const uint64_t ts = (uint64_t)max_segs << (3 * E);
-  hipLaunchKernelGGL(k_colscan_groups, dim3((uint32_t)((tg + 255) / 256)), dim3(256), 0, st, groups, ngroup, E, hist,
-                     gsum);
-  hipLaunchKernelGGL(k_colscan_segments, dim3((uint32_t)((ts + 255) / 256)), dim3(256), 0, st, segs, nseg, E, gsum,
-                     grids, pool);
-  hipLaunchKernelGGL(k_colscan_apply, dim3((uint32_t)((tg + 255) / 256)), dim3(256), 0, st, groups, ngroup, E, hist,
-                     gsum);
+  hipLaunchKernelGGL(k_colscan_groups, dim3(stride_blocks(tg)), dim3(256), 0, st, groups, ngroup, E, hist, gsum);
+  hipLaunchKernelGGL(k_colscan_segments, dim3(stride_blocks(ts)), dim3(256), 0, st, segs, nseg, E, gsum, grids, pool);
+  hipLaunchKernelGGL(k_colscan_apply, dim3(stride_blocks(tg)), dim3(256), 0, st, groups, ngroup, E, hist, gsum);
 }
 
 void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const GridDesc* grids,
                         uint32_t* pool, hipStream_t st) {
   if (!max_segs) return;
-  hipLaunchKernelGGL(k_grid_finish, dim3(max_segs), dim3(kGridWG), 0, st, segs, nseg, grids, pool);
+  hipLaunchKernelGGL(k_grid_finish, dim3(std::min<uint32_t>(max_segs, 2048)), dim3(kGridWG), 0, st, segs, nseg, grids,
+                     pool);
 }
 
-template <int E, bool IDS>
-static void scatter_e(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Cube* cube,
-                      const Segment* segs, const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks,
-                      const uint32_t* hist, const GridDesc* grids, const uint32_t* pool, hipStream_t st) {
-  hipLaunchKernelGGL((k_part_scatter<E, IDS>), dim3(max_chunks), dim3(kScatWG), 0, st, (const uint4*)src, src_ids,
-                     (uint4*)dst, dst_ids, cube, segs, chunks, nchunk, hist, grids, pool);
+template <int E, bool IDS, int DM>
+static void scatter_e(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const uint16_t* dig_in,
+                      uint16_t* dig_out, uint32_t E2, const Cube* cube, const Segment* segs, const Chunk* chunks,
+                      const uint32_t* nchunk, uint32_t max_chunks, const uint32_t* hist, const GridDesc* grids,
+                      const uint32_t* pool, hipStream_t st) {
+  hipLaunchKernelGGL((k_part_scatter<E, IDS, DM>), dim3(std::min<uint32_t>(max_chunks, kMaxPartBlocks)), dim3(kScatWG), 0,
+                     st, (const uint4*)src, src_ids,
+                     (uint4*)dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, hist, grids, pool);
+}
+
+template <int E>
+static void scatter_ids_dm(bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
+                           const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2, const Cube* cube,
+                           const Segment* segs, const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks,
+                           const uint32_t* hist, const GridDesc* grids, const uint32_t* pool, hipStream_t st) {
+  const int dm = dig_in ? 2 : (dig_out ? 1 : 0);
+#define LOD_SCAT(I, D)                                                                                           \
+  if (ids == I && dm == D) {                                                                                     \
+    scatter_e<E, I, D>(src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, \
+                       hist, grids, pool, st);                                                                   \
+    return;                                                                                                      \
+  }
+  LOD_SCAT(false, 0)
+  LOD_SCAT(false, 1)
+  LOD_SCAT(false, 2)
+  LOD_SCAT(true, 0)
+  LOD_SCAT(true, 1)
+  LOD_SCAT(true, 2)
+#undef LOD_SCAT
 }
 
 void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
-                         const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
-                         uint32_t max_chunks, const uint32_t* hist, const GridDesc* grids, const uint32_t* pool,
-                         hipStream_t st) {
+                         const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2, const Cube* cube, const Segment* segs,
+                         const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, const uint32_t* hist,
+                         const GridDesc* grids, const uint32_t* pool, hipStream_t st) {
   if (!max_chunks) return;
-#define LOD_SCAT(EE)                                                                                           \
-  case EE:                                                                                                     \
-    if (ids) scatter_e<EE, true>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); \
-    else scatter_e<EE, false>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st);    \
-    break;
   switch (E) {
-    LOD_SCAT(1)
-    LOD_SCAT(2)
-    LOD_SCAT(3)
-    LOD_SCAT(4)
+    case 1: scatter_ids_dm<1>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
+    case 2: scatter_ids_dm<2>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
+    case 3: scatter_ids_dm<3>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
+    case 4: scatter_ids_dm<4>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
     default: break;
   }
-#undef LOD_SCAT
 }
 
 void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,
                           const uint32_t* nseg, uint32_t max_segs, hipStream_t st) {
   if (!max_segs) return;
-  hipLaunchKernelGGL(k_copy_segments, dim3(max_segs, kCopySplit), dim3(256), 0, st, (const uint4*)src, src_ids,
+  hipLaunchKernelGGL(k_copy_segments, dim3(std::min<uint32_t>(max_segs, 256), kCopySplit), dim3(256), 0, st,
+                     (const uint4*)src, src_ids,
                      (uint4*)dst, dst_ids, segs, nseg);
 }
 

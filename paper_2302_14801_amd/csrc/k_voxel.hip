@@ -269,11 +269,14 @@ __device__ __forceinline__ Item item_of(const Nodes& nodes, uint32_t n, uint32_t
 //
 // One thread per item.  Coarse-list blocks are handed out by a wave-wide
 // prefix sum and one atomic add per wave on bs->coarse_used.
-__global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nodes, const GridDesc* __restrict__ grids,
+__global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, const GridDesc* __restrict__ grids,
                                                    const uint32_t* __restrict__ pool, BuildState* bs,
-                                                   ItemDesc* __restrict__ desc) {
-  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-  const bool valid = i < 8 * num_nodes;
+                                                   ItemDesc* __restrict__ desc, uint64_t t2cap) {
+  if (build_stopped(bs)) return;
+  const uint32_t nitems = 8u * bs->total_nodes;
+  for (uint32_t i0 = blockIdx.x * 256; i0 < nitems; i0 += gridDim.x * 256) {  // uniform per workgroup
+  const uint32_t i = i0 + threadIdx.x;
+  const bool valid = i < nitems;
   ItemDesc d;
   d.I0 = d.P = d.lvl = d.tree = 0;
   d.lkey = 0;
@@ -295,13 +298,18 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, uint32_t num_nod
   const uint64_t incl = wave_incl_scan(sz);
   const uint64_t total = __shfl(incl, 63, 64);
   uint64_t base = 0;
-  if (lane_id() == 63 && total) base = atomicAdd((unsigned long long*)&bs->coarse_used, (unsigned long long)total);
+  if (lane_id() == 63 && total) {
+    base = atomicAdd((unsigned long long*)&bs->coarse_used, (unsigned long long)total);
+    // the pool is an estimate: past it the build stops and is repeated
+    if (base + total > t2cap) atomicOr(&bs->overflow, (uint32_t)kOverCoarse);
+  }
   base = __shfl(base, 63, 64);
   d.t2 = base + incl - sz;
   if (valid) {
     const uint4* src = (const uint4*)&d;
     uint4* dst = (uint4*)(desc + i);
     for (int k = 0; k < 4; ++k) dst[k] = src[k];
+  }
   }
 }
 
@@ -349,7 +357,8 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
                                                                           uint64_t* __restrict__ T2,
                                                                           uint32_t* __restrict__ T2id,
                                                                           uint32_t* __restrict__ icnt,
-                                                                          uint64_t* __restrict__ iself, uint32_t seed) {
+                                                                          uint64_t* __restrict__ iself, uint32_t seed,
+                                                                          BuildState* bs) {
   __shared__ uint64_t acc[kSubCells];
   __shared__ uint32_t bm1[2][kSubCells / 32];  // depth-1 occupancy, alternating between micro-buckets
   __shared__ uint32_t over[8];                 // a cell of the micro-bucket passed 257 samples
@@ -357,12 +366,22 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   __shared__ uint64_t k4ok[8][8];              // depth-4 voxels of each micro-bucket: pick key and colour
   __shared__ uint32_t k4col[8][8];
   __shared__ uint32_t minid[MODE == 3 ? kSubCells : 1];  // mode 3: smallest id of every depth-1 cell
+  __shared__ uint32_t s_item;
   const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
-  const ItemDesc& sd = desc[blockIdx.x];  // uniform: scalar loads
+  if (build_stopped(bs)) return;
+  const uint32_t nitems = 8u * bs->total_nodes;
+  // work items from a queue, one at a time per workgroup
+  for (;;) {
+  if (t == 0) s_item = atomicAdd(&bs->item_next, 1u);
+  __syncthreads();
+  const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+  __syncthreads();
+  if (item >= nitems) break;
+  const ItemDesc& sd = desc[item];  // uniform: scalar loads
   const uint32_t P = sd.P;
   if (P == 0) {  // an empty child cell, or not a leaf item (uniform)
-    if (t < 6) icnt[6 * blockIdx.x + t] = 0;
-    return;
+    if (t < 6) icnt[6 * item + t] = 0;
+    continue;
   }
   const uint64_t init = MODE == 1 ? ~0ull : 0ull;
   for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
@@ -378,7 +397,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   }
   const CubeD cd = load_cube(cube + sd.tree);
   __syncthreads();
-  const uint32_t I0 = sd.I0, I1 = I0 + P, lvl = sd.lvl, grp = blockIdx.x & 7u;
+  const uint32_t I0 = sd.I0, I1 = I0 + P, lvl = sd.lvl, grp = item & 7u;
   const uint64_t lkey = sd.lkey, t2b = sd.t2;
   const uint32_t sub_bit = 15u - lvl;  // bit level of the depth-1 cells (level lvl + 6)
   const uint32_t cb3 = coarse_base(3, P), cb4 = coarse_base(4, P), cb5 = coarse_base(5, P), cb6 = coarse_base(6, P);
@@ -699,10 +718,10 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         const uint32_t rgba = smp_rgba<MODE>(s6);
         T2[t2b + cb6] = make_voxel(anc_code(lkey, 6, grp), rgba);
         if (MODE) T2id[t2b + cb6] = (uint32_t)s6.ok;
-        iself[blockIdx.x] = ((uint64_t)rgba << 32) | (uint32_t)s6.ok;
+        iself[item] = ((uint64_t)rgba << 32) | (uint32_t)s6.ok;
         c6 = 1;
       }
-      uint32_t* ic = icnt + 6 * blockIdx.x;
+      uint32_t* ic = icnt + 6 * item;
       ic[0] = base1;
       ic[1] = base2;
       ic[2] = base3;
@@ -710,6 +729,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
       ic[4] = c5;
       ic[5] = c6;
     }
+  }
   }
 }
 
@@ -721,11 +741,12 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
 //   >= 7 (its self voxel in the ancestor 7 levels up).
 // Leaves at level >= 7 also get their self voxel from their items' voxels.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_piece_sizes(Nodes nodes, VoxTree vt, uint32_t num_nodes,
+__global__ void __launch_bounds__(256) k_piece_sizes(Nodes nodes, VoxTree vt, const BuildState* bs,
                                                      const uint32_t* __restrict__ icnt,
                                                      const uint64_t* __restrict__ iself, uint32_t seed) {
-  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= num_nodes) return;
+  if (build_stopped(bs)) return;
+  const uint32_t num_nodes = bs->total_nodes;
+  for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < num_nodes; j += gridDim.x * 256) {
   const uint32_t L = nodes.level[j];
   const bool leaf = nodes.is_leaf[j] != 0;
   uint32_t ps[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -761,6 +782,7 @@ __global__ void __launch_bounds__(256) k_piece_sizes(Nodes nodes, VoxTree vt, ui
     vt.selfc[j] = smp_rgba<MODE>(sm);
     vt.selfid[j] = (uint32_t)sm.ok;
   }
+  }
 }
 
 // One workgroup per tree: subtree sizes (bottom-up), depth-first positions
@@ -770,7 +792,8 @@ __global__ void __launch_bounds__(256) k_piece_sizes(Nodes nodes, VoxTree vt, ui
 constexpr int kVTWG = 1024;
 template <int MODE>
 __global__ void __launch_bounds__(kVTWG) k_vox_tree(Nodes nodes, VoxTree vt, const TreeInfo* __restrict__ trees,
-                                                    uint32_t seed) {
+                                                    uint32_t seed, const BuildState* bs) {
+  if (build_stopped(bs)) return;
   const TreeInfo& ti = trees[blockIdx.x];
   const int deepest = (int)ti.deepest;
   for (int L = deepest; L >= 0; --L) {
@@ -830,10 +853,12 @@ __device__ __forceinline__ uint32_t piece_size(const Nodes& nodes, const VoxTree
   return d <= 7 ? vt.psize[8ull * N + d] : 0u;
 }
 
-__global__ void __launch_bounds__(kPieceWG) k_piece_count(Nodes nodes, VoxTree vt, uint32_t num_nodes) {
+__global__ void __launch_bounds__(kPieceWG) k_piece_count(Nodes nodes, VoxTree vt, const BuildState* bs) {
   __shared__ uint32_t sh[kPieceWG / 64];
-  const uint32_t a = blockIdx.x;
-  if (a >= num_nodes || nodes.is_leaf[a]) return;
+  if (build_stopped(bs)) return;
+  const uint32_t num_nodes = bs->total_nodes;
+  for (uint32_t a = blockIdx.x; a < num_nodes; a += gridDim.x) {
+  if (nodes.is_leaf[a]) continue;  // uniform
   const uint32_t L = nodes.level[a], b = vt.dfs[a] + 1, e = vt.dfs[a] + vt.sz[a];
   uint32_t s = 0;
   for (uint32_t i = b + threadIdx.x; i < e; i += kPieceWG) {
@@ -848,12 +873,15 @@ __global__ void __launch_bounds__(kPieceWG) k_piece_count(Nodes nodes, VoxTree v
     for (int q = 0; q < kPieceWG / 64; ++q) tot += sh[q];
     nodes.count[a] = tot;
   }
+  __syncthreads();
+  }
 }
 
 // Voxel offsets of the inner nodes of a tree in node order, counted from the
 // tree's first voxel (one workgroup per tree); the total goes to vtotal.
-__global__ void __launch_bounds__(kPrefWG) k_voxel_offsets(Nodes nodes, TreeInfo* trees) {
+__global__ void __launch_bounds__(kPrefWG) k_voxel_offsets(Nodes nodes, TreeInfo* trees, const BuildState* bs) {
   __shared__ uint64_t sh[kPrefWG / 64 + 1];
+  if (build_stopped(bs)) return;
   TreeInfo& ti = trees[blockIdx.x];
   const uint32_t b = ti.node_base, e = ti.node_base + ti.num_nodes;
   uint64_t base = 0;
@@ -868,15 +896,42 @@ __global__ void __launch_bounds__(kPrefWG) k_voxel_offsets(Nodes nodes, TreeInfo
   if (threadIdx.x == 0) ti.vtotal = base;
 }
 
+// First voxel of every tree in the build's voxel array (prefix sum of the
+// trees' voxel counts, one workgroup) and the total; a total above the
+// output's capacity flags the build (kOverVoxels), and nothing is written.
+__global__ void __launch_bounds__(kPrefWG) k_voxel_bases(TreeInfo* trees, uint32_t ntrees, uint64_t vcap,
+                                                         BuildState* bs) {
+  __shared__ uint64_t sh[kPrefWG / 64 + 1];
+  if (build_stopped(bs)) return;
+  uint64_t base = 0;
+  for (uint32_t c0 = 0; c0 < ntrees; c0 += kPrefWG) {
+    const uint32_t c = c0 + threadIdx.x;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan<kPrefWG>(c < ntrees ? trees[c].vtotal : (uint64_t)0, sh, &tot);
+    if (c < ntrees) trees[c].vbase = base + ex;
+    base += tot;
+  }
+  if (threadIdx.x == 0) {
+    bs->vtotal = base;
+    if (base > vcap) atomicOr(&bs->overflow, (uint32_t)kOverVoxels);
+  }
+}
+
+__device__ __forceinline__ bool voxels_refused(const BuildState* bs) {
+  return (*(volatile const uint32_t*)&bs->overflow & (kOverStop | kOverVoxels)) != 0;
+}
+
 // Output position of every piece of inner node A; self voxels are written
 // here directly.
 template <int MODE>
-__global__ void __launch_bounds__(kPieceWG) k_piece_offsets(Nodes nodes, VoxTree vt, uint32_t num_nodes,
+__global__ void __launch_bounds__(kPieceWG) k_piece_offsets(Nodes nodes, VoxTree vt, const BuildState* bs,
                                                             const TreeInfo* __restrict__ trees,
                                                             uint64_t* __restrict__ vox, uint32_t* __restrict__ vids) {
   __shared__ uint32_t sh[kPieceWG / 64 + 1];
-  const uint32_t a = blockIdx.x;
-  if (a >= num_nodes || nodes.is_leaf[a]) return;
+  if (voxels_refused(bs)) return;
+  const uint32_t num_nodes = bs->total_nodes;
+  for (uint32_t a = blockIdx.x; a < num_nodes; a += gridDim.x) {
+  if (nodes.is_leaf[a]) continue;  // uniform
   const uint32_t L = nodes.level[a], b = vt.dfs[a] + 1, e = vt.dfs[a] + vt.sz[a];
   uint64_t run = trees[nodes.tree[a]].vbase + nodes.offset[a];
   for (uint32_t i0 = b; i0 < e; i0 += kPieceWG) {
@@ -894,6 +949,7 @@ __global__ void __launch_bounds__(kPieceWG) k_piece_offsets(Nodes nodes, VoxTree
     }
     run += tot;
   }
+  }
 }
 
 // Copy every item's depth-1..6 lists to their output positions: the leaf's
@@ -902,7 +958,7 @@ __global__ void __launch_bounds__(kPieceWG) k_piece_offsets(Nodes nodes, VoxTree
 // then each wave copies every fourth list.
 constexpr int kGatherWG = 256;
 template <int MODE>
-__global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, uint32_t num_nodes,
+__global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, const BuildState* bs,
                                                       const uint32_t* __restrict__ icnt,
                                                       const ItemDesc* __restrict__ desc,
                                                       const uint64_t* __restrict__ T1, const uint32_t* __restrict__ T1id,
@@ -910,8 +966,11 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, u
                                                       uint64_t* __restrict__ vox, uint32_t* __restrict__ vids) {
   __shared__ uint64_t sdst[48], ssrc[48];
   __shared__ uint32_t scnt[48];
-  const uint32_t n = blockIdx.x, t = threadIdx.x;
-  if (n >= num_nodes || !nodes.is_leaf[n] || nodes.level[n] == 0) return;
+  const uint32_t t = threadIdx.x;
+  if (voxels_refused(bs)) return;
+  const uint32_t num_nodes = bs->total_nodes;
+  for (uint32_t n = blockIdx.x; n < num_nodes; n += gridDim.x) {
+  if (!nodes.is_leaf[n] || nodes.level[n] == 0) continue;  // uniform
   const uint32_t L = nodes.level[n];
   // list j: depth k = j / 8 + 1 of item g = j % 8
   const uint32_t k = t / 8 + 1, g = t % 8;
@@ -952,6 +1011,8 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, u
       if (MODE) vids[dst + i] = si[src + i];
     }
   }
+  __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ full precision
@@ -961,11 +1022,12 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, u
 // voxel of the call.  The voxel's tree is the last one whose first voxel is
 // not after it (trees without voxels share their first voxel with the next).
 __global__ void __launch_bounds__(256) k_voxel_points(const uint64_t* __restrict__ vox, const uint32_t* __restrict__ vids,
-                                                      uint64_t vtotal, const TreeInfo* __restrict__ trees,
+                                                      const BuildState* bs, const TreeInfo* __restrict__ trees,
                                                       const CloudInfo* __restrict__ clouds, uint32_t ntrees,
                                                       const uint4* __restrict__ pts, uint4* __restrict__ out) {
-  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= vtotal) return;
+  if (voxels_refused(bs)) return;
+  const uint64_t vtotal = bs->vtotal;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < vtotal; i += (uint64_t)gridDim.x * 256) {
   uint32_t lo = 0, hi = ntrees - 1;
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1) >> 1;
@@ -974,6 +1036,7 @@ __global__ void __launch_bounds__(256) k_voxel_points(const uint64_t* __restrict
   }
   const uint4 p = pts[(uint64_t)clouds[lo].start + vids[i]];
   out[i] = make_uint4(p.x, p.y, p.z, (uint32_t)(vox[i] >> 32));
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -983,11 +1046,14 @@ uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes) {
   return std::min<uint64_t>(5 * n, (uint64_t)coarse_base(7, 0xffffffffu) * 8ull * num_nodes) + 1;
 }
 
-void launch_item_desc(const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids, const uint32_t* pool,
-                      BuildState* bs, void* desc, hipStream_t s) {
-  if (!num_nodes) return;
-  hipLaunchKernelGGL(k_item_desc, dim3((8 * num_nodes + 255) / 256), dim3(256), 0, s, nodes, num_nodes, grids, pool, bs,
-                     (ItemDesc*)desc);
+static uint32_t grid_blocks(uint64_t units, uint32_t per_block, uint32_t cap) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((units + per_block - 1) / per_block, cap));
+}
+
+void launch_item_desc(const Nodes& nodes, uint32_t max_nodes, const GridDesc* grids, const uint32_t* pool,
+                      BuildState* bs, void* desc, uint64_t t2cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_item_desc, dim3(grid_blocks(8ull * max_nodes, 256, 4096)), dim3(256), 0, s, nodes, grids, pool,
+                     bs, (ItemDesc*)desc, t2cap);
 }
 
 #define LOD_MODE_SWITCH(mode, M, BODY) \
@@ -1010,47 +1076,49 @@ void launch_item_desc(const Nodes& nodes, uint32_t num_nodes, const GridDesc* gr
     } break;                           \
   }
 
-void launch_leaf_voxels(uint32_t mode, uint32_t num_nodes, const void* desc, const void* pts, const uint32_t* ids,
+void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, const void* desc, const void* pts, const uint32_t* ids,
                         const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2, uint32_t* T2id, uint32_t* icnt,
-                        uint64_t* iself, uint32_t seed, hipStream_t s) {
-  if (!num_nodes) return;
+                        uint64_t* iself, uint32_t seed, BuildState* bs, hipStream_t s) {
+  // workgroups that stay resident (256 CUs, up to 4 per CU) take the items
+  // from a queue
+  const uint32_t blocks = grid_blocks(8ull * max_nodes, 1, 1024);
   LOD_MODE_SWITCH(mode, M,
-                  hipLaunchKernelGGL(k_leaf_voxels<M>, dim3(num_nodes * 8), dim3(kLeafWG), 0, s,
-                                     (const ItemDesc*)desc, (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt,
-                                     iself, seed))
+                  hipLaunchKernelGGL(k_leaf_voxels<M>, dim3(blocks), dim3(kLeafWG), 0, s, (const ItemDesc*)desc,
+                                     (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt, iself, seed, bs))
 }
 
-void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes, TreeInfo* trees,
-                       uint32_t ntrees, const uint32_t* icnt, const uint64_t* iself, uint32_t seed, hipStream_t s) {
-  if (!num_nodes) return;
+void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t max_nodes, TreeInfo* trees,
+                       uint32_t ntrees, uint64_t vcap, const uint32_t* icnt, const uint64_t* iself, uint32_t seed,
+                       BuildState* bs, hipStream_t s) {
   LOD_MODE_SWITCH(mode, M, {
-    hipLaunchKernelGGL(k_piece_sizes<M>, dim3((num_nodes + 255) / 256), dim3(256), 0, s, nodes, vt, num_nodes, icnt,
-                       iself, seed);
-    hipLaunchKernelGGL(k_vox_tree<M>, dim3(ntrees), dim3(kVTWG), 0, s, nodes, vt, (const TreeInfo*)trees, seed);
+    hipLaunchKernelGGL(k_piece_sizes<M>, dim3(grid_blocks(max_nodes, 256, 4096)), dim3(256), 0, s, nodes, vt, bs,
+                       icnt, iself, seed);
+    hipLaunchKernelGGL(k_vox_tree<M>, dim3(ntrees), dim3(kVTWG), 0, s, nodes, vt, (const TreeInfo*)trees, seed, bs);
   })
-  hipLaunchKernelGGL(k_piece_count, dim3(num_nodes), dim3(kPieceWG), 0, s, nodes, vt, num_nodes);
-  hipLaunchKernelGGL(k_voxel_offsets, dim3(ntrees), dim3(kPrefWG), 0, s, nodes, trees);
+  hipLaunchKernelGGL(k_piece_count, dim3(grid_blocks(max_nodes, 1, 4096)), dim3(kPieceWG), 0, s, nodes, vt, bs);
+  hipLaunchKernelGGL(k_voxel_offsets, dim3(ntrees), dim3(kPrefWG), 0, s, nodes, trees, bs);
+  hipLaunchKernelGGL(k_voxel_bases, dim3(1), dim3(kPrefWG), 0, s, trees, ntrees, vcap, bs);
 }
 
-void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes,
+void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t max_nodes,
                          const TreeInfo* trees, const uint32_t* icnt, const void* desc, const uint64_t* T1,
                          const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
-                         hipStream_t s) {
-  if (!num_nodes) return;
+                         const BuildState* bs, hipStream_t s) {
   LOD_MODE_SWITCH(mode, M, {
-    hipLaunchKernelGGL(k_piece_offsets<M>, dim3(num_nodes), dim3(kPieceWG), 0, s, nodes, vt, num_nodes, trees, vox,
-                       vids);
-    hipLaunchKernelGGL(k_gather<M>, dim3(num_nodes), dim3(kGatherWG), 0, s, nodes, vt, num_nodes, icnt,
+    hipLaunchKernelGGL(k_piece_offsets<M>, dim3(grid_blocks(max_nodes, 1, 4096)), dim3(kPieceWG), 0, s, nodes, vt, bs,
+                       trees, vox, vids);
+    hipLaunchKernelGGL(k_gather<M>, dim3(grid_blocks(max_nodes, 1, 4096)), dim3(kGatherWG), 0, s, nodes, vt, bs, icnt,
                        (const ItemDesc*)desc, T1, T1id, T2, T2id, vox, vids);
   })
 }
 #undef LOD_MODE_SWITCH
 
-void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,
-                         const CloudInfo* clouds, uint32_t ntrees, const void* pts, void* out, hipStream_t s) {
-  if (!vtotal || !ntrees) return;
-  hipLaunchKernelGGL(k_voxel_points, dim3((uint32_t)((vtotal + 255) / 256)), dim3(256), 0, s, vox, vids, vtotal, trees,
-                     clouds, ntrees, (const uint4*)pts, (uint4*)out);
+void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vcap, const BuildState* bs,
+                         const TreeInfo* trees, const CloudInfo* clouds, uint32_t ntrees, const void* pts, void* out,
+                         hipStream_t s) {
+  if (!ntrees) return;
+  hipLaunchKernelGGL(k_voxel_points, dim3(grid_blocks(vcap, 256, 8192)), dim3(256), 0, s, vox, vids, bs, trees, clouds,
+                     ntrees, (const uint4*)pts, (uint4*)out);
 }
 
 }  // namespace lod

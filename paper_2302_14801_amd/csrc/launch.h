@@ -23,8 +23,11 @@ void launch_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, S
 void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t chunk, Chunk* chunks,
                         uint32_t* nchunk, uint32_t max_chunks, ChunkGroup* groups, uint32_t* ngroup,
                         uint32_t max_groups, hipStream_t st);
-void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
-                       const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st);
+// Counts of a partition: the cells of the points of every chunk (from the
+// records, or from `dig`, the 2-byte digits a previous insert wrote, if set).
+void launch_part_count(uint32_t E, const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs,
+                       const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist,
+                       hipStream_t st);
 void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const ChunkGroup* groups,
                          const uint32_t* ngroup, uint32_t max_groups, uint32_t E, uint32_t* hist, uint32_t* gsum,
                          const GridDesc* grids, uint32_t* pool, hipStream_t st);
@@ -32,14 +35,22 @@ void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_
                         uint32_t* pool, hipStream_t st);
 // Points per insert round of the partition scatter (with or without ids).
 uint32_t scatter_round(bool ids);
+// Insert of a partition.  dig_in: read every point's cell from these 2-byte
+// digits; dig_out: also write beside every record its cell of the E2 levels
+// below the E sorted here (the next partition's digit).  At most one is set.
 void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
-                         const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
-                         uint32_t max_chunks, const uint32_t* hist, const GridDesc* grids, const uint32_t* pool,
-                         hipStream_t st);
+                         const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2, const Cube* cube, const Segment* segs,
+                         const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, const uint32_t* hist,
+                         const GridDesc* grids, const uint32_t* pool, hipStream_t st);
 void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,
                           const uint32_t* nseg, uint32_t max_segs, hipStream_t st);
 void launch_segments_from_grid(GridDesc* grids, uint32_t ngrids, uint32_t* pool, uint32_t E2, uint64_t slot_base,
                                uint32_t first_grid, Segment* segs, uint32_t* nseg, hipStream_t st);
+// n words of v (a kernel: safe inside a captured graph, unlike a memset).
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
+// The build state at the start of a build: zero, with the grid and pool
+// counters at the grids and words the two main partitions reserve.
+void launch_build_init(BuildState* bs, uint32_t num_grids, uint64_t used_words, hipStream_t st);
 
 // k_tree.hip
 void launch_tree_init(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
@@ -48,28 +59,42 @@ void launch_tree_init(uint32_t leaf_cap, uint32_t max_level, const GridDesc* gri
 void launch_tree_build(uint32_t leaf_cap, uint32_t max_level, const GridDesc* grids, const uint32_t* pool,
                        const Nodes& nodes, TreeState* sts, uint32_t nclouds, uint32_t* refine, uint32_t* leaf_refine,
                        BuildState* bs, hipStream_t s);
+// Node table work sized by the capacity max_nodes; the real node count is
+// read from bs->total_nodes on the device.
 void launch_compact_nodes(const Nodes& src, const Nodes& dst, const TreeInfo* trees, const uint32_t* cap_begin,
-                          uint32_t ntrees, uint32_t total, hipStream_t s);
-void launch_finalize_nodes(const Nodes& nodes, const TreeInfo* trees, uint32_t total, uint8_t* o_level, uint8_t* o_leaf,
-                           uint8_t* o_mask, uint64_t* o_key, uint32_t* o_npts, uint32_t* o_count, uint32_t* o_first,
-                           uint64_t* o_off, hipStream_t s);
+                          uint32_t ntrees, uint32_t max_nodes, const BuildState* bs, hipStream_t s);
+void launch_finalize_nodes(const Nodes& nodes, const TreeInfo* trees, uint32_t max_nodes, const BuildState* bs,
+                           uint8_t* o_level, uint8_t* o_leaf, uint8_t* o_mask, uint64_t* o_key, uint32_t* o_npts,
+                           uint32_t* o_count, uint32_t* o_first, uint64_t* o_off, hipStream_t s);
+// Segments and grids for the nodes of `list` (*nlist of them, at most
+// max_list): grids numbered from bs->num_grids, storage from pool word
+// bs->used_words; refused (kOverGrids) beyond grid_cap / word_cap.
 void launch_refine_segments(const Nodes& nodes, const uint32_t* list, const uint32_t* nlist, uint32_t max_list,
-                            uint32_t E, uint32_t first_grid, uint64_t slot_base, GridDesc* grids, Segment* segs,
-                            uint32_t* nseg, hipStream_t s);
+                            uint32_t E, BuildState* bs, uint32_t grid_cap, uint64_t word_cap, GridDesc* grids,
+                            Segment* segs, uint32_t* nseg, hipStream_t s);
+void launch_refine_commit(BuildState* bs, const uint32_t* nseg, uint32_t E, hipStream_t s);
+// TreeInfo of every tree from its enumeration state; bs->total_nodes.
+void launch_tree_info(const TreeState* sts, const CloudInfo* clouds, uint32_t ntrees, TreeInfo* trees, BuildState* bs,
+                      hipStream_t s);
 
-// k_voxel.hip
-// Work-item descriptors: 64 bytes per item, 8 items per node.
-void launch_item_desc(const Nodes& nodes, uint32_t num_nodes, const GridDesc* grids, const uint32_t* pool,
-                      BuildState* bs, void* desc, hipStream_t s);
-void launch_leaf_voxels(uint32_t mode, uint32_t num_nodes, const void* desc, const void* pts, const uint32_t* ids,
+// k_voxel.hip (launches sized by the node capacity; counts on the device)
+// Work-item descriptors: 64 bytes per item, 8 items per node; coarse-list
+// blocks handed out from a pool of t2cap entries (kOverCoarse beyond).
+void launch_item_desc(const Nodes& nodes, uint32_t max_nodes, const GridDesc* grids, const uint32_t* pool,
+                      BuildState* bs, void* desc, uint64_t t2cap, hipStream_t s);
+// bs->item_next must be 0 (the work queue of the leaf kernel).
+void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, const void* desc, const void* pts, const uint32_t* ids,
                         const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2, uint32_t* T2id, uint32_t* icnt,
-                        uint64_t* iself, uint32_t seed, hipStream_t s);
-void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes, TreeInfo* trees,
-                       uint32_t ntrees, const uint32_t* icnt, const uint64_t* iself, uint32_t seed, hipStream_t s);
-void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t num_nodes,
+                        uint64_t* iself, uint32_t seed, BuildState* bs, hipStream_t s);
+// Piece sizes, depth-first order, voxel counts and offsets of every tree;
+// the trees' first voxels and bs->vtotal (kOverVoxels above vcap).
+void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t max_nodes, TreeInfo* trees,
+                       uint32_t ntrees, uint64_t vcap, const uint32_t* icnt, const uint64_t* iself, uint32_t seed,
+                       BuildState* bs, hipStream_t s);
+void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t max_nodes,
                          const TreeInfo* trees, const uint32_t* icnt, const void* desc, const uint64_t* T1,
                          const uint32_t* T1id, const uint64_t* T2, const uint32_t* T2id, uint64_t* vox, uint32_t* vids,
-                         hipStream_t s);
+                         const BuildState* bs, hipStream_t s);
 // Neighbourhood-weighted colours of all inner voxels (after the average
 // build), level by level.  lnodes: the node indices of the call grouped by
 // level, level L at [loff[L], loff[L + 1]) (loff: host array of deepest + 2
@@ -88,9 +113,10 @@ hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uin
                            uint32_t* slot_ctr, hipStream_t s);
 uint64_t weighted_bitmap_words();
 // Full-precision records (input coordinates of the accepted sample, voxel
-// colour) of the vtotal voxels of a call.
-void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vtotal, const TreeInfo* trees,
-                         const CloudInfo* clouds, uint32_t ntrees, const void* pts, void* out, hipStream_t s);
+// colour) of the bs->vtotal voxels of a call (at most vcap).
+void launch_voxel_points(const uint64_t* vox, const uint32_t* vids, uint64_t vcap, const BuildState* bs,
+                         const TreeInfo* trees, const CloudInfo* clouds, uint32_t ntrees, const void* pts, void* out,
+                         hipStream_t s);
 // Size of the coarse-list blocks of all work items, bounded from the node
 // count alone (for allocation before the item prefix is known).
 uint64_t coarse_space_bound(uint64_t n, uint32_t num_nodes);

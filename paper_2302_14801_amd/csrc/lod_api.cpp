@@ -15,13 +15,23 @@
 //   5. voxels of every leaf for all its ancestors up to 6 levels above it,
 //      then offsets and the gather into each tree's voxel list (Sec. 4.2,
 //      k_voxel.hip)
-// The host synchronises the stream once per enumeration round (to size and
-// launch refinements), once to size the voxel output, and at the end: a
-// constant number of times per call, however many clouds it builds.
+// Nothing is read back while the build runs.  Every capacity (segments,
+// chunks, grids, node slots, work items, voxel output) is fixed on the host
+// from the input sizes before the first kernel; the refinement rounds are
+// unrolled to the number the depth limit allows; counts that size later
+// work stay on the device, and launches are sized by the capacities with
+// kernels looping over the device counts.  The host reads the build state
+// once, after the last kernel: if a capacity chosen from an estimate (the
+// refinement grids, the voxel output) was too small, the build flagged it,
+// every later kernel returned at once, and the build runs again with the
+// capacities it reported.  Because the whole build is one sequence of
+// launches without host decisions, a batch is captured into a HIP graph and
+// launched as one graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -58,8 +68,7 @@ static void fail(lod_status st, const char* msg) { lod_fail(st, msg); }
 
 namespace {
 
-// Grow-only scratch buffer owned by a workspace.
-// Grow-only scratch buffer owned by a workspace.  A block outgrown during a
+// Grow-only device buffer owned by a workspace.  A block outgrown during a
 // build may still be read by kernels queued on the build's stream, and the
 // device cache is shared by every thread (the server builds on several
 // streams at once), so outgrown blocks are retired to the workspace and only
@@ -76,6 +85,8 @@ struct Scratch {
         if (retired) retired->push_back(p);
         else cache().release(dev, p);
       }
+      p = nullptr;
+      cap = 0;
       p = cache().alloc(dev, bytes);
       cap = bytes;
     }
@@ -117,25 +128,19 @@ struct Pinned {
 
 struct Workspace {
   int dev = 0;
-  Scratch X, Xid, bbox, cube, segs, chunks, counters, hist, grids, pool, pool2, refine, leaf_refine;
-  Scratch groups, gsum;
-  Scratch n_level, n_leaf, n_mask, n_key, n_npts, n_count, n_first, n_off, n_cover, n_grid, n_parent, n_tree;
-  Scratch c_level, c_leaf, c_mask, c_key, c_npts, c_count, c_first, c_off, c_cover, c_grid, c_parent, c_tree;
-  Scratch t2, t2id, icnt, idesc, iself, v_sz, v_dfs, v_dfsn, v_psize, v_poff, v_selfc, v_selfid;
-  Scratch state, bstate, clouds, trees, nbeg, wslot, wlist, wbits, wpre, wacc, wseg, wblk;
-  Pinned h_clouds, h_nbeg, h_states, h_trees, h_cubes, h_bs, h_wlist, h_wblk;
+  Scratch S;  // the device scratch region of a build
+  Pinned H;   // the host tables of a build (copied to the device, read back)
+  Scratch wslot, wlist, wbits, wpre, wacc, wseg, wblk;  // the weighted pass
+  Pinned h_wlist, h_wblk;
+  // capacities learned from earlier builds (grow-only; they change only how
+  // often a build has to be repeated, never its result)
+  double ref_grids_per_point = 0.0, voxels_per_point = 0.0, coarse_per_point = 0.0;
+  hipStream_t capture = nullptr;   // stream used only to record graphs
+  hipGraphExec_t exec = nullptr;   // the last graph instantiated here
   std::vector<void*> retired;  // outgrown blocks, released when the build's stream has drained
   hipEvent_t ev[16] = {};
   bool ev_ready = false;
-  std::vector<Scratch*> scratches() {
-    return {&X,       &Xid,     &bbox,    &cube,    &segs,     &chunks,  &counters, &hist,    &grids,
-            &pool,    &pool2,   &refine,  &leaf_refine, &groups, &gsum,     &n_level, &n_leaf,  &n_mask,
-            &n_key,   &n_npts,  &n_count, &n_first, &n_off,    &n_cover, &n_grid,   &n_parent, &n_tree,
-            &c_level, &c_leaf,  &c_mask,  &c_key,   &c_npts,   &c_count, &c_first,  &c_off,   &c_cover,
-            &c_grid,  &c_parent, &c_tree, &t2,      &t2id,     &icnt,    &idesc,    &iself,   &v_sz,
-            &v_dfs,   &v_dfsn,  &v_psize, &v_poff,  &v_selfc,  &v_selfid, &state,   &bstate,  &clouds,
-            &trees,   &nbeg,    &wslot,   &wlist,   &wbits,   &wpre,    &wacc,    &wseg,    &wblk};
-  }
+  std::vector<Scratch*> scratches() { return {&S, &wslot, &wlist, &wbits, &wpre, &wacc, &wseg, &wblk}; }
   Workspace() {
     for (Scratch* sc : scratches()) sc->retired = &retired;
   }
@@ -147,6 +152,8 @@ struct Workspace {
   ~Workspace() {
     if (ev_ready)
       for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (capture) (void)hipStreamDestroy(capture);
     flush_retired();
     for (Scratch* sc : scratches()) sc->drop(dev);
   }
@@ -201,10 +208,10 @@ struct DrainOnUnwind {
 enum { EV_START, EV_BBOX, EV_COUNT0, EV_OFF0, EV_SCAT0, EV_COUNT1, EV_OFF1, EV_SCAT1, EV_TREE, EV_LEAF, EV_LEVELS,
        EV_NUM };
 struct StageTimer {
-  Workspace& w;
+  hipEvent_t* ev;
   hipStream_t s;
   bool on;
-  StageTimer(Workspace& ws, hipStream_t st, bool enabled) : w(ws), s(st), on(enabled) {
+  StageTimer(Workspace& w, hipStream_t st, bool enabled) : ev(w.ev), s(st), on(enabled) {
     if (on && !w.ev_ready) {
       for (int i = 0; i < EV_NUM; ++i)
         if (hipEventCreate(&w.ev[i]) != hipSuccess) {
@@ -216,17 +223,20 @@ struct StageTimer {
     }
   }
   void mark(int i) {
-    if (on) (void)hipEventRecord(w.ev[i], s);
+    if (on) (void)hipEventRecord(ev[i], s);
   }
   float ms(int a, int b) {
     float t = 0.f;
-    if (on && hipEventElapsedTime(&t, w.ev[a], w.ev[b]) != hipSuccess) {
+    if (on && hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) {
       (void)hipGetLastError();
       t = 0.f;
     }
     return t;
   }
 };
+void mark(StageTimer* tm, int i) {
+  if (tm) tm->mark(i);
+}
 
 }  // namespace
 
@@ -270,145 +280,362 @@ Plan make_plan(uint64_t n_typical, uint64_t n_total, const lod_params& p) {
   return pl;
 }
 
-Nodes node_ptrs(Workspace& w, uint32_t cap) {
-  Nodes nd;
-  nd.level = w.n_level.get<uint8_t>(w.dev, cap);
-  nd.is_leaf = w.n_leaf.get<uint8_t>(w.dev, cap);
-  nd.child_mask = w.n_mask.get<uint8_t>(w.dev, cap);
-  nd.key = w.n_key.get<uint64_t>(w.dev, cap);
-  nd.npoints = w.n_npts.get<uint32_t>(w.dev, cap);
-  nd.count = w.n_count.get<uint32_t>(w.dev, cap);
-  nd.first_child = w.n_first.get<uint32_t>(w.dev, cap);
-  nd.offset = w.n_off.get<uint64_t>(w.dev, cap);
-  nd.cover = w.n_cover.get<int32_t>(w.dev, cap);
-  nd.grid = w.n_grid.get<int32_t>(w.dev, cap);
-  nd.parent = w.n_parent.get<uint32_t>(w.dev, cap);
-  nd.tree = w.n_tree.get<uint32_t>(w.dev, cap);
-  return nd;
+// Node slots a tree of n points can need: every inner node has more than T
+// points, so a level holds at most n / (T + 1) of them (and at most 8^L),
+// and every node but the root is the child of an inner node.
+uint64_t tree_node_cap(uint64_t n, uint32_t T, uint32_t ML) {
+  const uint64_t inner = n / ((uint64_t)T + 1);
+  uint64_t s = 0, p = 1;
+  for (uint32_t L = 0; L < ML; ++L) {
+    s += std::min(p, inner);
+    if (p < (1ull << 40)) p *= 8;
+  }
+  return 1 + 8 * s + 8;
 }
 
-Nodes compact_ptrs(Workspace& w, uint32_t cap) {
-  Nodes nd;
-  nd.level = w.c_level.get<uint8_t>(w.dev, cap);
-  nd.is_leaf = w.c_leaf.get<uint8_t>(w.dev, cap);
-  nd.child_mask = w.c_mask.get<uint8_t>(w.dev, cap);
-  nd.key = w.c_key.get<uint64_t>(w.dev, cap);
-  nd.npoints = w.c_npts.get<uint32_t>(w.dev, cap);
-  nd.count = w.c_count.get<uint32_t>(w.dev, cap);
-  nd.first_child = w.c_first.get<uint32_t>(w.dev, cap);
-  nd.offset = w.c_off.get<uint64_t>(w.dev, cap);
-  nd.cover = w.c_cover.get<int32_t>(w.dev, cap);
-  nd.grid = w.c_grid.get<int32_t>(w.dev, cap);
-  nd.parent = w.c_parent.get<uint32_t>(w.dev, cap);
-  nd.tree = w.c_tree.get<uint32_t>(w.dev, cap);
-  return nd;
+// Capacities of one build call, fixed before anything is enqueued.
+struct Caps {
+  uint64_t N = 0;
+  uint32_t nc = 0;
+  uint64_t passb = 0;     // segments of the second partition (one per possible root cell)
+  uint32_t rounds = 0;    // refinement rounds of inner nodes
+  uint32_t ref_grids = 0; // refinement grids over all rounds (estimate)
+  uint32_t segs = 0, chunks = 0, groups = 0;
+  uint64_t hist = 0, gsum = 0;  // words of histogram rows and group sums
+  uint32_t grids0 = 0;    // grid descriptors of the two main partitions
+  uint64_t words0 = 0;    // their pool words
+  uint32_t grids = 0;     // all grid descriptors
+  uint64_t words = 0;     // all pool words
+  uint32_t max_nodes = 0; // node slots of all trees
+  uint64_t t2cap = 0;     // coarse-list entries
+  uint64_t vcap = 0;      // output voxels (estimate)
+};
+
+void part_caps(Caps& c, uint64_t N, uint32_t chunk, uint32_t max_segs, uint32_t E) {
+  const uint64_t chunks = (uint64_t)ceil_div(N, chunk) + max_segs;
+  const uint64_t groups = (uint64_t)ceil_div(chunks, kGroupChunks) + max_segs;
+  if (chunks >= 0xffffffffull || groups >= 0xffffffffull) fail(LOD_ERR_CAPACITY, "partition work list too long");
+  c.chunks = std::max<uint32_t>(c.chunks, (uint32_t)chunks);
+  c.groups = std::max<uint32_t>(c.groups, (uint32_t)groups);
+  c.hist = std::max<uint64_t>(c.hist, chunks << (3 * E));
+  c.gsum = std::max<uint64_t>(c.gsum, groups << (3 * E));
+  c.segs = std::max<uint32_t>(c.segs, max_segs);
 }
 
-VoxTree vox_ptrs(Workspace& w, uint32_t num_nodes) {
-  VoxTree vt;
-  const size_t c = std::max<uint32_t>(num_nodes, 1);
-  vt.sz = w.v_sz.get<uint32_t>(w.dev, c);
-  vt.dfs = w.v_dfs.get<uint32_t>(w.dev, c);
-  vt.dfs_node = w.v_dfsn.get<uint32_t>(w.dev, c);
-  vt.psize = w.v_psize.get<uint32_t>(w.dev, 8 * c);
-  vt.poff = w.v_poff.get<uint64_t>(w.dev, 8 * c);
-  vt.selfc = w.v_selfc.get<uint32_t>(w.dev, c);
-  vt.selfid = w.v_selfid.get<uint32_t>(w.dev, c);
-  return vt;
+// sizes: points of every (non-empty) cloud; ref_grids, vcap, t2cap:
+// capacities of the estimated pools (0 = default estimate).
+Caps make_caps(const Plan& pl, const uint64_t* sizes, uint32_t nc, uint64_t N, const lod_params& p,
+               uint64_t ref_grids, uint64_t vcap, uint64_t t2cap = 0) {
+  Caps c;
+  c.N = N;
+  c.nc = nc;
+  const uint64_t root_cells = 1ull << (3 * pl.E0);
+  uint64_t nodes = 0, inner_per_level = 0;
+  for (uint32_t i = 0; i < nc; ++i) {
+    c.passb += std::min<uint64_t>(root_cells, sizes[i]);
+    nodes += tree_node_cap(sizes[i], p.leaf_cap, p.max_level);
+    inner_per_level += sizes[i] / ((uint64_t)p.leaf_cap + 1);
+  }
+  if (nodes >= 0x7fffffffull) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
+  c.max_nodes = (uint32_t)nodes;
+  const uint32_t D0 = pl.E0 + pl.E1;
+  c.rounds = p.max_level > D0 ? (p.max_level - D0 + 3) / 4 : 0;
+  // refinement grids: inner nodes at the deepest sorted level of a round
+  // (at most n / (T + 1) per tree) and leaves that lie fewer than two levels
+  // above their grid's deepest level; an estimate, checked on the device
+  if (!ref_grids) ref_grids = 256 + 2 * inner_per_level;
+  c.ref_grids = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(ref_grids, nodes), 0x7fffffffull);
+  part_caps(c, N, pl.chunk0, nc, pl.E0);
+  part_caps(c, N, pl.chunk1, (uint32_t)c.passb, pl.E1);
+  part_caps(c, N, pl.chunk_ref, c.ref_grids, 4);
+  c.segs = std::max<uint32_t>(c.segs, 1);
+  c.grids0 = (uint32_t)(nc + c.passb);
+  c.words0 = (uint64_t)nc * grid_words(pl.E0) + c.passb * grid_words(pl.E1);
+  c.grids = c.grids0 + c.ref_grids;
+  c.words = c.words0 + (uint64_t)c.ref_grids * grid_words(4);
+  // coarse lists: at most min(5p, 4681) entries per item of p points; the
+  // pool is an estimate (about one entry per point), checked on the device
+  const uint64_t t2max = coarse_space_bound(N, c.max_nodes);
+  c.t2cap = std::min<uint64_t>(t2max, t2cap ? t2cap : N + N / 2 + 65536);
+  c.vcap = vcap ? vcap : N + 64;
+  return c;
 }
 
-// Grid storage grows on demand; descriptors hold offsets, so relocation is a copy.
-struct GridPool {
-  Workspace& w;
-  uint64_t used_words = 0;
-  uint32_t num_grids = 0;
-  uint32_t cap_grids = 0;
-  uint64_t cap_words = 0;
-  GridDesc* grids = nullptr;
-  uint32_t* pool = nullptr;
-  hipStream_t s;
-  GridPool(Workspace& ws, hipStream_t st) : w(ws), s(st) {}
-  void reserve(uint32_t grids_needed, uint64_t words_needed) {
-    if (grids_needed > cap_grids) {
-      uint32_t nc = std::max<uint32_t>(grids_needed, cap_grids * 2);
-      if (w.grids.cap >= (size_t)nc * sizeof(GridDesc) || num_grids == 0) {
-        grids = w.grids.get<GridDesc>(w.dev, nc);
-      } else {
-        GridDesc* old = grids;
-        Scratch tmp;
-        GridDesc* nw = tmp.get<GridDesc>(w.dev, nc);
-        HIPCHK(hipMemcpyAsync(nw, old, sizeof(GridDesc) * num_grids, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-        w.grids.drop(w.dev);
-        tmp.retired = w.grids.retired;
-        w.grids = tmp;
-        grids = nw;
-      }
-      cap_grids = nc;
-    }
-    if (words_needed > cap_words) {
-      uint64_t nc = std::max<uint64_t>(words_needed, cap_words * 2);
-      if (w.pool.cap >= nc * 4 || used_words == 0) {
-        pool = w.pool.get<uint32_t>(w.dev, nc);
-      } else {
-        uint32_t* old = pool;
-        Scratch tmp;
-        uint32_t* nw = tmp.get<uint32_t>(w.dev, nc);
-        HIPCHK(hipMemcpyAsync(nw, old, 4ull * used_words, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-        w.pool.drop(w.dev);
-        tmp.retired = w.pool.retired;
-        w.pool = tmp;
-        pool = nw;
-      }
-      cap_words = nc;
-    }
+// Bump allocation of the buffers of one build in a region (256-byte
+// aligned); with a null base only the size is computed.
+struct Carve {
+  char* base;
+  uint64_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(uint64_t count) {
+    off = (off + 255) & ~255ull;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += std::max<uint64_t>(count, 1) * sizeof(T);
+    return p;
   }
 };
 
-// Partition `nseg` segments (device list, at most max_segs, covering at most
-// max_points points) by E levels from src into dst.
-void partition(Workspace& w, GridPool& gp, uint32_t E, uint32_t chunk, uint32_t max_segs, uint64_t max_points,
-               const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, bool ids, Segment* segs,
-               uint32_t* nseg, const Cube* cube, hipStream_t s, StageTimer* tm = nullptr, int ev0 = 0) {
+// Every buffer of a build: device scratch (S), device output owned by the
+// trees (O), host tables (H).
+struct Bufs {
+  uint4* X;
+  uint32_t* Xid;
+  uint16_t* Xdig;
+  BBoxAcc* bbox;
+  Cube* cube;
+  CloudInfo* clouds;
+  Segment* segs;
+  uint32_t* ctr;
+  Chunk* chunks;
+  ChunkGroup* groups;
+  uint32_t *hist, *gsum;
+  GridDesc* grids;
+  uint32_t* pool;
+  Nodes nd, cn;  // node slots per tree; compact table (the same with one tree)
+  uint32_t *refine, *leaf_refine;
+  TreeState* st;
+  BuildState* bs;
+  uint32_t* nbeg;
+  TreeInfo* tinfo;
+  ItemDesc* desc;
+  uint32_t* icnt;
+  uint64_t* iself;
+  uint64_t* T2;
+  uint32_t* T2id;
+  VoxTree vt;
+  lod_point* Y;
+  uint32_t* Yid;
+  uint64_t* vox;
+  uint32_t* vids;
+  lod_point* vpts;
+  uint8_t *o_level, *o_leaf, *o_mask;
+  uint64_t* o_key;
+  uint32_t *o_npts, *o_count, *o_first;
+  uint64_t* o_off;
+  CloudInfo* h_clouds;
+  uint32_t* h_nbeg;
+  Cube* h_cube_in;
+  BuildState* h_bs;
+  TreeInfo* h_trees;
+  Cube* h_cubes;
+};
+
+void take_nodes(Carve& s, Nodes& nd, uint32_t cap) {
+  nd.level = s.take<uint8_t>(cap);
+  nd.is_leaf = s.take<uint8_t>(cap);
+  nd.child_mask = s.take<uint8_t>(cap);
+  nd.key = s.take<uint64_t>(cap);
+  nd.npoints = s.take<uint32_t>(cap);
+  nd.count = s.take<uint32_t>(cap);
+  nd.first_child = s.take<uint32_t>(cap);
+  nd.offset = s.take<uint64_t>(cap);
+  nd.cover = s.take<int32_t>(cap);
+  nd.grid = s.take<int32_t>(cap);
+  nd.parent = s.take<uint32_t>(cap);
+  nd.tree = s.take<uint32_t>(cap);
+}
+
+struct RegionSizes {
+  uint64_t scratch, out, host;
+};
+
+RegionSizes layout(Bufs& b, const Caps& c, const Plan& pl, bool cube_given, bool want_vpts, void* S, void* O, void* H) {
+  Carve s(S), o(O), h(H);
+  b.X = s.take<uint4>(c.N);
+  b.Xid = s.take<uint32_t>(pl.ids ? c.N : 1);
+  b.Xdig = s.take<uint16_t>(c.N);
+  b.bbox = s.take<BBoxAcc>(c.nc);
+  b.cube = s.take<Cube>(c.nc);
+  b.clouds = s.take<CloudInfo>(c.nc);
+  b.segs = s.take<Segment>(c.segs);
+  b.ctr = s.take<uint32_t>(16);
+  b.chunks = s.take<Chunk>(c.chunks);
+  b.groups = s.take<ChunkGroup>(c.groups);
+  b.hist = s.take<uint32_t>(c.hist);
+  b.gsum = s.take<uint32_t>(c.gsum);
+  b.grids = s.take<GridDesc>(c.grids);
+  b.pool = s.take<uint32_t>(c.words);
+  take_nodes(s, b.nd, c.max_nodes);
+  if (c.nc > 1) take_nodes(s, b.cn, c.max_nodes);
+  else b.cn = b.nd;
+  b.refine = s.take<uint32_t>(c.max_nodes);
+  b.leaf_refine = s.take<uint32_t>(c.max_nodes);
+  b.st = s.take<TreeState>(c.nc);
+  b.bs = s.take<BuildState>(1);
+  b.nbeg = s.take<uint32_t>(2ull * c.nc);
+  b.tinfo = s.take<TreeInfo>(c.nc);
+  const uint64_t items = 8ull * c.max_nodes;
+  b.desc = s.take<ItemDesc>(items);
+  b.icnt = s.take<uint32_t>(6 * items);
+  b.iself = s.take<uint64_t>(items);
+  b.T2 = s.take<uint64_t>(c.t2cap);
+  b.T2id = pl.mode ? s.take<uint32_t>(c.t2cap) : nullptr;
+  b.vt.sz = s.take<uint32_t>(c.max_nodes);
+  b.vt.dfs = s.take<uint32_t>(c.max_nodes);
+  b.vt.dfs_node = s.take<uint32_t>(c.max_nodes);
+  b.vt.psize = s.take<uint32_t>(8ull * c.max_nodes);
+  b.vt.poff = s.take<uint64_t>(8ull * c.max_nodes);
+  b.vt.selfc = s.take<uint32_t>(c.max_nodes);
+  b.vt.selfid = s.take<uint32_t>(c.max_nodes);
+  b.Y = o.take<lod_point>(c.N);
+  b.Yid = pl.ids ? o.take<uint32_t>(c.N) : nullptr;
+  b.vox = o.take<uint64_t>(c.vcap);
+  b.vids = pl.mode ? o.take<uint32_t>(c.vcap) : nullptr;
+  b.vpts = want_vpts ? o.take<lod_point>(c.vcap) : nullptr;
+  b.o_level = o.take<uint8_t>(c.max_nodes);
+  b.o_leaf = o.take<uint8_t>(c.max_nodes);
+  b.o_mask = o.take<uint8_t>(c.max_nodes);
+  b.o_key = o.take<uint64_t>(c.max_nodes);
+  b.o_npts = o.take<uint32_t>(c.max_nodes);
+  b.o_count = o.take<uint32_t>(c.max_nodes);
+  b.o_first = o.take<uint32_t>(c.max_nodes);
+  b.o_off = o.take<uint64_t>(c.max_nodes);
+  b.h_clouds = h.take<CloudInfo>(c.nc);
+  b.h_nbeg = h.take<uint32_t>(2ull * c.nc);
+  b.h_cube_in = cube_given ? h.take<Cube>(c.nc) : nullptr;
+  b.h_bs = h.take<BuildState>(1);
+  b.h_trees = h.take<TreeInfo>(c.nc);
+  b.h_cubes = h.take<Cube>(c.nc);
+  return {s.off, o.off, h.off};
+}
+
+// Partition `nseg` segments (device count, at most max_segs, covering at most
+// max_points points) by E levels from src into dst.  dig_in: the points'
+// cells of this partition as 2-byte digits (instead of computing them from
+// the records); dig_out: write the digits of the next partition's E2 levels
+// beside the output records.
+void partition(const Bufs& b, uint32_t E, uint32_t chunk, uint32_t max_segs, uint64_t max_points, const void* src,
+               const uint32_t* src_ids, void* dst, uint32_t* dst_ids, bool ids, uint32_t* nseg, hipStream_t s,
+               StageTimer* tm, int ev0, const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2) {
   uint32_t* nchunk = nseg + 1;
   uint32_t* ngroup = nseg + 2;
   const uint32_t max_chunks = ceil_div(max_points, chunk) + max_segs;
   const uint32_t max_groups = ceil_div(max_chunks, kGroupChunks) + max_segs;
-  Chunk* chunks = w.chunks.get<Chunk>(w.dev, max_chunks);
-  ChunkGroup* groups = w.groups.get<ChunkGroup>(w.dev, max_groups);
-  uint32_t* hist = w.hist.get<uint32_t>(w.dev, (size_t)max_chunks << (3 * E));
-  uint32_t* gsum = w.gsum.get<uint32_t>(w.dev, (size_t)max_groups << (3 * E));
-  launch_make_chunks(segs, nseg, max_segs, chunk, chunks, nchunk, max_chunks, groups, ngroup, max_groups, s);
-  launch_part_count(E, src, cube, segs, chunks, nchunk, max_chunks, hist, s);
-  if (tm) tm->mark(ev0);
-  launch_part_colscan(segs, nseg, max_segs, groups, ngroup, max_groups, E, hist, gsum, gp.grids, gp.pool, s);
-  launch_grid_finish(segs, nseg, max_segs, gp.grids, gp.pool, s);
-  if (tm) tm->mark(ev0 + 1);
-  launch_part_scatter(E, ids, src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, hist, gp.grids,
-                      gp.pool, s);
-  if (tm) tm->mark(ev0 + 2);
+  launch_make_chunks(b.segs, nseg, max_segs, chunk, b.chunks, nchunk, max_chunks, b.groups, ngroup, max_groups, s);
+  launch_part_count(E, src, dig_in, b.cube, b.segs, b.chunks, nchunk, max_chunks, b.hist, s);
+  if (ev0) mark(tm, ev0);
+  launch_part_colscan(b.segs, nseg, max_segs, b.groups, ngroup, max_groups, E, b.hist, b.gsum, b.grids, b.pool, s);
+  launch_grid_finish(b.segs, nseg, max_segs, b.grids, b.pool, s);
+  if (ev0) mark(tm, ev0 + 1);
+  launch_part_scatter(E, ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, b.cube, b.segs, b.chunks, nchunk,
+                      max_chunks, b.hist, b.grids, b.pool, s);
+  if (ev0) mark(tm, ev0 + 2);
   HIPCHK(hipGetLastError());
 }
 
-// Refine the nodes in `list` (count known on the host): partition their
-// points by 4 more levels (Y -> X), copy back, attach the new grids.
-void refine_nodes(Workspace& w, GridPool& gp, const Nodes& nd, uint32_t* list, uint32_t count, uint64_t n, void* Y,
-                  uint32_t* Yid, bool ids, const Cube* cube, uint32_t chunk, hipStream_t s) {
+// Refine the nodes of `list` (*nlist of them, a device count): partition
+// their points by 4 more levels (Y -> X), copy back, attach the new grids.
+void refine(const Bufs& b, const Caps& c, const Plan& pl, const uint32_t* list, const uint32_t* nlist,
+            hipStream_t s) {
   const uint32_t E = 4;
-  const uint32_t first = gp.num_grids;
-  const uint64_t slot = gp.used_words;
-  gp.reserve(first + count, slot + (uint64_t)count * grid_words(E));
-  Segment* segs = w.segs.get<Segment>(w.dev, std::max<uint32_t>(count, 1));
-  uint32_t* ctr = w.counters.get<uint32_t>(w.dev, 16);
-  uint32_t* nseg = ctr + 4;
-  HIPCHK(hipMemcpyAsync(nseg, &count, 4, hipMemcpyHostToDevice, s));
-  launch_refine_segments(nd, list, nseg, count, E, first, slot, gp.grids, segs, nseg, s);
-  partition(w, gp, E, chunk, count, n, Y, Yid, w.X.p, (uint32_t*)w.Xid.p, ids, segs, nseg, cube, s);
-  launch_copy_segments(w.X.p, (const uint32_t*)w.Xid.p, Y, ids ? Yid : nullptr, segs, nseg, count, s);
+  uint32_t* nseg = b.ctr + 4;
+  launch_refine_segments(b.nd, list, nlist, c.max_nodes, E, b.bs, c.grids, c.words, b.grids, b.segs, nseg, s);
+  partition(b, E, pl.chunk_ref, c.ref_grids, c.N, b.Y, b.Yid, b.X, b.Xid, pl.ids, nseg, s, nullptr, 0, nullptr,
+            nullptr, 0);
+  launch_copy_segments(b.X, b.Xid, b.Y, pl.ids ? b.Yid : nullptr, b.segs, nseg, c.ref_grids, s);
+  launch_refine_commit(b.bs, nseg, E, s);
   HIPCHK(hipGetLastError());
-  gp.num_grids = first + count;
-  gp.used_words = slot + (uint64_t)count * grid_words(E);
+}
+
+// The whole build, from the host tables to the read-back of the build state:
+// launches and copies only, no synchronisation (so it can be captured).
+void enqueue(const Bufs& b, const Caps& c, const Plan& pl, const lod_params& prm, const lod_point* in,
+             const uint32_t* in_ids, uint32_t ntiles, bool cube_given, hipStream_t s, StageTimer* tm) {
+  const uint32_t nc = c.nc;
+  mark(tm, EV_START);
+  launch_build_init(b.bs, c.grids0, c.words0, s);
+  HIPCHK(hipMemcpyAsync(b.clouds, b.h_clouds, sizeof(CloudInfo) * nc, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(b.nbeg, b.h_nbeg, 8ull * nc, hipMemcpyHostToDevice, s));
+  // 1. bounding boxes and cubes (or the one cube given for all clouds)
+  if (cube_given) HIPCHK(hipMemcpyAsync(b.cube, b.h_cube_in, sizeof(Cube) * nc, hipMemcpyHostToDevice, s));
+  else launch_bbox(in, b.clouds, nc, ntiles, b.bbox, b.cube, s);
+  mark(tm, EV_BBOX);
+  // 2. root partition, input -> X, with every point's cell of the second
+  // partition as a 2-byte digit beside it
+  uint32_t* nseg = b.ctr;
+  launch_init_roots(b.clouds, nc, pl.E0, b.segs, nseg, b.grids, s);
+  partition(b, pl.E0, pl.chunk0, nc, c.N, in, in_ids, b.X, b.Xid, pl.ids, nseg, s, tm, EV_COUNT0, nullptr, b.Xdig,
+            pl.E1);
+  // 3. every root cell by E1 more levels, X -> Y
+  launch_fill_u32(nseg, 0, 1, s);
+  launch_segments_from_grid(b.grids, nc, b.pool, pl.E1, (uint64_t)nc * grid_words(pl.E0), nc, b.segs, nseg, s);
+  partition(b, pl.E1, pl.chunk1, (uint32_t)c.passb, c.N, b.X, b.Xid, b.Y, b.Yid, pl.ids, nseg, s, tm, EV_COUNT1,
+            b.Xdig, nullptr, 0);
+  // 4. nodes: one region of slots per tree, enumeration resumed after each
+  // refinement round (a round without nodes to refine does nothing)
+  launch_tree_init(prm.leaf_cap, prm.max_level, b.grids, b.pool, b.nd, b.st, b.nbeg, b.nbeg + nc, nc, s);
+  for (uint32_t r = 0; r <= c.rounds; ++r) {
+    launch_fill_u32(&b.bs->nref, 0, 1, s);
+    launch_tree_build(prm.leaf_cap, prm.max_level, b.grids, b.pool, b.nd, b.st, nc, b.refine, b.leaf_refine, b.bs, s);
+    if (r < c.rounds) refine(b, c, pl, b.refine, &b.bs->nref, s);
+  }
+  refine(b, c, pl, b.leaf_refine, &b.bs->nlref, s);
+  launch_tree_info(b.st, b.clouds, nc, b.tinfo, b.bs, s);
+  if (nc > 1) launch_compact_nodes(b.nd, b.cn, b.tinfo, b.nbeg, nc, c.max_nodes, b.bs, s);
+  HIPCHK(hipGetLastError());
+  mark(tm, EV_TREE);
+  // 5. voxels: every leaf's lists for its ancestors up to 6 levels above it
+  // (depth 1 into X, coarser ones into T2), the tree pass and the offsets,
+  // then the pieces' positions and the gather
+  uint64_t* T1 = (uint64_t*)b.X;
+  launch_item_desc(b.cn, c.max_nodes, b.grids, b.pool, b.bs, b.desc, c.t2cap, s);
+  launch_leaf_voxels(pl.mode, c.max_nodes, b.desc, b.Y, b.Yid, b.cube, T1, b.Xid, b.T2, b.T2id, b.icnt, b.iself,
+                     prm.seed, b.bs, s);
+  mark(tm, EV_LEAF);
+  launch_voxel_tree(pl.mode, b.cn, b.vt, c.max_nodes, b.tinfo, nc, c.vcap, b.icnt, b.iself, prm.seed, b.bs, s);
+  launch_voxel_gather(pl.mode, b.cn, b.vt, c.max_nodes, b.tinfo, b.icnt, b.desc, T1, b.Xid, b.T2, b.T2id, b.vox,
+                      b.vids, b.bs, s);
+  // full-precision records take the voxel colours: after the weighted pass
+  if (b.vpts && !pl.weighted)
+    launch_voxel_points(b.vox, b.vids, c.vcap, b.bs, b.tinfo, b.clouds, nc, in, b.vpts, s);
+  HIPCHK(hipGetLastError());
+  mark(tm, EV_LEVELS);
+  // 6. output node tables (per-tree indices and offsets)
+  launch_finalize_nodes(b.cn, b.tinfo, c.max_nodes, b.bs, b.o_level, b.o_leaf, b.o_mask, b.o_key, b.o_npts,
+                        b.o_count, b.o_first, b.o_off, s);
+  HIPCHK(hipGetLastError());
+  // 7. the one read-back of the build
+  HIPCHK(hipMemcpyAsync(b.h_bs, b.bs, sizeof(BuildState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(b.h_trees, b.tinfo, sizeof(TreeInfo) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(b.h_cubes, b.cube, sizeof(Cube) * nc, hipMemcpyDeviceToHost, s));
+}
+
+// Record the build into a graph on the workspace's capture stream and run it
+// on `s` as one graph launch.  The executable graph is kept and updated in
+// place for the next build of the same shape (only pointers and sizes
+// differ), or instantiated again.
+void run_as_graph(Workspace& w, const Bufs& b, const Caps& c, const Plan& pl, const lod_params& prm,
+                  const lod_point* in, const uint32_t* in_ids, uint32_t ntiles, bool cube_given, hipStream_t s) {
+  if (!w.capture) HIPCHK(hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(w.capture, hipStreamCaptureModeRelaxed));
+  hipGraph_t g = nullptr;
+  try {
+    enqueue(b, c, pl, prm, in, in_ids, ntiles, cube_given, w.capture, nullptr);
+  } catch (...) {
+    (void)hipStreamEndCapture(w.capture, &g);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(w.capture, &g));
+  struct GraphGuard {
+    hipGraph_t g;
+    ~GraphGuard() {
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } guard{g};
+  if (w.exec) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res;
+    if (hipGraphExecUpdate(w.exec, g, &err_node, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(w.exec);
+      w.exec = nullptr;
+    }
+  }
+  if (!w.exec) HIPCHK(hipGraphInstantiate(&w.exec, g, nullptr, nullptr, 0));
+  HIPCHK(hipGraphLaunch(w.exec, s));
 }
 
 }  // namespace
@@ -444,170 +671,70 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   std::vector<uint64_t> sorted = sizes;
   std::nth_element(sorted.begin(), sorted.begin() + nc / 2, sorted.end());
   const Plan pl = make_plan(sorted[nc / 2], N, prm);
-  const bool ids = pl.ids;
-
-  // cloud table
-  CloudInfo* hci = w.h_clouds.get<CloudInfo>(nc);
-  uint32_t ntiles = 0;
-  uint64_t passb_bound = 0;
-  const uint64_t root_cells = 1ull << (3 * pl.E0);
-  for (uint32_t c = 0; c < nc; ++c) {
-    hci[c].start = (uint32_t)(offs[active[c]] - offs[0]);
-    hci[c].count = (uint32_t)sizes[c];
-    hci[c].tile_base = ntiles;
-    hci[c].pad = 0;
-    ntiles += bbox_tiles(hci[c].count);
-    passb_bound += std::min<uint64_t>(root_cells, sizes[c]);
-  }
-  CloudInfo* clouds = w.clouds.get<CloudInfo>(dev, nc);
-  HIPCHK(hipMemcpyAsync(clouds, hci, sizeof(CloudInfo) * nc, hipMemcpyHostToDevice, s));
-
-  // outputs that do not depend on the tree shapes
-  std::shared_ptr<LodArena> arena = std::make_shared<LodArena>();
-  arena->dev = dev;
-  DrainOnUnwind drain(s);
-  lod_point* Y = arena->alloc<lod_point>(N);
-  uint32_t* Yid = ids ? arena->alloc<uint32_t>(N) : nullptr;
-  // scratch
-  void* X = w.X.get<uint4>(dev, N);
-  uint32_t* Xid = w.Xid.get<uint32_t>(dev, ids ? N : 1);
-  BBoxAcc* bb = w.bbox.get<BBoxAcc>(dev, nc);
-  Cube* cube = w.cube.get<Cube>(dev, nc);
-  uint32_t* ctr = w.counters.get<uint32_t>(dev, 16);
-  BuildState* bs = w.bstate.get<BuildState>(dev, 1);
-  HIPCHK(hipMemsetAsync(bs, 0, sizeof(BuildState), s));
-
-  GridPool gp(w, s);
-  gp.reserve((uint32_t)(nc + passb_bound), (uint64_t)nc * grid_words(pl.E0) + passb_bound * grid_words(pl.E1));
-
-  StageTimer tm(w, s, (prm.flags & LOD_FLAG_TIMING) != 0);
-  tm.mark(EV_START);
-  // 1. bounding boxes and cubes (or the one cube given for all clouds)
-  if (x && x->cube) {
-    Cube* hgc = w.h_cubes.get<Cube>(nc);
-    for (uint32_t c = 0; c < nc; ++c) hgc[c] = *(const Cube*)x->cube;
-    HIPCHK(hipMemcpyAsync(cube, hgc, sizeof(Cube) * nc, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));  // the pinned table is refilled below
-  } else {
-    launch_bbox(in, clouds, nc, ntiles, bb, cube, s);
-  }
-  tm.mark(EV_BBOX);
-  // 2. root partition, input -> X
-  Segment* segs = w.segs.get<Segment>(dev, std::max<uint64_t>(std::max<uint64_t>(passb_bound, nc), 1));
-  uint32_t* nseg = ctr;
-  launch_init_roots(clouds, nc, pl.E0, segs, nseg, gp.grids, s);
+  const bool cube_given = x && x->cube;
+  const bool want_vpts = pl.full && !(x && x->ids_only);
   const uint32_t* in_ids = x && x->d_ids ? x->d_ids + offs[0] : nullptr;
-  partition(w, gp, pl.E0, pl.chunk0, nc, N, in, in_ids, X, Xid, ids, segs, nseg, cube, s, &tm, EV_COUNT0);
-  gp.num_grids = nc;
-  gp.used_words = (uint64_t)nc * grid_words(pl.E0);
-  // 3. every root cell by E1 more levels, X -> Y
-  HIPCHK(hipMemsetAsync(nseg, 0, sizeof(uint32_t), s));
-  launch_segments_from_grid(gp.grids, nc, gp.pool, pl.E1, gp.used_words, nc, segs, nseg, s);
-  partition(w, gp, pl.E1, pl.chunk1, (uint32_t)passb_bound, N, X, Xid, Y, Yid, ids, segs, nseg, cube, s, &tm,
-            EV_COUNT1);
-  gp.num_grids = (uint32_t)(nc + passb_bound);  // descriptors past the real count are never referenced
-  gp.used_words += passb_bound * grid_words(pl.E1);
+  const bool graph = nc > 1 && !(prm.flags & (LOD_FLAG_NO_GRAPH | LOD_FLAG_TIMING)) && !pl.weighted;
 
-  // 4. nodes: one region of slots per tree
-  uint32_t* hnb = w.h_nbeg.get<uint32_t>(2 * (size_t)nc);
-  uint64_t cap_total = 0;
-  for (uint32_t c = 0; c < nc; ++c) {
-    const uint64_t inner_max = sizes[c] / ((uint64_t)prm.leaf_cap + 1);
-    const uint64_t cap = 1 + 8ull * inner_max * std::max<uint32_t>(prm.max_level, 1) + 8;
-    hnb[c] = (uint32_t)cap_total;
-    cap_total += cap;
-    if (cap_total >= 0x7fffffffull) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
-    hnb[nc + c] = (uint32_t)cap_total;
-  }
-  uint32_t* nbeg = w.nbeg.get<uint32_t>(dev, 2 * (size_t)nc);
-  HIPCHK(hipMemcpyAsync(nbeg, hnb, 8ull * nc, hipMemcpyHostToDevice, s));
-  const uint32_t max_nodes = (uint32_t)cap_total;
-  Nodes nd = node_ptrs(w, max_nodes);
-  TreeState* st = w.state.get<TreeState>(dev, nc);
-  uint32_t* refine = w.refine.get<uint32_t>(dev, max_nodes);
-  uint32_t* leaf_refine = w.leaf_refine.get<uint32_t>(dev, max_nodes);
-  launch_tree_init(prm.leaf_cap, prm.max_level, gp.grids, gp.pool, nd, st, nbeg, nbeg + nc, nc, s);
-  BuildState* hbs = w.h_bs.get<BuildState>(1);
-  TreeState* hst = w.h_states.get<TreeState>(nc);
-  Cube* hcube = w.h_cubes.get<Cube>(nc);
-  HIPCHK(hipMemcpyAsync(hcube, cube, sizeof(Cube) * nc, hipMemcpyDeviceToHost, s));
-  for (;;) {
-    HIPCHK(hipMemsetAsync(&bs->nref, 0, sizeof(uint32_t), s));
-    launch_tree_build(prm.leaf_cap, prm.max_level, gp.grids, gp.pool, nd, st, nc, refine, leaf_refine, bs, s);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(hbs, bs, sizeof(BuildState), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hst, st, sizeof(TreeState) * nc, hipMemcpyDeviceToHost, s));
+  uint64_t ref_grids = (uint64_t)std::ceil(w.ref_grids_per_point * (double)N);
+  uint64_t vcap = (uint64_t)std::ceil(w.voxels_per_point * (double)N);
+  uint64_t t2cap = (uint64_t)std::ceil(w.coarse_per_point * (double)N);
+  std::shared_ptr<LodArena> arena;
+  Bufs b{};
+  Caps c;
+  DrainOnUnwind drain(s);
+  StageTimer tm(w, s, (prm.flags & LOD_FLAG_TIMING) != 0);
+  for (int attempt = 0;; ++attempt) {
+    c = make_caps(pl, sizes.data(), nc, N, prm, ref_grids, vcap, t2cap);
+    const RegionSizes rs = layout(b, c, pl, cube_given, want_vpts, nullptr, nullptr, nullptr);
+    arena = std::make_shared<LodArena>();
+    arena->dev = dev;
+    void* O = arena->alloc<char>(rs.out);
+    layout(b, c, pl, cube_given, want_vpts, w.S.get<char>(dev, rs.scratch), O, w.H.get<char>(rs.host));
+    // host tables: clouds, node regions, the given cube
+    uint32_t ntiles = 0;
+    uint64_t cap_total = 0;
+    for (uint32_t i = 0; i < nc; ++i) {
+      b.h_clouds[i].start = (uint32_t)(offs[active[i]] - offs[0]);
+      b.h_clouds[i].count = (uint32_t)sizes[i];
+      b.h_clouds[i].tile_base = ntiles;
+      b.h_clouds[i].pad = 0;
+      ntiles += bbox_tiles(b.h_clouds[i].count);
+      b.h_nbeg[i] = (uint32_t)cap_total;
+      cap_total += tree_node_cap(sizes[i], prm.leaf_cap, prm.max_level);
+      b.h_nbeg[nc + i] = (uint32_t)cap_total;
+      if (cube_given) b.h_cube_in[i] = *(const Cube*)x->cube;
+    }
+    if (graph) {
+      run_as_graph(w, b, c, pl, prm, in, in_ids, ntiles, cube_given, s);
+    } else {
+      enqueue(b, c, pl, prm, in, in_ids, ntiles, cube_given, s, &tm);
+    }
     HIPCHK(hipStreamSynchronize(s));
-    for (uint32_t c = 0; c < nc; ++c)
-      if (hcube[c].nonfinite) fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
-    if (hbs->overflow) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
-    if (hbs->nref) {
-      refine_nodes(w, gp, nd, refine, hbs->nref, N, Y, Yid, ids, cube, pl.chunk_ref, s);
-      continue;
+    for (uint32_t i = 0; i < nc; ++i)
+      if (b.h_cubes[i].nonfinite) fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
+    const BuildState& hb = *b.h_bs;
+    if (hb.overflow & kOverNodes) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
+    if (!hb.overflow) break;
+    // a capacity estimate was too small: build again with what was asked for
+    if (attempt >= 4) fail(LOD_ERR_CAPACITY, "build capacities still exceeded after re-planning");
+    if (hb.overflow & kOverGrids) {
+      const uint64_t need = hb.need_grids - c.grids0;
+      ref_grids = std::max<uint64_t>(2ull * c.ref_grids, need + need / 4 + 64);
+      w.ref_grids_per_point = std::max(w.ref_grids_per_point, (double)ref_grids / (double)N);
     }
-    break;
-  }
-  if (hbs->nlref) refine_nodes(w, gp, nd, leaf_refine, hbs->nlref, N, Y, Yid, ids, cube, pl.chunk_ref, s);
-
-  // per-tree placement in the compact node table
-  TreeInfo* hti = w.h_trees.get<TreeInfo>(nc);
-  uint32_t num_nodes = 0;
-  for (uint32_t c = 0; c < nc; ++c) {
-    TreeInfo& ti = hti[c];
-    memset(&ti, 0, sizeof(ti));
-    const TreeState& ts = hst[c];
-    ti.node_base = num_nodes;
-    ti.num_nodes = ts.num_nodes - ts.node_begin;
-    ti.point_base = hci[c].start;
-    const uint32_t shift = ti.node_base - ts.node_begin;
-    for (int L = 0; L < 23; ++L) {
-      if (ts.level_end[L] > ts.level_begin[L]) {
-        ti.level_begin[L] = ts.level_begin[L] + shift;
-        ti.level_end[L] = ts.level_end[L] + shift;
-        ti.deepest = (uint32_t)L;
-      } else {
-        ti.level_begin[L] = ti.level_end[L] = 0;
-      }
+    if (hb.overflow & kOverVoxels) {
+      vcap = hb.vtotal + 64;
+      w.voxels_per_point = std::max(w.voxels_per_point, (double)vcap / (double)N);
     }
-    num_nodes += ti.num_nodes;
+    if (hb.overflow & kOverCoarse) {
+      t2cap = hb.coarse_used + hb.coarse_used / 16 + 4096;
+      w.coarse_per_point = std::max(w.coarse_per_point, (double)t2cap / (double)N);
+    }
   }
-  TreeInfo* tinfo = w.trees.get<TreeInfo>(dev, nc);
-  HIPCHK(hipMemcpyAsync(tinfo, hti, sizeof(TreeInfo) * nc, hipMemcpyHostToDevice, s));
-  if (nc > 1) {
-    const Nodes cn = compact_ptrs(w, num_nodes);
-    launch_compact_nodes(nd, cn, tinfo, nbeg, nc, num_nodes, s);
-    nd = cn;
-  }
-  tm.mark(EV_TREE);
-
-  // 5. voxels: every leaf's lists for its ancestors up to 6 levels above it
-  // (depth 1 into X, coarser ones into t2), then the tree pass and the node
-  // offsets, one sync to size the output, then piece offsets and the gather
-  const uint32_t items = 8 * num_nodes;
-  uint64_t* T1 = (uint64_t*)X;
-  uint32_t* icnt = w.icnt.get<uint32_t>(dev, 6ull * items);
-  void* desc = w.idesc.get<uint4>(dev, 4ull * items);
-  uint64_t* iself = w.iself.get<uint64_t>(dev, items);
-  const uint64_t t2cap = coarse_space_bound(N, num_nodes);
-  uint64_t* T2 = w.t2.get<uint64_t>(dev, t2cap);
-  uint32_t* T2id = pl.mode ? w.t2id.get<uint32_t>(dev, t2cap) : nullptr;
-  const VoxTree vt = vox_ptrs(w, num_nodes);
-  launch_item_desc(nd, num_nodes, gp.grids, gp.pool, bs, desc, s);
-  launch_leaf_voxels(pl.mode, num_nodes, desc, Y, Yid, cube, T1, Xid, T2, T2id, icnt, iself, prm.seed, s);
-  tm.mark(EV_LEAF);
-  launch_voxel_tree(pl.mode, nd, vt, num_nodes, tinfo, nc, icnt, iself, prm.seed, s);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(hti, tinfo, sizeof(TreeInfo) * nc, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  uint64_t vtotal = 0;
-  for (uint32_t c = 0; c < nc; ++c) {
-    hti[c].vbase = vtotal;
-    vtotal += hti[c].vtotal;
-  }
-  HIPCHK(hipMemcpyAsync(tinfo, hti, sizeof(TreeInfo) * nc, hipMemcpyHostToDevice, s));
-  uint64_t* vox = arena->alloc<uint64_t>(std::max<uint64_t>(vtotal, 1));
-  uint32_t* vids = pl.mode ? arena->alloc<uint32_t>(std::max<uint64_t>(vtotal, 1)) : nullptr;
-  launch_voxel_gather(pl.mode, nd, vt, num_nodes, tinfo, icnt, desc, T1, Xid, T2, T2id, vox, vids, s);
+  const uint32_t num_nodes = b.h_bs->total_nodes;
+  const uint64_t vtotal = b.h_bs->vtotal;
+  TreeInfo* hti = b.h_trees;
   if (pl.weighted && vtotal) {
     if (vtotal > 0xffffffffull) fail(LOD_ERR_INVALID, "weighted sampling handles at most 2^32 - 1 voxels per call");
     // the nodes of the call grouped by level (each tree's levels are
@@ -616,22 +743,22 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     // n / (T + 1) per tree (inner nodes of one level are disjoint and hold
     // more than T points each)
     uint32_t deepest = 0;
-    for (uint32_t c = 0; c < nc; ++c) deepest = std::max(deepest, hti[c].deepest);
+    for (uint32_t i = 0; i < nc; ++i) deepest = std::max(deepest, hti[i].deepest);
     uint32_t* hl = w.h_wlist.get<uint32_t>(num_nodes);
     uint64_t loff[25] = {};
     uint64_t slots = 1, k = 0;
     for (uint32_t L = 0; L <= deepest; ++L) {
       loff[L] = k;
-      for (uint32_t c = 0; c < nc; ++c) {
-        if (k + (hti[c].level_end[L] - hti[c].level_begin[L]) > num_nodes)
+      for (uint32_t i = 0; i < nc; ++i) {
+        if (k + (hti[i].level_end[L] - hti[i].level_begin[L]) > num_nodes)
           fail(LOD_ERR_CAPACITY, "level ranges exceed the node table");
-        for (uint32_t i = hti[c].level_begin[L]; i < hti[c].level_end[L]; ++i) hl[k++] = i;
+        for (uint32_t j = hti[i].level_begin[L]; j < hti[i].level_end[L]; ++j) hl[k++] = j;
       }
       slots = std::max<uint64_t>(slots, k - loff[L]);
     }
     loff[deepest + 1] = k;
     uint64_t inner_bound = 0;
-    for (uint32_t c = 0; c < nc; ++c) inner_bound += hci[c].count / ((uint64_t)prm.leaf_cap + 1);
+    for (uint32_t i = 0; i < nc; ++i) inner_bound += sizes[i] / ((uint64_t)prm.leaf_cap + 1);
     slots = std::max<uint64_t>(1, std::min(slots, inner_bound));
     const uint64_t words = slots * weighted_bitmap_words();
     uint32_t* wlist = w.wlist.get<uint32_t>(dev, num_nodes);
@@ -645,29 +772,13 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     HIPCHK(hipMemsetAsync(wbits, 0, 8 * words, s));
     HIPCHK(hipMemsetAsync(wacc, 0, 32 * vtotal, s));
     HIPCHK(hipMemsetAsync(wseg, 0, 64ull * sizeof(uint2) * num_nodes, s));
-    HIPCHK(launch_weighted(nd, wlist, loff, deepest, tinfo, cube, desc, Y, vox, wslot, wbits, wpre, wseg, wacc,
-                           wblk + 2, wblk, w.h_wblk.get<uint32_t>(1), wblk + 1, s));
+    HIPCHK(launch_weighted(b.cn, wlist, loff, deepest, b.tinfo, b.cube, b.desc, b.Y, b.vox, wslot, wbits, wpre, wseg,
+                           wacc, wblk + 2, wblk, w.h_wblk.get<uint32_t>(1), wblk + 1, s));
+    if (b.vpts) launch_voxel_points(b.vox, b.vids, c.vcap, b.bs, b.tinfo, b.clouds, nc, in, b.vpts, s);
+    HIPCHK(hipGetLastError());
+    tm.mark(EV_LEVELS);
+    HIPCHK(hipStreamSynchronize(s));
   }
-  lod_point* vpts = nullptr;
-  if (pl.full && !(x && x->ids_only)) {
-    vpts = arena->alloc<lod_point>(std::max<uint64_t>(vtotal, 1));
-    launch_voxel_points(vox, vids, vtotal, tinfo, clouds, nc, in, vpts, s);
-  }
-  HIPCHK(hipGetLastError());
-  tm.mark(EV_LEVELS);
-
-  // 6. output node tables (per-tree indices and offsets)
-  uint8_t* o_level = arena->alloc<uint8_t>(num_nodes);
-  uint8_t* o_leaf = arena->alloc<uint8_t>(num_nodes);
-  uint8_t* o_mask = arena->alloc<uint8_t>(num_nodes);
-  uint64_t* o_key = arena->alloc<uint64_t>(num_nodes);
-  uint32_t* o_npts = arena->alloc<uint32_t>(num_nodes);
-  uint32_t* o_count = arena->alloc<uint32_t>(num_nodes);
-  uint32_t* o_first = arena->alloc<uint32_t>(num_nodes);
-  uint64_t* o_off = arena->alloc<uint64_t>(num_nodes);
-  launch_finalize_nodes(nd, tinfo, num_nodes, o_level, o_leaf, o_mask, o_key, o_npts, o_count, o_first, o_off, s);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));
 
   lod_timings T{};
   if (tm.on) {
@@ -683,36 +794,64 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     T.levels = tm.ms(EV_LEAF, EV_LEVELS);
     T.total = tm.ms(EV_START, EV_LEVELS);
   }
-  for (uint32_t c = 0; c < nc; ++c) {
-    lod_tree& t = *trees[active[c]];
-    const TreeInfo& ti = hti[c];
+  for (uint32_t i = 0; i < nc; ++i) {
+    lod_tree& t = *trees[active[i]];
+    const TreeInfo& ti = hti[i];
+    const Cube& cb = b.h_cubes[i];
     t.arena = arena;
     t.timings = T;
-    t.footprint = (uint64_t)((double)arena->bytes * (double)hci[c].count / (double)N);
+    t.footprint = (uint64_t)((double)arena->bytes * (double)sizes[i] / (double)N);
     lod_tree_view& v = t.v;
     for (int a = 0; a < 3; ++a) {
-      v.aabb_min[a] = hcube[c].lo[a];
-      v.aabb_max[a] = hcube[c].hi[a];
+      v.aabb_min[a] = cb.lo[a];
+      v.aabb_max[a] = cb.hi[a];
     }
-    v.cube_side = hcube[c].side;
+    v.cube_side = cb.side;
     v.num_nodes = ti.num_nodes;
-    v.num_points = hci[c].count;
+    v.num_points = sizes[i];
     v.num_voxels = ti.vtotal;
-    v.node_level = o_level + ti.node_base;
-    v.node_is_leaf = o_leaf + ti.node_base;
-    v.node_child_mask = o_mask + ti.node_base;
-    v.node_key = o_key + ti.node_base;
-    v.node_npoints = o_npts + ti.node_base;
-    v.node_count = o_count + ti.node_base;
-    v.node_first_child = o_first + ti.node_base;
-    v.node_offset = o_off + ti.node_base;
-    v.points = Y + ti.point_base;
-    v.point_ids = Yid ? Yid + ti.point_base : nullptr;
-    v.voxels = (const lod_voxel*)(vox + ti.vbase);
-    v.voxel_ids = vids ? vids + ti.vbase : nullptr;
-    v.voxel_points = vpts ? vpts + ti.vbase : nullptr;
+    v.node_level = b.o_level + ti.node_base;
+    v.node_is_leaf = b.o_leaf + ti.node_base;
+    v.node_child_mask = b.o_mask + ti.node_base;
+    v.node_key = b.o_key + ti.node_base;
+    v.node_npoints = b.o_npts + ti.node_base;
+    v.node_count = b.o_count + ti.node_base;
+    v.node_first_child = b.o_first + ti.node_base;
+    v.node_offset = b.o_off + ti.node_base;
+    v.points = b.Y + ti.point_base;
+    v.point_ids = b.Yid ? b.Yid + ti.point_base : nullptr;
+    v.voxels = (const lod_voxel*)(b.vox + ti.vbase);
+    v.voxel_ids = b.vids ? b.vids + ti.vbase : nullptr;
+    v.voxel_points = b.vpts ? b.vpts + ti.vbase : nullptr;
   }
   return release_all();
+}
+
+uint64_t lod_plan_bytes(const uint64_t* sizes, uint32_t n, const lod_params& p) {
+  std::vector<uint64_t> nz;
+  uint64_t N = 0;
+  for (uint32_t i = 0; i < n; ++i)
+    if (sizes[i]) {
+      nz.push_back(sizes[i]);
+      N += sizes[i];
+    }
+  if (nz.empty()) return 0;
+  std::vector<uint64_t> sorted = nz;
+  std::nth_element(sorted.begin(), sorted.begin() + sorted.size() / 2, sorted.end());
+  const Plan pl = make_plan(sorted[sorted.size() / 2], N, p);
+  const Caps c = make_caps(pl, nz.data(), (uint32_t)nz.size(), N, p, 0, 0);
+  Bufs b{};
+  const RegionSizes rs = layout(b, c, pl, false, pl.full, nullptr, nullptr, nullptr);
+  uint64_t weighted = 0;
+  if (pl.weighted) {
+    // 32 B of sums per voxel, an occupancy bitmap and prefixes per inner
+    // node of the widest level (at most n / (T + 1) per tree), per-node
+    // block lists
+    uint64_t slots = 1;
+    for (uint64_t v : nz) slots += v / ((uint64_t)p.leaf_cap + 1);
+    weighted = 32 * c.vcap + slots * weighted_bitmap_words() * 12 + 800ull * c.max_nodes;
+  }
+  return rs.scratch + rs.out + weighted;
 }
 
 lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params& prm, hipStream_t s) {
@@ -759,7 +898,10 @@ lod_status lod_build(const lod_point* d_points, uint64_t n, const lod_params* p,
     return LOD_ERR_INVALID;
   }
   try {
-    *out = lod_build_tree(d_points, n, *p, (hipStream_t)hip_stream);
+    const uint64_t offs[2] = {0, n};
+    const lod_params q =
+        (p->flags & LOD_FLAG_AUTOTUNE) ? tune_batch(d_points, offs, 1, *p, (hipStream_t)hip_stream, nullptr) : *p;
+    *out = lod_build_tree(d_points, n, q, (hipStream_t)hip_stream);
     return LOD_OK;
   } catch (const LodError& e) {
     (void)hipGetLastError();
@@ -796,8 +938,46 @@ lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets,
   }
   if (num_chunks == 0) return LOD_OK;
   try {
-    std::vector<lod_tree*> t = lod_build_clouds(d_points, h_offsets, num_chunks, *p, (hipStream_t)hip_stream);
+    const lod_params q = (p->flags & LOD_FLAG_AUTOTUNE)
+                             ? tune_batch(d_points, h_offsets, num_chunks, *p, (hipStream_t)hip_stream, nullptr)
+                             : *p;
+    std::vector<lod_tree*> t = lod_build_clouds(d_points, h_offsets, num_chunks, q, (hipStream_t)hip_stream);
     for (uint32_t i = 0; i < num_chunks; ++i) out[i] = t[i];
+    return LOD_OK;
+  } catch (const LodError& e) {
+    (void)hipGetLastError();
+    return e.st;
+  } catch (...) {
+    set_err("unexpected host exception");
+    return LOD_ERR_OOM;
+  }
+}
+
+lod_status lod_tune_batch(const lod_point* d_points, const uint64_t* h_offsets, uint32_t num_chunks,
+                          const lod_params* p, void* hip_stream, lod_params* tuned, lod_tune_info* info) {
+  if (!tuned || (num_chunks && !h_offsets)) {
+    set_err("tuned/h_offsets is NULL");
+    return LOD_ERR_INVALID;
+  }
+  if (check_params(p) != LOD_OK) {
+    set_err("invalid parameters");
+    return LOD_ERR_INVALID;
+  }
+  for (uint32_t i = 0; i < num_chunks; ++i)
+    if (h_offsets[i + 1] < h_offsets[i] || h_offsets[i + 1] - h_offsets[i] >= 0xffffffffull) {
+      set_err("offsets must be non-decreasing and chunks below 2^32 points");
+      return LOD_ERR_INVALID;
+    }
+  if (num_chunks && h_offsets[num_chunks] - h_offsets[0] >= 0xffffffffull) {
+    set_err("a batch holds fewer than 2^32 points");
+    return LOD_ERR_INVALID;
+  }
+  if (num_chunks && h_offsets[num_chunks] > h_offsets[0] && !d_points) {
+    set_err("d_points is NULL");
+    return LOD_ERR_INVALID;
+  }
+  try {
+    *tuned = tune_batch(d_points, h_offsets, num_chunks, *p, (hipStream_t)hip_stream, info);
     return LOD_OK;
   } catch (const LodError& e) {
     (void)hipGetLastError();

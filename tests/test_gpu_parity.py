@@ -214,21 +214,26 @@ def test_batch_equals_single_builds(lod, sampling):
 
 
 def test_autotuned_batch_plan_gives_same_trees(lod):
+    """The library's tuner (lod_tune_batch, and LOD_FLAG_AUTOTUNE) picks a plan
+    whose trees are the oracle's; the second call of the class is cached."""
     from paper_2302_14801_amd import autotune
     sizes = [30_000, 200_000, 5_000, 90_000, 60_000, 1]
     pts, offs = synth.batch_chunks(sizes, seed=21)
     dev = to_dev(pts)
     base = lod.make_params(leaf_cap=4000, max_level=12)
-    tuned, info = autotune.tune_batch(dev, offs, base, sample_chunks=4, reps=1)
-    assert len(info["plan"]) == 3
-    a = lod.lod_build_batch(dev, offs, params=base)
-    b = lod.lod_build_batch(dev, offs, params=tuned)
-    for ta, tb in zip(a, b):
-        ga, gb = ta.to_host(), tb.to_host()
-        ta.free()
-        tb.free()
-        for k in ("level", "key", "npoints", "count", "first_child", "voxels"):
-            assert np.array_equal(ga[k], gb[k]), k
+    tuned, info = autotune.tune_batch(dev, offs, base)
+    assert len(info["plan"]) == 3 and info["cached"] == 0 and info["sample_chunks"] == len(sizes)
+    again, info2 = autotune.tune_batch(dev, offs, base)
+    assert info2["cached"] == 1 and info2["plan"] == info["plan"]
+    auto = lod.make_params(leaf_cap=4000, max_level=12)
+    auto.flags |= lod.LOD_FLAG_AUTOTUNE
+    for params in (tuned, auto):
+        trees = lod.lod_build_batch(dev, offs, params=params)
+        for i, t in enumerate(trees):
+            chunk = pts[offs[i]:offs[i + 1]]
+            g = t.to_host()
+            t.free()
+            canon.compare_trees(g, oracle.build(chunk, leaf_cap=4000, max_level=12), chunk)
 
 
 def test_batch_many_uneven_chunks(lod):
