@@ -17,7 +17,9 @@ Beside it, on the same box and in the same run:
            of 50M-point tiles of the same generator) through lod_submit /
            lod_poll, reporting throughput and p50/p99 latency (completion
            minus scheduled arrival, including queueing and the host-to-device
-           copy), against the same requests built one by one;
+           copy), against the same requests built one by one; and a stream of
+           many small requests (50k points at 20 000 requests/s), where the
+           server's batching of queued requests into one build matters most;
   full precision: the plain build again with a full-precision record (input
            coordinates of the cell's accepted sample, voxel colour) for every
            voxel of the lower levels;
@@ -54,17 +56,31 @@ SAMPLING = {"average": 0, "first": 1, "random": 2, "weighted": 3}
 
 
 def stage_bytes(stage: str, n: int, ids: bool) -> float:
-    """Algorithmic bytes of one launch of a stage: each 16-byte record pass
-    counted once (reads and writes), ids 4 bytes per point when carried."""
+    """Bytes one launch of a stage moves when every array it touches is read
+    or written once: 16-byte records, 4-byte ids when carried, and the 2-byte
+    cell digit of the second partition that the first partition's insert
+    writes beside each record (the second partition counts and inserts from
+    it instead of projecting the record again)."""
     idb = 4 if ids else 0
     return {
         "bbox": 16.0 * n,
         "count0": 16.0 * n,
-        "scatter0": (16.0 + 16.0 + idb) * n,
-        "count1": 16.0 * n,
-        "scatter1": (16.0 + idb + 16.0 + idb) * n,
+        "scatter0": (16.0 + idb + 16.0 + idb + 2.0) * n,
+        "count1": 2.0 * n,
+        "scatter1": (16.0 + idb + 2.0 + 16.0 + idb) * n,
         "leaf_voxels": (16.0 + idb) * n,
     }.get(stage, 0.0)
+
+
+def method_bytes_per_point(sampling: int, voxels: int, n: int) -> float:
+    """Bytes per point the method itself must move (each record pass once):
+    AVERAGE 16 (bounding box) + 16 (count) + 32 (insert) + 16 (leaf points
+    read) + 16 per voxel (written, then read by the parent level); the pick
+    modes add 8 B of ids per point and 8 B of ids per voxel."""
+    vn = voxels / max(n, 1)
+    if sampling in (1, 2):
+        return 80.0 + 8.0 + 24.0 * vn
+    return 80.0 + 16.0 * vn
 
 
 # Library kernels and the build stages (HIP-event brackets) that time their
@@ -161,14 +177,18 @@ def run_batched(lod, torch, num_chunks: int, reps: int, params):
 
 
 def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, inflight: int,
-               pool_tiles: int, keep: int):
+               pool_tiles: int, keep: int, fixed_size: int = 0):
     """Open-loop Poisson client of the request server, then the same requests
-    built one by one (host to device copy + lod_build each)."""
+    built one by one (host to device copy + lod_build each).  Sizes are
+    lognormal (median 2M, sigma 1.0, clipped 50k-50M), or all fixed_size."""
     import synth
     rng = np.random.default_rng(5)
     gaps = rng.exponential(1.0 / rate, num_requests)
     arrivals = np.cumsum(gaps) - gaps[0]
-    sizes = synth.chunk_sizes(num_requests, seed=5, median=2e6, sigma=1.0, lo=50_000, hi=50_000_000)
+    if fixed_size:
+        sizes = np.full(num_requests, fixed_size, np.int64)
+    else:
+        sizes = synth.chunk_sizes(num_requests, seed=5, median=2e6, sigma=1.0, lo=50_000, hi=50_000_000)
     tile_n = int(min(50_000_000, sizes.max()))
     print(f"[bench] served: generating {pool_tiles} tiles of {tile_n} points", file=sys.stderr, flush=True)
     tiles = []
@@ -195,7 +215,9 @@ def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, 
         while nxt < num_requests and arrivals[nxt] <= now:
             pending[srv.submit(reqs[nxt])] = nxt
             nxt += 1
-        for tk in list(pending):
+        # the oldest tickets first (the server takes requests in order), a
+        # bounded number per sweep so that a long queue does not slow the client
+        for tk in list(pending)[:256]:
             t = srv.poll(tk)
             if t is not None:
                 i = pending.pop(tk)
@@ -218,7 +240,7 @@ def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, 
     s0 = time.perf_counter()
     pending = {srv.submit(reqs[r]): r for r in range(num_requests)}
     while pending:
-        for tk in list(pending):
+        for tk in list(pending)[:256]:
             t = srv.poll(tk)
             if t is not None:
                 pending.pop(tk)
@@ -246,8 +268,9 @@ def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, 
     t_plain = time.perf_counter() - p0
     del dbuf, tiles, reqs
     torch.cuda.empty_cache()
-    return {"workload": f"{num_requests} requests, Poisson arrivals at {rate:g}/s, lognormal sizes (median 2M, "
-                        f"sigma 1.0, clipped 50k-50M), prefixes of {pool_tiles} pinned host tiles of {tile_n} points; "
+    size_desc = f"{fixed_size} points each" if fixed_size else "lognormal sizes (median 2M, sigma 1.0, clipped 50k-50M)"
+    return {"workload": f"{num_requests} requests, Poisson arrivals at {rate:g}/s, {size_desc}, "
+                        f"prefixes of {pool_tiles} pinned host tiles of {tile_n} points; "
                         f"budget {budget >> 30} GiB, {inflight} in flight, newest {keep} trees kept",
             "requests": num_requests, "points": total,
             "served_points_per_s": round(total / t_served, 1),
@@ -259,6 +282,42 @@ def run_served(lod, torch, num_requests: int, rate: float, params, budget: int, 
             "plain_points_per_s": round(total / t_plain, 1), "plain_s": round(t_plain, 3)}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pts, sample: int, args, sampling: int) -> dict:
+    """The CPU oracle (single-threaded C) on the first `sample` points of the
+    same cloud, pinned to one core, median of args.cpu_reps builds."""
+    import oracle
+    core = min(os.sched_getaffinity(0))
+    saved = os.sched_getaffinity(0)
+    times = []
+    print(f"[bench] CPU oracle on the first {sample} points, core {core}, {args.cpu_reps} builds",
+          file=sys.stderr, flush=True)
+    try:
+        os.sched_setaffinity(0, {core})
+        for r in range(max(1, args.cpu_reps)):
+            c0 = time.perf_counter()
+            oracle.build(pts[:sample], leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling)
+            times.append(time.perf_counter() - c0)
+            print(f"[bench] CPU oracle build {r}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    finally:
+        os.sched_setaffinity(0, saved)
+    med = float(np.median(times))
+    whole = "the whole" if sample == len(pts) else f"the first {sample} points of the same"
+    return {"value": round(sample / med, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"{whole} {args.workload} cloud ({sample} points); single-threaded C oracle pinned to core "
+                      f"{core} of {os.cpu_count()} ({cpu_model()}), build only, median of {len(times)}: "
+                      + ", ".join(f"{t:.2f}" for t in times) + " s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,8 +327,9 @@ def main():
     ap.add_argument("--sampling", default="average", choices=sorted(SAMPLING))
     ap.add_argument("--leaf-cap", type=int, default=50000)
     ap.add_argument("--max-level", type=int, default=12)
-    ap.add_argument("--cpu-sample", type=int, default=20_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
                     help="points of the workload the CPU oracle builds (0 = skip)")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="CPU oracle builds (the median is reported)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="run one plain device copy of the input first (known bytes, for counter calibration)")
     ap.add_argument("--batch-chunks", type=int, default=512, help="chunks of the batched run (0 = skip)")
@@ -277,6 +337,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400, help="requests of the served run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-tiles", type=int, default=4)
+    ap.add_argument("--serve-small-requests", type=int, default=4000,
+                    help="requests of the served run of many small requests (0 = skip)")
+    ap.add_argument("--serve-small-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-small-points", type=int, default=50_000)
     ap.add_argument("--full-precision-steps", type=int, default=5,
                     help="builds of the same cloud with full-precision lower levels (0 = skip)")
     ap.add_argument("--weighted-steps", type=int, default=3,
@@ -357,6 +421,13 @@ def main():
                 "avg_launch_ms": kd["avg_launch_ms"]}
     whole_alg = sum(stage_bytes(k, n, ids) for k in single)
     nodes, voxels = infos[-1]
+    # the whole build against the method's own bytes (each record pass once)
+    mb = method_bytes_per_point(sampling, voxels, n)
+    whole_gbs = mb * n / (ms_per_step * 1e-3) / 1e9
+    whole_roofline = {"bound": "hbm", "bytes_per_point": round(mb, 2), "voxels_per_point": round(voxels / n, 4),
+                      "achieved": round(whole_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(whole_gbs / HBM_PEAK_GBS, 4), "ms_per_step": round(ms_per_step, 4),
+                      "target_frac": 0.6, "ms_at_target": round(mb * n / (0.6 * HBM_PEAK_GBS * 1e9) * 1e3, 4)}
 
     def variant(steps, **kw):
         """The same cloud built `steps` times with other parameters (one warm-up)."""
@@ -420,25 +491,20 @@ def main():
 
     cpu = None
     if args.cpu_sample > 0:
-        import oracle
-        sample = min(args.cpu_sample, n)
-        print(f"[bench] CPU oracle on the first {sample} points", file=sys.stderr, flush=True)
-        c0 = time.perf_counter()
-        oracle.build(pts[:sample], leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling)
-        c1 = time.perf_counter()
-        cpu = {"value": round(sample / (c1 - c0), 1), "unit": "points/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {sample} points of the same {args.workload} cloud (a uniform subsample: the "
-                         f"generator interleaves scene components at random); single-threaded C oracle, "
-                         f"build only, {c1 - c0:.2f} s"}
+        cpu = cpu_baseline(pts, min(args.cpu_sample, n), args, sampling)
 
     del dev
     torch.cuda.empty_cache()
-    batched = served = None
+    batched = served = served_small = None
     if args.batch_chunks > 0:
         batched = run_batched(lod, torch, args.batch_chunks, args.batch_reps, params_plain(lod, args, sampling))
     if args.serve_requests > 0:
         served = run_served(lod, torch, args.serve_requests, args.serve_rate, params_plain(lod, args, sampling),
                             192 << 30, 4, args.serve_tiles, 256)
+    if args.serve_small_requests > 0:
+        served_small = run_served(lod, torch, args.serve_small_requests, args.serve_small_rate,
+                                  params_plain(lod, args, sampling), 192 << 30, 4, args.serve_tiles, 256,
+                                  fixed_size=args.serve_small_points)
 
     out = {
         "metric": METRIC,
@@ -460,7 +526,8 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k, v in avg.items()},
         "kernels": kernels,
-        "whole_build_alg_GBps": round(whole_alg / (ms_per_step * 1e-3) / 1e9, 1),
+        "whole_build_roofline": whole_roofline,
+        "whole_build_stage_GBps": round(whole_alg / (ms_per_step * 1e-3) / 1e9, 1),
         "nodes": nodes,
         "voxels": voxels,
         "full_precision": full,
@@ -468,6 +535,7 @@ def main():
         "chunked": chunked,
         "batched": batched,
         "served": served,
+        "served_small": served_small,
     }
     print(json.dumps(out), flush=True)
 

@@ -204,6 +204,11 @@ struct Chunk {
 };
 // A run of at most kGroupChunks consecutive chunks of one segment (column scans).
 constexpr uint32_t kGroupChunks = 32;
+// Key levels a refinement sorts: 4 below an inner node at the deepest sorted
+// level (enumeration continues there), 2 below a leaf whose points are not
+// yet sorted two levels down (the voxel stage's micro-buckets).
+constexpr uint32_t kRefineInnerE = 4;
+constexpr uint32_t kRefineLeafE = 2;
 struct ChunkGroup {
   uint32_t seg;
   uint32_t first;  // first chunk
@@ -300,7 +305,7 @@ struct BuildState {
   uint64_t used_words;   // pool words in use
   uint64_t need_words;   // pool words the refinements asked for
   uint64_t vtotal;       // voxels of all trees
-  uint32_t item_next;    // next work item of the leaf kernel's queue
+  uint32_t pad0;
   uint32_t pad;
 };
 

@@ -212,13 +212,10 @@ __global__ void k_chunk_fill(const Segment* __restrict__ segs, const uint32_t* n
 
 // Count one chunk into an LDS histogram of B = 8^E cells and write the row
 // (each workgroup takes chunks blockIdx.x, blockIdx.x + gridDim.x, ... of the
-// device-side chunk count).  The cell of a point is either computed from its
-// record, or (DIG) read as the 2-byte digit the previous pass's insert wrote
-// beside it.
+// device-side chunk count).
 constexpr int kCountWG = 512;
-template <int E, bool DIG>
-__global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict__ pts,
-                                                         const uint16_t* __restrict__ dig, const Cube* cube,
+template <int E>
+__global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict__ pts, const Cube* cube,
                                                          const Segment* __restrict__ segs,
                                                          const Chunk* __restrict__ chunks,
                                                          const uint32_t* nchunk_ptr, uint32_t* __restrict__ hist) {
@@ -231,33 +228,21 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
   for (uint32_t j = threadIdx.x; j < B; j += kCountWG) h[j] = 0;
   lds_barrier();
   uint32_t i = threadIdx.x;
-  if (DIG) {
-    const uint16_t* d = dig + ch.start;
-    for (; i + 15 * kCountWG < ch.count; i += 16 * kCountWG) {
-      uint32_t v[16];
+  const CubeD cd = load_cube(cube + sg.cloud);
+  const uint32_t lvl_bit = kKeyLevels - (sg.level + E);  // the E levels below the segment's level
+  const uint4* p = pts + ch.start;
+  for (; i + 7 * kCountWG < ch.count; i += 8 * kCountWG) {
+    uint4 v[8];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = d[i + k * kCountWG];
+    for (int k = 0; k < 8; ++k) v[k] = p[i + k * kCountWG];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) atomicAdd(&h[v[k]], 1u);
-    }
-    for (; i < ch.count; i += kCountWG) atomicAdd(&h[d[i]], 1u);
-  } else {
-    const CubeD cd = load_cube(cube + sg.cloud);
-    const uint32_t lvl_bit = kKeyLevels - (sg.level + E);  // the E levels below the segment's level
-    const uint4* p = pts + ch.start;
-    for (; i + 7 * kCountWG < ch.count; i += 8 * kCountWG) {
-      uint4 v[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = p[i + k * kCountWG];
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        atomicAdd(&h[point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E)],
-                  1u);
-    }
-    for (; i < ch.count; i += kCountWG) {
-      uint4 v = p[i];
-      atomicAdd(&h[point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, lvl_bit, E)], 1u);
-    }
+    for (int k = 0; k < 8; ++k)
+      atomicAdd(&h[point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E)],
+                1u);
+  }
+  for (; i < ch.count; i += kCountWG) {
+    uint4 v = p[i];
+    atomicAdd(&h[point_cell(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), cd, lvl_bit, E)], 1u);
   }
   lds_barrier();
   uint32_t* row = hist + (uint64_t)c * B;
@@ -376,14 +361,13 @@ __global__ void __launch_bounds__(kGridWG) k_grid_finish(const Segment* __restri
 // output deltas, and the rest of LDS holds as large a round as possible: the
 // stores of a round are runs of consecutive records per cell, and longer runs
 // write HBM more efficiently.
-// Digits (DM): with DM = 1 the insert also writes, beside every record, the
-// 2-byte cell of the E2 key levels below the ones it sorts by (the next
-// pass's digit, taken from the same quantization); with DM = 2 the cell is
-// read from such a digit array instead of being computed from the record.
 constexpr int kScatWG = 1024;
 // Workgroups of a count or insert launch at most; each takes every
 // gridDim.x-th chunk of the device-side chunk list.
 constexpr uint32_t kMaxPartBlocks = 4096;
+// Workgroups of the one-chunk insert launch at most (a launch holds fewer
+// than 2^32 threads).
+constexpr uint32_t kMaxOneChunkBlocks = 1u << 20;
 #define PAD(b) ((b) + ((b) >> 5))
 template <bool IDS>
 struct ScatShape {
@@ -391,15 +375,17 @@ struct ScatShape {
   static constexpr int R = kScatWG * PPT;
 };
 
-template <int E, bool IDS, int DM>
+// Workgroup b takes chunk c0 + b; with LOOP also c0 + b + gridDim.x, ...
+// (looping keeps more registers live: the one-chunk form covers the chunks
+// a partition can be expected to have, the looping form any beyond).
+template <int E, bool IDS, bool LOOP>
 __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restrict__ src, const uint32_t* __restrict__ src_ids,
                                                           uint4* __restrict__ dst, uint32_t* __restrict__ dst_ids,
-                                                          const uint16_t* __restrict__ dig_in,
-                                                          uint16_t* __restrict__ dig_out, uint32_t E2,
                                                           const Cube* cube, const Segment* __restrict__ segs,
                                                           const Chunk* __restrict__ chunks, const uint32_t* nchunk_ptr,
                                                           const uint32_t* __restrict__ hist,
-                                                          const GridDesc* __restrict__ grids, const uint32_t* __restrict__ pool) {
+                                                          const GridDesc* __restrict__ grids, const uint32_t* __restrict__ pool,
+                                                          uint32_t c0) {
   constexpr int PPT = ScatShape<IDS>::PPT;
   constexpr uint32_t R = ScatShape<IDS>::R;
   constexpr uint32_t B = 1u << (3 * E);
@@ -411,11 +397,10 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
   __shared__ uint4 stage[R];
   __shared__ uint16_t stage_b[R];
   __shared__ uint32_t stage_id[IDS ? R : 1];
-  constexpr bool kStageDig = DM == 1 && !IDS;  // with ids the digit is recomputed at the store
-  __shared__ uint16_t stage_d[kStageDig ? R : 1];
   __shared__ uint32_t sh[kScatWG / 64 + 1];
   const uint32_t nchunk = *nchunk_ptr;
-  for (uint32_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+  for (uint32_t c = c0 + blockIdx.x; c < nchunk; c += gridDim.x) {
+  if (LOOP) lds_barrier();  // the previous chunk's last reads of LDS are done
   const Chunk ch = chunks[c];
   const Segment sg = segs[ch.seg];
   const GridDesc g = grids[sg.grid];
@@ -437,8 +422,8 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
   // software pipeline: the records of round r + 1 are loaded while round r is
   // sorted in LDS and written out
   uint4 v[PPT];
-  uint32_t id[PPT], dd[PPT];
-  auto load_round = [&](uint32_t base, uint4* vv, uint32_t* ii, uint32_t* di) {
+  uint32_t id[PPT];
+  auto load_round = [&](uint32_t base, uint4* vv, uint32_t* ii) {
     const uint32_t nround = base < ch.count ? min(R, ch.count - base) : 0u;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -447,35 +432,24 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
         const uint32_t gi = ch.start + base + j;
         vv[k] = src[gi];
         if (IDS) ii[k] = src_ids ? src_ids[gi] : gi - ch_cloud_start;
-        if (DM == 2) di[k] = dig_in[gi];
       }
     }
   };
-  load_round(0, v, id, dd);
-  const uint32_t dmask = (1u << (3 * E2)) - 1u;
+  load_round(0, v, id);
   for (uint32_t base = 0; base < ch.count; base += R) {
     const uint32_t nround = min(R, ch.count - base);
-    uint32_t bk[PPT], rk[PPT], dg[PPT];
+    uint32_t bk[PPT], rk[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const uint32_t j = k * kScatWG + threadIdx.x;
       if (j < nround) {
-        if (DM == 2) {
-          bk[k] = dd[k];
-        } else if (DM == 1) {
-          const uint32_t full = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z),
-                                           cd, lvl_bit - E2, E + E2);
-          bk[k] = full >> (3 * E2);
-          dg[k] = full & dmask;
-        } else {
-          bk[k] = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E);
-        }
+        bk[k] = point_cell(__uint_as_float(v[k].x), __uint_as_float(v[k].y), __uint_as_float(v[k].z), cd, lvl_bit, E);
         rk[k] = atomicAdd(&cnt[PAD(bk[k])], 1u);
       }
     }
     uint4 vn[PPT];
-    uint32_t idn[PPT], ddn[PPT];
-    load_round(base + R, vn, idn, ddn);
+    uint32_t idn[PPT];
+    load_round(base + R, vn, idn);
     lds_barrier();
     // exclusive scan of the round's cell counts (in place); counts and
     // prefixes stay in registers
@@ -505,7 +479,6 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
         stage[pos] = v[k];
         stage_b[pos] = (uint16_t)bk[k];
         if (IDS) stage_id[pos] = id[k];
-        if (kStageDig) stage_d[pos] = (uint16_t)dg[k];
       }
     }
     lds_barrier();
@@ -519,13 +492,8 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     lds_barrier();
     for (uint32_t j = threadIdx.x; j < nround; j += kScatWG) {
       const uint32_t d = cnt[PAD(stage_b[j])] + j;
-      const uint4 r = stage[j];
-      dst[d] = r;
+      dst[d] = stage[j];
       if (IDS) dst_ids[d] = stage_id[j];
-      if (kStageDig) dig_out[d] = stage_d[j];
-      if (DM == 1 && IDS)
-        dig_out[d] = (uint16_t)point_cell(__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), cd,
-                                          lvl_bit - E2, E2);
     }
     lds_barrier();
 #pragma unroll
@@ -538,9 +506,9 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     for (int k = 0; k < PPT; ++k) {
       v[k] = vn[k];
       if (IDS) id[k] = idn[k];
-      if (DM == 2) dd[k] = ddn[k];
     }
   }
+  if (!LOOP) break;
   }
 }
 
@@ -715,26 +683,21 @@ void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, 
 }
 
 template <int E>
-static void count_e(const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs, const Chunk* chunks,
+static void count_e(const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
                     const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
   const uint32_t blocks = std::min<uint32_t>(max_chunks, kMaxPartBlocks);
-  if (dig)
-    hipLaunchKernelGGL((k_part_count<E, true>), dim3(blocks), dim3(kCountWG), 0, st, (const uint4*)pts, dig, cube,
-                       segs, chunks, nchunk, hist);
-  else
-    hipLaunchKernelGGL((k_part_count<E, false>), dim3(blocks), dim3(kCountWG), 0, st, (const uint4*)pts, dig, cube,
-                       segs, chunks, nchunk, hist);
+  hipLaunchKernelGGL((k_part_count<E>), dim3(blocks), dim3(kCountWG), 0, st, (const uint4*)pts, cube, segs, chunks,
+                     nchunk, hist);
 }
 
-void launch_part_count(uint32_t E, const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs,
-                       const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist,
-                       hipStream_t st) {
+void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
+                       const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
   if (!max_chunks) return;
   switch (E) {
-    case 1: count_e<1>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 2: count_e<2>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 3: count_e<3>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 4: count_e<4>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 1: count_e<1>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 2: count_e<2>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 3: count_e<3>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 4: count_e<4>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
     default: break;
   }
 }
@@ -761,49 +724,42 @@ void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_
                      pool);
 }
 
-template <int E, bool IDS, int DM>
-static void scatter_e(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const uint16_t* dig_in,
-                      uint16_t* dig_out, uint32_t E2, const Cube* cube, const Segment* segs, const Chunk* chunks,
-                      const uint32_t* nchunk, uint32_t max_chunks, const uint32_t* hist, const GridDesc* grids,
-                      const uint32_t* pool, hipStream_t st) {
-  hipLaunchKernelGGL((k_part_scatter<E, IDS, DM>), dim3(std::min<uint32_t>(max_chunks, kMaxPartBlocks)), dim3(kScatWG), 0,
-                     st, (const uint4*)src, src_ids,
-                     (uint4*)dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, hist, grids, pool);
-}
-
-template <int E>
-static void scatter_ids_dm(bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
-                           const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2, const Cube* cube,
-                           const Segment* segs, const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks,
-                           const uint32_t* hist, const GridDesc* grids, const uint32_t* pool, hipStream_t st) {
-  const int dm = dig_in ? 2 : (dig_out ? 1 : 0);
-#define LOD_SCAT(I, D)                                                                                           \
-  if (ids == I && dm == D) {                                                                                     \
-    scatter_e<E, I, D>(src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, \
-                       hist, grids, pool, st);                                                                   \
-    return;                                                                                                      \
-  }
-  LOD_SCAT(false, 0)
-  LOD_SCAT(false, 1)
-  LOD_SCAT(false, 2)
-  LOD_SCAT(true, 0)
-  LOD_SCAT(true, 1)
-  LOD_SCAT(true, 2)
-#undef LOD_SCAT
+template <int E, bool IDS>
+static void scatter_e(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Cube* cube,
+                      const Segment* segs, const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks,
+                      uint32_t expect_chunks, const uint32_t* hist, const GridDesc* grids, const uint32_t* pool,
+                      hipStream_t st) {
+  // one workgroup per expected chunk (those past the real count return at
+  // once), then a grid that loops over any chunks beyond
+  const uint32_t g1 = std::max<uint32_t>(1, std::min(std::min(max_chunks, expect_chunks), kMaxOneChunkBlocks));
+  hipLaunchKernelGGL((k_part_scatter<E, IDS, false>), dim3(g1), dim3(kScatWG), 0, st, (const uint4*)src, src_ids,
+                     (uint4*)dst, dst_ids, cube, segs, chunks, nchunk, hist, grids, pool, 0u);
+  if (max_chunks > g1)
+    hipLaunchKernelGGL((k_part_scatter<E, IDS, true>), dim3(std::min<uint32_t>(max_chunks - g1, kMaxPartBlocks)),
+                       dim3(kScatWG), 0, st, (const uint4*)src, src_ids, (uint4*)dst, dst_ids, cube, segs, chunks,
+                       nchunk, hist, grids, pool, g1);
 }
 
 void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
-                         const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2, const Cube* cube, const Segment* segs,
-                         const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, const uint32_t* hist,
-                         const GridDesc* grids, const uint32_t* pool, hipStream_t st) {
+                         const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
+                         uint32_t max_chunks, uint32_t expect_chunks, const uint32_t* hist, const GridDesc* grids,
+                         const uint32_t* pool, hipStream_t st) {
   if (!max_chunks) return;
+#define LOD_SCAT(EE)                                                                                                   \
+  case EE:                                                                                                             \
+    if (ids) scatter_e<EE, true>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, expect_chunks,   \
+                                 hist, grids, pool, st);                                                               \
+    else scatter_e<EE, false>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, expect_chunks,      \
+                              hist, grids, pool, st);                                                                  \
+    break;
   switch (E) {
-    case 1: scatter_ids_dm<1>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
-    case 2: scatter_ids_dm<2>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
-    case 3: scatter_ids_dm<3>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
-    case 4: scatter_ids_dm<4>(ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, cube, segs, chunks, nchunk, max_chunks, hist, grids, pool, st); break;
+    LOD_SCAT(1)
+    LOD_SCAT(2)
+    LOD_SCAT(3)
+    LOD_SCAT(4)
     default: break;
   }
+#undef LOD_SCAT
 }
 
 void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,

@@ -45,6 +45,7 @@ constexpr uint32_t kPackedMax = 65535;  // largest micro-bucket the packed 16-bi
 constexpr uint32_t kLeafSlots = 8;      // points per thread per pass
 constexpr uint32_t kLeafPass = kLeafWG * kLeafSlots;
 constexpr uint32_t kNoCell = 0xffffffffu;
+constexpr uint64_t kMaxOneItemBlocks = 1ull << 22;  // workgroups of the one-item leaf launch (2^30 threads)
 constexpr uint32_t kCodeMask = (1u << 21) - 1;
 
 // Cells of one work item (a leaf's child cell) in the grid of the ancestor
@@ -348,7 +349,11 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, const GridDesc* 
 // Depth-1 lists go to T1 at the item's first point (never more voxels than
 // points), the coarse lists to the item's block in T2.  icnt receives the 6
 // list lengths and iself the depth-6 voxel (colour, id) of every item.
-template <int MODE>  // 0 average, 1 first, 2 random, 3 average with smallest ids
+// Workgroup b takes work item item0 + b; with LOOP also item0 + b + gridDim.x,
+// ... (a loop over items keeps more registers live: the one-item form is the
+// fast one, launched over the expected number of items, and the looping form
+// takes whatever items lie beyond it).
+template <int MODE, bool LOOP>  // MODE: 0 average, 1 first, 2 random, 3 average with smallest ids
 __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(const ItemDesc* __restrict__ desc,
                                                                           const uint4* __restrict__ pts,
                                                                           const uint32_t* __restrict__ ids,
@@ -358,7 +363,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
                                                                           uint32_t* __restrict__ T2id,
                                                                           uint32_t* __restrict__ icnt,
                                                                           uint64_t* __restrict__ iself, uint32_t seed,
-                                                                          BuildState* bs) {
+                                                                          const BuildState* bs, uint32_t item0) {
   __shared__ uint64_t acc[kSubCells];
   __shared__ uint32_t bm1[2][kSubCells / 32];  // depth-1 occupancy, alternating between micro-buckets
   __shared__ uint32_t over[8];                 // a cell of the micro-bucket passed 257 samples
@@ -366,22 +371,17 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   __shared__ uint64_t k4ok[8][8];              // depth-4 voxels of each micro-bucket: pick key and colour
   __shared__ uint32_t k4col[8][8];
   __shared__ uint32_t minid[MODE == 3 ? kSubCells : 1];  // mode 3: smallest id of every depth-1 cell
-  __shared__ uint32_t s_item;
   const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
   if (build_stopped(bs)) return;
   const uint32_t nitems = 8u * bs->total_nodes;
-  // work items from a queue, one at a time per workgroup
-  for (;;) {
-  if (t == 0) s_item = atomicAdd(&bs->item_next, 1u);
-  __syncthreads();
-  const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
-  __syncthreads();
-  if (item >= nitems) break;
+  for (uint32_t item = item0 + blockIdx.x; item < nitems; item += gridDim.x) {
+  if (LOOP) __syncthreads();  // the previous item's reads of LDS are done
   const ItemDesc& sd = desc[item];  // uniform: scalar loads
   const uint32_t P = sd.P;
   if (P == 0) {  // an empty child cell, or not a leaf item (uniform)
     if (t < 6) icnt[6 * item + t] = 0;
-    continue;
+    if (LOOP) continue;
+    return;
   }
   const uint64_t init = MODE == 1 ? ~0ull : 0ull;
   for (uint32_t i = t; i < kSubCells; i += kLeafWG) acc[i] = init;
@@ -730,6 +730,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
       ic[5] = c6;
     }
   }
+  if (!LOOP) break;
   }
 }
 
@@ -1076,15 +1077,24 @@ void launch_item_desc(const Nodes& nodes, uint32_t max_nodes, const GridDesc* gr
     } break;                           \
   }
 
-void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, const void* desc, const void* pts, const uint32_t* ids,
-                        const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2, uint32_t* T2id, uint32_t* icnt,
-                        uint64_t* iself, uint32_t seed, BuildState* bs, hipStream_t s) {
-  // workgroups that stay resident (256 CUs, up to 4 per CU) take the items
-  // from a queue
-  const uint32_t blocks = grid_blocks(8ull * max_nodes, 1, 1024);
-  LOD_MODE_SWITCH(mode, M,
-                  hipLaunchKernelGGL(k_leaf_voxels<M>, dim3(blocks), dim3(kLeafWG), 0, s, (const ItemDesc*)desc,
-                                     (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt, iself, seed, bs))
+void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, uint32_t expect_items, const void* desc, const void* pts,
+                        const uint32_t* ids, const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2,
+                        uint32_t* T2id, uint32_t* icnt, uint64_t* iself, uint32_t seed, const BuildState* bs,
+                        hipStream_t s) {
+  // one workgroup per expected item (the workgroups past the real count
+  // return at once), then a resident grid that loops over any items beyond;
+  // a launch holds fewer than 2^32 threads
+  const uint64_t cap = 8ull * max_nodes;
+  const uint32_t g1 =
+      (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(std::min<uint64_t>(cap, expect_items), kMaxOneItemBlocks));
+  LOD_MODE_SWITCH(mode, M, {
+    hipLaunchKernelGGL((k_leaf_voxels<M, false>), dim3(g1), dim3(kLeafWG), 0, s, (const ItemDesc*)desc,
+                       (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt, iself, seed, bs, 0u);
+    if (cap > g1)
+      hipLaunchKernelGGL((k_leaf_voxels<M, true>), dim3(grid_blocks(cap - g1, 1, 1024)), dim3(kLeafWG), 0, s,
+                         (const ItemDesc*)desc, (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt, iself, seed,
+                         bs, g1);
+  })
 }
 
 void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t max_nodes, TreeInfo* trees,

@@ -23,11 +23,9 @@ void launch_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, S
 void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t chunk, Chunk* chunks,
                         uint32_t* nchunk, uint32_t max_chunks, ChunkGroup* groups, uint32_t* ngroup,
                         uint32_t max_groups, hipStream_t st);
-// Counts of a partition: the cells of the points of every chunk (from the
-// records, or from `dig`, the 2-byte digits a previous insert wrote, if set).
-void launch_part_count(uint32_t E, const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs,
-                       const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist,
-                       hipStream_t st);
+// Counts of a partition: the cells of the points of every chunk.
+void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
+                       const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st);
 void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const ChunkGroup* groups,
                          const uint32_t* ngroup, uint32_t max_groups, uint32_t E, uint32_t* hist, uint32_t* gsum,
                          const GridDesc* grids, uint32_t* pool, hipStream_t st);
@@ -35,13 +33,13 @@ void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_
                         uint32_t* pool, hipStream_t st);
 // Points per insert round of the partition scatter (with or without ids).
 uint32_t scatter_round(bool ids);
-// Insert of a partition.  dig_in: read every point's cell from these 2-byte
-// digits; dig_out: also write beside every record its cell of the E2 levels
-// below the E sorted here (the next partition's digit).  At most one is set.
+// Insert of a partition.  expect_chunks: how many chunks get a workgroup of
+// their own (the rest, up to max_chunks, are taken by a looping grid; results
+// never depend on it).
 void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
-                         const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2, const Cube* cube, const Segment* segs,
-                         const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, const uint32_t* hist,
-                         const GridDesc* grids, const uint32_t* pool, hipStream_t st);
+                         const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
+                         uint32_t max_chunks, uint32_t expect_chunks, const uint32_t* hist, const GridDesc* grids,
+                         const uint32_t* pool, hipStream_t st);
 void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,
                           const uint32_t* nseg, uint32_t max_segs, hipStream_t st);
 void launch_segments_from_grid(GridDesc* grids, uint32_t ngrids, uint32_t* pool, uint32_t E2, uint64_t slot_base,
@@ -82,10 +80,12 @@ void launch_tree_info(const TreeState* sts, const CloudInfo* clouds, uint32_t nt
 // blocks handed out from a pool of t2cap entries (kOverCoarse beyond).
 void launch_item_desc(const Nodes& nodes, uint32_t max_nodes, const GridDesc* grids, const uint32_t* pool,
                       BuildState* bs, void* desc, uint64_t t2cap, hipStream_t s);
-// bs->item_next must be 0 (the work queue of the leaf kernel).
-void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, const void* desc, const void* pts, const uint32_t* ids,
-                        const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2, uint32_t* T2id, uint32_t* icnt,
-                        uint64_t* iself, uint32_t seed, BuildState* bs, hipStream_t s);
+// The leaf kernel over the 8 * total_nodes work items: expect_items sets how
+// many get a workgroup of their own (results never depend on it).
+void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, uint32_t expect_items, const void* desc, const void* pts,
+                        const uint32_t* ids, const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2,
+                        uint32_t* T2id, uint32_t* icnt, uint64_t* iself, uint32_t seed, const BuildState* bs,
+                        hipStream_t s);
 // Piece sizes, depth-first order, voxel counts and offsets of every tree;
 // the trees' first voxels and bs->vtotal (kOverVoxels above vcap).
 void launch_voxel_tree(uint32_t mode, const Nodes& nodes, const VoxTree& vt, uint32_t max_nodes, TreeInfo* trees,

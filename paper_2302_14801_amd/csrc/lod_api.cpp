@@ -134,7 +134,7 @@ struct Workspace {
   Pinned h_wlist, h_wblk;
   // capacities learned from earlier builds (grow-only; they change only how
   // often a build has to be repeated, never its result)
-  double ref_grids_per_point = 0.0, voxels_per_point = 0.0, coarse_per_point = 0.0;
+  double voxels_per_point = 0.0, coarse_per_point = 0.0;
   hipStream_t capture = nullptr;   // stream used only to record graphs
   hipGraphExec_t exec = nullptr;   // the last graph instantiated here
   std::vector<void*> retired;  // outgrown blocks, released when the build's stream has drained
@@ -299,7 +299,8 @@ struct Caps {
   uint32_t nc = 0;
   uint64_t passb = 0;     // segments of the second partition (one per possible root cell)
   uint32_t rounds = 0;    // refinement rounds of inner nodes
-  uint32_t ref_grids = 0; // refinement grids over all rounds (estimate)
+  uint32_t ref_inner = 0; // grids of inner-node refinements (4 levels), all rounds
+  uint32_t ref_leaf = 0;  // grids of leaf refinements (2 levels)
   uint32_t segs = 0, chunks = 0, groups = 0;
   uint64_t hist = 0, gsum = 0;  // words of histogram rows and group sums
   uint32_t grids0 = 0;    // grid descriptors of the two main partitions
@@ -309,6 +310,7 @@ struct Caps {
   uint32_t max_nodes = 0; // node slots of all trees
   uint64_t t2cap = 0;     // coarse-list entries
   uint64_t vcap = 0;      // output voxels (estimate)
+  uint32_t items = 0;     // work items of the leaf kernel that get a workgroup each (estimate)
 };
 
 void part_caps(Caps& c, uint64_t N, uint32_t chunk, uint32_t max_segs, uint32_t E) {
@@ -322,10 +324,10 @@ void part_caps(Caps& c, uint64_t N, uint32_t chunk, uint32_t max_segs, uint32_t 
   c.segs = std::max<uint32_t>(c.segs, max_segs);
 }
 
-// sizes: points of every (non-empty) cloud; ref_grids, vcap, t2cap:
-// capacities of the estimated pools (0 = default estimate).
-Caps make_caps(const Plan& pl, const uint64_t* sizes, uint32_t nc, uint64_t N, const lod_params& p,
-               uint64_t ref_grids, uint64_t vcap, uint64_t t2cap = 0) {
+// sizes: points of every (non-empty) cloud; vcap, t2cap: capacities of the
+// estimated pools (0 = default estimate).
+Caps make_caps(const Plan& pl, const uint64_t* sizes, uint32_t nc, uint64_t N, const lod_params& p, uint64_t vcap,
+               uint64_t t2cap = 0) {
   Caps c;
   c.N = N;
   c.nc = nc;
@@ -340,24 +342,34 @@ Caps make_caps(const Plan& pl, const uint64_t* sizes, uint32_t nc, uint64_t N, c
   c.max_nodes = (uint32_t)nodes;
   const uint32_t D0 = pl.E0 + pl.E1;
   c.rounds = p.max_level > D0 ? (p.max_level - D0 + 3) / 4 : 0;
-  // refinement grids: inner nodes at the deepest sorted level of a round
-  // (at most n / (T + 1) per tree) and leaves that lie fewer than two levels
-  // above their grid's deepest level; an estimate, checked on the device
-  if (!ref_grids) ref_grids = 256 + 2 * inner_per_level;
-  c.ref_grids = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(ref_grids, nodes), 0x7fffffffull);
+  // refinement grids, bounded exactly: a round refines inner nodes of one
+  // level per tree (at most n / (T + 1) of them), a leaf at most once (it
+  // needs its points sorted two levels below it), so the leaf grids sort 2
+  // levels only (8^2 cells instead of 8^4 for the inner nodes' grids)
+  c.ref_inner = (uint32_t)std::min<uint64_t>(std::min<uint64_t>((uint64_t)c.rounds * inner_per_level, nodes),
+                                             0x7fffffffull);
+  c.ref_leaf = (uint32_t)nodes;
   part_caps(c, N, pl.chunk0, nc, pl.E0);
   part_caps(c, N, pl.chunk1, (uint32_t)c.passb, pl.E1);
-  part_caps(c, N, pl.chunk_ref, c.ref_grids, 4);
+  part_caps(c, N, pl.chunk_ref, c.ref_inner, kRefineInnerE);
+  part_caps(c, N, pl.chunk_ref, c.ref_leaf, kRefineLeafE);
   c.segs = std::max<uint32_t>(c.segs, 1);
   c.grids0 = (uint32_t)(nc + c.passb);
   c.words0 = (uint64_t)nc * grid_words(pl.E0) + c.passb * grid_words(pl.E1);
-  c.grids = c.grids0 + c.ref_grids;
-  c.words = c.words0 + (uint64_t)c.ref_grids * grid_words(4);
+  if ((uint64_t)c.grids0 + c.ref_inner + c.ref_leaf >= 0x7fffffffull) fail(LOD_ERR_CAPACITY, "too many grids");
+  c.grids = c.grids0 + c.ref_inner + c.ref_leaf;
+  c.words = c.words0 + (uint64_t)c.ref_inner * grid_words(kRefineInnerE) +
+            (uint64_t)c.ref_leaf * grid_words(kRefineLeafE);
   // coarse lists: at most min(5p, 4681) entries per item of p points; the
   // pool is an estimate (about one entry per point), checked on the device
   const uint64_t t2max = coarse_space_bound(N, c.max_nodes);
   c.t2cap = std::min<uint64_t>(t2max, t2cap ? t2cap : N + N / 2 + 65536);
   c.vcap = vcap ? vcap : N + 64;
+  // leaf-kernel items (8 per node): about 8 nodes per T points plus a few per
+  // tree; only the launch shape depends on it
+  uint64_t est = 0;
+  for (uint32_t i = 0; i < nc; ++i) est += 8 * (8 * sizes[i] / p.leaf_cap + 64);
+  c.items = (uint32_t)std::min<uint64_t>(est, 8ull * c.max_nodes);
   return c;
 }
 
@@ -381,7 +393,6 @@ struct Carve {
 struct Bufs {
   uint4* X;
   uint32_t* Xid;
-  uint16_t* Xdig;
   BBoxAcc* bbox;
   Cube* cube;
   CloudInfo* clouds;
@@ -444,7 +455,6 @@ RegionSizes layout(Bufs& b, const Caps& c, const Plan& pl, bool cube_given, bool
   Carve s(S), o(O), h(H);
   b.X = s.take<uint4>(c.N);
   b.Xid = s.take<uint32_t>(pl.ids ? c.N : 1);
-  b.Xdig = s.take<uint16_t>(c.N);
   b.bbox = s.take<BBoxAcc>(c.nc);
   b.cube = s.take<Cube>(c.nc);
   b.clouds = s.take<CloudInfo>(c.nc);
@@ -500,40 +510,40 @@ RegionSizes layout(Bufs& b, const Caps& c, const Plan& pl, bool cube_given, bool
   return {s.off, o.off, h.off};
 }
 
-// Partition `nseg` segments (device count, at most max_segs, covering at most
-// max_points points) by E levels from src into dst.  dig_in: the points'
-// cells of this partition as 2-byte digits (instead of computing them from
-// the records); dig_out: write the digits of the next partition's E2 levels
-// beside the output records.
-void partition(const Bufs& b, uint32_t E, uint32_t chunk, uint32_t max_segs, uint64_t max_points, const void* src,
-               const uint32_t* src_ids, void* dst, uint32_t* dst_ids, bool ids, uint32_t* nseg, hipStream_t s,
-               StageTimer* tm, int ev0, const uint16_t* dig_in, uint16_t* dig_out, uint32_t E2) {
+// Partition `nseg` segments (device count, at most max_segs, expected about
+// expect_segs, covering at most max_points points) by E levels from src into
+// dst.
+void partition(const Bufs& b, uint32_t E, uint32_t chunk, uint32_t max_segs, uint32_t expect_segs, uint64_t max_points,
+               const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, bool ids, uint32_t* nseg,
+               hipStream_t s, StageTimer* tm, int ev0) {
   uint32_t* nchunk = nseg + 1;
   uint32_t* ngroup = nseg + 2;
   const uint32_t max_chunks = ceil_div(max_points, chunk) + max_segs;
+  const uint32_t expect_chunks = ceil_div(max_points, chunk) + std::min(max_segs, expect_segs);
   const uint32_t max_groups = ceil_div(max_chunks, kGroupChunks) + max_segs;
   launch_make_chunks(b.segs, nseg, max_segs, chunk, b.chunks, nchunk, max_chunks, b.groups, ngroup, max_groups, s);
-  launch_part_count(E, src, dig_in, b.cube, b.segs, b.chunks, nchunk, max_chunks, b.hist, s);
+  launch_part_count(E, src, b.cube, b.segs, b.chunks, nchunk, max_chunks, b.hist, s);
   if (ev0) mark(tm, ev0);
   launch_part_colscan(b.segs, nseg, max_segs, b.groups, ngroup, max_groups, E, b.hist, b.gsum, b.grids, b.pool, s);
   launch_grid_finish(b.segs, nseg, max_segs, b.grids, b.pool, s);
   if (ev0) mark(tm, ev0 + 1);
-  launch_part_scatter(E, ids, src, src_ids, dst, dst_ids, dig_in, dig_out, E2, b.cube, b.segs, b.chunks, nchunk,
-                      max_chunks, b.hist, b.grids, b.pool, s);
+  launch_part_scatter(E, ids, src, src_ids, dst, dst_ids, b.cube, b.segs, b.chunks, nchunk, max_chunks, expect_chunks,
+                      b.hist, b.grids, b.pool, s);
   if (ev0) mark(tm, ev0 + 2);
   HIPCHK(hipGetLastError());
 }
 
-// Refine the nodes of `list` (*nlist of them, a device count): partition
-// their points by 4 more levels (Y -> X), copy back, attach the new grids.
-void refine(const Bufs& b, const Caps& c, const Plan& pl, const uint32_t* list, const uint32_t* nlist,
-            hipStream_t s) {
-  const uint32_t E = 4;
+// Refine the nodes of `list` (*nlist of them, a device count, at most
+// max_segs): partition their points by E more levels (Y -> X), copy back,
+// attach the new grids.
+void refine(const Bufs& b, const Caps& c, const Plan& pl, const uint32_t* list, const uint32_t* nlist, uint32_t E,
+            uint32_t max_segs, hipStream_t s) {
   uint32_t* nseg = b.ctr + 4;
   launch_refine_segments(b.nd, list, nlist, c.max_nodes, E, b.bs, c.grids, c.words, b.grids, b.segs, nseg, s);
-  partition(b, E, pl.chunk_ref, c.ref_grids, c.N, b.Y, b.Yid, b.X, b.Xid, pl.ids, nseg, s, nullptr, 0, nullptr,
-            nullptr, 0);
-  launch_copy_segments(b.X, b.Xid, b.Y, pl.ids ? b.Yid : nullptr, b.segs, nseg, c.ref_grids, s);
+  // refinements are few (none at all in most large builds): a workgroup
+  // each for a thousand segments' chunks, the rest to the looping grid
+  partition(b, E, pl.chunk_ref, max_segs, 1024, c.N, b.Y, b.Yid, b.X, b.Xid, pl.ids, nseg, s, nullptr, 0);
+  launch_copy_segments(b.X, b.Xid, b.Y, pl.ids ? b.Yid : nullptr, b.segs, nseg, max_segs, s);
   launch_refine_commit(b.bs, nseg, E, s);
   HIPCHK(hipGetLastError());
 }
@@ -551,26 +561,24 @@ void enqueue(const Bufs& b, const Caps& c, const Plan& pl, const lod_params& prm
   if (cube_given) HIPCHK(hipMemcpyAsync(b.cube, b.h_cube_in, sizeof(Cube) * nc, hipMemcpyHostToDevice, s));
   else launch_bbox(in, b.clouds, nc, ntiles, b.bbox, b.cube, s);
   mark(tm, EV_BBOX);
-  // 2. root partition, input -> X, with every point's cell of the second
-  // partition as a 2-byte digit beside it
+  // 2. root partition, input -> X
   uint32_t* nseg = b.ctr;
   launch_init_roots(b.clouds, nc, pl.E0, b.segs, nseg, b.grids, s);
-  partition(b, pl.E0, pl.chunk0, nc, c.N, in, in_ids, b.X, b.Xid, pl.ids, nseg, s, tm, EV_COUNT0, nullptr, b.Xdig,
-            pl.E1);
+  partition(b, pl.E0, pl.chunk0, nc, nc, c.N, in, in_ids, b.X, b.Xid, pl.ids, nseg, s, tm, EV_COUNT0);
   // 3. every root cell by E1 more levels, X -> Y
   launch_fill_u32(nseg, 0, 1, s);
   launch_segments_from_grid(b.grids, nc, b.pool, pl.E1, (uint64_t)nc * grid_words(pl.E0), nc, b.segs, nseg, s);
-  partition(b, pl.E1, pl.chunk1, (uint32_t)c.passb, c.N, b.X, b.Xid, b.Y, b.Yid, pl.ids, nseg, s, tm, EV_COUNT1,
-            b.Xdig, nullptr, 0);
+  partition(b, pl.E1, pl.chunk1, (uint32_t)c.passb, (uint32_t)c.passb, c.N, b.X, b.Xid, b.Y, b.Yid, pl.ids, nseg, s,
+            tm, EV_COUNT1);
   // 4. nodes: one region of slots per tree, enumeration resumed after each
   // refinement round (a round without nodes to refine does nothing)
   launch_tree_init(prm.leaf_cap, prm.max_level, b.grids, b.pool, b.nd, b.st, b.nbeg, b.nbeg + nc, nc, s);
   for (uint32_t r = 0; r <= c.rounds; ++r) {
     launch_fill_u32(&b.bs->nref, 0, 1, s);
     launch_tree_build(prm.leaf_cap, prm.max_level, b.grids, b.pool, b.nd, b.st, nc, b.refine, b.leaf_refine, b.bs, s);
-    if (r < c.rounds) refine(b, c, pl, b.refine, &b.bs->nref, s);
+    if (r < c.rounds) refine(b, c, pl, b.refine, &b.bs->nref, kRefineInnerE, c.ref_inner, s);
   }
-  refine(b, c, pl, b.leaf_refine, &b.bs->nlref, s);
+  refine(b, c, pl, b.leaf_refine, &b.bs->nlref, kRefineLeafE, c.ref_leaf, s);
   launch_tree_info(b.st, b.clouds, nc, b.tinfo, b.bs, s);
   if (nc > 1) launch_compact_nodes(b.nd, b.cn, b.tinfo, b.nbeg, nc, c.max_nodes, b.bs, s);
   HIPCHK(hipGetLastError());
@@ -580,7 +588,7 @@ void enqueue(const Bufs& b, const Caps& c, const Plan& pl, const lod_params& prm
   // then the pieces' positions and the gather
   uint64_t* T1 = (uint64_t*)b.X;
   launch_item_desc(b.cn, c.max_nodes, b.grids, b.pool, b.bs, b.desc, c.t2cap, s);
-  launch_leaf_voxels(pl.mode, c.max_nodes, b.desc, b.Y, b.Yid, b.cube, T1, b.Xid, b.T2, b.T2id, b.icnt, b.iself,
+  launch_leaf_voxels(pl.mode, c.max_nodes, c.items, b.desc, b.Y, b.Yid, b.cube, T1, b.Xid, b.T2, b.T2id, b.icnt, b.iself,
                      prm.seed, b.bs, s);
   mark(tm, EV_LEAF);
   launch_voxel_tree(pl.mode, b.cn, b.vt, c.max_nodes, b.tinfo, nc, c.vcap, b.icnt, b.iself, prm.seed, b.bs, s);
@@ -676,7 +684,6 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   const uint32_t* in_ids = x && x->d_ids ? x->d_ids + offs[0] : nullptr;
   const bool graph = nc > 1 && !(prm.flags & (LOD_FLAG_NO_GRAPH | LOD_FLAG_TIMING)) && !pl.weighted;
 
-  uint64_t ref_grids = (uint64_t)std::ceil(w.ref_grids_per_point * (double)N);
   uint64_t vcap = (uint64_t)std::ceil(w.voxels_per_point * (double)N);
   uint64_t t2cap = (uint64_t)std::ceil(w.coarse_per_point * (double)N);
   std::shared_ptr<LodArena> arena;
@@ -685,7 +692,7 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
   DrainOnUnwind drain(s);
   StageTimer tm(w, s, (prm.flags & LOD_FLAG_TIMING) != 0);
   for (int attempt = 0;; ++attempt) {
-    c = make_caps(pl, sizes.data(), nc, N, prm, ref_grids, vcap, t2cap);
+    c = make_caps(pl, sizes.data(), nc, N, prm, vcap, t2cap);
     const RegionSizes rs = layout(b, c, pl, cube_given, want_vpts, nullptr, nullptr, nullptr);
     arena = std::make_shared<LodArena>();
     arena->dev = dev;
@@ -714,15 +721,11 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     for (uint32_t i = 0; i < nc; ++i)
       if (b.h_cubes[i].nonfinite) fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
     const BuildState& hb = *b.h_bs;
-    if (hb.overflow & kOverNodes) fail(LOD_ERR_CAPACITY, "node table capacity exceeded");
+    // node slots and refinement grids are bounded exactly
+    if (hb.overflow & (kOverNodes | kOverGrids)) fail(LOD_ERR_CAPACITY, "node table or grid capacity exceeded");
     if (!hb.overflow) break;
     // a capacity estimate was too small: build again with what was asked for
     if (attempt >= 4) fail(LOD_ERR_CAPACITY, "build capacities still exceeded after re-planning");
-    if (hb.overflow & kOverGrids) {
-      const uint64_t need = hb.need_grids - c.grids0;
-      ref_grids = std::max<uint64_t>(2ull * c.ref_grids, need + need / 4 + 64);
-      w.ref_grids_per_point = std::max(w.ref_grids_per_point, (double)ref_grids / (double)N);
-    }
     if (hb.overflow & kOverVoxels) {
       vcap = hb.vtotal + 64;
       w.voxels_per_point = std::max(w.voxels_per_point, (double)vcap / (double)N);
@@ -839,7 +842,7 @@ uint64_t lod_plan_bytes(const uint64_t* sizes, uint32_t n, const lod_params& p) 
   std::vector<uint64_t> sorted = nz;
   std::nth_element(sorted.begin(), sorted.begin() + sorted.size() / 2, sorted.end());
   const Plan pl = make_plan(sorted[sorted.size() / 2], N, p);
-  const Caps c = make_caps(pl, nz.data(), (uint32_t)nz.size(), N, p, 0, 0);
+  const Caps c = make_caps(pl, nz.data(), (uint32_t)nz.size(), N, p, 0);
   Bufs b{};
   const RegionSizes rs = layout(b, c, pl, false, pl.full, nullptr, nullptr, nullptr);
   uint64_t weighted = 0;
