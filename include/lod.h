@@ -225,6 +225,36 @@ lod_status lod_tune_batch(const lod_point* d_points, const uint64_t* h_offsets, 
 lod_status lod_build_chunked(const lod_point* h_points, uint64_t n, const lod_params* p, uint64_t chunk_points,
                              void* hip_stream, lod_tree** out);
 
+/* Allocation-free build, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  The same build as lod_build (same nodes, points, voxels and
+ * ids) for one cloud of n points, with
+ *   - its device scratch in one static array of LOD_NOALLOC_SCRATCH_BYTES
+ *     inside the library, held by each GPU the library runs on until the
+ *     process ends (256 MiB: clouds of up to 2^22 - 1 points fit with the
+ *     default T and depth limit; a cloud that does not fit gives
+ *     LOD_ERR_TOO_LARGE before anything is launched);
+ *   - its output in the caller's device buffer d_out (256-byte aligned) of
+ *     *out_bytes bytes: the leaf points (n records), ids (pick modes,
+ *     LOD_FLAG_POINT_IDS, full precision), the node tables and as many
+ *     voxels as fit.  On success *out_bytes is set to the bytes used and
+ *     *view to device pointers into d_out (valid while the caller keeps
+ *     d_out; nothing to free).  With d_out NULL nothing is built and
+ *     *out_bytes receives the size for n + 64 voxels (a tree has fewer
+ *     voxels than points in typical scans).  If the voxels do not fit, the
+ *     result is LOD_ERR_CAPACITY and *out_bytes the size they need;
+ *   - no hipMalloc, hipFree, host-pinned or other allocating call, and no
+ *     HIP events or graphs.  Timing and autotuning flags are ignored;
+ *     LOD_WEIGHTED gives LOD_ERR_INVALID.
+ * Every call on a GPU uses that GPU's one array (the build clears what it
+ * needs); calls are serialised within the process, and calls that overlap on
+ * one GPU from several processes race.  The call returns once the tree is
+ * complete on hip_stream.  Errors: as lod_build, plus LOD_ERR_TOO_LARGE and
+ * LOD_ERR_CAPACITY as above. */
+#define LOD_NOALLOC_SCRATCH_BYTES (256ull << 20)
+lod_status lod_build_noalloc(const lod_point* d_points, uint64_t n, const lod_params* p, void* hip_stream,
+                             void* d_out, uint64_t* out_bytes, lod_tree_view* view);
+
 /* Per-stage device times in milliseconds of the build that made the tree,
  * measured with HIP events on the build stream (only with LOD_FLAG_TIMING;
  * otherwise all zero).  Stages: bounding box; the first partition (count,

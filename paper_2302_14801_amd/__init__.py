@@ -10,7 +10,7 @@ from .binding import (LOD_AVERAGE, LOD_FLAG_AUTOTUNE, LOD_FLAG_FULL_PRECISION, L
                       LOD_PICK_FIRST,
                       LOD_PICK_RANDOM, LOD_WEIGHTED,
                       LodError, Server, Tree,
-                      load_library, lod_build, lod_build_batch, lod_build_chunked, lod_poll,
+                      load_library, lod_build, lod_build_batch, lod_build_chunked, lod_build_noalloc, lod_poll,
                       lod_server_create, lod_server_destroy, lod_submit, lod_tree_free, lod_tree_view_get,
                       lod_tune_batch, make_params, view_to_host)
 

@@ -61,7 +61,7 @@ class lod_timings(ctypes.Structure):
                  "leaf_voxels", "levels", "total")]
 
 
-EXPORTED = ["lod_params_default", "lod_build", "lod_build_batch", "lod_tune_batch",
+EXPORTED = ["lod_params_default", "lod_build", "lod_build_batch", "lod_build_noalloc", "lod_tune_batch",
             "lod_tree_view_get", "lod_tree_free",
             "lod_tree_timings",
             "lod_server_create", "lod_submit", "lod_poll", "lod_server_destroy", "lod_status_str",
@@ -94,6 +94,8 @@ def load_library():
     lib.lod_build_batch.restype = ctypes.c_int
     lib.lod_tune_batch.argtypes = [vp, P(u64), u32, P(lod_params), vp, P(lod_params), P(lod_tune_info)]
     lib.lod_tune_batch.restype = ctypes.c_int
+    lib.lod_build_noalloc.argtypes = [vp, u64, P(lod_params), vp, vp, P(u64), P(lod_tree_view)]
+    lib.lod_build_noalloc.restype = ctypes.c_int
     lib.lod_build_chunked.argtypes = [vp, u64, P(lod_params), u64, vp, P(vp)]
     lib.lod_build_chunked.restype = ctypes.c_int
     lib.lod_tree_view_get.argtypes = [vp, P(lod_tree_view)]
@@ -244,6 +246,26 @@ def lod_build(points, leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0
     _check(load_library().lod_build(ctypes.c_void_p(points.data_ptr()), n, ctypes.byref(p),
                                     _stream_handle(stream), ctypes.byref(out)))
     return Tree(out.value)
+
+
+def lod_build_noalloc(points, out, params: lod_params | None = None, stream=None, **kw):
+    """Allocation-free build of `points` into the caller's device buffer `out`
+    (a contiguous device tensor, 256-byte aligned; None = size query).
+    Returns (view, bytes): the tree's view (device pointers into `out`) and
+    the bytes of `out` it occupies (with out=None: (None, bytes needed))."""
+    n = _check_points(points)
+    p = params if params is not None else make_params(**kw)
+    nbytes = ctypes.c_uint64(0)
+    ptr = None
+    if out is not None:
+        if not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous device tensor")
+        nbytes.value = out.numel() * out.element_size()
+        ptr = ctypes.c_void_p(out.data_ptr())
+    v = lod_tree_view()
+    _check(load_library().lod_build_noalloc(ctypes.c_void_p(points.data_ptr()), n, ctypes.byref(p),
+                                            _stream_handle(stream), ptr, ctypes.byref(nbytes), ctypes.byref(v)))
+    return (v if out is not None else None), nbytes.value
 
 
 def lod_tune_batch(points, offsets, params: lod_params, stream=None):

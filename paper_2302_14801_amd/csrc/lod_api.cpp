@@ -863,6 +863,145 @@ lod_tree* lod_build_tree(const lod_point* d_points, uint64_t n, const lod_params
   return t[0];
 }
 
+// ------------------------------------------------------ allocation-free build
+//
+// lod_build_noalloc is the one-cloud build with its device scratch in the
+// file-scope array below instead of blocks from the device cache, its output
+// in the caller's buffer and its few host tables in a static host buffer.
+// Each GPU the library runs on holds its own copy of the array until the
+// process ends.  In host code the name `scratch` denotes a host-side
+// stand-in, never the device memory: its device address is looked up once
+// per device (hipGetSymbolAddress, with the device current) and only that
+// address reaches kernels and copies.
+static __device__ __align__(256) unsigned char scratch[LOD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;                        // one allocation-free build at a time per process
+void* g_na_ptr[kNaMaxDevices] = {};        // device address of `scratch`, per device
+alignas(256) unsigned char g_na_host[16384];  // host tables of one build (one cloud)
+
+void* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kNaMaxDevices) fail(LOD_ERR_INVALID, "device index out of range");
+  if (!g_na_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(LOD_ERR_HIP, "no device address for the allocation-free build's scratch");
+    g_na_ptr[dev] = ptr;
+  }
+  return g_na_ptr[dev];
+}
+
+// Output bytes of a one-cloud build with room for vcap voxels.
+uint64_t noalloc_out_bytes(const Caps& c, const Plan& pl) {
+  Bufs b{};
+  return layout(b, c, pl, false, pl.full, nullptr, nullptr, nullptr).out;
+}
+
+// Caller holds g_na_mu.  *out_bytes: capacity of d_out in, bytes used (or,
+// with LOD_ERR_CAPACITY for voxels, bytes needed) out.
+void build_noalloc(const lod_point* in, uint64_t n, const lod_params& prm, hipStream_t s, void* d_out,
+                   uint64_t* out_bytes, lod_tree_view* view) {
+  memset(view, 0, sizeof(*view));
+  view->cube_side = 1.0;
+  if (n == 0) {
+    *out_bytes = 0;
+    return;
+  }
+  const Plan pl = make_plan(n, n, prm);
+  const uint64_t sizes[1] = {n};
+  uint64_t t2cap = 0;
+  // the voxel capacity: as many as the caller's buffer holds (n + 64 for a
+  // size query)
+  Caps c = make_caps(pl, sizes, 1, n, prm, n + 64);
+  {
+    Bufs q{};
+    if (layout(q, c, pl, false, pl.full, nullptr, nullptr, nullptr).scratch > LOD_NOALLOC_SCRATCH_BYTES)
+      fail(LOD_ERR_TOO_LARGE, "the build does not fit the allocation-free build's scratch (LOD_NOALLOC_SCRATCH_BYTES)");
+  }
+  const uint64_t fixed = noalloc_out_bytes(make_caps(pl, sizes, 1, n, prm, 1), pl);
+  if (!d_out) {
+    *out_bytes = noalloc_out_bytes(c, pl);
+    return;
+  }
+  if ((uintptr_t)d_out & 255) fail(LOD_ERR_INVALID, "d_out must be 256-byte aligned");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  void* S = noalloc_scratch(dev);
+  const uint64_t per_voxel = 8 + (pl.mode ? 4 : 0) + (pl.full ? 16 : 0);
+  if (*out_bytes < fixed) {
+    *out_bytes = noalloc_out_bytes(c, pl);
+    fail(LOD_ERR_CAPACITY, "output buffer too small for the points and node tables");
+  }
+  // the largest voxel capacity whose layout fits (sizes grow with it)
+  uint64_t vlo = 1, vhi = *out_bytes / per_voxel + 2;
+  while (vhi - vlo > 1) {
+    const uint64_t m = vlo + (vhi - vlo) / 2;
+    if (noalloc_out_bytes(make_caps(pl, sizes, 1, n, prm, m, 0), pl) <= *out_bytes) vlo = m;
+    else vhi = m;
+  }
+  const uint64_t vcap = vlo;
+  DrainOnUnwind drain(s);
+  Bufs b{};
+  for (int attempt = 0;; ++attempt) {
+    c = make_caps(pl, sizes, 1, n, prm, vcap, t2cap);
+    const RegionSizes rs = layout(b, c, pl, false, pl.full, nullptr, nullptr, nullptr);
+    if (rs.out > *out_bytes) fail(LOD_ERR_CAPACITY, "output buffer too small for the points and node tables");
+    if (rs.scratch > LOD_NOALLOC_SCRATCH_BYTES)
+      fail(attempt ? LOD_ERR_CAPACITY : LOD_ERR_TOO_LARGE,
+           "the build does not fit the allocation-free build's scratch (LOD_NOALLOC_SCRATCH_BYTES)");
+    if (rs.host > sizeof(g_na_host)) fail(LOD_ERR_CAPACITY, "host tables exceed their static buffer");
+    layout(b, c, pl, false, pl.full, S, d_out, g_na_host);
+    b.h_clouds[0].start = 0;
+    b.h_clouds[0].count = (uint32_t)n;
+    b.h_clouds[0].tile_base = 0;
+    b.h_clouds[0].pad = 0;
+    b.h_nbeg[0] = 0;
+    b.h_nbeg[1] = (uint32_t)tree_node_cap(n, prm.leaf_cap, prm.max_level);
+    enqueue(b, c, pl, prm, in, nullptr, bbox_tiles((uint32_t)n), false, s, nullptr);
+    HIPCHK(hipStreamSynchronize(s));
+    if (b.h_cubes[0].nonfinite) fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
+    const BuildState& hb = *b.h_bs;
+    if (hb.overflow & (kOverNodes | kOverGrids)) fail(LOD_ERR_CAPACITY, "node table or grid capacity exceeded");
+    if (!hb.overflow) break;
+    if (hb.overflow & kOverVoxels) {
+      *out_bytes = noalloc_out_bytes(make_caps(pl, sizes, 1, n, prm, hb.vtotal, t2cap), pl);
+      fail(LOD_ERR_CAPACITY, "output buffer too small for the voxels (its required size is in *out_bytes)");
+    }
+    // a scratch estimate was too small: again with what the build asked for,
+    // while it still fits the array
+    if (attempt >= 4) fail(LOD_ERR_CAPACITY, "build capacities still exceeded after re-planning");
+    if (hb.overflow & kOverCoarse) t2cap = hb.coarse_used + hb.coarse_used / 16 + 4096;
+  }
+  const TreeInfo& ti = b.h_trees[0];
+  const Cube& cb = b.h_cubes[0];
+  for (int a = 0; a < 3; ++a) {
+    view->aabb_min[a] = cb.lo[a];
+    view->aabb_max[a] = cb.hi[a];
+  }
+  view->cube_side = cb.side;
+  view->num_nodes = ti.num_nodes;
+  view->num_points = n;
+  view->num_voxels = ti.vtotal;
+  view->node_level = b.o_level;
+  view->node_is_leaf = b.o_leaf;
+  view->node_child_mask = b.o_mask;
+  view->node_key = b.o_key;
+  view->node_npoints = b.o_npts;
+  view->node_count = b.o_count;
+  view->node_first_child = b.o_first;
+  view->node_offset = b.o_off;
+  view->points = b.Y;
+  view->point_ids = b.Yid;
+  view->voxels = (const lod_voxel*)b.vox;
+  view->voxel_ids = b.vids;
+  view->voxel_points = b.vpts;
+  *out_bytes = noalloc_out_bytes(c, pl);
+}
+
+}  // namespace
+
 namespace {
 
 lod_status check_params(const lod_params* p) {
@@ -952,6 +1091,41 @@ lod_status lod_build_batch(const lod_point* d_points, const uint64_t* h_offsets,
     return e.st;
   } catch (...) {
     set_err("unexpected host exception");
+    return LOD_ERR_OOM;
+  }
+}
+
+lod_status lod_build_noalloc(const lod_point* d_points, uint64_t n, const lod_params* p, void* hip_stream,
+                             void* d_out, uint64_t* out_bytes, lod_tree_view* view) {
+  if (!out_bytes || !view) {
+    set_err("out_bytes/view is NULL");
+    return LOD_ERR_INVALID;
+  }
+  if (check_params(p) != LOD_OK) {
+    set_err("invalid parameters");
+    return LOD_ERR_INVALID;
+  }
+  if (p->sampling == LOD_WEIGHTED) {
+    set_err("lod_build_noalloc does not take LOD_WEIGHTED (its pass needs scratch beyond the static array)");
+    return LOD_ERR_INVALID;
+  }
+  if (n >= 0xffffffffull || (n && !d_points)) {
+    set_err("n must be below 2^32 and d_points non-NULL");
+    return LOD_ERR_INVALID;
+  }
+  try {
+    std::lock_guard<std::mutex> g(g_na_mu);
+    lod_params q = *p;
+    q.flags &= ~(uint32_t)(LOD_FLAG_TIMING | LOD_FLAG_AUTOTUNE);
+    build_noalloc(d_points, n, q, (hipStream_t)hip_stream, d_out, out_bytes, view);
+    return LOD_OK;
+  } catch (const LodError& e) {
+    (void)hipGetLastError();
+    memset(view, 0, sizeof(*view));
+    return e.st;
+  } catch (...) {
+    set_err("unexpected host exception");
+    memset(view, 0, sizeof(*view));
     return LOD_ERR_OOM;
   }
 }

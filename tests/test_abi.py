@@ -143,3 +143,26 @@ def test_build_entry_does_not_need_a_built_library():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().endswith("ok")
+
+
+def test_noalloc_host_checks_before_any_device_work(lib):
+    """The allocation-free build refuses inputs its static scratch cannot
+    hold, and the weighted average, before touching the device; a NULL
+    output buffer is a size query."""
+    from paper_2302_14801_amd import binding
+    p = binding.lod_params()
+    lib.lod_params_default(ctypes.byref(p))
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced by these calls
+    nbytes, v = ctypes.c_uint64(0), binding.lod_tree_view()
+    assert lib.lod_build_noalloc(fake, 10_000_000, ctypes.byref(p), None, None, ctypes.byref(nbytes),
+                                 ctypes.byref(v)) == binding.LOD_ERR_TOO_LARGE
+    assert b"LOD_NOALLOC_SCRATCH_BYTES" in lib.lod_last_error()
+    assert lib.lod_build_noalloc(fake, 1_000_000, ctypes.byref(p), None, None, ctypes.byref(nbytes),
+                                 ctypes.byref(v)) == binding.LOD_OK
+    # points (16 B), node tables and room for n + 64 voxels (8 B)
+    assert nbytes.value >= 16 * 1_000_000 + 8 * 1_000_064
+    assert lib.lod_build_noalloc(fake, 1_000_000, ctypes.byref(p), None, None, None,
+                                 ctypes.byref(v)) == binding.LOD_ERR_INVALID
+    p.sampling = binding.LOD_WEIGHTED
+    assert lib.lod_build_noalloc(fake, 1000, ctypes.byref(p), None, None, ctypes.byref(nbytes),
+                                 ctypes.byref(v)) == binding.LOD_ERR_INVALID
