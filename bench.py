@@ -57,17 +57,14 @@ SAMPLING = {"average": 0, "first": 1, "random": 2, "weighted": 3}
 
 def stage_bytes(stage: str, n: int, ids: bool) -> float:
     """Bytes one launch of a stage moves when every array it touches is read
-    or written once: 16-byte records, 4-byte ids when carried, and the 2-byte
-    cell digit of the second partition that the first partition's insert
-    writes beside each record (the second partition counts and inserts from
-    it instead of projecting the record again)."""
+    or written once: 16-byte records, and 4-byte ids when carried."""
     idb = 4 if ids else 0
     return {
         "bbox": 16.0 * n,
         "count0": 16.0 * n,
-        "scatter0": (16.0 + idb + 16.0 + idb + 2.0) * n,
-        "count1": 2.0 * n,
-        "scatter1": (16.0 + idb + 2.0 + 16.0 + idb) * n,
+        "scatter0": (16.0 + idb + 16.0 + idb) * n,
+        "count1": 16.0 * n,
+        "scatter1": (16.0 + idb + 16.0 + idb) * n,
         "leaf_voxels": (16.0 + idb) * n,
     }.get(stage, 0.0)
 
