@@ -345,6 +345,8 @@ def main():
     ap.add_argument("--chunked-steps", type=int, default=2,
                     help="chunked builds of the same cloud from host memory (0 = skip)")
     ap.add_argument("--chunk-points", type=int, default=10_000_000, help="chunk size of the chunked build")
+    ap.add_argument("--chunked-forms", default="both", choices=["both", "resident", "streaming"],
+                    help="forms of the chunked build to time: cloud resident on the device, or streaming")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -459,19 +461,23 @@ def main():
     chunked = None
     if args.chunked_steps > 0:
         print(f"[bench] chunked build, {args.chunk_points} points per chunk", file=sys.stderr, flush=True)
-        pc = lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling)
-
-        def cstep():
+        def cstep(pc):
             t = lod.lod_build_chunked(pts, args.chunk_points, params=pc, stream=stream)
             v = t.view()
             info = (v.num_nodes, v.num_voxels)
             t.free()
             return info
 
-        cstep()
-        c0 = time.perf_counter()
-        cinfo = [cstep() for _ in range(args.chunked_steps)]
-        cms = 1e3 * (time.perf_counter() - c0) / args.chunked_steps
+        def ctime(low_memory):
+            pc = lod.make_params(leaf_cap=args.leaf_cap, max_level=args.max_level, sampling=sampling,
+                                 low_memory=low_memory)
+            cstep(pc)
+            c0 = time.perf_counter()
+            info = [cstep(pc) for _ in range(args.chunked_steps)]
+            return 1e3 * (time.perf_counter() - c0) / args.chunked_steps, info[-1]
+
+        cms, cinfo = ctime(False) if args.chunked_forms != "streaming" else (None, infos[-1])
+        sms, sinfo = ctime(True) if args.chunked_forms != "resident" else (None, infos[-1])
         h0 = time.perf_counter()
         for _ in range(args.chunked_steps):
             d2 = host.to("cuda:0", non_blocking=False)
@@ -480,11 +486,15 @@ def main():
             del d2
         torch.cuda.synchronize()
         hms = 1e3 * (time.perf_counter() - h0) / args.chunked_steps
-        chunked = {"chunk_points": args.chunk_points, "ms_per_build": round(cms, 2),
-                   "points_per_s": round(n / (cms * 1e-3), 1), "steps": args.chunked_steps,
-                   "in_core_from_host_ms": round(hms, 2), "same_nodes_and_voxels": cinfo[-1] == infos[-1],
-                   "note": "host input: a streaming pass for the cube, one that sorts each piece by cell on the GPU (its counts give the split level), "
-                           "chunk uploads and builds, the merge above the chunk roots"}
+        rnd = (lambda v: None if v is None else round(v, 2))
+        chunked = {"chunk_points": args.chunk_points, "ms_per_build": rnd(cms),
+                   "points_per_s": None if cms is None else round(n / (cms * 1e-3), 1), "steps": args.chunked_steps,
+                   "in_core_from_host_ms": round(hms, 2), "same_nodes_and_voxels": cinfo == infos[-1] == sinfo,
+                   "streaming_ms_per_build": rnd(sms),
+                   "note": "host input: one upload that also gives the cube, each piece sorted by cell on the GPU "
+                           "(its counts give the split level), chunk builds from the sorted pieces, the merge above "
+                           "the chunk roots; streaming (low-memory flag): the sorted pieces kept in host memory and "
+                           "chunks uploaded batch by batch"}
 
     cpu = None
     if args.cpu_sample > 0:

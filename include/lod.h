@@ -108,7 +108,13 @@ enum {
   /* lod_build_batch / lod_build with the tune_* fields 0: use the plan that
    * lod_tune_batch chooses for a workload of this class (tuning it on this
    * call's input the first time the class is seen in the process). */
-  LOD_FLAG_AUTOTUNE = 16
+  LOD_FLAG_AUTOTUNE = 16,
+  /* lod_build_chunked: stream the cloud through host memory, keeping only
+   * the pieces in flight and one batch of chunks on the device.  Without it
+   * the cloud stays on the device while it is sorted and cut into chunks
+   * whenever it fits in half of the free device memory (one host -> device
+   * pass instead of four PCIe crossings).  The result is the same. */
+  LOD_FLAG_LOW_MEMORY = 32
 };
 
 typedef struct {
@@ -206,16 +212,20 @@ lod_status lod_tune_batch(const lod_point* d_points, const uint64_t* h_offsets, 
  * combines them).  h_points: HOST array of n records (pageable or pinned),
  * borrowed; the result equals lod_build on the whole cloud (same nodes, node
  * order, leaf point sets, voxels and ids; ids are indices into h_points).
- * The cloud streams through the GPU in pieces of max(chunk_points, 2^20)
- * records for its bounding cube, and once more to be sorted by cell piece by
- * piece; it is cut at the shallowest level b (at most
- * min(7, max_level - 1)) whose cells hold at most chunk_points points, and
- * every cell of level b with more than T points is built as a chunk (chunks
- * are batched up to chunk_points points) with the common cube; the levels
- * above b are then voxelized from the chunk roots' voxels and the points of
- * the leaves above them.  Device memory: the build workspace of one batch,
- * plus the chunk results and the output tree (about twice the output).  Host
- * memory: 20 B per point (pinned) for the pieces sorted by cell on the GPU.
+ * The cloud goes to the GPU in pieces of max(chunk_points, 2^20) records for
+ * its bounding cube and is sorted by cell piece by piece; it is cut at the
+ * shallowest level b (at most min(7, max_level - 1)) whose cells hold at
+ * most chunk_points points, and every cell of level b with more than T points
+ * is built as a chunk (chunks are batched up to chunk_points points) with the
+ * common cube; the levels above b are then voxelized from the chunk roots'
+ * voxels and the points of the leaves above them.  When the cloud fits in
+ * half of the free device memory (40 B per point with ids) and
+ * LOD_FLAG_LOW_MEMORY is not set, the pieces stay on the device: one host ->
+ * device pass.  Otherwise they stream: uploaded once for the cube and once
+ * more to be sorted, sent back sorted (20 B per point of pinned host memory)
+ * and uploaded again batch by batch; device memory then holds the build
+ * workspace of one batch.  Both also hold the chunk results and the output
+ * tree (about twice the output).
  * With n <= chunk_points, or max_level < 2, this is
  * the in-core build of a device copy.  Every sampling mode and flag; with
  * LOD_FLAG_FULL_PRECISION the accepted samples' records are gathered from

@@ -6,7 +6,8 @@ The work runs in ``liblod.so`` (hand-written HIP kernels behind the C ABI in
 ``include/lod.h``); this package is a thin ctypes binding with the same names.
 Importing it loads the library and raises if it has not been built.
 """
-from .binding import (LOD_AVERAGE, LOD_FLAG_AUTOTUNE, LOD_FLAG_FULL_PRECISION, LOD_FLAG_NO_GRAPH,  # noqa: F401
+from .binding import (LOD_AVERAGE, LOD_FLAG_AUTOTUNE, LOD_FLAG_FULL_PRECISION, LOD_FLAG_LOW_MEMORY,
+                      LOD_FLAG_NO_GRAPH,  # noqa: F401
                       LOD_PICK_FIRST,
                       LOD_PICK_RANDOM, LOD_WEIGHTED,
                       LodError, Server, Tree,

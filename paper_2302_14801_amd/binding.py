@@ -23,6 +23,7 @@ LOD_FLAG_TIMING = 2
 LOD_FLAG_FULL_PRECISION = 4
 LOD_FLAG_NO_GRAPH = 8
 LOD_FLAG_AUTOTUNE = 16
+LOD_FLAG_LOW_MEMORY = 32
 
 
 class LodError(RuntimeError):
@@ -134,12 +135,13 @@ def _check(status: int):
 
 
 def make_params(leaf_cap=50000, max_level=12, sampling=LOD_AVERAGE, seed=0, keep_ids=False,
-                tune_levels0=0, tune_levels1=0, timing=False, tune_chunk=0, full_precision=False) -> lod_params:
+                tune_levels0=0, tune_levels1=0, timing=False, tune_chunk=0, full_precision=False,
+                low_memory=False) -> lod_params:
     p = lod_params()
     load_library().lod_params_default(ctypes.byref(p))
     p.leaf_cap, p.max_level, p.sampling, p.seed = leaf_cap, max_level, sampling, seed
     p.flags = ((LOD_FLAG_POINT_IDS if keep_ids else 0) | (LOD_FLAG_TIMING if timing else 0)
-               | (LOD_FLAG_FULL_PRECISION if full_precision else 0))
+               | (LOD_FLAG_FULL_PRECISION if full_precision else 0) | (LOD_FLAG_LOW_MEMORY if low_memory else 0))
     p.tune_levels0, p.tune_levels1, p.tune_chunk = tune_levels0, tune_levels1, tune_chunk
     return p
 

@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_scatter_cells(const uint4* __restrict__
   if (i >= n) return;
   const uint32_t pos = atomicAdd(cursor + cell[i], 1u);
   out[pos] = pts[i];
-  out_ids[pos] = id0 + i;
+  if (out_ids) out_ids[pos] = id0 + i;
 }
 
 // Few cells: a workgroup ranks a tile of 4096 points per cell in LDS, then
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) k_scatter_cells_lds(const uint4* __restri
     if (i < n) {
       const uint32_t pos = lb[cc[k]] + rk[k];
       out[pos] = pts[i];
-      out_ids[pos] = id0 + i;
+      if (out_ids) out_ids[pos] = id0 + i;
     }
   }
 }
@@ -423,6 +423,32 @@ void launch_voxel_records(const void* rec, const uint64_t* vox, uint64_t n, void
   if (!n) return;
   const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_voxel_records, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint4*)rec, vox, n, (uint4*)out);
+}
+
+// out[i] = {pts[ids[i]].x, .y, .z, colour of vox[i]}: the input records of
+// accepted samples gathered by id from a cloud on the device; an id beyond the
+// cloud raises *bad and writes nothing.
+__global__ void __launch_bounds__(256) k_voxel_records_by_id(const uint4* __restrict__ pts, uint32_t npts,
+                                                             const uint32_t* __restrict__ ids,
+                                                             const uint64_t* __restrict__ vox, uint64_t n,
+                                                             uint4* __restrict__ out, uint32_t* bad) {
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint32_t id = ids[i];
+    if (id >= npts) {
+      atomicOr(bad, 1u);
+      continue;
+    }
+    const uint4 r = pts[id];
+    out[i] = make_uint4(r.x, r.y, r.z, (uint32_t)(vox[i] >> 32));
+  }
+}
+
+void launch_voxel_records_by_id(const void* pts, uint32_t npts, const uint32_t* ids, const uint64_t* vox, uint64_t n,
+                                void* out, uint32_t* bad, hipStream_t s) {
+  if (!n) return;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_voxel_records_by_id, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint4*)pts, npts, ids, vox,
+                     n, (uint4*)out, bad);
 }
 
 // Run r copies runs[r].len elements from the device address runs[r].src to

@@ -128,7 +128,8 @@ void launch_cells(const void* pts, uint32_t n, const Cube* cube, uint32_t h, uin
                   hipStream_t s);
 // A piece sorted by cell (nbins <= 2^21 cells, hist: its histogram): tiles
 // (nbins / 4096 rounded up, at most 1024) and cursor (nbins) are scratch;
-// out / out_ids receive the points and their ids id0 + index.
+// out / out_ids receive the points and their ids id0 + index (out_ids may be
+// NULL).
 void launch_sort_by_cell(const void* pts, const uint32_t* cell, uint32_t n, uint32_t id0, const uint32_t* hist,
                          uint32_t nbins, uint32_t* tiles, uint32_t* cursor, void* out, uint32_t* out_ids,
                          hipStream_t s);
@@ -179,5 +180,8 @@ struct CopyRun {
 void launch_copy_runs(const CopyRun* runs, uint32_t nruns, uint32_t elem_bytes, void* dst, hipStream_t s);
 // out[i] = {rec[i].x, .y, .z, colour of vox[i]} (16-byte records).
 void launch_voxel_records(const void* rec, const uint64_t* vox, uint64_t n, void* out, hipStream_t s);
+// out[i] = {pts[ids[i]].x, .y, .z, colour of vox[i]}; an id >= npts sets *bad.
+void launch_voxel_records_by_id(const void* pts, uint32_t npts, const uint32_t* ids, const uint64_t* vox, uint64_t n,
+                                void* out, uint32_t* bad, hipStream_t s);
 
 }  // namespace lod

@@ -3,11 +3,14 @@
 // (Sec. 7: a bottom-up out-of-core pipeline cuts the input into chunks of
 // about 10M points, builds each on the GPU and combines them).
 //
-//   1. the bounding cube of the whole cloud, streaming it through the GPU;
-//   2. each piece sorted by cell on the GPU and sent back, so that a cell's
-//      points are one run per piece; the same pass counts the level-h cells
-//      (h <= 7), which give the split level b, the shallowest level whose
-//      cells hold at most chunk_points points;
+//   1. the bounding cube of the whole cloud, piece by piece on the GPU;
+//   2. each piece sorted by cell on the GPU, so that a cell's points are one
+//      run per piece; the same pass counts the level-h cells (h <= 7), which
+//      give the split level b, the shallowest level whose cells hold at most
+//      chunk_points points.  When the cloud fits in device memory it stays
+//      there (one host -> device pass for everything); otherwise the pieces
+//      stream: each is uploaded for the cube, uploaded again to be sorted,
+//      and sent back sorted, and chunks are uploaded batch by batch;
 //   4. the nodes of levels 0..b from the counts alone: a node at level L is
 //      inner iff it holds more than T points and L < max_level, exactly the
 //      in-core rule;
@@ -154,7 +157,7 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
       d_soff(dev), d_runs(dev), d_sorted(dev), d_sorted2(dev), d_sids(dev), d_sids2(dev), d_cursor(dev),
       d_tiles(dev), d_hist2(dev);
   HostBuf h_ci, h_cube, h_sorted, h_sids, h_vid, h_rec;
-  DevBuf d_rec(dev);
+  DevBuf d_rec(dev), d_res(dev), d_ress(dev), d_resid(dev), d_bruns(dev), d_bad(dev);
   std::vector<std::unique_ptr<DevBuf>> lvox, lvid;  // voxels of the levels above b
   Drain drain{s};  // declared last: the stream drains before any buffer above is released
 
@@ -165,10 +168,20 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     return lod_build_tree(dp, n, prm, s);
   }
 
+  // The cloud stays on the device when it fits in half of the free device
+  // memory: the input, its pieces sorted by cell and their ids.
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  const bool resident =
+      !(prm.flags & LOD_FLAG_LOW_MEMORY) && n * (32ull + (ids ? 8 : 0)) + (1ull << 30) <= free_b / 2;
+  lod_point* R = resident ? d_res.get<lod_point>(n) : nullptr;            // the input
+  lod_point* RS = resident ? d_ress.get<lod_point>(n) : nullptr;          // pieces sorted by cell
+  uint32_t* RSid = resident && ids ? d_resid.get<uint32_t>(n) : nullptr;  // their input indices
+
   // 1. the bounding cube, piece by piece (pieces of at least 2^20 points)
   const uint64_t P = std::min<uint64_t>(n, std::max<uint64_t>(chunk, 1u << 20));
   const uint64_t npieces = (n + P - 1) / P;
-  lod_point* stage = d_stage.get<lod_point>(P);
+  lod_point* stage = resident ? nullptr : d_stage.get<lod_point>(P);
   CloudInfo* hci = h_ci.get<CloudInfo>(npieces + 1);
   for (uint64_t k = 0; k < npieces; ++k) {
     const uint64_t m = std::min<uint64_t>(P, n - k * P);
@@ -183,8 +196,9 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   launch_bbox_reset(acc, s);
   for (uint64_t k = 0; k < npieces; ++k) {
     const uint64_t m = hci[k].count;
-    HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
-    launch_bbox_add(stage, dci + k, bbox_tiles((uint32_t)m), acc, s);
+    lod_point* dst = resident ? R + k * P : stage;
+    HIPCHK(hipMemcpyAsync(dst, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
+    launch_bbox_add(dst, dci + k, bbox_tiles((uint32_t)m), acc, s);
   }
   launch_bbox_cube(acc, dci + npieces, dcube, s);
   Cube* hc = h_cube.get<Cube>(1);
@@ -192,20 +206,22 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   HIPCHK(hipStreamSynchronize(s));
   if (hc->nonfinite) lod_fail(LOD_ERR_NONFINITE, "input contains a NaN or infinite coordinate");
 
-  // 2. every piece sorted by cell on the GPU and sent back, so that a cell's
-  // points are one run per piece.  Pieces are sorted by level s = min(h, 4)
+  // 2. every piece sorted by cell on the GPU (and sent back when streaming),
+  // so that a cell's points are one run per piece.  Pieces are sorted by level s = min(h, 4)
   // cells (at most 4096: counts and ranks in LDS), h = min(7, max_level - 1).
   // The sort's counts give the split level b, the shallowest level whose
   // cells hold at most chunk_points points, when that is level s or above;
   // otherwise a pass counts the level-h cells and the pieces are sorted
   // again by level-b cells.  pst[k][c]: first
   // point of cell c in piece k (piece k starts at k * PS of the sorted
-  // arrays).  The sorted pieces return on a second stream while the next
-  // piece is uploaded and sorted.
+  // arrays).  When streaming, the sorted pieces return on a second stream
+  // while the next piece is uploaded and sorted.
   const uint32_t h = std::min<uint32_t>(7, prm.max_level - 1);
   const uint32_t nh = 1u << (3 * h);
-  lod_point* sp = h_sorted.get<lod_point>(n);
-  uint32_t* sid = ids ? h_sids.get<uint32_t>(n) : nullptr;  // input indices travel only when used
+  // the sorted pieces on the host when streaming; input indices travel only
+  // when used
+  lod_point* sp = resident ? nullptr : h_sorted.get<lod_point>(n);
+  uint32_t* sid = !resident && ids ? h_sids.get<uint32_t>(n) : nullptr;
   std::vector<std::vector<uint32_t>> pst;
   uint32_t* hist_h = d_hist.get<uint32_t>(nh);
   uint64_t PS = 0, npieces_s = 0;
@@ -217,15 +233,30 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     npieces_s = (n + PS - 1) / PS;
     sorted_level = level;
     pst.assign(npieces_s, std::vector<uint32_t>((size_t)ns + 1));
-    stage = d_stage.get<lod_point>(PS);
     uint32_t* hist_s = d_hist2.get<uint32_t>(ns);
     uint32_t* dcell = d_cell.get<uint32_t>(PS);
     uint32_t* cursor = d_cursor.get<uint32_t>(ns);
     uint32_t* tiles = d_tiles.get<uint32_t>(1024);
-    lod_point* dsorted[2] = {d_sorted.get<lod_point>(PS), d_sorted2.get<lod_point>(PS)};
-    uint32_t* dsids[2] = {d_sids.get<uint32_t>(PS), d_sids2.get<uint32_t>(PS)};
+    if (resident) {
+      // every piece from the resident input into the resident sorted array
+      for (uint64_t k = 0; k < npieces_s; ++k) {
+        const uint64_t m = std::min<uint64_t>(PS, n - k * PS);
+        HIPCHK(hipMemsetAsync(hist_s, 0, 4ull * ns, s));
+        launch_cells(R + k * PS, (uint32_t)m, dcube, level, dcell, hist_s, s);
+        HIPCHK(hipMemcpyAsync(pst[k].data(), hist_s, 4ull * ns, hipMemcpyDeviceToHost, s));
+        launch_sort_by_cell(R + k * PS, dcell, (uint32_t)m, (uint32_t)(k * PS), hist_s, ns, tiles, cursor, RS + k * PS,
+                            RSid ? RSid + k * PS : nullptr, s);
+        HIPCHK(hipGetLastError());
+      }
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    stage = resident ? nullptr : d_stage.get<lod_point>(PS);
+    lod_point* dsorted[2] = {resident ? nullptr : d_sorted.get<lod_point>(PS),
+                             resident ? nullptr : d_sorted2.get<lod_point>(PS)};
+    uint32_t* dsids[2] = {resident ? nullptr : d_sids.get<uint32_t>(PS),
+                          resident ? nullptr : d_sids2.get<uint32_t>(PS)};
     SideStream s2;
-    for (uint64_t k = 0; k < npieces_s; ++k) {
+    for (uint64_t k = 0; !resident && k < npieces_s; ++k) {
       const uint64_t m = std::min<uint64_t>(PS, n - k * PS);
       const int q = (int)(k & 1);
       HIPCHK(hipMemcpyAsync(stage, hin + k * PS, 16ull * m, hipMemcpyHostToDevice, s));
@@ -282,11 +313,11 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     // level s is not fine enough: count the level-h cells, then sort again
     HIPCHK(hipMemsetAsync(hist_h, 0, 4ull * nh, s));
     uint32_t* dcell = d_cell.get<uint32_t>(P);
-    stage = d_stage.get<lod_point>(P);
+    stage = resident ? nullptr : d_stage.get<lod_point>(P);
     for (uint64_t k = 0; k < npieces; ++k) {
       const uint64_t m = hci[k].count;
-      HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
-      launch_cells(stage, (uint32_t)m, dcube, h, dcell, hist_h, s);
+      if (!resident) HIPCHK(hipMemcpyAsync(stage, hin + k * P, 16ull * m, hipMemcpyHostToDevice, s));
+      launch_cells(resident ? R + k * P : stage, (uint32_t)m, dcube, h, dcell, hist_h, s);
       HIPCHK(hipGetLastError());
     }
     std::vector<uint32_t> hh(nh);
@@ -370,8 +401,33 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     r0 = r1;
   }
   lod_point* bpts[2] = {d_stage.get<lod_point>(max_pts), d_sorted.get<lod_point>(max_pts)};
-  uint32_t* bids[2] = {sid ? d_ids.get<uint32_t>(max_pts) : nullptr, sid ? d_sids.get<uint32_t>(max_pts) : nullptr};
+  uint32_t* bids[2] = {ids ? d_ids.get<uint32_t>(max_pts) : nullptr, ids ? d_sids.get<uint32_t>(max_pts) : nullptr};
   SideStream up;
+  // resident: a batch's points gathered from the sorted pieces on the device
+  // (one run per root cell and piece) on the build stream
+  std::vector<CopyRun> pr, ir;  // read by the copies until the batch's closing synchronisation
+  auto gather = [&](size_t i) {
+    const int q = (int)(i & 1);
+    pr.clear();
+    ir.clear();
+    uint64_t o = 0;
+    for (size_t r = bstart[i]; r < bstart[i + 1]; ++r) {
+      const uint64_t c = roots[r];
+      for_runs(c, c + 1, [&](uint64_t beg, uint64_t len, uint64_t at) {
+        pr.push_back(CopyRun{RS + beg, o + at, len});
+        if (RSid) ir.push_back(CopyRun{RSid + beg, o + at, len});
+      });
+      o += cnt[b][c];
+    }
+    CopyRun* dr = d_bruns.get<CopyRun>(pr.size() + ir.size());
+    if (pr.empty()) return;
+    HIPCHK(hipMemcpyAsync(dr, pr.data(), sizeof(CopyRun) * pr.size(), hipMemcpyHostToDevice, s));
+    if (!ir.empty())
+      HIPCHK(hipMemcpyAsync(dr + pr.size(), ir.data(), sizeof(CopyRun) * ir.size(), hipMemcpyHostToDevice, s));
+    launch_copy_runs(dr, (uint32_t)pr.size(), 16, bpts[q], s);
+    if (!ir.empty()) launch_copy_runs(dr + pr.size(), (uint32_t)ir.size(), 4, bids[q], s);
+    HIPCHK(hipGetLastError());
+  };
   auto upload = [&](size_t i) {
     const int q = (int)(i & 1);
     uint64_t o = 0;
@@ -386,13 +442,17 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     HIPCHK(hipEventRecord(up.done[q], up.s));
   };
   const size_t nbatches = bstart.size() - 1;
-  if (nbatches) upload(0);
+  if (nbatches && !resident) upload(0);
   for (size_t i = 0; i < nbatches; ++i) {
     const size_t r0 = bstart[i], r1 = bstart[i + 1];
     const int q = (int)(i & 1);
-    // the other buffer pair was last read by batch i - 1, whose build has ended
-    if (i + 1 < nbatches) upload(i + 1);
-    HIPCHK(hipStreamWaitEvent(s, up.done[q], 0));
+    if (resident) {
+      gather(i);  // the run table is free: the previous batch ended with a synchronisation
+    } else {
+      // the other buffer pair was last read by batch i - 1, whose build has ended
+      if (i + 1 < nbatches) upload(i + 1);
+      HIPCHK(hipStreamWaitEvent(s, up.done[q], 0));
+    }
     lod_point* bp = bpts[q];
     uint32_t* bid = bids[q];
     std::vector<uint64_t> offs(r1 - r0 + 1, 0);
@@ -478,8 +538,8 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
     if (run != n) lod_fail(LOD_ERR_CAPACITY, "leaf points do not add up to the input");
   }
 
-  // 6. output points: top leaves from the sorted host points, chunk leaves
-  // from their trees
+  // 6. output points: top leaves from the sorted pieces (on the device, or
+  // on the host when streaming), chunk leaves from their trees
   std::shared_ptr<LodArena> arena = std::make_shared<LodArena>();
   arena->dev = dev;
   lod_point* Y = arena->alloc<lod_point>(n);
@@ -487,7 +547,12 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   std::vector<CopyRun> prun, irun;
   for (const MNode& m : nodes) {
     if (!m.leaf || !m.count) continue;
-    if (m.src == 0) {
+    if (m.src == 0 && resident) {
+      for_runs(m.c0, m.c1, [&](uint64_t beg, uint64_t len, uint64_t at) {
+        prun.push_back(CopyRun{RS + beg, m.off + at, len});
+        if (Yid) irun.push_back(CopyRun{RSid + beg, m.off + at, len});
+      });
+    } else if (m.src == 0) {
       for_runs(m.c0, m.c1, [&](uint64_t beg, uint64_t len, uint64_t at) {
         HIPCHK(hipMemcpyAsync(Y + m.off + at, sp + beg, 16ull * len, hipMemcpyHostToDevice, s));
         if (Yid) HIPCHK(hipMemcpyAsync(Yid + m.off + at, sid + beg, 4ull * len, hipMemcpyHostToDevice, s));
@@ -636,10 +701,20 @@ lod_tree* lod_build_chunked_tree(const lod_point* hin, uint64_t n, const lod_par
   run_copies(vrun, 8, vox);
   if (vids) run_copies(vidrun, 4, vids);
 
-  // full precision: the accepted samples' input records, gathered from the
-  // host cloud by id, with the voxels' colours
+  // full precision: the accepted samples' input records, gathered by id from
+  // the resident cloud or from the host cloud, with the voxels' colours
   lod_point* vpts = nullptr;
-  if (full && vtotal) {
+  if (full && vtotal && resident) {
+    vpts = arena->alloc<lod_point>(vtotal);
+    uint32_t* bad = d_bad.get<uint32_t>(1);
+    HIPCHK(hipMemsetAsync(bad, 0, 4, s));
+    launch_voxel_records_by_id(R, (uint32_t)n, vids, vox, vtotal, vpts, bad, s);
+    HIPCHK(hipGetLastError());
+    uint32_t hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad) lod_fail(LOD_ERR_CAPACITY, "an accepted sample id lies outside the input");
+  } else if (full && vtotal) {
     uint32_t* hv = h_vid.get<uint32_t>(vtotal);
     lod_point* hr = h_rec.get<lod_point>(vtotal);
     HIPCHK(hipMemcpyAsync(hv, vids, 4ull * vtotal, hipMemcpyDeviceToHost, s));

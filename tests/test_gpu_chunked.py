@@ -2,7 +2,9 @@
 built through cells of one level of the common cube and merged above them,
 equals the oracle's in-core tree of the whole cloud, and has the layout of
 the in-core GPU build (same node table, same voxel array, same leaf ranges),
-in all four sampling modes."""
+in all four sampling modes.  Each case runs both forms of the build: the
+cloud resident on the device (the default when it fits) and the streaming
+form that keeps the sorted pieces in host memory (LOD_FLAG_LOW_MEMORY)."""
 from __future__ import annotations
 
 import numpy as np
@@ -39,14 +41,17 @@ def check_chunked(lod, points, chunk, T, ml=12, sampling=0, seed=0, keep_ids=Fal
     print(f"case n={len(points)} chunk={chunk} T={T} ml={ml} sampling={sampling} full={full}", flush=True)
     kw = dict(leaf_cap=T, max_level=ml, sampling=sampling, seed=seed, keep_ids=keep_ids)
     params = lod.make_params(full_precision=full, **kw)
-    g = host_tree(lod.lod_build_chunked(np.ascontiguousarray(points), chunk, params=params))
     o = oracle.build(points, leaf_cap=T, max_level=ml, sampling=sampling, seed=seed, full_precision=full)
-    canon.compare_trees(g, o, points)
-    if full:
-        assert g["voxel_points"] is not None and g["voxel_ids"] is not None
-        for i in np.nonzero(g["is_leaf"] == 0)[0]:
-            go, oo, c = int(g["offset"][i]), int(o["offset"][i]), int(g["count"][i])
-            assert np.array_equal(g["voxel_points"][go:go + c], o["voxel_points"][oo:oo + c]), f"records of node {i}"
+    for low_memory in (True, False):  # the resident form last: it is returned
+        pm = lod.make_params(full_precision=full, low_memory=low_memory, **kw)
+        g = host_tree(lod.lod_build_chunked(np.ascontiguousarray(points), chunk, params=pm))
+        canon.compare_trees(g, o, points)
+        if full:
+            assert g["voxel_points"] is not None and g["voxel_ids"] is not None
+            for i in np.nonzero(g["is_leaf"] == 0)[0]:
+                go, oo, c = int(g["offset"][i]), int(o["offset"][i]), int(g["count"][i])
+                assert np.array_equal(g["voxel_points"][go:go + c], o["voxel_points"][oo:oo + c]), \
+                    f"records of node {i} (low_memory={low_memory})"
     d = host_tree(lod.lod_build(to_dev(points), params=params))
     for f in canon.NODE_FIELDS + ("offset",):
         assert np.array_equal(g[f], d[f]), f"node field {f} differs from the in-core build"
@@ -148,9 +153,10 @@ def test_empty(lod):
 def test_errors(lod):
     p = synth.uniform_cloud(1_000, 47)
     p["y"][500] = np.nan
-    with pytest.raises(lod.LodError) as e:
-        lod.lod_build_chunked(p, 100)
-    assert e.value.status == -2
+    for low_memory in (False, True):
+        with pytest.raises(lod.LodError) as e:
+            lod.lod_build_chunked(p, 100, params=lod.make_params(low_memory=low_memory))
+        assert e.value.status == -2
     with pytest.raises(lod.LodError) as e:
         lod.lod_build_chunked(synth.uniform_cloud(1_000, 48), 100, max_level=15)
     assert e.value.status == -1

@@ -145,6 +145,17 @@ def test_aerial_100m_chunked_equals_in_core():
     raw = np.ascontiguousarray(pts).view(np.uint8).reshape(-1, 16)
     assert np.array_equal(g["points"], raw[g["point_ids"]])
     fullsize.check_build(g, pts, T, ML)
+    fullsize.log("streaming chunked build (sorted pieces in host memory)")
+    t = lod.lod_build_chunked(pts, 10_000_000, params=lod.make_params(leaf_cap=T, max_level=ML, keep_ids=True,
+                                                                      low_memory=True))
+    s = t.to_host()
+    t.free()
+    for f in ("level", "key", "is_leaf", "npoints", "child_mask", "first_child", "count", "offset"):
+        assert np.array_equal(s[f], d[f]), f
+    assert np.array_equal(s["voxels"], d["voxels"])
+    ks = np.sort((owner << np.uint64(32)) | s["point_ids"].astype(np.uint64))
+    assert np.array_equal(ks, kb)
+    assert np.array_equal(s["points"], raw[s["point_ids"]])
 
 
 @pytest.mark.timeout(600)
