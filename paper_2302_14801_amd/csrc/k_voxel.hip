@@ -47,6 +47,7 @@ constexpr uint32_t kLeafPass = kLeafWG * kLeafSlots;
 constexpr uint32_t kNoCell = 0xffffffffu;
 constexpr uint64_t kMaxOneItemBlocks = 1ull << 22;  // workgroups of the one-item leaf launch (2^30 threads)
 constexpr uint32_t kCodeMask = (1u << 21) - 1;
+constexpr uint32_t kListCap = 3072;  // occupied depth-1 cells of a micro-bucket the shared list holds
 
 // Cells of one work item (a leaf's child cell) in the grid of the ancestor
 // k = 1..6 levels above the leaf: 8^(6-k).
@@ -232,6 +233,13 @@ __device__ __forceinline__ uint32_t smp_rgba(const Smp<MODE>& s) {
   return s.col;
 }
 
+// Coordinates of a depth-1 cell inside its micro-bucket from its 12-bit
+// Morton index: x | y << 8 | z << 16, 4 bits each.
+__device__ __forceinline__ uint32_t cell_xyz(uint32_t sc) {
+  auto c4 = [](uint32_t v) { return (v & 1u) | ((v >> 2) & 2u) | ((v >> 4) & 4u) | ((v >> 6) & 8u); };
+  return c4(sc) | (c4(sc >> 1) << 8) | (c4(sc >> 2) << 16);
+}
+
 // Exclusive prefix over the wave of counts below 2^BITS: one ballot per bit.
 template <int BITS>
 __device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c) {
@@ -371,6 +379,7 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   __shared__ uint64_t k4ok[8][8];              // depth-4 voxels of each micro-bucket: pick key and colour
   __shared__ uint32_t k4col[8][8];
   __shared__ uint32_t minid[MODE == 3 ? kSubCells : 1];  // mode 3: smallest id of every depth-1 cell
+  __shared__ uint16_t clist[avg_mode(MODE) ? kListCap : 1];  // occupied depth-1 cells in Morton order
   const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
   if (build_stopped(bs)) return;
   const uint32_t nitems = 8u * bs->total_nodes;
@@ -455,6 +464,10 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         // (no returned values, so nothing waits)
 #pragma unroll
         for (uint32_t k = 0; k < kLeafSlots; ++k) {
+          // slots whose points all lie outside the micro-bucket (a uniform test:
+          // the points are sorted by micro-bucket)
+          const uint32_t pk = P0 + k * kLeafWG;
+          if (pk >= off + cnt || pk + kLeafWG <= off) continue;
           // keep the per-slot work inside the loop over micro-buckets (hoisted
           // out of it, it would hold several registers per slot)
           asm volatile("" : "+v"(cell[k]), "+v"(col[k]));
@@ -495,10 +508,12 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         }
         lds_barrier();
       }
-      // coordinates of the thread's first depth-1 cell at level lvl + 6
-      const uint32_t Xb = (X0 << 6) | (((jm & 1u) | ((grp & 1u) << 1)) << 4) | xt;
-      const uint32_t Yb = (Y0 << 6) | ((((jm >> 1) & 1u) | (((grp >> 1) & 1u) << 1)) << 4) | yt;
-      const uint32_t Zb = (Z0 << 6) | ((((jm >> 2) & 1u) | (((grp >> 2) & 1u) << 1)) << 4) | zt;
+      // coordinates of the micro-bucket's first depth-1 cell at level lvl + 6,
+      // and of the thread's first one
+      const uint32_t Xm = (X0 << 6) | (((jm & 1u) | ((grp & 1u) << 1)) << 4);
+      const uint32_t Ym = (Y0 << 6) | ((((jm >> 1) & 1u) | (((grp >> 1) & 1u) << 1)) << 4);
+      const uint32_t Zm = (Z0 << 6) | ((((jm >> 2) & 1u) | (((grp >> 2) & 1u) << 1)) << 4);
+      const uint32_t Xb = Xm | xt, Yb = Ym | yt, Zb = Zm | zt;
       // Emission at depths 1..4, run once, or twice when an average cell
       // overflowed the packed sums (second round: exact colours of the wide
       // accumulation).  The occupancy bits are exact in both rounds, so the
@@ -589,6 +604,60 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
         Smp<MODE> h0 = smp_empty<MODE>(), h1 = smp_empty<MODE>();
         const uint32_t* colw = (const uint32_t*)(acc + 2048);
         bool ovf = false;
+        if (avg_mode(MODE) && round == 0 && tot1 <= kListCap) {
+          // Average modes: the occupied cells go into a list in Morton order
+          // (a cell's index there is its rank), which all threads then share,
+          // whatever the cells' spread over the threads.
+          for (uint32_t mm = m, lp = cross1 + (exs & 0x7ffu); mm; mm &= mm - 1)
+            clist[lp++] = (uint16_t)(16 * t + (uint32_t)__ffs(mm) - 1);
+          lds_barrier();
+          // depth 1: the voxels, each one's colour put back into acc as one
+          // sample of its depth-2 cell
+          const uint64_t vox1 = vox_at(0, Xm, Ym, Zm, 0);
+          for (uint32_t i = t; i < tot1; i += kLeafWG) {
+            const uint32_t sc = clist[i];
+            const uint64_t a = acc[sc];
+            const uint32_t c = (uint32_t)(a >> 48);
+            ovf |= c > 257;  // the packed sums are exact up to 257 samples
+            const uint32_t rgba =
+                mean_rgba((uint32_t)(a & 0xffffu), (uint32_t)((a >> 16) & 0xffffu), (uint32_t)((a >> 32) & 0xffffu), c);
+            if (MODE == 3) T1id[I0 + base1 + i] = minid[sc];
+            T1[I0 + base1 + i] = vox1 | cell_xyz(sc) | ((uint64_t)rgba << 32);
+            acc[sc] = (uint64_t)(rgba & 0xffu) | ((uint64_t)((rgba >> 8) & 0xffu) << 16) |
+                      ((uint64_t)((rgba >> 16) & 0xffu) << 32) | (1ull << 48);
+          }
+          lds_barrier();
+          // depth-2 cells 2t and 2t + 1 of the thread: sums of their depth-1
+          // voxels (at most 8 of 8-bit values per field); acc and the smallest
+          // ids return to their empty state
+#pragma unroll
+          for (uint32_t e = 0; e < 2; ++e) {
+            if (((m >> (8 * e)) & 0xffu) == 0) continue;
+            uint64_t* q = acc + 16 * t + 8 * e;
+            uint64_t sum = 0;
+#pragma unroll 2
+            for (uint32_t k = 0; k < 8; ++k) {
+              sum += q[k];
+              q[k] = 0;
+            }
+            Smp<MODE>& h = e ? h1 : h0;
+            h.r = (uint32_t)(sum & 0xffffu);
+            h.g = (uint32_t)((sum >> 16) & 0xffffu);
+            h.b = (uint32_t)((sum >> 32) & 0xffffu);
+            h.n = (uint32_t)(sum >> 48);
+            if (MODE == 3) {
+              uint32_t* mi = minid + 16 * t + 8 * e;
+              uint32_t mn = ~0u;
+#pragma unroll
+              for (uint32_t k = 0; k < 8; ++k) {
+                mn = min(mn, mi[k]);
+                mi[k] = ~0u;
+              }
+              h.ok = mn;
+            }
+          }
+          m = 0;
+        }
         while (m) {
           const uint32_t b = (uint32_t)(__ffs(m) - 1);
           m &= m - 1;
