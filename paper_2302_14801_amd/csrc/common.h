@@ -305,7 +305,9 @@ struct BuildState {
   uint64_t used_words;   // pool words in use
   uint64_t need_words;   // pool words the refinements asked for
   uint64_t vtotal;       // voxels of all trees
-  uint32_t pad0;
+  uint32_t redo_items;    // leaf work items handed to the general leaf kernel
+  uint32_t sparse_items;  // leaf work items listed for the sparse leaf kernel
+  uint32_t sparse_next;   // the sparse leaf kernel's next list position
   uint32_t pad;
 };
 

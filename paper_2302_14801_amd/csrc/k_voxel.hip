@@ -23,8 +23,13 @@
 //
 // Stages (each launched once per build, whatever the depth of the tree):
 //   k_item_desc      descriptor and coarse-list space of every (leaf, child
-//                    cell) work item
-//   k_leaf_voxels    the depth 1..6 lists of every item
+//                    cell) work item; in the average mode also the list of
+//                    items for the sparse kernel
+//   k_leaf_sparse    average mode: the depth 1..6 lists of the items that fit
+//                    its LDS (occupancy mask, ranks, one accumulator per
+//                    occupied cell)
+//   k_leaf_voxels    the depth 1..6 lists of every item (average mode: of the
+//                    items the sparse kernel leaves)
 //   k_piece_sizes    piece sizes of every node; self voxels of deep leaves
 //   k_vox_tree       subtree sizes, depth-first order, inner self voxels
 //   k_piece_count    voxel count of every inner node
@@ -48,6 +53,13 @@ constexpr uint32_t kNoCell = 0xffffffffu;
 constexpr uint64_t kMaxOneItemBlocks = 1ull << 22;  // workgroups of the one-item leaf launch (2^30 threads)
 constexpr uint32_t kCodeMask = (1u << 21) - 1;
 constexpr uint32_t kListCap = 3072;  // occupied depth-1 cells of a micro-bucket the shared list holds
+// the sparse average-mode leaf kernel (k_leaf_sparse)
+constexpr int kSpWG = 512;                          // 8 waves
+constexpr uint32_t kSpSlots = 16;                   // points per thread
+constexpr uint32_t kSpMaxPts = kSpWG * kSpSlots;    // 8192
+constexpr uint32_t kSpWords = 32768 / 32;           // occupancy words of an item
+constexpr uint32_t kSpCap = 4096;                   // occupied cells of all depths an item may have
+constexpr uint32_t kSpNone = 0xffffu;               // no point in a slot
 
 // Cells of one work item (a leaf's child cell) in the grid of the ancestor
 // k = 1..6 levels above the leaf: 8^(6-k).
@@ -277,10 +289,25 @@ __device__ __forceinline__ Item item_of(const Nodes& nodes, uint32_t n, uint32_t
 // ------------------------------------------------------------ item descriptors
 //
 // One thread per item.  Coarse-list blocks are handed out by a wave-wide
-// prefix sum and one atomic add per wave on bs->coarse_used.
+// prefix sum and one atomic add per wave on bs->coarse_used.  With `sparse`
+// (the average mode) the item is also routed: an empty item gets its list
+// lengths (all zero) here, an item of at most kSpMaxPts points goes on the
+// sparse kernel's list, a larger one on the general kernel's (`redo`); both
+// lists are filled with one atomic add per wave.
+__device__ __forceinline__ void wave_append(bool take, uint32_t value, uint32_t* ctr, uint32_t* list) {
+  const uint64_t m = __ballot(take);
+  if (!m) return;
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (take) list[base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1))] = value;
+}
 __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, const GridDesc* __restrict__ grids,
                                                    const uint32_t* __restrict__ pool, BuildState* bs,
-                                                   ItemDesc* __restrict__ desc, uint64_t t2cap) {
+                                                   ItemDesc* __restrict__ desc, uint64_t t2cap, bool sparse,
+                                                   uint32_t* __restrict__ icnt, uint32_t* __restrict__ slist,
+                                                   uint32_t* __restrict__ redo) {
   if (build_stopped(bs)) return;
   const uint32_t nitems = 8u * bs->total_nodes;
   for (uint32_t i0 = blockIdx.x * 256; i0 < nitems; i0 += gridDim.x * 256) {  // uniform per workgroup
@@ -318,6 +345,12 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, const GridDesc* 
     const uint4* src = (const uint4*)&d;
     uint4* dst = (uint4*)(desc + i);
     for (int k = 0; k < 4; ++k) dst[k] = src[k];
+  }
+  if (sparse) {
+    if (valid && d.P == 0)
+      for (int k = 0; k < 6; ++k) icnt[6ull * i + k] = 0;
+    wave_append(valid && d.P != 0 && d.P <= kSpMaxPts, i, &bs->sparse_items, slist);
+    wave_append(valid && d.P > kSpMaxPts, i, &bs->redo_items, redo);
   }
   }
 }
@@ -360,7 +393,8 @@ __global__ void __launch_bounds__(256) k_item_desc(Nodes nodes, const GridDesc* 
 // Workgroup b takes work item item0 + b; with LOOP also item0 + b + gridDim.x,
 // ... (a loop over items keeps more registers live: the one-item form is the
 // fast one, launched over the expected number of items, and the looping form
-// takes whatever items lie beyond it).
+// takes whatever items lie beyond it).  With `list`, the indices are positions
+// in that list of items (bs->redo_items of them) instead of items.
 template <int MODE, bool LOOP>  // MODE: 0 average, 1 first, 2 random, 3 average with smallest ids
 __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(const ItemDesc* __restrict__ desc,
                                                                           const uint4* __restrict__ pts,
@@ -371,7 +405,8 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
                                                                           uint32_t* __restrict__ T2id,
                                                                           uint32_t* __restrict__ icnt,
                                                                           uint64_t* __restrict__ iself, uint32_t seed,
-                                                                          const BuildState* bs, uint32_t item0) {
+                                                                          const BuildState* bs, uint32_t item0,
+                                                                          const uint32_t* __restrict__ list) {
   __shared__ uint64_t acc[kSubCells];
   __shared__ uint32_t bm1[2][kSubCells / 32];  // depth-1 occupancy, alternating between micro-buckets
   __shared__ uint32_t over[8];                 // a cell of the micro-bucket passed 257 samples
@@ -382,8 +417,10 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   __shared__ uint16_t clist[avg_mode(MODE) ? kListCap : 1];  // occupied depth-1 cells in Morton order
   const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
   if (build_stopped(bs)) return;
-  const uint32_t nitems = 8u * bs->total_nodes;
-  for (uint32_t item = item0 + blockIdx.x; item < nitems; item += gridDim.x) {
+  // all work items, or (list) the ones the sparse kernel handed over
+  const uint32_t nitems = list ? bs->redo_items : 8u * bs->total_nodes;
+  for (uint32_t li = item0 + blockIdx.x; li < nitems; li += gridDim.x) {
+  const uint32_t item = list ? list[li] : li;
   if (LOOP) __syncthreads();  // the previous item's reads of LDS are done
   const ItemDesc& sd = desc[item];  // uniform: scalar loads
   const uint32_t P = sd.P;
@@ -803,6 +840,305 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   }
 }
 
+// ------------------------------------------------------------ sparse leaf kernel (average)
+//
+// The average mode's fast path.  A work item's 8 micro-buckets are taken at
+// once: their 32768 depth-1 cells (5 levels below the leaf's child cell) form
+// a 32768-bit occupancy mask in LDS, and one workgroup-wide scan of the mask
+// ranks the occupied cells of every depth (a cell's rank is its position in
+// its depth's list, which is in Morton order).  Each depth then has one
+// accumulator and one cell code per occupied cell, packed one depth after the
+// other in a pool: a sample adds its colour to its cell's accumulator with
+// one 64-bit LDS atomic (16-bit fields, as in the general kernel), and each
+// depth is emitted one occupied cell per thread, whose colour is in turn a
+// sample of its parent.  The work is proportional to the points and the
+// occupied cells; nothing is done per empty cell.
+//   Phase A: load the points (at most kSpMaxPts, kept in registers as cell
+//            code and colour) and set the occupancy bits.
+//   Phase B: thread t owns mask words 2t, 2t + 1: depth-1 cells 64t..64t+63,
+//            i.e. depth-2 cells 8t..8t+7 (its "byte mask") and depth-3 cell
+//            t; depth-4 cell g is threads 8g..8g+7 and the depth-5 cell (a
+//            micro-bucket) w is wave w.  A block scan of (depth-1 cells |
+//            depth-2 cells << 16) per thread, ballots and the waves' totals
+//            give the rank of each word's first depth-1 cell, of each thread's
+//            first depth-2 cell, and of each depth-3, 4 and 5 cell.
+//   Phase C: every sample into its depth-1 cell.
+//   Depths 1 .. 5: one occupied cell per thread: mean colour, voxel, and the
+//            colour into the parent's accumulator.  Depth 6 is the item.
+// An item with more points or occupied cells than the LDS holds, or a cell
+// with more than 257 samples (beyond the exact range of the 16-bit sums), is
+// listed in `redo` and left to the general kernel, which rewrites all of its
+// outputs.  Lists, counts and the item's own voxel are those of k_leaf_voxels<0>.
+
+// Bits 0, 3, 6, ... of x gathered into bits 0, 1, 2, ... (inverse of spread10).
+__host__ __device__ __forceinline__ uint32_t compact10(uint32_t x) {
+  x &= 0x09249249u;
+  x = (x | (x >> 2)) & 0x030c30c3u;
+  x = (x | (x >> 4)) & 0x0300f00fu;
+  x = (x | (x >> 8)) & 0x030000ffu;
+  x = (x | (x >> 16)) & 0x000003ffu;
+  return x;
+}
+// Voxel of a cell with 21-bit Morton code `code` in its ancestor's grid.
+__device__ __forceinline__ uint64_t sp_voxel(uint32_t code, uint32_t rgba) {
+  return (uint64_t)(compact10(code) | (compact10(code >> 1) << 8) | (compact10(code >> 2) << 16)) |
+         ((uint64_t)rgba << 32);
+}
+// An 8-bit colour as one sample in the packed form of the accumulators.
+__device__ __forceinline__ uint64_t sp_sample(uint32_t rgba) {
+  return (uint64_t)(rgba & 0xffu) | ((uint64_t)((rgba >> 8) & 0xffu) << 16) |
+         ((uint64_t)((rgba >> 16) & 0xffu) << 32) | (1ull << 48);
+}
+__device__ __forceinline__ uint32_t sp_mean(uint64_t a) {
+  return mean_rgba((uint32_t)(a & 0xffffu), (uint32_t)((a >> 16) & 0xffffu), (uint32_t)((a >> 32) & 0xffffu),
+                   (uint32_t)(a >> 48));
+}
+// quantize() for a coordinate inside the cube (p >= lo, so the scaled value
+// is at least 0 and at most 2^21 up to rounding): truncation is the floor
+// there, and only the upper clamp can apply.
+__device__ __forceinline__ uint32_t quantize_in_cube(float p, double lo, double scale) {
+  const double v = __dmul_rn(__dsub_rn((double)p, lo), scale);
+  return min((uint32_t)v, kMaxQ);
+}
+
+__global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __restrict__ desc,
+                                                       const uint4* __restrict__ pts, const Cube* cube,
+                                                       uint64_t* __restrict__ T1, uint64_t* __restrict__ T2,
+                                                       uint32_t* __restrict__ icnt, uint64_t* __restrict__ iself,
+                                                       BuildState* bs, const uint32_t* __restrict__ list,
+                                                       uint32_t* __restrict__ redo) {
+  __shared__ uint32_t mask[kSpWords];
+  __shared__ uint16_t wpre[kSpWords];  // rank of the first occupied depth-1 cell of each word
+  __shared__ uint64_t acc[kSpCap];     // accumulators of depths 1 .. 6, one after the other
+  __shared__ uint16_t code[kSpCap];    // cell codes (index within the item at that depth)
+  __shared__ uint16_t pre2[kSpWG];     // rank of each thread's first depth-2 cell
+  __shared__ uint16_t rk3[kSpWG];      // rank of each depth-3 cell
+  __shared__ uint8_t bm2[kSpWG];       // each thread's depth-2 cells
+  __shared__ uint8_t rk4[64], rk5[8];  // ranks of the depth-4 and depth-5 cells
+  __shared__ uint32_t wtot[8], wocc[8];
+  __shared__ uint32_t flag, nxt;
+  const uint32_t t0 = threadIdx.x;
+  if (build_stopped(bs)) return;
+  // Resident workgroups take list positions from a counter.  While an item's
+  // voxels are emitted, the first kSpWG * 8 points of the next one are
+  // already on their way into registers.
+  const uint32_t nlist = bs->sparse_items;
+  if (t0 == 0) nxt = atomicAdd(&bs->sparse_next, 1u);
+  __syncthreads();
+  const uint32_t li0 = nxt;
+  if (li0 >= nlist) return;
+  uint32_t item = list[li0];
+  uint4 pv[8];  // the current item's first points
+  {
+    const ItemDesc& sn = desc[item];
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      uint4 x = make_uint4(0u, 0u, 0u, 0u);  // every lane assigns: the old values die here
+      if (k * kSpWG + t0 < sn.P) x = pts[sn.I0 + k * kSpWG + t0];
+      pv[k] = x;
+    }
+  }
+  for (;;) {
+  // values derived from the thread index are recomputed in every iteration
+  // (hoisted out of the loop they would hold registers throughout)
+  uint32_t t = t0;
+  asm volatile("" : "+v"(t));
+  const uint32_t w = t >> 6, l = t & 63u;
+  const ItemDesc& sd = desc[item];  // uniform: scalar loads
+  const uint32_t P = sd.P;
+  const CubeD cd = load_cube(cube + sd.tree);
+  const uint32_t I0 = sd.I0, lvl = sd.lvl, grp = item & 7u;
+  const uint32_t lk = (uint32_t)sd.lkey;
+  const uint64_t t2b = sd.t2;
+  const uint32_t sub_bit = 15u - lvl;  // bit level of the depth-1 cells (level lvl + 6)
+  __syncthreads();  // the previous item's reads of LDS (and of nxt) are done
+  mask[t] = 0;
+  mask[t + kSpWG] = 0;
+  if (t == 0) {
+    flag = 0;
+    nxt = atomicAdd(&bs->sparse_next, 1u);
+  }
+  __syncthreads();
+  const uint32_t li = nxt;
+  const bool more = li < nlist;
+
+  // ---- phase A: cells, colours, occupancy
+  uint32_t col[kSpSlots], cc[kSpSlots / 2];
+#pragma unroll
+  for (uint32_t h = 0; h < 2; ++h) {
+    const uint32_t b0 = h * 8 * kSpWG;
+    if (b0 >= P) {  // uniform
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) cc[4 * h + k] = kSpNone | (kSpNone << 16);
+      continue;
+    }
+    uint4 v1[8];  // the points after the first 8 * kSpWG
+    if (h) {
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k)
+        if (b0 + k * kSpWG + t < P) v1[k] = pts[I0 + b0 + k * kSpWG + t];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      const uint32_t i = b0 + k * kSpWG + t;
+      uint32_t c = kSpNone;
+      if (i < P) {
+        const uint4 v = h ? v1[k] : pv[k];
+        const uint32_t qx = (quantize_in_cube(__uint_as_float(v.x), cd.lo[0], cd.scale) >> sub_bit) & 31u;
+        const uint32_t qy = (quantize_in_cube(__uint_as_float(v.y), cd.lo[1], cd.scale) >> sub_bit) & 31u;
+        const uint32_t qz = (quantize_in_cube(__uint_as_float(v.z), cd.lo[2], cd.scale) >> sub_bit) & 31u;
+        c = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+        atomicOr(&mask[c >> 5], 1u << (c & 31u));
+        col[8 * h + k] = v.w;
+      }
+      if (k & 1) cc[4 * h + k / 2] |= c << 16;
+      else cc[4 * h + k / 2] = c;
+    }
+  }
+  __syncthreads();
+
+  // ---- phase B: ranks
+  const uint32_t m0 = mask[2 * t], m1 = mask[2 * t + 1];
+  auto nzb = [](uint32_t x) {  // nonzero bytes of a word, as 4 bits
+    uint32_t y = x | (x >> 4);
+    y |= y >> 2;
+    y |= y >> 1;
+    y &= 0x01010101u;
+    return (y | (y >> 7) | (y >> 14) | (y >> 21)) & 15u;
+  };
+  const uint32_t b2 = nzb(m0) | (nzb(m1) << 4);  // occupied depth-2 cells 8t + b
+  const uint32_t a = (uint32_t)(__popc(m0) + __popc(m1)) | ((uint32_t)__popc(b2) << 16);
+  const uint32_t inc = wave_incl_scan_dpp(a);
+  const uint64_t b3 = __ballot(b2 != 0u);  // bit l: depth-3 cell 64w + l occupied
+  uint32_t m4 = 0;                         // occupied depth-4 cells (groups of 8 lanes) of the wave
+#pragma unroll
+  for (int q = 0; q < 8; ++q) m4 |= ((b3 >> (8 * q)) & 0xffu) ? (1u << q) : 0u;
+  if (l == 63) {
+    wtot[w] = inc;
+    wocc[w] = (uint32_t)__popcll(b3) | ((uint32_t)__popc(m4) << 10) | ((inc != 0u ? 1u : 0u) << 20);
+  }
+  __syncthreads();
+  uint32_t xa = 0, xo = 0, ta = 0, to = 0;
+#pragma unroll
+  for (uint32_t v = 0; v < 8; ++v) {
+    const uint32_t A = wtot[v], O = wocc[v];
+    if (v < w) {
+      xa += A;
+      xo += O;
+    }
+    ta += A;
+    to += O;
+  }
+  const uint32_t exa = inc - a;
+  const uint32_t ex1 = (xa & 0xffffu) + (exa & 0xffffu), ex2 = (xa >> 16) + (exa >> 16);
+  const uint32_t tot1 = ta & 0xffffu, tot2 = ta >> 16;
+  const uint32_t tot3 = to & 0x3ffu, tot4 = (to >> 10) & 0x7fu, tot5 = (to >> 20) & 0xfu;
+  // pool offsets of depths 2 .. 6
+  const uint32_t o2 = tot1, o3p = o2 + tot2, o4 = o3p + tot3, o5 = o4 + tot4, o6 = o5 + tot5;
+  const bool fits = o6 + 1 <= kSpCap;  // uniform
+  if (fits) {
+    wpre[2 * t] = (uint16_t)ex1;
+    wpre[2 * t + 1] = (uint16_t)(ex1 + (uint32_t)__popc(m0));
+    pre2[t] = (uint16_t)ex2;
+    bm2[t] = (uint8_t)b2;
+    const uint64_t below = (1ull << l) - 1;
+    rk3[t] = (uint16_t)((xo & 0x3ffu) + (uint32_t)__popcll(b3 & below));
+    if ((l & 7u) == 0)
+      rk4[t >> 3] = (uint8_t)(((xo >> 10) & 0x7fu) + (uint32_t)__popc(m4 & ((1u << (l >> 3)) - 1u)));
+    if (l == 0) rk5[w] = (uint8_t)((xo >> 20) & 0xfu);
+    for (uint32_t r = t; r <= o6; r += kSpWG) acc[r] = 0;
+  }
+  __syncthreads();
+
+  // ---- phase C: samples into their depth-1 cells
+  if (fits) {
+#pragma unroll
+    for (uint32_t k = 0; k < kSpSlots; ++k) {
+      const uint32_t c = (cc[k / 2] >> (16 * (k & 1))) & 0xffffu;
+      if (c != kSpNone) {
+        const uint32_t r = wpre[c >> 5] + (uint32_t)__popc(mask[c >> 5] & ((1u << (c & 31u)) - 1u));
+        atomicAdd((unsigned long long*)&acc[r], (unsigned long long)sp_sample(col[k]));
+        code[r] = (uint16_t)c;
+      }
+    }
+  }
+  // the next item's first points
+  uint32_t nitem = 0;
+  if (more) {
+    nitem = list[li];
+    const ItemDesc& sn = desc[nitem];
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      uint4 x = make_uint4(0u, 0u, 0u, 0u);
+      if (k * kSpWG + t < sn.P) x = pts[sn.I0 + k * kSpWG + t];
+      pv[k] = x;
+    }
+  }
+  __syncthreads();
+
+  // ---- depth 1: voxels, and their colours into the depth-2 cells
+  if (fits) {
+    const uint32_t hi = ((lk & 7u) << 18) | (grp << 15);
+    bool ovf = false;
+    for (uint32_t r = t; r < tot1; r += kSpWG) {
+      const uint64_t s = acc[r];
+      const uint32_t c = code[r];
+      ovf |= (uint32_t)(s >> 48) > 257u;  // the packed sums are exact up to 257 samples
+      const uint32_t rgba = sp_mean(s);
+      T1[(uint64_t)I0 + r] = sp_voxel(hi | c, rgba);
+      const uint32_t d = c >> 3, u = c >> 6;  // depth-2 cell, its owner thread
+      const uint32_t r2 = o2 + pre2[u] + (uint32_t)__popc(bm2[u] & ((1u << (d & 7u)) - 1u));
+      atomicAdd((unsigned long long*)&acc[r2], (unsigned long long)sp_sample(rgba));
+      code[r2] = (uint16_t)d;
+    }
+    if (ovf) flag = 1;
+  }
+  __syncthreads();
+  if (fits && !flag) {  // uniform
+    // ---- depths 2 .. 5: the same one level up (depth 2 -> 3 -> 4 -> 5 -> 6)
+    const uint32_t cb[5] = {0u, coarse_base(3, P), coarse_base(4, P), coarse_base(5, P), coarse_base(6, P)};
+    const uint32_t off[6] = {o2, o3p, o4, o5, o6, o6 + 1};
+    const uint32_t tot[4] = {tot2, tot3, tot4, tot5};
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {  // depth k + 2
+      const uint32_t dep = k + 2;
+      const uint32_t hi = ((lk & ((1u << (3 * dep)) - 1u)) << (21 - 3 * dep)) | (grp << (18 - 3 * dep));
+      for (uint32_t r = t; r < tot[k]; r += kSpWG) {
+        const uint64_t s = acc[off[k] + r];
+        const uint32_t c = code[off[k] + r];
+        const uint32_t rgba = sp_mean(s);
+        T2[t2b + cb[k] + r] = sp_voxel(hi | c, rgba);
+        uint32_t rp;  // the parent's rank
+        if (k == 0) rp = rk3[c >> 3];
+        else if (k == 1) rp = rk4[c >> 3];
+        else if (k == 2) rp = rk5[c >> 3];
+        else rp = 0;
+        atomicAdd((unsigned long long*)&acc[off[k + 1] + rp], (unsigned long long)sp_sample(rgba));
+        if (k < 3) code[off[k + 1] + rp] = (uint16_t)(c >> 3);
+      }
+      __syncthreads();
+    }
+    // ---- depth 6: the item
+    if (t == 0) {
+      const uint32_t rgba = sp_mean(acc[o6]);
+      T2[t2b + cb[4]] = sp_voxel(((lk & 262143u) << 3) | grp, rgba);
+      iself[item] = (uint64_t)rgba << 32;
+      uint32_t* ic = icnt + 6 * item;
+      ic[0] = tot1;
+      ic[1] = tot2;
+      ic[2] = tot3;
+      ic[3] = tot4;
+      ic[4] = tot5;
+      ic[5] = 1;
+    }
+  } else if (t == 0) {
+    redo[atomicAdd(&bs->redo_items, 1u)] = item;
+  }
+  if (!more) break;
+  item = nitem;
+  }
+}
+
 // ------------------------------------------------------------ tree pass
 //
 // Piece sizes of every node (one thread per node):
@@ -1121,9 +1457,24 @@ static uint32_t grid_blocks(uint64_t units, uint32_t per_block, uint32_t cap) {
 }
 
 void launch_item_desc(const Nodes& nodes, uint32_t max_nodes, const GridDesc* grids, const uint32_t* pool,
-                      BuildState* bs, void* desc, uint64_t t2cap, hipStream_t s) {
+                      BuildState* bs, void* desc, uint64_t t2cap, bool sparse, uint32_t* icnt, uint32_t* slist,
+                      uint32_t* redo, hipStream_t s) {
   hipLaunchKernelGGL(k_item_desc, dim3(grid_blocks(8ull * max_nodes, 256, 4096)), dim3(256), 0, s, nodes, grids, pool,
-                     bs, (ItemDesc*)desc, t2cap);
+                     bs, (ItemDesc*)desc, t2cap, sparse, icnt, slist, redo);
+}
+
+// Workgroups of the sparse leaf kernel that fit on the device at once (two
+// per compute unit at four waves per SIMD).
+static uint32_t sparse_resident_blocks() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cached[dev] = cus;
+  }
+  return 2u * (uint32_t)cached[dev];
 }
 
 #define LOD_MODE_SWITCH(mode, M, BODY) \
@@ -1148,21 +1499,35 @@ void launch_item_desc(const Nodes& nodes, uint32_t max_nodes, const GridDesc* gr
 
 void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, uint32_t expect_items, const void* desc, const void* pts,
                         const uint32_t* ids, const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2,
-                        uint32_t* T2id, uint32_t* icnt, uint64_t* iself, uint32_t seed, const BuildState* bs,
-                        hipStream_t s) {
+                        uint32_t* T2id, uint32_t* icnt, uint64_t* iself, uint32_t seed, BuildState* bs,
+                        const uint32_t* slist, uint32_t* redo, hipStream_t s) {
   // one workgroup per expected item (the workgroups past the real count
   // return at once), then a resident grid that loops over any items beyond;
   // a launch holds fewer than 2^32 threads
   const uint64_t cap = 8ull * max_nodes;
   const uint32_t g1 =
       (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(std::min<uint64_t>(cap, expect_items), kMaxOneItemBlocks));
+  const ItemDesc* d = (const ItemDesc*)desc;
+  const uint4* p = (const uint4*)pts;
+  if (mode == 0) {
+    // the sparse kernel over its list (resident workgroups), then the general
+    // kernel over the items listed for it (one-item form for the first g1 / 16,
+    // looping form for any more)
+    const uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(sparse_resident_blocks(), cap));
+    hipLaunchKernelGGL(k_leaf_sparse, dim3(gs), dim3(kSpWG), 0, s, d, p, cube, T1, T2, icnt, iself, bs, slist, redo);
+    const uint32_t g2 = std::max<uint32_t>(1, g1 / 16);
+    hipLaunchKernelGGL((k_leaf_voxels<0, false>), dim3(g2), dim3(kLeafWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id,
+                       icnt, iself, seed, bs, 0u, (const uint32_t*)redo);
+    hipLaunchKernelGGL((k_leaf_voxels<0, true>), dim3(256), dim3(kLeafWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id,
+                       icnt, iself, seed, bs, g2, (const uint32_t*)redo);
+    return;
+  }
   LOD_MODE_SWITCH(mode, M, {
-    hipLaunchKernelGGL((k_leaf_voxels<M, false>), dim3(g1), dim3(kLeafWG), 0, s, (const ItemDesc*)desc,
-                       (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt, iself, seed, bs, 0u);
+    hipLaunchKernelGGL((k_leaf_voxels<M, false>), dim3(g1), dim3(kLeafWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id,
+                       icnt, iself, seed, bs, 0u, (const uint32_t*)nullptr);
     if (cap > g1)
-      hipLaunchKernelGGL((k_leaf_voxels<M, true>), dim3(grid_blocks(cap - g1, 1, 1024)), dim3(kLeafWG), 0, s,
-                         (const ItemDesc*)desc, (const uint4*)pts, ids, cube, T1, T1id, T2, T2id, icnt, iself, seed,
-                         bs, g1);
+      hipLaunchKernelGGL((k_leaf_voxels<M, true>), dim3(grid_blocks(cap - g1, 1, 1024)), dim3(kLeafWG), 0, s, d, p, ids,
+                         cube, T1, T1id, T2, T2id, icnt, iself, seed, bs, g1, (const uint32_t*)nullptr);
   })
 }
 

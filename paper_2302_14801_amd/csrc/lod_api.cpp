@@ -412,6 +412,8 @@ struct Bufs {
   ItemDesc* desc;
   uint32_t* icnt;
   uint64_t* iself;
+  uint32_t* redo;
+  uint32_t* slist;
   uint64_t* T2;
   uint32_t* T2id;
   VoxTree vt;
@@ -479,6 +481,8 @@ RegionSizes layout(Bufs& b, const Caps& c, const Plan& pl, bool cube_given, bool
   b.desc = s.take<ItemDesc>(items);
   b.icnt = s.take<uint32_t>(6 * items);
   b.iself = s.take<uint64_t>(items);
+  b.redo = s.take<uint32_t>(items);
+  b.slist = s.take<uint32_t>(pl.mode == 0 ? items : 1);
   b.T2 = s.take<uint64_t>(c.t2cap);
   b.T2id = pl.mode ? s.take<uint32_t>(c.t2cap) : nullptr;
   b.vt.sz = s.take<uint32_t>(c.max_nodes);
@@ -587,9 +591,10 @@ void enqueue(const Bufs& b, const Caps& c, const Plan& pl, const lod_params& prm
   // (depth 1 into X, coarser ones into T2), the tree pass and the offsets,
   // then the pieces' positions and the gather
   uint64_t* T1 = (uint64_t*)b.X;
-  launch_item_desc(b.cn, c.max_nodes, b.grids, b.pool, b.bs, b.desc, c.t2cap, s);
+  launch_item_desc(b.cn, c.max_nodes, b.grids, b.pool, b.bs, b.desc, c.t2cap, pl.mode == 0, b.icnt, b.slist, b.redo,
+                   s);
   launch_leaf_voxels(pl.mode, c.max_nodes, c.items, b.desc, b.Y, b.Yid, b.cube, T1, b.Xid, b.T2, b.T2id, b.icnt, b.iself,
-                     prm.seed, b.bs, s);
+                     prm.seed, b.bs, b.slist, b.redo, s);
   mark(tm, EV_LEAF);
   launch_voxel_tree(pl.mode, b.cn, b.vt, c.max_nodes, b.tinfo, nc, c.vcap, b.icnt, b.iself, prm.seed, b.bs, s);
   launch_voxel_gather(pl.mode, b.cn, b.vt, c.max_nodes, b.tinfo, b.icnt, b.desc, T1, b.Xid, b.T2, b.T2id, b.vox,
