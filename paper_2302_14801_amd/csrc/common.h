@@ -54,6 +54,17 @@ __device__ __forceinline__ uint32_t quantize(float p, double lo, double scale) {
   return (uint32_t)v;
 }
 
+// quantize() for a coordinate of a point inside the cube (p >= lo, as for
+// every point of a cloud in its own cube or in a cube given for all of it):
+// the scaled value is then at least 0 and at most 2^21 up to rounding, so the
+// truncating conversion is the floor and only the upper clamp can apply.
+// (For a NaN coordinate the conversion gives 0, as quantize() does; such an
+// input fails the build anyway.)
+__device__ __forceinline__ uint32_t quantize_in_cube(float p, double lo, double scale) {
+  const double v = __dmul_rn(__dsub_rn((double)p, lo), scale);
+  return min((uint32_t)v, kMaxQ);
+}
+
 // Spread the low 21 bits of v so that bit i lands at bit 3i.
 __host__ __device__ __forceinline__ uint64_t spread21(uint32_t v) {
   uint64_t x = v & 0x1fffffu;
@@ -107,12 +118,13 @@ __host__ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
 }
 
 // The E <= 10 key levels below bit level p of the Morton key, i.e.
-// (point_key >> 3p) & (8^E - 1), from the E bits of each axis at and above p.
+// (point_key >> 3p) & (8^E - 1), from the E bits of each axis at and above p
+// (for a point inside the cube).
 __device__ __forceinline__ uint32_t point_cell(float x, float y, float z, const CubeD& c, uint32_t p, uint32_t E) {
   const uint32_t m = (1u << E) - 1u;
-  const uint32_t qx = (quantize(x, c.lo[0], c.scale) >> p) & m;
-  const uint32_t qy = (quantize(y, c.lo[1], c.scale) >> p) & m;
-  const uint32_t qz = (quantize(z, c.lo[2], c.scale) >> p) & m;
+  const uint32_t qx = (quantize_in_cube(x, c.lo[0], c.scale) >> p) & m;
+  const uint32_t qy = (quantize_in_cube(y, c.lo[1], c.scale) >> p) & m;
+  const uint32_t qz = (quantize_in_cube(z, c.lo[2], c.scale) >> p) & m;
   return spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
 }
 

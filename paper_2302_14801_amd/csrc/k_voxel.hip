@@ -893,13 +893,6 @@ __device__ __forceinline__ uint32_t sp_mean(uint64_t a) {
   return mean_rgba((uint32_t)(a & 0xffffu), (uint32_t)((a >> 16) & 0xffffu), (uint32_t)((a >> 32) & 0xffffu),
                    (uint32_t)(a >> 48));
 }
-// quantize() for a coordinate inside the cube (p >= lo, so the scaled value
-// is at least 0 and at most 2^21 up to rounding): truncation is the floor
-// there, and only the upper clamp can apply.
-__device__ __forceinline__ uint32_t quantize_in_cube(float p, double lo, double scale) {
-  const double v = __dmul_rn(__dsub_rn((double)p, lo), scale);
-  return min((uint32_t)v, kMaxQ);
-}
 
 __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __restrict__ desc,
                                                        const uint4* __restrict__ pts, const Cube* cube,

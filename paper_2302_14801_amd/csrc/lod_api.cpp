@@ -255,6 +255,43 @@ struct Plan {
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// Compute units of the current device (cached per device).
+static uint32_t device_cus() {
+  static std::atomic<int> cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int v = cached[dev].load();
+  if (v <= 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached[dev].store(v);
+  }
+  return (uint32_t)v;
+}
+
+// Insert rounds per chunk of a large first partition.  The insert runs one
+// workgroup per chunk and compute unit, the count four per compute unit, so
+// the last wave of workgroups of either pass can be nearly empty; m is chosen
+// to keep both passes' makespans close to their averages without making
+// chunks too short.
+static uint32_t rounds_per_chunk(uint64_t n, uint32_t R) {
+  const uint64_t cus = device_cus();
+  const uint64_t rounds = (n + R - 1) / R;
+  uint32_t best = 9;
+  uint64_t best_cost = ~0ull;
+  for (uint32_t m = 4; m <= 12; ++m) {
+    const uint64_t chunks = (rounds + m - 1) / m;
+    // (a round takes an insert workgroup about 6/7 of the time it takes a
+    // count workgroup; plus a small cost per chunk: its histogram row and scans)
+    const uint64_t cost =
+        6 * cus * ((chunks + cus - 1) / cus) * m + 7 * cus * ((chunks + 4 * cus - 1) / (4 * cus)) * m + 2 * chunks;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = m;
+    }
+  }
+  return best;
+}
+
 // E0/E1 follow the typical (median) cloud, chunk sizes the total: chunks set
 // the parallelism of a pass over all clouds.
 Plan make_plan(uint64_t n_typical, uint64_t n_total, const lod_params& p) {
@@ -269,11 +306,11 @@ Plan make_plan(uint64_t n_typical, uint64_t n_total, const lod_params& p) {
   const bool averaging = p.sampling == LOD_AVERAGE || pl.weighted;
   pl.mode = averaging ? (pl.full ? 3u : 0u) : p.sampling;
   pl.ids = !averaging || (p.flags & LOD_FLAG_POINT_IDS) || pl.full;
-  // chunks are whole numbers of insert rounds (about 64k points for large
+  // chunks are whole numbers of insert rounds (4 to 12 of them for large
   // inputs, two rounds in the middle range and for refinements)
   const uint32_t R = scatter_round(pl.ids);
   const uint64_t N = n_total;
-  pl.chunk0 = N >= (64u << 20) ? R * ((65536 + R / 2) / R) : (N >= (4u << 20) ? 2 * R : 4096);
+  pl.chunk0 = N >= (64u << 20) ? R * rounds_per_chunk(N, R) : (N >= (4u << 20) ? 2 * R : 4096);
   if (p.tune_chunk) pl.chunk0 = std::max<uint32_t>(1, (p.tune_chunk + R / 2) / R) * R;
   pl.chunk1 = pl.chunk0;
   pl.chunk_ref = 2 * R;
