@@ -117,6 +117,16 @@ __host__ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   return x;
 }
 
+// Bits 0, 3, 6, ... of x gathered into bits 0, 1, 2, ... (inverse of spread10).
+__host__ __device__ __forceinline__ uint32_t compact10(uint32_t x) {
+  x &= 0x09249249u;
+  x = (x | (x >> 2)) & 0x030c30c3u;
+  x = (x | (x >> 4)) & 0x0300f00fu;
+  x = (x | (x >> 8)) & 0x030000ffu;
+  x = (x | (x >> 16)) & 0x000003ffu;
+  return x;
+}
+
 // The E <= 10 key levels below bit level p of the Morton key, i.e.
 // (point_key >> 3p) & (8^E - 1), from the E bits of each axis at and above p
 // (for a point inside the cube).
@@ -137,6 +147,11 @@ __host__ __device__ __forceinline__ uint32_t morton7(uint32_t x, uint32_t y, uin
 __host__ __device__ __forceinline__ uint64_t make_voxel(uint32_t code21, uint32_t rgba) {
   uint32_t x = compact21(code21), y = compact21(code21 >> 1), z = compact21(code21 >> 2);
   return (uint64_t)(x | (y << 8) | (z << 16)) | ((uint64_t)rgba << 32);
+}
+// make_voxel() in 32-bit arithmetic.
+__host__ __device__ __forceinline__ uint64_t make_voxel32(uint32_t code21, uint32_t rgba) {
+  return (uint64_t)(compact10(code21) | (compact10(code21 >> 1) << 8) | (compact10(code21 >> 2) << 16)) |
+         ((uint64_t)rgba << 32);
 }
 __host__ __device__ __forceinline__ uint32_t voxel_code(uint64_t v) {
   return morton7((uint32_t)(v & 0xff), (uint32_t)((v >> 8) & 0xff), (uint32_t)((v >> 16) & 0xff));

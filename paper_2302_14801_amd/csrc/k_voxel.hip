@@ -870,20 +870,8 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
 // listed in `redo` and left to the general kernel, which rewrites all of its
 // outputs.  Lists, counts and the item's own voxel are those of k_leaf_voxels<0>.
 
-// Bits 0, 3, 6, ... of x gathered into bits 0, 1, 2, ... (inverse of spread10).
-__host__ __device__ __forceinline__ uint32_t compact10(uint32_t x) {
-  x &= 0x09249249u;
-  x = (x | (x >> 2)) & 0x030c30c3u;
-  x = (x | (x >> 4)) & 0x0300f00fu;
-  x = (x | (x >> 8)) & 0x030000ffu;
-  x = (x | (x >> 16)) & 0x000003ffu;
-  return x;
-}
 // Voxel of a cell with 21-bit Morton code `code` in its ancestor's grid.
-__device__ __forceinline__ uint64_t sp_voxel(uint32_t code, uint32_t rgba) {
-  return (uint64_t)(compact10(code) | (compact10(code >> 1) << 8) | (compact10(code >> 2) << 16)) |
-         ((uint64_t)rgba << 32);
-}
+__device__ __forceinline__ uint64_t sp_voxel(uint32_t code, uint32_t rgba) { return make_voxel32(code, rgba); }
 // An 8-bit colour as one sample in the packed form of the accumulators.
 __device__ __forceinline__ uint64_t sp_sample(uint32_t rgba) {
   return (uint64_t)(rgba & 0xffu) | ((uint64_t)((rgba >> 8) & 0xffu) << 16) |

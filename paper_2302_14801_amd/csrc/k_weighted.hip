@@ -29,10 +29,11 @@
 // A child's samples are taken per aligned 16^3 block of the parent's grid
 // (a leaf's micro-bucket of points, or a 32^3 block of an inner child's own
 // cells, which is a contiguous range of its sorted voxel list): a workgroup
-// sums the block's splats per target cell in an LDS hash.  Cells one cell or
-// more inside the block get all their samples from it and take their colour
-// there; the other cells add their sums to global 64-bit sums, and a last
-// pass gives them their colour.
+// sums the block's splats per target cell in LDS, by the cell's rank among
+// the block's occupied cells (a small hash takes the cells around the block).
+// Cells one cell or more inside the block get all their samples from it and
+// take their colour there; the other cells add their sums to global 64-bit
+// sums, and a last pass gives them their colour.
 #include "common.h"
 #include "launch.h"
 #include "scan.h"
@@ -121,7 +122,7 @@ __device__ __forceinline__ uint32_t wfind(const unsigned long long* __restrict__
   return (uint32_t)(vbase + wpre[sb + (code >> 6)] + (uint32_t)__popcll(word & ((1ull << b) - 1ull)));
 }
 
-constexpr int kWProbe = 32;  // LDS probes before a splat goes global
+constexpr int kWProbe = 32;  // LDS hash probes before a splat goes to the global sums
 
 __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi, uint64_t w, uint64_t R, uint64_t Gc,
                                             uint64_t B) {
@@ -137,23 +138,29 @@ __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi
 // aligned 16^3 block of the parent's cells inside the child's octant (64 per
 // child): a leaf's micro-bucket (its points two levels down), or an inner
 // child's 32^3 block of its own cells (a contiguous range of its voxel list).
-// A block's cells are a contiguous range of 4096 cell codes.  All of a
-// block's splats are summed in an LDS hash first.  A cell at least one cell
-// inside the block gets samples from this block only (weights vanish beyond
-// one cell, and the block lies inside one child's octant), so its colour is
-// final here and is written directly; cells on the block's border and the
-// cells around it take the sums through global atomics and get their colour
-// in k_wfinal.  If the table overflows, every cell goes through the atomics.
-// The block's 64 bitmap words are read once, so cells inside it find their
-// voxel index in LDS.
-constexpr uint32_t kWLSlots = 2048;
+// A block's cells are a contiguous range of 4096 cell codes.  The block's 64
+// bitmap words are read into LDS once: a target cell inside the block that is
+// occupied has a rank among the block's occupied cells, and its sums are kept
+// in LDS at that rank (cells without samples of their own are not voxels and
+// get nothing); cells around the block are summed in a small LDS hash.  A
+// cell at least one cell inside the block gets samples from this block only
+// (weights vanish beyond one cell, and the block lies inside one child's
+// octant), so its colour is final here and is written directly; cells on the
+// block's border and the cells around it take the sums through global
+// atomics and get their colour in k_wfinal.  A block with more occupied cells
+// than the LDS holds sends its own cells' sums through the atomics as well,
+// and so does a full hash for the cells around it.
+constexpr uint32_t kWRankCap = 1536;  // occupied cells of a block summed in LDS
+constexpr uint32_t kWOutSlots = 512;  // hash slots of the cells around the block
 constexpr uint32_t kWLThreads = 512;
 struct WBlockLocal {
-  uint32_t key[kWLSlots];                 // cell code + 1 (0 = empty)
-  unsigned long long sum[4][kWLSlots];    // w * R, w * G, w * B, w (one array each: no bank conflicts)
-  unsigned long long bbits[64];           // the block's occupancy words
-  uint32_t bpre[64];                      // list index (from the node's first voxel) of each word's first cell
-  uint32_t overflow;
+  unsigned long long sum[4][kWRankCap];    // w * R, w * G, w * B, w of the block's cells, by rank
+  unsigned long long osum[4][kWOutSlots];  // the same for the cells around the block
+  uint32_t okey[kWOutSlots];               // cell code + 1 (0 = empty)
+  unsigned long long bbits[64];            // the block's occupancy words
+  uint32_t bpre[64];                       // list index (from the node's first voxel) of each word's first cell
+  uint32_t brank[64];                      // rank in the block of each word's first cell
+  uint32_t nocc;                           // occupied cells of the block
 };
 // Samples of a (child, block) pair: the leaf micro-bucket's point range or
 // the inner child's voxel range; cnt = 0 for an empty block.
@@ -224,12 +231,9 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
   };
   uint4 nxt = make_uint4(0, 0, 0, 0);
   if (t < cnt) nxt = load(t);
-  for (uint32_t i = t; i < kWLSlots; i += kWLThreads) {
-    lt.key[i] = 0;
-    lt.sum[0][i] = lt.sum[1][i] = lt.sum[2][i] = lt.sum[3][i] = 0;
-  }
   if (t < 64) {
-    // the block's bitmap words and the list index of each word's first cell
+    // the block's bitmap words, the list index of each word's first cell and
+    // its rank in the block
     const uint64_t w0 = sb + ((uint64_t)blk << 6);
     const unsigned long long wd = bits[w0 + t];
     const uint32_t pc = (uint32_t)__popcll(wd);
@@ -238,100 +242,119 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
     const uint32_t start = nz ? wpre[w0 + (uint32_t)(__ffsll((unsigned long long)nz) - 1)] : 0u;
     lt.bbits[t] = wd;
     lt.bpre[t] = start + inc - pc;
-    if (t == 0) lt.overflow = 0;
+    lt.brank[t] = inc - pc;
+    if (t == 63) lt.nocc = inc;
   }
+  for (uint32_t i = t; i < kWOutSlots; i += kWLThreads) {
+    lt.okey[i] = 0;
+    lt.osum[0][i] = lt.osum[1][i] = lt.osum[2][i] = lt.osum[3][i] = 0;
+  }
+  __syncthreads();
+  const uint32_t nocc = lt.nocc;
+  const bool local = nocc <= kWRankCap;  // the block's own cells are summed in LDS
+  if (local)
+    for (uint32_t i = t; i < nocc; i += kWLThreads) lt.sum[0][i] = lt.sum[1][i] = lt.sum[2][i] = lt.sum[3][i] = 0;
   __syncthreads();
   for (uint32_t i = t; i < cnt; i += kWLThreads) {
     // the next sample is loaded while this one is splat
     const uint4 v = nxt;
     if (i + kWLThreads < cnt) nxt = load(i + kWLThreads);
-    uint64_t pos2[3];
+    uint32_t pos2[3];
     uint32_t rgba;
     if (leaf) {
       // a point at the centre of its 2^21-grid cell
-      pos2[0] = 2ull * quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) + 1;
-      pos2[1] = 2ull * quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) + 1;
-      pos2[2] = 2ull * quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) + 1;
+      pos2[0] = 2u * quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) + 1u;
+      pos2[1] = 2u * quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) + 1u;
+      pos2[2] = 2u * quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) + 1u;
       rgba = v.w;
     } else {
       // a child voxel at the centre of its cell (level L + 8)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const uint64_t j = ((uint64_t)C[a] << 7) + ((v.x >> (8 * a)) & 0xffu);
-        pos2[a] = (2 * j + 1) << (13 - L);
+        const uint32_t j = (C[a] << 7) + ((v.x >> (8 * a)) & 0xffu);
+        pos2[a] = (2u * j + 1u) << (13 - L);
       }
       rgba = v.y;
     }
-    const uint64_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
-    wtargets(L, G, pos2, [&](uint32_t code, uint64_t w) {
-      // a cell of the block without samples of its own is not a voxel: its
-      // sums would be dropped, so they are not made
-      if ((code >> 12) == blk && !((lt.bbits[(code >> 6) & 63u] >> (code & 63u)) & 1ull)) return;
-      uint32_t slot = (code * 0x9E3779B1u) >> 21;  // 11 bits
-      bool done = false;
-      for (int probe = 0; probe < kWProbe; ++probe) {
-        const uint32_t prev = atomicCAS(&lt.key[slot], 0u, code + 1);
-        if (prev == 0u || prev == code + 1) {
-          atomicAdd(&lt.sum[0][slot], (unsigned long long)(w * R));
-          atomicAdd(&lt.sum[1][slot], (unsigned long long)(w * Gc));
-          atomicAdd(&lt.sum[2][slot], (unsigned long long)(w * B));
-          atomicAdd(&lt.sum[3][slot], (unsigned long long)w);
-          done = true;
-          break;
+    const uint32_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
+    wtargets32(L, G, pos2, [&](uint32_t code, uint32_t w) {
+      if ((code >> 12) == blk) {
+        // a cell of the block without samples of its own is not a voxel
+        const uint32_t wi = (code >> 6) & 63u, b = code & 63u;
+        const unsigned long long wd = lt.bbits[wi];
+        if (!((wd >> b) & 1ull)) return;
+        const uint32_t below = (uint32_t)__popcll(wd & ((1ull << b) - 1ull));
+        if (local) {
+          const uint32_t r = lt.brank[wi] + below;
+          atomicAdd(&lt.sum[0][r], (unsigned long long)(w * R));
+          atomicAdd(&lt.sum[1][r], (unsigned long long)(w * Gc));
+          atomicAdd(&lt.sum[2][r], (unsigned long long)(w * B));
+          atomicAdd(&lt.sum[3][r], (unsigned long long)w);
+        } else {
+          wadd_global(acc, (uint32_t)(vbase + lt.bpre[wi] + below), w, R, Gc, B);
         }
-        slot = (slot + 1) & (kWLSlots - 1);
+        return;
       }
-      if (!done) {  // table full around this code: straight to the global sums
-        lt.overflow = 1;
-        const uint32_t vi = wfind(bits, wpre, sb, vbase, code);
-        if (vi != 0xffffffffu) wadd_global(acc, vi, w, R, Gc, B);
+      uint32_t slot = (code * 0x9E3779B1u) >> 23;  // 9 bits
+#pragma unroll 1
+      for (int probe = 0; probe < kWProbe; ++probe) {
+        const uint32_t prev = atomicCAS(&lt.okey[slot], 0u, code + 1);
+        if (prev == 0u || prev == code + 1) {
+          atomicAdd(&lt.osum[0][slot], (unsigned long long)(w * R));
+          atomicAdd(&lt.osum[1][slot], (unsigned long long)(w * Gc));
+          atomicAdd(&lt.osum[2][slot], (unsigned long long)(w * B));
+          atomicAdd(&lt.osum[3][slot], (unsigned long long)w);
+          return;
+        }
+        slot = (slot + 1) & (kWOutSlots - 1);
       }
+      // table full around this code: straight to the global sums
+      const uint32_t vi = wfind(bits, wpre, sb, vbase, code);
+      if (vi != 0xffffffffu) wadd_global(acc, vi, w, R, Gc, B);
     });
   }
   __syncthreads();
-  const bool direct_ok = lt.overflow == 0;
-  // each thread's kWLSlots / kWLThreads slots at once: the bitmap words of cells
-  // outside the block are loaded together, then their prefixes, so a flush
-  // waits for two global round trips
-  constexpr int kPer = kWLSlots / kWLThreads;
-  uint32_t code[kPer], vi[kPer];
-  unsigned long long wd[kPer];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const uint32_t key = lt.key[t + kWLThreads * j];
-    code[j] = key - 1u;
-    wd[j] = 0ull;
-    if (key != 0u) {
-      if ((code[j] >> 12) == blk) wd[j] = lt.bbits[(code[j] >> 6) & 63u];
-      else wd[j] = bits[sb + (code[j] >> 6)];
+  // the block's own cells: 8 threads per bitmap word, 8 cells each
+  if (local) {
+    const uint32_t wi = t >> 3, sh = 8 * (t & 7u);
+    const unsigned long long wd = lt.bbits[wi];
+    uint32_t m = (uint32_t)(wd >> sh) & 0xffu;
+    const uint32_t r = lt.brank[wi] + (uint32_t)__popcll(wd & ((1ull << sh) - 1ull));
+    const uint32_t vi0 = (uint32_t)(vbase + lt.bpre[wi]) + (r - lt.brank[wi]);
+    for (uint32_t k = 0; m; m &= m - 1, ++k) {
+      const uint32_t b = sh + (uint32_t)(__ffs(m) - 1);
+      const uint32_t c = (blk << 12) | (wi << 6) | b;
+      // inside by one cell on every axis: the axis's 4 bits of the block's
+      // 12-bit Morton index are neither all zero nor all one
+      const uint32_t c12 = c & 4095u, ix = c12 & 0x249u, iy = c12 & 0x492u, iz = c12 & 0x924u;
+      const bool interior = ix != 0u && ix != 0x249u && iy != 0u && iy != 0x492u && iz != 0u && iz != 0x924u;
+      const unsigned long long s0 = lt.sum[0][r + k], s1 = lt.sum[1][r + k], s2 = lt.sum[2][r + k],
+                               ws = lt.sum[3][r + k];
+      const uint32_t vi = vi0 + k;
+      if (interior) {
+        // every occupied cell holds a sample of its own: ws > 0
+        const uint32_t rgba = wdiv(s0, ws) | (wdiv(s1, ws) << 8) | (wdiv(s2, ws) << 16) | (255u << 24);
+        vox[vi] = make_voxel32(c, rgba);
+      } else {
+        unsigned long long* a4 = acc + 4ull * vi;
+        atomicAdd(a4 + 0, s0);
+        atomicAdd(a4 + 1, s1);
+        atomicAdd(a4 + 2, s2);
+        atomicAdd(a4 + 3, ws);
+      }
     }
   }
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const uint32_t b = code[j] & 63u;
-    vi[j] = 0xffffffffu;
-    if ((wd[j] >> b) & 1ull) {
-      const uint32_t pre = (code[j] >> 12) == blk ? lt.bpre[(code[j] >> 6) & 63u] : wpre[sb + (code[j] >> 6)];
-      vi[j] = (uint32_t)(vbase + pre + (uint32_t)__popcll(wd[j] & ((1ull << b) - 1ull)));
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    if (vi[j] == 0xffffffffu) continue;  // untouched slot, or not an occupied cell
-    const uint32_t k = t + kWLThreads * j, c = code[j];
-    const uint32_t x = compact21(c) & 15u, y = compact21(c >> 1) & 15u, z = compact21(c >> 2) & 15u;
-    const bool interior = direct_ok && (c >> 12) == blk && x - 1u < 14u && y - 1u < 14u && z - 1u < 14u;
-    const unsigned long long s0 = lt.sum[0][k], s1 = lt.sum[1][k], s2 = lt.sum[2][k], ws = lt.sum[3][k];
-    if (interior && ws != 0ull) {
-      const uint32_t rgba = (uint32_t)(s0 / ws) | ((uint32_t)(s1 / ws) << 8) | ((uint32_t)(s2 / ws) << 16) | (255u << 24);
-      vox[vi[j]] = make_voxel(c, rgba);
-    } else {
-      unsigned long long* a4 = acc + 4ull * vi[j];
-      atomicAdd(a4 + 0, s0);
-      atomicAdd(a4 + 1, s1);
-      atomicAdd(a4 + 2, s2);
-      atomicAdd(a4 + 3, ws);
-    }
+  // the cells around the block: their voxel index from the node's bitmap
+  for (uint32_t k = t; k < kWOutSlots; k += kWLThreads) {
+    const uint32_t key = lt.okey[k];
+    if (key == 0u) continue;
+    const uint32_t vi = wfind(bits, wpre, sb, vbase, key - 1u);
+    if (vi == 0xffffffffu) continue;  // not an occupied cell
+    unsigned long long* a4 = acc + 4ull * vi;
+    atomicAdd(a4 + 0, lt.osum[0][k]);
+    atomicAdd(a4 + 1, lt.osum[1][k]);
+    atomicAdd(a4 + 2, lt.osum[2][k]);
+    atomicAdd(a4 + 3, lt.osum[3][k]);
   }
 }
 
@@ -348,8 +371,7 @@ __global__ void __launch_bounds__(256) k_wfinal(Nodes nodes, const uint32_t* __r
     const unsigned long long* a4 = acc + 4ull * (base + i);
     const uint64_t ws = a4[3];
     if (ws == 0) continue;  // colour already final
-    const uint32_t rgba = (uint32_t)(a4[0] / ws) | ((uint32_t)(a4[1] / ws) << 8) | ((uint32_t)(a4[2] / ws) << 16) |
-                          (255u << 24);
+    const uint32_t rgba = wdiv(a4[0], ws) | (wdiv(a4[1], ws) << 8) | (wdiv(a4[2], ws) << 16) | (255u << 24);
     vox[base + i] = (vox[base + i] & 0xffffffffull) | ((uint64_t)rgba << 32);
   }
 }
