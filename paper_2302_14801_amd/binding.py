@@ -298,13 +298,14 @@ def lod_build_batch(points, offsets, leaf_cap=50000, max_level=12, sampling=LOD_
 
 def lod_build_chunked(host_points: np.ndarray, chunk_points: int, leaf_cap=50000, max_level=12,
                       sampling=LOD_AVERAGE, seed=0, keep_ids=False, stream=None,
-                      params: lod_params | None = None) -> Tree:
+                      params: lod_params | None = None, full_precision=False, low_memory=False) -> Tree:
     """The tree of a HOST array of 16-byte records, built chunk by chunk."""
     a = host_points
     if not a.flags.c_contiguous or a.nbytes % 16:
         raise ValueError("host_points must be a contiguous array of 16-byte records")
     n = a.nbytes // 16
-    p = params if params is not None else make_params(leaf_cap, max_level, sampling, seed, keep_ids)
+    p = params if params is not None else make_params(leaf_cap, max_level, sampling, seed, keep_ids,
+                                                      full_precision=full_precision, low_memory=low_memory)
     out = ctypes.c_void_p()
     _check(load_library().lod_build_chunked(ctypes.c_void_p(a.ctypes.data if n else 0), n, ctypes.byref(p),
                                             int(chunk_points), _stream_handle(stream), ctypes.byref(out)))

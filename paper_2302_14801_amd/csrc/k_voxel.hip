@@ -882,16 +882,20 @@ __device__ __forceinline__ uint32_t sp_mean(uint64_t a) {
                    (uint32_t)(a >> 48));
 }
 
+template <int MODE>  // 0 average, 3 average with the smallest sample id of every cell
 __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __restrict__ desc,
-                                                       const uint4* __restrict__ pts, const Cube* cube,
-                                                       uint64_t* __restrict__ T1, uint64_t* __restrict__ T2,
-                                                       uint32_t* __restrict__ icnt, uint64_t* __restrict__ iself,
-                                                       BuildState* bs, const uint32_t* __restrict__ list,
-                                                       uint32_t* __restrict__ redo) {
+                                                       const uint4* __restrict__ pts, const uint32_t* __restrict__ ids,
+                                                       const Cube* cube, uint64_t* __restrict__ T1,
+                                                       uint32_t* __restrict__ T1id, uint64_t* __restrict__ T2,
+                                                       uint32_t* __restrict__ T2id, uint32_t* __restrict__ icnt,
+                                                       uint64_t* __restrict__ iself, BuildState* bs,
+                                                       const uint32_t* __restrict__ list, uint32_t* __restrict__ redo) {
+  static_assert(MODE == 0 || MODE == 3, "the sparse kernel takes the average modes");
   __shared__ uint32_t mask[kSpWords];
   __shared__ uint16_t wpre[kSpWords];  // rank of the first occupied depth-1 cell of each word
   __shared__ uint64_t acc[kSpCap];     // accumulators of depths 1 .. 6, one after the other
   __shared__ uint16_t code[kSpCap];    // cell codes (index within the item at that depth)
+  __shared__ uint32_t minid[MODE == 3 ? kSpCap : 1];  // mode 3: smallest sample id of every cell
   __shared__ uint16_t pre2[kSpWG];     // rank of each thread's first depth-2 cell
   __shared__ uint16_t rk3[kSpWG];      // rank of each depth-3 cell
   __shared__ uint8_t bm2[kSpWG];       // each thread's depth-2 cells
@@ -1027,19 +1031,33 @@ __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __rest
     if ((l & 7u) == 0)
       rk4[t >> 3] = (uint8_t)(((xo >> 10) & 0x7fu) + (uint32_t)__popc(m4 & ((1u << (l >> 3)) - 1u)));
     if (l == 0) rk5[w] = (uint8_t)((xo >> 20) & 0xfu);
-    for (uint32_t r = t; r <= o6; r += kSpWG) acc[r] = 0;
+    for (uint32_t r = t; r <= o6; r += kSpWG) {
+      acc[r] = 0;
+      if (MODE == 3) minid[r] = ~0u;
+    }
   }
   __syncthreads();
 
   // ---- phase C: samples into their depth-1 cells
   if (fits) {
 #pragma unroll
-    for (uint32_t k = 0; k < kSpSlots; ++k) {
-      const uint32_t c = (cc[k / 2] >> (16 * (k & 1))) & 0xffffu;
-      if (c != kSpNone) {
-        const uint32_t r = wpre[c >> 5] + (uint32_t)__popc(mask[c >> 5] & ((1u << (c & 31u)) - 1u));
-        atomicAdd((unsigned long long*)&acc[r], (unsigned long long)sp_sample(col[k]));
-        code[r] = (uint16_t)c;
+    for (uint32_t h = 0; h < 2; ++h) {
+      uint32_t pid[MODE == 3 ? 8 : 1];  // mode 3: the points' ids, 8 slots at a time
+      if (MODE == 3) {
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k)
+          if ((8 * h + k) * kSpWG + t < P) pid[MODE == 3 ? k : 0] = ids[I0 + (8 * h + k) * kSpWG + t];
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) {
+        const uint32_t kk = 8 * h + k;
+        const uint32_t c = (cc[kk / 2] >> (16 * (kk & 1))) & 0xffffu;
+        if (c != kSpNone) {
+          const uint32_t r = wpre[c >> 5] + (uint32_t)__popc(mask[c >> 5] & ((1u << (c & 31u)) - 1u));
+          atomicAdd((unsigned long long*)&acc[r], (unsigned long long)sp_sample(col[kk]));
+          if (MODE == 3) atomicMin(&minid[r], pid[MODE == 3 ? k : 0]);
+          code[r] = (uint16_t)c;
+        }
       }
     }
   }
@@ -1070,6 +1088,11 @@ __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __rest
       const uint32_t d = c >> 3, u = c >> 6;  // depth-2 cell, its owner thread
       const uint32_t r2 = o2 + pre2[u] + (uint32_t)__popc(bm2[u] & ((1u << (d & 7u)) - 1u));
       atomicAdd((unsigned long long*)&acc[r2], (unsigned long long)sp_sample(rgba));
+      if (MODE == 3) {
+        const uint32_t id = minid[r];
+        T1id[(uint64_t)I0 + r] = id;
+        atomicMin(&minid[r2], id);
+      }
       code[r2] = (uint16_t)d;
     }
     if (ovf) flag = 1;
@@ -1095,6 +1118,11 @@ __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __rest
         else if (k == 2) rp = rk5[c >> 3];
         else rp = 0;
         atomicAdd((unsigned long long*)&acc[off[k + 1] + rp], (unsigned long long)sp_sample(rgba));
+        if (MODE == 3) {
+          const uint32_t id = minid[off[k] + r];
+          T2id[t2b + cb[k] + r] = id;
+          atomicMin(&minid[off[k + 1] + rp], id);
+        }
         if (k < 3) code[off[k + 1] + rp] = (uint16_t)(c >> 3);
       }
       __syncthreads();
@@ -1103,7 +1131,9 @@ __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __rest
     if (t == 0) {
       const uint32_t rgba = sp_mean(acc[o6]);
       T2[t2b + cb[4]] = sp_voxel(((lk & 262143u) << 3) | grp, rgba);
-      iself[item] = (uint64_t)rgba << 32;
+      const uint32_t id6 = MODE == 3 ? minid[o6] : 0u;
+      if (MODE == 3) T2id[t2b + cb[4]] = id6;
+      iself[item] = ((uint64_t)rgba << 32) | id6;
       uint32_t* ic = icnt + 6 * item;
       ic[0] = tot1;
       ic[1] = tot2;
@@ -1490,17 +1520,25 @@ void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, uint32_t expect_items
       (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(std::min<uint64_t>(cap, expect_items), kMaxOneItemBlocks));
   const ItemDesc* d = (const ItemDesc*)desc;
   const uint4* p = (const uint4*)pts;
-  if (mode == 0) {
+  if (mode == 0 || mode == 3) {
     // the sparse kernel over its list (resident workgroups), then the general
     // kernel over the items listed for it (one-item form for the first g1 / 16,
     // looping form for any more)
     const uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(sparse_resident_blocks(), cap));
-    hipLaunchKernelGGL(k_leaf_sparse, dim3(gs), dim3(kSpWG), 0, s, d, p, cube, T1, T2, icnt, iself, bs, slist, redo);
     const uint32_t g2 = std::max<uint32_t>(1, g1 / 16);
-    hipLaunchKernelGGL((k_leaf_voxels<0, false>), dim3(g2), dim3(kLeafWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id,
-                       icnt, iself, seed, bs, 0u, (const uint32_t*)redo);
-    hipLaunchKernelGGL((k_leaf_voxels<0, true>), dim3(256), dim3(kLeafWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id,
-                       icnt, iself, seed, bs, g2, (const uint32_t*)redo);
+#define LOD_SPARSE(M)                                                                                                 \
+  hipLaunchKernelGGL((k_leaf_sparse<M>), dim3(gs), dim3(kSpWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id, icnt,   \
+                     iself, bs, slist, redo);                                                                         \
+  hipLaunchKernelGGL((k_leaf_voxels<M, false>), dim3(g2), dim3(kLeafWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id, \
+                     icnt, iself, seed, bs, 0u, (const uint32_t*)redo);                                               \
+  hipLaunchKernelGGL((k_leaf_voxels<M, true>), dim3(256), dim3(kLeafWG), 0, s, d, p, ids, cube, T1, T1id, T2, T2id,  \
+                     icnt, iself, seed, bs, g2, (const uint32_t*)redo);
+    if (mode == 0) {
+      LOD_SPARSE(0)
+    } else {
+      LOD_SPARSE(3)
+    }
+#undef LOD_SPARSE
     return;
   }
   LOD_MODE_SWITCH(mode, M, {

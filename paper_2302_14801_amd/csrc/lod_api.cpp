@@ -519,7 +519,7 @@ RegionSizes layout(Bufs& b, const Caps& c, const Plan& pl, bool cube_given, bool
   b.icnt = s.take<uint32_t>(6 * items);
   b.iself = s.take<uint64_t>(items);
   b.redo = s.take<uint32_t>(items);
-  b.slist = s.take<uint32_t>(pl.mode == 0 ? items : 1);
+  b.slist = s.take<uint32_t>(pl.mode == 0 || pl.mode == 3 ? items : 1);
   b.T2 = s.take<uint64_t>(c.t2cap);
   b.T2id = pl.mode ? s.take<uint32_t>(c.t2cap) : nullptr;
   b.vt.sz = s.take<uint32_t>(c.max_nodes);
@@ -628,7 +628,8 @@ void enqueue(const Bufs& b, const Caps& c, const Plan& pl, const lod_params& prm
   // (depth 1 into X, coarser ones into T2), the tree pass and the offsets,
   // then the pieces' positions and the gather
   uint64_t* T1 = (uint64_t*)b.X;
-  launch_item_desc(b.cn, c.max_nodes, b.grids, b.pool, b.bs, b.desc, c.t2cap, pl.mode == 0, b.icnt, b.slist, b.redo,
+  launch_item_desc(b.cn, c.max_nodes, b.grids, b.pool, b.bs, b.desc, c.t2cap, pl.mode == 0 || pl.mode == 3, b.icnt,
+                   b.slist, b.redo,
                    s);
   launch_leaf_voxels(pl.mode, c.max_nodes, c.items, b.desc, b.Y, b.Yid, b.cube, T1, b.Xid, b.T2, b.T2id, b.icnt, b.iself,
                      prm.seed, b.bs, b.slist, b.redo, s);
