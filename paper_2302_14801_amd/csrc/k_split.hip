@@ -213,7 +213,7 @@ __global__ void k_chunk_fill(const Segment* __restrict__ segs, const uint32_t* n
 // Count one chunk into an LDS histogram of B = 8^E cells and write the row
 // (each workgroup takes chunks blockIdx.x, blockIdx.x + gridDim.x, ... of the
 // device-side chunk count).
-constexpr int kCountWG = 512;
+constexpr int kCountWG = 1024;
 template <int E>
 __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict__ pts, const Cube* cube,
                                                          const Segment* __restrict__ segs,

@@ -269,7 +269,7 @@ static uint32_t device_cus() {
 }
 
 // Insert rounds per chunk of a large first partition.  The insert runs one
-// workgroup per chunk and compute unit, the count four per compute unit, so
+// workgroup per chunk and compute unit, the count two per compute unit, so
 // the last wave of workgroups of either pass can be nearly empty; m is chosen
 // to keep both passes' makespans close to their averages without making
 // chunks too short.
@@ -280,10 +280,10 @@ static uint32_t rounds_per_chunk(uint64_t n, uint32_t R) {
   uint64_t best_cost = ~0ull;
   for (uint32_t m = 4; m <= 12; ++m) {
     const uint64_t chunks = (rounds + m - 1) / m;
-    // (a round takes an insert workgroup about 6/7 of the time it takes a
-    // count workgroup; plus a small cost per chunk: its histogram row and scans)
+    // (a round takes a count workgroup about 7/12 of the time it takes an
+    // insert workgroup; plus a small cost per chunk: its histogram row and scans)
     const uint64_t cost =
-        6 * cus * ((chunks + cus - 1) / cus) * m + 7 * cus * ((chunks + 4 * cus - 1) / (4 * cus)) * m + 2 * chunks;
+        12 * cus * ((chunks + cus - 1) / cus) * m + 7 * cus * ((chunks + 2 * cus - 1) / (2 * cus)) * m + 4 * chunks;
     if (cost < best_cost) {
       best_cost = cost;
       best = m;
