@@ -1382,7 +1382,7 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, c
                                                       const uint64_t* __restrict__ T2, const uint32_t* __restrict__ T2id,
                                                       uint64_t* __restrict__ vox, uint32_t* __restrict__ vids) {
   __shared__ uint64_t sdst[48], ssrc[48];
-  __shared__ uint32_t scnt[48];
+  __shared__ uint32_t scnt[48], spre[49];
   const uint32_t t = threadIdx.x;
   if (voxels_refused(bs)) return;
   const uint32_t num_nodes = bs->total_nodes;
@@ -1393,8 +1393,10 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, c
   const uint32_t k = t / 8 + 1, g = t % 8;
   if (t < 48) scnt[t] = k <= L ? icnt[6ull * (8 * n + g) + k - 1] : 0u;
   __syncthreads();
-  if (t < 48) {
-    const uint32_t c = scnt[t];
+  if (t < 64) {
+    // where each list goes and comes from, and its first element in the
+    // leaf's lists taken one after the other
+    const uint32_t c = t < 48 ? scnt[t] : 0u;
     uint64_t dst = 0, src = 0;
     if (c) {
       dst = vt.poff[8ull * n + k];
@@ -1402,30 +1404,40 @@ __global__ void __launch_bounds__(kGatherWG) k_gather(Nodes nodes, VoxTree vt, c
       const ItemDesc& d = desc[8 * n + g];
       src = k == 1 ? (uint64_t)d.I0 : d.t2 + coarse_base(k, d.P);
     }
-    sdst[t] = dst;
-    ssrc[t] = src;
+    const uint32_t inc = wave_incl_scan(c);
+    if (t < 48) {
+      sdst[t] = dst;
+      ssrc[t] = src;
+      spre[t] = inc - c;
+    }
+    if (t == 47) spre[48] = inc;
   }
   __syncthreads();
-  const uint32_t w = t / 64, l = lane_id();
-  for (uint32_t j = w; j < 48; j += kGatherWG / 64) {
-    const uint32_t c = scnt[j];
-    if (c == 0) continue;
-    const uint64_t dst = sdst[j], src = ssrc[j];
-    const uint64_t* sv = j < 8 ? T1 : T2;
-    const uint32_t* si = j < 8 ? T1id : T2id;
-    uint32_t i = l;
-    for (; i + 192 < c; i += 256) {
-      const uint64_t a0 = sv[src + i], a1 = sv[src + i + 64], a2 = sv[src + i + 128], a3 = sv[src + i + 192];
-      vox[dst + i] = a0;
-      vox[dst + i + 64] = a1;
-      vox[dst + i + 128] = a2;
-      vox[dst + i + 192] = a3;
-      if (MODE)
-        for (uint32_t q = 0; q < 4; ++q) vids[dst + i + 64 * q] = si[src + i + 64 * q];
+  // every thread copies elements t, t + kGatherWG, ... of the leaf's lists,
+  // four at a time (its list index only moves forward)
+  const uint32_t total = spre[48];
+  uint32_t j = 0;
+  for (uint32_t e0 = t; e0 < total; e0 += 4 * kGatherWG) {
+    uint64_t a[4], dv[4];
+    uint32_t iv[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t e = e0 + q * kGatherWG;
+      if (e < total) {
+        while (spre[j + 1] <= e) ++j;
+        const uint32_t off = e - spre[j];
+        const uint64_t src = ssrc[j] + off;
+        dv[q] = sdst[j] + off;
+        a[q] = j < 8 ? T1[src] : T2[src];
+        if (MODE) iv[q] = j < 8 ? T1id[src] : T2id[src];
+      }
     }
-    for (; i < c; i += 64) {
-      vox[dst + i] = sv[src + i];
-      if (MODE) vids[dst + i] = si[src + i];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      if (e0 + q * kGatherWG < total) {
+        vox[dv[q]] = a[q];
+        if (MODE) vids[dv[q]] = iv[q];
+      }
     }
   }
   __syncthreads();
