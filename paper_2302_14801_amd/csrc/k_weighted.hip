@@ -26,11 +26,11 @@
 // the list index of the word's first voxel: the position of an occupied cell
 // is that index plus the set bits below it (the lists are sorted by cell).
 //
-// A child's samples are taken per aligned 16^3 block of the parent's grid
-// (a leaf's micro-bucket of points, or a 32^3 block of an inner child's own
-// cells, which is a contiguous range of its sorted voxel list): a workgroup
-// sums the block's splats per target cell in LDS, by the cell's rank among
-// the block's occupied cells (a small hash takes the cells around the block).
+// A child's samples are taken per aligned 16^3 or 32^3 block of the parent's
+// grid (a contiguous range of the child's points or sorted voxels): a
+// workgroup sums the block's splats per target cell in LDS, by the cell's rank
+// among the block's occupied cells (a small hash takes the cells around the
+// block).
 // Cells one cell or more inside the block get all their samples from it and
 // take their colour there; the other cells add their sums to global 64-bit
 // sums, and a last pass gives them their colour.
@@ -135,66 +135,114 @@ __device__ __forceinline__ void wadd_global(unsigned long long* acc, uint32_t vi
 
 // The samples of the children at level L + 1 (points of leaves, voxels of
 // inner nodes) into their parents (level L), one workgroup per child and
-// aligned 16^3 block of the parent's cells inside the child's octant (64 per
-// child): a leaf's micro-bucket (its points two levels down), or an inner
-// child's 32^3 block of its own cells (a contiguous range of its voxel list).
-// A block's cells are a contiguous range of 4096 cell codes.  The block's 64
-// bitmap words are read into LDS once: a target cell inside the block that is
-// occupied has a rank among the block's occupied cells, and its sums are kept
-// in LDS at that rank (cells without samples of their own are not voxels and
-// get nothing); cells around the block are summed in a small LDS hash.  A
-// cell at least one cell inside the block gets samples from this block only
-// (weights vanish beyond one cell, and the block lies inside one child's
-// octant), so its colour is final here and is written directly; cells on the
-// block's border and the cells around it take the sums through global
-// atomics and get their colour in k_wfinal.  A block with more occupied cells
-// than the LDS holds sends its own cells' sums through the atomics as well,
-// and so does a full hash for the cells around it.
-constexpr uint32_t kWRankCap = 1536;  // occupied cells of a block summed in LDS
-constexpr uint32_t kWOutSlots = 512;  // hash slots of the cells around the block
+// aligned block of the parent's cells inside the child's octant.  Blocks are
+// 16^3 cells (LB = 4, 64 per child: a leaf's micro-bucket, its points two
+// levels down, or an inner child's 32^3 block of its own cells) or 32^3 cells
+// (LB = 5, 8 per child: a leaf's work item, or an octant of an inner child's
+// own cells); either is a contiguous range of the child's points or sorted
+// voxels.  The deepest levels, with many sparse blocks, take 32^3 blocks (fewer
+// border cells, less set-up per sample); the upper levels, with few dense
+// blocks, take 16^3.  A block's cells are a contiguous range of 8^LB cell
+// codes.  Its bitmap words are read into LDS once: a target cell inside the
+// block that is occupied has a rank among the block's occupied cells, and its
+// sums are kept in LDS at that rank (cells without samples of their own are
+// not voxels and get nothing); the cells around the block are summed in a
+// small LDS hash.  A cell at least one cell inside the block gets samples from
+// this block only (weights vanish beyond one cell, and the block lies inside
+// one child's octant), so its colour is final here and is written directly;
+// cells on the block's border and the cells around it take the sums through
+// global atomics and get their colour in k_wfinal (as do cells around the
+// block that a full hash cannot take).  A block with more occupied cells than
+// the LDS holds is summed in windows of ranks, one pass over its samples per
+// window (32^3), or sends its own cells' sums to the global atomics (16^3).
 constexpr uint32_t kWLThreads = 512;
-struct WBlockLocal {
-  unsigned long long sum[4][kWRankCap];    // w * R, w * G, w * B, w of the block's cells, by rank
-  unsigned long long osum[4][kWOutSlots];  // the same for the cells around the block
-  uint32_t okey[kWOutSlots];               // cell code + 1 (0 = empty)
-  unsigned long long bbits[64];            // the block's occupancy words
-  uint32_t bpre[64];                       // list index (from the node's first voxel) of each word's first cell
-  uint32_t brank[64];                      // rank in the block of each word's first cell
-  uint32_t nocc;                           // occupied cells of the block
+template <int LB>
+struct WBlk;
+template <>
+struct WBlk<4> {
+  static constexpr uint32_t kWords = 64;      // 64-bit occupancy words of a block
+  static constexpr uint32_t kPer = 64;        // blocks per child
+  static constexpr uint32_t kRankCap = 1536;  // occupied cells of a block summed in LDS (at a time)
+  static constexpr uint32_t kOutSlots = 512;  // hash slots of the cells around the block
+  static constexpr bool kWindows = false;
 };
-// Samples of a (child, block) pair: the leaf micro-bucket's point range or
-// the inner child's voxel range; cnt = 0 for an empty block.
+template <>
+struct WBlk<5> {
+  static constexpr uint32_t kWords = 512;
+  static constexpr uint32_t kPer = 8;
+  static constexpr uint32_t kRankCap = 1792;
+  static constexpr uint32_t kOutSlots = 256;
+  static constexpr bool kWindows = true;
+};
+template <int LB>
+struct WBlockLocal {
+  using P = WBlk<LB>;
+  unsigned long long sum[4][P::kRankCap];    // w * R, w * G, w * B, w of the block's cells, by rank
+  unsigned long long osum[4][P::kOutSlots];  // the same for the cells around the block
+  uint32_t okey[P::kOutSlots];               // cell code + 1 (0 = empty)
+  unsigned long long bbits[P::kWords];       // the block's occupancy words
+  uint16_t brank[P::kWords];                 // rank in the block of each word's first cell
+  uint32_t sh[kWLThreads / 64 + 1];
+  uint32_t first_word;                       // the block's first occupied word
+};
+// Samples of a (child, block) pair; cnt = 0 for an empty block.
+template <int LB>
 __device__ __forceinline__ void wblock_range(const Nodes& nodes, const ItemDesc* __restrict__ desc,
                                              const uint2* __restrict__ bseg, const TreeInfo* __restrict__ trees,
                                              uint32_t n, uint32_t sub, bool leaf, uint64_t& first, uint32_t& cnt) {
   if (leaf) {
-    // work item sub / 8 of the leaf (a child cell), micro-bucket sub % 8
-    const ItemDesc& d = desc[8 * n + (sub >> 3)];
-    cnt = d.P ? d.mc[sub & 7u] : 0u;
-    uint32_t o = d.I0;
-    for (uint32_t k = 0; k < (sub & 7u); ++k) o += d.mc[k];
-    first = o;
+    if (LB == 4) {
+      // work item sub / 8 of the leaf (a child cell), micro-bucket sub % 8
+      const ItemDesc& d = desc[8 * n + (sub >> 3)];
+      cnt = d.P ? d.mc[sub & 7u] : 0u;
+      uint32_t o = d.I0;
+      for (uint32_t k = 0; k < (sub & 7u); ++k) o += d.mc[k];
+      first = o;
+    } else {
+      const ItemDesc& d = desc[8 * n + sub];
+      cnt = d.P;
+      first = d.I0;
+    }
   } else {
-    const uint2 sg = bseg[64ull * n + sub];
-    cnt = sg.y - sg.x;
-    first = trees[nodes.tree[n]].vbase + nodes.offset[n] + sg.x;
+    uint32_t lo = 0, hi = 0;
+    if (LB == 4) {
+      const uint2 sg = bseg[64ull * n + sub];
+      lo = sg.x;
+      hi = sg.y;
+    } else {
+      // the octant: its 8 blocks of the child's list, contiguous (the list is sorted)
+      lo = 0xffffffffu;
+      for (uint32_t q = 0; q < 8; ++q) {
+        const uint2 sg = bseg[64ull * n + 8 * sub + q];
+        if (sg.y > sg.x) {
+          lo = min(lo, sg.x);
+          hi = max(hi, sg.y);
+        }
+      }
+      if (hi == 0) lo = 0;
+    }
+    cnt = hi - lo;
+    first = trees[nodes.tree[n]].vbase + nodes.offset[n] + lo;
   }
 }
 
 // The non-empty (child, block) pairs of a level: list[0 .. *count) holds
-// 64 * (position in ln) + block, in any order.
+// kPer * (position in ln) + block, in any order.
+template <int LB>
 __global__ void __launch_bounds__(256) k_wblocks(Nodes nodes, const uint32_t* __restrict__ ln, uint32_t nch,
                                                  const ItemDesc* __restrict__ desc, const uint2* __restrict__ bseg,
                                                  const TreeInfo* __restrict__ trees, uint32_t* list, uint32_t* count) {
+  constexpr uint32_t kPer = WBlk<LB>::kPer;
   const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= 64 * nch) return;
-  const uint32_t n = ln[idx >> 6];
+  if (idx >= kPer * nch) return;
+  const uint32_t n = ln[idx / kPer];
   uint64_t first;
   uint32_t cnt;
-  wblock_range(nodes, desc, bseg, trees, n, idx & 63u, nodes.is_leaf[n] != 0, first, cnt);
+  wblock_range<LB>(nodes, desc, bseg, trees, n, idx % kPer, nodes.is_leaf[n] != 0, first, cnt);
   if (cnt) list[atomicAdd(count, 1u)] = idx;
 }
 
+template <int LB>
 __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const uint32_t* __restrict__ ln,
                                                              const uint32_t* __restrict__ blocks, uint32_t L,
                                                              const ItemDesc* __restrict__ desc,
@@ -205,13 +253,16 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
                                                              const unsigned long long* __restrict__ bits,
                                                              const uint32_t* __restrict__ wpre,
                                                              unsigned long long* acc) {
-  __shared__ WBlockLocal lt;
+  using P = WBlk<LB>;
+  constexpr uint32_t kTpw = kWLThreads / P::kWords;  // threads per word in the flush (8 or 1)
+  constexpr uint32_t kBpt = 64 / kTpw;               // cells per thread in the flush
+  __shared__ WBlockLocal<LB> lt;
   const uint32_t idx = blocks[blockIdx.x];
-  const uint32_t n = ln[idx >> 6], sub = idx & 63u, t = threadIdx.x;
+  const uint32_t n = ln[idx / P::kPer], sub = idx % P::kPer, t = threadIdx.x;
   const bool leaf = nodes.is_leaf[n] != 0;
   uint64_t first;
   uint32_t cnt;
-  wblock_range(nodes, desc, bseg, trees, n, sub, leaf, first, cnt);
+  wblock_range<LB>(nodes, desc, bseg, trees, n, sub, leaf, first, cnt);
   if (cnt == 0) return;
   const uint32_t A = nodes.parent[n];
   const uint64_t ka = nodes.key[A], kn = nodes.key[n];
@@ -219,10 +270,9 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
   const uint32_t C[3] = {compact21(kn), compact21(kn >> 1), compact21(kn >> 2)};
   const uint64_t sb = (uint64_t)wslot[A] * kWWords, vbase = trees[nodes.tree[A]].vbase + nodes.offset[A];
   const CubeD cd = load_cube(cube + nodes.tree[n]);
-  // the block's cells in A's grid: codes blk * 4096 + [0, 4096), blk = the
-  // child's octant, then the octants of the two levels below it (for a leaf,
-  // the work item's and the micro-bucket's)
-  const uint32_t blk = ((uint32_t)(kn & 7u) << 6) | sub;
+  // the block's cells in A's grid: codes blk * 8^LB + [0, 8^LB), blk = the
+  // child's octant, then the block's place inside it
+  const uint32_t blk = (uint32_t)(kn & 7u) * P::kPer + sub;
   // a sample: a point record, or a voxel word in .x / .y
   auto load = [&](uint32_t i) -> uint4 {
     if (leaf) return Y[first + i];
@@ -231,130 +281,145 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
   };
   uint4 nxt = make_uint4(0, 0, 0, 0);
   if (t < cnt) nxt = load(t);
-  if (t < 64) {
-    // the block's bitmap words, the list index of each word's first cell and
-    // its rank in the block
-    const uint64_t w0 = sb + ((uint64_t)blk << 6);
-    const unsigned long long wd = bits[w0 + t];
-    const uint32_t pc = (uint32_t)__popcll(wd);
-    const uint32_t inc = wave_incl_scan(pc);
-    const unsigned long long nz = __ballot(wd != 0ull);
-    const uint32_t start = nz ? wpre[w0 + (uint32_t)(__ffsll((unsigned long long)nz) - 1)] : 0u;
+  // the block's bitmap words and the rank of each word's first cell
+  const uint64_t wbase = sb + (uint64_t)blk * P::kWords;
+  const unsigned long long wd = t < P::kWords ? bits[wbase + t] : 0ull;
+  uint32_t nocc;
+  const uint32_t ex = block_excl_scan<kWLThreads>((uint32_t)__popcll(wd), lt.sh, &nocc);
+  if (t < P::kWords) {
     lt.bbits[t] = wd;
-    lt.bpre[t] = start + inc - pc;
-    lt.brank[t] = inc - pc;
-    if (t == 63) lt.nocc = inc;
+    lt.brank[t] = (uint16_t)ex;
   }
-  for (uint32_t i = t; i < kWOutSlots; i += kWLThreads) {
+  if (t == 0) lt.first_word = P::kWords;
+  for (uint32_t i = t; i < P::kOutSlots; i += kWLThreads) {
     lt.okey[i] = 0;
     lt.osum[0][i] = lt.osum[1][i] = lt.osum[2][i] = lt.osum[3][i] = 0;
   }
   __syncthreads();
-  const uint32_t nocc = lt.nocc;
-  const bool local = nocc <= kWRankCap;  // the block's own cells are summed in LDS
-  if (local)
-    for (uint32_t i = t; i < nocc; i += kWLThreads) lt.sum[0][i] = lt.sum[1][i] = lt.sum[2][i] = lt.sum[3][i] = 0;
+  if (wd) atomicMin(&lt.first_word, t);
   __syncthreads();
-  for (uint32_t i = t; i < cnt; i += kWLThreads) {
-    // the next sample is loaded while this one is splat
-    const uint4 v = nxt;
-    if (i + kWLThreads < cnt) nxt = load(i + kWLThreads);
-    uint32_t pos2[3];
-    uint32_t rgba;
-    if (leaf) {
-      // a point at the centre of its 2^21-grid cell
-      pos2[0] = 2u * quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) + 1u;
-      pos2[1] = 2u * quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) + 1u;
-      pos2[2] = 2u * quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) + 1u;
-      rgba = v.w;
-    } else {
-      // a child voxel at the centre of its cell (level L + 8)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const uint32_t j = (C[a] << 7) + ((v.x >> (8 * a)) & 0xffu);
-        pos2[a] = (2u * j + 1u) << (13 - L);
+  // list index (from A's first voxel) of the block's first cell
+  const uint32_t lbase = nocc ? wpre[wbase + lt.first_word] : 0u;
+  // the block's own cells are summed in LDS (in windows of ranks), or, for a
+  // 16^3 block with more occupied cells than the LDS holds, globally
+  const bool local = P::kWindows || nocc <= P::kRankCap;
+  const uint32_t wend = local ? nocc : 1u;
+  for (uint32_t w0 = 0; w0 < wend; w0 += P::kRankCap) {  // uniform
+    const uint32_t wn = local ? min(P::kRankCap, nocc - w0) : 0u;
+    for (uint32_t i = t; i < wn; i += kWLThreads) lt.sum[0][i] = lt.sum[1][i] = lt.sum[2][i] = lt.sum[3][i] = 0;
+    __syncthreads();
+    const bool around = w0 == 0;  // the cells around the block are summed in the first pass
+    for (uint32_t i = t; i < cnt; i += kWLThreads) {
+      uint4 v;
+      if (around) {  // the next sample is loaded while this one is splat
+        v = nxt;
+        if (i + kWLThreads < cnt) nxt = load(i + kWLThreads);
+      } else {
+        v = load(i);
       }
-      rgba = v.y;
-    }
-    const uint32_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
-    wtargets32(L, G, pos2, [&](uint32_t code, uint32_t w) {
-      if ((code >> 12) == blk) {
-        // a cell of the block without samples of its own is not a voxel
-        const uint32_t wi = (code >> 6) & 63u, b = code & 63u;
-        const unsigned long long wd = lt.bbits[wi];
-        if (!((wd >> b) & 1ull)) return;
-        const uint32_t below = (uint32_t)__popcll(wd & ((1ull << b) - 1ull));
-        if (local) {
-          const uint32_t r = lt.brank[wi] + below;
+      uint32_t pos2[3];
+      uint32_t rgba;
+      if (leaf) {
+        // a point at the centre of its 2^21-grid cell
+        pos2[0] = 2u * quantize(__uint_as_float(v.x), cd.lo[0], cd.scale) + 1u;
+        pos2[1] = 2u * quantize(__uint_as_float(v.y), cd.lo[1], cd.scale) + 1u;
+        pos2[2] = 2u * quantize(__uint_as_float(v.z), cd.lo[2], cd.scale) + 1u;
+        rgba = v.w;
+      } else {
+        // a child voxel at the centre of its cell (level L + 8)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const uint32_t j = (C[a] << 7) + ((v.x >> (8 * a)) & 0xffu);
+          pos2[a] = (2u * j + 1u) << (13 - L);
+        }
+        rgba = v.y;
+      }
+      const uint32_t R = rgba & 0xffu, Gc = (rgba >> 8) & 0xffu, B = (rgba >> 16) & 0xffu;
+      wtargets32(L, G, pos2, [&](uint32_t code, uint32_t w) {
+        if ((code >> (3 * LB)) == blk) {
+          // a cell of the block without samples of its own is not a voxel
+          const uint32_t wi = (code >> 6) & (P::kWords - 1u), b = code & 63u;
+          const unsigned long long cw = lt.bbits[wi];
+          if (!((cw >> b) & 1ull)) return;
+          const uint32_t rank = lt.brank[wi] + (uint32_t)__popcll(cw & ((1ull << b) - 1ull));
+          if (!local) {
+            wadd_global(acc, (uint32_t)(vbase + lbase + rank), w, R, Gc, B);
+            return;
+          }
+          const uint32_t r = rank - w0;
+          if (r >= wn) return;  // another window's cell
           atomicAdd(&lt.sum[0][r], (unsigned long long)(w * R));
           atomicAdd(&lt.sum[1][r], (unsigned long long)(w * Gc));
           atomicAdd(&lt.sum[2][r], (unsigned long long)(w * B));
           atomicAdd(&lt.sum[3][r], (unsigned long long)w);
-        } else {
-          wadd_global(acc, (uint32_t)(vbase + lt.bpre[wi] + below), w, R, Gc, B);
-        }
-        return;
-      }
-      uint32_t slot = (code * 0x9E3779B1u) >> 23;  // 9 bits
-#pragma unroll 1
-      for (int probe = 0; probe < kWProbe; ++probe) {
-        const uint32_t prev = atomicCAS(&lt.okey[slot], 0u, code + 1);
-        if (prev == 0u || prev == code + 1) {
-          atomicAdd(&lt.osum[0][slot], (unsigned long long)(w * R));
-          atomicAdd(&lt.osum[1][slot], (unsigned long long)(w * Gc));
-          atomicAdd(&lt.osum[2][slot], (unsigned long long)(w * B));
-          atomicAdd(&lt.osum[3][slot], (unsigned long long)w);
           return;
         }
-        slot = (slot + 1) & (kWOutSlots - 1);
-      }
-      // table full around this code: straight to the global sums
-      const uint32_t vi = wfind(bits, wpre, sb, vbase, code);
-      if (vi != 0xffffffffu) wadd_global(acc, vi, w, R, Gc, B);
-    });
-  }
-  __syncthreads();
-  // the block's own cells: 8 threads per bitmap word, 8 cells each
-  if (local) {
-    const uint32_t wi = t >> 3, sh = 8 * (t & 7u);
-    const unsigned long long wd = lt.bbits[wi];
-    uint32_t m = (uint32_t)(wd >> sh) & 0xffu;
-    const uint32_t r = lt.brank[wi] + (uint32_t)__popcll(wd & ((1ull << sh) - 1ull));
-    const uint32_t vi0 = (uint32_t)(vbase + lt.bpre[wi]) + (r - lt.brank[wi]);
-    for (uint32_t k = 0; m; m &= m - 1, ++k) {
-      const uint32_t b = sh + (uint32_t)(__ffs(m) - 1);
-      const uint32_t c = (blk << 12) | (wi << 6) | b;
-      // inside by one cell on every axis: the axis's 4 bits of the block's
-      // 12-bit Morton index are neither all zero nor all one
-      const uint32_t c12 = c & 4095u, ix = c12 & 0x249u, iy = c12 & 0x492u, iz = c12 & 0x924u;
-      const bool interior = ix != 0u && ix != 0x249u && iy != 0u && iy != 0x492u && iz != 0u && iz != 0x924u;
-      const unsigned long long s0 = lt.sum[0][r + k], s1 = lt.sum[1][r + k], s2 = lt.sum[2][r + k],
-                               ws = lt.sum[3][r + k];
-      const uint32_t vi = vi0 + k;
-      if (interior) {
-        // every occupied cell holds a sample of its own: ws > 0
-        const uint32_t rgba = wdiv(s0, ws) | (wdiv(s1, ws) << 8) | (wdiv(s2, ws) << 16) | (255u << 24);
-        vox[vi] = make_voxel32(c, rgba);
-      } else {
-        unsigned long long* a4 = acc + 4ull * vi;
-        atomicAdd(a4 + 0, s0);
-        atomicAdd(a4 + 1, s1);
-        atomicAdd(a4 + 2, s2);
-        atomicAdd(a4 + 3, ws);
+        if (!around) return;
+        uint32_t slot = (code * 0x9E3779B1u) % P::kOutSlots;
+#pragma unroll 1
+        for (int probe = 0; probe < kWProbe; ++probe) {
+          const uint32_t prev = atomicCAS(&lt.okey[slot], 0u, code + 1);
+          if (prev == 0u || prev == code + 1) {
+            atomicAdd(&lt.osum[0][slot], (unsigned long long)(w * R));
+            atomicAdd(&lt.osum[1][slot], (unsigned long long)(w * Gc));
+            atomicAdd(&lt.osum[2][slot], (unsigned long long)(w * B));
+            atomicAdd(&lt.osum[3][slot], (unsigned long long)w);
+            return;
+          }
+          slot = (slot + 1) % P::kOutSlots;
+        }
+        // table full around this code: straight to the global sums
+        const uint32_t vi = wfind(bits, wpre, sb, vbase, code);
+        if (vi != 0xffffffffu) wadd_global(acc, vi, w, R, Gc, B);
+      });
+    }
+    __syncthreads();
+    // the window's cells of the block: kTpw threads per word, kBpt cells each
+    if (local) {
+      const uint32_t wi = t / kTpw, sh = kBpt * (t % kTpw);
+      const unsigned long long cw = lt.bbits[wi];
+      const unsigned long long mask = kBpt == 64 ? ~0ull : ((1ull << kBpt) - 1ull);
+      const uint32_t r0 = lt.brank[wi] + (uint32_t)__popcll(cw & ((1ull << sh) - 1ull));
+      uint32_t k = 0;
+      for (unsigned long long m = (cw >> sh) & mask; m; m &= m - 1, ++k) {
+        const uint32_t r = r0 + k - w0;
+        if (r >= wn) continue;
+        const uint32_t b = sh + (uint32_t)(__ffsll(m) - 1);
+        const uint32_t cl = (wi << 6) | b;  // the cell's Morton index in the block
+        // inside by one cell on every axis: the axis's LB bits of the index
+        // are neither all zero nor all one
+        constexpr uint32_t mx = LB == 4 ? 0x249u : 0x1249u;
+        const uint32_t ix = cl & mx, iy = cl & (mx << 1), iz = cl & (mx << 2);
+        const bool interior = ix != 0u && ix != mx && iy != 0u && iy != (mx << 1) && iz != 0u && iz != (mx << 2);
+        const unsigned long long s0 = lt.sum[0][r], s1 = lt.sum[1][r], s2 = lt.sum[2][r], ws = lt.sum[3][r];
+        const uint32_t vi = (uint32_t)(vbase + lbase) + r0 + k;
+        if (interior) {
+          // every occupied cell holds a sample of its own: ws > 0
+          const uint32_t rgba = wdiv(s0, ws) | (wdiv(s1, ws) << 8) | (wdiv(s2, ws) << 16) | (255u << 24);
+          vox[vi] = make_voxel32((blk << (3 * LB)) | cl, rgba);
+        } else {
+          unsigned long long* a4 = acc + 4ull * vi;
+          atomicAdd(a4 + 0, s0);
+          atomicAdd(a4 + 1, s1);
+          atomicAdd(a4 + 2, s2);
+          atomicAdd(a4 + 3, ws);
+        }
       }
     }
-  }
-  // the cells around the block: their voxel index from the node's bitmap
-  for (uint32_t k = t; k < kWOutSlots; k += kWLThreads) {
-    const uint32_t key = lt.okey[k];
-    if (key == 0u) continue;
-    const uint32_t vi = wfind(bits, wpre, sb, vbase, key - 1u);
-    if (vi == 0xffffffffu) continue;  // not an occupied cell
-    unsigned long long* a4 = acc + 4ull * vi;
-    atomicAdd(a4 + 0, lt.osum[0][k]);
-    atomicAdd(a4 + 1, lt.osum[1][k]);
-    atomicAdd(a4 + 2, lt.osum[2][k]);
-    atomicAdd(a4 + 3, lt.osum[3][k]);
+    // the cells around the block: their voxel index from the node's bitmap
+    if (around)
+      for (uint32_t k = t; k < P::kOutSlots; k += kWLThreads) {
+        const uint32_t key = lt.okey[k];
+        if (key == 0u) continue;
+        const uint32_t vi = wfind(bits, wpre, sb, vbase, key - 1u);
+        if (vi == 0xffffffffu) continue;  // not an occupied cell
+        unsigned long long* a4 = acc + 4ull * vi;
+        atomicAdd(a4 + 0, lt.osum[0][k]);
+        atomicAdd(a4 + 1, lt.osum[1][k]);
+        atomicAdd(a4 + 2, lt.osum[2][k]);
+        atomicAdd(a4 + 3, lt.osum[3][k]);
+      }
+    __syncthreads();  // before the next window clears the sums
   }
 }
 
@@ -392,17 +457,30 @@ hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uin
     hipLaunchKernelGGL(k_wslots, dim3((na + 255) / 256), dim3(256), 0, s, nodes, pa, na, wslot, slot_ctr);
     hipLaunchKernelGGL(k_wbits, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, (const uint64_t*)vox,
                        (const uint32_t*)wslot, bits, wpre, bseg, true);
-    // the non-empty blocks only (most micro-buckets of a surface are empty)
+    // the non-empty blocks only (most micro-buckets of a surface are empty);
+    // 32^3 blocks for the two deepest parent levels, 16^3 above them
+    const bool big = l + 2 >= deepest;
     if ((e = hipMemsetAsync(nblocks, 0, sizeof(uint32_t), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wblocks, dim3((64 * nch + 255) / 256), dim3(256), 0, s, nodes, ch, nch, (const ItemDesc*)desc,
-                       (const uint2*)bseg, trees, blocks, nblocks);
+    const uint32_t per = big ? WBlk<5>::kPer : WBlk<4>::kPer;
+    if (big)
+      hipLaunchKernelGGL(k_wblocks<5>, dim3((per * nch + 255) / 256), dim3(256), 0, s, nodes, ch, nch,
+                         (const ItemDesc*)desc, (const uint2*)bseg, trees, blocks, nblocks);
+    else
+      hipLaunchKernelGGL(k_wblocks<4>, dim3((per * nch + 255) / 256), dim3(256), 0, s, nodes, ch, nch,
+                         (const ItemDesc*)desc, (const uint2*)bseg, trees, blocks, nblocks);
     if ((e = hipMemcpyAsync(h_nblocks, nblocks, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const uint32_t nblk = std::min<uint32_t>(*h_nblocks, 64 * nch);
-    if (nblk)
-      hipLaunchKernelGGL(k_wsplat_block, dim3(nblk), dim3(kWLThreads), 0, s, nodes, ch, (const uint32_t*)blocks,
-                         l, (const ItemDesc*)desc, (const uint2*)bseg, trees, cube, (const uint4*)Y, vox,
-                         (const uint32_t*)wslot, (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
+    const uint32_t nblk = std::min<uint32_t>(*h_nblocks, per * nch);
+    if (nblk) {
+      if (big)
+        hipLaunchKernelGGL(k_wsplat_block<5>, dim3(nblk), dim3(kWLThreads), 0, s, nodes, ch, (const uint32_t*)blocks,
+                           l, (const ItemDesc*)desc, (const uint2*)bseg, trees, cube, (const uint4*)Y, vox,
+                           (const uint32_t*)wslot, (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
+      else
+        hipLaunchKernelGGL(k_wsplat_block<4>, dim3(nblk), dim3(kWLThreads), 0, s, nodes, ch, (const uint32_t*)blocks,
+                           l, (const ItemDesc*)desc, (const uint2*)bseg, trees, cube, (const uint4*)Y, vox,
+                           (const uint32_t*)wslot, (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
+    }
     hipLaunchKernelGGL(k_wfinal, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, vox,
                        (const unsigned long long*)acc);
     // the bitmaps are cleared word by word (from the unchanged cell lists) for
