@@ -23,12 +23,12 @@
 //
 // Stages (each launched once per build, whatever the depth of the tree):
 //   k_item_desc      descriptor and coarse-list space of every (leaf, child
-//                    cell) work item; in the average mode also the list of
+//                    cell) work item; in the average modes also the list of
 //                    items for the sparse kernel
-//   k_leaf_sparse    average mode: the depth 1..6 lists of the items that fit
+//   k_leaf_sparse    average modes: the depth 1..6 lists of the items that fit
 //                    its LDS (occupancy mask, ranks, one accumulator per
 //                    occupied cell)
-//   k_leaf_voxels    the depth 1..6 lists of every item (average mode: of the
+//   k_leaf_voxels    the depth 1..6 lists of every item (average modes: of the
 //                    items the sparse kernel leaves)
 //   k_piece_sizes    piece sizes of every node; self voxels of deep leaves
 //   k_vox_tree       subtree sizes, depth-first order, inner self voxels
@@ -53,7 +53,7 @@ constexpr uint32_t kNoCell = 0xffffffffu;
 constexpr uint64_t kMaxOneItemBlocks = 1ull << 22;  // workgroups of the one-item leaf launch (2^30 threads)
 constexpr uint32_t kCodeMask = (1u << 21) - 1;
 constexpr uint32_t kListCap = 3072;  // occupied depth-1 cells of a micro-bucket the shared list holds
-// the sparse average-mode leaf kernel (k_leaf_sparse)
+// the sparse leaf kernel of the average modes (k_leaf_sparse)
 constexpr int kSpWG = 512;                          // 8 waves
 constexpr uint32_t kSpSlots = 16;                   // points per thread
 constexpr uint32_t kSpMaxPts = kSpWG * kSpSlots;    // 8192
@@ -290,7 +290,7 @@ __device__ __forceinline__ Item item_of(const Nodes& nodes, uint32_t n, uint32_t
 //
 // One thread per item.  Coarse-list blocks are handed out by a wave-wide
 // prefix sum and one atomic add per wave on bs->coarse_used.  With `sparse`
-// (the average mode) the item is also routed: an empty item gets its list
+// (the average modes) the item is also routed: an empty item gets its list
 // lengths (all zero) here, an item of at most kSpMaxPts points goes on the
 // sparse kernel's list, a larger one on the general kernel's (`redo`); both
 // lists are filled with one atomic add per wave.
@@ -840,9 +840,9 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
   }
 }
 
-// ------------------------------------------------------------ sparse leaf kernel (average)
+// ------------------------------------------------------------ sparse leaf kernel (average modes)
 //
-// The average mode's fast path.  A work item's 8 micro-buckets are taken at
+// The average modes' fast path.  A work item's 8 micro-buckets are taken at
 // once: their 32768 depth-1 cells (5 levels below the leaf's child cell) form
 // a 32768-bit occupancy mask in LDS, and one workgroup-wide scan of the mask
 // ranks the occupied cells of every depth (a cell's rank is its position in
@@ -865,10 +865,14 @@ __global__ void __launch_bounds__(kLeafWG, MODE == 0 ? 4 : 1) k_leaf_voxels(cons
 //   Phase C: every sample into its depth-1 cell.
 //   Depths 1 .. 5: one occupied cell per thread: mean colour, voxel, and the
 //            colour into the parent's accumulator.  Depth 6 is the item.
-// An item with more points or occupied cells than the LDS holds, or a cell
-// with more than 257 samples (beyond the exact range of the 16-bit sums), is
-// listed in `redo` and left to the general kernel, which rewrites all of its
-// outputs.  Lists, counts and the item's own voxel are those of k_leaf_voxels<0>.
+// Mode 3 also keeps the smallest sample id of every pooled cell (an LDS atomic
+// min per sample, and each emitted cell's id into its parent's).
+// The kernel takes the items k_item_desc listed for it (at most kSpMaxPts
+// points; larger ones go straight to the general kernel).  An item with more
+// occupied cells than the pool holds, or a cell with more than 257 samples
+// (beyond the exact range of the 16-bit sums), is listed in `redo` and left to
+// the general kernel, which rewrites all of its outputs.  Lists, counts and the
+// item's own voxel are those of k_leaf_voxels<MODE>.
 
 // Voxel of a cell with 21-bit Morton code `code` in its ancestor's grid.
 __device__ __forceinline__ uint64_t sp_voxel(uint32_t code, uint32_t rgba) { return make_voxel32(code, rgba); }

@@ -78,14 +78,14 @@ void launch_tree_info(const TreeState* sts, const CloudInfo* clouds, uint32_t nt
 // k_voxel.hip (launches sized by the node capacity; counts on the device)
 // Work-item descriptors: 64 bytes per item, 8 items per node; coarse-list
 // blocks handed out from a pool of t2cap entries (kOverCoarse beyond).
-// sparse (the average mode): also the lengths of empty items, the sparse leaf
+// sparse (the average modes): also the lengths of empty items, the sparse leaf
 // kernel's list `slist` and the general kernel's `redo` (capacity 8 * max_nodes each)
 void launch_item_desc(const Nodes& nodes, uint32_t max_nodes, const GridDesc* grids, const uint32_t* pool,
                       BuildState* bs, void* desc, uint64_t t2cap, bool sparse, uint32_t* icnt, uint32_t* slist,
                       uint32_t* redo, hipStream_t s);
 // The leaf kernels over the 8 * total_nodes work items: expect_items sets how
 // many get a workgroup of their own (results never depend on it).  In the
-// average mode the sparse kernel takes the items of `slist` (from
+// average modes the sparse kernel takes the items of `slist` (from
 // launch_item_desc) and lists those it cannot hold in `redo` for the general kernel.
 void launch_leaf_voxels(uint32_t mode, uint32_t max_nodes, uint32_t expect_items, const void* desc, const void* pts,
                         const uint32_t* ids, const Cube* cube, uint64_t* T1, uint32_t* T1id, uint64_t* T2,
