@@ -58,7 +58,8 @@ constexpr int kSpWG = 512;                          // 8 waves
 constexpr uint32_t kSpSlots = 16;                   // points per thread
 constexpr uint32_t kSpMaxPts = kSpWG * kSpSlots;    // 8192
 constexpr uint32_t kSpWords = 32768 / 32;           // occupancy words of an item
-constexpr uint32_t kSpCap = 4096;                   // occupied cells of all depths an item may have
+// occupied cells of all depths an item may have (LDS: 10 B each, 14 B in mode 3)
+__host__ __device__ constexpr uint32_t sp_cap(int mode) { return mode == 3 ? 4096u : 6144u; }
 constexpr uint32_t kSpNone = 0xffffu;               // no point in a slot
 
 // Cells of one work item (a leaf's child cell) in the grid of the ancestor
@@ -897,9 +898,10 @@ __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __rest
   static_assert(MODE == 0 || MODE == 3, "the sparse kernel takes the average modes");
   __shared__ uint32_t mask[kSpWords];
   __shared__ uint16_t wpre[kSpWords];  // rank of the first occupied depth-1 cell of each word
-  __shared__ uint64_t acc[kSpCap];     // accumulators of depths 1 .. 6, one after the other
-  __shared__ uint16_t code[kSpCap];    // cell codes (index within the item at that depth)
-  __shared__ uint32_t minid[MODE == 3 ? kSpCap : 1];  // mode 3: smallest sample id of every cell
+  constexpr uint32_t kCap = sp_cap(MODE);
+  __shared__ uint64_t acc[kCap];     // accumulators of depths 1 .. 6, one after the other
+  __shared__ uint16_t code[kCap];    // cell codes (index within the item at that depth)
+  __shared__ uint32_t minid[MODE == 3 ? kCap : 1];  // mode 3: smallest sample id of every cell
   __shared__ uint16_t pre2[kSpWG];     // rank of each thread's first depth-2 cell
   __shared__ uint16_t rk3[kSpWG];      // rank of each depth-3 cell
   __shared__ uint8_t bm2[kSpWG];       // each thread's depth-2 cells
@@ -1024,7 +1026,7 @@ __global__ void __launch_bounds__(kSpWG, 4) k_leaf_sparse(const ItemDesc* __rest
   const uint32_t tot3 = to & 0x3ffu, tot4 = (to >> 10) & 0x7fu, tot5 = (to >> 20) & 0xfu;
   // pool offsets of depths 2 .. 6
   const uint32_t o2 = tot1, o3p = o2 + tot2, o4 = o3p + tot3, o5 = o4 + tot4, o6 = o5 + tot5;
-  const bool fits = o6 + 1 <= kSpCap;  // uniform
+  const bool fits = o6 + 1 <= kCap;  // uniform
   if (fits) {
     wpre[2 * t] = (uint16_t)ex1;
     wpre[2 * t + 1] = (uint16_t)(ex1 + (uint32_t)__popc(m0));
