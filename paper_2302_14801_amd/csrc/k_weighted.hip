@@ -244,7 +244,8 @@ __global__ void __launch_bounds__(256) k_wblocks(Nodes nodes, const uint32_t* __
 
 template <int LB>
 __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const uint32_t* __restrict__ ln,
-                                                             const uint32_t* __restrict__ blocks, uint32_t L,
+                                                             const uint32_t* __restrict__ blocks,
+                                                             const uint32_t* __restrict__ nblocks, uint32_t L,
                                                              const ItemDesc* __restrict__ desc,
                                                              const uint2* __restrict__ bseg,
                                                              const TreeInfo* __restrict__ trees, const Cube* cube,
@@ -257,6 +258,9 @@ __global__ void __launch_bounds__(kWLThreads) k_wsplat_block(Nodes nodes, const 
   constexpr uint32_t kTpw = kWLThreads / P::kWords;  // threads per word in the flush (8 or 1)
   constexpr uint32_t kBpt = 64 / kTpw;               // cells per thread in the flush
   __shared__ WBlockLocal<LB> lt;
+  // the grid covers every (child, block) pair of the level; the list holds
+  // the non-empty ones
+  if (blockIdx.x >= *nblocks) return;
   const uint32_t idx = blocks[blockIdx.x];
   const uint32_t n = ln[idx / P::kPer], sub = idx % P::kPer, t = threadIdx.x;
   const bool leaf = nodes.is_leaf[n] != 0;
@@ -444,8 +448,8 @@ __global__ void __launch_bounds__(256) k_wfinal(Nodes nodes, const uint32_t* __r
 hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t* loff, uint32_t deepest,
                            const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
                            uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg,
-                           unsigned long long* acc, uint32_t* blocks, uint32_t* nblocks, uint32_t* h_nblocks,
-                           uint32_t* slot_ctr, hipStream_t s) {
+                           unsigned long long* acc, uint32_t* blocks, uint32_t* nblocks, uint32_t* slot_ctr,
+                           hipStream_t s) {
   for (int L = (int)deepest - 1; L >= 0; --L) {
     const uint32_t l = (uint32_t)L;
     const uint32_t* pa = lnodes + loff[l];       // the parents' level
@@ -468,19 +472,18 @@ hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uin
     else
       hipLaunchKernelGGL(k_wblocks<4>, dim3((per * nch + 255) / 256), dim3(256), 0, s, nodes, ch, nch,
                          (const ItemDesc*)desc, (const uint2*)bseg, trees, blocks, nblocks);
-    if ((e = hipMemcpyAsync(h_nblocks, nblocks, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const uint32_t nblk = std::min<uint32_t>(*h_nblocks, per * nch);
-    if (nblk) {
-      if (big)
-        hipLaunchKernelGGL(k_wsplat_block<5>, dim3(nblk), dim3(kWLThreads), 0, s, nodes, ch, (const uint32_t*)blocks,
-                           l, (const ItemDesc*)desc, (const uint2*)bseg, trees, cube, (const uint4*)Y, vox,
-                           (const uint32_t*)wslot, (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
-      else
-        hipLaunchKernelGGL(k_wsplat_block<4>, dim3(nblk), dim3(kWLThreads), 0, s, nodes, ch, (const uint32_t*)blocks,
-                           l, (const ItemDesc*)desc, (const uint2*)bseg, trees, cube, (const uint4*)Y, vox,
-                           (const uint32_t*)wslot, (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
-    }
+    // one workgroup per possible block (those beyond the count end at once):
+    // the count stays on the device and the levels run without a host wait
+    if (big)
+      hipLaunchKernelGGL(k_wsplat_block<5>, dim3(per * nch), dim3(kWLThreads), 0, s, nodes, ch,
+                         (const uint32_t*)blocks, (const uint32_t*)nblocks, l, (const ItemDesc*)desc,
+                         (const uint2*)bseg, trees, cube, (const uint4*)Y, vox, (const uint32_t*)wslot,
+                         (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
+    else
+      hipLaunchKernelGGL(k_wsplat_block<4>, dim3(per * nch), dim3(kWLThreads), 0, s, nodes, ch,
+                         (const uint32_t*)blocks, (const uint32_t*)nblocks, l, (const ItemDesc*)desc,
+                         (const uint2*)bseg, trees, cube, (const uint4*)Y, vox, (const uint32_t*)wslot,
+                         (const unsigned long long*)bits, (const uint32_t*)wpre, acc);
     hipLaunchKernelGGL(k_wfinal, dim3(na, kWSplit), dim3(256), 0, s, nodes, pa, trees, vox,
                        (const unsigned long long*)acc);
     // the bitmaps are cleared word by word (from the unchanged cell lists) for

@@ -108,14 +108,14 @@ void launch_voxel_gather(uint32_t mode, const Nodes& nodes, const VoxTree& vt, u
 // inner node of the level (at most the sum over trees of n / (T + 1)), zero
 // on entry and on return; wslot: one u32 per node; slot_ctr: one u32; acc: 4
 // zeroed u64 per voxel; bseg: 64 zeroed uint2 per node; blocks: 64 u32 per
-// node, nblocks one u32 (device) and h_nblocks one u32 (pinned host), the
-// list of a level's non-empty blocks and its length (the host reads it
-// back once per level).  desc and Y: the leaf items and leaf-ordered points.
+// node and nblocks one u32 (device): the list of a level's non-empty blocks
+// and its length.  Runs without host waits.  desc and Y: the leaf items and
+// leaf-ordered points.
 hipError_t launch_weighted(const Nodes& nodes, const uint32_t* lnodes, const uint64_t* loff, uint32_t deepest,
                            const TreeInfo* trees, const Cube* cube, const void* desc, const void* Y, uint64_t* vox,
                            uint32_t* wslot, unsigned long long* bits, uint32_t* wpre, uint2* bseg,
-                           unsigned long long* acc, uint32_t* blocks, uint32_t* nblocks, uint32_t* h_nblocks,
-                           uint32_t* slot_ctr, hipStream_t s);
+                           unsigned long long* acc, uint32_t* blocks, uint32_t* nblocks, uint32_t* slot_ctr,
+                           hipStream_t s);
 uint64_t weighted_bitmap_words();
 // Full-precision records (input coordinates of the accepted sample, voxel
 // colour) of the bs->vtotal voxels of a call (at most vcap).

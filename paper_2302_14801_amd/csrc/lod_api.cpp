@@ -131,7 +131,7 @@ struct Workspace {
   Scratch S;  // the device scratch region of a build
   Pinned H;   // the host tables of a build (copied to the device, read back)
   Scratch wslot, wlist, wbits, wpre, wacc, wseg, wblk;  // the weighted pass
-  Pinned h_wlist, h_wblk;
+  Pinned h_wlist;
   // capacities learned from earlier builds (grow-only; they change only how
   // often a build has to be repeated, never its result)
   double voxels_per_point = 0.0, coarse_per_point = 0.0;
@@ -819,7 +819,7 @@ std::vector<lod_tree*> lod_build_clouds(const lod_point* d_points, const uint64_
     HIPCHK(hipMemsetAsync(wacc, 0, 32 * vtotal, s));
     HIPCHK(hipMemsetAsync(wseg, 0, 64ull * sizeof(uint2) * num_nodes, s));
     HIPCHK(launch_weighted(b.cn, wlist, loff, deepest, b.tinfo, b.cube, b.desc, b.Y, b.vox, wslot, wbits, wpre, wseg,
-                           wacc, wblk + 2, wblk, w.h_wblk.get<uint32_t>(1), wblk + 1, s));
+                           wacc, wblk + 2, wblk, wblk + 1, s));
     if (b.vpts) launch_voxel_points(b.vox, b.vids, c.vcap, b.bs, b.tinfo, b.clouds, nc, in, b.vpts, s);
     HIPCHK(hipGetLastError());
     tm.mark(EV_LEVELS);
