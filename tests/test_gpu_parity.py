@@ -368,3 +368,34 @@ def test_server_rejects_too_large(lod):
 
 if __name__ == "__main__":
     sys.exit(pytest.main([__file__, "-x", "-v"]))
+
+
+def lattice_cloud(side: int, seed: int) -> np.ndarray:
+    """One point at the centre of every cell of a side^3 lattice in [0, 1)^3,
+    in shuffled order, with random colours."""
+    rng = np.random.default_rng(seed)
+    g = ((np.arange(side, dtype=np.float64) + 0.5) / side).astype(np.float32)
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    a = np.empty(side ** 3, synth.POINT_DTYPE)
+    a["x"], a["y"], a["z"] = x.ravel(), y.ravel(), z.ravel()
+    for ax in "rgb":
+        a[ax] = rng.integers(0, 256, a.size, dtype=np.uint8)
+    a["a"] = 255
+    return a[rng.permutation(a.size)]
+
+
+def test_weighted_dense_blocks_windows(lod):
+    # 64^3 lattice, T = 50 000: the root is inner and its 8 children are
+    # leaves.  Each leaf work item brings 4096 points, each in a root cell of
+    # its own, to one 32^3 block of the root's grid: more occupied cells than
+    # one LDS window holds, and the cells around the block overflow the LDS
+    # hash (their sums go through the global fallback).
+    check(lod, lattice_cloud(64, 5), T=50000, ml=12, sampling=2, seed=3)
+
+
+def test_weighted_dense_blocks_global_sums(lod):
+    # 128^3 lattice, T = 5000: leaves at level 3, so the root's level uses
+    # 16^3 blocks, and every such block of the root's grid is fully occupied
+    # (4096 cells, more than its LDS sums hold): its own cells are summed
+    # through the global atomics.
+    check(lod, lattice_cloud(128, 6), T=5000, ml=12, sampling=2, seed=4)
