@@ -399,3 +399,21 @@ def test_weighted_dense_blocks_global_sums(lod):
     # (4096 cells, more than its LDS sums hold): its own cells are summed
     # through the global atomics.
     check(lod, lattice_cloud(128, 6), T=5000, ml=12, sampling=2, seed=4)
+
+
+@pytest.mark.parametrize("full_precision", [False, True])
+@pytest.mark.parametrize("side,T", [(72, 50000), (80, 70000), (96, 120000)])
+def test_leaf_items_at_the_sparse_kernel_limits(lod, side, T, full_precision):
+    # Lattices whose 8 leaves (level 1) split into work items of side^3 / 64
+    # points, each point in a leaf cell of its own: 5832 cells fit the sparse
+    # leaf kernel's pool in the average mode but not with full-precision
+    # records (4096 cells); 8000 points enter the sparse kernel and are handed
+    # back for their cells in both; 13 824 points (over 8192) go straight to
+    # the general leaf kernel.
+    p = lattice_cloud(side, 7)
+    print(f"leaf items side={side} T={T} full_precision={full_precision}", flush=True)
+    if not full_precision:
+        check(lod, p, T=T, ml=12, sampling=0, seed=3)
+        return
+    g = gpu_tree(lod, p, leaf_cap=T, max_level=12, sampling=0, seed=3, full_precision=True)
+    check_full(g, oracle.build(p, leaf_cap=T, max_level=12, sampling=0, seed=3, full_precision=True), p)
