@@ -251,6 +251,36 @@ __global__ void __launch_bounds__(kCountWG) k_part_count(const uint4* __restrict
   }
 }
 
+// k_part_count() from the cells the previous insert stored beside the
+// records (one 16-bit cell per record, in the records' order).
+template <int E>
+__global__ void __launch_bounds__(kCountWG) k_part_count_dig(const uint16_t* __restrict__ dig,
+                                                             const Chunk* __restrict__ chunks,
+                                                             const uint32_t* nchunk_ptr, uint32_t* __restrict__ hist) {
+  constexpr uint32_t B = 1u << (3 * E);
+  __shared__ uint32_t h[B];
+  const uint32_t nchunk = *nchunk_ptr;
+  for (uint32_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+    const Chunk ch = chunks[c];
+    for (uint32_t j = threadIdx.x; j < B; j += kCountWG) h[j] = 0;
+    lds_barrier();
+    const uint16_t* p = dig + ch.start;
+    uint32_t i = threadIdx.x;
+    for (; i + 7 * kCountWG < ch.count; i += 8 * kCountWG) {
+      uint32_t d[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) d[k] = p[i + k * kCountWG];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) atomicAdd(&h[d[k]], 1u);
+    }
+    for (; i < ch.count; i += kCountWG) atomicAdd(&h[p[i]], 1u);
+    lds_barrier();
+    uint32_t* row = hist + (uint64_t)c * B;
+    for (uint32_t j = threadIdx.x; j < B; j += kCountWG) row[j] = h[j];
+    lds_barrier();
+  }
+}
+
 // Column scan of the chunk rows, in three steps so that no thread walks more
 // than kGroupChunks rows: (1) per (group, cell) sums, (2) per (segment, cell)
 // exclusive scan over the segment's groups, whose total is the segment's cell
@@ -385,7 +415,7 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
                                                           const Chunk* __restrict__ chunks, const uint32_t* nchunk_ptr,
                                                           const uint32_t* __restrict__ hist,
                                                           const GridDesc* __restrict__ grids, const uint32_t* __restrict__ pool,
-                                                          uint32_t c0) {
+                                                          uint16_t* __restrict__ dig, uint32_t c0) {
   constexpr int PPT = ScatShape<IDS>::PPT;
   constexpr uint32_t R = ScatShape<IDS>::R;
   constexpr uint32_t B = 1u << (3 * E);
@@ -492,8 +522,13 @@ __global__ void __launch_bounds__(kScatWG) k_part_scatter(const uint4* __restric
     lds_barrier();
     for (uint32_t j = threadIdx.x; j < nround; j += kScatWG) {
       const uint32_t d = cnt[PAD(stage_b[j])] + j;
-      dst[d] = stage[j];
+      const uint4 r = stage[j];
+      dst[d] = r;
       if (IDS) dst_ids[d] = stage_id[j];
+      // the record's cell in the next partition (E levels further down),
+      // stored beside it so that the next count need not read the records
+      if (dig) dig[d] = (uint16_t)point_cell(__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), cd,
+                                             lvl_bit - E, E);
     }
     lds_barrier();
 #pragma unroll
@@ -683,21 +718,25 @@ void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, 
 }
 
 template <int E>
-static void count_e(const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
+static void count_e(const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs, const Chunk* chunks,
                     const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
   const uint32_t blocks = std::min<uint32_t>(max_chunks, kMaxPartBlocks);
-  hipLaunchKernelGGL((k_part_count<E>), dim3(blocks), dim3(kCountWG), 0, st, (const uint4*)pts, cube, segs, chunks,
-                     nchunk, hist);
+  if (dig)
+    hipLaunchKernelGGL((k_part_count_dig<E>), dim3(blocks), dim3(kCountWG), 0, st, dig, chunks, nchunk, hist);
+  else
+    hipLaunchKernelGGL((k_part_count<E>), dim3(blocks), dim3(kCountWG), 0, st, (const uint4*)pts, cube, segs, chunks,
+                       nchunk, hist);
 }
 
-void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
-                       const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st) {
+void launch_part_count(uint32_t E, const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs,
+                       const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist,
+                       hipStream_t st) {
   if (!max_chunks) return;
   switch (E) {
-    case 1: count_e<1>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 2: count_e<2>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 3: count_e<3>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
-    case 4: count_e<4>(pts, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 1: count_e<1>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 2: count_e<2>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 3: count_e<3>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
+    case 4: count_e<4>(pts, dig, cube, segs, chunks, nchunk, max_chunks, hist, st); break;
     default: break;
   }
 }
@@ -725,31 +764,31 @@ void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_
 }
 
 template <int E, bool IDS>
-static void scatter_e(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Cube* cube,
-                      const Segment* segs, const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks,
-                      uint32_t expect_chunks, const uint32_t* hist, const GridDesc* grids, const uint32_t* pool,
-                      hipStream_t st) {
+static void scatter_e(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, uint16_t* dig,
+                      const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
+                      uint32_t max_chunks, uint32_t expect_chunks, const uint32_t* hist, const GridDesc* grids,
+                      const uint32_t* pool, hipStream_t st) {
   // one workgroup per expected chunk (those past the real count return at
   // once), then a grid that loops over any chunks beyond
   const uint32_t g1 = std::max<uint32_t>(1, std::min(std::min(max_chunks, expect_chunks), kMaxOneChunkBlocks));
   hipLaunchKernelGGL((k_part_scatter<E, IDS, false>), dim3(g1), dim3(kScatWG), 0, st, (const uint4*)src, src_ids,
-                     (uint4*)dst, dst_ids, cube, segs, chunks, nchunk, hist, grids, pool, 0u);
+                     (uint4*)dst, dst_ids, cube, segs, chunks, nchunk, hist, grids, pool, dig, 0u);
   if (max_chunks > g1)
     hipLaunchKernelGGL((k_part_scatter<E, IDS, true>), dim3(std::min<uint32_t>(max_chunks - g1, kMaxPartBlocks)),
                        dim3(kScatWG), 0, st, (const uint4*)src, src_ids, (uint4*)dst, dst_ids, cube, segs, chunks,
-                       nchunk, hist, grids, pool, g1);
+                       nchunk, hist, grids, pool, dig, g1);
 }
 
 void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
-                         const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
-                         uint32_t max_chunks, uint32_t expect_chunks, const uint32_t* hist, const GridDesc* grids,
-                         const uint32_t* pool, hipStream_t st) {
+                         uint16_t* dig, const Cube* cube, const Segment* segs, const Chunk* chunks,
+                         const uint32_t* nchunk, uint32_t max_chunks, uint32_t expect_chunks, const uint32_t* hist,
+                         const GridDesc* grids, const uint32_t* pool, hipStream_t st) {
   if (!max_chunks) return;
 #define LOD_SCAT(EE)                                                                                                   \
   case EE:                                                                                                             \
-    if (ids) scatter_e<EE, true>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, expect_chunks,   \
-                                 hist, grids, pool, st);                                                               \
-    else scatter_e<EE, false>(src, src_ids, dst, dst_ids, cube, segs, chunks, nchunk, max_chunks, expect_chunks,      \
+    if (ids) scatter_e<EE, true>(src, src_ids, dst, dst_ids, dig, cube, segs, chunks, nchunk, max_chunks,             \
+                                 expect_chunks, hist, grids, pool, st);                                                \
+    else scatter_e<EE, false>(src, src_ids, dst, dst_ids, dig, cube, segs, chunks, nchunk, max_chunks, expect_chunks, \
                               hist, grids, pool, st);                                                                  \
     break;
   switch (E) {

@@ -23,9 +23,12 @@ void launch_init_roots(const CloudInfo* clouds, uint32_t nclouds, uint32_t E0, S
 void launch_make_chunks(Segment* segs, const uint32_t* nseg, uint32_t max_segs, uint32_t chunk, Chunk* chunks,
                         uint32_t* nchunk, uint32_t max_chunks, ChunkGroup* groups, uint32_t* ngroup,
                         uint32_t max_groups, hipStream_t st);
-// Counts of a partition: the cells of the points of every chunk.
-void launch_part_count(uint32_t E, const void* pts, const Cube* cube, const Segment* segs, const Chunk* chunks,
-                       const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist, hipStream_t st);
+// Counts of a partition: the cells of the points of every chunk, from the
+// records, or (dig non-null) from the cells the previous insert stored
+// beside them.
+void launch_part_count(uint32_t E, const void* pts, const uint16_t* dig, const Cube* cube, const Segment* segs,
+                       const Chunk* chunks, const uint32_t* nchunk, uint32_t max_chunks, uint32_t* hist,
+                       hipStream_t st);
 void launch_part_colscan(const Segment* segs, const uint32_t* nseg, uint32_t max_segs, const ChunkGroup* groups,
                          const uint32_t* ngroup, uint32_t max_groups, uint32_t E, uint32_t* hist, uint32_t* gsum,
                          const GridDesc* grids, uint32_t* pool, hipStream_t st);
@@ -35,11 +38,13 @@ void launch_grid_finish(const Segment* segs, const uint32_t* nseg, uint32_t max_
 uint32_t scatter_round(bool ids);
 // Insert of a partition.  expect_chunks: how many chunks get a workgroup of
 // their own (the rest, up to max_chunks, are taken by a looping grid; results
-// never depend on it).
+// never depend on it).  dig (one u16 per destination record, or null): each
+// record's cell E levels below its cell of this partition, for the next
+// partition's count.
 void launch_part_scatter(uint32_t E, bool ids, const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids,
-                         const Cube* cube, const Segment* segs, const Chunk* chunks, const uint32_t* nchunk,
-                         uint32_t max_chunks, uint32_t expect_chunks, const uint32_t* hist, const GridDesc* grids,
-                         const uint32_t* pool, hipStream_t st);
+                         uint16_t* dig, const Cube* cube, const Segment* segs, const Chunk* chunks,
+                         const uint32_t* nchunk, uint32_t max_chunks, uint32_t expect_chunks, const uint32_t* hist,
+                         const GridDesc* grids, const uint32_t* pool, hipStream_t st);
 void launch_copy_segments(const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, const Segment* segs,
                           const uint32_t* nseg, uint32_t max_segs, hipStream_t st);
 void launch_segments_from_grid(GridDesc* grids, uint32_t ngrids, uint32_t* pool, uint32_t E2, uint64_t slot_base,

@@ -251,6 +251,7 @@ struct Plan {
   bool ids;
   bool full;      // full-precision records of the voxels
   bool weighted;  // neighbourhood-weighted colours, rewritten after the average build
+  bool digits;    // the first insert stores each record's cell of the second partition for its count
 };
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -314,6 +315,9 @@ Plan make_plan(uint64_t n_typical, uint64_t n_total, const lod_params& p) {
   if (p.tune_chunk) pl.chunk0 = std::max<uint32_t>(1, (p.tune_chunk + R / 2) / R) * R;
   pl.chunk1 = pl.chunk0;
   pl.chunk_ref = 2 * R;
+  // large inputs: the second count reads 2 bytes per point instead of the
+  // 16-byte record (both partitions take the same number of levels)
+  pl.digits = N >= (64u << 20) && pl.E0 == pl.E1;
   return pl;
 }
 
@@ -430,6 +434,7 @@ struct Carve {
 struct Bufs {
   uint4* X;
   uint32_t* Xid;
+  uint16_t* dig;  // per record of X: its cell in the second partition (or null)
   BBoxAcc* bbox;
   Cube* cube;
   CloudInfo* clouds;
@@ -494,6 +499,7 @@ RegionSizes layout(Bufs& b, const Caps& c, const Plan& pl, bool cube_given, bool
   Carve s(S), o(O), h(H);
   b.X = s.take<uint4>(c.N);
   b.Xid = s.take<uint32_t>(pl.ids ? c.N : 1);
+  b.dig = pl.digits ? s.take<uint16_t>(c.N) : nullptr;
   b.bbox = s.take<BBoxAcc>(c.nc);
   b.cube = s.take<Cube>(c.nc);
   b.clouds = s.take<CloudInfo>(c.nc);
@@ -553,23 +559,25 @@ RegionSizes layout(Bufs& b, const Caps& c, const Plan& pl, bool cube_given, bool
 
 // Partition `nseg` segments (device count, at most max_segs, expected about
 // expect_segs, covering at most max_points points) by E levels from src into
-// dst.
+// dst.  dig_in: the cells of src's records, stored by the previous insert
+// (counted instead of the records); dig_out: where this insert stores each
+// record's cell E levels further down (either may be null).
 void partition(const Bufs& b, uint32_t E, uint32_t chunk, uint32_t max_segs, uint32_t expect_segs, uint64_t max_points,
                const void* src, const uint32_t* src_ids, void* dst, uint32_t* dst_ids, bool ids, uint32_t* nseg,
-               hipStream_t s, StageTimer* tm, int ev0) {
+               const uint16_t* dig_in, uint16_t* dig_out, hipStream_t s, StageTimer* tm, int ev0) {
   uint32_t* nchunk = nseg + 1;
   uint32_t* ngroup = nseg + 2;
   const uint32_t max_chunks = ceil_div(max_points, chunk) + max_segs;
   const uint32_t expect_chunks = ceil_div(max_points, chunk) + std::min(max_segs, expect_segs);
   const uint32_t max_groups = ceil_div(max_chunks, kGroupChunks) + max_segs;
   launch_make_chunks(b.segs, nseg, max_segs, chunk, b.chunks, nchunk, max_chunks, b.groups, ngroup, max_groups, s);
-  launch_part_count(E, src, b.cube, b.segs, b.chunks, nchunk, max_chunks, b.hist, s);
+  launch_part_count(E, src, dig_in, b.cube, b.segs, b.chunks, nchunk, max_chunks, b.hist, s);
   if (ev0) mark(tm, ev0);
   launch_part_colscan(b.segs, nseg, max_segs, b.groups, ngroup, max_groups, E, b.hist, b.gsum, b.grids, b.pool, s);
   launch_grid_finish(b.segs, nseg, max_segs, b.grids, b.pool, s);
   if (ev0) mark(tm, ev0 + 1);
-  launch_part_scatter(E, ids, src, src_ids, dst, dst_ids, b.cube, b.segs, b.chunks, nchunk, max_chunks, expect_chunks,
-                      b.hist, b.grids, b.pool, s);
+  launch_part_scatter(E, ids, src, src_ids, dst, dst_ids, dig_out, b.cube, b.segs, b.chunks, nchunk, max_chunks,
+                      expect_chunks, b.hist, b.grids, b.pool, s);
   if (ev0) mark(tm, ev0 + 2);
   HIPCHK(hipGetLastError());
 }
@@ -583,7 +591,8 @@ void refine(const Bufs& b, const Caps& c, const Plan& pl, const uint32_t* list, 
   launch_refine_segments(b.nd, list, nlist, c.max_nodes, E, b.bs, c.grids, c.words, b.grids, b.segs, nseg, s);
   // refinements are few (none at all in most large builds): a workgroup
   // each for a thousand segments' chunks, the rest to the looping grid
-  partition(b, E, pl.chunk_ref, max_segs, 1024, c.N, b.Y, b.Yid, b.X, b.Xid, pl.ids, nseg, s, nullptr, 0);
+  partition(b, E, pl.chunk_ref, max_segs, 1024, c.N, b.Y, b.Yid, b.X, b.Xid, pl.ids, nseg, nullptr, nullptr, s,
+            nullptr, 0);
   launch_copy_segments(b.X, b.Xid, b.Y, pl.ids ? b.Yid : nullptr, b.segs, nseg, max_segs, s);
   launch_refine_commit(b.bs, nseg, E, s);
   HIPCHK(hipGetLastError());
@@ -605,12 +614,13 @@ void enqueue(const Bufs& b, const Caps& c, const Plan& pl, const lod_params& prm
   // 2. root partition, input -> X
   uint32_t* nseg = b.ctr;
   launch_init_roots(b.clouds, nc, pl.E0, b.segs, nseg, b.grids, s);
-  partition(b, pl.E0, pl.chunk0, nc, nc, c.N, in, in_ids, b.X, b.Xid, pl.ids, nseg, s, tm, EV_COUNT0);
+  partition(b, pl.E0, pl.chunk0, nc, nc, c.N, in, in_ids, b.X, b.Xid, pl.ids, nseg, nullptr, b.dig, s, tm,
+            EV_COUNT0);
   // 3. every root cell by E1 more levels, X -> Y
   launch_fill_u32(nseg, 0, 1, s);
   launch_segments_from_grid(b.grids, nc, b.pool, pl.E1, (uint64_t)nc * grid_words(pl.E0), nc, b.segs, nseg, s);
-  partition(b, pl.E1, pl.chunk1, (uint32_t)c.passb, (uint32_t)c.passb, c.N, b.X, b.Xid, b.Y, b.Yid, pl.ids, nseg, s,
-            tm, EV_COUNT1);
+  partition(b, pl.E1, pl.chunk1, (uint32_t)c.passb, (uint32_t)c.passb, c.N, b.X, b.Xid, b.Y, b.Yid, pl.ids, nseg,
+            b.dig, nullptr, s, tm, EV_COUNT1);
   // 4. nodes: one region of slots per tree, enumeration resumed after each
   // refinement round (a round without nodes to refine does nothing)
   launch_tree_init(prm.leaf_cap, prm.max_level, b.grids, b.pool, b.nd, b.st, b.nbeg, b.nbeg + nc, nc, s);
