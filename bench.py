@@ -57,13 +57,16 @@ SAMPLING = {"average": 0, "first": 1, "random": 2, "weighted": 3}
 
 def stage_bytes(stage: str, n: int, ids: bool) -> float:
     """Bytes one launch of a stage moves when every array it touches is read
-    or written once: 16-byte records, and 4-byte ids when carried."""
+    or written once: 16-byte records, and 4-byte ids when carried.  From 64M
+    points on, the first insert also writes each record's 2-byte cell of the
+    second partition, which the second count reads instead of the records."""
     idb = 4 if ids else 0
+    dig = 2.0 if n >= (64 << 20) else 0.0
     return {
         "bbox": 16.0 * n,
         "count0": 16.0 * n,
-        "scatter0": (16.0 + idb + 16.0 + idb) * n,
-        "count1": 16.0 * n,
+        "scatter0": (16.0 + idb + 16.0 + idb + dig) * n,
+        "count1": (dig if dig else 16.0) * n,
         "scatter1": (16.0 + idb + 16.0 + idb) * n,
         "leaf_voxels": (16.0 + idb) * n,
     }.get(stage, 0.0)
