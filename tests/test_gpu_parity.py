@@ -417,3 +417,25 @@ def test_leaf_items_at_the_sparse_kernel_limits(lod, side, T, full_precision):
         return
     g = gpu_tree(lod, p, leaf_cap=T, max_level=12, sampling=0, seed=3, full_precision=True)
     check_full(g, oracle.build(p, leaf_cap=T, max_level=12, sampling=0, seed=3, full_precision=True), p)
+
+
+def test_large_batch_second_count_from_cells(lod):
+    # 68.9M points in 7 clouds (median 1M points, so 3 levels per partition):
+    # the plan for the batch's total takes the second partition's counts from
+    # the 2-byte cells the first insert stores; single builds of the clouds
+    # (each under 64M points) count the records themselves.  Both must give
+    # the same trees.
+    sizes = [40_000_000, 1_000_000, 1_200_000, 0, 800_000, 25_000_000, 900_000]
+    pts, offs = synth.batch_chunks(sizes, seed=8)
+    print(f"large batch n={len(pts)}", flush=True)
+    trees = lod.lod_build_batch(to_dev(pts), offs, leaf_cap=50000, max_level=12)
+    for i, t in enumerate(trees):
+        chunk = np.ascontiguousarray(pts[offs[i]:offs[i + 1]])
+        g = t.to_host()
+        t.free()
+        if len(chunk) == 0:
+            assert g["num_voxels"] == 0
+            continue
+        alone = gpu_tree(lod, chunk, leaf_cap=50000, max_level=12)
+        for k in ("level", "key", "npoints", "count", "first_child", "voxels"):
+            assert np.array_equal(g[k], alone[k]), (i, k)
